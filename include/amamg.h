@@ -1,0 +1,165 @@
+/*
+ * amamg.h -- C ABI of the MI355X (gfx950) AM-AMG-preconditioned FGMRES solver for the
+ * two-flavour Schwinger-model Wilson-Dirac system D x = psi.
+ *
+ * Method (arXiv 2608.03515):
+ *   - D: Schwinger Model subsection, Wilson operator with U(1) links, two spin components,
+ *     sigma_0 = [[0,1],[1,0]], sigma_1 = [[0,-i],[i,0]]; periodic in space, antiperiodic in
+ *     time for the fermion field.
+ *   - Multigrid setup (Multilevel approach section): coarsening into structured wirebaskets
+ *     of aggregate size a and overlap o (SM-AMG subsection, wirebasket figure), interpolation
+ *     by the per-wirebasket Schur-complement formula (interpolation equation) with a
+ *     normalisation, restriction P^H, Galerkin coarse operator P^H A P.
+ *   - Solve: FGMRES right-preconditioned by a V-cycle of the two-level scheme algorithm with
+ *     0 pre- and 2 post-smoothing sweeps of a block smoother (Numerical Results section),
+ *     relative tolerance 1e-10; the coarsest level is solved directly.
+ *
+ * Conventions
+ *   Layout at the boundary (host and device pointers alike):
+ *     links  double [2 mu][nt][nx][2 (re,im)]     mu = 0 is the time direction
+ *     fields double [nrhs][nt][nx][2 spin][2 (re,im)]
+ *     site index t * nx + x; a field is also a complex128 tensor [nrhs][nt][nx][2].
+ *   Ownership: the caller owns every buffer it passes; the library copies links at load and
+ *     results out at solve.  Handles belong to the library until their *_destroy call.  A
+ *     hierarchy keeps its gauge alive: amamg_gauge_destroy fails while hierarchies exist.
+ *   Threading: one context = one HIP stream = one host thread at a time; distinct contexts
+ *     are independent.  Every call that takes a handle runs on that handle's context stream.
+ *   Errors: a negative status means no output was written; amamg_last_error gives a message.
+ *     AMAMG_NOT_CONVERGED (> 0) still writes x (the last iterate), info and the history.
+ *     Arguments are validated before any device work.
+ */
+#ifndef AMAMG_H
+#define AMAMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AMAMG_OK = 0,
+  AMAMG_NOT_CONVERGED = 1,            /* iteration cap reached; outputs valid              */
+  AMAMG_ERR_INVALID_ARG = -1,         /* null pointer, bad enum, handle misuse            */
+  AMAMG_ERR_UNSUPPORTED_SHAPE = -2,   /* odd lattice, a does not divide L, o >= a, ...      */
+  AMAMG_ERR_OUT_OF_MEMORY = -3,
+  AMAMG_ERR_DEVICE = -4,              /* a HIP runtime call failed                          */
+  AMAMG_ERR_SINGULAR_LOCAL = -5,      /* zero pivot in a wirebasket or diagonal-block solve */
+  AMAMG_ERR_SINGULAR_COARSEST = -6,   /* zero pivot in the coarsest factorisation          */
+  AMAMG_ERR_NONFINITE = -7            /* NaN/Inf in links, mass, right-hand side or result  */
+} amamg_status;
+
+typedef enum {
+  AMAMG_FP64 = 0,                     /* every step in binary64                             */
+  AMAMG_MIXED_FP32 = 1,               /* FP32 Arnoldi matvec and V-cycle, FP64 outer loop    */
+  AMAMG_MIXED_FP32_BF16LINKS = 2      /* as MIXED_FP32, fine-level smoother links in BF16    */
+} amamg_precision;
+
+typedef enum {
+  AMAMG_NORM_TESTVEC = 0,             /* least-squares row scale from smoothed test vectors  */
+  AMAMG_NORM_CONST = 1,               /* row sums of P equal 1 (constant -> constant)        */
+  AMAMG_NORM_NONE = 2
+} amamg_norm;
+
+typedef struct {
+  int32_t levels;              /* >= 2; the last level is solved directly (default 2)        */
+  int32_t agg_size;            /* a: wirebasket spacing (default 4)                          */
+  int32_t overlap;             /* o: shared border width, 1 <= o < a (default 1)             */
+  int32_t n_test_vectors;      /* N_v for AMAMG_NORM_TESTVEC, 1..16 (default 4)              */
+  int32_t test_vector_sweeps;  /* smoother sweeps on A w = 0 per level (default 4)           */
+  int32_t pre_sweeps;          /* default 0                                                  */
+  int32_t post_sweeps;         /* default 2                                                  */
+  int32_t norm;                /* amamg_norm (default AMAMG_NORM_TESTVEC)                    */
+  uint64_t seed;               /* test-vector hash seed (default 0)                          */
+} amamg_setup_params;
+
+typedef struct {
+  int32_t restart;             /* FGMRES restart length m, 1..31 (default 20)                */
+  int32_t max_iters;           /* cap on Arnoldi steps per right-hand side (default 10000)   */
+  double rel_tol;              /* ||psi - D x|| <= rel_tol ||psi|| (default 1e-10)           */
+  int32_t precision;           /* amamg_precision (default AMAMG_FP64)                       */
+  int32_t use_initial_guess;   /* nonzero: x holds x0 on entry (default 0)                   */
+} amamg_solve_params;
+
+typedef struct {
+  int32_t iterations;          /* Arnoldi steps                                              */
+  int32_t restarts;            /* completed cycles that did not converge                     */
+  int32_t converged;           /* 1 if the true relative residual met rel_tol                */
+  int32_t reserved;
+  double true_rel_residual;    /* ||psi - D x|| / ||psi|| in FP64 at the end                 */
+} amamg_solve_info;
+
+typedef struct amamg_context amamg_context;
+typedef struct amamg_gauge amamg_gauge;
+typedef struct amamg_hierarchy amamg_hierarchy;
+
+/* Fill defaults (values listed above). */
+void amamg_default_setup_params(amamg_setup_params *p);
+void amamg_default_solve_params(amamg_solve_params *p);
+
+/* Context on HIP device `device`.  hip_stream: a hipStream_t to run on (borrowed, not
+ * destroyed), or NULL for a stream the library creates and owns. */
+amamg_status amamg_context_create(int device, void *hip_stream, amamg_context **out);
+amamg_status amamg_context_destroy(amamg_context *ctx);
+/* Message for the last failure on this context (static storage owned by the context). */
+const char *amamg_last_error(const amamg_context *ctx);
+
+/* Load gauge links (host pointer, layout above, |U| = 1 expected but not required) and the
+ * bare mass m0 of D (Schwinger Model subsection).  nt, nx even and >= 4. */
+amamg_status amamg_gauge_load(amamg_context *ctx, int32_t nt, int32_t nx, const double *links,
+                              double m0, amamg_gauge **out);
+/* Change m0; hierarchies built from this gauge keep the mass they were built with. */
+amamg_status amamg_gauge_set_mass(amamg_gauge *g, double m0);
+amamg_status amamg_gauge_destroy(amamg_gauge *g);
+
+/* AM-AMG setup (Multilevel approach section: coarsening, interpolation, Galerkin operator)
+ * with aggregate size and overlap from params (NULL: defaults).  Runs on the GPU. */
+amamg_status amamg_setup(amamg_gauge *g, const amamg_setup_params *params, amamg_hierarchy **out);
+amamg_status amamg_hierarchy_destroy(amamg_hierarchy *h);
+
+/* Solve D x = psi for nrhs right-hand sides (host pointers, layout above).  info: array of
+ * nrhs entries (may be NULL).  Returns AMAMG_NOT_CONVERGED if any right-hand side hit the
+ * iteration cap. */
+amamg_status amamg_solve(amamg_hierarchy *h, int32_t nrhs, const double *psi, double *x,
+                         const amamg_solve_params *params, amamg_solve_info *info);
+/* Same with device pointers (resident in HBM, same layout); runs on the context stream and
+ * returns after the solve has finished. */
+amamg_status amamg_solve_device(amamg_hierarchy *h, int32_t nrhs, const void *psi_dev,
+                                void *x_dev, const amamg_solve_params *params,
+                                amamg_solve_info *info);
+
+/* Residual history of right-hand side `rhs` of the last solve: one entry per Arnoldi step
+ * (the FGMRES estimate |g_{j+1}| / ||psi||) and one per cycle end (the true relative
+ * residual, flagged 1 in is_true_residual).  Writes min(capacity, length) entries;
+ * n_written receives the full length. */
+amamg_status amamg_residual_history(const amamg_hierarchy *h, int32_t rhs, double *out,
+                                    int32_t *is_true_residual, int32_t capacity,
+                                    int32_t *n_written);
+
+/* ---- test hooks (host buffers) ---------------------------------------------------------- */
+/* out = D in for nrhs fields at the given precision (FP64 or FP32 links). */
+amamg_status amamg_apply_dirac(amamg_gauge *g, int32_t precision, int32_t nrhs,
+                               const double *in, double *out);
+/* Grid of level `level` (0 = fine lattice) and degrees of freedom per node. */
+amamg_status amamg_level_info(const amamg_hierarchy *h, int32_t level, int32_t *lt,
+                              int32_t *lx, int32_t *b);
+/* Wirebasket classification of level `level` (not the coarsest): per grid point the kind
+ * (0 interior, 1 edge, 2 vertex), the primary wirebasket (-1 for vertices) and the coarse
+ * node of a vertex (-1 otherwise).  Arrays of lt*lx entries. */
+amamg_status amamg_get_aggregates(const amamg_hierarchy *h, int32_t level, int8_t *kind,
+                                  int32_t *owner, int32_t *node);
+/* Interpolation rows of level `level`: double [lt*lx][b][4*bc][2]; row (p, i) holds the
+ * weights of the 4 corner nodes of p's primary wirebasket W(I,J), corner c = 2*ct + cx is
+ * node ((I+ct) mod, (J+cx) mod), column c*bc + j.  Vertex rows are zero (identity). */
+amamg_status amamg_get_prolongator(const amamg_hierarchy *h, int32_t level, double *out);
+/* Operator of level `level` >= 1: if not coarsest, double [lt*lx][25][b][b][2], block of
+ * offset (dt, dx) in [-2,2]^2 at index (dt+2)*5 + (dx+2) couples node n to node n+(dt,dx);
+ * at the coarsest level the dense matrix double [n][n][2], n = lt*lx*b. */
+amamg_status amamg_get_coarse_operator(const amamg_hierarchy *h, int32_t level, double *out);
+/* Smoothed test vectors of level `level`: double [n_test_vectors][lt*lx*b][2]. */
+amamg_status amamg_get_test_vectors(const amamg_hierarchy *h, int32_t level, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMAMG_H */

@@ -1,0 +1,242 @@
+"""Thin ctypes binding of libamamg.so (the C ABI in include/amamg.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.  The library
+must have been built (``python -m paper_2608_03515_amd.build``); importing this module
+raises ``ImportError`` when it is missing, there is no fallback.
+
+Fields use the ABI layout: float64 arrays [nrhs][nt][nx][2 spin][2 (re, im)] (numpy), or
+complex128 tensors [nrhs][nt][nx][2] on the GPU (torch) for the device entry points.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libamamg.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2608_03515_amd.build")
+_lib = C.CDLL(LIB_PATH)
+
+OK, NOT_CONVERGED = 0, 1
+FP64, MIXED_FP32, MIXED_FP32_BF16LINKS = 0, 1, 2
+NORM_TESTVEC, NORM_CONST, NORM_NONE = 0, 1, 2
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARG", -2: "UNSUPPORTED_SHAPE",
+                -3: "OUT_OF_MEMORY", -4: "DEVICE", -5: "SINGULAR_LOCAL",
+                -6: "SINGULAR_COARSEST", -7: "NONFINITE"}
+
+EXPORTED = ["amamg_default_setup_params", "amamg_default_solve_params", "amamg_context_create",
+            "amamg_context_destroy", "amamg_last_error", "amamg_gauge_load",
+            "amamg_gauge_set_mass", "amamg_gauge_destroy", "amamg_setup",
+            "amamg_hierarchy_destroy", "amamg_solve", "amamg_solve_device",
+            "amamg_residual_history", "amamg_apply_dirac", "amamg_level_info",
+            "amamg_get_aggregates", "amamg_get_prolongator", "amamg_get_coarse_operator",
+            "amamg_get_test_vectors"]
+
+
+class SetupParams(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("agg_size", C.c_int32), ("overlap", C.c_int32),
+                ("n_test_vectors", C.c_int32), ("test_vector_sweeps", C.c_int32),
+                ("pre_sweeps", C.c_int32), ("post_sweeps", C.c_int32), ("norm", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("max_iters", C.c_int32), ("rel_tol", C.c_double),
+                ("precision", C.c_int32), ("use_initial_guess", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
+                ("reserved", C.c_int32), ("true_rel_residual", C.c_double)]
+
+
+_vp = C.c_void_p
+_P = C.POINTER
+_sig = {
+    "amamg_default_setup_params": (None, [_P(SetupParams)]),
+    "amamg_default_solve_params": (None, [_P(SolveParams)]),
+    "amamg_context_create": (C.c_int, [C.c_int, _vp, _P(_vp)]),
+    "amamg_context_destroy": (C.c_int, [_vp]),
+    "amamg_last_error": (C.c_char_p, [_vp]),
+    "amamg_gauge_load": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, C.c_double, _P(_vp)]),
+    "amamg_gauge_set_mass": (C.c_int, [_vp, C.c_double]),
+    "amamg_gauge_destroy": (C.c_int, [_vp]),
+    "amamg_setup": (C.c_int, [_vp, _P(SetupParams), _P(_vp)]),
+    "amamg_hierarchy_destroy": (C.c_int, [_vp]),
+    "amamg_solve": (C.c_int, [_vp, C.c_int32, _vp, _vp, _P(SolveParams), _P(SolveInfo)]),
+    "amamg_solve_device": (C.c_int, [_vp, C.c_int32, _vp, _vp, _P(SolveParams), _P(SolveInfo)]),
+    "amamg_residual_history": (C.c_int, [_vp, C.c_int32, _vp, _vp, C.c_int32, _P(C.c_int32)]),
+    "amamg_apply_dirac": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _vp]),
+    "amamg_level_info": (C.c_int, [_vp, C.c_int32, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32)]),
+    "amamg_get_aggregates": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp]),
+    "amamg_get_prolongator": (C.c_int, [_vp, C.c_int32, _vp]),
+    "amamg_get_coarse_operator": (C.c_int, [_vp, C.c_int32, _vp]),
+    "amamg_get_test_vectors": (C.c_int, [_vp, C.c_int32, _vp]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class AmamgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_vp)
+
+
+def default_setup_params(**kw) -> SetupParams:
+    p = SetupParams()
+    _lib.amamg_default_setup_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def default_solve_params(**kw) -> SolveParams:
+    p = SolveParams()
+    _lib.amamg_default_solve_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+class Context:
+    """amamg_context on a HIP device; stream: a raw hipStream_t handle (int) or None."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        h = _vp()
+        st = _lib.amamg_context_create(device, _vp(stream) if stream else None, C.byref(h))
+        if st != OK:
+            raise AmamgError(st, "context creation failed")
+        self.h = h
+
+    def check(self, st: int, ok=(OK,)) -> int:
+        if st not in ok:
+            raise AmamgError(st, _lib.amamg_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if self.h:
+            _lib.amamg_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Gauge:
+    """amamg_gauge: links float64 [2][nt][nx][2] (host), bare mass m0."""
+
+    def __init__(self, ctx: Context, links: np.ndarray, m0: float):
+        links = np.ascontiguousarray(links, dtype=np.float64)
+        _, nt, nx, _ = links.shape
+        h = _vp()
+        ctx.check(_lib.amamg_gauge_load(ctx.h, nt, nx, _ptr(links), float(m0), C.byref(h)))
+        self.ctx, self.h, self.nt, self.nx = ctx, h, nt, nx
+
+    def set_mass(self, m0: float):
+        self.ctx.check(_lib.amamg_gauge_set_mass(self.h, float(m0)))
+
+    def apply_dirac(self, fields: np.ndarray, precision: int = FP64) -> np.ndarray:
+        fields = np.ascontiguousarray(fields, dtype=np.float64)
+        out = np.empty_like(fields)
+        nrhs = fields.shape[0]
+        self.ctx.check(_lib.amamg_apply_dirac(self.h, precision, nrhs, _ptr(fields), _ptr(out)))
+        return out
+
+    def close(self):
+        if self.h:
+            self.ctx.check(_lib.amamg_gauge_destroy(self.h))
+            self.h = None
+
+
+class Hierarchy:
+    """amamg_hierarchy built by amamg_setup on the GPU."""
+
+    def __init__(self, gauge: Gauge, params: SetupParams | None = None):
+        h = _vp()
+        gauge.ctx.check(_lib.amamg_setup(gauge.h, C.byref(params) if params else None, C.byref(h)))
+        self.gauge, self.ctx, self.h = gauge, gauge.ctx, h
+
+    def close(self):
+        if self.h:
+            self.ctx.check(_lib.amamg_hierarchy_destroy(self.h))
+            self.h = None
+
+    def solve(self, psi: np.ndarray, params: SolveParams | None = None, x0: np.ndarray | None = None):
+        """Host solve; psi float64 [nrhs][nt][nx][2][2].  Returns (x, [SolveInfo], status)."""
+        psi = np.ascontiguousarray(psi, dtype=np.float64)
+        nrhs = psi.shape[0]
+        x = np.zeros_like(psi) if x0 is None else np.ascontiguousarray(x0, dtype=np.float64).copy()
+        infos = (SolveInfo * nrhs)()
+        p = params or default_solve_params()
+        if x0 is not None:
+            p.use_initial_guess = 1
+        st = _lib.amamg_solve(self.h, nrhs, _ptr(psi), _ptr(x), C.byref(p), infos)
+        self.ctx.check(st, ok=(OK, NOT_CONVERGED))
+        return x, list(infos), st
+
+    def solve_device(self, psi_ptr: int, x_ptr: int, nrhs: int, params: SolveParams | None = None):
+        """Device solve on raw device pointers (e.g. torch ``data_ptr()``)."""
+        infos = (SolveInfo * nrhs)()
+        st = _lib.amamg_solve_device(self.h, nrhs, _vp(psi_ptr), _vp(x_ptr),
+                                     C.byref(params) if params else None, infos)
+        self.ctx.check(st, ok=(OK, NOT_CONVERGED))
+        return list(infos), st
+
+    def residual_history(self, rhs: int = 0):
+        n = C.c_int32()
+        self.ctx.check(_lib.amamg_residual_history(self.h, rhs, None, None, 0, C.byref(n)))
+        vals = np.zeros(n.value)
+        flags = np.zeros(n.value, dtype=np.int32)
+        self.ctx.check(_lib.amamg_residual_history(self.h, rhs, _ptr(vals), _ptr(flags), n.value,
+                                                   C.byref(n)))
+        return vals, flags.astype(bool)
+
+    def level_info(self, level: int):
+        lt, lx, b = C.c_int32(), C.c_int32(), C.c_int32()
+        self.ctx.check(_lib.amamg_level_info(self.h, level, C.byref(lt), C.byref(lx), C.byref(b)))
+        return lt.value, lx.value, b.value
+
+    def aggregates(self, level: int):
+        lt, lx, _ = self.level_info(level)
+        kind = np.zeros(lt * lx, dtype=np.int8)
+        owner = np.zeros(lt * lx, dtype=np.int32)
+        node = np.zeros(lt * lx, dtype=np.int32)
+        self.ctx.check(_lib.amamg_get_aggregates(self.h, level, _ptr(kind), _ptr(owner), _ptr(node)))
+        return kind, owner, node
+
+    def prolongator_rows(self, level: int, overlap: int) -> np.ndarray:
+        """complex [lt*lx][b][4*bc] interpolation rows (vertex rows zero)."""
+        lt, lx, b = self.level_info(level)
+        bc = overlap * overlap * b
+        out = np.zeros((lt * lx, b, 4 * bc, 2))
+        self.ctx.check(_lib.amamg_get_prolongator(self.h, level, _ptr(out)))
+        return out[..., 0] + 1j * out[..., 1]
+
+    def coarse_operator(self, level: int, coarsest: bool) -> np.ndarray:
+        lt, lx, b = self.level_info(level)
+        if coarsest:
+            n = lt * lx * b
+            out = np.zeros((n, n, 2))
+        else:
+            out = np.zeros((lt * lx, 25, b, b, 2))
+        self.ctx.check(_lib.amamg_get_coarse_operator(self.h, level, _ptr(out)))
+        return out[..., 0] + 1j * out[..., 1]
+
+    def test_vectors(self, level: int, nv: int) -> np.ndarray:
+        lt, lx, b = self.level_info(level)
+        out = np.zeros((nv, lt * lx * b, 2))
+        self.ctx.check(_lib.amamg_get_test_vectors(self.h, level, _ptr(out)))
+        return out[..., 0] + 1j * out[..., 1]

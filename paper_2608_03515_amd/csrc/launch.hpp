@@ -1,0 +1,120 @@
+// Host-side launchers of the HIP kernels (one declaration per operation; the definitions sit
+// beside their kernels).  All launches are asynchronous on `s`.
+#pragma once
+
+#include "common.hpp"
+
+namespace amamg {
+
+enum Real { F64 = 0, F32 = 1 };
+enum LinkStore { LINK_F64 = 0, LINK_F32 = 1, LINK_BF16 = 2 };
+
+// Geometry of one level's grid and of its wirebaskets (for the transfer to the next level).
+struct Geom {
+  int Lt, Lx, b;      // grid and degrees of freedom per node
+  int a, o;           // aggregate size, overlap
+  int nI, nJ;         // wirebaskets per direction (Lt / a, Lx / a)
+  int bc;             // degrees of freedom per coarse node (o * o * b)
+  __host__ __device__ int nnode() const { return Lt * Lx; }
+  __host__ __device__ int64_t ndof() const { return int64_t(Lt) * Lx * b; }
+  __host__ __device__ int ncol() const { return 4 * bc; }   // interpolation columns per row
+  __host__ __device__ int fp() const { return (a + o) * (a + o); }
+};
+
+// ---- fine level (Wilson stencil); vectors [rhs][site][2 spin] complex ---------------------
+// y = D x   (x: vin; y: vout; b == nullptr)  or  y = b - D x  (b: FP64 right-hand side)
+void wilson_apply(hipStream_t s, LinkStore ls, const void* U0, const void* U1, Real vin,
+                  const void* x, Real vout, void* y, const double2* b, int nt, int nx, double m0,
+                  int nrhs, int64_t stride, const RhsState* st);
+// one colour of the red-black point Gauss-Seidel sweep on D x = b (b FP64 or null = 0)
+void wilson_gs(hipStream_t s, LinkStore ls, const void* U0, const void* U1, Real vx, void* x,
+               const double2* b, int nt, int nx, double m0, int colour, int nrhs, int64_t stride,
+               const RhsState* st);
+// A0 blocks of the fine operator in block-stencil form: [site][5][2][2], offsets
+// (0,0), (+1,0), (-1,0), (0,+1), (0,-1)
+void build_fine_stencil(hipStream_t s, const double2* U0, const double2* U1, int nt, int nx,
+                        double m0, double2* A0);
+// link copies in lower precision (FP32, BF16 round to nearest even)
+void links_to_f32(hipStream_t s, const double2* U, float2* out, int64_t n);
+void links_to_bf16(hipStream_t s, const double2* U, bf16c* out, int64_t n);
+// canonical <-> internal is the identity; casts between vector precisions
+void cast_vec(hipStream_t s, Real from, const void* x, Real to, void* y, int64_t n);
+
+// ---- coarse levels (block stencil [node][25][b][b]) -------------------------------------
+// y = A x or y = f - A x (f non-null, same type as vout)
+void stencil_apply(hipStream_t s, Real prec, const void* A, const void* x, void* y,
+                   const void* f, int Lt, int Lx, int b, int nrhs, int64_t stride,
+                   const RhsState* st);
+// one colour of the 16-colour point-block Gauss-Seidel sweep: x_n = Dinv_n (f_n - sum_{d!=0} A_nd x_{n+d})
+// f may be null (zero right-hand side)
+void stencil_gs(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
+                int Lt, int Lx, int b, int colour, int nrhs, int64_t stride, const RhsState* st);
+// coarsest: y = Ainv v (matrix FP64 always; vectors in prec)
+void dense_apply(hipStream_t s, Real prec, const double2* Ainv, const void* v, void* y, int n,
+                 int nrhs, int64_t stride, const RhsState* st);
+
+// ---- transfer between level k (fine side, geometry g) and k+1 ----------------------------
+// y = P e   (add != 0: y += P e); e: coarse vector in prec; y: fine vector in prec
+void prolong(hipStream_t s, Real prec, const void* P, const int* owner, const int* node,
+             const void* e, void* y, const Geom& g, int add, int nrhs, int64_t stride_f,
+             int64_t stride_c, const RhsState* st);
+// rc = P^H r; r in `rin` precision (FP64 basis vector or prec), rc in prec
+void restrict_(hipStream_t s, Real prec, const void* P, const int* owner, Real rin,
+               const void* r, void* rc, const Geom& g, int nrhs, int64_t stride_f,
+               int64_t stride_c, const RhsState* st);
+
+// ---- setup -------------------------------------------------------------------------------
+void classify(hipStream_t s, const Geom& g, int8_t* kind, int* owner, int* node);
+void testvec_hash(hipStream_t s, uint64_t seed, int level, int nv, int64_t ndof, double2* W);
+void inject(hipStream_t s, const Geom& g, const int* node, const int8_t* kind, const double2* w,
+            double2* wc, int nv);
+// local systems of every wirebasket: Aff [W][nfd][nfd], Bneg = -A_FV [W][nfd][ncol]
+void gather_local(hipStream_t s, const Geom& g, const double2* A, int noff, const int* offs_dev,
+                  const int* postab, int nf, double2* Aff, double2* Bneg);
+// batched LU with partial pivoting (one workgroup per system) and solves
+void lu_factor(hipStream_t s, double2* A, int n, int nsys, int* piv, int* info);
+void lu_solve(hipStream_t s, const double2* LU, const int* piv, int n, int nsys, double2* B,
+              int nrhs);
+void scatter_P(hipStream_t s, const Geom& g, const double2* X, const int* postab, int nf,
+               const int* owner, double2* P);
+// P rows scaled by the normalisation (mode 0 TESTVEC, 1 CONST; 2 NONE is a no-op)
+void normalise(hipStream_t s, const Geom& g, double2* P, const int* owner, const double2* tv,
+               const double2* tvc, int nv, int mode);
+void probe_make(hipStream_t s, const Geom& gc, int pt, int px, int ct, int cx, double2* e);
+// scatter probe results u [bc][ndof_c] into the coarse stencil [node][25][bc][bc] or dense
+void probe_extract(hipStream_t s, const Geom& gc, int pt, int px, int ct, int cx,
+                   const double2* u, double2* out, int dense);
+void extract_diag(hipStream_t s, const double2* A, int nnode, int b, double2* D);
+void set_identity(hipStream_t s, double2* B, int n, int nsys);
+void cast_matrix(hipStream_t s, const double2* A, float2* out, int64_t n);
+
+// ---- Krylov (FP64) -----------------------------------------------------------------------
+// partial sums per block: out[rhs][blk][i] = sum conj(V_i) w over the block's range, i < nv
+struct KrylovDims { int64_t n; int nrhs; int nblk; int m; };
+void dots_partial(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vstride_j,
+                  int nv, const double2* w, double2* part, const RhsState* st);
+// w -= sum_i V_i h_i; then dots of the updated w (mode 1) or its squared norm (mode 2)
+void update_partial(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vstride_j,
+                     int nv, double2* w, const double2* h, int hstride, double2* part, int mode,
+                     const RhsState* st);
+void sum_partials(hipStream_t s, const KrylovDims& d, const double2* part, int nv, double2* out,
+                  int ostride, const RhsState* st);
+void norm_partial(hipStream_t s, const KrylovDims& d, const double2* x, double2* part,
+                  const RhsState* st, int only_active);
+// per-rhs cycle control (see krylov.hip)
+void cycle_begin(hipStream_t s, const KrylovDims& d, RhsState* st, const double2* part, double2* g,
+                 double tol, int first, int max_iters, double2* hist, int hist_cap);
+void arnoldi_finish(hipStream_t s, const KrylovDims& d, RhsState* st, const double2* part,
+                    const double2* h1, const double2* h2, double2* H, double* cs, double2* sn,
+                    double2* g, int j, double tol, double inner_tol, int max_iters,
+                    double2* hist, int hist_cap);
+void scale_next(hipStream_t s, const KrylovDims& d, const double2* w, double2* v,
+                const RhsState* st);
+void backsolve_update(hipStream_t s, const KrylovDims& d, RhsState* st, const double2* H,
+                      const double2* g, double2* y, Real zprec, const void* Z,
+                      int64_t zstride_j, double2* x);
+void init_states(hipStream_t s, const KrylovDims& d, RhsState* st, const double2* part);
+void copy_vec(hipStream_t s, const double2* x, double2* y, int64_t n);
+void zero_vec(hipStream_t s, void* x, int64_t bytes);
+
+}  // namespace amamg

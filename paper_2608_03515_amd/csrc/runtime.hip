@@ -1,0 +1,879 @@
+// Host runtime and C ABI of the AM-AMG library: handles, the GPU setup pipeline and the
+// FGMRES driver.  Every numerical step runs in the kernels of this directory; the host only
+// sequences launches, owns device memory and reads per-rhs status once per restart cycle.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/amamg.h"
+#include "launch.hpp"
+
+using namespace amamg;
+
+namespace {
+
+struct Fail {
+  amamg_status code;
+  std::string msg;
+};
+
+#define HIPCHECK(expr)                                                                          \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess) {                                                                     \
+      if (e_ == hipErrorOutOfMemory)                                                            \
+        throw Fail{AMAMG_ERR_OUT_OF_MEMORY, std::string(#expr) + ": out of device memory"};    \
+      throw Fail{AMAMG_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)};         \
+    }                                                                                           \
+  } while (0)
+
+#define REQUIRE(cond, code, msg) \
+  do {                           \
+    if (!(cond)) throw Fail{code, msg}; \
+  } while (0)
+
+// Device allocations owned by a handle, released together.
+struct Arena {
+  std::vector<void*> ptrs;
+  template <typename T> T* alloc(size_t count) {
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    HIPCHECK(hipMalloc(&p, count * sizeof(T)));
+    ptrs.push_back(p);
+    return static_cast<T*>(p);
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+  ~Arena() { release(); }
+};
+
+int period_of(int L) {
+  for (int d = 5; d <= L; ++d)
+    if (L % d == 0) return d;
+  return L;
+}
+
+}  // namespace
+
+struct amamg_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+};
+
+struct amamg_gauge {
+  amamg_context* ctx = nullptr;
+  int nt = 0, nx = 0;
+  double m0 = 0;
+  int nhier = 0;
+  Arena mem;
+  double2* U = nullptr;     // [2][nt*nx]
+  float2* U32 = nullptr;
+  bf16c* U16 = nullptr;
+};
+
+namespace {
+
+struct LevelData {
+  Geom g{};
+  bool coarsest = false;
+  // operator of this level (k >= 1)
+  double2* A = nullptr;      // stencil [nnode][25][b][b] (non-coarsest)
+  float2* A32 = nullptr;
+  double2* Dinv = nullptr;   // [nnode][b][b]
+  float2* Dinv32 = nullptr;
+  double2* Adense = nullptr; // coarsest [n][n]
+  double2* Ainv = nullptr;   // coarsest inverse [n][n]
+  // transfer to the next level (non-coarsest)
+  int8_t* kind = nullptr;
+  int* owner = nullptr;
+  int* node = nullptr;
+  double2* P = nullptr;      // [nnode][b][4 bc]
+  float2* P32 = nullptr;
+  double2* tv = nullptr;     // smoothed test vectors [nv][ndof]
+  // solve workspace (k >= 1): right-hand side, iterate, scratch
+  void* f = nullptr;
+  void* x = nullptr;
+  void* tmp = nullptr;
+};
+
+}  // namespace
+
+struct amamg_hierarchy {
+  amamg_gauge* gauge = nullptr;
+  amamg_setup_params prm{};
+  double m0 = 0;
+  std::vector<LevelData> lv;
+  Arena mem;       // setup products
+  Arena ws;        // solve workspace
+  int ws_nrhs = 0, ws_m = 0, ws_hist = 0;
+  Real ws_prec = F64;
+  double2 *V = nullptr, *w = nullptr, *H = nullptr, *g = nullptr, *sn = nullptr, *y = nullptr;
+  double2 *h1 = nullptr, *h2 = nullptr, *part = nullptr, *hist = nullptr;
+  double* cs = nullptr;
+  void* Z = nullptr;
+  RhsState* st = nullptr;
+  int nblk = 1;
+  std::vector<std::vector<double2>> history;
+};
+
+// ------------------------------------------------------------------------------- helpers
+
+namespace {
+
+amamg_status fail(amamg_context* ctx, const Fail& f) {
+  if (ctx) ctx->err = f.msg;
+  return f.code;
+}
+
+void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Fail{AMAMG_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e)};
+}
+
+// footprint tables: postab[pos] = F index or -(1 + vcol); followed by fpos[nf]
+std::vector<int> footprint_tables(int a, int o, int b, int* nf_out) {
+  const int fpw = a + o, bc = o * o * b;
+  std::vector<int> postab(fpw * fpw), fpos;
+  for (int dt = 0; dt < fpw; ++dt)
+    for (int dx = 0; dx < fpw; ++dx) {
+      const int pos = dt * fpw + dx;
+      const bool vt = dt < o || dt >= a, vx = dx < o || dx >= a;
+      if (vt && vx) {
+        const int ct = dt >= a, cx = dx >= a;
+        const int pt = dt - ct * a, px = dx - cx * a;
+        postab[pos] = -(1 + (2 * ct + cx) * bc + (pt * o + px) * b);
+      } else {
+        postab[pos] = int(fpos.size());
+        fpos.push_back(pos);
+      }
+    }
+  *nf_out = int(fpos.size());
+  postab.insert(postab.end(), fpos.begin(), fpos.end());
+  return postab;
+}
+
+struct LevelPlan {
+  int Lt, Lx, b;
+};
+
+std::vector<LevelPlan> plan_levels(int nt, int nx, const amamg_setup_params& p) {
+  REQUIRE(p.levels >= 2 && p.levels <= 8, AMAMG_ERR_INVALID_ARG, "levels must be in [2, 8]");
+  REQUIRE(p.overlap >= 1 && p.overlap < p.agg_size, AMAMG_ERR_UNSUPPORTED_SHAPE,
+          "overlap must satisfy 1 <= o < a");
+  REQUIRE(p.norm >= 0 && p.norm <= 2, AMAMG_ERR_INVALID_ARG, "unknown normalisation");
+  REQUIRE(p.norm != AMAMG_NORM_TESTVEC || (p.n_test_vectors >= 1 && p.n_test_vectors <= 16),
+          AMAMG_ERR_INVALID_ARG, "n_test_vectors must be in [1, 16]");
+  REQUIRE(p.test_vector_sweeps >= 0 && p.pre_sweeps >= 0 && p.post_sweeps >= 0,
+          AMAMG_ERR_INVALID_ARG, "sweep counts must be >= 0");
+  std::vector<LevelPlan> out;
+  int Lt = nt, Lx = nx, b = 2;
+  const int a = p.agg_size, o = p.overlap;
+  for (int k = 0; k < p.levels; ++k) {
+    out.push_back({Lt, Lx, b});
+    if (k == p.levels - 1) break;
+    REQUIRE(Lt % a == 0 && Lx % a == 0 && Lt / a >= 2 && Lx / a >= 2, AMAMG_ERR_UNSUPPORTED_SHAPE,
+            "aggregate size must divide every non-coarsest grid with at least 2 wirebaskets per direction");
+    if (k >= 1) {
+      REQUIRE(Lt % 4 == 0 && Lx % 4 == 0 && Lt >= 8 && Lx >= 8, AMAMG_ERR_UNSUPPORTED_SHAPE,
+              "intermediate coarse grids must be multiples of 4 and at least 8 (16-colour smoother)");
+      REQUIRE(b <= 64 && (64 % b) == 0, AMAMG_ERR_UNSUPPORTED_SHAPE,
+              "intermediate coarse levels need a power-of-two block size <= 64");
+    }
+    REQUIRE(o * o * b <= 256, AMAMG_ERR_UNSUPPORTED_SHAPE, "coarse block size above 256");
+    Lt /= a;
+    Lx /= a;
+    b *= o * o;
+  }
+  const LevelPlan& c = out.back();
+  REQUIRE(int64_t(c.Lt) * c.Lx * c.b <= 4096, AMAMG_ERR_UNSUPPORTED_SHAPE,
+          "coarsest level above 4096 unknowns (add a level)");
+  return out;
+}
+
+Geom make_geom(const LevelPlan& l, int a, int o, bool coarsest) {
+  Geom g{};
+  g.Lt = l.Lt; g.Lx = l.Lx; g.b = l.b; g.a = a; g.o = o;
+  g.nI = coarsest ? 0 : l.Lt / a;
+  g.nJ = coarsest ? 0 : l.Lx / a;
+  g.bc = o * o * l.b;
+  return g;
+}
+
+Geom coarse_geom_of(const Geom& g) {
+  Geom c{};
+  c.Lt = g.nI; c.Lx = g.nJ; c.b = g.bc; c.a = g.a; c.o = g.o;
+  return c;
+}
+
+// ------------------------------------------------------------------------- GPU setup
+
+void run_setup(amamg_hierarchy* h) {
+  amamg_gauge* gg = h->gauge;
+  hipStream_t s = gg->ctx->stream;
+  const amamg_setup_params& p = h->prm;
+  const auto plan = plan_levels(gg->nt, gg->nx, p);
+  const int K = int(plan.size());
+  const int a = p.agg_size, o = p.overlap;
+  h->lv.resize(K);
+  for (int k = 0; k < K; ++k) {
+    h->lv[k].g = make_geom(plan[k], a, o, k == K - 1);
+    h->lv[k].coarsest = (k == K - 1);
+  }
+  const double2* U0 = gg->U;
+  const double2* U1 = gg->U + int64_t(gg->nt) * gg->nx;
+  Arena tmp;   // setup temporaries
+  const int nv = (p.norm == AMAMG_NORM_TESTVEC) ? p.n_test_vectors : 0;
+
+  // fine operator in block-stencil form, used to gather the wirebasket systems
+  double2* A0 = tmp.alloc<double2>(size_t(gg->nt) * gg->nx * 5 * 4);
+  build_fine_stencil(s, U0, U1, gg->nt, gg->nx, h->m0, A0);
+  const int offs5[10] = {0, 0, 1, 0, -1, 0, 0, 1, 0, -1};
+  int offs25[50];
+  for (int dt = -2, q = 0; dt <= 2; ++dt)
+    for (int dx = -2; dx <= 2; ++dx, ++q) { offs25[2 * q] = dt; offs25[2 * q + 1] = dx; }
+  int* d_offs5 = tmp.alloc<int>(10);
+  int* d_offs25 = tmp.alloc<int>(50);
+  HIPCHECK(hipMemcpyAsync(d_offs5, offs5, sizeof(offs5), hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(d_offs25, offs25, sizeof(offs25), hipMemcpyHostToDevice, s));
+
+  double2* W = nullptr;   // test vectors entering level k
+  for (int k = 0; k < K - 1; ++k) {
+    LevelData& L = h->lv[k];
+    const Geom& g = L.g;
+    const int nnode = g.nnode();
+    const int64_t ndof = g.ndof();
+    L.kind = h->mem.alloc<int8_t>(nnode);
+    L.owner = h->mem.alloc<int>(nnode);
+    L.node = h->mem.alloc<int>(nnode);
+    classify(s, g, L.kind, L.owner, L.node);
+    check_launch();
+
+    // test vectors: random at level 0, injected from the finer level otherwise; nu sweeps
+    if (nv > 0) {
+      L.tv = h->mem.alloc<double2>(size_t(nv) * ndof);
+      if (k == 0) testvec_hash(s, p.seed, 0, nv, ndof, L.tv);
+      else HIPCHECK(hipMemcpyAsync(L.tv, W, sizeof(double2) * nv * ndof, hipMemcpyDeviceToDevice, s));
+      for (int sw = 0; sw < p.test_vector_sweeps; ++sw) {
+        if (k == 0) {
+          for (int c = 0; c < 2; ++c)
+            wilson_gs(s, LINK_F64, U0, U1, F64, L.tv, nullptr, g.Lt, g.Lx, h->m0, c, nv, ndof, nullptr);
+        } else {
+          for (int c = 0; c < 16; ++c)
+            stencil_gs(s, F64, L.A, L.Dinv, L.tv, nullptr, g.Lt, g.Lx, g.b, c, nv, ndof, nullptr);
+        }
+      }
+      check_launch();
+    }
+
+    // local Schur-complement interpolation per wirebasket
+    int nf = 0;
+    const std::vector<int> tabs = footprint_tables(a, o, g.b, &nf);
+    int* d_tabs = tmp.alloc<int>(tabs.size());
+    HIPCHECK(hipMemcpyAsync(d_tabs, tabs.data(), sizeof(int) * tabs.size(), hipMemcpyHostToDevice, s));
+    const int nW = g.nI * g.nJ, nfd = nf * g.b, ncol = g.ncol();
+    double2* Aff = tmp.alloc<double2>(size_t(nW) * nfd * nfd);
+    double2* Bn = tmp.alloc<double2>(size_t(nW) * nfd * ncol);
+    int* piv = tmp.alloc<int>(size_t(nW) * nfd);
+    int* info = tmp.alloc<int>(nW);
+    if (k == 0) gather_local(s, g, A0, 5, d_offs5, d_tabs, nf, Aff, Bn);
+    else gather_local(s, g, L.A, 25, d_offs25, d_tabs, nf, Aff, Bn);
+    lu_factor(s, Aff, nfd, nW, piv, info);
+    check_launch();
+    std::vector<int> hinfo(nW);
+    HIPCHECK(hipMemcpyAsync(hinfo.data(), info, sizeof(int) * nW, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    for (int w = 0; w < nW; ++w)
+      REQUIRE(hinfo[w] == 0, AMAMG_ERR_SINGULAR_LOCAL,
+              "zero pivot in the local system of wirebasket " + std::to_string(w) + " on level " + std::to_string(k));
+    lu_solve(s, Aff, piv, nfd, nW, Bn, ncol);
+    L.P = h->mem.alloc<double2>(size_t(ndof) * ncol);
+    HIPCHECK(hipMemsetAsync(L.P, 0, sizeof(double2) * ndof * ncol, s));
+    scatter_P(s, g, Bn, d_tabs, nf, L.owner, L.P);
+    check_launch();
+
+    // normalisation (and the test vectors handed to the next level)
+    double2* Wc = nullptr;
+    const Geom gc = coarse_geom_of(g);
+    const int64_t ndof_c = gc.ndof();
+    if (nv > 0) {
+      Wc = tmp.alloc<double2>(size_t(nv) * ndof_c);
+      inject(s, g, L.node, L.kind, L.tv, Wc, nv);
+    }
+    normalise(s, g, L.P, L.owner, L.tv, Wc, nv, p.norm);
+    check_launch();
+
+    // Galerkin operator by probing: for every colour class of coarse nodes (periods >= 5),
+    // A_c e = P^H (A (P e)) with unit vectors on that class yields the blocks of its columns.
+    LevelData& C = h->lv[k + 1];
+    const bool dense = C.coarsest;
+    const int bc = g.bc;
+    const int nnc = gc.nnode();
+    const int pt = period_of(gc.Lt), px = period_of(gc.Lx);
+    double2* out = nullptr;
+    if (dense) {
+      C.Adense = h->mem.alloc<double2>(size_t(ndof_c) * ndof_c);
+      out = C.Adense;
+      HIPCHECK(hipMemsetAsync(out, 0, sizeof(double2) * ndof_c * ndof_c, s));
+    } else {
+      C.A = h->mem.alloc<double2>(size_t(nnc) * 25 * bc * bc);
+      out = C.A;
+      HIPCHECK(hipMemsetAsync(out, 0, sizeof(double2) * nnc * 25 * bc * bc, s));
+    }
+    double2* pe = tmp.alloc<double2>(size_t(bc) * ndof_c);
+    double2* py = tmp.alloc<double2>(size_t(bc) * ndof);
+    double2* pz = tmp.alloc<double2>(size_t(bc) * ndof);
+    double2* pu = tmp.alloc<double2>(size_t(bc) * ndof_c);
+    for (int ct = 0; ct < pt; ++ct)
+      for (int cx = 0; cx < px; ++cx) {
+        probe_make(s, gc, pt, px, ct, cx, pe);
+        prolong(s, F64, L.P, L.owner, L.node, pe, py, g, 0, bc, ndof, ndof_c, nullptr);
+        if (k == 0)
+          wilson_apply(s, LINK_F64, U0, U1, F64, py, F64, pz, nullptr, g.Lt, g.Lx, h->m0, bc, ndof, nullptr);
+        else
+          stencil_apply(s, F64, L.A, py, pz, nullptr, g.Lt, g.Lx, g.b, bc, ndof, nullptr);
+        restrict_(s, F64, L.P, L.owner, F64, pz, pu, g, bc, ndof, ndof_c, nullptr);
+        probe_extract(s, gc, pt, px, ct, cx, pu, out, dense ? 1 : 0);
+      }
+    check_launch();
+
+    // smoother blocks of the next level, or the coarsest inverse
+    if (!dense) {
+      C.Dinv = h->mem.alloc<double2>(size_t(nnc) * bc * bc);
+      double2* Dg = tmp.alloc<double2>(size_t(nnc) * bc * bc);
+      int* dpiv = tmp.alloc<int>(size_t(nnc) * bc);
+      int* dinfo = tmp.alloc<int>(nnc);
+      extract_diag(s, C.A, nnc, bc, Dg);
+      lu_factor(s, Dg, bc, nnc, dpiv, dinfo);
+      set_identity(s, C.Dinv, bc, nnc);
+      lu_solve(s, Dg, dpiv, bc, nnc, C.Dinv, bc);
+      check_launch();
+      std::vector<int> hd(nnc);
+      HIPCHECK(hipMemcpyAsync(hd.data(), dinfo, sizeof(int) * nnc, hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      for (int n = 0; n < nnc; ++n)
+        REQUIRE(hd[n] == 0, AMAMG_ERR_SINGULAR_LOCAL, "singular diagonal block on level " + std::to_string(k + 1));
+    } else {
+      const int n = int(ndof_c);
+      double2* LUc = tmp.alloc<double2>(size_t(n) * n);
+      int* cpiv = tmp.alloc<int>(n);
+      int* cinfo = tmp.alloc<int>(1);
+      HIPCHECK(hipMemcpyAsync(LUc, C.Adense, sizeof(double2) * n * n, hipMemcpyDeviceToDevice, s));
+      lu_factor(s, LUc, n, 1, cpiv, cinfo);
+      C.Ainv = h->mem.alloc<double2>(size_t(n) * n);
+      set_identity(s, C.Ainv, n, 1);
+      lu_solve(s, LUc, cpiv, n, 1, C.Ainv, n);
+      check_launch();
+      int hc = 0;
+      HIPCHECK(hipMemcpyAsync(&hc, cinfo, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      REQUIRE(hc == 0, AMAMG_ERR_SINGULAR_COARSEST, "zero pivot in the coarsest factorisation");
+    }
+    W = Wc;
+    // the next level's test vectors must outlive this iteration's temporaries
+    if (nv > 0 && !dense) {
+      double2* keep = h->mem.alloc<double2>(size_t(nv) * ndof_c);
+      HIPCHECK(hipMemcpyAsync(keep, Wc, sizeof(double2) * nv * ndof_c, hipMemcpyDeviceToDevice, s));
+      W = keep;
+    }
+  }
+
+  // FP32 copies for the mixed-precision V-cycle
+  for (int k = 0; k < K; ++k) {
+    LevelData& L = h->lv[k];
+    if (L.P) {
+      const int64_t n = L.g.ndof() * L.g.ncol();
+      L.P32 = h->mem.alloc<float2>(n);
+      cast_matrix(s, L.P, L.P32, n);
+    }
+    if (L.A) {
+      const int64_t n = int64_t(L.g.nnode()) * 25 * L.g.b * L.g.b;
+      L.A32 = h->mem.alloc<float2>(n);
+      cast_matrix(s, L.A, L.A32, n);
+    }
+    if (L.Dinv) {
+      const int64_t n = int64_t(L.g.nnode()) * L.g.b * L.g.b;
+      L.Dinv32 = h->mem.alloc<float2>(n);
+      cast_matrix(s, L.Dinv, L.Dinv32, n);
+    }
+  }
+  check_launch();
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------- solve
+
+void ensure_links(amamg_gauge* gg, LinkStore ls) {
+  hipStream_t s = gg->ctx->stream;
+  const int64_t n = 2 * int64_t(gg->nt) * gg->nx;
+  if (ls == LINK_F32 && !gg->U32) {
+    gg->U32 = gg->mem.alloc<float2>(n);
+    links_to_f32(s, gg->U, gg->U32, n);
+  }
+  if (ls == LINK_BF16 && !gg->U16) {
+    gg->U16 = gg->mem.alloc<bf16c>(n);
+    links_to_bf16(s, gg->U, gg->U16, n);
+  }
+}
+
+void ensure_workspace(amamg_hierarchy* h, int nrhs, int m, Real prec, int hist_cap) {
+  if (h->ws_nrhs >= nrhs && h->ws_m >= m && h->ws_prec == prec && h->ws_hist >= hist_cap) return;
+  h->ws.release();
+  const int64_t n = h->lv[0].g.ndof();
+  const size_t rs = prec == F64 ? sizeof(double2) : sizeof(float2);
+  h->V = h->ws.alloc<double2>(size_t(m + 1) * nrhs * n);
+  h->Z = h->ws.alloc<char>(size_t(m) * nrhs * n * rs);
+  h->w = h->ws.alloc<double2>(size_t(nrhs) * n);
+  h->H = h->ws.alloc<double2>(size_t(nrhs) * (m + 1) * m);
+  h->g = h->ws.alloc<double2>(size_t(nrhs) * (m + 1));
+  h->cs = h->ws.alloc<double>(size_t(nrhs) * m);
+  h->sn = h->ws.alloc<double2>(size_t(nrhs) * m);
+  h->y = h->ws.alloc<double2>(size_t(nrhs) * m);
+  h->h1 = h->ws.alloc<double2>(size_t(nrhs) * 32);
+  h->h2 = h->ws.alloc<double2>(size_t(nrhs) * 32);
+  h->nblk = int(std::min<int64_t>(1024, std::max<int64_t>(1, n / 256)));
+  h->part = h->ws.alloc<double2>(size_t(nrhs) * h->nblk * 32);
+  h->st = h->ws.alloc<RhsState>(nrhs);
+  h->hist = h->ws.alloc<double2>(size_t(nrhs) * hist_cap);
+  for (size_t k = 1; k < h->lv.size(); ++k) {
+    LevelData& L = h->lv[k];
+    const int64_t nd = L.g.ndof();
+    L.f = h->ws.alloc<char>(size_t(nrhs) * nd * rs);
+    L.x = h->ws.alloc<char>(size_t(nrhs) * nd * rs);
+    L.tmp = h->ws.alloc<char>(size_t(nrhs) * nd * rs);
+  }
+  h->lv[0].tmp = h->ws.alloc<char>(size_t(nrhs) * n * rs);
+  h->ws_nrhs = nrhs;
+  h->ws_m = m;
+  h->ws_prec = prec;
+  h->ws_hist = hist_cap;
+}
+
+struct SolveCtx {
+  amamg_hierarchy* h;
+  hipStream_t s;
+  Real T;
+  LinkStore smooth_links, mat_links;
+  int nrhs;
+};
+
+const void* link0(amamg_gauge* g, LinkStore ls) {
+  return ls == LINK_F64 ? (const void*)g->U : ls == LINK_F32 ? (const void*)g->U32 : (const void*)g->U16;
+}
+const void* link1(amamg_gauge* g, LinkStore ls) {
+  const int64_t v = int64_t(g->nt) * g->nx;
+  return ls == LINK_F64 ? (const void*)(g->U + v) : ls == LINK_F32 ? (const void*)(g->U32 + v)
+                                                                      : (const void*)(g->U16 + v);
+}
+
+// x = M_k f (V-cycle of the paper's two-level scheme, recursively; start x = 0)
+void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x) {
+  amamg_hierarchy* h = c.h;
+  LevelData& L = h->lv[k];
+  const Geom& g = L.g;
+  const int64_t nd = g.ndof();
+  const RhsState* st = h->st;
+  const bool f64 = c.T == F64;
+  if (L.coarsest) {
+    dense_apply(c.s, c.T, L.Ainv, f, x, int(nd), c.nrhs, nd, st);
+    return;
+  }
+  LevelData& C = h->lv[k + 1];
+  const int64_t ndc = C.g.ndof();
+  const void* P = f64 ? (const void*)L.P : (const void*)L.P32;
+  const int pre = h->prm.pre_sweeps, post = h->prm.post_sweeps;
+  amamg_gauge* gg = h->gauge;
+  const void* U0 = link0(gg, c.smooth_links);
+  const void* U1 = link1(gg, c.smooth_links);
+  const void* Ak = f64 ? (const void*)L.A : (const void*)L.A32;
+  const void* Dk = f64 ? (const void*)L.Dinv : (const void*)L.Dinv32;
+  if (pre > 0) {
+    HIPCHECK(hipMemsetAsync(x, 0, nd * c.nrhs * (f64 ? 16 : 8), c.s));
+    for (int sw = 0; sw < pre; ++sw) {
+      if (k == 0)
+        for (int col = 0; col < 2; ++col)
+          wilson_gs(c.s, c.smooth_links, U0, U1, c.T, x, (const double2*)f, g.Lt, g.Lx, h->m0, col, c.nrhs, nd, st);
+      else
+        for (int col = 0; col < 16; ++col)
+          stencil_gs(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, col, c.nrhs, nd, st);
+    }
+    if (k == 0)
+      wilson_apply(c.s, c.smooth_links, U0, U1, c.T, x, c.T, L.tmp, (const double2*)f, g.Lt, g.Lx, h->m0, c.nrhs, nd, st);
+    else
+      stencil_apply(c.s, c.T, Ak, x, L.tmp, f, g.Lt, g.Lx, g.b, c.nrhs, nd, st);
+    restrict_(c.s, c.T, P, L.owner, c.T, L.tmp, C.f, g, c.nrhs, nd, ndc, st);
+  } else {
+    restrict_(c.s, c.T, P, L.owner, fprec, f, C.f, g, c.nrhs, nd, ndc, st);
+  }
+  vcycle(c, k + 1, c.T, C.f, C.x);
+  prolong(c.s, c.T, P, L.owner, L.node, C.x, x, g, pre > 0 ? 1 : 0, c.nrhs, nd, ndc, st);
+  for (int sw = 0; sw < post; ++sw) {
+    if (k == 0)
+      for (int col = 0; col < 2; ++col)
+        wilson_gs(c.s, c.smooth_links, U0, U1, c.T, x, (const double2*)f, g.Lt, g.Lx, h->m0, col, c.nrhs, nd, st);
+    else
+      for (int col = 0; col < 16; ++col)
+        stencil_gs(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, col, c.nrhs, nd, st);
+  }
+}
+
+amamg_status run_solve(amamg_hierarchy* h, int nrhs, const double2* b, double2* x,
+                       const amamg_solve_params& p, amamg_solve_info* info) {
+  amamg_gauge* gg = h->gauge;
+  hipStream_t s = gg->ctx->stream;
+  REQUIRE(nrhs >= 1, AMAMG_ERR_INVALID_ARG, "nrhs must be >= 1");
+  REQUIRE(p.restart >= 1 && p.restart <= 31, AMAMG_ERR_INVALID_ARG, "restart must be in [1, 31]");
+  REQUIRE(p.max_iters >= 1, AMAMG_ERR_INVALID_ARG, "max_iters must be >= 1");
+  REQUIRE(p.rel_tol > 0 && std::isfinite(p.rel_tol), AMAMG_ERR_INVALID_ARG, "rel_tol must be > 0");
+  REQUIRE(p.precision >= 0 && p.precision <= 2, AMAMG_ERR_INVALID_ARG, "unknown precision");
+  const int m = p.restart;
+  const Real T = p.precision == AMAMG_FP64 ? F64 : F32;
+  const int hist_cap = 2 * p.max_iters + 2;
+  ensure_workspace(h, nrhs, m, T, hist_cap);
+  SolveCtx c{h, s, T, LINK_F64, LINK_F64, nrhs};
+  if (p.precision == AMAMG_MIXED_FP32) { c.smooth_links = LINK_F32; c.mat_links = LINK_F32; }
+  if (p.precision == AMAMG_MIXED_FP32_BF16LINKS) { c.smooth_links = LINK_BF16; c.mat_links = LINK_F32; }
+  ensure_links(gg, c.smooth_links);
+  ensure_links(gg, c.mat_links);
+  const double inner_tol = T == F64 ? 0.0 : 1e-5;
+
+  const int64_t n = h->lv[0].g.ndof();
+  const int nt = gg->nt, nx = gg->nx;
+  KrylovDims kd{n, nrhs, h->nblk, m};
+  RhsState* st = h->st;
+  const size_t zs = T == F64 ? sizeof(double2) : sizeof(float2);
+  const int64_t vsj = int64_t(nrhs) * n;   // basis stride between j
+
+  // ||b||; refuse non-finite input before touching x
+  norm_partial(s, kd, b, h->part, nullptr, 0);
+  init_states(s, kd, st, h->part);
+  check_launch();
+  std::vector<RhsState> hs(nrhs);
+  HIPCHECK(hipMemcpyAsync(hs.data(), st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  for (int r = 0; r < nrhs; ++r)
+    REQUIRE(!hs[r].nonfinite, AMAMG_ERR_NONFINITE, "non-finite value in right-hand side " + std::to_string(r));
+
+  if (!p.use_initial_guess) HIPCHECK(hipMemsetAsync(x, 0, sizeof(double2) * nrhs * n, s));
+  // r = b - D x into V_0
+  wilson_apply(s, LINK_F64, gg->U, gg->U + int64_t(nt) * nx, F64, x, F64, h->V, b, nt, nx, h->m0, nrhs, n, st);
+  norm_partial(s, kd, h->V, h->part, st, 1);
+  cycle_begin(s, kd, st, h->part, h->g, p.rel_tol, 1, p.max_iters, h->hist, hist_cap);
+  scale_next(s, kd, h->V, h->V, st);
+  check_launch();
+
+  const void* Um0 = link0(gg, c.mat_links);
+  const void* Um1 = link1(gg, c.mat_links);
+  for (;;) {
+    HIPCHECK(hipMemcpyAsync(hs.data(), st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    bool any = false;
+    for (int r = 0; r < nrhs; ++r) any = any || hs[r].in_cycle;
+    if (!any) break;
+    for (int j = 0; j < m; ++j) {
+      double2* vj = h->V + j * vsj;
+      void* zj = (char*)h->Z + size_t(j) * vsj * zs;
+      vcycle(c, 0, F64, vj, zj);
+      wilson_apply(s, c.mat_links, Um0, Um1, T, zj, F64, h->w, nullptr, nt, nx, h->m0, nrhs, n, st);
+      dots_partial(s, kd, h->V, vsj, j + 1, h->w, h->part, st);
+      sum_partials(s, kd, h->part, j + 1, h->h1, 32, st);
+      update_partial(s, kd, h->V, vsj, j + 1, h->w, h->h1, 32, h->part, 1, st);
+      sum_partials(s, kd, h->part, j + 1, h->h2, 32, st);
+      update_partial(s, kd, h->V, vsj, j + 1, h->w, h->h2, 32, h->part, 2, st);
+      arnoldi_finish(s, kd, st, h->part, h->h1, h->h2, h->H, h->cs, h->sn, h->g, j, p.rel_tol,
+                     inner_tol, p.max_iters, h->hist, hist_cap);
+      if (j + 1 < m) scale_next(s, kd, h->w, h->V + (j + 1) * vsj, st);
+      check_launch();
+    }
+    backsolve_update(s, kd, st, h->H, h->g, h->y, T, h->Z, vsj, x);
+    wilson_apply(s, LINK_F64, gg->U, gg->U + int64_t(nt) * nx, F64, x, F64, h->V, b, nt, nx, h->m0, nrhs, n, st);
+    norm_partial(s, kd, h->V, h->part, st, 1);
+    cycle_begin(s, kd, st, h->part, h->g, p.rel_tol, 0, p.max_iters, h->hist, hist_cap);
+    scale_next(s, kd, h->V, h->V, st);
+    check_launch();
+  }
+  // results
+  h->history.assign(nrhs, {});
+  std::vector<double2> hh(size_t(nrhs) * hist_cap);
+  HIPCHECK(hipMemcpyAsync(hh.data(), h->hist, sizeof(double2) * hh.size(), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  bool all_conv = true, nonfinite = false;
+  for (int r = 0; r < nrhs; ++r) {
+    h->history[r].assign(hh.begin() + size_t(r) * hist_cap, hh.begin() + size_t(r) * hist_cap + hs[r].hist_len);
+    all_conv = all_conv && hs[r].converged;
+    nonfinite = nonfinite || hs[r].nonfinite;
+    if (info) {
+      info[r].iterations = hs[r].iters;
+      info[r].restarts = hs[r].restarts;
+      info[r].converged = hs[r].converged;
+      info[r].reserved = 0;
+      info[r].true_rel_residual = hs[r].true_res;
+    }
+  }
+  REQUIRE(!nonfinite, AMAMG_ERR_NONFINITE, "non-finite value during the solve");
+  return all_conv ? AMAMG_OK : AMAMG_NOT_CONVERGED;
+}
+
+bool finite_all(const double* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------- ABI
+
+extern "C" {
+
+void amamg_default_setup_params(amamg_setup_params* p) {
+  if (!p) return;
+  p->levels = 2; p->agg_size = 4; p->overlap = 1; p->n_test_vectors = 4;
+  p->test_vector_sweeps = 4; p->pre_sweeps = 0; p->post_sweeps = 2;
+  p->norm = AMAMG_NORM_TESTVEC; p->seed = 0;
+}
+
+void amamg_default_solve_params(amamg_solve_params* p) {
+  if (!p) return;
+  p->restart = 20; p->max_iters = 10000; p->rel_tol = 1e-10; p->precision = AMAMG_FP64;
+  p->use_initial_guess = 0;
+}
+
+amamg_status amamg_context_create(int device, void* hip_stream, amamg_context** out) {
+  if (!out) return AMAMG_ERR_INVALID_ARG;
+  *out = nullptr;
+  amamg_context* c = new amamg_context();
+  try {
+    int ndev = 0;
+    HIPCHECK(hipGetDeviceCount(&ndev));
+    REQUIRE(device >= 0 && device < ndev, AMAMG_ERR_INVALID_ARG, "no such device");
+    HIPCHECK(hipSetDevice(device));
+    c->device = device;
+    if (hip_stream) {
+      c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+      HIPCHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+  } catch (const Fail& f) {
+    delete c;
+    return f.code;
+  }
+  *out = c;
+  return AMAMG_OK;
+}
+
+amamg_status amamg_context_destroy(amamg_context* ctx) {
+  if (!ctx) return AMAMG_ERR_INVALID_ARG;
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return AMAMG_OK;
+}
+
+const char* amamg_last_error(const amamg_context* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+amamg_status amamg_gauge_load(amamg_context* ctx, int32_t nt, int32_t nx, const double* links,
+                              double m0, amamg_gauge** out) {
+  if (!ctx || !out || !links) return ctx ? fail(ctx, {AMAMG_ERR_INVALID_ARG, "null argument"}) : AMAMG_ERR_INVALID_ARG;
+  *out = nullptr;
+  amamg_gauge* g = new amamg_gauge();
+  try {
+    REQUIRE(nt >= 4 && nx >= 4 && nt % 2 == 0 && nx % 2 == 0, AMAMG_ERR_UNSUPPORTED_SHAPE,
+            "lattice sizes must be even and >= 4");
+    REQUIRE(int64_t(nt) * nx <= (int64_t(1) << 28), AMAMG_ERR_UNSUPPORTED_SHAPE, "lattice too large");
+    const size_t nval = size_t(2) * nt * nx * 2;
+    REQUIRE(std::isfinite(m0) && finite_all(links, nval), AMAMG_ERR_NONFINITE, "non-finite link or mass");
+    HIPCHECK(hipSetDevice(ctx->device));
+    g->ctx = ctx; g->nt = nt; g->nx = nx; g->m0 = m0;
+    g->U = g->mem.alloc<double2>(size_t(2) * nt * nx);
+    HIPCHECK(hipMemcpyAsync(g->U, links, sizeof(double) * nval, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+  } catch (const Fail& f) {
+    delete g;
+    return fail(ctx, f);
+  }
+  *out = g;
+  return AMAMG_OK;
+}
+
+amamg_status amamg_gauge_set_mass(amamg_gauge* g, double m0) {
+  if (!g) return AMAMG_ERR_INVALID_ARG;
+  if (!std::isfinite(m0)) return fail(g->ctx, {AMAMG_ERR_NONFINITE, "non-finite mass"});
+  g->m0 = m0;
+  return AMAMG_OK;
+}
+
+amamg_status amamg_gauge_destroy(amamg_gauge* g) {
+  if (!g) return AMAMG_ERR_INVALID_ARG;
+  if (g->nhier > 0) return fail(g->ctx, {AMAMG_ERR_INVALID_ARG, "gauge still used by hierarchies"});
+  delete g;
+  return AMAMG_OK;
+}
+
+amamg_status amamg_setup(amamg_gauge* g, const amamg_setup_params* params, amamg_hierarchy** out) {
+  if (!g || !out) return g ? fail(g->ctx, {AMAMG_ERR_INVALID_ARG, "null argument"}) : AMAMG_ERR_INVALID_ARG;
+  *out = nullptr;
+  amamg_hierarchy* h = new amamg_hierarchy();
+  h->gauge = g;
+  h->m0 = g->m0;
+  if (params) h->prm = *params;
+  else amamg_default_setup_params(&h->prm);
+  try {
+    HIPCHECK(hipSetDevice(g->ctx->device));
+    run_setup(h);
+  } catch (const Fail& f) {
+    delete h;
+    return fail(g->ctx, f);
+  }
+  g->nhier += 1;
+  *out = h;
+  return AMAMG_OK;
+}
+
+amamg_status amamg_hierarchy_destroy(amamg_hierarchy* h) {
+  if (!h) return AMAMG_ERR_INVALID_ARG;
+  h->gauge->nhier -= 1;
+  delete h;
+  return AMAMG_OK;
+}
+
+amamg_status amamg_solve_device(amamg_hierarchy* h, int32_t nrhs, const void* psi_dev, void* x_dev,
+                                const amamg_solve_params* params, amamg_solve_info* info) {
+  if (!h) return AMAMG_ERR_INVALID_ARG;
+  if (!psi_dev || !x_dev) return fail(h->gauge->ctx, {AMAMG_ERR_INVALID_ARG, "null field pointer"});
+  amamg_solve_params p;
+  if (params) p = *params;
+  else amamg_default_solve_params(&p);
+  try {
+    HIPCHECK(hipSetDevice(h->gauge->ctx->device));
+    return run_solve(h, nrhs, static_cast<const double2*>(psi_dev), static_cast<double2*>(x_dev), p, info);
+  } catch (const Fail& f) {
+    return fail(h->gauge->ctx, f);
+  }
+}
+
+amamg_status amamg_solve(amamg_hierarchy* h, int32_t nrhs, const double* psi, double* x,
+                         const amamg_solve_params* params, amamg_solve_info* info) {
+  if (!h) return AMAMG_ERR_INVALID_ARG;
+  amamg_context* ctx = h->gauge->ctx;
+  if (!psi || !x || nrhs < 1) return fail(ctx, {AMAMG_ERR_INVALID_ARG, "null field pointer or nrhs < 1"});
+  amamg_solve_params p;
+  if (params) p = *params;
+  else amamg_default_solve_params(&p);
+  const size_t bytes = sizeof(double2) * size_t(nrhs) * h->lv[0].g.ndof();
+  Arena io;
+  try {
+    HIPCHECK(hipSetDevice(ctx->device));
+    double2* db = io.alloc<double2>(bytes / sizeof(double2));
+    double2* dx = io.alloc<double2>(bytes / sizeof(double2));
+    HIPCHECK(hipMemcpyAsync(db, psi, bytes, hipMemcpyHostToDevice, ctx->stream));
+    if (p.use_initial_guess) HIPCHECK(hipMemcpyAsync(dx, x, bytes, hipMemcpyHostToDevice, ctx->stream));
+    amamg_status st = run_solve(h, nrhs, db, dx, p, info);
+    HIPCHECK(hipMemcpyAsync(x, dx, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+    return st;
+  } catch (const Fail& f) {
+    return fail(ctx, f);
+  }
+}
+
+amamg_status amamg_residual_history(const amamg_hierarchy* h, int32_t rhs, double* out,
+                                    int32_t* is_true, int32_t capacity, int32_t* n_written) {
+  if (!h || rhs < 0 || rhs >= int(h->history.size())) return AMAMG_ERR_INVALID_ARG;
+  const auto& v = h->history[rhs];
+  if (n_written) *n_written = int32_t(v.size());
+  const int nw = std::min<int>(capacity, int(v.size()));
+  for (int i = 0; i < nw; ++i) {
+    if (out) out[i] = v[i].x;
+    if (is_true) is_true[i] = v[i].y != 0.0;
+  }
+  return AMAMG_OK;
+}
+
+amamg_status amamg_apply_dirac(amamg_gauge* g, int32_t precision, int32_t nrhs, const double* in,
+                               double* out) {
+  if (!g || !in || !out || nrhs < 1) return g ? fail(g->ctx, {AMAMG_ERR_INVALID_ARG, "bad argument"}) : AMAMG_ERR_INVALID_ARG;
+  amamg_context* ctx = g->ctx;
+  try {
+    REQUIRE(precision == AMAMG_FP64 || precision == AMAMG_MIXED_FP32, AMAMG_ERR_INVALID_ARG,
+            "precision must be FP64 or MIXED_FP32");
+    HIPCHECK(hipSetDevice(ctx->device));
+    const int64_t n = int64_t(g->nt) * g->nx * 2;
+    Arena io;
+    double2* dx = io.alloc<double2>(size_t(nrhs) * n);
+    double2* dy = io.alloc<double2>(size_t(nrhs) * n);
+    HIPCHECK(hipMemcpyAsync(dx, in, sizeof(double2) * nrhs * n, hipMemcpyHostToDevice, ctx->stream));
+    LinkStore ls = precision == AMAMG_FP64 ? LINK_F64 : LINK_F32;
+    ensure_links(g, ls);
+    wilson_apply(ctx->stream, ls, link0(g, ls), link1(g, ls), F64, dx, F64, dy, nullptr, g->nt, g->nx,
+                 g->m0, nrhs, n, nullptr);
+    check_launch();
+    HIPCHECK(hipMemcpyAsync(out, dy, sizeof(double2) * nrhs * n, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+  } catch (const Fail& f) {
+    return fail(ctx, f);
+  }
+  return AMAMG_OK;
+}
+
+amamg_status amamg_level_info(const amamg_hierarchy* h, int32_t level, int32_t* lt, int32_t* lx,
+                              int32_t* b) {
+  if (!h || level < 0 || level >= int(h->lv.size())) return AMAMG_ERR_INVALID_ARG;
+  const Geom& g = h->lv[level].g;
+  if (lt) *lt = g.Lt;
+  if (lx) *lx = g.Lx;
+  if (b) *b = g.b;
+  return AMAMG_OK;
+}
+
+static amamg_status copy_out(const amamg_hierarchy* h, void* dst, const void* src, size_t bytes) {
+  amamg_context* ctx = h->gauge->ctx;
+  try {
+    HIPCHECK(hipSetDevice(ctx->device));
+    HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+  } catch (const Fail& f) {
+    return fail(ctx, f);
+  }
+  return AMAMG_OK;
+}
+
+amamg_status amamg_get_aggregates(const amamg_hierarchy* h, int32_t level, int8_t* kind,
+                                  int32_t* owner, int32_t* node) {
+  if (!h || level < 0 || level >= int(h->lv.size()) - 1) return AMAMG_ERR_INVALID_ARG;
+  const LevelData& L = h->lv[level];
+  const size_t nn = L.g.nnode();
+  amamg_status s = AMAMG_OK;
+  if (kind && (s = copy_out(h, kind, L.kind, nn)) != AMAMG_OK) return s;
+  if (owner && (s = copy_out(h, owner, L.owner, nn * 4)) != AMAMG_OK) return s;
+  if (node && (s = copy_out(h, node, L.node, nn * 4)) != AMAMG_OK) return s;
+  return AMAMG_OK;
+}
+
+amamg_status amamg_get_prolongator(const amamg_hierarchy* h, int32_t level, double* out) {
+  if (!h || !out || level < 0 || level >= int(h->lv.size()) - 1) return AMAMG_ERR_INVALID_ARG;
+  const LevelData& L = h->lv[level];
+  return copy_out(h, out, L.P, sizeof(double2) * L.g.ndof() * L.g.ncol());
+}
+
+amamg_status amamg_get_coarse_operator(const amamg_hierarchy* h, int32_t level, double* out) {
+  if (!h || !out || level < 1 || level >= int(h->lv.size())) return AMAMG_ERR_INVALID_ARG;
+  const LevelData& L = h->lv[level];
+  if (L.coarsest) return copy_out(h, out, L.Adense, sizeof(double2) * L.g.ndof() * L.g.ndof());
+  return copy_out(h, out, L.A, sizeof(double2) * L.g.nnode() * 25 * L.g.b * L.g.b);
+}
+
+amamg_status amamg_get_test_vectors(const amamg_hierarchy* h, int32_t level, double* out) {
+  if (!h || !out || level < 0 || level >= int(h->lv.size()) - 1) return AMAMG_ERR_INVALID_ARG;
+  const LevelData& L = h->lv[level];
+  if (!L.tv) return fail(h->gauge->ctx, {AMAMG_ERR_INVALID_ARG, "no test vectors (normalisation is not TESTVEC)"});
+  return copy_out(h, out, L.tv, sizeof(double2) * h->prm.n_test_vectors * L.g.ndof());
+}
+
+}  // extern "C"

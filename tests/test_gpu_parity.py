@@ -1,0 +1,287 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on the same seeded inputs.
+
+Bars: integer outputs (wirebasket classes, owners, nodes) bit-exact; FP64 operator applies
+within 1e-13 relative; setup products (interpolation rows, coarse operators) within 1e-10
+relative (batched LU with a different pivot order and summation order than LAPACK/SciPy);
+FP64 solves with identical iteration counts and relative solution error <= 1e-9.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import amg
+from oracle.dirac import dirac_matrix
+from oracle.solve import solve as oracle_solve
+from oracle.wirebasket import KIND_V
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context(0)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+def make_gauge(lib, ctx, U, m0):
+    return lib.Gauge(ctx, synth.links_to_abi(U), m0)
+
+
+# --------------------------------------------------------------------------- stencil
+
+@pytest.mark.parametrize("nt,nx", [(4, 4), (8, 12), (16, 16), (64, 64), (6, 10)])
+def test_dirac_apply_matches_oracle(lib, ctx, nt, nx):
+    say("dirac apply", nt, nx)
+    U = np.exp(1j * np.random.default_rng(nt * 100 + nx).uniform(-np.pi, np.pi, (2, nt, nx)))
+    g = make_gauge(lib, ctx, U, 0.137)
+    psi = synth.gaussian_rhs(nt, nx, 5, nrhs=3)
+    out = synth.field_from_abi(g.apply_dirac(synth.field_to_abi(psi)))
+    D = dirac_matrix(U, 0.137)
+    for r in range(3):
+        ref = (D @ psi[r].reshape(-1)).reshape(nt, nx, 2)
+        assert rel(out[r], ref) < 1e-13
+    out32 = synth.field_from_abi(g.apply_dirac(synth.field_to_abi(psi), precision=lib.MIXED_FP32))
+    ref = (D @ psi[0].reshape(-1)).reshape(nt, nx, 2)
+    assert rel(out32[0], ref) < 2e-6
+    g.close()
+
+
+# ------------------------------------------------------------------------------ setup
+
+def oracle_rows(lev, a, o):
+    """Oracle interpolation as rows [p][i][4*bc] in the library's corner ordering."""
+    P = lev.P.tocsr()
+    b, Lt, Lx = lev.b, lev.Lt, lev.Lx
+    bc = o * o * b
+    nI, nJ = Lt // a, Lx // a
+    out = np.zeros((Lt * Lx, b, 4 * bc), dtype=complex)
+    for p in range(Lt * Lx):
+        w = lev.cls["owner"][p]
+        if lev.cls["kind"][p] == KIND_V:
+            continue
+        I, J = divmod(int(w), nJ)
+        for c in range(4):
+            ct, cx = c >> 1, c & 1
+            node = ((I + ct) % nI) * nJ + (J + cx) % nJ
+            cols = node * bc + np.arange(bc)
+            for i in range(b):
+                out[p, i, c * bc:(c + 1) * bc] = P[p * b + i, cols].toarray().ravel()
+    return out
+
+
+def oracle_stencil(A, Lt, Lx, b):
+    A = A.tocsr()
+    out = np.zeros((Lt * Lx, 25, b, b), dtype=complex)
+    for n in range(Lt * Lx):
+        t, x = divmod(n, Lx)
+        for dt in range(-2, 3):
+            for dx in range(-2, 3):
+                m = ((t + dt) % Lt) * Lx + (x + dx) % Lx
+                out[n, (dt + 2) * 5 + dx + 2] = A[n * b:(n + 1) * b, m * b:(m + 1) * b].toarray()
+    return out
+
+
+SETUP_CASES = [
+    # L, beta, levels, a, o, nv, norm, m0
+    (16, 3.0, 2, 4, 1, 4, amg.NORM_TESTVEC, 0.1),
+    (32, 6.0, 3, 4, 1, 8, amg.NORM_TESTVEC, 0.05),
+    (32, 6.0, 2, 8, 2, 4, amg.NORM_TESTVEC, 0.05),
+    (16, 2.0, 2, 4, 1, 1, amg.NORM_CONST, 0.2),
+    (24, 4.0, 2, 6, 2, 2, amg.NORM_NONE, 0.1),
+]
+
+
+@pytest.mark.parametrize("case", SETUP_CASES)
+def test_setup_matches_oracle(lib, ctx, case):
+    L, beta, levels, a, o, nv, norm, m0 = case
+    say("setup", case)
+    U = synth.gen_links(L, L, beta, 50, 300 + L)
+    prm = amg.SetupParams(levels=levels, agg=a, overlap=o, n_test_vectors=nv, norm=norm, seed=11)
+    olev = amg.setup(U, m0, prm)
+    g = make_gauge(lib, ctx, U, m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=levels, agg_size=a, overlap=o,
+                                                   n_test_vectors=nv, norm=norm, seed=11))
+    for k in range(levels - 1):
+        lev = olev[k]
+        assert h.level_info(k) == (lev.Lt, lev.Lx, lev.b)
+        kind, owner, node = h.aggregates(k)
+        assert np.array_equal(kind, lev.cls["kind"])
+        assert np.array_equal(owner, lev.cls["owner"])
+        assert np.array_equal(node, lev.cls["node"])
+        if norm == amg.NORM_TESTVEC:
+            tv = h.test_vectors(k, nv)
+            assert rel(tv, lev.test_vectors) < 1e-12
+        rows = h.prolongator_rows(k, o)
+        ref = oracle_rows(lev, a, o)
+        assert rel(rows, ref) < 1e-10
+        nxt = olev[k + 1]
+        if nxt.coarsest:
+            Ac = h.coarse_operator(k + 1, coarsest=True)
+            assert rel(Ac, nxt.A.toarray()) < 1e-10
+        else:
+            Ac = h.coarse_operator(k + 1, coarsest=False)
+            assert rel(Ac, oracle_stencil(nxt.A, nxt.Lt, nxt.Lx, nxt.b)) < 1e-10
+    h.close()
+    g.close()
+
+
+# ------------------------------------------------------------------------------ solves
+
+def run_pair(lib, ctx, U, m0, psi, levels, a, o, nv, precision=0, tol=1e-10, restart=20,
+             olevels=None):
+    prm = amg.SetupParams(levels=levels, agg=a, overlap=o, n_test_vectors=nv)
+    xo, info_o, olevels = oracle_solve(U, m0, psi, prm, restart=restart, tol=tol, levels=olevels)
+    g = make_gauge(lib, ctx, U, m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=levels, agg_size=a, overlap=o,
+                                                   n_test_vectors=nv))
+    sp = lib.default_solve_params(precision=precision, rel_tol=tol, restart=restart)
+    x, infos, st = h.solve(synth.field_to_abi(psi[None]), sp)
+    hist, flags = h.residual_history(0)
+    h.close()
+    g.close()
+    return xo, info_o, synth.field_from_abi(x)[0], infos[0], st, hist, flags, olevels
+
+
+def test_c1_fp64_solve_matches_oracle(lib, ctx):
+    w = synth.WORKLOADS["C1"]
+    say("C1 solve")
+    U = w.links()
+    psi = synth.gaussian_rhs(w.L, w.L, w.rhs_seed)[0]
+    xo, io, x, ig, st, hist, flags, _ = run_pair(lib, ctx, U, w.m0, psi, w.levels, w.agg,
+                                                 w.overlap, w.n_test_vectors)
+    assert st == lib.OK and ig.converged
+    assert ig.iterations == io.iterations
+    assert ig.restarts == io.restarts
+    assert rel(x, xo) <= 1e-9
+    oh = np.array([v for v, _ in io.history])
+    of = np.array([f for _, f in io.history])
+    assert np.array_equal(flags, of)
+    assert np.allclose(hist, oh, rtol=1e-6, atol=1e-14)
+    D = dirac_matrix(U, w.m0)
+    r = psi.reshape(-1) - D @ x.reshape(-1)
+    assert np.linalg.norm(r) / np.linalg.norm(psi) <= 1e-10
+
+
+def test_c2_fp64_mass_sweep_matches_oracle(lib, ctx):
+    w = synth.WORKLOADS["C2"]
+    mc = synth.critical_masses()["C2"]
+    U = w.links()
+    for i, gap in enumerate(w.gaps):
+        say("C2 gap", gap)
+        psi = synth.gaussian_rhs(w.L, w.L, w.rhs_seed + i)[0]
+        xo, io, x, ig, st, _, _, _ = run_pair(lib, ctx, U, mc + gap, psi, w.levels, w.agg,
+                                              w.overlap, w.n_test_vectors)
+        assert ig.converged and io.converged
+        assert ig.iterations == io.iterations, (gap, ig.iterations, io.iterations)
+        assert rel(x, xo) <= 1e-9
+
+
+@pytest.mark.parametrize("precision,bound", [(1, 1e-9), (2, 1e-8)])
+def test_c2_mixed_precision_within_bound(lib, ctx, precision, bound):
+    w = synth.WORKLOADS["C2"]
+    mc = synth.critical_masses()["C2"]
+    U = w.links()
+    gap = 0.02
+    psi = synth.gaussian_rhs(w.L, w.L, w.rhs_seed + 2)[0]
+    say("C2 mixed", precision)
+    xo, io, x, ig, st, _, _, _ = run_pair(lib, ctx, U, mc + gap, psi, w.levels, w.agg, w.overlap,
+                                          w.n_test_vectors, precision=precision)
+    assert ig.converged and ig.true_rel_residual <= 1e-10
+    assert rel(x, xo) <= bound
+    # iteration counts are reported, not gated; they stay close to FP64
+    assert abs(ig.iterations - io.iterations) <= max(5, io.iterations // 10)
+
+
+def test_batched_rhs_equal_to_single(lib, ctx):
+    w = synth.WORKLOADS["C1"]
+    U = w.links()
+    psi = synth.gaussian_rhs(w.L, w.L, 77, nrhs=4)
+    g = make_gauge(lib, ctx, U, w.m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=2, agg_size=4, overlap=1, n_test_vectors=4))
+    xb, ib, _ = h.solve(synth.field_to_abi(psi))
+    for r in range(4):
+        x1, i1, _ = h.solve(synth.field_to_abi(psi[r:r + 1]))
+        assert i1[0].iterations == ib[r].iterations
+        assert np.array_equal(x1[0], xb[r])          # same kernels, same order: bitwise
+    h.close()
+    g.close()
+
+
+def test_invalid_shapes_and_args(lib, ctx):
+    U = np.ones((2, 16, 16), dtype=complex)
+    g = make_gauge(lib, ctx, U, 0.1)
+    with pytest.raises(lib.AmamgError) as e:
+        lib.Hierarchy(g, lib.default_setup_params(agg_size=5))
+    assert e.value.status == -2
+    with pytest.raises(lib.AmamgError) as e:
+        lib.Hierarchy(g, lib.default_setup_params(agg_size=4, overlap=4))
+    assert e.value.status == -2
+    with pytest.raises(lib.AmamgError) as e:
+        lib.Gauge(ctx, synth.links_to_abi(np.ones((2, 15, 16), dtype=complex)), 0.1)
+    assert e.value.status == -2
+    bad = synth.links_to_abi(U)
+    bad[0, 3, 3, 0] = np.nan
+    with pytest.raises(lib.AmamgError) as e:
+        lib.Gauge(ctx, bad, 0.1)
+    assert e.value.status == -7
+    h = lib.Hierarchy(g, lib.default_setup_params())
+    psi = synth.field_to_abi(synth.gaussian_rhs(16, 16, 1))
+    psi[0, 1, 1, 0, 0] = np.inf
+    with pytest.raises(lib.AmamgError) as e:
+        h.solve(psi)
+    assert e.value.status == -7
+    # iteration cap: NOT_CONVERGED with outputs written
+    psi = synth.field_to_abi(synth.gaussian_rhs(16, 16, 1))
+    x, infos, st = h.solve(psi, lib.default_solve_params(max_iters=3))
+    assert st == lib.NOT_CONVERGED and infos[0].iterations == 3 and not infos[0].converged
+    with pytest.raises(lib.AmamgError):
+        g.close()          # hierarchy still alive
+    h.close()
+    g.close()
+
+
+def test_c3_full_size_setup_sampled_parity(lib, ctx):
+    """256x256, a = 8, o = 2, 3 levels: classification bit-exact, sampled interpolation rows and
+    coarse blocks against the oracle's setup."""
+    w = synth.WORKLOADS["C3"]
+    m0 = synth.critical_masses()["C3"] + w.gaps[0]
+    U = w.links()
+    say("C3 setup parity")
+    prm = amg.SetupParams(levels=3, agg=8, overlap=2, n_test_vectors=8)
+    olev = amg.setup(U, m0, prm)
+    g = make_gauge(lib, ctx, U, m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=8, overlap=2, n_test_vectors=8))
+    kind, owner, node = h.aggregates(0)
+    assert np.array_equal(kind, olev[0].cls["kind"]) and np.array_equal(owner, olev[0].cls["owner"])
+    rows = h.prolongator_rows(0, 2)
+    P = olev[0].P.tocsr()
+    rng = np.random.default_rng(0)
+    for p in rng.choice(256 * 256, 200, replace=False):
+        if olev[0].cls["kind"][p] == KIND_V:
+            continue
+        wb = olev[0].cls["owner"][p]
+        I, J = divmod(int(wb), 32)
+        for c in range(4):
+            nd = ((I + (c >> 1)) % 32) * 32 + (J + (c & 1)) % 32
+            ref = P[2 * p:2 * p + 2, nd * 8:(nd + 1) * 8].toarray()
+            assert np.abs(rows[p, :, c * 8:(c + 1) * 8] - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+    A1 = h.coarse_operator(1, coarsest=False)
+    ref1 = olev[1].A.tocsr()
+    for n in rng.choice(1024, 40, replace=False):
+        t, x = divmod(int(n), 32)
+        for off in (0, 1, 7, 12, 13, 17, 24):
+            dt, dx = off // 5 - 2, off % 5 - 2
+            m = ((t + dt) % 32) * 32 + (x + dx) % 32
+            blk = ref1[n * 8:(n + 1) * 8, m * 8:(m + 1) * 8].toarray()
+            assert np.abs(A1[n, off] - blk).max() <= 1e-10 * max(1.0, np.abs(ref1[n * 8:(n + 1) * 8].toarray()).max())
+    A2 = h.coarse_operator(2, coarsest=True)
+    assert rel(A2, olev[2].A.toarray()) < 1e-10
+    h.close()
+    g.close()
