@@ -110,11 +110,19 @@ amamg_status amamg_gauge_load(amamg_context *ctx, int32_t nt, int32_t nx, const 
                               double m0, amamg_gauge **out);
 /* Change m0; hierarchies built from this gauge keep the mass they were built with. */
 amamg_status amamg_gauge_set_mass(amamg_gauge *g, double m0);
+/* Replace the links (host pointer, same layout and size as at load).  Hierarchies keep their
+ * operators until amamg_hierarchy_update. */
+amamg_status amamg_gauge_update_links(amamg_gauge *g, const double *links);
 amamg_status amamg_gauge_destroy(amamg_gauge *g);
 
 /* AM-AMG setup (Multilevel approach section: coarsening, interpolation, Galerkin operator)
  * with aggregate size and overlap from params (NULL: defaults).  Runs on the GPU. */
 amamg_status amamg_setup(amamg_gauge *g, const amamg_setup_params *params, amamg_hierarchy **out);
+/* Re-run the setup of an existing hierarchy in place, from the gauge's current links and mass
+ * and the parameters it was created with.  Reuses the hierarchy's device memory: after the
+ * first setup it allocates nothing.  Same errors as amamg_setup; on error the hierarchy must
+ * not be used for solves until an update succeeds. */
+amamg_status amamg_hierarchy_update(amamg_hierarchy *h);
 amamg_status amamg_hierarchy_destroy(amamg_hierarchy *h);
 
 /* Solve D x = psi for nrhs right-hand sides (host pointers, layout above).  info: array of
@@ -140,6 +148,11 @@ amamg_status amamg_residual_history(const amamg_hierarchy *h, int32_t rhs, doubl
 /* out = D in for nrhs fields at the given precision (FP64 or FP32 links). */
 amamg_status amamg_apply_dirac(amamg_gauge *g, int32_t precision, int32_t nrhs,
                                const double *in, double *out);
+/* out = D in on device buffers (same layout) at the given precision: AMAMG_FP64 uses FP64
+ * fields and links; the mixed modes use FP32 fields ([nrhs][nt][nx][2][2] float) with FP32
+ * or BF16 links.  Asynchronous on the context stream. */
+amamg_status amamg_apply_dirac_device(amamg_gauge *g, int32_t precision, int32_t nrhs,
+                                      const void *in_dev, void *out_dev);
 /* Grid of level `level` (0 = fine lattice) and degrees of freedom per node. */
 amamg_status amamg_level_info(const amamg_hierarchy *h, int32_t level, int32_t *lt,
                               int32_t *lx, int32_t *b);

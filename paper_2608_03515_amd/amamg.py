@@ -29,9 +29,10 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARG", -2: "UNSUPPORTED
 
 EXPORTED = ["amamg_default_setup_params", "amamg_default_solve_params", "amamg_context_create",
             "amamg_context_destroy", "amamg_last_error", "amamg_gauge_load",
-            "amamg_gauge_set_mass", "amamg_gauge_destroy", "amamg_setup",
-            "amamg_hierarchy_destroy", "amamg_solve", "amamg_solve_device",
-            "amamg_residual_history", "amamg_apply_dirac", "amamg_level_info",
+            "amamg_gauge_set_mass", "amamg_gauge_update_links", "amamg_gauge_destroy",
+            "amamg_setup", "amamg_hierarchy_update", "amamg_hierarchy_destroy", "amamg_solve", "amamg_solve_device",
+            "amamg_residual_history", "amamg_apply_dirac", "amamg_apply_dirac_device",
+            "amamg_level_info",
             "amamg_get_aggregates", "amamg_get_prolongator", "amamg_get_coarse_operator",
             "amamg_get_test_vectors"]
 
@@ -63,13 +64,16 @@ _sig = {
     "amamg_last_error": (C.c_char_p, [_vp]),
     "amamg_gauge_load": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, C.c_double, _P(_vp)]),
     "amamg_gauge_set_mass": (C.c_int, [_vp, C.c_double]),
+    "amamg_gauge_update_links": (C.c_int, [_vp, _vp]),
     "amamg_gauge_destroy": (C.c_int, [_vp]),
     "amamg_setup": (C.c_int, [_vp, _P(SetupParams), _P(_vp)]),
+    "amamg_hierarchy_update": (C.c_int, [_vp]),
     "amamg_hierarchy_destroy": (C.c_int, [_vp]),
     "amamg_solve": (C.c_int, [_vp, C.c_int32, _vp, _vp, _P(SolveParams), _P(SolveInfo)]),
     "amamg_solve_device": (C.c_int, [_vp, C.c_int32, _vp, _vp, _P(SolveParams), _P(SolveInfo)]),
     "amamg_residual_history": (C.c_int, [_vp, C.c_int32, _vp, _vp, C.c_int32, _P(C.c_int32)]),
     "amamg_apply_dirac": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _vp]),
+    "amamg_apply_dirac_device": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _vp]),
     "amamg_level_info": (C.c_int, [_vp, C.c_int32, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32)]),
     "amamg_get_aggregates": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp]),
     "amamg_get_prolongator": (C.c_int, [_vp, C.c_int32, _vp]),
@@ -148,12 +152,21 @@ class Gauge:
     def set_mass(self, m0: float):
         self.ctx.check(_lib.amamg_gauge_set_mass(self.h, float(m0)))
 
+    def update_links(self, links: np.ndarray):
+        links = np.ascontiguousarray(links, dtype=np.float64)
+        assert links.shape == (2, self.nt, self.nx, 2)
+        self.ctx.check(_lib.amamg_gauge_update_links(self.h, _ptr(links)))
+
     def apply_dirac(self, fields: np.ndarray, precision: int = FP64) -> np.ndarray:
         fields = np.ascontiguousarray(fields, dtype=np.float64)
         out = np.empty_like(fields)
         nrhs = fields.shape[0]
         self.ctx.check(_lib.amamg_apply_dirac(self.h, precision, nrhs, _ptr(fields), _ptr(out)))
         return out
+
+    def apply_dirac_device(self, in_ptr: int, out_ptr: int, nrhs: int, precision: int = FP64):
+        """Asynchronous D on device buffers (FP64 fields for FP64, FP32 fields otherwise)."""
+        self.ctx.check(_lib.amamg_apply_dirac_device(self.h, precision, nrhs, _vp(in_ptr), _vp(out_ptr)))
 
     def close(self):
         if self.h:
@@ -168,6 +181,10 @@ class Hierarchy:
         h = _vp()
         gauge.ctx.check(_lib.amamg_setup(gauge.h, C.byref(params) if params else None, C.byref(h)))
         self.gauge, self.ctx, self.h = gauge, gauge.ctx, h
+
+    def update(self):
+        """Re-run the setup in place from the gauge's current links and mass."""
+        self.ctx.check(_lib.amamg_hierarchy_update(self.h))
 
     def close(self):
         if self.h:

@@ -4,91 +4,135 @@
 // A coarse operator is stored as a 5 x 5 block stencil: node n couples to n + (dt, dx),
 // dt, dx in [-2, 2], through a b x b complex block A[n][(dt+2)*5 + (dx+2)][i][j] (node-major:
 // everything a node needs is contiguous).  Coarse vectors are [rhs][node][b] complex.
+//
+// Lane layout (block size B a power of two, B <= 64): the lanes of one node cover its B rows,
+// LJ lanes per row; lane (i, jl) handles columns jl, jl + LJ, ...  With B*B <= 64 one wave
+// holds 64 / (B*B) nodes and reads whole B x B blocks per offset in one coalesced access;
+// otherwise one node per wave.  Row sums are finished with xor shuffles inside the LJ lanes.
 #include "launch.hpp"
 
 namespace amamg {
 
-__device__ inline int wrapi(int v, int L) { v %= L; return v < 0 ? v + L : v; }
+template <int B> struct Lanes {
+  static constexpr int LJ = (B * B <= 64) ? B : 64 / B;     // lanes per row
+  static constexpr int CPL = B / LJ;                        // columns per lane
+  static constexpr int LPN = B * LJ;                        // lanes per node
+  static constexpr int NPW = 64 / LPN;                      // nodes per wave
+  static constexpr int NPB = 4 * NPW;                       // nodes per 256-thread block
+};
 
-// One thread per (node, row i): y[n][i] = sum_d sum_j A[n][d][i][j] x[n+d][j]  (or f - that)
-template <typename R, typename M, typename Vin, typename Vout>
+__device__ inline int wrap1(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
+
+template <int LJ, typename R> __device__ inline R group_sum(R v) {
+#pragma unroll
+  for (int off = LJ >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// y[n] = sum_d A[n][d] x[n+d]   (or f - that)
+template <int B, typename R, typename M, typename Vin, typename Vout>
 __global__ __launch_bounds__(256) void k_stencil_apply(const M* __restrict__ A,
                                                        const Vin* __restrict__ x,
                                                        Vout* __restrict__ y,
                                                        const Vout* __restrict__ f, int Lt, int Lx,
-                                                       int b, int64_t stride,
+                                                       int64_t stride,
                                                        const RhsState* __restrict__ st) {
+  using Ly = Lanes<B>;
+  using C = cplx<R>;
   const int r = blockIdx.y;
   if (st && !st[r].active) return;
-  const int64_t gid = int64_t(xcd_block(blockIdx.x, gridDim.x)) * 256 + threadIdx.x;
-  if (gid >= int64_t(Lt) * Lx * b) return;
-  using C = cplx<R>;
-  const int n = int(gid / b), i = int(gid - int64_t(n) * b);
-  const int t = n / Lx, xc = n - t * Lx;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int slot = lane / Ly::LPN, i = (lane / Ly::LJ) % B, jl = lane % Ly::LJ;
+  const int n = (xcd_block(blockIdx.x, gridDim.x) * 4 + wv) * Ly::NPW + slot;
+  const bool live = n < Lt * Lx;
+  const int nn = live ? n : 0;
+  const int t = nn / Lx, xc = nn - t * Lx;
   const Vin* xr = x + r * stride;
-  const M* An = A + int64_t(n) * 25 * b * b + int64_t(i) * b;
+  const M* An = A + int64_t(nn) * 25 * B * B + i * B;
   C acc = czero<R>();
+#pragma unroll
   for (int dt = -2; dt <= 2; ++dt) {
-    const int tt = wrapi(t + dt, Lt);
+    const int tt = wrap1(t + dt, Lt) * Lx;
+#pragma unroll
     for (int dx = -2; dx <= 2; ++dx) {
-      const int m = tt * Lx + wrapi(xc + dx, Lx);
-      const M* blk = An + int64_t((dt + 2) * 5 + (dx + 2)) * b * b;
-      const Vin* xm = xr + int64_t(m) * b;
-      for (int j = 0; j < b; ++j) acc = cfma(cconv<C>(blk[j]), cconv<C>(xm[j]), acc);
-    }
-  }
-  Vout* yr = y + r * stride;
-  if (f) acc = csub(cconv<C>(f[r * stride + gid]), acc);
-  yr[gid] = cconv<Vout>(acc);
-}
-
-// Colour c = (I mod 4) * 4 + (J mod 4); nodes of one colour do not couple (stencil reach 2).
-// Lanes of one node sit in one wavefront (b divides 64), so the b-vector of residuals is
-// exchanged with shuffles before applying Dinv_n.
-template <typename R, typename M, typename Vx>
-__global__ __launch_bounds__(256) void k_stencil_gs(const M* __restrict__ A,
-                                                    const M* __restrict__ Dinv, Vx* x,
-                                                    const Vx* __restrict__ f, int Lt, int Lx,
-                                                    int b, int colour, int64_t stride,
-                                                    const RhsState* __restrict__ st) {
-  const int r = blockIdx.y;
-  if (st && !st[r].active) return;
-  const int gid = blockIdx.x * 256 + threadIdx.x;
-  const int qx = Lx >> 2;
-  const int ncn = (Lt >> 2) * qx;                 // nodes of this colour
-  const int k = gid / b, i = gid - (gid / b) * b;
-  const bool live = k < ncn;
-  using C = cplx<R>;
-  C res = czero<R>();
-  int n = 0;
-  if (live) {
-    const int ct = colour >> 2, cx = colour & 3;
-    const int t = 4 * (k / qx) + ct, xc = 4 * (k % qx) + cx;
-    n = t * Lx + xc;
-    const Vx* xr = x + r * stride;
-    const M* An = A + int64_t(n) * 25 * b * b + int64_t(i) * b;
-    if (f) res = cconv<C>(f[r * stride + int64_t(n) * b + i]);
-    for (int dt = -2; dt <= 2; ++dt) {
-      const int tt = wrapi(t + dt, Lt);
-      for (int dx = -2; dx <= 2; ++dx) {
-        if (dt == 0 && dx == 0) continue;
-        const int m = tt * Lx + wrapi(xc + dx, Lx);
-        const M* blk = An + int64_t((dt + 2) * 5 + (dx + 2)) * b * b;
-        const Vx* xm = xr + int64_t(m) * b;
-        for (int j = 0; j < b; ++j) res = csub(res, cmul(cconv<C>(blk[j]), cconv<C>(xm[j])));
+      const int m = tt + wrap1(xc + dx, Lx);
+      const M* blk = An + ((dt + 2) * 5 + (dx + 2)) * B * B;
+      const Vin* xm = xr + int64_t(m) * B;
+#pragma unroll
+      for (int c = 0; c < Ly::CPL; ++c) {
+        const int j = jl + Ly::LJ * c;
+        acc = cfma(cconv<C>(blk[j]), cconv<C>(xm[j]), acc);
       }
     }
   }
-  // x_n[i] = sum_j Dinv[n][i][j] res_j, res_j held by lane (lane - i + j)
-  const int lane = threadIdx.x & (AMAMG_WAVE - 1);
-  const int base = lane - i;
-  C out = czero<R>();
-  const M* Dn = Dinv + int64_t(n) * b * b + int64_t(i) * b;
-  for (int j = 0; j < b; ++j) {
-    R re = __shfl(res.x, base + j), im = __shfl(res.y, base + j);
-    if (live) out = cfma(cconv<C>(Dn[j]), mk<R>(re, im), out);
+  acc.x = group_sum<Ly::LJ>(acc.x);
+  acc.y = group_sum<Ly::LJ>(acc.y);
+  if (live && jl == 0) {
+    const int64_t o = r * stride + int64_t(n) * B + i;
+    if (f) acc = csub(cconv<C>(f[o]), acc);
+    y[o] = cconv<Vout>(acc);
   }
-  if (live) x[r * stride + int64_t(n) * b + i] = cconv<Vx>(out);
+}
+
+// Colour c = (I mod 4) * 4 + (J mod 4); nodes of one colour do not couple (stencil reach 2).
+// x_n <- Dinv_n (f_n - sum_{d != 0} A_nd x_{n+d})  (equals x_n + Dinv_n (f - A x)_n).
+template <int B, typename R, typename M, typename Vx>
+__global__ __launch_bounds__(256) void k_stencil_gs(const M* __restrict__ A,
+                                                    const M* __restrict__ Dinv, Vx* x,
+                                                    const Vx* __restrict__ f, int Lt, int Lx,
+                                                    int colour, int64_t stride,
+                                                    const RhsState* __restrict__ st) {
+  using Ly = Lanes<B>;
+  using C = cplx<R>;
+  const int r = blockIdx.y;
+  if (st && !st[r].active) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int slot = lane / Ly::LPN, i = (lane / Ly::LJ) % B, jl = lane % Ly::LJ;
+  const int k = (blockIdx.x * 4 + wv) * Ly::NPW + slot;
+  const int qx = Lx >> 2;
+  const int ncn = (Lt >> 2) * qx;
+  const bool live = k < ncn;
+  const int kk = live ? k : 0;
+  const int t = 4 * (kk / qx) + (colour >> 2), xc = 4 * (kk % qx) + (colour & 3);
+  const int n = t * Lx + xc;
+  Vx* xr = x + r * stride;
+  const M* An = A + int64_t(n) * 25 * B * B + i * B;
+  C acc = czero<R>();
+#pragma unroll
+  for (int dt = -2; dt <= 2; ++dt) {
+    const int tt = wrap1(t + dt, Lt) * Lx;
+#pragma unroll
+    for (int dx = -2; dx <= 2; ++dx) {
+      if (dt == 0 && dx == 0) continue;
+      const int m = tt + wrap1(xc + dx, Lx);
+      const M* blk = An + ((dt + 2) * 5 + (dx + 2)) * B * B;
+      const Vx* xm = xr + int64_t(m) * B;
+#pragma unroll
+      for (int c = 0; c < Ly::CPL; ++c) {
+        const int j = jl + Ly::LJ * c;
+        acc = cfma(cconv<C>(blk[j]), cconv<C>(xm[j]), acc);
+      }
+    }
+  }
+  acc.x = group_sum<Ly::LJ>(acc.x);
+  acc.y = group_sum<Ly::LJ>(acc.y);
+  C res = acc;
+  res.x = -res.x;
+  res.y = -res.y;
+  if (f && live) res = cadd(res, cconv<C>(f[r * stride + int64_t(n) * B + i]));
+  // x_n[i] = sum_j Dinv[n][i][j] res_j; res_j sits in every lane of row j of this node
+  const int node_lane0 = slot * Ly::LPN;
+  const M* Dn = Dinv + int64_t(n) * B * B + i * B;
+  C out = czero<R>();
+#pragma unroll
+  for (int c = 0; c < Ly::CPL; ++c) {
+    const int j = jl + Ly::LJ * c;
+    const R re = __shfl(res.x, node_lane0 + j * Ly::LJ), im = __shfl(res.y, node_lane0 + j * Ly::LJ);
+    out = cfma(cconv<C>(Dn[j]), mk<R>(re, im), out);
+  }
+  out.x = group_sum<Ly::LJ>(out.x);
+  out.y = group_sum<Ly::LJ>(out.y);
+  if (live && jl == 0) xr[int64_t(n) * B + i] = cconv<Vx>(out);
 }
 
 // y = Ainv v for the coarsest level (matrix FP64): 64 lanes per row, 4 rows per block.
@@ -117,31 +161,57 @@ __global__ __launch_bounds__(256) void k_dense_apply(const double2* __restrict__
 
 // ------------------------------------------------------------------------------ launchers
 
+template <int B, typename R, typename M, typename V>
+static void apply_b(hipStream_t s, const void* A, const void* x, void* y, const void* f, int Lt,
+                    int Lx, int nrhs, int64_t stride, const RhsState* st) {
+  const int nn = Lt * Lx;
+  dim3 g(unsigned((nn + Lanes<B>::NPB - 1) / Lanes<B>::NPB), unsigned(nrhs));
+  hipLaunchKernelGGL((k_stencil_apply<B, R, M, V, V>), g, dim3(256), 0, s, (const M*)A, (const V*)x,
+                     (V*)y, (const V*)f, Lt, Lx, stride, st);
+}
+
+template <int B, typename R, typename M, typename V>
+static void gs_b(hipStream_t s, const void* A, const void* D, void* x, const void* f, int Lt, int Lx,
+                 int colour, int nrhs, int64_t stride, const RhsState* st) {
+  const int ncn = (Lt / 4) * (Lx / 4);
+  dim3 g(unsigned((ncn + Lanes<B>::NPB - 1) / Lanes<B>::NPB), unsigned(nrhs));
+  hipLaunchKernelGGL((k_stencil_gs<B, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
+                     (const V*)f, Lt, Lx, colour, stride, st);
+}
+
+#define AMAMG_B_DISPATCH(fn, prec, ...)                                                       \
+  do {                                                                                        \
+    if (prec == F64) {                                                                        \
+      switch (b) {                                                                            \
+        case 2: fn<2, double, double2, double2>(__VA_ARGS__); break;                          \
+        case 4: fn<4, double, double2, double2>(__VA_ARGS__); break;                          \
+        case 8: fn<8, double, double2, double2>(__VA_ARGS__); break;                          \
+        case 16: fn<16, double, double2, double2>(__VA_ARGS__); break;                        \
+        case 32: fn<32, double, double2, double2>(__VA_ARGS__); break;                        \
+        case 64: fn<64, double, double2, double2>(__VA_ARGS__); break;                        \
+        default: break;                                                                       \
+      }                                                                                       \
+    } else {                                                                                  \
+      switch (b) {                                                                            \
+        case 2: fn<2, float, float2, float2>(__VA_ARGS__); break;                             \
+        case 4: fn<4, float, float2, float2>(__VA_ARGS__); break;                             \
+        case 8: fn<8, float, float2, float2>(__VA_ARGS__); break;                             \
+        case 16: fn<16, float, float2, float2>(__VA_ARGS__); break;                           \
+        case 32: fn<32, float, float2, float2>(__VA_ARGS__); break;                           \
+        case 64: fn<64, float, float2, float2>(__VA_ARGS__); break;                           \
+        default: break;                                                                       \
+      }                                                                                       \
+    }                                                                                         \
+  } while (0)
+
 void stencil_apply(hipStream_t s, Real prec, const void* A, const void* x, void* y, const void* f,
                    int Lt, int Lx, int b, int nrhs, int64_t stride, const RhsState* st) {
-  dim3 g(unsigned((int64_t(Lt) * Lx * b + 255) / 256), unsigned(nrhs));
-  if (prec == F64)
-    hipLaunchKernelGGL((k_stencil_apply<double, double2, double2, double2>), g, dim3(256), 0, s,
-                       (const double2*)A, (const double2*)x, (double2*)y, (const double2*)f, Lt,
-                       Lx, b, stride, st);
-  else
-    hipLaunchKernelGGL((k_stencil_apply<float, float2, float2, float2>), g, dim3(256), 0, s,
-                       (const float2*)A, (const float2*)x, (float2*)y, (const float2*)f, Lt, Lx,
-                       b, stride, st);
+  AMAMG_B_DISPATCH(apply_b, prec, s, A, x, y, f, Lt, Lx, nrhs, stride, st);
 }
 
 void stencil_gs(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
                 int Lt, int Lx, int b, int colour, int nrhs, int64_t stride, const RhsState* st) {
-  const int ncn = (Lt / 4) * (Lx / 4);
-  dim3 g(unsigned((ncn * b + 255) / 256), unsigned(nrhs));
-  if (prec == F64)
-    hipLaunchKernelGGL((k_stencil_gs<double, double2, double2>), g, dim3(256), 0, s,
-                       (const double2*)A, (const double2*)Dinv, (double2*)x, (const double2*)f, Lt,
-                       Lx, b, colour, stride, st);
-  else
-    hipLaunchKernelGGL((k_stencil_gs<float, float2, float2>), g, dim3(256), 0, s,
-                       (const float2*)A, (const float2*)Dinv, (float2*)x, (const float2*)f, Lt, Lx,
-                       b, colour, stride, st);
+  AMAMG_B_DISPATCH(gs_b, prec, s, A, Dinv, x, f, Lt, Lx, colour, nrhs, stride, st);
 }
 
 void dense_apply(hipStream_t s, Real prec, const double2* Ainv, const void* v, void* y, int n,

@@ -1,14 +1,17 @@
 // FGMRES(m) kernels, FP64 (paper: FGMRES outer solver, relative tolerance 1e-10).
 //
-// Right-preconditioned flexible Arnoldi with classical Gram-Schmidt applied twice.  All
-// reductions are two-pass and fixed-order (per-block partial sums, then a sum over blocks in
-// block order), so results are bitwise reproducible.  Givens rotation for (a, b) =
-// (H_jj, H_{j+1,j}): nu = sqrt(|a|^2 + |b|^2), c = |a| / nu, s = (a / |a|) conj(b) / nu
-// (c = 0, s = 1 when a = 0); a rotation maps (x, y) -> (c x + s y, -conj(s) x + c y).
+// Right-preconditioned flexible Arnoldi with classical Gram-Schmidt applied twice.  Every
+// reduction is two-level and fixed-order: each block writes its partial sums, and the block
+// that finishes last (a device-scope counter decides which) adds the partials in block
+// order.  Results are therefore bitwise reproducible although blocks finish in any order.
+// The last block also runs the scalar bookkeeping that needs the reduced value (Hessenberg
+// column, Givens rotations, cycle start and end), so no extra launch is spent on it.
+//
+// Givens rotation for (a, b) = (H_jj, H_{j+1,j}): nu = sqrt(|a|^2 + |b|^2), c = |a| / nu,
+// s = (a / |a|) conj(b) / nu (c = 0, s = 1 when a = 0); a rotation maps (x, y) to
+// (c x + s y, -conj(s) x + c y); g_{j+1} = -conj(s) g_j, g_j = c g_j.
 //
 // Vector layouts: basis V [j][rhs][n], search directions Z [j][rhs][n], w and x [rhs][n].
-// Scalars per right-hand side live in RhsState and small arrays on the device; the host
-// reads them once per cycle.
 #include "launch.hpp"
 
 namespace amamg {
@@ -16,13 +19,13 @@ namespace amamg {
 #define KMAXV 32
 
 template <int NV>
-__device__ inline void block_reduce_store(double2 (&acc)[NV], int nv, double2* out, double* lds) {
-  // lds: 2 * NV * 4 doubles
+__device__ inline void block_partial(const double2 (&acc)[NV], int nv, double2* out, double* lds) {
+  // lds: NV * 4 * 2 doubles; writes nv block totals to out[0..nv)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     if (i < nv) {
-      double re = wave_sum(acc[i].x), im = wave_sum(acc[i].y);
+      const double re = wave_sum(acc[i].x), im = wave_sum(acc[i].y);
       if (lane == 0) { lds[(i * 4 + wv) * 2] = re; lds[(i * 4 + wv) * 2 + 1] = im; }
     }
   }
@@ -34,15 +37,121 @@ __device__ inline void block_reduce_store(double2 (&acc)[NV], int nv, double2* o
   }
 }
 
-// part[r][blk][i] = sum_{d in block} conj(V_i[r][d]) w[r][d]
-__global__ __launch_bounds__(256) void k_dots_partial(KrylovDims dm, const double2* __restrict__ V,
-                                                      int64_t vsj, int nv,
-                                                      const double2* __restrict__ w,
-                                                      double2* __restrict__ part,
-                                                      const RhsState* __restrict__ st) {
+// After block_partial: returns true in the block that arrives last; that block then holds in
+// fin[0..nv) the sums over all blocks, added in block order.
+__device__ inline bool last_block_sum(const double2* part_r, int nv, unsigned* counter,
+                                      double2* fin /* shared [KMAXV] */,
+                                      double2* scratch /* shared [8][KMAXV] */) {
+  __shared__ int amlast;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) amlast = (atomicAdd(counter, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (!amlast) return false;
+  __threadfence();
+  // thread (i, c): column i, blocks c, c + 8, ...; eight independent partial sums keep the
+  // loads in flight, then combine in a fixed order
+  const int i = threadIdx.x & (KMAXV - 1), c = threadIdx.x / KMAXV;   // 8 groups of 32
+  double2 s = make_double2(0, 0);
+  if (i < nv) {
+    double2 q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) q[u] = make_double2(0, 0);
+    const int nb = int(gridDim.x);
+    for (int b = c; b < nb; b += 64) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (b + 8 * u < nb) q[u] = cadd(q[u], part_r[int64_t(b + 8 * u) * KMAXV + i]);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s = cadd(s, q[u]);
+  }
+  scratch[c * KMAXV + i] = s;
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    double2 t = make_double2(0, 0);
+    for (int q = 0; q < 8; ++q) t = cadd(t, scratch[q * KMAXV + threadIdx.x]);
+    fin[threadIdx.x] = t;
+  }
+  if (threadIdx.x == 0) *counter = 0u;
+  __syncthreads();
+  return true;
+}
+
+__device__ inline bool finite_d(double v) { return v == v && v - v == 0.0; }
+
+struct ArnoldiArgs {
+  double2* H;       // [rhs][(m+1) m], H[i][j] at i*m + j
+  double* cs;       // [rhs][m]
+  double2* sn;      // [rhs][m]
+  double2* g;       // [rhs][m+1]
+  const double2* h1;  // [rhs][KMAXV]
+  const double2* h2;
+  int j;
+  double tol, inner_tol;
+  int max_iters;
+  double2* hist;
+  int hist_cap;
+};
+
+// Arnoldi step j for one rhs, given hn = ||w|| after CGS2.
+__device__ inline void arnoldi_step(const KrylovDims& dm, RhsState& s, int r, double hn,
+                                    const ArnoldiArgs& a) {
+  const int m = dm.m, j = a.j;
+  double2* Hr = a.H + int64_t(r) * (m + 1) * m;
+  double* csr = a.cs + int64_t(r) * m;
+  double2* snr = a.sn + int64_t(r) * m;
+  double2* gr = a.g + int64_t(r) * (m + 1);
+  for (int i = 0; i <= j; ++i) Hr[i * m + j] = cadd(a.h1[r * KMAXV + i], a.h2[r * KMAXV + i]);
+  Hr[(j + 1) * m + j] = make_double2(hn, 0.0);
+  for (int i = 0; i < j; ++i) {
+    const double2 x = Hr[i * m + j], y = Hr[(i + 1) * m + j];
+    const double c = csr[i];
+    const double2 sv = snr[i];
+    Hr[i * m + j] = cadd(cscale(x, c), cmul(sv, y));
+    Hr[(i + 1) * m + j] = csub(cscale(y, c), cmulc(sv, x));
+  }
+  const double2 av = Hr[j * m + j], bv = Hr[(j + 1) * m + j];
+  double c;
+  double2 sv;
+  const double aa = sqrt(cabs2(av));
+  if (aa == 0.0) {
+    c = 0.0;
+    sv = make_double2(1.0, 0.0);
+  } else {
+    const double nu = sqrt(cabs2(av) + cabs2(bv));
+    c = aa / nu;
+    sv = cscale(cmul(make_double2(av.x / aa, av.y / aa), cconj(bv)), 1.0 / nu);
+  }
+  Hr[j * m + j] = cadd(cscale(av, c), cmul(sv, bv));
+  Hr[(j + 1) * m + j] = make_double2(0, 0);
+  csr[j] = c;
+  snr[j] = sv;
+  const double2 gj = gr[j];
+  gr[j + 1] = cscale(cmulc(sv, gj), -1.0);
+  gr[j] = cscale(gj, c);
+  s.iters += 1;
+  s.k = j + 1;
+  const double gabs = sqrt(cabs2(gr[j + 1]));
+  s.est = gabs / s.bnorm;
+  if (s.hist_len < a.hist_cap) a.hist[int64_t(r) * a.hist_cap + s.hist_len++] = make_double2(s.est, 0.0);
+  bool end = (gabs <= a.tol * s.bnorm) || (hn <= 1e-300 * s.bnorm) || (s.iters >= a.max_iters) ||
+             (j + 1 == m) || (a.inner_tol > 0.0 && gabs <= a.inner_tol * s.beta);
+  if (!finite_d(hn) || !finite_d(gabs)) { s.nonfinite = 1; end = true; }
+  if (end) s.active = 0;
+  else s.inv_h = 1.0 / hn;
+}
+
+// h = V^H w  (V_0 .. V_{nv-1}); final sums to hout[r][0..nv)
+__global__ __launch_bounds__(256) void k_dots(KrylovDims dm, const double2* __restrict__ V,
+                                              int64_t vsj, int nv, const double2* __restrict__ w,
+                                              double2* __restrict__ part, unsigned* __restrict__ cnt,
+                                              double2* __restrict__ hout,
+                                              const RhsState* __restrict__ st) {
   const int r = blockIdx.y;
   if (st && !st[r].active) return;
   __shared__ double lds[2 * KMAXV * 4];
+  __shared__ double2 fin[KMAXV], scratch[8 * KMAXV];
   double2 acc[KMAXV];
 #pragma unroll
   for (int i = 0; i < KMAXV; ++i) acc[i] = make_double2(0, 0);
@@ -54,112 +163,84 @@ __global__ __launch_bounds__(256) void k_dots_partial(KrylovDims dm, const doubl
     for (int i = 0; i < KMAXV; ++i)
       if (i < nv) acc[i] = cfmac(Vr[i * vsj + d], wd, acc[i]);
   }
-  block_reduce_store<KMAXV>(acc, nv, part + (int64_t(r) * gridDim.x + blockIdx.x) * KMAXV, lds);
+  double2* pr = part + int64_t(r) * gridDim.x * KMAXV;
+  block_partial<KMAXV>(acc, nv, pr + int64_t(blockIdx.x) * KMAXV, lds);
+  if (last_block_sum(pr, nv, cnt + r, fin, scratch) && threadIdx.x < nv)
+    hout[r * KMAXV + threadIdx.x] = fin[threadIdx.x];
 }
 
-// w -= sum_i V_i h_i, then (mode 1) part = V^H w_new, or (mode 2) part[0] = |w_new|^2
-__global__ __launch_bounds__(256) void k_update_partial(KrylovDims dm, const double2* __restrict__ V,
-                                                        int64_t vsj, int nv, double2* __restrict__ w,
-                                                        const double2* __restrict__ h, int hstride,
-                                                        double2* __restrict__ part, int mode,
-                                                        const RhsState* __restrict__ st) {
+// w -= sum_i V_i h_i; mode 1: h' = V^H w_new to hout; mode 2: ||w_new|| and Arnoldi step j.
+template <int NVC>
+__global__ __launch_bounds__(256) void k_update(KrylovDims dm, const double2* __restrict__ V,
+                                                int64_t vsj, int nv, double2* __restrict__ w,
+                                                const double2* __restrict__ h,
+                                                double2* __restrict__ part,
+                                                unsigned* __restrict__ cnt,
+                                                double2* __restrict__ hout, int mode,
+                                                RhsState* __restrict__ st, ArnoldiArgs aa) {
   const int r = blockIdx.y;
-  if (st && !st[r].active) return;
+  if (!st[r].active) return;
   __shared__ double lds[2 * KMAXV * 4];
-  __shared__ double2 hs[KMAXV];
-  if (threadIdx.x < nv) hs[threadIdx.x] = h[r * hstride + threadIdx.x];
+  __shared__ double2 hs[KMAXV], fin[KMAXV], scratch[8 * KMAXV];
+  if (threadIdx.x < nv) hs[threadIdx.x] = h[r * KMAXV + threadIdx.x];
   __syncthreads();
-  double2 acc[KMAXV];
+  double2 acc[NVC];
 #pragma unroll
-  for (int i = 0; i < KMAXV; ++i) acc[i] = make_double2(0, 0);
+  for (int i = 0; i < NVC; ++i) acc[i] = make_double2(0, 0);
   double2* wr = w + r * dm.n;
   const double2* Vr = V + r * dm.n;
   for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < dm.n; d += int64_t(gridDim.x) * 256) {
-    double2 v[KMAXV];
     double2 wd = wr[d];
 #pragma unroll
     for (int i = 0; i < KMAXV; ++i)
-      if (i < nv) { v[i] = Vr[i * vsj + d]; wd = csub(wd, cmul(v[i], hs[i])); }
+      if (i < nv) wd = csub(wd, cmul(Vr[i * vsj + d], hs[i]));
     wr[d] = wd;
-    if (mode == 1) {
+    if (NVC > 1) {
 #pragma unroll
-      for (int i = 0; i < KMAXV; ++i)
-        if (i < nv) acc[i] = cfmac(v[i], wd, acc[i]);
+      for (int i = 0; i < NVC; ++i)
+        if (i < nv) acc[i] = cfmac(Vr[i * vsj + d], wd, acc[i]);
     } else {
       acc[0].x += cabs2(wd);
     }
   }
-  block_reduce_store<KMAXV>(acc, mode == 1 ? nv : 1, part + (int64_t(r) * gridDim.x + blockIdx.x) * KMAXV, lds);
+  const int nout = NVC > 1 ? nv : 1;
+  double2* pr = part + int64_t(r) * gridDim.x * KMAXV;
+  block_partial<NVC>(acc, nout, pr + int64_t(blockIdx.x) * KMAXV, lds);
+  if (!last_block_sum(pr, nout, cnt + r, fin, scratch)) return;
+  if (mode == 1) {
+    if (threadIdx.x < nv) hout[r * KMAXV + threadIdx.x] = fin[threadIdx.x];
+  } else if (threadIdx.x == 0) {
+    RhsState s = st[r];
+    arnoldi_step(dm, s, r, sqrt(fin[0].x), aa);
+    st[r] = s;
+  }
 }
 
-// out[r*ostride + i] = sum over blocks (in block order) of part[r][blk][i]
-__global__ void k_sum_partials(int nblk, const double2* __restrict__ part, int nv,
-                               double2* __restrict__ out, int ostride,
-                               const RhsState* __restrict__ st) {
-  const int r = blockIdx.x;
-  if (st && !st[r].active) return;
-  const int i = threadIdx.x;
-  if (i >= nv) return;
-  double2 acc = make_double2(0, 0);
-  for (int b = 0; b < nblk; ++b) acc = cadd(acc, part[(int64_t(r) * nblk + b) * KMAXV + i]);
-  out[r * ostride + i] = acc;
-}
+// ||x||^2 per rhs, then: mode 0 store only; 1 start states (x = b); 2 first cycle start
+// (x = r_0); 3 end of a cycle (x = b - D x): convergence test and the next cycle's start.
+struct CycleArgs {
+  double2* g;
+  double tol;
+  int max_iters;
+  double2* hist;
+  int hist_cap;
+};
 
-__global__ __launch_bounds__(256) void k_norm_partial(KrylovDims dm, const double2* __restrict__ x,
-                                                      double2* __restrict__ part,
-                                                      const RhsState* __restrict__ st,
-                                                      int only_active) {
-  const int r = blockIdx.y;
-  if (only_active && st && !st[r].active) return;
-  __shared__ double lds[2 * KMAXV * 4];
-  double2 acc[1] = {make_double2(0, 0)};
-  const double2* xr = x + r * dm.n;
-  for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < dm.n; d += int64_t(gridDim.x) * 256)
-    acc[0].x += cabs2(xr[d]);
-  block_reduce_store<1>(acc, 1, part + (int64_t(r) * gridDim.x + blockIdx.x) * KMAXV, lds);
-}
-
-__device__ inline double part_norm(const double2* part, int r, int nblk) {
-  double s = 0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t(r) * nblk + b) * KMAXV].x;
-  return sqrt(s);
-}
-
-__device__ inline bool finite_d(double v) { return v == v && v - v == 0.0; }
-
-// ||b|| and a fresh state per right-hand side
-__global__ void k_init_states(KrylovDims dm, RhsState* __restrict__ st, const double2* __restrict__ part) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= dm.nrhs) return;
-  RhsState s = {};
-  s.bnorm = part_norm(part, r, dm.nblk);
-  s.true_res = 1.0;
-  if (!finite_d(s.bnorm)) { s.nonfinite = 1; s.done = 1; }
-  else if (s.bnorm == 0.0) { s.converged = 1; s.done = 1; s.true_res = 0.0; }
-  s.active = s.done ? 0 : 1;   // the first residual is computed for every live rhs
-  s.in_cycle = s.active;
-  st[r] = s;
-}
-
-// Called with part = |r|^2 partials of r = b - D x (stored in V_0).  first: the residual of the
-// start vector; otherwise the true residual after a cycle.  Starts the next cycle when needed.
-__global__ void k_cycle_begin(KrylovDims dm, RhsState* __restrict__ st, const double2* __restrict__ part,
-                              double2* __restrict__ g, double tol, int first, int max_iters,
-                              double2* __restrict__ hist, int hist_cap) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= dm.nrhs) return;
-  RhsState s = st[r];
+__device__ inline void begin_cycle(const KrylovDims& dm, RhsState& s, int r, double beta,
+                                   int first, const CycleArgs& ca) {
   if (s.done || !s.in_cycle || s.nonfinite) {
     if (s.nonfinite) s.done = 1;
-    s.active = 0; s.in_cycle = 0; st[r] = s; return;
+    s.active = 0;
+    s.in_cycle = 0;
+    return;
   }
-  const double beta = part_norm(part, r, dm.nblk);
   s.true_res = beta / s.bnorm;
-  if (!finite_d(beta)) { s.nonfinite = 1; s.done = 1; s.active = 0; s.in_cycle = 0; st[r] = s; return; }
-  if (!first && s.hist_len < hist_cap) hist[int64_t(r) * hist_cap + s.hist_len++] = make_double2(s.true_res, 1.0);
-  if (beta <= tol * s.bnorm) {
+  if (!finite_d(beta)) { s.nonfinite = 1; s.done = 1; s.active = 0; s.in_cycle = 0; return; }
+  if (!first && s.hist_len < ca.hist_cap)
+    ca.hist[int64_t(r) * ca.hist_cap + s.hist_len++] = make_double2(s.true_res, 1.0);
+  if (beta <= ca.tol * s.bnorm) {
     s.converged = 1; s.done = 1; s.active = 0; s.in_cycle = 0;
-  } else if (s.iters >= max_iters) {
+  } else if (s.iters >= ca.max_iters) {
     s.done = 1; s.active = 0; s.in_cycle = 0;
   } else {
     if (!first) s.restarts += 1;
@@ -168,69 +249,41 @@ __global__ void k_cycle_begin(KrylovDims dm, RhsState* __restrict__ st, const do
     s.k = 0;
     s.active = 1;
     s.in_cycle = 1;
-    double2* gr = g + int64_t(r) * (dm.m + 1);
+    double2* gr = ca.g + int64_t(r) * (dm.m + 1);
     gr[0] = make_double2(beta, 0.0);
     for (int i = 1; i <= dm.m; ++i) gr[i] = make_double2(0, 0);
   }
-  st[r] = s;
 }
 
-// Arnoldi step j: new Hessenberg column, rotations, residual estimate, end-of-cycle test.
-__global__ void k_arnoldi_finish(KrylovDims dm, RhsState* __restrict__ st, const double2* __restrict__ part,
-                                 const double2* __restrict__ h1, const double2* __restrict__ h2,
-                                 double2* __restrict__ H, double* __restrict__ cs,
-                                 double2* __restrict__ sn, double2* __restrict__ g, int j,
-                                 double tol, double inner_tol, int max_iters,
-                                 double2* __restrict__ hist, int hist_cap) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= dm.nrhs) return;
-  RhsState s = st[r];
-  if (!s.active) return;
-  const int m = dm.m;
-  double2* Hr = H + int64_t(r) * (m + 1) * m;     // H[i][j] at i*m + j
-  double* csr = cs + int64_t(r) * m;
-  double2* snr = sn + int64_t(r) * m;
-  double2* gr = g + int64_t(r) * (m + 1);
-  const double hn = part_norm(part, r, dm.nblk);
-  for (int i = 0; i <= j; ++i) Hr[i * m + j] = cadd(h1[r * KMAXV + i], h2[r * KMAXV + i]);
-  Hr[(j + 1) * m + j] = make_double2(hn, 0.0);
-  for (int i = 0; i < j; ++i) {
-    const double2 x = Hr[i * m + j], y = Hr[(i + 1) * m + j];
-    const double c = csr[i];
-    const double2 sv = snr[i];
-    Hr[i * m + j] = cadd(cscale(x, c), cmul(sv, y));
-    Hr[(i + 1) * m + j] = csub(cscale(y, c), cmulc(sv, x));
+__global__ __launch_bounds__(256) void k_norm(KrylovDims dm, const double2* __restrict__ x,
+                                              double2* __restrict__ part, unsigned* __restrict__ cnt,
+                                              RhsState* __restrict__ st, int mode, CycleArgs ca) {
+  const int r = blockIdx.y;
+  if (mode >= 2 && !st[r].active) return;
+  __shared__ double lds[2 * KMAXV * 4];
+  __shared__ double2 fin[KMAXV], scratch[8 * KMAXV];
+  double2 acc[1] = {make_double2(0, 0)};
+  const double2* xr = x + r * dm.n;
+  for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < dm.n; d += int64_t(gridDim.x) * 256)
+    acc[0].x += cabs2(xr[d]);
+  double2* pr = part + int64_t(r) * gridDim.x * KMAXV;
+  block_partial<1>(acc, 1, pr + int64_t(blockIdx.x) * KMAXV, lds);
+  if (!last_block_sum(pr, 1, cnt + r, fin, scratch) || threadIdx.x != 0) return;
+  const double nrm = sqrt(fin[0].x);
+  if (mode == 1) {
+    RhsState s = {};
+    s.bnorm = nrm;
+    s.true_res = 1.0;
+    if (!finite_d(nrm)) { s.nonfinite = 1; s.done = 1; }
+    else if (nrm == 0.0) { s.converged = 1; s.done = 1; s.true_res = 0.0; }
+    s.active = s.done ? 0 : 1;
+    s.in_cycle = s.active;
+    st[r] = s;
+  } else if (mode >= 2) {
+    RhsState s = st[r];
+    begin_cycle(dm, s, r, nrm, mode == 2, ca);
+    st[r] = s;
   }
-  const double2 a = Hr[j * m + j], bb = Hr[(j + 1) * m + j];
-  double c;
-  double2 sv;
-  const double aa = sqrt(cabs2(a));
-  if (aa == 0.0) {
-    c = 0.0;
-    sv = make_double2(1.0, 0.0);
-  } else {
-    const double nu = sqrt(cabs2(a) + cabs2(bb));
-    c = aa / nu;
-    sv = cscale(cmul(make_double2(a.x / aa, a.y / aa), cconj(bb)), 1.0 / nu);
-  }
-  Hr[j * m + j] = cadd(cscale(a, c), cmul(sv, bb));
-  Hr[(j + 1) * m + j] = make_double2(0, 0);
-  csr[j] = c;
-  snr[j] = sv;
-  const double2 gj = gr[j];
-  gr[j + 1] = cscale(cmulc(sv, gj), -1.0);
-  gr[j] = cscale(gj, c);
-  s.iters += 1;
-  s.k = j + 1;
-  const double gabs = sqrt(cabs2(gr[j + 1]));
-  s.est = gabs / s.bnorm;
-  if (s.hist_len < hist_cap) hist[int64_t(r) * hist_cap + s.hist_len++] = make_double2(s.est, 0.0);
-  bool end = (gabs <= tol * s.bnorm) || (hn <= 1e-300 * s.bnorm) || (s.iters >= max_iters) ||
-             (j + 1 == m) || (inner_tol > 0.0 && gabs <= inner_tol * s.beta);
-  if (!finite_d(hn) || !finite_d(gabs)) { s.nonfinite = 1; end = true; }
-  if (end) s.active = 0;
-  else s.inv_h = 1.0 / hn;
-  st[r] = s;
 }
 
 __global__ __launch_bounds__(256) void k_scale_next(KrylovDims dm, const double2* __restrict__ w,
@@ -283,51 +336,35 @@ __global__ __launch_bounds__(256) void k_update_x(KrylovDims dm, const RhsState*
   x[r * dm.n + d] = acc;
 }
 
-__global__ void k_copy(const double2* __restrict__ x, double2* __restrict__ y, int64_t n) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = x[i];
-}
-
 // ------------------------------------------------------------------------------ launchers
 
-void dots_partial(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
-                  const double2* w, double2* part, const RhsState* st) {
-  hipLaunchKernelGGL(k_dots_partial, dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, nv, w, part, st);
+void dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
+          const double2* w, double2* part, unsigned* cnt, double2* hout, const RhsState* st) {
+  hipLaunchKernelGGL(k_dots, dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, nv, w, part, cnt, hout, st);
 }
 
-void update_partial(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
-                    double2* w, const double2* h, int hstride, double2* part, int mode,
-                    const RhsState* st) {
-  hipLaunchKernelGGL(k_update_partial, dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, nv, w, h,
-                     hstride, part, mode, st);
+void update_dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
+                 double2* w, const double2* h, double2* part, unsigned* cnt, double2* hout,
+                 RhsState* st) {
+  ArnoldiArgs aa{};
+  hipLaunchKernelGGL((k_update<KMAXV>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, nv, w, h,
+                     part, cnt, hout, 1, st, aa);
 }
 
-void sum_partials(hipStream_t s, const KrylovDims& d, const double2* part, int nv, double2* out,
-                  int ostride, const RhsState* st) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(d.nrhs), dim3(64), 0, s, d.nblk, part, nv, out, ostride, st);
+void update_norm_arnoldi(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
+                         double2* w, const double2* h2, double2* part, unsigned* cnt, RhsState* st,
+                         double2* H, double* cs, double2* sn, double2* g, const double2* h1, int j,
+                         double tol, double inner_tol, int max_iters, double2* hist, int hist_cap) {
+  ArnoldiArgs aa{H, cs, sn, g, h1, h2, j, tol, inner_tol, max_iters, hist, hist_cap};
+  hipLaunchKernelGGL((k_update<1>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, nv, w, h2,
+                     part, cnt, (double2*)nullptr, 2, st, aa);
 }
 
-void norm_partial(hipStream_t s, const KrylovDims& d, const double2* x, double2* part,
-                  const RhsState* st, int only_active) {
-  hipLaunchKernelGGL(k_norm_partial, dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, x, part, st, only_active);
-}
-
-void init_states(hipStream_t s, const KrylovDims& d, RhsState* st, const double2* part) {
-  hipLaunchKernelGGL(k_init_states, dim3((d.nrhs + 63) / 64), dim3(64), 0, s, d, st, part);
-}
-
-void cycle_begin(hipStream_t s, const KrylovDims& d, RhsState* st, const double2* part, double2* g,
-                 double tol, int first, int max_iters, double2* hist, int hist_cap) {
-  hipLaunchKernelGGL(k_cycle_begin, dim3((d.nrhs + 63) / 64), dim3(64), 0, s, d, st, part, g, tol,
-                     first, max_iters, hist, hist_cap);
-}
-
-void arnoldi_finish(hipStream_t s, const KrylovDims& d, RhsState* st, const double2* part,
-                    const double2* h1, const double2* h2, double2* H, double* cs, double2* sn,
-                    double2* g, int j, double tol, double inner_tol, int max_iters,
-                    double2* hist, int hist_cap) {
-  hipLaunchKernelGGL(k_arnoldi_finish, dim3((d.nrhs + 63) / 64), dim3(64), 0, s, d, st, part, h1, h2,
-                     H, cs, sn, g, j, tol, inner_tol, max_iters, hist, hist_cap);
+void norm_control(hipStream_t s, const KrylovDims& d, const double2* x, double2* part, unsigned* cnt,
+                  RhsState* st, int mode, double2* g, double tol, int max_iters, double2* hist,
+                  int hist_cap) {
+  CycleArgs ca{g, tol, max_iters, hist, hist_cap};
+  hipLaunchKernelGGL(k_norm, dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, x, part, cnt, st, mode, ca);
 }
 
 void scale_next(hipStream_t s, const KrylovDims& d, const double2* w, double2* v, const RhsState* st) {
@@ -344,11 +381,5 @@ void backsolve_update(hipStream_t s, const KrylovDims& d, RhsState* st, const do
   else
     hipLaunchKernelGGL((k_update_x<float2>), grid, dim3(256), 0, s, d, st, y, (const float2*)Z, zsj, x);
 }
-
-void copy_vec(hipStream_t s, const double2* x, double2* y, int64_t n) {
-  hipLaunchKernelGGL(k_copy, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, x, y, n);
-}
-
-void zero_vec(hipStream_t s, void* x, int64_t bytes) { (void)hipMemsetAsync(x, 0, bytes, s); }
 
 }  // namespace amamg

@@ -58,23 +58,30 @@ void dense_apply(hipStream_t s, Real prec, const double2* Ainv, const void* v, v
 void prolong(hipStream_t s, Real prec, const void* P, const int* owner, const int* node,
              const void* e, void* y, const Geom& g, int add, int nrhs, int64_t stride_f,
              int64_t stride_c, const RhsState* st);
-// rc = P^H r; r in `rin` precision (FP64 basis vector or prec), rc in prec
-void restrict_(hipStream_t s, Real prec, const void* P, const int* owner, Real rin,
-               const void* r, void* rc, const Geom& g, int nrhs, int64_t stride_f,
-               int64_t stride_c, const RhsState* st);
+// rc = P^H r; r in `rin` precision (FP64 basis vector or prec), rc in prec.  rows/nrows: the
+// owned fine rows of each wirebasket (owned_rows); part: scratch of
+// nrhs * nW * restrict_chunks(g, nf) * ncol complex values in prec.
+int restrict_chunks(const Geom& g, int nf);
+void owned_rows(hipStream_t s, const Geom& g, const int* fpos, int nf, const int* owner, int* rows,
+                int* nrows);
+void restrict_(hipStream_t s, Real prec, const void* P, const int* rows, const int* nrows, int nf,
+               Real rin, const void* r, void* rc, void* part, const Geom& g, int nrhs,
+               int64_t stride_f, int64_t stride_c, const RhsState* st);
 
 // ---- setup -------------------------------------------------------------------------------
 void classify(hipStream_t s, const Geom& g, int8_t* kind, int* owner, int* node);
 void testvec_hash(hipStream_t s, uint64_t seed, int level, int nv, int64_t ndof, double2* W);
 void inject(hipStream_t s, const Geom& g, const int* node, const int8_t* kind, const double2* w,
             double2* wc, int nv);
-// local systems of every wirebasket: Aff [W][nfd][nfd], Bneg = -A_FV [W][nfd][ncol]
+// local systems of every wirebasket: Aug [W][nfd][nfd + ncol] = [A_FF | -A_FV]
 void gather_local(hipStream_t s, const Geom& g, const double2* A, int noff, const int* offs_dev,
-                  const int* postab, int nf, double2* Aff, double2* Bneg);
-// batched LU with partial pivoting (one workgroup per system) and solves
-void lu_factor(hipStream_t s, double2* A, int n, int nsys, int* piv, int* info);
-void lu_solve(hipStream_t s, const double2* LU, const int* piv, int n, int nsys, double2* B,
-              int nrhs);
+                  const int* postab, int nf, double2* Aug);
+// batched dense solves on augmented [A | B] (n x (n + nrhs) row-major per system): B <- A^-1 B
+void dense_solve(hipStream_t s, double2* Aug, int n, int nrhs, int nsys, int* info);
+void aug_extract(hipStream_t s, const double2* Aug, int n, int nrhs, double2* out, int nsys);
+// Aug = [A | I] from nsys n x n blocks at stride astride with row stride arow
+void aug_identity(hipStream_t s, const double2* A, int64_t astride, int arow, int n, double2* Aug,
+                  int nsys);
 void scatter_P(hipStream_t s, const Geom& g, const double2* X, const int* postab, int nf,
                const int* owner, double2* P);
 // P rows scaled by the normalisation (mode 0 TESTVEC, 1 CONST; 2 NONE is a no-op)
@@ -84,37 +91,32 @@ void probe_make(hipStream_t s, const Geom& gc, int pt, int px, int ct, int cx, d
 // scatter probe results u [bc][ndof_c] into the coarse stencil [node][25][bc][bc] or dense
 void probe_extract(hipStream_t s, const Geom& gc, int pt, int px, int ct, int cx,
                    const double2* u, double2* out, int dense);
-void extract_diag(hipStream_t s, const double2* A, int nnode, int b, double2* D);
-void set_identity(hipStream_t s, double2* B, int n, int nsys);
 void cast_matrix(hipStream_t s, const double2* A, float2* out, int64_t n);
 
 // ---- Krylov (FP64) -----------------------------------------------------------------------
-// partial sums per block: out[rhs][blk][i] = sum conj(V_i) w over the block's range, i < nv
+// Reductions finish in the last block to arrive (per-rhs counters, zero between launches).
 struct KrylovDims { int64_t n; int nrhs; int nblk; int m; };
-void dots_partial(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vstride_j,
-                  int nv, const double2* w, double2* part, const RhsState* st);
-// w -= sum_i V_i h_i; then dots of the updated w (mode 1) or its squared norm (mode 2)
-void update_partial(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vstride_j,
-                     int nv, double2* w, const double2* h, int hstride, double2* part, int mode,
-                     const RhsState* st);
-void sum_partials(hipStream_t s, const KrylovDims& d, const double2* part, int nv, double2* out,
-                  int ostride, const RhsState* st);
-void norm_partial(hipStream_t s, const KrylovDims& d, const double2* x, double2* part,
-                  const RhsState* st, int only_active);
-// per-rhs cycle control (see krylov.hip)
-void cycle_begin(hipStream_t s, const KrylovDims& d, RhsState* st, const double2* part, double2* g,
-                 double tol, int first, int max_iters, double2* hist, int hist_cap);
-void arnoldi_finish(hipStream_t s, const KrylovDims& d, RhsState* st, const double2* part,
-                    const double2* h1, const double2* h2, double2* H, double* cs, double2* sn,
-                    double2* g, int j, double tol, double inner_tol, int max_iters,
-                    double2* hist, int hist_cap);
+// hout[r][i] = (V_i^H w)_r for i < nv
+void dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
+          const double2* w, double2* part, unsigned* cnt, double2* hout, const RhsState* st);
+// w -= V h; hout = V^H w_new
+void update_dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
+                 double2* w, const double2* h, double2* part, unsigned* cnt, double2* hout,
+                 RhsState* st);
+// w -= V h2; h_{j+1,j} = ||w||; Hessenberg column h1 + h2, rotations, end-of-cycle test
+void update_norm_arnoldi(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
+                         double2* w, const double2* h2, double2* part, unsigned* cnt, RhsState* st,
+                         double2* H, double* cs, double2* sn, double2* g, const double2* h1, int j,
+                         double tol, double inner_tol, int max_iters, double2* hist, int hist_cap);
+// ||x|| then mode 1: fresh states (x = b); 2: first cycle start (x = r_0); 3: cycle end and
+// restart (x = b - D x)
+void norm_control(hipStream_t s, const KrylovDims& d, const double2* x, double2* part, unsigned* cnt,
+                  RhsState* st, int mode, double2* g, double tol, int max_iters, double2* hist,
+                  int hist_cap);
 void scale_next(hipStream_t s, const KrylovDims& d, const double2* w, double2* v,
                 const RhsState* st);
 void backsolve_update(hipStream_t s, const KrylovDims& d, RhsState* st, const double2* H,
                       const double2* g, double2* y, Real zprec, const void* Z,
                       int64_t zstride_j, double2* x);
-void init_states(hipStream_t s, const KrylovDims& d, RhsState* st, const double2* part);
-void copy_vec(hipStream_t s, const double2* x, double2* y, int64_t n);
-void zero_vec(hipStream_t s, void* x, int64_t bytes);
 
 }  // namespace amamg

@@ -52,6 +52,33 @@ struct Arena {
   ~Arena() { release(); }
 };
 
+// Device buffers looked up by (name, level): allocated on first use, reused afterwards, so a
+// repeated setup on the same hierarchy allocates nothing.
+struct Pool {
+  struct Item { std::string key; void* p; size_t bytes; };
+  std::vector<Item> items;
+  template <typename T> T* get(const char* name, int level, size_t count) {
+    if (count == 0) count = 1;
+    const std::string key = std::string(name) + "#" + std::to_string(level);
+    for (Item& it : items)
+      if (it.key == key) {
+        if (it.bytes >= count * sizeof(T)) return static_cast<T*>(it.p);
+        (void)hipFree(it.p);
+        it.p = nullptr;
+        HIPCHECK(hipMalloc(&it.p, count * sizeof(T)));
+        it.bytes = count * sizeof(T);
+        return static_cast<T*>(it.p);
+      }
+    void* p = nullptr;
+    HIPCHECK(hipMalloc(&p, count * sizeof(T)));
+    items.push_back({key, p, count * sizeof(T)});
+    return static_cast<T*>(p);
+  }
+  ~Pool() {
+    for (Item& it : items) (void)hipFree(it.p);
+  }
+};
+
 int period_of(int L) {
   for (int d = 5; d <= L; ++d)
     if (L % d == 0) return d;
@@ -76,6 +103,8 @@ struct amamg_gauge {
   double2* U = nullptr;     // [2][nt*nx]
   float2* U32 = nullptr;
   bf16c* U16 = nullptr;
+  int version = 0;          // bumped by amamg_gauge_update_links
+  int v32 = -1, v16 = -1;   // version the low-precision copies were made from
 };
 
 namespace {
@@ -97,6 +126,11 @@ struct LevelData {
   double2* P = nullptr;      // [nnode][b][4 bc]
   float2* P32 = nullptr;
   double2* tv = nullptr;     // smoothed test vectors [nv][ndof]
+  int* tabs = nullptr;       // footprint tables: postab [fp] then fpos [nf]
+  int nf = 0;                // F positions per wirebasket footprint
+  int* rows = nullptr;       // owned fine rows per wirebasket [nW][nf*b]
+  int* nrows = nullptr;      // their counts [nW]
+  void* rpart = nullptr;     // restriction partial sums (solve workspace)
   // solve workspace (k >= 1): right-hand side, iterate, scratch
   void* f = nullptr;
   void* x = nullptr;
@@ -110,7 +144,7 @@ struct amamg_hierarchy {
   amamg_setup_params prm{};
   double m0 = 0;
   std::vector<LevelData> lv;
-  Arena mem;       // setup products
+  Pool mem;        // setup products and setup scratch
   Arena ws;        // solve workspace
   int ws_nrhs = 0, ws_m = 0, ws_hist = 0;
   Real ws_prec = F64;
@@ -119,6 +153,7 @@ struct amamg_hierarchy {
   double* cs = nullptr;
   void* Z = nullptr;
   RhsState* st = nullptr;
+  unsigned* cnt = nullptr;   // reduction counters [4][nrhs]
   int nblk = 1;
   std::vector<std::vector<double2>> history;
 };
@@ -228,18 +263,17 @@ void run_setup(amamg_hierarchy* h) {
   }
   const double2* U0 = gg->U;
   const double2* U1 = gg->U + int64_t(gg->nt) * gg->nx;
-  Arena tmp;   // setup temporaries
   const int nv = (p.norm == AMAMG_NORM_TESTVEC) ? p.n_test_vectors : 0;
 
   // fine operator in block-stencil form, used to gather the wirebasket systems
-  double2* A0 = tmp.alloc<double2>(size_t(gg->nt) * gg->nx * 5 * 4);
+  double2* A0 = h->mem.get<double2>("A0", -1, size_t(gg->nt) * gg->nx * 5 * 4);
   build_fine_stencil(s, U0, U1, gg->nt, gg->nx, h->m0, A0);
   const int offs5[10] = {0, 0, 1, 0, -1, 0, 0, 1, 0, -1};
   int offs25[50];
   for (int dt = -2, q = 0; dt <= 2; ++dt)
     for (int dx = -2; dx <= 2; ++dx, ++q) { offs25[2 * q] = dt; offs25[2 * q + 1] = dx; }
-  int* d_offs5 = tmp.alloc<int>(10);
-  int* d_offs25 = tmp.alloc<int>(50);
+  int* d_offs5 = h->mem.get<int>("d_offs5", -1, 10);
+  int* d_offs25 = h->mem.get<int>("d_offs25", -1, 50);
   HIPCHECK(hipMemcpyAsync(d_offs5, offs5, sizeof(offs5), hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(d_offs25, offs25, sizeof(offs25), hipMemcpyHostToDevice, s));
 
@@ -249,15 +283,15 @@ void run_setup(amamg_hierarchy* h) {
     const Geom& g = L.g;
     const int nnode = g.nnode();
     const int64_t ndof = g.ndof();
-    L.kind = h->mem.alloc<int8_t>(nnode);
-    L.owner = h->mem.alloc<int>(nnode);
-    L.node = h->mem.alloc<int>(nnode);
+    L.kind = h->mem.get<int8_t>("L_kind", k, nnode);
+    L.owner = h->mem.get<int>("L_owner", k, nnode);
+    L.node = h->mem.get<int>("L_node", k, nnode);
     classify(s, g, L.kind, L.owner, L.node);
     check_launch();
 
     // test vectors: random at level 0, injected from the finer level otherwise; nu sweeps
     if (nv > 0) {
-      L.tv = h->mem.alloc<double2>(size_t(nv) * ndof);
+      L.tv = h->mem.get<double2>("L_tv", k, size_t(nv) * ndof);
       if (k == 0) testvec_hash(s, p.seed, 0, nv, ndof, L.tv);
       else HIPCHECK(hipMemcpyAsync(L.tv, W, sizeof(double2) * nv * ndof, hipMemcpyDeviceToDevice, s));
       for (int sw = 0; sw < p.test_vector_sweeps; ++sw) {
@@ -275,16 +309,19 @@ void run_setup(amamg_hierarchy* h) {
     // local Schur-complement interpolation per wirebasket
     int nf = 0;
     const std::vector<int> tabs = footprint_tables(a, o, g.b, &nf);
-    int* d_tabs = tmp.alloc<int>(tabs.size());
+    int* d_tabs = h->mem.get<int>("d_tabs", k, tabs.size());
+    L.tabs = d_tabs;
+    L.nf = nf;
+    L.rows = h->mem.get<int>("L_rows", k, size_t(g.nI) * g.nJ * nf * g.b);
+    L.nrows = h->mem.get<int>("L_nrows", k, size_t(g.nI) * g.nJ);
     HIPCHECK(hipMemcpyAsync(d_tabs, tabs.data(), sizeof(int) * tabs.size(), hipMemcpyHostToDevice, s));
+    owned_rows(s, g, d_tabs + g.fp(), nf, L.owner, L.rows, L.nrows);
     const int nW = g.nI * g.nJ, nfd = nf * g.b, ncol = g.ncol();
-    double2* Aff = tmp.alloc<double2>(size_t(nW) * nfd * nfd);
-    double2* Bn = tmp.alloc<double2>(size_t(nW) * nfd * ncol);
-    int* piv = tmp.alloc<int>(size_t(nW) * nfd);
-    int* info = tmp.alloc<int>(nW);
-    if (k == 0) gather_local(s, g, A0, 5, d_offs5, d_tabs, nf, Aff, Bn);
-    else gather_local(s, g, L.A, 25, d_offs25, d_tabs, nf, Aff, Bn);
-    lu_factor(s, Aff, nfd, nW, piv, info);
+    double2* Aug = h->mem.get<double2>("Aug", k, size_t(nW) * nfd * (nfd + ncol));
+    int* info = h->mem.get<int>("info", k, nW);
+    if (k == 0) gather_local(s, g, A0, 5, d_offs5, d_tabs, nf, Aug);
+    else gather_local(s, g, L.A, 25, d_offs25, d_tabs, nf, Aug);
+    dense_solve(s, Aug, nfd, ncol, nW, info);
     check_launch();
     std::vector<int> hinfo(nW);
     HIPCHECK(hipMemcpyAsync(hinfo.data(), info, sizeof(int) * nW, hipMemcpyDeviceToHost, s));
@@ -292,10 +329,9 @@ void run_setup(amamg_hierarchy* h) {
     for (int w = 0; w < nW; ++w)
       REQUIRE(hinfo[w] == 0, AMAMG_ERR_SINGULAR_LOCAL,
               "zero pivot in the local system of wirebasket " + std::to_string(w) + " on level " + std::to_string(k));
-    lu_solve(s, Aff, piv, nfd, nW, Bn, ncol);
-    L.P = h->mem.alloc<double2>(size_t(ndof) * ncol);
+    L.P = h->mem.get<double2>("L_P", k, size_t(ndof) * ncol);
     HIPCHECK(hipMemsetAsync(L.P, 0, sizeof(double2) * ndof * ncol, s));
-    scatter_P(s, g, Bn, d_tabs, nf, L.owner, L.P);
+    scatter_P(s, g, Aug, d_tabs, nf, L.owner, L.P);
     check_launch();
 
     // normalisation (and the test vectors handed to the next level)
@@ -303,7 +339,7 @@ void run_setup(amamg_hierarchy* h) {
     const Geom gc = coarse_geom_of(g);
     const int64_t ndof_c = gc.ndof();
     if (nv > 0) {
-      Wc = tmp.alloc<double2>(size_t(nv) * ndof_c);
+      Wc = h->mem.get<double2>("Wc", k, size_t(nv) * ndof_c);
       inject(s, g, L.node, L.kind, L.tv, Wc, nv);
     }
     normalise(s, g, L.P, L.owner, L.tv, Wc, nv, p.norm);
@@ -318,18 +354,19 @@ void run_setup(amamg_hierarchy* h) {
     const int pt = period_of(gc.Lt), px = period_of(gc.Lx);
     double2* out = nullptr;
     if (dense) {
-      C.Adense = h->mem.alloc<double2>(size_t(ndof_c) * ndof_c);
+      C.Adense = h->mem.get<double2>("C_Adense", k, size_t(ndof_c) * ndof_c);
       out = C.Adense;
       HIPCHECK(hipMemsetAsync(out, 0, sizeof(double2) * ndof_c * ndof_c, s));
     } else {
-      C.A = h->mem.alloc<double2>(size_t(nnc) * 25 * bc * bc);
+      C.A = h->mem.get<double2>("C_A", k, size_t(nnc) * 25 * bc * bc);
       out = C.A;
       HIPCHECK(hipMemsetAsync(out, 0, sizeof(double2) * nnc * 25 * bc * bc, s));
     }
-    double2* pe = tmp.alloc<double2>(size_t(bc) * ndof_c);
-    double2* py = tmp.alloc<double2>(size_t(bc) * ndof);
-    double2* pz = tmp.alloc<double2>(size_t(bc) * ndof);
-    double2* pu = tmp.alloc<double2>(size_t(bc) * ndof_c);
+    double2* pe = h->mem.get<double2>("pe", k, size_t(bc) * ndof_c);
+    double2* py = h->mem.get<double2>("py", k, size_t(bc) * ndof);
+    double2* pz = h->mem.get<double2>("pz", k, size_t(bc) * ndof);
+    double2* pu = h->mem.get<double2>("pu", k, size_t(bc) * ndof_c);
+    double2* ppart = h->mem.get<double2>("ppart", k, size_t(bc) * g.nI * g.nJ * restrict_chunks(g, nf) * g.ncol());
     for (int ct = 0; ct < pt; ++ct)
       for (int cx = 0; cx < px; ++cx) {
         probe_make(s, gc, pt, px, ct, cx, pe);
@@ -338,21 +375,19 @@ void run_setup(amamg_hierarchy* h) {
           wilson_apply(s, LINK_F64, U0, U1, F64, py, F64, pz, nullptr, g.Lt, g.Lx, h->m0, bc, ndof, nullptr);
         else
           stencil_apply(s, F64, L.A, py, pz, nullptr, g.Lt, g.Lx, g.b, bc, ndof, nullptr);
-        restrict_(s, F64, L.P, L.owner, F64, pz, pu, g, bc, ndof, ndof_c, nullptr);
+        restrict_(s, F64, L.P, L.rows, L.nrows, L.nf, F64, pz, pu, ppart, g, bc, ndof, ndof_c, nullptr);
         probe_extract(s, gc, pt, px, ct, cx, pu, out, dense ? 1 : 0);
       }
     check_launch();
 
     // smoother blocks of the next level, or the coarsest inverse
     if (!dense) {
-      C.Dinv = h->mem.alloc<double2>(size_t(nnc) * bc * bc);
-      double2* Dg = tmp.alloc<double2>(size_t(nnc) * bc * bc);
-      int* dpiv = tmp.alloc<int>(size_t(nnc) * bc);
-      int* dinfo = tmp.alloc<int>(nnc);
-      extract_diag(s, C.A, nnc, bc, Dg);
-      lu_factor(s, Dg, bc, nnc, dpiv, dinfo);
-      set_identity(s, C.Dinv, bc, nnc);
-      lu_solve(s, Dg, dpiv, bc, nnc, C.Dinv, bc);
+      C.Dinv = h->mem.get<double2>("C_Dinv", k, size_t(nnc) * bc * bc);
+      double2* Dg = h->mem.get<double2>("Dg", k, size_t(nnc) * bc * 2 * bc);
+      int* dinfo = h->mem.get<int>("dinfo", k, nnc);
+      aug_identity(s, C.A + 12 * bc * bc, int64_t(25) * bc * bc, bc, bc, Dg, nnc);
+      dense_solve(s, Dg, bc, bc, nnc, dinfo);
+      aug_extract(s, Dg, bc, bc, C.Dinv, nnc);
       check_launch();
       std::vector<int> hd(nnc);
       HIPCHECK(hipMemcpyAsync(hd.data(), dinfo, sizeof(int) * nnc, hipMemcpyDeviceToHost, s));
@@ -361,14 +396,12 @@ void run_setup(amamg_hierarchy* h) {
         REQUIRE(hd[n] == 0, AMAMG_ERR_SINGULAR_LOCAL, "singular diagonal block on level " + std::to_string(k + 1));
     } else {
       const int n = int(ndof_c);
-      double2* LUc = tmp.alloc<double2>(size_t(n) * n);
-      int* cpiv = tmp.alloc<int>(n);
-      int* cinfo = tmp.alloc<int>(1);
-      HIPCHECK(hipMemcpyAsync(LUc, C.Adense, sizeof(double2) * n * n, hipMemcpyDeviceToDevice, s));
-      lu_factor(s, LUc, n, 1, cpiv, cinfo);
-      C.Ainv = h->mem.alloc<double2>(size_t(n) * n);
-      set_identity(s, C.Ainv, n, 1);
-      lu_solve(s, LUc, cpiv, n, 1, C.Ainv, n);
+      double2* LUc = h->mem.get<double2>("LUc", k, size_t(n) * 2 * n);
+      int* cinfo = h->mem.get<int>("cinfo", k, 1);
+      aug_identity(s, C.Adense, 0, n, n, LUc, 1);
+      dense_solve(s, LUc, n, n, 1, cinfo);
+      C.Ainv = h->mem.get<double2>("C_Ainv", k, size_t(n) * n);
+      aug_extract(s, LUc, n, n, C.Ainv, 1);
       check_launch();
       int hc = 0;
       HIPCHECK(hipMemcpyAsync(&hc, cinfo, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -378,7 +411,7 @@ void run_setup(amamg_hierarchy* h) {
     W = Wc;
     // the next level's test vectors must outlive this iteration's temporaries
     if (nv > 0 && !dense) {
-      double2* keep = h->mem.alloc<double2>(size_t(nv) * ndof_c);
+      double2* keep = h->mem.get<double2>("keep", k, size_t(nv) * ndof_c);
       HIPCHECK(hipMemcpyAsync(keep, Wc, sizeof(double2) * nv * ndof_c, hipMemcpyDeviceToDevice, s));
       W = keep;
     }
@@ -389,17 +422,17 @@ void run_setup(amamg_hierarchy* h) {
     LevelData& L = h->lv[k];
     if (L.P) {
       const int64_t n = L.g.ndof() * L.g.ncol();
-      L.P32 = h->mem.alloc<float2>(n);
+      L.P32 = h->mem.get<float2>("L_P32", k, n);
       cast_matrix(s, L.P, L.P32, n);
     }
     if (L.A) {
       const int64_t n = int64_t(L.g.nnode()) * 25 * L.g.b * L.g.b;
-      L.A32 = h->mem.alloc<float2>(n);
+      L.A32 = h->mem.get<float2>("L_A32", k, n);
       cast_matrix(s, L.A, L.A32, n);
     }
     if (L.Dinv) {
       const int64_t n = int64_t(L.g.nnode()) * L.g.b * L.g.b;
-      L.Dinv32 = h->mem.alloc<float2>(n);
+      L.Dinv32 = h->mem.get<float2>("L_Dinv32", k, n);
       cast_matrix(s, L.Dinv, L.Dinv32, n);
     }
   }
@@ -412,13 +445,15 @@ void run_setup(amamg_hierarchy* h) {
 void ensure_links(amamg_gauge* gg, LinkStore ls) {
   hipStream_t s = gg->ctx->stream;
   const int64_t n = 2 * int64_t(gg->nt) * gg->nx;
-  if (ls == LINK_F32 && !gg->U32) {
-    gg->U32 = gg->mem.alloc<float2>(n);
+  if (ls == LINK_F32 && gg->v32 != gg->version) {
+    if (!gg->U32) gg->U32 = gg->mem.alloc<float2>(n);
     links_to_f32(s, gg->U, gg->U32, n);
+    gg->v32 = gg->version;
   }
-  if (ls == LINK_BF16 && !gg->U16) {
-    gg->U16 = gg->mem.alloc<bf16c>(n);
+  if (ls == LINK_BF16 && gg->v16 != gg->version) {
+    if (!gg->U16) gg->U16 = gg->mem.alloc<bf16c>(n);
     links_to_bf16(s, gg->U, gg->U16, n);
+    gg->v16 = gg->version;
   }
 }
 
@@ -437,9 +472,11 @@ void ensure_workspace(amamg_hierarchy* h, int nrhs, int m, Real prec, int hist_c
   h->y = h->ws.alloc<double2>(size_t(nrhs) * m);
   h->h1 = h->ws.alloc<double2>(size_t(nrhs) * 32);
   h->h2 = h->ws.alloc<double2>(size_t(nrhs) * 32);
-  h->nblk = int(std::min<int64_t>(1024, std::max<int64_t>(1, n / 256)));
+  h->nblk = int(std::min<int64_t>(256, std::max<int64_t>(1, n / 512)));
   h->part = h->ws.alloc<double2>(size_t(nrhs) * h->nblk * 32);
   h->st = h->ws.alloc<RhsState>(nrhs);
+  h->cnt = h->ws.alloc<unsigned>(size_t(4) * nrhs);
+  HIPCHECK(hipMemsetAsync(h->cnt, 0, sizeof(unsigned) * 4 * nrhs, h->gauge->ctx->stream));
   h->hist = h->ws.alloc<double2>(size_t(nrhs) * hist_cap);
   for (size_t k = 1; k < h->lv.size(); ++k) {
     LevelData& L = h->lv[k];
@@ -449,6 +486,10 @@ void ensure_workspace(amamg_hierarchy* h, int nrhs, int m, Real prec, int hist_c
     L.tmp = h->ws.alloc<char>(size_t(nrhs) * nd * rs);
   }
   h->lv[0].tmp = h->ws.alloc<char>(size_t(nrhs) * n * rs);
+  for (size_t k = 0; k + 1 < h->lv.size(); ++k) {
+    LevelData& L = h->lv[k];
+    L.rpart = h->ws.alloc<char>(size_t(nrhs) * L.g.nI * L.g.nJ * restrict_chunks(L.g, L.nf) * L.g.ncol() * rs);
+  }
   h->ws_nrhs = nrhs;
   h->ws_m = m;
   h->ws_prec = prec;
@@ -507,9 +548,9 @@ void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x) {
       wilson_apply(c.s, c.smooth_links, U0, U1, c.T, x, c.T, L.tmp, (const double2*)f, g.Lt, g.Lx, h->m0, c.nrhs, nd, st);
     else
       stencil_apply(c.s, c.T, Ak, x, L.tmp, f, g.Lt, g.Lx, g.b, c.nrhs, nd, st);
-    restrict_(c.s, c.T, P, L.owner, c.T, L.tmp, C.f, g, c.nrhs, nd, ndc, st);
+    restrict_(c.s, c.T, P, L.rows, L.nrows, L.nf, c.T, L.tmp, C.f, L.rpart, g, c.nrhs, nd, ndc, st);
   } else {
-    restrict_(c.s, c.T, P, L.owner, fprec, f, C.f, g, c.nrhs, nd, ndc, st);
+    restrict_(c.s, c.T, P, L.rows, L.nrows, L.nf, fprec, f, C.f, L.rpart, g, c.nrhs, nd, ndc, st);
   }
   vcycle(c, k + 1, c.T, C.f, C.x);
   prolong(c.s, c.T, P, L.owner, L.node, C.x, x, g, pre > 0 ? 1 : 0, c.nrhs, nd, ndc, st);
@@ -550,9 +591,12 @@ amamg_status run_solve(amamg_hierarchy* h, int nrhs, const double2* b, double2* 
   const size_t zs = T == F64 ? sizeof(double2) : sizeof(float2);
   const int64_t vsj = int64_t(nrhs) * n;   // basis stride between j
 
+  unsigned* cnt_dot = h->cnt;
+  unsigned* cnt_up1 = h->cnt + nrhs;
+  unsigned* cnt_up2 = h->cnt + 2 * nrhs;
+  unsigned* cnt_nrm = h->cnt + 3 * nrhs;
   // ||b||; refuse non-finite input before touching x
-  norm_partial(s, kd, b, h->part, nullptr, 0);
-  init_states(s, kd, st, h->part);
+  norm_control(s, kd, b, h->part, cnt_nrm, st, 1, h->g, p.rel_tol, p.max_iters, h->hist, hist_cap);
   check_launch();
   std::vector<RhsState> hs(nrhs);
   HIPCHECK(hipMemcpyAsync(hs.data(), st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, s));
@@ -561,10 +605,9 @@ amamg_status run_solve(amamg_hierarchy* h, int nrhs, const double2* b, double2* 
     REQUIRE(!hs[r].nonfinite, AMAMG_ERR_NONFINITE, "non-finite value in right-hand side " + std::to_string(r));
 
   if (!p.use_initial_guess) HIPCHECK(hipMemsetAsync(x, 0, sizeof(double2) * nrhs * n, s));
-  // r = b - D x into V_0
+  // r = b - D x into V_0, its norm, the first cycle start, V_0 = r / ||r||
   wilson_apply(s, LINK_F64, gg->U, gg->U + int64_t(nt) * nx, F64, x, F64, h->V, b, nt, nx, h->m0, nrhs, n, st);
-  norm_partial(s, kd, h->V, h->part, st, 1);
-  cycle_begin(s, kd, st, h->part, h->g, p.rel_tol, 1, p.max_iters, h->hist, hist_cap);
+  norm_control(s, kd, h->V, h->part, cnt_nrm, st, 2, h->g, p.rel_tol, p.max_iters, h->hist, hist_cap);
   scale_next(s, kd, h->V, h->V, st);
   check_launch();
 
@@ -581,20 +624,16 @@ amamg_status run_solve(amamg_hierarchy* h, int nrhs, const double2* b, double2* 
       void* zj = (char*)h->Z + size_t(j) * vsj * zs;
       vcycle(c, 0, F64, vj, zj);
       wilson_apply(s, c.mat_links, Um0, Um1, T, zj, F64, h->w, nullptr, nt, nx, h->m0, nrhs, n, st);
-      dots_partial(s, kd, h->V, vsj, j + 1, h->w, h->part, st);
-      sum_partials(s, kd, h->part, j + 1, h->h1, 32, st);
-      update_partial(s, kd, h->V, vsj, j + 1, h->w, h->h1, 32, h->part, 1, st);
-      sum_partials(s, kd, h->part, j + 1, h->h2, 32, st);
-      update_partial(s, kd, h->V, vsj, j + 1, h->w, h->h2, 32, h->part, 2, st);
-      arnoldi_finish(s, kd, st, h->part, h->h1, h->h2, h->H, h->cs, h->sn, h->g, j, p.rel_tol,
-                     inner_tol, p.max_iters, h->hist, hist_cap);
+      dots(s, kd, h->V, vsj, j + 1, h->w, h->part, cnt_dot, h->h1, st);
+      update_dots(s, kd, h->V, vsj, j + 1, h->w, h->h1, h->part, cnt_up1, h->h2, st);
+      update_norm_arnoldi(s, kd, h->V, vsj, j + 1, h->w, h->h2, h->part, cnt_up2, st, h->H, h->cs,
+                          h->sn, h->g, h->h1, j, p.rel_tol, inner_tol, p.max_iters, h->hist, hist_cap);
       if (j + 1 < m) scale_next(s, kd, h->w, h->V + (j + 1) * vsj, st);
       check_launch();
     }
     backsolve_update(s, kd, st, h->H, h->g, h->y, T, h->Z, vsj, x);
     wilson_apply(s, LINK_F64, gg->U, gg->U + int64_t(nt) * nx, F64, x, F64, h->V, b, nt, nx, h->m0, nrhs, n, st);
-    norm_partial(s, kd, h->V, h->part, st, 1);
-    cycle_begin(s, kd, st, h->part, h->g, p.rel_tol, 0, p.max_iters, h->hist, hist_cap);
+    norm_control(s, kd, h->V, h->part, cnt_nrm, st, 3, h->g, p.rel_tol, p.max_iters, h->hist, hist_cap);
     scale_next(s, kd, h->V, h->V, st);
     check_launch();
   }
@@ -709,6 +748,22 @@ amamg_status amamg_gauge_set_mass(amamg_gauge* g, double m0) {
   return AMAMG_OK;
 }
 
+amamg_status amamg_gauge_update_links(amamg_gauge* g, const double* links) {
+  if (!g || !links) return g ? fail(g->ctx, {AMAMG_ERR_INVALID_ARG, "null argument"}) : AMAMG_ERR_INVALID_ARG;
+  amamg_context* ctx = g->ctx;
+  try {
+    const size_t nval = size_t(2) * g->nt * g->nx * 2;
+    REQUIRE(finite_all(links, nval), AMAMG_ERR_NONFINITE, "non-finite link");
+    HIPCHECK(hipSetDevice(ctx->device));
+    HIPCHECK(hipMemcpyAsync(g->U, links, sizeof(double) * nval, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+    g->version += 1;
+  } catch (const Fail& f) {
+    return fail(ctx, f);
+  }
+  return AMAMG_OK;
+}
+
 amamg_status amamg_gauge_destroy(amamg_gauge* g) {
   if (!g) return AMAMG_ERR_INVALID_ARG;
   if (g->nhier > 0) return fail(g->ctx, {AMAMG_ERR_INVALID_ARG, "gauge still used by hierarchies"});
@@ -733,6 +788,19 @@ amamg_status amamg_setup(amamg_gauge* g, const amamg_setup_params* params, amamg
   }
   g->nhier += 1;
   *out = h;
+  return AMAMG_OK;
+}
+
+amamg_status amamg_hierarchy_update(amamg_hierarchy* h) {
+  if (!h) return AMAMG_ERR_INVALID_ARG;
+  amamg_gauge* g = h->gauge;
+  try {
+    HIPCHECK(hipSetDevice(g->ctx->device));
+    h->m0 = g->m0;
+    run_setup(h);
+  } catch (const Fail& f) {
+    return fail(g->ctx, f);
+  }
   return AMAMG_OK;
 }
 
@@ -816,6 +884,28 @@ amamg_status amamg_apply_dirac(amamg_gauge* g, int32_t precision, int32_t nrhs, 
     check_launch();
     HIPCHECK(hipMemcpyAsync(out, dy, sizeof(double2) * nrhs * n, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHECK(hipStreamSynchronize(ctx->stream));
+  } catch (const Fail& f) {
+    return fail(ctx, f);
+  }
+  return AMAMG_OK;
+}
+
+amamg_status amamg_apply_dirac_device(amamg_gauge* g, int32_t precision, int32_t nrhs,
+                                      const void* in_dev, void* out_dev) {
+  if (!g || !in_dev || !out_dev || nrhs < 1)
+    return g ? fail(g->ctx, {AMAMG_ERR_INVALID_ARG, "bad argument"}) : AMAMG_ERR_INVALID_ARG;
+  amamg_context* ctx = g->ctx;
+  try {
+    REQUIRE(precision >= AMAMG_FP64 && precision <= AMAMG_MIXED_FP32_BF16LINKS, AMAMG_ERR_INVALID_ARG,
+            "unknown precision");
+    HIPCHECK(hipSetDevice(ctx->device));
+    const int64_t n = int64_t(g->nt) * g->nx * 2;
+    const LinkStore ls = precision == AMAMG_FP64 ? LINK_F64 : precision == AMAMG_MIXED_FP32 ? LINK_F32 : LINK_BF16;
+    const Real v = precision == AMAMG_FP64 ? F64 : F32;
+    ensure_links(g, ls);
+    wilson_apply(ctx->stream, ls, link0(g, ls), link1(g, ls), v, in_dev, v, out_dev, nullptr, g->nt,
+                 g->nx, g->m0, nrhs, n, nullptr);
+    check_launch();
   } catch (const Fail& f) {
     return fail(ctx, f);
   }

@@ -17,21 +17,18 @@ namespace amamg {
 
 __device__ inline int wrap_s(int v, int L) { v %= L; return v < 0 ? v + L : v; }
 
-// Aff [W][nfd][nfd], Bneg [W][nfd][ncol]; A: block stencil [node][noff][b][b]
+// Aug [W][nfd][nfd + ncol] = [A_FF | -A_FV]; A: block stencil [node][noff][b][b]
 __global__ __launch_bounds__(256) void k_gather_local(Geom g, const double2* __restrict__ A, int noff,
                                                       const int* __restrict__ offs,
                                                       const int* __restrict__ postab,
                                                       const int* __restrict__ fpos, int nf,
-                                                      double2* __restrict__ Aff,
-                                                      double2* __restrict__ Bneg) {
+                                                      double2* __restrict__ Aug) {
   const int w = blockIdx.x;
   const int I = w / g.nJ, J = w - (w / g.nJ) * g.nJ;
   const int fpw = g.a + g.o;
-  const int nfd = nf * g.b, ncol = g.ncol();
-  double2* Aw = Aff + int64_t(w) * nfd * nfd;
-  double2* Bw = Bneg + int64_t(w) * nfd * ncol;
-  for (int64_t e = threadIdx.x; e < int64_t(nfd) * nfd; e += blockDim.x) Aw[e] = make_double2(0, 0);
-  for (int64_t e = threadIdx.x; e < int64_t(nfd) * ncol; e += blockDim.x) Bw[e] = make_double2(0, 0);
+  const int nfd = nf * g.b, ncol = g.ncol(), ld = nfd + ncol;
+  double2* Aw = Aug + int64_t(w) * nfd * ld;
+  for (int64_t e = threadIdx.x; e < int64_t(nfd) * ld; e += blockDim.x) Aw[e] = make_double2(0, 0);
   __syncthreads();
   for (int rrow = threadIdx.x; rrow < nfd; rrow += blockDim.x) {
     const int fi = rrow / g.b, i = rrow - (rrow / g.b) * g.b;
@@ -46,108 +43,182 @@ __global__ __launch_bounds__(256) void k_gather_local(Geom g, const double2* __r
       const int code = postab[ldt * fpw + ldx];
       const double2* blk = A + (int64_t(p) * noff + d) * g.b * g.b + int64_t(i) * g.b;
       if (code >= 0) {
-        double2* dst = Aw + int64_t(rrow) * nfd + int64_t(code) * g.b;
+        double2* dst = Aw + int64_t(rrow) * ld + int64_t(code) * g.b;
         for (int j = 0; j < g.b; ++j) dst[j] = cadd(dst[j], blk[j]);
       } else {
-        double2* dst = Bw + int64_t(rrow) * ncol + (-code - 1);
+        double2* dst = Aw + int64_t(rrow) * ld + nfd + (-code - 1);
         for (int j = 0; j < g.b; ++j) dst[j] = csub(dst[j], blk[j]);
       }
     }
   }
 }
 
-// In-place LU with partial pivoting (largest |a_ik|, lowest index on ties) of one n x n
-// row-major system per workgroup.  info[sys] = 0, or k + 1 for a zero pivot at step k.
-__global__ __launch_bounds__(256) void k_lu_factor(double2* __restrict__ A, int n, int* __restrict__ piv,
-                                                   int* __restrict__ info) {
-  const int sys = blockIdx.x;
-  double2* M = A + int64_t(sys) * n * n;
-  int* pv = piv + int64_t(sys) * n;
-  __shared__ double sv[256];
-  __shared__ int si[256];
+// Batched dense solve X = A^{-1} B, one workgroup per system, on the augmented row-major
+// matrix [A | B] (n rows, ld = n + nrhs columns).  Blocked right-looking LU with partial
+// pivoting (largest |a_ik|, lowest row index on ties; the swaps are applied to whole rows, so
+// B is permuted and eliminated along the way), panel width LU_NB; the trailing rank-LU_NB
+// updates run on 64 x 64 tiles staged in LDS.  Then a blocked back substitution U X = B' with
+// the same tiled update.  On exit the B columns hold X.  info[sys] = 0, or k + 1 when the pivot
+// column k is zero or not finite.
+#define LU_NB 16
+
+// M[r][c] -= sum_{q < kb} M[r][lc + q] * M[ur + q][c]  for r in [r0, r1), c in [c0, c1)
+__device__ void tile_update(double2* __restrict__ M, int ld, int r0, int r1, int c0, int c1,
+                            int lc, int ur, int kb, double2 (*Ls)[LU_NB + 1],
+                            double2 (*Us)[64 + 1]) {
   const int tid = threadIdx.x;
-  if (tid == 0) info[sys] = 0;
-  for (int k = 0; k < n; ++k) {
-    double best = -1.0;
-    int bi = n;
-    for (int i = k + tid; i < n; i += 256) {
-      const double v = cabs2(M[int64_t(i) * n + k]);
-      if (v > best) { best = v; bi = i; }
-    }
-    sv[tid] = best;
-    si[tid] = bi;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if (tid < off) {
-        const double v2 = sv[tid + off];
-        const int i2 = si[tid + off];
-        if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) { sv[tid] = v2; si[tid] = i2; }
+  const int ty = tid >> 4, tx = tid & 15;
+  for (int tr = r0; tr < r1; tr += 64) {
+    for (int tc = c0; tc < c1; tc += 64) {
+      for (int e = tid; e < 64 * LU_NB; e += 256) {
+        const int rr = e / LU_NB, q = e - (e / LU_NB) * LU_NB;
+        Ls[rr][q] = (tr + rr < r1 && q < kb) ? M[int64_t(tr + rr) * ld + lc + q] : make_double2(0, 0);
+      }
+      for (int e = tid; e < LU_NB * 64; e += 256) {
+        const int q = e >> 6, cc = e & 63;
+        Us[q][cc] = (q < kb && tc + cc < c1) ? M[int64_t(ur + q) * ld + tc + cc] : make_double2(0, 0);
+      }
+      __syncthreads();
+      double2 acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0, 0);
+      for (int q = 0; q < kb; ++q) {
+        double2 lv[4], uv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) lv[a] = Ls[ty * 4 + a][q];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) uv[b] = Us[q][tx + 16 * b];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = cfma(lv[a], uv[b], acc[a][b]);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int r = tr + ty * 4 + a;
+        if (r >= r1) continue;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int c = tc + tx + 16 * b;
+          if (c < c1) M[int64_t(r) * ld + c] = csub(M[int64_t(r) * ld + c], acc[a][b]);
+        }
       }
       __syncthreads();
     }
-    const int p = si[0];
-    const double pmax = sv[0];
-    __syncthreads();
-    if (!(pmax > 0.0) || p >= n) {       // zero or non-finite pivot column
-      if (tid == 0) info[sys] = k + 1;
-      for (int kk = k + tid; kk < n; kk += 256) pv[kk] = kk;
-      return;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dense_solve(double2* __restrict__ A, int n, int ld,
+                                                     int* __restrict__ info) {
+  const int sys = blockIdx.x;
+  double2* M = A + int64_t(sys) * n * ld;
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  __shared__ double2 Ls[64][LU_NB + 1];
+  __shared__ double2 Us[LU_NB][64 + 1];
+  const int tid = threadIdx.x;
+  if (tid == 0) info[sys] = 0;
+  for (int k0 = 0; k0 < n; k0 += LU_NB) {
+    const int kb = min(LU_NB, n - k0);
+    for (int k = k0; k < k0 + kb; ++k) {
+      double best = -1.0;
+      int bi = n;
+      for (int i = k + tid; i < n; i += 256) {
+        const double v = cabs2(M[int64_t(i) * ld + k]);
+        if (v > best) { best = v; bi = i; }
+      }
+      sv[tid] = best;
+      si[tid] = bi;
+      __syncthreads();
+      for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off) {
+          const double v2 = sv[tid + off];
+          const int i2 = si[tid + off];
+          if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) { sv[tid] = v2; si[tid] = i2; }
+        }
+        __syncthreads();
+      }
+      const int p = si[0];
+      const double pmax = sv[0];
+      __syncthreads();
+      if (!(pmax > 0.0) || !(pmax < 1e300) || p >= n) {
+        if (tid == 0) info[sys] = k + 1;
+        return;
+      }
+      if (p != k) {
+        for (int j = tid; j < ld; j += 256) {
+          const double2 t = M[int64_t(k) * ld + j];
+          M[int64_t(k) * ld + j] = M[int64_t(p) * ld + j];
+          M[int64_t(p) * ld + j] = t;
+        }
+        __syncthreads();
+      }
+      const double2 akk = M[int64_t(k) * ld + k];
+      const double den = cabs2(akk);
+      const double2 inv = make_double2(akk.x / den, -akk.y / den);
+      for (int i = k + 1 + tid; i < n; i += 256) {
+        double2* Mi = M + int64_t(i) * ld;
+        const double2 l = cmul(Mi[k], inv);
+        Mi[k] = l;
+        for (int j = k + 1; j < k0 + kb; ++j) Mi[j] = csub(Mi[j], cmul(l, M[int64_t(k) * ld + j]));
+      }
+      __syncthreads();
     }
-    if (tid == 0) pv[k] = p;
-    if (p != k) {
-      for (int j = tid; j < n; j += 256) {
-        const double2 t = M[int64_t(k) * n + j];
-        M[int64_t(k) * n + j] = M[int64_t(p) * n + j];
-        M[int64_t(p) * n + j] = t;
+    // U12 = L11^{-1} A12 for the columns right of the panel (unit lower triangle)
+    for (int c = k0 + kb + tid; c < ld; c += 256) {
+      for (int r = 1; r < kb; ++r) {
+        double2 acc = M[int64_t(k0 + r) * ld + c];
+        for (int q = 0; q < r; ++q) acc = csub(acc, cmul(M[int64_t(k0 + r) * ld + k0 + q], M[int64_t(k0 + q) * ld + c]));
+        M[int64_t(k0 + r) * ld + c] = acc;
       }
     }
     __syncthreads();
-    const double2 akk = M[int64_t(k) * n + k];
-    const double den = cabs2(akk);
-    const double2 inv = make_double2(akk.x / den, -akk.y / den);
-    for (int i = k + 1 + tid; i < n; i += 256) M[int64_t(i) * n + k] = cmul(M[int64_t(i) * n + k], inv);
+    tile_update(M, ld, k0 + kb, n, k0 + kb, ld, k0, k0, kb, Ls, Us);
     __syncthreads();
-    // trailing update: wave wv takes rows k+1+wv, k+5+wv, ...; lanes sweep the columns
-    const int lane = tid & 63, wv = tid >> 6;
-    for (int i = k + 1 + wv; i < n; i += 4) {
-      const double2 lik = M[int64_t(i) * n + k];
-      double2* Mi = M + int64_t(i) * n;
-      const double2* Mk = M + int64_t(k) * n;
-      for (int j = k + 1 + lane; j < n; j += 64) Mi[j] = csub(Mi[j], cmul(lik, Mk[j]));
+  }
+  // back substitution U X = B' on the right-hand-side columns
+  const int last = ((n - 1) / LU_NB) * LU_NB;
+  for (int k0 = last; k0 >= 0; k0 -= LU_NB) {
+    const int kb = min(LU_NB, n - k0);
+    for (int c = n + tid; c < ld; c += 256) {
+      for (int r = kb - 1; r >= 0; --r) {
+        double2 acc = M[int64_t(k0 + r) * ld + c];
+        for (int q = r + 1; q < kb; ++q) acc = csub(acc, cmul(M[int64_t(k0 + r) * ld + k0 + q], M[int64_t(k0 + q) * ld + c]));
+        const double2 d = M[int64_t(k0 + r) * ld + k0 + r];
+        const double den = cabs2(d);
+        M[int64_t(k0 + r) * ld + c] = cmul(acc, make_double2(d.x / den, -d.y / den));
+      }
     }
+    __syncthreads();
+    if (k0 > 0) tile_update(M, ld, 0, k0, n, ld, k0, k0, kb, Ls, Us);
     __syncthreads();
   }
 }
 
-// Solve with the factors for nrhs right-hand sides B [sys][n][nrhs]; one thread per column.
-__global__ __launch_bounds__(64) void k_lu_solve(const double2* __restrict__ LU, const int* __restrict__ piv,
-                                                 int n, double2* __restrict__ B, int nrhs) {
-  const int sys = blockIdx.x;
-  const int col = blockIdx.y * 64 + threadIdx.x;
-  if (col >= nrhs) return;
-  const double2* M = LU + int64_t(sys) * n * n;
-  const int* pv = piv + int64_t(sys) * n;
-  double2* Bs = B + int64_t(sys) * n * nrhs + col;
-  for (int k = 0; k < n; ++k) {
-    const int p = pv[k];
-    if (p != k) {
-      const double2 t = Bs[int64_t(k) * nrhs];
-      Bs[int64_t(k) * nrhs] = Bs[int64_t(p) * nrhs];
-      Bs[int64_t(p) * nrhs] = t;
-    }
-  }
-  for (int i = 1; i < n; ++i) {
-    double2 acc = Bs[int64_t(i) * nrhs];
-    for (int k = 0; k < i; ++k) acc = csub(acc, cmul(M[int64_t(i) * n + k], Bs[int64_t(k) * nrhs]));
-    Bs[int64_t(i) * nrhs] = acc;
-  }
-  for (int i = n - 1; i >= 0; --i) {
-    double2 acc = Bs[int64_t(i) * nrhs];
-    for (int k = i + 1; k < n; ++k) acc = csub(acc, cmul(M[int64_t(i) * n + k], Bs[int64_t(k) * nrhs]));
-    const double2 d = M[int64_t(i) * n + i];
-    const double den = cabs2(d);
-    Bs[int64_t(i) * nrhs] = cmul(acc, make_double2(d.x / den, -d.y / den));
-  }
+// out[sys][i][j] = Aug[sys][i][n + j]
+__global__ void k_aug_extract(const double2* __restrict__ Aug, int n, int nrhs, double2* __restrict__ out,
+                              int nsys) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= int64_t(nsys) * n * nrhs) return;
+  const int64_t sys = e / (int64_t(n) * nrhs);
+  const int64_t rem = e - sys * n * nrhs;
+  const int i = int(rem / nrhs), j = int(rem - int64_t(i) * nrhs);
+  out[e] = Aug[(sys * n + i) * (n + nrhs) + n + j];
+}
+
+// Aug[sys] = [A[sys] | I]: A given as nsys blocks of n x n with stride astride (elements) and
+// row stride arow
+__global__ void k_aug_identity(const double2* __restrict__ A, int64_t astride, int arow, int n,
+                               double2* __restrict__ Aug, int nsys) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int ld = 2 * n;
+  if (e >= int64_t(nsys) * n * ld) return;
+  const int64_t sys = e / (int64_t(n) * ld);
+  const int64_t rem = e - sys * n * ld;
+  const int i = int(rem / ld), j = int(rem - int64_t(i) * ld);
+  Aug[e] = j < n ? A[sys * astride + int64_t(i) * arow + j] : make_double2(j - n == i ? 1.0 : 0.0, 0.0);
 }
 
 // Copy the rows of each wirebasket's solution that the wirebasket owns into P [p][i][ncol].
@@ -156,7 +227,7 @@ __global__ void k_scatter_P(Geom g, const double2* __restrict__ X, const int* __
   const int w = blockIdx.x;
   const int I = w / g.nJ, J = w - (w / g.nJ) * g.nJ;
   const int fpw = g.a + g.o, ncol = g.ncol(), nfd = nf * g.b;
-  const double2* Xw = X + int64_t(w) * nfd * ncol;
+  const double2* Xw = X + int64_t(w) * nfd * (nfd + ncol);
   for (int64_t e = threadIdx.x; e < int64_t(nfd) * ncol; e += blockDim.x) {
     const int rrow = int(e / ncol), col = int(e - int64_t(rrow) * ncol);
     const int fi = rrow / g.b, i = rrow - (rrow / g.b) * g.b;
@@ -164,7 +235,7 @@ __global__ void k_scatter_P(Geom g, const double2* __restrict__ X, const int* __
     const int dt = pos / fpw, dx = pos - (pos / fpw) * fpw;
     const int p = wrap_s(g.a * I + dt, g.Lt) * g.Lx + wrap_s(g.a * J + dx, g.Lx);
     if (owner[p] != w) continue;
-    P[(int64_t(p) * g.b + i) * ncol + col] = Xw[e];
+    P[(int64_t(p) * g.b + i) * ncol + col] = Xw[int64_t(rrow) * (nfd + ncol) + nfd + col];
   }
 }
 
@@ -257,21 +328,6 @@ __global__ void k_probe_extract(Geom gc, int pt, int px, int ct, int cx,
   }
 }
 
-__global__ void k_extract_diag(const double2* __restrict__ A, int nnode, int b, double2* __restrict__ D) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= int64_t(nnode) * b * b) return;
-  const int64_t n = i / (b * b), e = i - n * b * b;
-  D[i] = A[(n * 25 + 12) * b * b + e];
-}
-
-__global__ void k_set_identity(double2* __restrict__ B, int n, int nsys) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= int64_t(nsys) * n * n) return;
-  const int64_t e = i % (int64_t(n) * n);
-  const int r = int(e / n), c = int(e - int64_t(r) * n);
-  B[i] = make_double2(r == c ? 1.0 : 0.0, 0.0);
-}
-
 __global__ void k_cast_matrix(const double2* __restrict__ A, float2* __restrict__ out, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) out[i] = make_float2(float(A[i].x), float(A[i].y));
@@ -282,19 +338,24 @@ __global__ void k_cast_matrix(const double2* __restrict__ A, float2* __restrict_
 static inline dim3 g1(int64_t n) { return dim3(unsigned((n + 255) / 256)); }
 
 void gather_local(hipStream_t s, const Geom& g, const double2* A, int noff, const int* offs,
-                  const int* postab_fpos, int nf, double2* Aff, double2* Bneg) {
+                  const int* postab_fpos, int nf, double2* Aug) {
   const int fp = g.fp();
   hipLaunchKernelGGL(k_gather_local, dim3(g.nI * g.nJ), dim3(256), 0, s, g, A, noff, offs,
-                     postab_fpos, postab_fpos + fp, nf, Aff, Bneg);
+                     postab_fpos, postab_fpos + fp, nf, Aug);
 }
 
-void lu_factor(hipStream_t s, double2* A, int n, int nsys, int* piv, int* info) {
-  hipLaunchKernelGGL(k_lu_factor, dim3(nsys), dim3(256), 0, s, A, n, piv, info);
+void dense_solve(hipStream_t s, double2* Aug, int n, int nrhs, int nsys, int* info) {
+  hipLaunchKernelGGL(k_dense_solve, dim3(nsys), dim3(256), 0, s, Aug, n, n + nrhs, info);
 }
 
-void lu_solve(hipStream_t s, const double2* LU, const int* piv, int n, int nsys, double2* B,
-              int nrhs) {
-  hipLaunchKernelGGL(k_lu_solve, dim3(nsys, (nrhs + 63) / 64), dim3(64), 0, s, LU, piv, n, B, nrhs);
+void aug_extract(hipStream_t s, const double2* Aug, int n, int nrhs, double2* out, int nsys) {
+  hipLaunchKernelGGL(k_aug_extract, g1(int64_t(nsys) * n * nrhs), dim3(256), 0, s, Aug, n, nrhs, out, nsys);
+}
+
+void aug_identity(hipStream_t s, const double2* A, int64_t astride, int arow, int n, double2* Aug,
+                  int nsys) {
+  hipLaunchKernelGGL(k_aug_identity, g1(int64_t(nsys) * n * 2 * n), dim3(256), 0, s, A, astride, arow,
+                     n, Aug, nsys);
 }
 
 void scatter_P(hipStream_t s, const Geom& g, const double2* X, const int* postab_fpos, int nf,
@@ -320,13 +381,6 @@ void probe_extract(hipStream_t s, const Geom& gc, int pt, int px, int ct, int cx
   hipLaunchKernelGGL(k_probe_extract, g1(n), dim3(256), 0, s, gc, pt, px, ct, cx, u, out, dense);
 }
 
-void extract_diag(hipStream_t s, const double2* A, int nnode, int b, double2* D) {
-  hipLaunchKernelGGL(k_extract_diag, g1(int64_t(nnode) * b * b), dim3(256), 0, s, A, nnode, b, D);
-}
-
-void set_identity(hipStream_t s, double2* B, int n, int nsys) {
-  hipLaunchKernelGGL(k_set_identity, g1(int64_t(nsys) * n * n), dim3(256), 0, s, B, n, nsys);
-}
 
 void cast_matrix(hipStream_t s, const double2* A, float2* out, int64_t n) {
   hipLaunchKernelGGL(k_cast_matrix, g1(n), dim3(256), 0, s, A, out, n);

@@ -80,58 +80,132 @@ __global__ __launch_bounds__(256) void k_prolong(const M* __restrict__ P,
   }
 }
 
-// rc[N][j] = sum over the 4 wirebaskets W having N as corner c, over the rows (p, i) whose
-// primary wirebasket is W, of conj(P[p][i][c*bc + j]) r[p][i], plus r at N's vertices.
-// One workgroup per coarse node; thread = (column j, slot); slots split the rows, then an
-// LDS reduction over slots in a fixed order (deterministic, no atomics).
-template <typename R, typename M, typename Vin, typename Vout>
-__global__ __launch_bounds__(256) void k_restrict(const M* __restrict__ P,
-                                                  const int* __restrict__ owner,
-                                                  const Vin* __restrict__ rin,
-                                                  Vout* __restrict__ rc, Geom g,
-                                                  int64_t stride_f, int64_t stride_c,
-                                                  const RhsState* __restrict__ st) {
+// Restriction rc = P^H r in two passes, both fixed-order (deterministic, no atomics).
+// Pass 1, one workgroup per (wirebasket W, chunk of W's owned rows): for every interpolation
+// column col of W, part[W][chunk][col] = sum over the chunk's rows of conj(P[row][col]) r[row].
+// rows[W][k] lists W's owned fine rows (p*b + i) in footprint order (nrows[W] of them); the
+// chunk's r values are staged in LDS, lanes run over columns, so each P row is read as one
+// contiguous segment.
+// Pass 2: rc[N][j] = sum over the 4 wirebaskets W having N as corner c and over their chunks
+// of part[W][chunk][c*bc + j], plus r at N's vertices; L lanes per output, xor-reduced.
+#define RCHUNK_MAX 256
+template <typename R, typename M, typename Vin>
+__global__ __launch_bounds__(256) void k_restrict_partial(const M* __restrict__ P,
+                                                          const int* __restrict__ rows,
+                                                          const int* __restrict__ nrows,
+                                                          int maxrows,
+                                                          const Vin* __restrict__ rin,
+                                                          cplx<R>* __restrict__ part, Geom g,
+                                                          int nchunk, int64_t stride_f,
+                                                          const RhsState* __restrict__ st) {
   const int r = blockIdx.y;
   if (st && !st[r].active) return;
   using C = cplx<R>;
   __shared__ R red[2][256];
-  const int N = xcd_block(blockIdx.x, gridDim.x);
-  const int I = N / g.nJ, J = N - (N / g.nJ) * g.nJ;
-  const int bc = g.bc, ncol = g.ncol();
-  const int nslot = 256 / bc;   // bc <= 256
-  const int j = threadIdx.x % bc, slot = threadIdx.x / bc;
-  const int fpw = g.a + g.o, fp = fpw * fpw;
+  __shared__ C rs[RCHUNK_MAX];
+  __shared__ int ri[RCHUNK_MAX];
+  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  const int w = bid / nchunk, chunk = bid - (bid / nchunk) * nchunk;
+  const int ncol = g.ncol();
+  const int nr = nrows[w];
+  const int rpc = (maxrows + nchunk - 1) / nchunk;
+  const int r0 = chunk * rpc, r1 = min(nr, r0 + rpc);
+  const int cnt = r1 > r0 ? r1 - r0 : 0;
   const Vin* rr = rin + r * stride_f;
-  C acc = czero<R>();
-  if (slot < nslot) {
-    const int nitem = 4 * fp * g.b;
-    for (int it = slot; it < nitem; it += nslot) {
-      const int c = it / (fp * g.b);
-      const int rem = it - c * fp * g.b;
-      const int pos = rem / g.b, i = rem - (rem / g.b) * g.b;
-      const int ct = c >> 1, cx = c & 1;
-      const int WI = wrapt(I - ct, g.nI), WJ = wrapt(J - cx, g.nJ);
-      const int w = WI * g.nJ + WJ;
-      const int dt = pos / fpw, dx = pos - (pos / fpw) * fpw;
-      const int p = wrapt(g.a * WI + dt, g.Lt) * g.Lx + wrapt(g.a * WJ + dx, g.Lx);
-      if (owner[p] != w) continue;
-      const int64_t row = int64_t(p) * g.b + i;
-      acc = cfmac(cconv<C>(P[row * ncol + c * bc + j]), cconv<C>(rr[row]), acc);
-    }
+  for (int k = threadIdx.x; k < cnt; k += 256) {
+    const int row = rows[int64_t(w) * maxrows + r0 + k];
+    ri[k] = row;
+    rs[k] = cconv<C>(rr[row]);
   }
-  red[0][threadIdx.x] = acc.x;
-  red[1][threadIdx.x] = acc.y;
   __syncthreads();
-  if (slot == 0) {
-    C sum = czero<R>();
-    for (int s = 0; s < nslot; ++s) sum = cadd(sum, mk<R>(red[0][s * bc + j], red[1][s * bc + j]));
-    // vertex part: dof j = (pt*o + px)*b + q of node N
-    const int q = j % g.b, pp = j / g.b;
-    const int pt = pp / g.o, px = pp - (pp / g.o) * g.o;
-    const int p = (g.a * I + pt) * g.Lx + (g.a * J + px);
-    sum = cadd(sum, cconv<C>(rr[int64_t(p) * g.b + q]));
-    rc[r * stride_c + int64_t(N) * bc + j] = cconv<Vout>(sum);
+  const int CW = ncol < 256 ? ncol : 256;
+  const int nslot = 256 / CW;
+  const int cl = threadIdx.x % CW, slot = threadIdx.x / CW;
+  C* out = part + ((int64_t(r) * g.nI * g.nJ + w) * nchunk + chunk) * ncol;
+  for (int c0 = 0; c0 < ncol; c0 += CW) {
+    const int col = c0 + cl;
+    C acc = czero<R>();
+    if (slot < nslot && col < ncol) {
+      int k = slot;
+      for (; k + 3 * nslot < cnt; k += 4 * nslot) {
+        const M p0 = P[int64_t(ri[k]) * ncol + col];
+        const M p1 = P[int64_t(ri[k + nslot]) * ncol + col];
+        const M p2 = P[int64_t(ri[k + 2 * nslot]) * ncol + col];
+        const M p3 = P[int64_t(ri[k + 3 * nslot]) * ncol + col];
+        acc = cfmac(cconv<C>(p0), rs[k], acc);
+        acc = cfmac(cconv<C>(p1), rs[k + nslot], acc);
+        acc = cfmac(cconv<C>(p2), rs[k + 2 * nslot], acc);
+        acc = cfmac(cconv<C>(p3), rs[k + 3 * nslot], acc);
+      }
+      for (; k < cnt; k += nslot) acc = cfmac(cconv<C>(P[int64_t(ri[k]) * ncol + col]), rs[k], acc);
+    }
+    red[0][threadIdx.x] = acc.x;
+    red[1][threadIdx.x] = acc.y;
+    __syncthreads();
+    if (slot == 0 && col < ncol) {
+      C sum = czero<R>();
+      for (int q = 0; q < nslot; ++q) sum = cadd(sum, mk<R>(red[0][q * CW + cl], red[1][q * CW + cl]));
+      out[col] = sum;
+    }
+    __syncthreads();
   }
+}
+
+template <typename R, typename Vin, typename Vout>
+__global__ __launch_bounds__(256) void k_restrict_gather(const cplx<R>* __restrict__ part,
+                                                         const Vin* __restrict__ rin,
+                                                         Vout* __restrict__ rc, Geom g, int nchunk,
+                                                         int lanes, int64_t stride_f,
+                                                         int64_t stride_c,
+                                                         const RhsState* __restrict__ st) {
+  const int r = blockIdx.y;
+  if (st && !st[r].active) return;
+  using C = cplx<R>;
+  const int64_t gid = (int64_t(blockIdx.x) * 256 + threadIdx.x) / lanes;
+  const int ln = threadIdx.x % lanes;
+  const int nW = g.nI * g.nJ;
+  const bool live = gid < int64_t(nW) * g.bc;
+  const int64_t gg = live ? gid : 0;
+  const int N = int(gg / g.bc), j = int(gg - int64_t(N) * g.bc);
+  const int I = N / g.nJ, J = N - (N / g.nJ) * g.nJ;
+  const int ncol = g.ncol();
+  C sum = czero<R>();
+  for (int c = 0; c < 4; ++c) {
+    const int WI = I - (c >> 1), WJ = J - (c & 1);
+    const int w = (WI < 0 ? WI + g.nI : WI) * g.nJ + (WJ < 0 ? WJ + g.nJ : WJ);
+    const C* pw = part + (int64_t(r) * nW + w) * nchunk * ncol + c * g.bc + j;
+    for (int ch = ln; ch < nchunk; ch += lanes) sum = cadd(sum, pw[int64_t(ch) * ncol]);
+  }
+  for (int off = lanes >> 1; off > 0; off >>= 1) {
+    sum.x += __shfl_xor(sum.x, off);
+    sum.y += __shfl_xor(sum.y, off);
+  }
+  if (!live || ln != 0) return;
+  const int q = j % g.b, pp = j / g.b;
+  const int pt = pp / g.o, px = pp - (pp / g.o) * g.o;
+  const int p = (g.a * I + pt) * g.Lx + (g.a * J + px);
+  sum = cadd(sum, cconv<C>(rin[r * stride_f + int64_t(p) * g.b + q]));
+  rc[r * stride_c + gid] = cconv<Vout>(sum);
+}
+
+// rows[W][k]: owned fine rows of each wirebasket in footprint order; nrows[W] their count
+__global__ void k_owned_rows(Geom g, const int* __restrict__ fpos, int nf,
+                             const int* __restrict__ owner, int* __restrict__ rows,
+                             int* __restrict__ nrows, int maxrows) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= g.nI * g.nJ) return;
+  const int I = w / g.nJ, J = w - (w / g.nJ) * g.nJ;
+  const int fpw = g.a + g.o;
+  int k = 0;
+  for (int fi = 0; fi < nf; ++fi) {
+    const int pos = fpos[fi];
+    const int dt = pos / fpw, dx = pos - (pos / fpw) * fpw;
+    const int tt = g.a * I + dt, xx = g.a * J + dx;
+    const int p = (tt >= g.Lt ? tt - g.Lt : tt) * g.Lx + (xx >= g.Lx ? xx - g.Lx : xx);
+    if (owner[p] != w) continue;
+    for (int i = 0; i < g.b && k < maxrows; ++i) rows[int64_t(w) * maxrows + k++] = p * g.b + i;
+  }
+  nrows[w] = k;
 }
 
 // Classification of every point: multiplicity 4 / 2 / 1 -> vertex / edge / interior.
@@ -217,22 +291,52 @@ void prolong(hipStream_t s, Real prec, const void* P, const int* owner, const in
                        stride_f, stride_c, st);
 }
 
-void restrict_(hipStream_t s, Real prec, const void* P, const int* owner, Real rin, const void* r,
-               void* rc, const Geom& g, int nrhs, int64_t stride_f, int64_t stride_c,
-               const RhsState* st) {
-  dim3 grid(unsigned(g.nI * g.nJ), unsigned(nrhs));
-  if (prec == F64)
-    hipLaunchKernelGGL((k_restrict<double, double2, double2, double2>), grid, dim3(256), 0, s,
-                       (const double2*)P, owner, (const double2*)r, (double2*)rc, g, stride_f,
-                       stride_c, st);
-  else if (rin == F64)
-    hipLaunchKernelGGL((k_restrict<float, float2, double2, float2>), grid, dim3(256), 0, s,
-                       (const float2*)P, owner, (const double2*)r, (float2*)rc, g, stride_f,
-                       stride_c, st);
-  else
-    hipLaunchKernelGGL((k_restrict<float, float2, float2, float2>), grid, dim3(256), 0, s,
-                       (const float2*)P, owner, (const float2*)r, (float2*)rc, g, stride_f,
-                       stride_c, st);
+int restrict_chunks(const Geom& g, int nf) {
+  const int nW = g.nI * g.nJ, nfd = nf * g.b;
+  int nchunk = (1024 + nW - 1) / nW;
+  const int maxc = (nfd + 7) / 8;
+  if (nchunk > maxc) nchunk = maxc;
+  while ((nfd + nchunk - 1) / nchunk > RCHUNK_MAX) ++nchunk;
+  return nchunk < 1 ? 1 : nchunk;
+}
+
+void owned_rows(hipStream_t s, const Geom& g, const int* fpos, int nf, const int* owner, int* rows,
+                int* nrows) {
+  hipLaunchKernelGGL(k_owned_rows, dim3((g.nI * g.nJ + 63) / 64), dim3(64), 0, s, g, fpos, nf, owner,
+                     rows, nrows, nf * g.b);
+}
+
+void restrict_(hipStream_t s, Real prec, const void* P, const int* rows, const int* nrows, int nf,
+               Real rin, const void* r, void* rc, void* part, const Geom& g, int nrhs,
+               int64_t stride_f, int64_t stride_c, const RhsState* st) {
+  const int nchunk = restrict_chunks(g, nf);
+  const int maxrows = nf * g.b;
+  int lanes = 1;
+  while (lanes < 16 && lanes < nchunk) lanes <<= 1;
+  dim3 g1(unsigned(g.nI * g.nJ * nchunk), unsigned(nrhs));
+  dim3 g2(unsigned((int64_t(g.nI) * g.nJ * g.bc * lanes + 255) / 256), unsigned(nrhs));
+  if (prec == F64) {
+    hipLaunchKernelGGL((k_restrict_partial<double, double2, double2>), g1, dim3(256), 0, s,
+                       (const double2*)P, rows, nrows, maxrows, (const double2*)r, (double2*)part, g,
+                       nchunk, stride_f, st);
+    hipLaunchKernelGGL((k_restrict_gather<double, double2, double2>), g2, dim3(256), 0, s,
+                       (const double2*)part, (const double2*)r, (double2*)rc, g, nchunk, lanes,
+                       stride_f, stride_c, st);
+  } else if (rin == F64) {
+    hipLaunchKernelGGL((k_restrict_partial<float, float2, double2>), g1, dim3(256), 0, s,
+                       (const float2*)P, rows, nrows, maxrows, (const double2*)r, (float2*)part, g,
+                       nchunk, stride_f, st);
+    hipLaunchKernelGGL((k_restrict_gather<float, double2, float2>), g2, dim3(256), 0, s,
+                       (const float2*)part, (const double2*)r, (float2*)rc, g, nchunk, lanes,
+                       stride_f, stride_c, st);
+  } else {
+    hipLaunchKernelGGL((k_restrict_partial<float, float2, float2>), g1, dim3(256), 0, s,
+                       (const float2*)P, rows, nrows, maxrows, (const float2*)r, (float2*)part, g,
+                       nchunk, stride_f, st);
+    hipLaunchKernelGGL((k_restrict_gather<float, float2, float2>), g2, dim3(256), 0, s,
+                       (const float2*)part, (const float2*)r, (float2*)rc, g, nchunk, lanes,
+                       stride_f, stride_c, st);
+  }
 }
 
 void classify(hipStream_t s, const Geom& g, int8_t* kind, int* owner, int* node) {
