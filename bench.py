@@ -36,13 +36,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_steps(lib, torch, g, h, b, x, nrhs, precision, steps, warmup):
+FAMILIES = ["fine_matvec", "fine_gs", "restrict0", "prolong0", "coarse_gs", "dots", "update"]
+KERNEL_NAMES = {"fine_matvec": "k_wilson_apply", "fine_gs": "k_wilson_gs",
+                "restrict0": "k_restrict_partial (fine level)", "prolong0": "k_prolong (fine level)",
+                "coarse_gs": "k_stencil_gs (level 1)", "dots": "k_dots", "update": "k_update<32>"}
+
+
+def run_steps(lib, torch, ctx, h, b, x, nrhs, precision, steps, warmup, timer=None):
+    """warmup + timed steps; a step = in-place setup + solve of nrhs right-hand sides."""
     sp = lib.default_solve_params(precision=precision)
     infos = None
     for _ in range(warmup):
         h.update()
         infos, _ = h.solve_device(b.data_ptr(), x.data_ptr(), nrhs, sp)
     torch.cuda.synchronize()
+    if timer:
+        ctx.kernel_timer([timer])
     t_setup = 0.0
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -52,7 +61,22 @@ def run_steps(lib, torch, g, h, b, x, nrhs, precision, steps, warmup):
         infos, st = h.solve_device(b.data_ptr(), x.data_ptr(), nrhs, sp)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return dt, t_setup, infos
+    timed = None
+    if timer:
+        timed = ctx.kernel_timer_read(timer)
+        ctx.kernel_timer([])
+    return dt, t_setup, infos, timed
+
+
+def dominant_family(lib, torch, ctx, h, b, x, nrhs, precision):
+    """One instrumented step with every family timed; returns (family, {family: ms})."""
+    ctx.kernel_timer(FAMILIES)
+    h.update()
+    h.solve_device(b.data_ptr(), x.data_ptr(), nrhs, lib.default_solve_params(precision=precision))
+    torch.cuda.synchronize()
+    tot = {f: ctx.kernel_timer_read(f)[1] for f in FAMILIES}
+    ctx.kernel_timer([])
+    return max(tot, key=tot.get), tot
 
 
 def stencil_bandwidth(lib, torch, ctx, L=4096, reps=20):
@@ -126,11 +150,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--nrhs", type=int, default=64)
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stencil", action="store_true")
-    ap.add_argument("--precisions", default="fp64,mixed")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-rhs FP64 path")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -144,36 +168,59 @@ def main():
     torch.cuda.set_stream(stream)
     w = synth.WORKLOADS[args.workload]
     m0 = synth.critical_masses()[w.name] + w.gaps[0] if w.m0 is None else w.m0
-    log(f"workload {w.name}: L={w.L} beta={w.beta} m0={m0:.6f} levels={w.levels} a={w.agg} o={w.overlap}")
+    log(f"workload {w.name}: L={w.L} beta={w.beta} m0={m0:.6f} levels={w.levels} a={w.agg} "
+        f"o={w.overlap} nrhs={args.nrhs}")
     U = w.links()
-    ctx = lib.Context(0, torch.cuda.current_stream().cuda_stream)
+    ctx = lib.Context(0, stream.cuda_stream)
     g = lib.Gauge(ctx, synth.links_to_abi(U), m0)
     h = lib.Hierarchy(g, lib.default_setup_params(levels=w.levels, agg_size=w.agg, overlap=w.overlap,
                                                    n_test_vectors=w.n_test_vectors))
     psi = synth.gaussian_rhs(w.L, w.L, w.rhs_seed, nrhs=args.nrhs)
     b = torch.from_numpy(synth.field_to_abi(psi)).to("cuda")
     x = torch.zeros_like(b)
-    res = {}
-    xs = {}
-    for name in args.precisions.split(","):
-        prec = {"fp64": lib.FP64, "mixed": lib.MIXED_FP32, "bf16": lib.MIXED_FP32_BF16LINKS}[name]
-        dt, t_setup, infos = run_steps(lib, torch, g, h, b, x, args.nrhs, prec, args.steps, args.warmup)
+
+    def summarize(dt, t_setup, infos, nrhs, steps):
         its = [i.iterations for i in infos]
-        res[name] = {"s_per_step": dt / args.steps, "setup_s": t_setup / args.steps,
-                     "solves_per_s": args.nrhs * args.steps / dt,
-                     "solve_only_per_s": args.nrhs * args.steps / (dt - t_setup),
-                     "iterations": its, "true_rel_residual": max(i.true_rel_residual for i in infos),
-                     "converged": all(i.converged for i in infos)}
-        xs[name] = x.clone()
-        log(name, json.dumps(res[name]))
-    if "fp64" in xs and "mixed" in xs:
-        d = (xs["mixed"] - xs["fp64"]).norm() / xs["fp64"].norm()
-        res["mixed"]["rel_diff_vs_fp64"] = float(d)
+        return {"s_per_step": dt / steps, "setup_s": t_setup / steps,
+                "solves_per_s": nrhs * steps / dt,
+                "solve_only_per_s": nrhs * steps / (dt - t_setup),
+                "iterations_min_max": [min(its), max(its)],
+                "true_rel_residual_max": max(i.true_rel_residual for i in infos),
+                "converged": all(i.converged for i in infos)}
+
+    res = {}
+    dt, ts, infos, _ = run_steps(lib, torch, ctx, h, b, x, args.nrhs, lib.FP64, args.steps, args.warmup)
+    res["fp64"] = summarize(dt, ts, infos, args.nrhs, args.steps)
+    x64 = x.clone()
+    log("fp64", json.dumps(res["fp64"]))
+    fam, fam_ms = dominant_family(lib, torch, ctx, h, b, x, args.nrhs, lib.MIXED_FP32)
+    log("dominant family (mixed):", fam, json.dumps({k: round(v, 2) for k, v in fam_ms.items()}))
+    dt, ts, infos, timed = run_steps(lib, torch, ctx, h, b, x, args.nrhs, lib.MIXED_FP32, args.steps,
+                                     args.warmup, timer=fam)
+    res["mixed"] = summarize(dt, ts, infos, args.nrhs, args.steps)
+    res["mixed"]["rel_diff_vs_fp64"] = float((x - x64).norm() / x64.norm())
+    log("mixed", json.dumps(res["mixed"]))
+    launches, ms, nbytes = timed
+    roofline = {"bound": "hbm", "achieved": nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
+                "kernel": KERNEL_NAMES[fam], "family": fam, "launches": launches,
+                "avg_launch_us": ms * 1e3 / max(launches, 1),
+                "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
+                "family_ms_instrumented_step": {k: round(v, 3) for k, v in fam_ms.items()}}
+    roofline["frac"] = roofline["achieved"] / HBM_PEAK_GBS
+    if not args.no_single:
+        h1 = lib.Hierarchy(g, lib.default_setup_params(levels=w.levels, agg_size=w.agg, overlap=w.overlap,
+                                                        n_test_vectors=w.n_test_vectors))
+        b1, x1 = b[:1].contiguous(), torch.zeros_like(b[:1])
+        dt, ts, infos, _ = run_steps(lib, torch, ctx, h1, b1, x1, 1, lib.FP64, args.steps, args.warmup)
+        res["fp64_single_rhs"] = summarize(dt, ts, infos, 1, args.steps)
+        log("fp64 single rhs", json.dumps(res["fp64_single_rhs"]))
+        h1.close()
 
     stencil = None if args.no_stencil else stencil_bandwidth(lib, torch, ctx)
     if stencil:
         log("stencil", json.dumps(stencil))
-    head = res.get("mixed") or res[next(iter(res))]
+    head = res["mixed"]
     line = {
         "metric": "solves/s to rel. residual 1e-10 at L=256 (mixed vs FP64); stencil GB/s; p99",
         "value": head["solves_per_s"],
@@ -181,21 +228,24 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": head["s_per_step"] * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp32+fp64" if "mixed" in res else "f64",
+        "dtype": "f32+f64",
         "data": "synthetic quenched U(1) links (Metropolis), Gaussian right-hand sides",
         "config": {"workload": f"{w.L}x{w.L} beta={w.beta} m0=m_c+{w.gaps[0] if w.gaps else 0}, "
-                               f"{w.levels} levels a={w.agg} o={w.overlap}, Nv={w.n_test_vectors}, "
-                               f"FGMRES({w.restart}) to 1e-10; step = setup + solve of {args.nrhs} rhs",
-                   "nrhs": args.nrhs, "precision": "mixed FP32 V-cycle/matvec in FP64 FGMRES"},
-        "fp64": res.get("fp64"), "mixed": res.get("mixed"),
-        "mixed_over_fp64": (res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"])
-        if "mixed" in res and "fp64" in res else None,
+                               f"{w.levels} levels a={w.agg} o={w.overlap} Nv={w.n_test_vectors}, "
+                               f"FGMRES({w.restart}) to 1e-10; step = AM-AMG setup + solve of "
+                               f"{args.nrhs} right-hand sides",
+                   "nrhs": args.nrhs,
+                   "precision": "FP32 V-cycle and Arnoldi matvec inside FP64 FGMRES"},
+        "fp64": res["fp64"], "mixed": res["mixed"], "fp64_single_rhs": res.get("fp64_single_rhs"),
+        "mixed_over_fp64": res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"],
+        "mixed_batched_over_fp64_single": (res["mixed"]["solves_per_s"] / res["fp64_single_rhs"]["solves_per_s"])
+        if "fp64_single_rhs" in res else None,
+        "roofline": roofline,
         "stencil_4096": stencil,
     }
     if not args.no_cpu_baseline:
-        its = (res.get("fp64") or head)["iterations"][0]
         log("cpu baseline ...")
-        line["cpu_baseline"] = cpu_baseline(w, m0, its)
+        line["cpu_baseline"] = cpu_baseline(w, m0, res["fp64"]["iterations_min_max"][0])
     h.close()
     g.close()
     print(json.dumps(line), flush=True)

@@ -144,6 +144,27 @@ amamg_status amamg_residual_history(const amamg_hierarchy *h, int32_t rhs, doubl
                                     int32_t *is_true_residual, int32_t capacity,
                                     int32_t *n_written);
 
+/* ---- measurement ------------------------------------------------------------------------- */
+typedef enum {
+  AMAMG_KT_OFF = 0,
+  AMAMG_KT_FINE_MATVEC = 1,   /* Arnoldi D z on the fine lattice                            */
+  AMAMG_KT_FINE_GS = 2,       /* one colour of the fine red-black Gauss-Seidel sweep        */
+  AMAMG_KT_RESTRICT0 = 3,     /* fine-level restriction, per-wirebasket pass                 */
+  AMAMG_KT_PROLONG0 = 4,      /* fine-level prolongation                                     */
+  AMAMG_KT_COARSE_GS = 5,     /* one colour of the level-1 block Gauss-Seidel sweep          */
+  AMAMG_KT_DOTS = 6,          /* first Gram-Schmidt projection V^H w                          */
+  AMAMG_KT_UPDATE = 7         /* w -= V h fused with the second projection                    */
+} amamg_kernel_family;
+/* Benchmark hook: from now on, bracket every solve-phase launch of the families whose bits
+ * (1 << family) are set in family_mask (0 stops) with HIP events on the context stream, and
+ * count algorithmic bytes: the bytes the operation must move once, per right-hand side it
+ * served.  Resets all totals. */
+amamg_status amamg_kernel_timer(amamg_context *ctx, uint32_t family_mask);
+/* Totals of one family since the last amamg_kernel_timer call: launches that served at least
+ * one right-hand side, their summed event time in ms and their summed algorithmic bytes. */
+amamg_status amamg_kernel_timer_read(const amamg_context *ctx, int32_t family, int64_t *launches,
+                                     double *total_ms, double *algorithmic_bytes);
+
 /* ---- test hooks (host buffers) ---------------------------------------------------------- */
 /* out = D in for nrhs fields at the given precision (FP64 or FP32 links). */
 amamg_status amamg_apply_dirac(amamg_gauge *g, int32_t precision, int32_t nrhs,

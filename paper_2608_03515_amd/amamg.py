@@ -34,7 +34,9 @@ EXPORTED = ["amamg_default_setup_params", "amamg_default_solve_params", "amamg_c
             "amamg_residual_history", "amamg_apply_dirac", "amamg_apply_dirac_device",
             "amamg_level_info",
             "amamg_get_aggregates", "amamg_get_prolongator", "amamg_get_coarse_operator",
-            "amamg_get_test_vectors"]
+            "amamg_get_test_vectors", "amamg_kernel_timer", "amamg_kernel_timer_read"]
+KT = {"off": 0, "fine_matvec": 1, "fine_gs": 2, "restrict0": 3, "prolong0": 4, "coarse_gs": 5,
+      "dots": 6, "update": 7}
 
 
 class SetupParams(C.Structure):
@@ -79,6 +81,8 @@ _sig = {
     "amamg_get_prolongator": (C.c_int, [_vp, C.c_int32, _vp]),
     "amamg_get_coarse_operator": (C.c_int, [_vp, C.c_int32, _vp]),
     "amamg_get_test_vectors": (C.c_int, [_vp, C.c_int32, _vp]),
+    "amamg_kernel_timer": (C.c_int, [_vp, C.c_uint32]),
+    "amamg_kernel_timer_read": (C.c_int, [_vp, C.c_int32, _P(C.c_int64), _P(C.c_double), _P(C.c_double)]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -126,6 +130,19 @@ class Context:
         if st not in ok:
             raise AmamgError(st, _lib.amamg_last_error(self.h).decode())
         return st
+
+    def kernel_timer(self, families):
+        """Time the named kernel families (list of KT keys; empty list stops)."""
+        mask = 0
+        for f in families:
+            mask |= 1 << KT[f]
+        self.check(_lib.amamg_kernel_timer(self.h, mask))
+
+    def kernel_timer_read(self, family: str):
+        """(launches, total ms, algorithmic bytes) of one family."""
+        n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+        self.check(_lib.amamg_kernel_timer_read(self.h, KT[family], C.byref(n), C.byref(ms), C.byref(by)))
+        return n.value, ms.value, by.value
 
     def close(self):
         if self.h:

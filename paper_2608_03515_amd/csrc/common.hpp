@@ -110,6 +110,8 @@ struct RhsState {
   int done;           // finished: converged or capped
   int hist_len;
   int nonfinite;
+  int last_k;         // Arnoldi steps of the cycle that ended last
+  int pad;
 };
 
 }  // namespace amamg

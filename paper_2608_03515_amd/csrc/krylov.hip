@@ -37,31 +37,22 @@ __device__ inline void block_partial(const double2 (&acc)[NV], int nv, double2* 
   }
 }
 
-// After block_partial: returns true in the block that arrives last; that block then holds in
-// fin[0..nv) the sums over all blocks, added in block order.
-__device__ inline bool last_block_sum(const double2* part_r, int nv, unsigned* counter,
-                                      double2* fin /* shared [KMAXV] */,
-                                      double2* scratch /* shared [8][KMAXV] */) {
-  __shared__ int amlast;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) amlast = (atomicAdd(counter, 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (!amlast) return false;
-  __threadfence();
-  // thread (i, c): column i, blocks c, c + 8, ...; eight independent partial sums keep the
-  // loads in flight, then combine in a fixed order
-  const int i = threadIdx.x & (KMAXV - 1), c = threadIdx.x / KMAXV;   // 8 groups of 32
+// fin[i] = sum over blocks of part_r[blk][i] for i < nv, added in a fixed order (8 strided
+// groups of blocks with eight independent partial sums each, then the groups in order).  Every
+// kernel that needs the total recomputes it with this routine, so all agree bitwise.  Must be
+// called by all 256 threads; fin and scratch are shared arrays.
+__device__ inline void sum_blocks(const double2* __restrict__ part_r, int nblk, int nv,
+                                  double2* fin, double2* scratch) {
+  const int i = threadIdx.x & (KMAXV - 1), c = threadIdx.x / KMAXV;
   double2 s = make_double2(0, 0);
   if (i < nv) {
     double2 q[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) q[u] = make_double2(0, 0);
-    const int nb = int(gridDim.x);
-    for (int b = c; b < nb; b += 64) {
+    for (int b = c; b < nblk; b += 64) {
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (b + 8 * u < nb) q[u] = cadd(q[u], part_r[int64_t(b + 8 * u) * KMAXV + i]);
+        if (b + 8 * u < nblk) q[u] = cadd(q[u], part_r[int64_t(b + 8 * u) * KMAXV + i]);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) s = cadd(s, q[u]);
@@ -73,9 +64,7 @@ __device__ inline bool last_block_sum(const double2* part_r, int nv, unsigned* c
     for (int q = 0; q < 8; ++q) t = cadd(t, scratch[q * KMAXV + threadIdx.x]);
     fin[threadIdx.x] = t;
   }
-  if (threadIdx.x == 0) *counter = 0u;
   __syncthreads();
-  return true;
 }
 
 __device__ inline bool finite_d(double v) { return v == v && v - v == 0.0; }
@@ -85,8 +74,6 @@ struct ArnoldiArgs {
   double* cs;       // [rhs][m]
   double2* sn;      // [rhs][m]
   double2* g;       // [rhs][m+1]
-  const double2* h1;  // [rhs][KMAXV]
-  const double2* h2;
   int j;
   double tol, inner_tol;
   int max_iters;
@@ -96,13 +83,13 @@ struct ArnoldiArgs {
 
 // Arnoldi step j for one rhs, given hn = ||w|| after CGS2.
 __device__ inline void arnoldi_step(const KrylovDims& dm, RhsState& s, int r, double hn,
-                                    const ArnoldiArgs& a) {
+                                    const double2* h1, const double2* h2, const ArnoldiArgs& a) {
   const int m = dm.m, j = a.j;
   double2* Hr = a.H + int64_t(r) * (m + 1) * m;
   double* csr = a.cs + int64_t(r) * m;
   double2* snr = a.sn + int64_t(r) * m;
   double2* gr = a.g + int64_t(r) * (m + 1);
-  for (int i = 0; i <= j; ++i) Hr[i * m + j] = cadd(a.h1[r * KMAXV + i], a.h2[r * KMAXV + i]);
+  for (int i = 0; i <= j; ++i) Hr[i * m + j] = cadd(h1[i], h2[i]);
   Hr[(j + 1) * m + j] = make_double2(hn, 0.0);
   for (int i = 0; i < j; ++i) {
     const double2 x = Hr[i * m + j], y = Hr[(i + 1) * m + j];
@@ -142,16 +129,14 @@ __device__ inline void arnoldi_step(const KrylovDims& dm, RhsState& s, int r, do
   else s.inv_h = 1.0 / hn;
 }
 
-// h = V^H w  (V_0 .. V_{nv-1}); final sums to hout[r][0..nv)
+// partials of h = V^H w  (V_0 .. V_{nv-1})
 __global__ __launch_bounds__(256) void k_dots(KrylovDims dm, const double2* __restrict__ V,
                                               int64_t vsj, int nv, const double2* __restrict__ w,
-                                              double2* __restrict__ part, unsigned* __restrict__ cnt,
-                                              double2* __restrict__ hout,
+                                              double2* __restrict__ part,
                                               const RhsState* __restrict__ st) {
   const int r = blockIdx.y;
   if (st && !st[r].active) return;
   __shared__ double lds[2 * KMAXV * 4];
-  __shared__ double2 fin[KMAXV], scratch[8 * KMAXV];
   double2 acc[KMAXV];
 #pragma unroll
   for (int i = 0; i < KMAXV; ++i) acc[i] = make_double2(0, 0);
@@ -163,27 +148,22 @@ __global__ __launch_bounds__(256) void k_dots(KrylovDims dm, const double2* __re
     for (int i = 0; i < KMAXV; ++i)
       if (i < nv) acc[i] = cfmac(Vr[i * vsj + d], wd, acc[i]);
   }
-  double2* pr = part + int64_t(r) * gridDim.x * KMAXV;
-  block_partial<KMAXV>(acc, nv, pr + int64_t(blockIdx.x) * KMAXV, lds);
-  if (last_block_sum(pr, nv, cnt + r, fin, scratch) && threadIdx.x < nv)
-    hout[r * KMAXV + threadIdx.x] = fin[threadIdx.x];
+  block_partial<KMAXV>(acc, nv, part + (int64_t(r) * gridDim.x + blockIdx.x) * KMAXV, lds);
 }
 
-// w -= sum_i V_i h_i; mode 1: h' = V^H w_new to hout; mode 2: ||w_new|| and Arnoldi step j.
+// w -= sum_i V_i h_i with h the total of the previous kernel's partials hpart; then partials
+// of V^H w_new (NVC = KMAXV) or of ||w_new||^2 (NVC = 1) into part.
 template <int NVC>
 __global__ __launch_bounds__(256) void k_update(KrylovDims dm, const double2* __restrict__ V,
                                                 int64_t vsj, int nv, double2* __restrict__ w,
-                                                const double2* __restrict__ h,
+                                                const double2* __restrict__ hpart,
                                                 double2* __restrict__ part,
-                                                unsigned* __restrict__ cnt,
-                                                double2* __restrict__ hout, int mode,
-                                                RhsState* __restrict__ st, ArnoldiArgs aa) {
+                                                const RhsState* __restrict__ st) {
   const int r = blockIdx.y;
   if (!st[r].active) return;
   __shared__ double lds[2 * KMAXV * 4];
-  __shared__ double2 hs[KMAXV], fin[KMAXV], scratch[8 * KMAXV];
-  if (threadIdx.x < nv) hs[threadIdx.x] = h[r * KMAXV + threadIdx.x];
-  __syncthreads();
+  __shared__ double2 hs[KMAXV], scratch[8 * KMAXV];
+  sum_blocks(hpart + int64_t(r) * gridDim.x * KMAXV, gridDim.x, nv, hs, scratch);
   double2 acc[NVC];
 #pragma unroll
   for (int i = 0; i < NVC; ++i) acc[i] = make_double2(0, 0);
@@ -203,17 +183,25 @@ __global__ __launch_bounds__(256) void k_update(KrylovDims dm, const double2* __
       acc[0].x += cabs2(wd);
     }
   }
-  const int nout = NVC > 1 ? nv : 1;
-  double2* pr = part + int64_t(r) * gridDim.x * KMAXV;
-  block_partial<NVC>(acc, nout, pr + int64_t(blockIdx.x) * KMAXV, lds);
-  if (!last_block_sum(pr, nout, cnt + r, fin, scratch)) return;
-  if (mode == 1) {
-    if (threadIdx.x < nv) hout[r * KMAXV + threadIdx.x] = fin[threadIdx.x];
-  } else if (threadIdx.x == 0) {
-    RhsState s = st[r];
-    arnoldi_step(dm, s, r, sqrt(fin[0].x), aa);
-    st[r] = s;
-  }
+  block_partial<NVC>(acc, NVC > 1 ? nv : 1, part + (int64_t(r) * gridDim.x + blockIdx.x) * KMAXV, lds);
+}
+
+// Arnoldi step j, one block per rhs: h1, h2 and ||w||^2 are the totals of the three partial
+// sets of the Gram-Schmidt kernels.
+__global__ __launch_bounds__(256) void k_arnoldi(KrylovDims dm, const double2* __restrict__ p1,
+                                                 const double2* __restrict__ p2,
+                                                 const double2* __restrict__ p3,
+                                                 RhsState* __restrict__ st, ArnoldiArgs aa, int nv) {
+  const int r = blockIdx.x;
+  if (!st[r].active) return;
+  __shared__ double2 h1[KMAXV], h2[KMAXV], hn[KMAXV], scratch[8 * KMAXV];
+  sum_blocks(p1 + int64_t(r) * dm.nblk * KMAXV, dm.nblk, nv, h1, scratch);
+  sum_blocks(p2 + int64_t(r) * dm.nblk * KMAXV, dm.nblk, nv, h2, scratch);
+  sum_blocks(p3 + int64_t(r) * dm.nblk * KMAXV, dm.nblk, 1, hn, scratch);
+  if (threadIdx.x != 0) return;
+  RhsState s = st[r];
+  arnoldi_step(dm, s, r, sqrt(hn[0].x), h1, h2, aa);
+  st[r] = s;
 }
 
 // ||x||^2 per rhs, then: mode 0 store only; 1 start states (x = b); 2 first cycle start
@@ -228,6 +216,7 @@ struct CycleArgs {
 
 __device__ inline void begin_cycle(const KrylovDims& dm, RhsState& s, int r, double beta,
                                    int first, const CycleArgs& ca) {
+  s.last_k = s.k;
   if (s.done || !s.in_cycle || s.nonfinite) {
     if (s.nonfinite) s.done = 1;
     s.active = 0;
@@ -256,20 +245,28 @@ __device__ inline void begin_cycle(const KrylovDims& dm, RhsState& s, int r, dou
 }
 
 __global__ __launch_bounds__(256) void k_norm(KrylovDims dm, const double2* __restrict__ x,
-                                              double2* __restrict__ part, unsigned* __restrict__ cnt,
-                                              RhsState* __restrict__ st, int mode, CycleArgs ca) {
+                                              double2* __restrict__ part,
+                                              const RhsState* __restrict__ st, int only_active) {
   const int r = blockIdx.y;
-  if (mode >= 2 && !st[r].active) return;
+  if (only_active && !st[r].active) return;
   __shared__ double lds[2 * KMAXV * 4];
-  __shared__ double2 fin[KMAXV], scratch[8 * KMAXV];
   double2 acc[1] = {make_double2(0, 0)};
   const double2* xr = x + r * dm.n;
   for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < dm.n; d += int64_t(gridDim.x) * 256)
     acc[0].x += cabs2(xr[d]);
-  double2* pr = part + int64_t(r) * gridDim.x * KMAXV;
-  block_partial<1>(acc, 1, pr + int64_t(blockIdx.x) * KMAXV, lds);
-  if (!last_block_sum(pr, 1, cnt + r, fin, scratch) || threadIdx.x != 0) return;
-  const double nrm = sqrt(fin[0].x);
+  block_partial<1>(acc, 1, part + (int64_t(r) * gridDim.x + blockIdx.x) * KMAXV, lds);
+}
+
+// one block per rhs: mode 1 fresh states (x = b); 2 first cycle start (x = r_0); 3 end of a
+// cycle (x = b - D x) and the next cycle's start
+__global__ __launch_bounds__(256) void k_cycle(KrylovDims dm, const double2* __restrict__ part,
+                                               RhsState* __restrict__ st, int mode, CycleArgs ca) {
+  const int r = blockIdx.x;
+  if (mode >= 2 && !st[r].active) return;
+  __shared__ double2 nr[KMAXV], scratch[8 * KMAXV];
+  sum_blocks(part + int64_t(r) * dm.nblk * KMAXV, dm.nblk, 1, nr, scratch);
+  if (threadIdx.x != 0) return;
+  const double nrm = sqrt(nr[0].x);
   if (mode == 1) {
     RhsState s = {};
     s.bnorm = nrm;
@@ -279,7 +276,7 @@ __global__ __launch_bounds__(256) void k_norm(KrylovDims dm, const double2* __re
     s.active = s.done ? 0 : 1;
     s.in_cycle = s.active;
     st[r] = s;
-  } else if (mode >= 2) {
+  } else {
     RhsState s = st[r];
     begin_cycle(dm, s, r, nrm, mode == 2, ca);
     st[r] = s;
@@ -339,32 +336,34 @@ __global__ __launch_bounds__(256) void k_update_x(KrylovDims dm, const RhsState*
 // ------------------------------------------------------------------------------ launchers
 
 void dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
-          const double2* w, double2* part, unsigned* cnt, double2* hout, const RhsState* st) {
-  hipLaunchKernelGGL(k_dots, dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, nv, w, part, cnt, hout, st);
+          const double2* w, double2* part, const RhsState* st) {
+  hipLaunchKernelGGL(k_dots, dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, nv, w, part, st);
 }
 
 void update_dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
-                 double2* w, const double2* h, double2* part, unsigned* cnt, double2* hout,
-                 RhsState* st) {
-  ArnoldiArgs aa{};
-  hipLaunchKernelGGL((k_update<KMAXV>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, nv, w, h,
-                     part, cnt, hout, 1, st, aa);
+                 double2* w, const double2* hpart, double2* part, const RhsState* st) {
+  hipLaunchKernelGGL((k_update<KMAXV>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, nv, w, hpart,
+                     part, st);
 }
 
-void update_norm_arnoldi(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
-                         double2* w, const double2* h2, double2* part, unsigned* cnt, RhsState* st,
-                         double2* H, double* cs, double2* sn, double2* g, const double2* h1, int j,
-                         double tol, double inner_tol, int max_iters, double2* hist, int hist_cap) {
-  ArnoldiArgs aa{H, cs, sn, g, h1, h2, j, tol, inner_tol, max_iters, hist, hist_cap};
-  hipLaunchKernelGGL((k_update<1>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, nv, w, h2,
-                     part, cnt, (double2*)nullptr, 2, st, aa);
+void update_norm(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
+                 double2* w, const double2* hpart, double2* part, const RhsState* st) {
+  hipLaunchKernelGGL((k_update<1>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, nv, w, hpart,
+                     part, st);
 }
 
-void norm_control(hipStream_t s, const KrylovDims& d, const double2* x, double2* part, unsigned* cnt,
-                  RhsState* st, int mode, double2* g, double tol, int max_iters, double2* hist,
-                  int hist_cap) {
+void arnoldi(hipStream_t s, const KrylovDims& d, const double2* p1, const double2* p2,
+             const double2* p3, RhsState* st, double2* H, double* cs, double2* sn, double2* g,
+             int j, double tol, double inner_tol, int max_iters, double2* hist, int hist_cap) {
+  ArnoldiArgs aa{H, cs, sn, g, j, tol, inner_tol, max_iters, hist, hist_cap};
+  hipLaunchKernelGGL(k_arnoldi, dim3(d.nrhs), dim3(256), 0, s, d, p1, p2, p3, st, aa, j + 1);
+}
+
+void norm_control(hipStream_t s, const KrylovDims& d, const double2* x, double2* part, RhsState* st,
+                  int mode, double2* g, double tol, int max_iters, double2* hist, int hist_cap) {
   CycleArgs ca{g, tol, max_iters, hist, hist_cap};
-  hipLaunchKernelGGL(k_norm, dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, x, part, cnt, st, mode, ca);
+  hipLaunchKernelGGL(k_norm, dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, x, part, st, mode >= 2 ? 1 : 0);
+  hipLaunchKernelGGL(k_cycle, dim3(d.nrhs), dim3(256), 0, s, d, part, st, mode, ca);
 }
 
 void scale_next(hipStream_t s, const KrylovDims& d, const double2* w, double2* v, const RhsState* st) {

@@ -94,25 +94,26 @@ void probe_extract(hipStream_t s, const Geom& gc, int pt, int px, int ct, int cx
 void cast_matrix(hipStream_t s, const double2* A, float2* out, int64_t n);
 
 // ---- Krylov (FP64) -----------------------------------------------------------------------
-// Reductions finish in the last block to arrive (per-rhs counters, zero between launches).
+// Reductions are per-block partials [rhs][nblk][32]; the consumer of a reduction adds them in a
+// fixed order itself.
 struct KrylovDims { int64_t n; int nrhs; int nblk; int m; };
-// hout[r][i] = (V_i^H w)_r for i < nv
+// partials of V^H w (V_0 .. V_{nv-1})
 void dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
-          const double2* w, double2* part, unsigned* cnt, double2* hout, const RhsState* st);
-// w -= V h; hout = V^H w_new
+          const double2* w, double2* part, const RhsState* st);
+// w -= V h (h = total of hpart); partials of V^H w_new into part
 void update_dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
-                 double2* w, const double2* h, double2* part, unsigned* cnt, double2* hout,
-                 RhsState* st);
-// w -= V h2; h_{j+1,j} = ||w||; Hessenberg column h1 + h2, rotations, end-of-cycle test
-void update_norm_arnoldi(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
-                         double2* w, const double2* h2, double2* part, unsigned* cnt, RhsState* st,
-                         double2* H, double* cs, double2* sn, double2* g, const double2* h1, int j,
-                         double tol, double inner_tol, int max_iters, double2* hist, int hist_cap);
+                 double2* w, const double2* hpart, double2* part, const RhsState* st);
+// w -= V h (h = total of hpart); partials of ||w_new||^2 into part
+void update_norm(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
+                 double2* w, const double2* hpart, double2* part, const RhsState* st);
+// Arnoldi step j from the three partial sets: Hessenberg column, rotations, end-of-cycle test
+void arnoldi(hipStream_t s, const KrylovDims& d, const double2* p1, const double2* p2,
+             const double2* p3, RhsState* st, double2* H, double* cs, double2* sn, double2* g,
+             int j, double tol, double inner_tol, int max_iters, double2* hist, int hist_cap);
 // ||x|| then mode 1: fresh states (x = b); 2: first cycle start (x = r_0); 3: cycle end and
 // restart (x = b - D x)
-void norm_control(hipStream_t s, const KrylovDims& d, const double2* x, double2* part, unsigned* cnt,
-                  RhsState* st, int mode, double2* g, double tol, int max_iters, double2* hist,
-                  int hist_cap);
+void norm_control(hipStream_t s, const KrylovDims& d, const double2* x, double2* part, RhsState* st,
+                  int mode, double2* g, double tol, int max_iters, double2* hist, int hist_cap);
 void scale_next(hipStream_t s, const KrylovDims& d, const double2* w, double2* v,
                 const RhsState* st);
 void backsolve_update(hipStream_t s, const KrylovDims& d, RhsState* st, const double2* H,

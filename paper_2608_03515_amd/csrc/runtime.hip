@@ -87,11 +87,25 @@ int period_of(int L) {
 
 }  // namespace
 
+// Benchmark timer: HIP events around every launch of one kernel family in the solve.  A
+// launch's algorithmic bytes are its per-rhs bytes times the right-hand sides it served,
+// which the host learns at the end of each restart cycle.
+struct KernelTimer {
+  static constexpr int NF = 8;
+  uint32_t mask = 0;
+  std::vector<hipEvent_t> events;
+  struct Rec { int e0, e1, step, family; double bytes_per_rhs; };
+  std::vector<Rec> pending;
+  int64_t launches[NF] = {};
+  double total_ms[NF] = {}, total_bytes[NF] = {};
+};
+
 struct amamg_context {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
+  KernelTimer timer;
 };
 
 struct amamg_gauge {
@@ -149,11 +163,10 @@ struct amamg_hierarchy {
   int ws_nrhs = 0, ws_m = 0, ws_hist = 0;
   Real ws_prec = F64;
   double2 *V = nullptr, *w = nullptr, *H = nullptr, *g = nullptr, *sn = nullptr, *y = nullptr;
-  double2 *h1 = nullptr, *h2 = nullptr, *part = nullptr, *hist = nullptr;
+  double2 *part = nullptr, *hist = nullptr;
   double* cs = nullptr;
   void* Z = nullptr;
   RhsState* st = nullptr;
-  unsigned* cnt = nullptr;   // reduction counters [4][nrhs]
   int nblk = 1;
   std::vector<std::vector<double2>> history;
 };
@@ -170,6 +183,44 @@ amamg_status fail(amamg_context* ctx, const Fail& f) {
 void check_launch() {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw Fail{AMAMG_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e)};
+}
+
+int timer_event(KernelTimer& t, size_t idx) {
+  while (t.events.size() <= idx) {
+    hipEvent_t e;
+    HIPCHECK(hipEventCreate(&e));
+    t.events.push_back(e);
+  }
+  return int(idx);
+}
+
+// Start / stop recording one launch of `family` at Arnoldi step `step`.
+int timer_start(amamg_context* ctx, int family, int step, double bytes_per_rhs) {
+  KernelTimer& t = ctx->timer;
+  if (!(t.mask & (1u << family))) return -1;
+  const int e0 = timer_event(t, 2 * t.pending.size()), e1 = timer_event(t, 2 * t.pending.size() + 1);
+  HIPCHECK(hipEventRecord(t.events[e0], ctx->stream));
+  t.pending.push_back({e0, e1, step, family, bytes_per_rhs});
+  return int(t.pending.size()) - 1;
+}
+void timer_stop(amamg_context* ctx, int rec) {
+  if (rec < 0) return;
+  KernelTimer& t = ctx->timer;
+  HIPCHECK(hipEventRecord(t.events[t.pending[rec].e1], ctx->stream));
+}
+// After a synchronisation: account the pending launches; served(step) = rhs active at that step.
+template <typename F> void timer_flush(amamg_context* ctx, F served) {
+  KernelTimer& t = ctx->timer;
+  for (const auto& r : t.pending) {
+    const int n = served(r.step);
+    if (n <= 0) continue;
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, t.events[r.e0], t.events[r.e1]));
+    t.launches[r.family] += 1;
+    t.total_ms[r.family] += ms;
+    t.total_bytes[r.family] += r.bytes_per_rhs * n;
+  }
+  t.pending.clear();
 }
 
 // footprint tables: postab[pos] = F index or -(1 + vcol); followed by fpos[nf]
@@ -470,13 +521,9 @@ void ensure_workspace(amamg_hierarchy* h, int nrhs, int m, Real prec, int hist_c
   h->cs = h->ws.alloc<double>(size_t(nrhs) * m);
   h->sn = h->ws.alloc<double2>(size_t(nrhs) * m);
   h->y = h->ws.alloc<double2>(size_t(nrhs) * m);
-  h->h1 = h->ws.alloc<double2>(size_t(nrhs) * 32);
-  h->h2 = h->ws.alloc<double2>(size_t(nrhs) * 32);
   h->nblk = int(std::min<int64_t>(256, std::max<int64_t>(1, n / 512)));
-  h->part = h->ws.alloc<double2>(size_t(nrhs) * h->nblk * 32);
+  h->part = h->ws.alloc<double2>(size_t(3) * nrhs * h->nblk * 32);
   h->st = h->ws.alloc<RhsState>(nrhs);
-  h->cnt = h->ws.alloc<unsigned>(size_t(4) * nrhs);
-  HIPCHECK(hipMemsetAsync(h->cnt, 0, sizeof(unsigned) * 4 * nrhs, h->gauge->ctx->stream));
   h->hist = h->ws.alloc<double2>(size_t(nrhs) * hist_cap);
   for (size_t k = 1; k < h->lv.size(); ++k) {
     LevelData& L = h->lv[k];
@@ -502,6 +549,7 @@ struct SolveCtx {
   Real T;
   LinkStore smooth_links, mat_links;
   int nrhs;
+  int step;        // Arnoldi step of the current V-cycle (kernel timer)
 };
 
 const void* link0(amamg_gauge* g, LinkStore ls) {
@@ -534,6 +582,7 @@ void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x) {
   const void* U1 = link1(gg, c.smooth_links);
   const void* Ak = f64 ? (const void*)L.A : (const void*)L.A32;
   const void* Dk = f64 ? (const void*)L.Dinv : (const void*)L.Dinv32;
+  const double cb = f64 ? 16.0 : 8.0;   // bytes per complex value
   if (pre > 0) {
     HIPCHECK(hipMemsetAsync(x, 0, nd * c.nrhs * (f64 ? 16 : 8), c.s));
     for (int sw = 0; sw < pre; ++sw) {
@@ -550,17 +599,42 @@ void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x) {
       stencil_apply(c.s, c.T, Ak, x, L.tmp, f, g.Lt, g.Lx, g.b, c.nrhs, nd, st);
     restrict_(c.s, c.T, P, L.rows, L.nrows, L.nf, c.T, L.tmp, C.f, L.rpart, g, c.nrhs, nd, ndc, st);
   } else {
+    const double fb = fprec == F64 ? 16 : 8;
+    const double owned = double(nd) * (1.0 - double(g.o * g.o) / double(g.a * g.a));
+    const int rec = k == 0 ? timer_start(gg->ctx, AMAMG_KT_RESTRICT0, c.step,
+                                         owned * (g.ncol() * cb + fb) + double(g.nI) * g.nJ * restrict_chunks(g, L.nf) * g.ncol() * cb)
+                           : -1;
     restrict_(c.s, c.T, P, L.rows, L.nrows, L.nf, fprec, f, C.f, L.rpart, g, c.nrhs, nd, ndc, st);
+    timer_stop(gg->ctx, rec);
   }
   vcycle(c, k + 1, c.T, C.f, C.x);
-  prolong(c.s, c.T, P, L.owner, L.node, C.x, x, g, pre > 0 ? 1 : 0, c.nrhs, nd, ndc, st);
+  {
+    const double owned = double(nd) * (1.0 - double(g.o * g.o) / double(g.a * g.a));
+    const int rec = k == 0 ? timer_start(gg->ctx, AMAMG_KT_PROLONG0, c.step,
+                                         owned * g.ncol() * cb + double(nd) * cb + double(ndc) * cb)
+                           : -1;
+    prolong(c.s, c.T, P, L.owner, L.node, C.x, x, g, pre > 0 ? 1 : 0, c.nrhs, nd, ndc, st);
+    timer_stop(gg->ctx, rec);
+  }
   for (int sw = 0; sw < post; ++sw) {
-    if (k == 0)
-      for (int col = 0; col < 2; ++col)
+    if (k == 0) {
+      const double cl = c.smooth_links == LINK_F64 ? 16 : c.smooth_links == LINK_F32 ? 8 : 4;
+      for (int col = 0; col < 2; ++col) {
+        const int rec = timer_start(gg->ctx, AMAMG_KT_FINE_GS, c.step,
+                                    double(g.nnode()) * (2 * cb + 2 * cl + 16));
         wilson_gs(c.s, c.smooth_links, U0, U1, c.T, x, (const double2*)f, g.Lt, g.Lx, h->m0, col, c.nrhs, nd, st);
-    else
-      for (int col = 0; col < 16; ++col)
+        timer_stop(gg->ctx, rec);
+      }
+    } else {
+      for (int col = 0; col < 16; ++col) {
+        const double ncn = double(g.nnode()) / 16.0;
+        const int rec = k == 1 ? timer_start(gg->ctx, AMAMG_KT_COARSE_GS, c.step,
+                                             ncn * 25.0 * g.b * g.b * cb + double(nd) * cb + 2.0 * ncn * g.b * cb)
+                               : -1;
         stencil_gs(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, col, c.nrhs, nd, st);
+        timer_stop(gg->ctx, rec);
+      }
+    }
   }
 }
 
@@ -577,7 +651,7 @@ amamg_status run_solve(amamg_hierarchy* h, int nrhs, const double2* b, double2* 
   const Real T = p.precision == AMAMG_FP64 ? F64 : F32;
   const int hist_cap = 2 * p.max_iters + 2;
   ensure_workspace(h, nrhs, m, T, hist_cap);
-  SolveCtx c{h, s, T, LINK_F64, LINK_F64, nrhs};
+  SolveCtx c{h, s, T, LINK_F64, LINK_F64, nrhs, 0};
   if (p.precision == AMAMG_MIXED_FP32) { c.smooth_links = LINK_F32; c.mat_links = LINK_F32; }
   if (p.precision == AMAMG_MIXED_FP32_BF16LINKS) { c.smooth_links = LINK_BF16; c.mat_links = LINK_F32; }
   ensure_links(gg, c.smooth_links);
@@ -591,12 +665,11 @@ amamg_status run_solve(amamg_hierarchy* h, int nrhs, const double2* b, double2* 
   const size_t zs = T == F64 ? sizeof(double2) : sizeof(float2);
   const int64_t vsj = int64_t(nrhs) * n;   // basis stride between j
 
-  unsigned* cnt_dot = h->cnt;
-  unsigned* cnt_up1 = h->cnt + nrhs;
-  unsigned* cnt_up2 = h->cnt + 2 * nrhs;
-  unsigned* cnt_nrm = h->cnt + 3 * nrhs;
+  double2* p1 = h->part;
+  double2* p2 = h->part + size_t(nrhs) * h->nblk * 32;
+  double2* p3 = h->part + size_t(2) * nrhs * h->nblk * 32;
   // ||b||; refuse non-finite input before touching x
-  norm_control(s, kd, b, h->part, cnt_nrm, st, 1, h->g, p.rel_tol, p.max_iters, h->hist, hist_cap);
+  norm_control(s, kd, b, p1, st, 1, h->g, p.rel_tol, p.max_iters, h->hist, hist_cap);
   check_launch();
   std::vector<RhsState> hs(nrhs);
   HIPCHECK(hipMemcpyAsync(hs.data(), st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, s));
@@ -607,33 +680,53 @@ amamg_status run_solve(amamg_hierarchy* h, int nrhs, const double2* b, double2* 
   if (!p.use_initial_guess) HIPCHECK(hipMemsetAsync(x, 0, sizeof(double2) * nrhs * n, s));
   // r = b - D x into V_0, its norm, the first cycle start, V_0 = r / ||r||
   wilson_apply(s, LINK_F64, gg->U, gg->U + int64_t(nt) * nx, F64, x, F64, h->V, b, nt, nx, h->m0, nrhs, n, st);
-  norm_control(s, kd, h->V, h->part, cnt_nrm, st, 2, h->g, p.rel_tol, p.max_iters, h->hist, hist_cap);
+  norm_control(s, kd, h->V, p1, st, 2, h->g, p.rel_tol, p.max_iters, h->hist, hist_cap);
   scale_next(s, kd, h->V, h->V, st);
   check_launch();
 
   const void* Um0 = link0(gg, c.mat_links);
   const void* Um1 = link1(gg, c.mat_links);
+  std::vector<int> cycle_in(nrhs, 0);
+  gg->ctx->timer.pending.clear();
   for (;;) {
     HIPCHECK(hipMemcpyAsync(hs.data(), st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
+    // kernel timer: rhs served at step j of the cycle that just ended
+    timer_flush(gg->ctx, [&](int step) {
+      int cnt = 0;
+      for (int r = 0; r < nrhs; ++r) cnt += (cycle_in[r] && hs[r].last_k > step) ? 1 : 0;
+      return cnt;
+    });
     bool any = false;
-    for (int r = 0; r < nrhs; ++r) any = any || hs[r].in_cycle;
+    for (int r = 0; r < nrhs; ++r) {
+      cycle_in[r] = hs[r].in_cycle;
+      any = any || hs[r].in_cycle;
+    }
     if (!any) break;
+    const double cl = c.mat_links == LINK_F64 ? 16 : 8;
     for (int j = 0; j < m; ++j) {
       double2* vj = h->V + j * vsj;
       void* zj = (char*)h->Z + size_t(j) * vsj * zs;
+      c.step = j;
       vcycle(c, 0, F64, vj, zj);
+      int rec = timer_start(gg->ctx, AMAMG_KT_FINE_MATVEC, j, double(nt) * nx * (2 * zs + 2 * cl + 32));
       wilson_apply(s, c.mat_links, Um0, Um1, T, zj, F64, h->w, nullptr, nt, nx, h->m0, nrhs, n, st);
-      dots(s, kd, h->V, vsj, j + 1, h->w, h->part, cnt_dot, h->h1, st);
-      update_dots(s, kd, h->V, vsj, j + 1, h->w, h->h1, h->part, cnt_up1, h->h2, st);
-      update_norm_arnoldi(s, kd, h->V, vsj, j + 1, h->w, h->h2, h->part, cnt_up2, st, h->H, h->cs,
-                          h->sn, h->g, h->h1, j, p.rel_tol, inner_tol, p.max_iters, h->hist, hist_cap);
+      timer_stop(gg->ctx, rec);
+      rec = timer_start(gg->ctx, AMAMG_KT_DOTS, j, double(j + 2) * n * 16);
+      dots(s, kd, h->V, vsj, j + 1, h->w, p1, st);
+      timer_stop(gg->ctx, rec);
+      rec = timer_start(gg->ctx, AMAMG_KT_UPDATE, j, double(j + 3) * n * 16);
+      update_dots(s, kd, h->V, vsj, j + 1, h->w, p1, p2, st);
+      timer_stop(gg->ctx, rec);
+      update_norm(s, kd, h->V, vsj, j + 1, h->w, p2, p3, st);
+      arnoldi(s, kd, p1, p2, p3, st, h->H, h->cs, h->sn, h->g, j, p.rel_tol, inner_tol, p.max_iters,
+              h->hist, hist_cap);
       if (j + 1 < m) scale_next(s, kd, h->w, h->V + (j + 1) * vsj, st);
       check_launch();
     }
     backsolve_update(s, kd, st, h->H, h->g, h->y, T, h->Z, vsj, x);
     wilson_apply(s, LINK_F64, gg->U, gg->U + int64_t(nt) * nx, F64, x, F64, h->V, b, nt, nx, h->m0, nrhs, n, st);
-    norm_control(s, kd, h->V, h->part, cnt_nrm, st, 3, h->g, p.rel_tol, p.max_iters, h->hist, hist_cap);
+    norm_control(s, kd, h->V, p1, st, 3, h->g, p.rel_tol, p.max_iters, h->hist, hist_cap);
     scale_next(s, kd, h->V, h->V, st);
     check_launch();
   }
@@ -710,6 +803,7 @@ amamg_status amamg_context_create(int device, void* hip_stream, amamg_context** 
 
 amamg_status amamg_context_destroy(amamg_context* ctx) {
   if (!ctx) return AMAMG_ERR_INVALID_ARG;
+  for (hipEvent_t e : ctx->timer.events) (void)hipEventDestroy(e);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return AMAMG_OK;
@@ -909,6 +1003,28 @@ amamg_status amamg_apply_dirac_device(amamg_gauge* g, int32_t precision, int32_t
   } catch (const Fail& f) {
     return fail(ctx, f);
   }
+  return AMAMG_OK;
+}
+
+amamg_status amamg_kernel_timer(amamg_context* ctx, uint32_t family_mask) {
+  if (!ctx || (family_mask & 1u) || family_mask >= (1u << KernelTimer::NF)) return AMAMG_ERR_INVALID_ARG;
+  KernelTimer& t = ctx->timer;
+  t.mask = family_mask;
+  t.pending.clear();
+  for (int f = 0; f < KernelTimer::NF; ++f) {
+    t.launches[f] = 0;
+    t.total_ms[f] = 0.0;
+    t.total_bytes[f] = 0.0;
+  }
+  return AMAMG_OK;
+}
+
+amamg_status amamg_kernel_timer_read(const amamg_context* ctx, int32_t family, int64_t* launches,
+                                     double* total_ms, double* algorithmic_bytes) {
+  if (!ctx || family <= 0 || family >= KernelTimer::NF) return AMAMG_ERR_INVALID_ARG;
+  if (launches) *launches = ctx->timer.launches[family];
+  if (total_ms) *total_ms = ctx->timer.total_ms[family];
+  if (algorithmic_bytes) *algorithmic_bytes = ctx->timer.total_bytes[family];
   return AMAMG_OK;
 }
 
