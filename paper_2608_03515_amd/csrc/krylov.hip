@@ -12,6 +12,9 @@
 // (c x + s y, -conj(s) x + c y); g_{j+1} = -conj(s) g_j, g_j = c g_j.
 //
 // Vector layouts: basis V [j][rhs][n], search directions Z [j][rhs][n], w and x [rhs][n].
+#include <array>
+#include <utility>
+
 #include "launch.hpp"
 
 namespace amamg {
@@ -129,61 +132,63 @@ __device__ inline void arnoldi_step(const KrylovDims& dm, RhsState& s, int r, do
   else s.inv_h = 1.0 / hn;
 }
 
-// partials of h = V^H w  (V_0 .. V_{nv-1})
+// partials of h = V^H w  (V_0 .. V_{NV-1}); NV is a compile-time count so the accumulators
+// fit the actual basis size
+template <int NV>
 __global__ __launch_bounds__(256) void k_dots(KrylovDims dm, const double2* __restrict__ V,
-                                              int64_t vsj, int nv, const double2* __restrict__ w,
+                                              int64_t vsj, const double2* __restrict__ w,
                                               double2* __restrict__ part,
                                               const RhsState* __restrict__ st) {
   const int r = blockIdx.y;
   if (st && !st[r].active) return;
-  __shared__ double lds[2 * KMAXV * 4];
-  double2 acc[KMAXV];
+  __shared__ double lds[2 * NV * 4];
+  double2 acc[NV];
 #pragma unroll
-  for (int i = 0; i < KMAXV; ++i) acc[i] = make_double2(0, 0);
+  for (int i = 0; i < NV; ++i) acc[i] = make_double2(0, 0);
   const double2* wr = w + r * dm.n;
   const double2* Vr = V + r * dm.n;
   for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < dm.n; d += int64_t(gridDim.x) * 256) {
     const double2 wd = wr[d];
 #pragma unroll
-    for (int i = 0; i < KMAXV; ++i)
-      if (i < nv) acc[i] = cfmac(Vr[i * vsj + d], wd, acc[i]);
+    for (int i = 0; i < NV; ++i) acc[i] = cfmac(Vr[i * vsj + d], wd, acc[i]);
   }
-  block_partial<KMAXV>(acc, nv, part + (int64_t(r) * gridDim.x + blockIdx.x) * KMAXV, lds);
+  block_partial<NV>(acc, NV, part + (int64_t(r) * gridDim.x + blockIdx.x) * KMAXV, lds);
 }
 
 // w -= sum_i V_i h_i with h the total of the previous kernel's partials hpart; then partials
-// of V^H w_new (NVC = KMAXV) or of ||w_new||^2 (NVC = 1) into part.
-template <int NVC>
-__global__ __launch_bounds__(256) void k_update(KrylovDims dm, const double2* __restrict__ V,
-                                                int64_t vsj, int nv, double2* __restrict__ w,
+// of V^H w_new (DOTS) or of ||w_new||^2 into part.
+template <int NV, bool DOTS>
+__global__ __launch_bounds__(256) void k_update(KrylovDims dm, const double2* V,
+                                                int64_t vsj, double2* w,
                                                 const double2* __restrict__ hpart,
                                                 double2* __restrict__ part,
                                                 const RhsState* __restrict__ st) {
   const int r = blockIdx.y;
   if (!st[r].active) return;
-  __shared__ double lds[2 * KMAXV * 4];
+  constexpr int NA = DOTS ? NV : 1;
+  __shared__ double lds[2 * NA * 4];
   __shared__ double2 hs[KMAXV], scratch[8 * KMAXV];
-  sum_blocks(hpart + int64_t(r) * gridDim.x * KMAXV, gridDim.x, nv, hs, scratch);
-  double2 acc[NVC];
+  sum_blocks(hpart + int64_t(r) * gridDim.x * KMAXV, gridDim.x, NV, hs, scratch);
+  double2 acc[NA];
 #pragma unroll
-  for (int i = 0; i < NVC; ++i) acc[i] = make_double2(0, 0);
+  for (int i = 0; i < NA; ++i) acc[i] = make_double2(0, 0);
   double2* wr = w + r * dm.n;
   const double2* Vr = V + r * dm.n;
   for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < dm.n; d += int64_t(gridDim.x) * 256) {
     double2 wd = wr[d];
 #pragma unroll
-    for (int i = 0; i < KMAXV; ++i)
-      if (i < nv) wd = csub(wd, cmul(Vr[i * vsj + d], hs[i]));
+    for (int i = 0; i < NV; ++i) wd = csub(wd, cmul(Vr[i * vsj + d], hs[i]));
     wr[d] = wd;
-    if (NVC > 1) {
+    if (DOTS) {
+      // second read of the basis elements (cache hits; V and w are not declared restrict, so
+      // the store above keeps the compiler from holding all NV values in registers)
 #pragma unroll
-      for (int i = 0; i < NVC; ++i)
-        if (i < nv) acc[i] = cfmac(Vr[i * vsj + d], wd, acc[i]);
+      for (int i = 0; i < NA; ++i) acc[i] = cfmac(Vr[i * vsj + d], wd, acc[i]);
     } else {
       acc[0].x += cabs2(wd);
     }
   }
-  block_partial<NVC>(acc, NVC > 1 ? nv : 1, part + (int64_t(r) * gridDim.x + blockIdx.x) * KMAXV, lds);
+  block_partial<NA>(acc, NA, part + (int64_t(r) * gridDim.x + blockIdx.x) * KMAXV, lds);
 }
 
 // Arnoldi step j, one block per rhs: h1, h2 and ||w||^2 are the totals of the three partial
@@ -335,21 +340,44 @@ __global__ __launch_bounds__(256) void k_update_x(KrylovDims dm, const RhsState*
 
 // ------------------------------------------------------------------------------ launchers
 
+using KFn = void (*)(hipStream_t, const KrylovDims&, const double2*, int64_t, double2*,
+                    const double2*, double2*, const RhsState*);
+
+template <int NV> void launch_dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj,
+                                   double2* w, const double2*, double2* part, const RhsState* st) {
+  hipLaunchKernelGGL((k_dots<NV>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, w, part, st);
+}
+template <int NV, bool DOTS>
+void launch_update(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, double2* w,
+                   const double2* hpart, double2* part, const RhsState* st) {
+  hipLaunchKernelGGL((k_update<NV, DOTS>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, w, hpart,
+                     part, st);
+}
+template <int... I>
+static constexpr std::array<KFn, sizeof...(I)> table_dots(std::integer_sequence<int, I...>) {
+  return {&launch_dots<I + 1>...};
+}
+template <bool DOTS, int... I>
+static constexpr std::array<KFn, sizeof...(I)> table_update(std::integer_sequence<int, I...>) {
+  return {&launch_update<I + 1, DOTS>...};
+}
+static const auto kDots = table_dots(std::make_integer_sequence<int, KMAXV>{});
+static const auto kUpdDots = table_update<true>(std::make_integer_sequence<int, KMAXV>{});
+static const auto kUpdNorm = table_update<false>(std::make_integer_sequence<int, KMAXV>{});
+
 void dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
           const double2* w, double2* part, const RhsState* st) {
-  hipLaunchKernelGGL(k_dots, dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, nv, w, part, st);
+  kDots[nv - 1](s, d, V, vsj, const_cast<double2*>(w), nullptr, part, st);
 }
 
 void update_dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
                  double2* w, const double2* hpart, double2* part, const RhsState* st) {
-  hipLaunchKernelGGL((k_update<KMAXV>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, nv, w, hpart,
-                     part, st);
+  kUpdDots[nv - 1](s, d, V, vsj, w, hpart, part, st);
 }
 
 void update_norm(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
                  double2* w, const double2* hpart, double2* part, const RhsState* st) {
-  hipLaunchKernelGGL((k_update<1>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, nv, w, hpart,
-                     part, st);
+  kUpdNorm[nv - 1](s, d, V, vsj, w, hpart, part, st);
 }
 
 void arnoldi(hipStream_t s, const KrylovDims& d, const double2* p1, const double2* p2,

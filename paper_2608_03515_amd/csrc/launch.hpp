@@ -54,16 +54,16 @@ void dense_apply(hipStream_t s, Real prec, const double2* Ainv, const void* v, v
                  int nrhs, int64_t stride, const RhsState* st);
 
 // ---- transfer between level k (fine side, geometry g) and k+1 ----------------------------
-// y = P e   (add != 0: y += P e); e: coarse vector in prec; y: fine vector in prec
-void prolong(hipStream_t s, Real prec, const void* P, const int* owner, const int* node,
-             const void* e, void* y, const Geom& g, int add, int nrhs, int64_t stride_f,
-             int64_t stride_c, const RhsState* st);
-// rc = P^H r; r in `rin` precision (FP64 basis vector or prec), rc in prec.  rows/nrows: the
-// owned fine rows of each wirebasket (owned_rows); part: scratch of
-// nrhs * nW * restrict_chunks(g, nf) * ncol complex values in prec.
-int restrict_chunks(const Geom& g, int nf);
+// rows/nrows: the owned fine rows of each wirebasket in footprint order (owned_rows).
 void owned_rows(hipStream_t s, const Geom& g, const int* fpos, int nf, const int* owner, int* rows,
                 int* nrows);
+// y = P e   (add != 0: y += P e); e: coarse vectors in prec; y: fine vectors in prec
+void prolong(hipStream_t s, Real prec, const void* P, const int* rows, const int* nrows, int nf,
+             const void* e, void* y, const Geom& g, int add, int nrhs, int64_t stride_f,
+             int64_t stride_c, const RhsState* st);
+// rc = P^H r; r in `rin` precision (FP64 basis vector or prec), rc in prec; part: scratch of
+// nrhs * nW * restrict_chunks(g, nf, prec) * ncol complex values in prec.
+int restrict_chunks(const Geom& g, int nf, Real prec);
 void restrict_(hipStream_t s, Real prec, const void* P, const int* rows, const int* nrows, int nf,
                Real rin, const void* r, void* rc, void* part, const Geom& g, int nrhs,
                int64_t stride_f, int64_t stride_c, const RhsState* st);

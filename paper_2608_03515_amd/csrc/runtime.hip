@@ -417,11 +417,11 @@ void run_setup(amamg_hierarchy* h) {
     double2* py = h->mem.get<double2>("py", k, size_t(bc) * ndof);
     double2* pz = h->mem.get<double2>("pz", k, size_t(bc) * ndof);
     double2* pu = h->mem.get<double2>("pu", k, size_t(bc) * ndof_c);
-    double2* ppart = h->mem.get<double2>("ppart", k, size_t(bc) * g.nI * g.nJ * restrict_chunks(g, nf) * g.ncol());
+    double2* ppart = h->mem.get<double2>("ppart", k, size_t(bc) * g.nI * g.nJ * restrict_chunks(g, nf, F64) * g.ncol());
     for (int ct = 0; ct < pt; ++ct)
       for (int cx = 0; cx < px; ++cx) {
         probe_make(s, gc, pt, px, ct, cx, pe);
-        prolong(s, F64, L.P, L.owner, L.node, pe, py, g, 0, bc, ndof, ndof_c, nullptr);
+        prolong(s, F64, L.P, L.rows, L.nrows, L.nf, pe, py, g, 0, bc, ndof, ndof_c, nullptr);
         if (k == 0)
           wilson_apply(s, LINK_F64, U0, U1, F64, py, F64, pz, nullptr, g.Lt, g.Lx, h->m0, bc, ndof, nullptr);
         else
@@ -535,7 +535,7 @@ void ensure_workspace(amamg_hierarchy* h, int nrhs, int m, Real prec, int hist_c
   h->lv[0].tmp = h->ws.alloc<char>(size_t(nrhs) * n * rs);
   for (size_t k = 0; k + 1 < h->lv.size(); ++k) {
     LevelData& L = h->lv[k];
-    L.rpart = h->ws.alloc<char>(size_t(nrhs) * L.g.nI * L.g.nJ * restrict_chunks(L.g, L.nf) * L.g.ncol() * rs);
+    L.rpart = h->ws.alloc<char>(size_t(nrhs) * L.g.nI * L.g.nJ * restrict_chunks(L.g, L.nf, prec) * L.g.ncol() * rs);
   }
   h->ws_nrhs = nrhs;
   h->ws_m = m;
@@ -602,7 +602,7 @@ void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x) {
     const double fb = fprec == F64 ? 16 : 8;
     const double owned = double(nd) * (1.0 - double(g.o * g.o) / double(g.a * g.a));
     const int rec = k == 0 ? timer_start(gg->ctx, AMAMG_KT_RESTRICT0, c.step,
-                                         owned * (g.ncol() * cb + fb) + double(g.nI) * g.nJ * restrict_chunks(g, L.nf) * g.ncol() * cb)
+                                         owned * (g.ncol() * cb + fb) + double(g.nI) * g.nJ * restrict_chunks(g, L.nf, c.T) * g.ncol() * cb)
                            : -1;
     restrict_(c.s, c.T, P, L.rows, L.nrows, L.nf, fprec, f, C.f, L.rpart, g, c.nrhs, nd, ndc, st);
     timer_stop(gg->ctx, rec);
@@ -613,7 +613,7 @@ void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x) {
     const int rec = k == 0 ? timer_start(gg->ctx, AMAMG_KT_PROLONG0, c.step,
                                          owned * g.ncol() * cb + double(nd) * cb + double(ndc) * cb)
                            : -1;
-    prolong(c.s, c.T, P, L.owner, L.node, C.x, x, g, pre > 0 ? 1 : 0, c.nrhs, nd, ndc, st);
+    prolong(c.s, c.T, P, L.rows, L.nrows, L.nf, C.x, x, g, pre > 0 ? 1 : 0, c.nrhs, nd, ndc, st);
     timer_stop(gg->ctx, rec);
   }
   for (int sw = 0; sw < post; ++sw) {

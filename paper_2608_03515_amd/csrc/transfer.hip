@@ -23,63 +23,6 @@ __device__ inline int corner_node(int w, int c, int nI, int nJ) {
   return ((I + ct) % nI) * nJ + (J + cx) % nJ;
 }
 
-__device__ inline int lanes_per_row(int ncol) {
-  int g = 1;
-  while (g < 32 && g < ncol) g <<= 1;
-  return g;
-}
-
-// y[p][i] = sum_col P[p][i][col] e[corner(col)][col mod bc]  (F rows)
-// y[p][i] = e[node(p)][(pt*o + px)*b + i]                  (vertex rows)
-// G lanes share a row (strided columns, then a shuffle reduction); 64/G rows per wave.
-template <typename R, typename M, typename Vin, typename Vout>
-__global__ __launch_bounds__(256) void k_prolong(const M* __restrict__ P,
-                                                 const int* __restrict__ owner,
-                                                 const int* __restrict__ node,
-                                                 const Vin* __restrict__ e,
-                                                 Vout* __restrict__ y, Geom g, int add,
-                                                 int64_t stride_f, int64_t stride_c,
-                                                 const RhsState* __restrict__ st) {
-  const int r = blockIdx.y;
-  if (st && !st[r].active) return;
-  using C = cplx<R>;
-  const int ncol = g.ncol();
-  const int G = lanes_per_row(ncol);
-  const int rows_per_block = 256 / G;
-  const int lane_g = threadIdx.x % G;
-  const int64_t row = int64_t(xcd_block(blockIdx.x, gridDim.x)) * rows_per_block + threadIdx.x / G;
-  const int64_t nrow = g.ndof();
-  const bool live = row < nrow;
-  const int p = live ? int(row / g.b) : 0;
-  const int i = live ? int(row - int64_t(p) * g.b) : 0;
-  const Vin* er = e + r * stride_c;
-  C acc = czero<R>();
-  const int w = live ? owner[p] : -1;
-  if (w >= 0) {
-    const M* Pr = P + row * ncol;
-    for (int col = lane_g; col < ncol; col += G) {
-      const int c = col / g.bc, j = col - c * g.bc;
-      const int cn = corner_node(w, c, g.nI, g.nJ);
-      acc = cfma(cconv<C>(Pr[col]), cconv<C>(er[int64_t(cn) * g.bc + j]), acc);
-    }
-  }
-  // reduce over the G lanes of this row (aligned groups, so xor stays inside the group)
-  for (int off = G >> 1; off > 0; off >>= 1) {
-    acc.x += __shfl_xor(acc.x, off);
-    acc.y += __shfl_xor(acc.y, off);
-  }
-  if (live && lane_g == 0) {
-    if (w < 0) {
-      const int t = p / g.Lx, xc = p - (p / g.Lx) * g.Lx;
-      const int pt = t % g.a, px = xc % g.a;
-      acc = cconv<C>(er[int64_t(node[p]) * g.bc + (pt * g.o + px) * g.b + i]);
-    }
-    Vout* yr = y + r * stride_f;
-    if (add) acc = cadd(acc, cconv<C>(yr[row]));
-    yr[row] = cconv<Vout>(acc);
-  }
-}
-
 // Restriction rc = P^H r in two passes, both fixed-order (deterministic, no atomics).
 // Pass 1, one workgroup per (wirebasket W, chunk of W's owned rows): for every interpolation
 // column col of W, part[W][chunk][col] = sum over the chunk's rows of conj(P[row][col]) r[row].
@@ -88,7 +31,26 @@ __global__ __launch_bounds__(256) void k_prolong(const M* __restrict__ P,
 // contiguous segment.
 // Pass 2: rc[N][j] = sum over the 4 wirebaskets W having N as corner c and over their chunks
 // of part[W][chunk][c*bc + j], plus r at N's vertices; L lanes per output, xor-reduced.
-#define RCHUNK_MAX 256
+// Multi-rhs transfer tiles.  A workgroup owns one wirebasket W and a chunk of at most
+// `rch` of its owned rows: the interpolation rows of the chunk are staged once in LDS (row
+// stride ncol + 1 against bank conflicts) and reused for every right-hand side, which are
+// taken `rg` at a time.
+struct TileShape { int rch, rg, nchunk; };
+
+__host__ __device__ inline TileShape tile_shape(int ncol, int cs, int maxrows) {
+  int rch = 128;
+  while (rch > 8 && rch * (ncol + 1) * cs > 32768) rch >>= 1;
+  int rg = 16;
+  while (rg > 1 && rg * ncol * cs > 16384) rg >>= 1;
+  TileShape t;
+  t.rch = rch;
+  t.rg = rg;
+  t.nchunk = (maxrows + rch - 1) / rch;
+  return t;
+}
+
+// Pass 1 of the restriction: part[r][W][chunk][col] = sum over the chunk's rows of
+// conj(P[row][col]) rin_r[row]
 template <typename R, typename M, typename Vin>
 __global__ __launch_bounds__(256) void k_restrict_partial(const M* __restrict__ P,
                                                           const int* __restrict__ rows,
@@ -96,58 +58,107 @@ __global__ __launch_bounds__(256) void k_restrict_partial(const M* __restrict__ 
                                                           int maxrows,
                                                           const Vin* __restrict__ rin,
                                                           cplx<R>* __restrict__ part, Geom g,
-                                                          int nchunk, int64_t stride_f,
+                                                          TileShape ts, int nrhs, int64_t stride_f,
                                                           const RhsState* __restrict__ st) {
-  const int r = blockIdx.y;
-  if (st && !st[r].active) return;
   using C = cplx<R>;
-  __shared__ R red[2][256];
-  __shared__ C rs[RCHUNK_MAX];
-  __shared__ int ri[RCHUNK_MAX];
+  extern __shared__ __align__(16) char smem[];
+  const int ncol = g.ncol(), pld = ncol + 1;
+  C* Pl = reinterpret_cast<C*>(smem);                 // [rch][ncol + 1]
+  C* Rl = Pl + ts.rch * pld;                           // [rg][rch]
+  int* ri = reinterpret_cast<int*>(Rl + ts.rg * ts.rch);
   const int bid = xcd_block(blockIdx.x, gridDim.x);
-  const int w = bid / nchunk, chunk = bid - (bid / nchunk) * nchunk;
-  const int ncol = g.ncol();
+  const int w = bid / ts.nchunk, chunk = bid - (bid / ts.nchunk) * ts.nchunk;
   const int nr = nrows[w];
-  const int rpc = (maxrows + nchunk - 1) / nchunk;
-  const int r0 = chunk * rpc, r1 = min(nr, r0 + rpc);
-  const int cnt = r1 > r0 ? r1 - r0 : 0;
-  const Vin* rr = rin + r * stride_f;
-  for (int k = threadIdx.x; k < cnt; k += 256) {
-    const int row = rows[int64_t(w) * maxrows + r0 + k];
-    ri[k] = row;
-    rs[k] = cconv<C>(rr[row]);
-  }
+  const int r0 = chunk * ts.rch, cnt = max(0, min(nr - r0, ts.rch));
+  for (int k = threadIdx.x; k < cnt; k += 256) ri[k] = rows[int64_t(w) * maxrows + r0 + k];
   __syncthreads();
-  const int CW = ncol < 256 ? ncol : 256;
-  const int nslot = 256 / CW;
-  const int cl = threadIdx.x % CW, slot = threadIdx.x / CW;
-  C* out = part + ((int64_t(r) * g.nI * g.nJ + w) * nchunk + chunk) * ncol;
-  for (int c0 = 0; c0 < ncol; c0 += CW) {
-    const int col = c0 + cl;
-    C acc = czero<R>();
-    if (slot < nslot && col < ncol) {
-      int k = slot;
-      for (; k + 3 * nslot < cnt; k += 4 * nslot) {
-        const M p0 = P[int64_t(ri[k]) * ncol + col];
-        const M p1 = P[int64_t(ri[k + nslot]) * ncol + col];
-        const M p2 = P[int64_t(ri[k + 2 * nslot]) * ncol + col];
-        const M p3 = P[int64_t(ri[k + 3 * nslot]) * ncol + col];
-        acc = cfmac(cconv<C>(p0), rs[k], acc);
-        acc = cfmac(cconv<C>(p1), rs[k + nslot], acc);
-        acc = cfmac(cconv<C>(p2), rs[k + 2 * nslot], acc);
-        acc = cfmac(cconv<C>(p3), rs[k + 3 * nslot], acc);
+  for (int e = threadIdx.x; e < cnt * ncol; e += 256) {
+    const int k = e / ncol, col = e - (e / ncol) * ncol;
+    Pl[k * pld + col] = cconv<C>(P[int64_t(ri[k]) * ncol + col]);
+  }
+  const int nW = g.nI * g.nJ;
+  for (int g0 = 0; g0 < nrhs; g0 += ts.rg) {
+    const int ng = min(ts.rg, nrhs - g0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < ng * cnt; e += 256) {
+      const int rr = e / cnt, k = e - (e / cnt) * cnt;
+      const bool live = !st || st[g0 + rr].active;
+      Rl[rr * ts.rch + k] = live ? cconv<C>(rin[(g0 + rr) * stride_f + ri[k]]) : czero<R>();
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < ng * ncol; q += 256) {
+      const int rr = q / ncol, col = q - (q / ncol) * ncol;
+      if (st && !st[g0 + rr].active) continue;
+      C acc = czero<R>();
+      for (int k = 0; k < cnt; ++k) acc = cfmac(Pl[k * pld + col], Rl[rr * ts.rch + k], acc);
+      part[((int64_t(g0 + rr) * nW + w) * ts.nchunk + chunk) * ncol + col] = acc;
+    }
+  }
+}
+
+// Prolongation y = P e (add: y += P e) for every right-hand side.  Workgroup (W, chunk) writes
+// the chunk's owned rows of W; chunk 0 also writes the vertex rows of node (I, J) of W, which
+// are the identity on corner 0 of W.
+template <typename R, typename M, typename Vin, typename Vout>
+__global__ __launch_bounds__(256) void k_prolong(const M* __restrict__ P,
+                                                 const int* __restrict__ rows,
+                                                 const int* __restrict__ nrows, int maxrows,
+                                                 const Vin* __restrict__ e, Vout* __restrict__ y,
+                                                 Geom g, TileShape ts, int add, int nrhs,
+                                                 int64_t stride_f, int64_t stride_c,
+                                                 const RhsState* __restrict__ st) {
+  using C = cplx<R>;
+  extern __shared__ __align__(16) char smem[];
+  const int ncol = g.ncol(), pld = ncol + 1;
+  C* Pl = reinterpret_cast<C*>(smem);                 // [rch][ncol + 1]
+  C* El = Pl + ts.rch * pld;                           // [rg][ncol]
+  int* ri = reinterpret_cast<int*>(El + ts.rg * ncol);
+  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  const int w = bid / ts.nchunk, chunk = bid - (bid / ts.nchunk) * ts.nchunk;
+  const int I = w / g.nJ, J = w - (w / g.nJ) * g.nJ;
+  const int nr = nrows[w];
+  const int r0 = chunk * ts.rch, cnt = max(0, min(nr - r0, ts.rch));
+  const int nv_rows = chunk == 0 ? g.o * g.o * g.b : 0;     // vertex rows of node (I, J)
+  for (int k = threadIdx.x; k < cnt; k += 256) ri[k] = rows[int64_t(w) * maxrows + r0 + k];
+  __syncthreads();
+  for (int q = threadIdx.x; q < cnt * ncol; q += 256) {
+    const int k = q / ncol, col = q - (q / ncol) * ncol;
+    Pl[k * pld + col] = cconv<C>(P[int64_t(ri[k]) * ncol + col]);
+  }
+  int cn[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) cn[c] = ((I + (c >> 1)) % g.nI) * g.nJ + (J + (c & 1)) % g.nJ;
+  const int nout = cnt + nv_rows;
+  for (int g0 = 0; g0 < nrhs; g0 += ts.rg) {
+    const int ng = min(ts.rg, nrhs - g0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < ng * ncol; q += 256) {
+      const int rr = q / ncol, col = q - (q / ncol) * ncol;
+      const int c = col / g.bc, j = col - (col / g.bc) * g.bc;
+      El[rr * ncol + col] = cconv<C>(e[(g0 + rr) * stride_c + int64_t(cn[c]) * g.bc + j]);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < ng * nout; q += 256) {
+      const int rr = q / nout, k = q - (q / nout) * nout;
+      if (st && !st[g0 + rr].active) continue;
+      C acc;
+      int64_t row;
+      if (k < cnt) {
+        acc = czero<R>();
+        const C* El_r = El + rr * ncol;
+        for (int col = 0; col < ncol; ++col) acc = cfma(Pl[k * pld + col], El_r[col], acc);
+        row = ri[k];
+      } else {
+        const int v = k - cnt;                       // (pt*o + px)*b + q of node (I, J)
+        const int qq = v % g.b, pp = v / g.b;
+        const int pt = pp / g.o, px = pp - (pp / g.o) * g.o;
+        row = int64_t((g.a * I + pt) * g.Lx + (g.a * J + px)) * g.b + qq;
+        acc = El[rr * ncol + v];                     // corner 0 is node (I, J)
       }
-      for (; k < cnt; k += nslot) acc = cfmac(cconv<C>(P[int64_t(ri[k]) * ncol + col]), rs[k], acc);
+      Vout* yr = y + (g0 + rr) * stride_f;
+      if (add) acc = cadd(acc, cconv<C>(yr[row]));
+      yr[row] = cconv<Vout>(acc);
     }
-    red[0][threadIdx.x] = acc.x;
-    red[1][threadIdx.x] = acc.y;
-    __syncthreads();
-    if (slot == 0 && col < ncol) {
-      C sum = czero<R>();
-      for (int q = 0; q < nslot; ++q) sum = cadd(sum, mk<R>(red[0][q * CW + cl], red[1][q * CW + cl]));
-      out[col] = sum;
-    }
-    __syncthreads();
   }
 }
 
@@ -274,30 +285,13 @@ __global__ void k_inject(Geom g, const int* __restrict__ node, const int8_t* __r
 
 // ------------------------------------------------------------------------------ launchers
 
-void prolong(hipStream_t s, Real prec, const void* P, const int* owner, const int* node,
-             const void* e, void* y, const Geom& g, int add, int nrhs, int64_t stride_f,
-             int64_t stride_c, const RhsState* st) {
-  int G = 1;
-  while (G < 32 && G < g.ncol()) G <<= 1;
-  const int rows_per_block = 256 / G;
-  dim3 grid(unsigned((g.ndof() + rows_per_block - 1) / rows_per_block), unsigned(nrhs));
-  if (prec == F64)
-    hipLaunchKernelGGL((k_prolong<double, double2, double2, double2>), grid, dim3(256), 0, s,
-                       (const double2*)P, owner, node, (const double2*)e, (double2*)y, g, add,
-                       stride_f, stride_c, st);
-  else
-    hipLaunchKernelGGL((k_prolong<float, float2, float2, float2>), grid, dim3(256), 0, s,
-                       (const float2*)P, owner, node, (const float2*)e, (float2*)y, g, add,
-                       stride_f, stride_c, st);
+static size_t tile_smem(const TileShape& t, int ncol, int cs) {
+  return size_t(t.rch) * (ncol + 1) * cs + size_t(t.rg) * (t.rch > ncol ? t.rch : ncol) * cs +
+         size_t(t.rch) * sizeof(int);
 }
 
-int restrict_chunks(const Geom& g, int nf) {
-  const int nW = g.nI * g.nJ, nfd = nf * g.b;
-  int nchunk = (1024 + nW - 1) / nW;
-  const int maxc = (nfd + 7) / 8;
-  if (nchunk > maxc) nchunk = maxc;
-  while ((nfd + nchunk - 1) / nchunk > RCHUNK_MAX) ++nchunk;
-  return nchunk < 1 ? 1 : nchunk;
+int restrict_chunks(const Geom& g, int nf, Real prec) {
+  return tile_shape(g.ncol(), prec == F64 ? 16 : 8, nf * g.b).nchunk;
 }
 
 void owned_rows(hipStream_t s, const Geom& g, const int* fpos, int nf, const int* owner, int* rows,
@@ -306,35 +300,54 @@ void owned_rows(hipStream_t s, const Geom& g, const int* fpos, int nf, const int
                      rows, nrows, nf * g.b);
 }
 
+void prolong(hipStream_t s, Real prec, const void* P, const int* rows, const int* nrows, int nf,
+             const void* e, void* y, const Geom& g, int add, int nrhs, int64_t stride_f,
+             int64_t stride_c, const RhsState* st) {
+  const int cs = prec == F64 ? 16 : 8;
+  const TileShape ts = tile_shape(g.ncol(), cs, nf * g.b);
+  dim3 grid(unsigned(g.nI * g.nJ * ts.nchunk));
+  const size_t sm = tile_smem(ts, g.ncol(), cs);
+  if (prec == F64)
+    hipLaunchKernelGGL((k_prolong<double, double2, double2, double2>), grid, dim3(256), sm, s,
+                       (const double2*)P, rows, nrows, nf * g.b, (const double2*)e, (double2*)y, g,
+                       ts, add, nrhs, stride_f, stride_c, st);
+  else
+    hipLaunchKernelGGL((k_prolong<float, float2, float2, float2>), grid, dim3(256), sm, s,
+                       (const float2*)P, rows, nrows, nf * g.b, (const float2*)e, (float2*)y, g,
+                       ts, add, nrhs, stride_f, stride_c, st);
+}
+
 void restrict_(hipStream_t s, Real prec, const void* P, const int* rows, const int* nrows, int nf,
                Real rin, const void* r, void* rc, void* part, const Geom& g, int nrhs,
                int64_t stride_f, int64_t stride_c, const RhsState* st) {
-  const int nchunk = restrict_chunks(g, nf);
+  const int cs = prec == F64 ? 16 : 8;
+  const TileShape ts = tile_shape(g.ncol(), cs, nf * g.b);
   const int maxrows = nf * g.b;
   int lanes = 1;
-  while (lanes < 16 && lanes < nchunk) lanes <<= 1;
-  dim3 g1(unsigned(g.nI * g.nJ * nchunk), unsigned(nrhs));
+  while (lanes < 16 && lanes < ts.nchunk) lanes <<= 1;
+  dim3 g1(unsigned(g.nI * g.nJ * ts.nchunk));
   dim3 g2(unsigned((int64_t(g.nI) * g.nJ * g.bc * lanes + 255) / 256), unsigned(nrhs));
+  const size_t sm = tile_smem(ts, g.ncol(), cs);
   if (prec == F64) {
-    hipLaunchKernelGGL((k_restrict_partial<double, double2, double2>), g1, dim3(256), 0, s,
+    hipLaunchKernelGGL((k_restrict_partial<double, double2, double2>), g1, dim3(256), sm, s,
                        (const double2*)P, rows, nrows, maxrows, (const double2*)r, (double2*)part, g,
-                       nchunk, stride_f, st);
+                       ts, nrhs, stride_f, st);
     hipLaunchKernelGGL((k_restrict_gather<double, double2, double2>), g2, dim3(256), 0, s,
-                       (const double2*)part, (const double2*)r, (double2*)rc, g, nchunk, lanes,
+                       (const double2*)part, (const double2*)r, (double2*)rc, g, ts.nchunk, lanes,
                        stride_f, stride_c, st);
   } else if (rin == F64) {
-    hipLaunchKernelGGL((k_restrict_partial<float, float2, double2>), g1, dim3(256), 0, s,
+    hipLaunchKernelGGL((k_restrict_partial<float, float2, double2>), g1, dim3(256), sm, s,
                        (const float2*)P, rows, nrows, maxrows, (const double2*)r, (float2*)part, g,
-                       nchunk, stride_f, st);
+                       ts, nrhs, stride_f, st);
     hipLaunchKernelGGL((k_restrict_gather<float, double2, float2>), g2, dim3(256), 0, s,
-                       (const float2*)part, (const double2*)r, (float2*)rc, g, nchunk, lanes,
+                       (const float2*)part, (const double2*)r, (float2*)rc, g, ts.nchunk, lanes,
                        stride_f, stride_c, st);
   } else {
-    hipLaunchKernelGGL((k_restrict_partial<float, float2, float2>), g1, dim3(256), 0, s,
+    hipLaunchKernelGGL((k_restrict_partial<float, float2, float2>), g1, dim3(256), sm, s,
                        (const float2*)P, rows, nrows, maxrows, (const float2*)r, (float2*)part, g,
-                       nchunk, stride_f, st);
+                       ts, nrhs, stride_f, st);
     hipLaunchKernelGGL((k_restrict_gather<float, float2, float2>), g2, dim3(256), 0, s,
-                       (const float2*)part, (const float2*)r, (float2*)rc, g, nchunk, lanes,
+                       (const float2*)part, (const float2*)r, (float2*)rc, g, ts.nchunk, lanes,
                        stride_f, stride_c, st);
   }
 }
