@@ -39,7 +39,8 @@ def log(*a):
 FAMILIES = ["fine_matvec", "fine_gs", "restrict0", "prolong0", "coarse_gs", "dots", "update"]
 KERNEL_NAMES = {"fine_matvec": "k_wilson_apply", "fine_gs": "k_wilson_gs",
                 "restrict0": "k_restrict_partial (fine level)", "prolong0": "k_prolong (fine level)",
-                "coarse_gs": "k_stencil_gs (level 1)", "dots": "k_dots", "update": "k_update<32>"}
+                "coarse_gs": "k_stencil_gs (level 1)", "dots": "k_dots<nv> (all basis sizes)",
+                "update": "k_update<nv, *> (all basis sizes)"}
 
 
 def run_steps(lib, torch, ctx, h, b, x, nrhs, precision, steps, warmup, timer=None):
@@ -145,6 +146,98 @@ def cpu_baseline(w, m0, gpu_iterations, budget_s=25.0):
                       "NumPy/SciPy FP64, sparse matvecs single-threaded"}
 
 
+# ------------------------------------------------------------------ profile summaries
+FAMILY_PATTERNS = {"update": "k_update<", "dots": "k_dots<"}
+TRAFFIC_MD = os.path.join(ROOT, "profiles", "gram_schmidt_256x256_64rhs_mixed_traffic.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2608_03515_amd", "csrc", "krylov.hip")
+
+
+def _sha(path):
+    import hashlib
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def trace_summary(stats_csv, out_md, command, top=25):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats kernel_stats.csv."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# Kernel time, {os.path.basename(out_md)[:-3]}", "", "Command (from the repository root):", "",
+             f"    {command}", "", f"Total kernel time {total / 1e6:.1f} ms over "
+             f"{sum(int(r['Calls']) for r in rows)} dispatches.", "",
+             "| total ms | calls | avg us | % | kernel |", "|---:|---:|---:|---:|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:top]:
+        name = r["Name"].split("(")[0].replace("|", "/")[:90]
+        lines.append(f"| {float(r['TotalDurationNs']) / 1e6:.2f} | {r['Calls']} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} | `{name}` |")
+    lines += ["", "Families (all instantiations):", "", "| family | calls | avg us | total ms |", "|---|---:|---:|---:|"]
+    for fam, pat in FAMILY_PATTERNS.items():
+        sel = [r for r in rows if pat in r["Name"]]
+        n = sum(int(r["Calls"]) for r in sel)
+        t = sum(float(r["TotalDurationNs"]) for r in sel)
+        if n:
+            lines.append(f"| {fam} (`{pat}*`) | {n} | {t / n / 1e3:.2f} | {t / 1e6:.2f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
+def pmc_summary(fetch_csv, write_csv, out_md, command, timer_json):
+    """Traffic per launch of the Gram-Schmidt families from two rocprofv3 --pmc runs, scaled by
+    the same counters on a plain 1 GiB elementwise copy in the same run."""
+    import csv
+    from collections import defaultdict
+
+    def load(path):
+        per = defaultdict(list)
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                per[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+        return per
+    fe, wr = load(fetch_csv), load(write_csv)
+    cal = [k for k in fe if "neg_kernel" in k]
+    f_fac = fe[cal[0]][0] * 1024 / 2 ** 30          # counter bytes per byte read
+    w_fac = wr[cal[0]][0] * 1024 / 2 ** 30          # counter bytes per byte written
+    t = json.loads(timer_json)
+    lines = [f"# HBM traffic, {os.path.basename(out_md)[:-3]}", "",
+             "Two counter passes (one counter each), from the repository root:", ""]
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        lines.append(f"    {command.replace('COUNTER', c)}")
+    lines += ["", f"Calibration: a 1 GiB elementwise copy (`neg`) reads as {fe[cal[0]][0]:.0f} KiB of "
+              f"FETCH_SIZE and writes as {wr[cal[0]][0]:.0f} KiB of WRITE_SIZE: scale factors "
+              f"{f_fac:.4f} (fetch) and {w_fac:.4f} (write) counter bytes per byte.", "",
+              "| family | dispatches with traffic | read MB / launch | written MB / launch | "
+              "algorithmic MB / launch (timer) | traffic / algorithmic |", "|---|---:|---:|---:|---:|---:|"]
+    rec = {}
+    for fam, pat in FAMILY_PATTERNS.items():
+        fv = [v for k, vs in fe.items() if pat in k for v in vs]
+        wv = [v for k, vs in wr.items() if pat in k for v in vs]
+        nwork = sum(1 for v in fv if v * 1024 / f_fac > 1e6)
+        rd = sum(fv) * 1024 / f_fac / max(1, nwork)
+        wt = sum(wv) * 1024 / w_fac / max(1, nwork)
+        alg = t.get("algorithmic_bytes_per_launch") if t.get("family") == fam else None
+        rec[fam] = (rd, wt, nwork)
+        lines.append(f"| {fam} | {nwork} | {rd / 1e6:.1f} | {wt / 1e6:.1f} | "
+                     f"{alg / 1e6 if alg else float('nan'):.1f} | "
+                     f"{(rd + wt) / alg if alg else float('nan'):.3f} |")
+    fam = t["family"]
+    lines += ["", f"<!-- traffic family={fam} source_sha={_sha(KERNEL_SRC)} "
+                  f"bytes_per_launch={rec[fam][0] + rec[fam][1]:.0f} -->"]
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
+def committed_traffic(family):
+    """Per-launch HBM bytes of `family` from the committed counter summary, or None when the
+    summary is missing, covers another family, or the kernel source changed since."""
+    import re
+    try:
+        text = open(TRAFFIC_MD).read()
+    except OSError:
+        return None
+    m = re.search(r"<!-- traffic family=(\w+) source_sha=(\w+) bytes_per_launch=([0-9.]+) -->", text)
+    if not m or m.group(1) != family or m.group(2) != _sha(KERNEL_SRC):
+        return None
+    return float(m.group(3))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,7 +248,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stencil", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="skip the single-rhs FP64 path")
+    ap.add_argument("--trace-summary", nargs=3, metavar=("STATS_CSV", "OUT_MD", "COMMAND"))
+    ap.add_argument("--pmc-summary", nargs=5,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD", "COMMAND", "TIMER_JSON"))
+    ap.add_argument("--profile-mixed", action="store_true",
+                    help="profiling run: only the timed mixed-precision steps (no FP64, single-rhs, "
+                         "stencil or CPU legs) followed by a device copy of known size")
     args = ap.parse_args()
+    if args.trace_summary:
+        trace_summary(*args.trace_summary)
+        return
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(independent lattices and requests would run one per GPU).", file=sys.stderr)
@@ -189,8 +294,25 @@ def main():
                 "converged": all(i.converged for i in infos)}
 
     res = {}
+    if args.profile_mixed:
+        fam = "update"
+        dt, ts, infos, timed = run_steps(lib, torch, ctx, h, b, x, args.nrhs, lib.MIXED_FP32, args.steps,
+                                         args.warmup, timer=fam)
+        launches, ms, nbytes = timed
+        # traffic-counter calibration: a plain elementwise copy of known size
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").normal_()
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)          # one elementwise kernel: 1 GiB read, 1 GiB written
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_mixed": summarize(dt, ts, infos, args.nrhs, args.steps),
+                          "family": fam, "launches": launches, "avg_launch_us": ms * 1e3 / max(1, launches),
+                          "algorithmic_bytes_per_launch": nbytes / max(1, launches),
+                          "copy_bytes_each_way": src.numel() * 8}), flush=True)
+        return
     dt, ts, infos, _ = run_steps(lib, torch, ctx, h, b, x, args.nrhs, lib.FP64, args.steps, args.warmup)
     res["fp64"] = summarize(dt, ts, infos, args.nrhs, args.steps)
+    rhs0_iterations = infos[0].iterations          # the right-hand side the CPU oracle samples
     x64 = x.clone()
     log("fp64", json.dumps(res["fp64"]))
     fam, fam_ms = dominant_family(lib, torch, ctx, h, b, x, args.nrhs, lib.MIXED_FP32)
@@ -201,8 +323,10 @@ def main():
     res["mixed"]["rel_diff_vs_fp64"] = float((x - x64).norm() / x64.norm())
     log("mixed", json.dumps(res["mixed"]))
     launches, ms, nbytes = timed
+    traffic = committed_traffic(fam)
     roofline = {"bound": "hbm", "achieved": nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic,
+                "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
                 "kernel": KERNEL_NAMES[fam], "family": fam, "launches": launches,
                 "avg_launch_us": ms * 1e3 / max(launches, 1),
                 "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
@@ -245,7 +369,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        line["cpu_baseline"] = cpu_baseline(w, m0, res["fp64"]["iterations_min_max"][0])
+        line["cpu_baseline"] = cpu_baseline(w, m0, rhs0_iterations)
     h.close()
     g.close()
     print(json.dumps(line), flush=True)

@@ -152,8 +152,9 @@ typedef enum {
   AMAMG_KT_RESTRICT0 = 3,     /* fine-level restriction, per-wirebasket pass                 */
   AMAMG_KT_PROLONG0 = 4,      /* fine-level prolongation                                     */
   AMAMG_KT_COARSE_GS = 5,     /* one colour of the level-1 block Gauss-Seidel sweep          */
-  AMAMG_KT_DOTS = 6,          /* first Gram-Schmidt projection V^H w                          */
-  AMAMG_KT_UPDATE = 7         /* w -= V h fused with the second projection                    */
+  AMAMG_KT_DOTS = 6,          /* every Gram-Schmidt projection pass V^H w (k_dots)            */
+  AMAMG_KT_UPDATE = 7         /* every w -= V h pass (k_update, with its fused projection or  */
+                              /* norm)                                                         */
 } amamg_kernel_family;
 /* Benchmark hook: from now on, bracket every solve-phase launch of the families whose bits
  * (1 << family) are set in family_mask (0 stops) with HIP events on the context stream, and

@@ -158,8 +158,8 @@ __global__ __launch_bounds__(256) void k_dots(KrylovDims dm, const double2* __re
 // w -= sum_i V_i h_i with h the total of the previous kernel's partials hpart; then partials
 // of V^H w_new (DOTS) or of ||w_new||^2 into part.
 template <int NV, bool DOTS>
-__global__ __launch_bounds__(256) void k_update(KrylovDims dm, const double2* V,
-                                                int64_t vsj, double2* w,
+__global__ __launch_bounds__(256) void k_update(KrylovDims dm, const double2* __restrict__ V,
+                                                int64_t vsj, double2* __restrict__ w,
                                                 const double2* __restrict__ hpart,
                                                 double2* __restrict__ part,
                                                 const RhsState* __restrict__ st) {
@@ -174,17 +174,24 @@ __global__ __launch_bounds__(256) void k_update(KrylovDims dm, const double2* V,
   for (int i = 0; i < NA; ++i) acc[i] = make_double2(0, 0);
   double2* wr = w + r * dm.n;
   const double2* Vr = V + r * dm.n;
+#pragma unroll 1
   for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < dm.n; d += int64_t(gridDim.x) * 256) {
     double2 wd = wr[d];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) wd = csub(wd, cmul(Vr[i * vsj + d], hs[i]));
-    wr[d] = wd;
     if (DOTS) {
-      // second read of the basis elements (cache hits; V and w are not declared restrict, so
-      // the store above keeps the compiler from holding all NV values in registers)
+      // the basis values stay in registers for the second projection: reading them twice
+      // would exceed the per-XCD L2 with 64 right-hand sides and go back to HBM
+      double2 v[NV];
 #pragma unroll
-      for (int i = 0; i < NA; ++i) acc[i] = cfmac(Vr[i * vsj + d], wd, acc[i]);
+      for (int i = 0; i < NV; ++i) v[i] = Vr[i * vsj + d];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) wd = csub(wd, cmul(v[i], hs[i]));
+      wr[d] = wd;
+#pragma unroll
+      for (int i = 0; i < NA; ++i) acc[i] = cfmac(v[i], wd, acc[i]);
     } else {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) wd = csub(wd, cmul(Vr[i * vsj + d], hs[i]));
+      wr[d] = wd;
       acc[0].x += cabs2(wd);
     }
   }

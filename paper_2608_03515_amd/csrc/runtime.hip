@@ -543,6 +543,10 @@ void ensure_workspace(amamg_hierarchy* h, int nrhs, int m, Real prec, int hist_c
   h->ws_hist = hist_cap;
 }
 
+// Largest basis for which w -= V h and the second projection run as one fused pass (the
+// fused kernel holds the basis values in registers: about 12 VGPRs per vector).
+constexpr int kFusedUpdateMax = 14;
+
 struct SolveCtx {
   amamg_hierarchy* h;
   hipStream_t s;
@@ -712,13 +716,27 @@ amamg_status run_solve(amamg_hierarchy* h, int nrhs, const double2* b, double2* 
       int rec = timer_start(gg->ctx, AMAMG_KT_FINE_MATVEC, j, double(nt) * nx * (2 * zs + 2 * cl + 32));
       wilson_apply(s, c.mat_links, Um0, Um1, T, zj, F64, h->w, nullptr, nt, nx, h->m0, nrhs, n, st);
       timer_stop(gg->ctx, rec);
-      rec = timer_start(gg->ctx, AMAMG_KT_DOTS, j, double(j + 2) * n * 16);
+      // Gram-Schmidt: family DOTS = every V^H w pass, family UPDATE = every w -= V h pass
+      const double dot_bytes = double(j + 2) * n * 16, upd_bytes = double(j + 3) * n * 16;
+      rec = timer_start(gg->ctx, AMAMG_KT_DOTS, j, dot_bytes);
       dots(s, kd, h->V, vsj, j + 1, h->w, p1, st);
       timer_stop(gg->ctx, rec);
-      rec = timer_start(gg->ctx, AMAMG_KT_UPDATE, j, double(j + 3) * n * 16);
-      update_dots(s, kd, h->V, vsj, j + 1, h->w, p1, p2, st);
-      timer_stop(gg->ctx, rec);
+      if (j + 1 <= kFusedUpdateMax) {
+        rec = timer_start(gg->ctx, AMAMG_KT_UPDATE, j, upd_bytes);
+        update_dots(s, kd, h->V, vsj, j + 1, h->w, p1, p2, st);
+        timer_stop(gg->ctx, rec);
+      } else {
+        // large bases: the fused kernel runs out of registers; two streaming passes are faster
+        rec = timer_start(gg->ctx, AMAMG_KT_UPDATE, j, upd_bytes);
+        update_norm(s, kd, h->V, vsj, j + 1, h->w, p1, p3, st);
+        timer_stop(gg->ctx, rec);
+        rec = timer_start(gg->ctx, AMAMG_KT_DOTS, j, dot_bytes);
+        dots(s, kd, h->V, vsj, j + 1, h->w, p2, st);
+        timer_stop(gg->ctx, rec);
+      }
+      rec = timer_start(gg->ctx, AMAMG_KT_UPDATE, j, upd_bytes);
       update_norm(s, kd, h->V, vsj, j + 1, h->w, p2, p3, st);
+      timer_stop(gg->ctx, rec);
       arnoldi(s, kd, p1, p2, p3, st, h->H, h->cs, h->sn, h->g, j, p.rel_tol, inner_tol, p.max_iters,
               h->hist, hist_cap);
       if (j + 1 < m) scale_next(s, kd, h->w, h->V + (j + 1) * vsj, st);
