@@ -40,7 +40,7 @@ FAMILIES = ["fine_matvec", "fine_gs", "restrict0", "prolong0", "coarse_gs", "dot
 KERNEL_NAMES = {"fine_matvec": "k_wilson_apply", "fine_gs": "k_wilson_gs",
                 "restrict0": "k_restrict_partial (fine level)", "prolong0": "k_prolong (fine level)",
                 "coarse_gs": "k_stencil_gs (level 1)", "dots": "k_dots<nv> (all basis sizes)",
-                "update": "k_update<nv, *> (all basis sizes)"}
+                "update": "k_update_dots<nv, s> + k_update_norm<nv> (all basis sizes)"}
 
 
 def run_steps(lib, torch, ctx, h, b, x, nrhs, precision, steps, warmup, timer=None):
@@ -147,7 +147,7 @@ def cpu_baseline(w, m0, gpu_iterations, budget_s=25.0):
 
 
 # ------------------------------------------------------------------ profile summaries
-FAMILY_PATTERNS = {"update": "k_update<", "dots": "k_dots<"}
+FAMILY_PATTERNS = {"update": "k_update_", "dots": "k_dots<"}
 TRAFFIC_MD = os.path.join(ROOT, "profiles", "gram_schmidt_256x256_64rhs_mixed_traffic.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2608_03515_amd", "csrc", "krylov.hip")
 

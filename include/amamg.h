@@ -130,8 +130,9 @@ amamg_status amamg_hierarchy_destroy(amamg_hierarchy *h);
  * iteration cap. */
 amamg_status amamg_solve(amamg_hierarchy *h, int32_t nrhs, const double *psi, double *x,
                          const amamg_solve_params *params, amamg_solve_info *info);
-/* Same with device pointers (resident in HBM, same layout); runs on the context stream and
- * returns after the solve has finished. */
+/* Same with device pointers (resident in HBM, same layout, 16-byte aligned, else
+ * AMAMG_ERR_INVALID_ARG); runs on the context stream and returns after the solve has
+ * finished. */
 amamg_status amamg_solve_device(amamg_hierarchy *h, int32_t nrhs, const void *psi_dev,
                                 void *x_dev, const amamg_solve_params *params,
                                 amamg_solve_info *info);
@@ -172,7 +173,8 @@ amamg_status amamg_apply_dirac(amamg_gauge *g, int32_t precision, int32_t nrhs,
                                const double *in, double *out);
 /* out = D in on device buffers (same layout) at the given precision: AMAMG_FP64 uses FP64
  * fields and links; the mixed modes use FP32 fields ([nrhs][nt][nx][2][2] float) with FP32
- * or BF16 links.  Asynchronous on the context stream. */
+ * or BF16 links.  Both pointers must be 16-byte aligned (else AMAMG_ERR_INVALID_ARG).
+ * Asynchronous on the context stream. */
 amamg_status amamg_apply_dirac_device(amamg_gauge *g, int32_t precision, int32_t nrhs,
                                       const void *in_dev, void *out_dev);
 /* Grid of level `level` (0 = fine lattice) and degrees of freedom per node. */

@@ -88,3 +88,28 @@ def field_to_vector(psi: np.ndarray) -> np.ndarray:
 
 def vector_to_field(v: np.ndarray, nt: int, nx: int) -> np.ndarray:
     return v.reshape(nt, nx, 2)
+
+
+def dirac_at_sites(U: np.ndarray, m0: float, psi: np.ndarray, ts: np.ndarray,
+                   xs: np.ndarray) -> np.ndarray:
+    """(D psi)(n) at the sites n = (ts[k], xs[k]) only, from the same definition as
+    dirac_matrix, for lattices too large to assemble D: returns [len(ts)][2] complex.
+
+    Each site takes its two forward and two backward neighbours with the spin projectors
+    (1 -/+ sigma_mu), the links U_mu(n) and U_mu(n - mu)^*, and the time-boundary sign."""
+    nt, nx = U.shape[1], U.shape[2]
+    ts = np.asarray(ts)
+    xs = np.asarray(xs)
+    out = (m0 + 2.0) * psi[ts, xs]
+    for mu in range(2):
+        if mu == 0:
+            tf, xf, tb, xb = (ts + 1) % nt, xs, (ts - 1) % nt, xs
+            sf = np.where(ts == nt - 1, -1.0, 1.0)
+            sb = np.where(ts == 0, -1.0, 1.0)
+        else:
+            tf, xf, tb, xb = ts, (xs + 1) % nx, ts, (xs - 1) % nx
+            sf = sb = np.ones(ts.shape)
+        fwd = (sf * U[mu][ts, xs])[:, None] * psi[tf, xf]
+        bwd = (sb * np.conj(U[mu][tb, xb]))[:, None] * psi[tb, xb]
+        out = out - 0.5 * (fwd @ (EYE2 - SIGMA[mu]).T + bwd @ (EYE2 + SIGMA[mu]).T)
+    return out

@@ -10,48 +10,55 @@
 //   (1 - sigma_1) psi = (psi0 + i psi1) (1, -i)   (1 + sigma_1) psi = (psi0 - i psi1) (1, i)
 // so each hop costs one complex projection, one link multiply and two accumulations.
 //
-// Layout: one thread per site, site = t * nx + x; a field is [rhs][site][2 spin] complex.
-// Bytes per site (FP64): 4 neighbour spinors + own (cache-reused: 32 B from HBM), 2 links
-// (32 B), result (32 B) = 96 B; about 60 flops.
+// Layout: a field is [rhs][site][2 spin] complex, site = t * nx + x.  Each workgroup stages a
+// tile of the field with its one-site halo in LDS (read from HBM once), then one thread per site
+// applies the stencil.  Bytes per site (FP64): spinor 32 B, 2 links 32 B, result 32 B = 96 B;
+// about 60 flops.
 #include "launch.hpp"
 
 namespace amamg {
 
-template <typename R, typename L, typename Vin>
-__device__ inline void wilson_hops(const L* __restrict__ U0, const L* __restrict__ U1,
-                                   const Vin* __restrict__ x, int t, int xc, int nt, int nx,
-                                   cplx<R>& o0, cplx<R>& o1) {
-  using C = cplx<R>;
-  const int n = t * nx + xc;
-  const int tf = (t + 1 == nt) ? 0 : t + 1, tb = (t == 0) ? nt - 1 : t - 1;
-  const int xf = (xc + 1 == nx) ? 0 : xc + 1, xb = (xc == 0) ? nx - 1 : xc - 1;
-  const int nf0 = tf * nx + xc, nb0 = tb * nx + xc, nf1 = t * nx + xf, nb1 = t * nx + xb;
-  const R sf = (t == nt - 1) ? R(-1) : R(1);
-  const R sb = (t == 0) ? R(-1) : R(1);
-  // forward time hop
-  C a0 = cconv<C>(x[2 * nf0]), a1 = cconv<C>(x[2 * nf0 + 1]);
-  C h = cscale(cmul(load_link<R>(U0, n), csub(a0, a1)), sf);
-  C s0 = h, s1 = mk<R>(-h.x, -h.y);
-  // backward time hop
-  C b0 = cconv<C>(x[2 * nb0]), b1 = cconv<C>(x[2 * nb0 + 1]);
-  h = cscale(cmulc(load_link<R>(U0, nb0), cadd(b0, b1)), sb);
-  s0 = cadd(s0, h);
-  s1 = cadd(s1, h);
-  // forward space hop: (1, -i) (psi0 + i psi1)
-  C c0 = cconv<C>(x[2 * nf1]), c1 = cconv<C>(x[2 * nf1 + 1]);
-  h = cmul(load_link<R>(U1, n), cadd(c0, ctimes_i(c1)));
-  s0 = cadd(s0, h);
-  s1 = csub(s1, ctimes_i(h));
-  // backward space hop: (1, i) (psi0 - i psi1)
-  C d0 = cconv<C>(x[2 * nb1]), d1 = cconv<C>(x[2 * nb1 + 1]);
-  h = cmulc(load_link<R>(U1, nb1), csub(d0, ctimes_i(d1)));
-  s0 = cadd(s0, h);
-  s1 = cadd(s1, ctimes_i(h));
-  o0 = cscale(s0, R(-0.5));
-  o1 = cscale(s1, R(-0.5));
+// One site's two spin components, moved as one 16-byte (FP32) or two 16-byte (FP64) accesses;
+// fields are 16-byte aligned.
+template <typename V> struct alignas(16) Spinor { V s0, s1; };
+
+template <typename To, typename From> __device__ inline Spinor<To> sconv(Spinor<From> a) {
+  return Spinor<To>{cconv<To>(a.s0), cconv<To>(a.s1)};
 }
 
-template <typename R, typename L, typename Vin, typename Vout>
+// Spin-projected hops of one site, -1/2 sum_mu [(1 - sigma_mu) U_mu(n) psi(n + mu) +
+// (1 + sigma_mu) U_mu(n - mu)^* psi(n - mu)], from its four neighbours; u0f = U0(n),
+// u0b = U0(n - t), u1f = U1(n), u1b = U1(n - x); sf, sb are the time-boundary signs.
+template <typename C, typename R>
+__device__ inline Spinor<C> hops(Spinor<C> tp, Spinor<C> tm, Spinor<C> xp, Spinor<C> xm, C u0f,
+                                 C u0b, C u1f, C u1b, R sf, R sb) {
+  C h = cscale(cmul(u0f, csub(tp.s0, tp.s1)), sf);
+  C s0 = h, s1 = mk<R>(-h.x, -h.y);
+  h = cscale(cmulc(u0b, cadd(tm.s0, tm.s1)), sb);
+  s0 = cadd(s0, h);
+  s1 = cadd(s1, h);
+  h = cmul(u1f, cadd(xp.s0, ctimes_i(xp.s1)));
+  s0 = cadd(s0, h);
+  s1 = csub(s1, ctimes_i(h));
+  h = cmulc(u1b, csub(xm.s0, ctimes_i(xm.s1)));
+  s0 = cadd(s0, h);
+  s1 = cadd(s1, ctimes_i(h));
+  return Spinor<C>{cscale(s0, R(-0.5)), cscale(s1, R(-0.5))};
+}
+
+// Periodic index for v in [-1, ...): the halo row/column -1 maps to n - 1 and n maps to 0.  Tile
+// positions past n (a tile wider than a small lattice) hold no site's neighbour; they are
+// clamped to 0 so that every load stays inside the field.
+__device__ inline int wrap_index(int v, int n) {
+  if (v < 0) return v + n;
+  if (v < n) return v;
+  return v - n < n ? v - n : 0;
+}
+
+// y = D x (or b - D x) on TR x TC tiles (TR * TC = 256, one thread per site): the tile and its
+// one-site halo, rows t0 - 1 .. t0 + TR and columns x0 - 1 .. x0 + TC (periodic wrap), are read
+// from HBM once into LDS; every site then takes its four neighbours from LDS.
+template <int TC, typename R, typename L, typename Vin, typename Vout>
 __global__ __launch_bounds__(256) void k_wilson_apply(const L* __restrict__ U0,
                                                       const L* __restrict__ U1,
                                                       const Vin* __restrict__ x,
@@ -59,58 +66,88 @@ __global__ __launch_bounds__(256) void k_wilson_apply(const L* __restrict__ U0,
                                                       const double2* __restrict__ b, int nt,
                                                       int nx, R mp2, int64_t stride,
                                                       const RhsState* __restrict__ st) {
+  constexpr int TR = 256 / TC, W = TC + 2;
+  using C = cplx<R>;
   const int r = blockIdx.y;
   if (st && !st[r].active) return;
-  const int n = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  if (n >= nt * nx) return;
-  using C = cplx<R>;
-  const Vin* xr = x + r * stride;
-  const int t = n / nx, xc = n - t * nx;
-  C o0, o1;
-  wilson_hops<R, L, Vin>(U0, U1, xr, t, xc, nt, nx, o0, o1);
-  C p0 = cconv<C>(xr[2 * n]), p1 = cconv<C>(xr[2 * n + 1]);
-  C y0 = cadd(cscale(p0, mp2), o0), y1 = cadd(cscale(p1, mp2), o1);
-  Vout* yr = y + r * stride;
+  __shared__ Spinor<C> s[(TR + 2) * W];
+  const int tiles_x = (nx + TC - 1) / TC;
+  const int ty = blockIdx.x / tiles_x, tx = blockIdx.x - ty * tiles_x;
+  const int t0 = ty * TR, x0 = tx * TC;
+  const Spinor<Vin>* xr = reinterpret_cast<const Spinor<Vin>*>(x + r * stride);
+  for (int e = threadIdx.x; e < (TR + 2) * W; e += 256) {
+    const int rw = e / W, c = e - rw * W;
+    const int tt = wrap_index(t0 + rw - 1, nt), xx = wrap_index(x0 + c - 1, nx);
+    s[e] = sconv<C>(xr[int64_t(tt) * nx + xx]);
+  }
+  __syncthreads();
+  const int rr = threadIdx.x / TC, cc = threadIdx.x - rr * TC;
+  const int t = t0 + rr, xc = x0 + cc;
+  if (t >= nt || xc >= nx) return;
+  const int n = t * nx + xc;
+  const int tb = t == 0 ? nt - 1 : t - 1, xb = xc == 0 ? nx - 1 : xc - 1;
+  const int Ls = (rr + 1) * W + (cc + 1);
+  const Spinor<C> h = hops<C, R>(s[Ls + W], s[Ls - W], s[Ls + 1], s[Ls - 1], load_link<R>(U0, n),
+                                 load_link<R>(U0, int64_t(tb) * nx + xc), load_link<R>(U1, n),
+                                 load_link<R>(U1, int64_t(t) * nx + xb), t == nt - 1 ? R(-1) : R(1),
+                                 t == 0 ? R(-1) : R(1));
+  const Spinor<C> me = s[Ls];
+  Spinor<C> o{cadd(cscale(me.s0, mp2), h.s0), cadd(cscale(me.s1, mp2), h.s1)};
+  Spinor<Vout>* yr = reinterpret_cast<Spinor<Vout>*>(y + r * stride);
   if (b) {
-    const double2* br = b + r * stride;
-    // residual in FP64
-    double2 e0 = cconv<double2>(y0), e1 = cconv<double2>(y1);
-    yr[2 * n] = cconv<Vout>(csub(br[2 * n], e0));
-    yr[2 * n + 1] = cconv<Vout>(csub(br[2 * n + 1], e1));
+    const Spinor<double2> bb = reinterpret_cast<const Spinor<double2>*>(b + r * stride)[n];
+    const Spinor<double2> od = sconv<double2>(o);
+    yr[n] = sconv<Vout>(Spinor<double2>{csub(bb.s0, od.s0), csub(bb.s1, od.s1)});
   } else {
-    yr[2 * n] = cconv<Vout>(y0);
-    yr[2 * n + 1] = cconv<Vout>(y1);
+    yr[n] = sconv<Vout>(o);
   }
 }
 
-// Sites of one colour c = (t + x) mod 2: x(n) <- x(n) + (b(n) - (D x)(n)) / (m0 + 2), which
-// equals (b(n) - hops(n)) / (m0 + 2) because the diagonal of D at n is (m0 + 2) I.
-template <typename R, typename L, typename Vx>
+// One colour c = (t + x) mod 2 of the red-black point Gauss-Seidel sweep on D x = b:
+// x(n) <- x(n) + (b(n) - (D x)(n)) / (m0 + 2) = (b(n) - hops(n)) / (m0 + 2) for n of colour c
+// (the diagonal of D is (m0 + 2) I); b = null means b = 0.  Tiles of TR x TC sites
+// (TR * TC = 512, t0 and x0 even) hold the 256 colour-c sites of the tile, one per thread; only
+// the opposite colour, which their neighbours have, is staged in LDS: row rw of the halo
+// region keeps its W / 2 opposite-colour sites, column c at slot c / 2.
+template <int TC, typename R, typename L, typename Vx>
 __global__ __launch_bounds__(256) void k_wilson_gs(const L* __restrict__ U0,
                                                    const L* __restrict__ U1, Vx* x,
                                                    const double2* __restrict__ b, int nt,
                                                    int nx, R inv_mp2, int colour, int64_t stride,
                                                    const RhsState* __restrict__ st) {
+  constexpr int TR = 512 / TC, W = TC + 2, H = W / 2;
+  using C = cplx<R>;
   const int r = blockIdx.y;
   if (st && !st[r].active) return;
-  const int idx = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  const int half = nx >> 1;
-  if (idx >= nt * half) return;
-  using C = cplx<R>;
-  const int t = idx / half;
-  const int xc = 2 * (idx - t * half) + ((t + colour) & 1);
-  const int n = t * nx + xc;
-  Vx* xr = x + r * stride;
-  C o0, o1;
-  wilson_hops<R, L, Vx>(U0, U1, xr, t, xc, nt, nx, o0, o1);
-  C f0 = czero<R>(), f1 = czero<R>();
-  if (b) {
-    const double2* br = b + r * stride;
-    f0 = cconv<C>(br[2 * n]);
-    f1 = cconv<C>(br[2 * n + 1]);
+  __shared__ Spinor<C> s[(TR + 2) * H];
+  const int tiles_x = (nx + TC - 1) / TC;
+  const int ty = blockIdx.x / tiles_x, tx = blockIdx.x - ty * tiles_x;
+  const int t0 = ty * TR, x0 = tx * TC;
+  Spinor<Vx>* xr = reinterpret_cast<Spinor<Vx>*>(x + r * stride);
+  // halo position (rw, c) is site (t0 + rw - 1, x0 + c - 1), of colour (rw + c) mod 2
+  for (int e = threadIdx.x; e < (TR + 2) * H; e += 256) {
+    const int rw = e / H, j = e - rw * H;
+    const int c = 2 * j + ((1 - colour + rw) & 1);
+    const int tt = wrap_index(t0 + rw - 1, nt), xx = wrap_index(x0 + c - 1, nx);
+    s[e] = sconv<C>(xr[int64_t(tt) * nx + xx]);
   }
-  xr[2 * n] = cconv<Vx>(cscale(csub(f0, o0), inv_mp2));
-  xr[2 * n + 1] = cconv<Vx>(cscale(csub(f1, o1), inv_mp2));
+  __syncthreads();
+  const int rr = threadIdx.x / (TC / 2), k = threadIdx.x - rr * (TC / 2);
+  const int t = t0 + rr;
+  const int cc = 2 * k + ((t + colour) & 1);
+  const int xc = x0 + cc;
+  if (t >= nt || xc >= nx) return;
+  const int n = t * nx + xc;
+  const int tb = t == 0 ? nt - 1 : t - 1, xb = xc == 0 ? nx - 1 : xc - 1;
+  const int R0 = rr + 1, C0 = cc + 1;
+  const Spinor<C> h = hops<C, R>(s[(R0 + 1) * H + (C0 >> 1)], s[(R0 - 1) * H + (C0 >> 1)],
+                                 s[R0 * H + ((C0 + 1) >> 1)], s[R0 * H + ((C0 - 1) >> 1)],
+                                 load_link<R>(U0, n), load_link<R>(U0, int64_t(tb) * nx + xc),
+                                 load_link<R>(U1, n), load_link<R>(U1, int64_t(t) * nx + xb),
+                                 t == nt - 1 ? R(-1) : R(1), t == 0 ? R(-1) : R(1));
+  Spinor<C> f{czero<R>(), czero<R>()};
+  if (b) f = sconv<C>(reinterpret_cast<const Spinor<double2>*>(b + r * stride)[n]);
+  xr[n] = sconv<Vx>(Spinor<C>{cscale(csub(f.s0, h.s0), inv_mp2), cscale(csub(f.s1, h.s1), inv_mp2)});
 }
 
 __global__ void k_build_fine_stencil(const double2* __restrict__ U0, const double2* __restrict__ U1,
@@ -159,15 +196,20 @@ __global__ void k_cast(const A* __restrict__ x, B* __restrict__ y, int64_t n) {
 
 // ------------------------------------------------------------------------------ launchers
 
-static inline dim3 grid1(int64_t n, int nrhs) { return dim3(unsigned((n + 255) / 256), unsigned(nrhs)); }
 
 template <typename R, typename L, typename Vin, typename Vout>
 static void wilson_apply_t(hipStream_t s, const void* U0, const void* U1, const void* x, void* y,
                            const double2* b, int nt, int nx, double m0, int nrhs, int64_t stride,
                            const RhsState* st) {
-  hipLaunchKernelGGL((k_wilson_apply<R, L, Vin, Vout>), grid1(int64_t(nt) * nx, nrhs), dim3(256), 0, s,
-                     (const L*)U0, (const L*)U1, (const Vin*)x, (Vout*)y, b, nt, nx, R(m0 + 2.0),
-                     stride, st);
+  if (nx >= 64) {
+    dim3 g(unsigned(((nx + 63) / 64) * ((nt + 3) / 4)), unsigned(nrhs));
+    hipLaunchKernelGGL((k_wilson_apply<64, R, L, Vin, Vout>), g, dim3(256), 0, s, (const L*)U0,
+                       (const L*)U1, (const Vin*)x, (Vout*)y, b, nt, nx, R(m0 + 2.0), stride, st);
+  } else {
+    dim3 g(unsigned(((nx + 15) / 16) * ((nt + 15) / 16)), unsigned(nrhs));
+    hipLaunchKernelGGL((k_wilson_apply<16, R, L, Vin, Vout>), g, dim3(256), 0, s, (const L*)U0,
+                       (const L*)U1, (const Vin*)x, (Vout*)y, b, nt, nx, R(m0 + 2.0), stride, st);
+  }
 }
 
 void wilson_apply(hipStream_t s, LinkStore ls, const void* U0, const void* U1, Real vin,
@@ -192,9 +234,15 @@ template <typename R, typename L, typename Vx>
 static void wilson_gs_t(hipStream_t s, const void* U0, const void* U1, void* x, const double2* b,
                         int nt, int nx, double m0, int colour, int nrhs, int64_t stride,
                         const RhsState* st) {
-  hipLaunchKernelGGL((k_wilson_gs<R, L, Vx>), grid1(int64_t(nt) * (nx / 2), nrhs), dim3(256), 0, s,
-                     (const L*)U0, (const L*)U1, (Vx*)x, b, nt, nx, R(1.0 / (m0 + 2.0)), colour,
-                     stride, st);
+  if (nx >= 64) {
+    dim3 g(unsigned(((nx + 63) / 64) * ((nt + 7) / 8)), unsigned(nrhs));
+    hipLaunchKernelGGL((k_wilson_gs<64, R, L, Vx>), g, dim3(256), 0, s, (const L*)U0, (const L*)U1,
+                       (Vx*)x, b, nt, nx, R(1.0 / (m0 + 2.0)), colour, stride, st);
+  } else {
+    dim3 g(unsigned(((nx + 15) / 16) * ((nt + 31) / 32)), unsigned(nrhs));
+    hipLaunchKernelGGL((k_wilson_gs<16, R, L, Vx>), g, dim3(256), 0, s, (const L*)U0, (const L*)U1,
+                       (Vx*)x, b, nt, nx, R(1.0 / (m0 + 2.0)), colour, stride, st);
+  }
 }
 
 void wilson_gs(hipStream_t s, LinkStore ls, const void* U0, const void* U1, Real vx, void* x,

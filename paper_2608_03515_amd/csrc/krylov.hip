@@ -156,46 +156,103 @@ __global__ __launch_bounds__(256) void k_dots(KrylovDims dm, const double2* __re
 }
 
 // w -= sum_i V_i h_i with h the total of the previous kernel's partials hpart; then partials
-// of V^H w_new (DOTS) or of ||w_new||^2 into part.
-template <int NV, bool DOTS>
-__global__ __launch_bounds__(256) void k_update(KrylovDims dm, const double2* __restrict__ V,
-                                                int64_t vsj, double2* __restrict__ w,
-                                                const double2* __restrict__ hpart,
-                                                double2* __restrict__ part,
-                                                const RhsState* __restrict__ st) {
+// of ||w_new||^2 into part.
+template <int NV>
+__global__ __launch_bounds__(256) void k_update_norm(KrylovDims dm, const double2* __restrict__ V,
+                                                     int64_t vsj, double2* __restrict__ w,
+                                                     const double2* __restrict__ hpart,
+                                                     double2* __restrict__ part,
+                                                     const RhsState* __restrict__ st) {
   const int r = blockIdx.y;
   if (!st[r].active) return;
-  constexpr int NA = DOTS ? NV : 1;
-  __shared__ double lds[2 * NA * 4];
+  __shared__ double lds[2 * 4];
   __shared__ double2 hs[KMAXV], scratch[8 * KMAXV];
   sum_blocks(hpart + int64_t(r) * gridDim.x * KMAXV, gridDim.x, NV, hs, scratch);
-  double2 acc[NA];
-#pragma unroll
-  for (int i = 0; i < NA; ++i) acc[i] = make_double2(0, 0);
+  double2 acc[1] = {make_double2(0, 0)};
   double2* wr = w + r * dm.n;
   const double2* Vr = V + r * dm.n;
 #pragma unroll 1
   for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < dm.n; d += int64_t(gridDim.x) * 256) {
     double2 wd = wr[d];
-    if (DOTS) {
-      // the basis values stay in registers for the second projection: reading them twice
-      // would exceed the per-XCD L2 with 64 right-hand sides and go back to HBM
-      double2 v[NV];
 #pragma unroll
-      for (int i = 0; i < NV; ++i) v[i] = Vr[i * vsj + d];
-#pragma unroll
-      for (int i = 0; i < NV; ++i) wd = csub(wd, cmul(v[i], hs[i]));
-      wr[d] = wd;
-#pragma unroll
-      for (int i = 0; i < NA; ++i) acc[i] = cfmac(v[i], wd, acc[i]);
-    } else {
-#pragma unroll
-      for (int i = 0; i < NV; ++i) wd = csub(wd, cmul(Vr[i * vsj + d], hs[i]));
-      wr[d] = wd;
-      acc[0].x += cabs2(wd);
-    }
+    for (int i = 0; i < NV; ++i) wd = csub(wd, cmul(Vr[i * vsj + d], hs[i]));
+    wr[d] = wd;
+    acc[0].x += cabs2(wd);
   }
-  block_partial<NA>(acc, NA, part + (int64_t(r) * gridDim.x + blockIdx.x) * KMAXV, lds);
+  block_partial<1>(acc, 1, part + (int64_t(r) * gridDim.x + blockIdx.x) * KMAXV, lds);
+}
+
+// Lanes per element of the fused update: enough to keep the per-lane share of the basis (and
+// its accumulators) in a few registers, few enough that the shuffles stay cheap.
+constexpr int update_lanes(int nv) { return nv <= 2 ? 1 : nv <= 12 ? 2 : 4; }
+
+// Fused first-projection update and second projection: w -= sum_i V_i h_i (h from hpart), then
+// partials of V^H w_new into part, in one pass over V.  S lanes share an element: lane `sub`
+// holds the basis vectors i = sub + S k in registers, the S partial sums of V_i h_i are added
+// with lane shuffles, and every lane then accumulates conj(V_i) w_new for its own vectors, so
+// each basis value is read from memory once.
+template <int NV, int S>
+__global__ __launch_bounds__(256) void k_update_dots(KrylovDims dm, const double2* __restrict__ V,
+                                                     int64_t vsj, double2* __restrict__ w,
+                                                     const double2* __restrict__ hpart,
+                                                     double2* __restrict__ part,
+                                                     const RhsState* __restrict__ st) {
+  constexpr int K = (NV + S - 1) / S, EPB = 256 / S;
+  const int r = blockIdx.y;
+  if (!st[r].active) return;
+  __shared__ double2 hs[KMAXV], scratch[8 * KMAXV], red[4][KMAXV];
+  sum_blocks(hpart + int64_t(r) * gridDim.x * KMAXV, gridDim.x, NV, hs, scratch);
+  const int sub = threadIdx.x % S;
+  double2 hk[K], acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = sub + S * k;
+    hk[k] = i < NV ? hs[i] : make_double2(0, 0);
+    acc[k] = make_double2(0, 0);
+  }
+  double2* wr = w + r * dm.n;
+  const double2* Vr = V + r * dm.n;
+#pragma unroll 1
+  for (int64_t d = int64_t(blockIdx.x) * EPB + threadIdx.x / S; d < dm.n; d += int64_t(gridDim.x) * EPB) {
+    double2 v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = sub + S * k;
+      v[k] = i < NV ? Vr[i * vsj + d] : make_double2(0, 0);
+    }
+    double2 p = make_double2(0, 0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) p = cfma(v[k], hk[k], p);
+#pragma unroll
+    for (int o = 1; o < S; o <<= 1) {
+      p.x += __shfl_xor(p.x, o);
+      p.y += __shfl_xor(p.y, o);
+    }
+    const double2 wd = csub(wr[d], p);
+    if (sub == 0) wr[d] = wd;
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = cfmac(v[k], wd, acc[k]);
+  }
+  // block totals: lanes with equal `sub` hold the same basis vectors (xor offsets S .. 32 within
+  // a wave), then the four waves in order
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double2 a = acc[k];
+#pragma unroll
+    for (int o = S; o < 64; o <<= 1) {
+      a.x += __shfl_xor(a.x, o);
+      a.y += __shfl_xor(a.y, o);
+    }
+    const int i = sub + S * k;
+    if (lane < S && i < NV) red[wv][i] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double2 t = red[0][threadIdx.x];
+    for (int q = 1; q < 4; ++q) t = cadd(t, red[q][threadIdx.x]);
+    part[(int64_t(r) * gridDim.x + blockIdx.x) * KMAXV + threadIdx.x] = t;
+  }
 }
 
 // Arnoldi step j, one block per rhs: h1, h2 and ||w||^2 are the totals of the three partial
@@ -354,23 +411,33 @@ template <int NV> void launch_dots(hipStream_t s, const KrylovDims& d, const dou
                                    double2* w, const double2*, double2* part, const RhsState* st) {
   hipLaunchKernelGGL((k_dots<NV>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, w, part, st);
 }
-template <int NV, bool DOTS>
-void launch_update(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, double2* w,
-                   const double2* hpart, double2* part, const RhsState* st) {
-  hipLaunchKernelGGL((k_update<NV, DOTS>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, w, hpart,
+template <int NV>
+void launch_update_norm(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, double2* w,
+                        const double2* hpart, double2* part, const RhsState* st) {
+  hipLaunchKernelGGL((k_update_norm<NV>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, w, hpart,
                      part, st);
+}
+template <int NV>
+void launch_update_dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, double2* w,
+                        const double2* hpart, double2* part, const RhsState* st) {
+  hipLaunchKernelGGL((k_update_dots<NV, update_lanes(NV)>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d,
+                     V, vsj, w, hpart, part, st);
 }
 template <int... I>
 static constexpr std::array<KFn, sizeof...(I)> table_dots(std::integer_sequence<int, I...>) {
   return {&launch_dots<I + 1>...};
 }
-template <bool DOTS, int... I>
-static constexpr std::array<KFn, sizeof...(I)> table_update(std::integer_sequence<int, I...>) {
-  return {&launch_update<I + 1, DOTS>...};
+template <int... I>
+static constexpr std::array<KFn, sizeof...(I)> table_update_dots(std::integer_sequence<int, I...>) {
+  return {&launch_update_dots<I + 1>...};
+}
+template <int... I>
+static constexpr std::array<KFn, sizeof...(I)> table_update_norm(std::integer_sequence<int, I...>) {
+  return {&launch_update_norm<I + 1>...};
 }
 static const auto kDots = table_dots(std::make_integer_sequence<int, KMAXV>{});
-static const auto kUpdDots = table_update<true>(std::make_integer_sequence<int, KMAXV>{});
-static const auto kUpdNorm = table_update<false>(std::make_integer_sequence<int, KMAXV>{});
+static const auto kUpdDots = table_update_dots(std::make_integer_sequence<int, KMAXV>{});
+static const auto kUpdNorm = table_update_norm(std::make_integer_sequence<int, KMAXV>{});
 
 void dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
           const double2* w, double2* part, const RhsState* st) {

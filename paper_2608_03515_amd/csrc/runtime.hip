@@ -1,6 +1,7 @@
 // Host runtime and C ABI of the AM-AMG library: handles, the GPU setup pipeline and the
 // FGMRES driver.  Every numerical step runs in the kernels of this directory; the host only
 // sequences launches, owns device memory and reads per-rhs status once per restart cycle.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -167,7 +168,6 @@ struct amamg_hierarchy {
   double* cs = nullptr;
   void* Z = nullptr;
   RhsState* st = nullptr;
-  int nblk = 1;
   std::vector<std::vector<double2>> history;
 };
 
@@ -179,6 +179,9 @@ amamg_status fail(amamg_context* ctx, const Fail& f) {
   if (ctx) ctx->err = f.msg;
   return f.code;
 }
+
+// Fields are moved one site (two spin components, 16 or 32 bytes) per vector access.
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 void check_launch() {
   hipError_t e = hipGetLastError();
@@ -508,6 +511,16 @@ void ensure_links(amamg_gauge* gg, LinkStore ls) {
   }
 }
 
+// Blocks per right-hand side of the Gram-Schmidt and norm kernels: about 4096 blocks in all
+// (16 per compute unit), at least 8 elements per thread once that many blocks exist (the
+// per-block reduction of the previous pass's partials is then amortised), at most one block
+// per 256 elements and at most kMaxKrylovBlocks.
+constexpr int kMaxKrylovBlocks = 256;
+int krylov_blocks(int64_t n, int nrhs) {
+  const int64_t want = std::max<int64_t>(n / 2048, (4096 + nrhs - 1) / nrhs);
+  return int(std::max<int64_t>(1, std::min<int64_t>({int64_t(kMaxKrylovBlocks), n / 256, want})));
+}
+
 void ensure_workspace(amamg_hierarchy* h, int nrhs, int m, Real prec, int hist_cap) {
   if (h->ws_nrhs >= nrhs && h->ws_m >= m && h->ws_prec == prec && h->ws_hist >= hist_cap) return;
   h->ws.release();
@@ -521,8 +534,7 @@ void ensure_workspace(amamg_hierarchy* h, int nrhs, int m, Real prec, int hist_c
   h->cs = h->ws.alloc<double>(size_t(nrhs) * m);
   h->sn = h->ws.alloc<double2>(size_t(nrhs) * m);
   h->y = h->ws.alloc<double2>(size_t(nrhs) * m);
-  h->nblk = int(std::min<int64_t>(256, std::max<int64_t>(1, n / 512)));
-  h->part = h->ws.alloc<double2>(size_t(3) * nrhs * h->nblk * 32);
+  h->part = h->ws.alloc<double2>(size_t(3) * nrhs * kMaxKrylovBlocks * 32);
   h->st = h->ws.alloc<RhsState>(nrhs);
   h->hist = h->ws.alloc<double2>(size_t(nrhs) * hist_cap);
   for (size_t k = 1; k < h->lv.size(); ++k) {
@@ -543,9 +555,6 @@ void ensure_workspace(amamg_hierarchy* h, int nrhs, int m, Real prec, int hist_c
   h->ws_hist = hist_cap;
 }
 
-// Largest basis for which w -= V h and the second projection run as one fused pass (the
-// fused kernel holds the basis values in registers: about 12 VGPRs per vector).
-constexpr int kFusedUpdateMax = 14;
 
 struct SolveCtx {
   amamg_hierarchy* h;
@@ -664,14 +673,15 @@ amamg_status run_solve(amamg_hierarchy* h, int nrhs, const double2* b, double2* 
 
   const int64_t n = h->lv[0].g.ndof();
   const int nt = gg->nt, nx = gg->nx;
-  KrylovDims kd{n, nrhs, h->nblk, m};
+  const int nblk = krylov_blocks(n, nrhs);
+  KrylovDims kd{n, nrhs, nblk, m};
   RhsState* st = h->st;
   const size_t zs = T == F64 ? sizeof(double2) : sizeof(float2);
   const int64_t vsj = int64_t(nrhs) * n;   // basis stride between j
 
   double2* p1 = h->part;
-  double2* p2 = h->part + size_t(nrhs) * h->nblk * 32;
-  double2* p3 = h->part + size_t(2) * nrhs * h->nblk * 32;
+  double2* p2 = h->part + size_t(nrhs) * nblk * 32;
+  double2* p3 = h->part + size_t(2) * nrhs * nblk * 32;
   // ||b||; refuse non-finite input before touching x
   norm_control(s, kd, b, p1, st, 1, h->g, p.rel_tol, p.max_iters, h->hist, hist_cap);
   check_launch();
@@ -721,19 +731,9 @@ amamg_status run_solve(amamg_hierarchy* h, int nrhs, const double2* b, double2* 
       rec = timer_start(gg->ctx, AMAMG_KT_DOTS, j, dot_bytes);
       dots(s, kd, h->V, vsj, j + 1, h->w, p1, st);
       timer_stop(gg->ctx, rec);
-      if (j + 1 <= kFusedUpdateMax) {
-        rec = timer_start(gg->ctx, AMAMG_KT_UPDATE, j, upd_bytes);
-        update_dots(s, kd, h->V, vsj, j + 1, h->w, p1, p2, st);
-        timer_stop(gg->ctx, rec);
-      } else {
-        // large bases: the fused kernel runs out of registers; two streaming passes are faster
-        rec = timer_start(gg->ctx, AMAMG_KT_UPDATE, j, upd_bytes);
-        update_norm(s, kd, h->V, vsj, j + 1, h->w, p1, p3, st);
-        timer_stop(gg->ctx, rec);
-        rec = timer_start(gg->ctx, AMAMG_KT_DOTS, j, dot_bytes);
-        dots(s, kd, h->V, vsj, j + 1, h->w, p2, st);
-        timer_stop(gg->ctx, rec);
-      }
+      rec = timer_start(gg->ctx, AMAMG_KT_UPDATE, j, upd_bytes);
+      update_dots(s, kd, h->V, vsj, j + 1, h->w, p1, p2, st);
+      timer_stop(gg->ctx, rec);
       rec = timer_start(gg->ctx, AMAMG_KT_UPDATE, j, upd_bytes);
       update_norm(s, kd, h->V, vsj, j + 1, h->w, p2, p3, st);
       timer_stop(gg->ctx, rec);
@@ -927,6 +927,8 @@ amamg_status amamg_solve_device(amamg_hierarchy* h, int32_t nrhs, const void* ps
                                 const amamg_solve_params* params, amamg_solve_info* info) {
   if (!h) return AMAMG_ERR_INVALID_ARG;
   if (!psi_dev || !x_dev) return fail(h->gauge->ctx, {AMAMG_ERR_INVALID_ARG, "null field pointer"});
+  if (!aligned16(psi_dev) || !aligned16(x_dev))
+    return fail(h->gauge->ctx, {AMAMG_ERR_INVALID_ARG, "field pointers must be 16-byte aligned"});
   amamg_solve_params p;
   if (params) p = *params;
   else amamg_default_solve_params(&p);
@@ -1010,6 +1012,8 @@ amamg_status amamg_apply_dirac_device(amamg_gauge* g, int32_t precision, int32_t
   try {
     REQUIRE(precision >= AMAMG_FP64 && precision <= AMAMG_MIXED_FP32_BF16LINKS, AMAMG_ERR_INVALID_ARG,
             "unknown precision");
+    REQUIRE(aligned16(in_dev) && aligned16(out_dev), AMAMG_ERR_INVALID_ARG,
+            "field pointers must be 16-byte aligned");
     HIPCHECK(hipSetDevice(ctx->device));
     const int64_t n = int64_t(g->nt) * g->nx * 2;
     const LinkStore ls = precision == AMAMG_FP64 ? LINK_F64 : precision == AMAMG_MIXED_FP32 ? LINK_F32 : LINK_BF16;

@@ -10,6 +10,7 @@ import pytest
 
 import synth
 from oracle import amg
+from oracle import dirac
 from oracle.dirac import dirac_matrix
 from oracle.solve import solve as oracle_solve
 from oracle.wirebasket import KIND_V
@@ -36,7 +37,7 @@ def make_gauge(lib, ctx, U, m0):
 
 # --------------------------------------------------------------------------- stencil
 
-@pytest.mark.parametrize("nt,nx", [(4, 4), (8, 12), (16, 16), (64, 64), (6, 10)])
+@pytest.mark.parametrize("nt,nx", [(4, 4), (8, 12), (16, 16), (64, 64), (6, 10), (10, 130), (36, 96)])
 def test_dirac_apply_matches_oracle(lib, ctx, nt, nx):
     say("dirac apply", nt, nx)
     U = np.exp(1j * np.random.default_rng(nt * 100 + nx).uniform(-np.pi, np.pi, (2, nt, nx)))
@@ -50,6 +51,57 @@ def test_dirac_apply_matches_oracle(lib, ctx, nt, nx):
     out32 = synth.field_from_abi(g.apply_dirac(synth.field_to_abi(psi), precision=lib.MIXED_FP32))
     ref = (D @ psi[0].reshape(-1)).reshape(nt, nx, 2)
     assert rel(out32[0], ref) < 2e-6
+    g.close()
+
+
+def bf16_round(a):
+    """Round-to-nearest-even of float32 values to bfloat16, returned as float32."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32)
+
+
+def test_stencil_full_size_sampled(lib, ctx):
+    """4096 x 4096 lattice, one right-hand side, device buffers: the configuration whose
+    bandwidth is measured.  Sampled sites (lattice and tile boundaries plus random ones) against
+    the oracle's per-site D, for FP64, FP32 and FP32 with BF16 links.  The reduced-precision
+    references use the rounded links and fields the kernel sees; their bound is 16 units of
+    FP32 rounding times sum |terms| of the site."""
+    import torch
+    L, m0 = 4096, 0.05
+    rng = np.random.default_rng(4096)
+    U = np.exp(1j * rng.uniform(-np.pi, np.pi, (2, L, L)))
+    g = make_gauge(lib, ctx, U, m0)
+    psi = (rng.standard_normal((L, L, 2)) + 1j * rng.standard_normal((L, L, 2)))
+    edge = np.array([0, 1, 2, 3, 4, 62, 63, 64, 65, 127, 128, L - 65, L - 64, L - 2, L - 1])
+    ts = np.concatenate([np.repeat(edge, edge.size), rng.integers(0, L, 3000)])
+    xs = np.concatenate([np.tile(edge, edge.size), rng.integers(0, L, 3000)])
+    say("stencil 4096 sampled", ts.size)
+    for prec in (lib.FP64, lib.MIXED_FP32, lib.MIXED_FP32_BF16LINKS):
+        if prec == lib.FP64:
+            p_in, U_ref, dt = psi, U, torch.float64
+        else:
+            p_in = (psi.real.astype(np.float32).astype(np.float64)
+                    + 1j * psi.imag.astype(np.float32).astype(np.float64))
+            rnd = (lambda a: a.astype(np.float32)) if prec == lib.MIXED_FP32 else bf16_round
+            U_ref = rnd(U.real).astype(np.float64) + 1j * rnd(U.imag).astype(np.float64)
+            dt = torch.float32
+        xin = torch.from_numpy(np.stack([p_in.real, p_in.imag], -1)[None]).to(dt).cuda()
+        y = torch.empty_like(xin)
+        g.apply_dirac_device(xin.data_ptr(), y.data_ptr(), 1, prec)
+        torch.cuda.synchronize()
+        out = y[0].double().cpu().numpy()
+        got = out[ts, xs, :, 0] + 1j * out[ts, xs, :, 1]
+        ref = dirac.dirac_at_sites(U_ref, m0, p_in, ts, xs)
+        err = np.abs(got - ref).max(axis=1)
+        if prec == lib.FP64:
+            assert err.max() < 1e-12
+        else:
+            mag = (m0 + 2) * np.abs(p_in[ts, xs]).sum(1)
+            for dtn, dxn in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                mag += 2 * np.abs(p_in[(ts + dtn) % L, (xs + dxn) % L]).sum(1)
+            assert np.all(err <= 16 * 2.0 ** -24 * mag), (prec, float((err / mag).max()))
+        del xin, y
     g.close()
 
 
@@ -231,7 +283,16 @@ def test_invalid_shapes_and_args(lib, ctx):
     with pytest.raises(lib.AmamgError) as e:
         lib.Gauge(ctx, bad, 0.1)
     assert e.value.status == -7
+    import torch
+    buf = torch.zeros(2 * 16 * 16 * 4 + 2, dtype=torch.float64, device="cuda")
+    for bad_ptr in (buf.data_ptr() + 8, buf.data_ptr()):
+        with pytest.raises(lib.AmamgError) as e:      # misaligned input / misaligned output
+            g.apply_dirac_device(bad_ptr, buf.data_ptr() + 8, 1, lib.FP64)
+        assert e.value.status == -1
     h = lib.Hierarchy(g, lib.default_setup_params())
+    with pytest.raises(lib.AmamgError) as e:
+        h.solve_device(buf.data_ptr() + 8, buf.data_ptr(), 1)
+    assert e.value.status == -1
     psi = synth.field_to_abi(synth.gaussian_rhs(16, 16, 1))
     psi[0, 1, 1, 0, 0] = np.inf
     with pytest.raises(lib.AmamgError) as e:

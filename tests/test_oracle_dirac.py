@@ -112,3 +112,34 @@ def test_plaquette_and_topology_of_generator():
         assert abs(plaq - expect) < 6 * np.sqrt(var / (L * L)) + 0.01
         q = np.sum(np.angle(np.exp(1j * tp))) / (2 * np.pi)
         assert abs(q - round(q)) < 1e-9
+
+
+def test_dirac_at_sites_plane_wave_closed_form():
+    """Constant links U_mu = exp(i phi_mu), psi = exp(i (p_t t + p_x x)) chi with an antiperiodic
+    momentum p_t: D psi = M psi with M = m0 + sum_mu (1 - cos q_mu) + i sum_mu sigma_mu sin q_mu,
+    q_mu = p_mu + phi_mu, at every site including both boundaries."""
+    nt, nx, m0, phi = 8, 12, 0.21, (0.3, -0.7)
+    U = np.empty((2, nt, nx), dtype=complex)
+    U[0], U[1] = np.exp(1j * phi[0]), np.exp(1j * phi[1])
+    pt, px = 3 * np.pi / nt, 2 * np.pi * 5 / nx
+    chi = np.array([0.4 - 0.2j, -1.1 + 0.7j])
+    T, X = np.meshgrid(np.arange(nt), np.arange(nx), indexing="ij")
+    psi = np.exp(1j * (pt * T + px * X))[..., None] * chi
+    qt, qx = pt + phi[0], px + phi[1]
+    M = ((m0 + 2 - np.cos(qt) - np.cos(qx)) * np.eye(2)
+         + 1j * (np.sin(qt) * dirac.SIGMA0 + np.sin(qx) * dirac.SIGMA1))
+    got = dirac.dirac_at_sites(U, m0, psi, T.ravel(), X.ravel())
+    want = psi[T.ravel(), X.ravel()] @ M.T
+    assert np.abs(got - want).max() < 1e-13
+
+
+def test_dirac_at_sites_agrees_with_matrix_on_random_links():
+    nt, nx = 6, 10
+    rng = np.random.default_rng(17)
+    U = np.exp(1j * rng.uniform(-np.pi, np.pi, (2, nt, nx)))
+    psi = rng.standard_normal((nt, nx, 2)) + 1j * rng.standard_normal((nt, nx, 2))
+    D = dirac_matrix(U, -0.3)
+    want = (D @ psi.reshape(-1)).reshape(nt, nx, 2)
+    T, X = np.meshgrid(np.arange(nt), np.arange(nx), indexing="ij")
+    got = dirac.dirac_at_sites(U, -0.3, psi, T.ravel(), X.ravel()).reshape(nt, nx, 2)
+    assert np.abs(got - want).max() < 1e-13
