@@ -43,9 +43,9 @@ KERNEL_NAMES = {"fine_matvec": "k_wilson_apply", "fine_gs": "k_wilson_gs",
                 "update": "k_update_dots<nv, s> + k_update_norm<nv> (all basis sizes)"}
 
 
-def run_steps(lib, torch, ctx, h, b, x, nrhs, precision, steps, warmup, timer=None):
+def run_steps(lib, torch, ctx, h, b, x, nrhs, precision, steps, warmup, timer=None, groups=1):
     """warmup + timed steps; a step = in-place setup + solve of nrhs right-hand sides."""
-    sp = lib.default_solve_params(precision=precision)
+    sp = lib.default_solve_params(precision=precision, groups=groups)
     infos = None
     for _ in range(warmup):
         h.update()
@@ -69,11 +69,11 @@ def run_steps(lib, torch, ctx, h, b, x, nrhs, precision, steps, warmup, timer=No
     return dt, t_setup, infos, timed
 
 
-def dominant_family(lib, torch, ctx, h, b, x, nrhs, precision):
+def dominant_family(lib, torch, ctx, h, b, x, nrhs, precision, groups=1):
     """One instrumented step with every family timed; returns (family, {family: ms})."""
     ctx.kernel_timer(FAMILIES)
     h.update()
-    h.solve_device(b.data_ptr(), x.data_ptr(), nrhs, lib.default_solve_params(precision=precision))
+    h.solve_device(b.data_ptr(), x.data_ptr(), nrhs, lib.default_solve_params(precision=precision, groups=groups))
     torch.cuda.synchronize()
     tot = {f: ctx.kernel_timer_read(f)[1] for f in FAMILIES}
     ctx.kernel_timer([])
@@ -244,6 +244,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nrhs", type=int, default=64)
+    ap.add_argument("--groups", type=int, default=2,
+                    help="right-hand-side batches run concurrently on separate streams")
+    ap.add_argument("--family", default=None, choices=FAMILIES,
+                    help="kernel family of the roofline (default: the largest in an instrumented "
+                         "one-stream step)")
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stencil", action="store_true")
@@ -297,7 +302,7 @@ def main():
     if args.profile_mixed:
         fam = "update"
         dt, ts, infos, timed = run_steps(lib, torch, ctx, h, b, x, args.nrhs, lib.MIXED_FP32, args.steps,
-                                         args.warmup, timer=fam)
+                                         args.warmup, timer=fam, groups=args.groups)
         launches, ms, nbytes = timed
         # traffic-counter calibration: a plain elementwise copy of known size
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").normal_()
@@ -310,15 +315,18 @@ def main():
                           "algorithmic_bytes_per_launch": nbytes / max(1, launches),
                           "copy_bytes_each_way": src.numel() * 8}), flush=True)
         return
-    dt, ts, infos, _ = run_steps(lib, torch, ctx, h, b, x, args.nrhs, lib.FP64, args.steps, args.warmup)
+    dt, ts, infos, _ = run_steps(lib, torch, ctx, h, b, x, args.nrhs, lib.FP64, args.steps, args.warmup,
+                                 groups=args.groups)
     res["fp64"] = summarize(dt, ts, infos, args.nrhs, args.steps)
     rhs0_iterations = infos[0].iterations          # the right-hand side the CPU oracle samples
     x64 = x.clone()
     log("fp64", json.dumps(res["fp64"]))
     fam, fam_ms = dominant_family(lib, torch, ctx, h, b, x, args.nrhs, lib.MIXED_FP32)
+    if args.family:
+        fam = args.family
     log("dominant family (mixed):", fam, json.dumps({k: round(v, 2) for k, v in fam_ms.items()}))
     dt, ts, infos, timed = run_steps(lib, torch, ctx, h, b, x, args.nrhs, lib.MIXED_FP32, args.steps,
-                                     args.warmup, timer=fam)
+                                     args.warmup, timer=fam, groups=args.groups)
     res["mixed"] = summarize(dt, ts, infos, args.nrhs, args.steps)
     res["mixed"]["rel_diff_vs_fp64"] = float((x - x64).norm() / x64.norm())
     log("mixed", json.dumps(res["mixed"]))
@@ -358,7 +366,7 @@ def main():
                                f"{w.levels} levels a={w.agg} o={w.overlap} Nv={w.n_test_vectors}, "
                                f"FGMRES({w.restart}) to 1e-10; step = AM-AMG setup + solve of "
                                f"{args.nrhs} right-hand sides",
-                   "nrhs": args.nrhs,
+                   "nrhs": args.nrhs, "stream_groups": args.groups,
                    "precision": "FP32 V-cycle and Arnoldi matvec inside FP64 FGMRES"},
         "fp64": res["fp64"], "mixed": res["mixed"], "fp64_single_rhs": res.get("fp64_single_rhs"),
         "mixed_over_fp64": res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"],

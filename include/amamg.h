@@ -79,6 +79,12 @@ typedef struct {
   double rel_tol;              /* ||psi - D x|| <= rel_tol ||psi|| (default 1e-10)           */
   int32_t precision;           /* amamg_precision (default AMAMG_FP64)                       */
   int32_t use_initial_guess;   /* nonzero: x holds x0 on entry (default 0)                   */
+  int32_t groups;              /* the right-hand sides are split into this many batches that  */
+                               /* run concurrently on separate HIP streams, overlapping one   */
+                               /* batch's latency-bound coarse levels with another's          */
+                               /* bandwidth-bound work; 0 or 1 = one batch on the context     */
+                               /* stream (default 1, at most 16)                              */
+  int32_t reserved;
 } amamg_solve_params;
 
 typedef struct {
@@ -131,8 +137,9 @@ amamg_status amamg_hierarchy_destroy(amamg_hierarchy *h);
 amamg_status amamg_solve(amamg_hierarchy *h, int32_t nrhs, const double *psi, double *x,
                          const amamg_solve_params *params, amamg_solve_info *info);
 /* Same with device pointers (resident in HBM, same layout, 16-byte aligned, else
- * AMAMG_ERR_INVALID_ARG); runs on the context stream and returns after the solve has
- * finished. */
+ * AMAMG_ERR_INVALID_ARG); runs on the context stream (and, with groups > 1, on streams the
+ * hierarchy creates, ordered after the work already queued on the context stream) and
+ * returns after the solve has finished. */
 amamg_status amamg_solve_device(amamg_hierarchy *h, int32_t nrhs, const void *psi_dev,
                                 void *x_dev, const amamg_solve_params *params,
                                 amamg_solve_info *info);

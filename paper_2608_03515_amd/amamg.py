@@ -48,7 +48,8 @@ class SetupParams(C.Structure):
 
 class SolveParams(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iters", C.c_int32), ("rel_tol", C.c_double),
-                ("precision", C.c_int32), ("use_initial_guess", C.c_int32)]
+                ("precision", C.c_int32), ("use_initial_guess", C.c_int32), ("groups", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

@@ -273,8 +273,9 @@ __global__ __launch_bounds__(256) void k_arnoldi(KrylovDims dm, const double2* _
   st[r] = s;
 }
 
-// ||x||^2 per rhs, then: mode 0 store only; 1 start states (x = b); 2 first cycle start
-// (x = r_0); 3 end of a cycle (x = b - D x): convergence test and the next cycle's start.
+// ||x||^2 per rhs whose state is active, then: mode 1 fresh states (x = b; the host marks the
+// slots to start as active); 2 first cycle start (x = r_0); 3 end of a cycle (x = b - D x):
+// convergence test and the next cycle's start.
 struct CycleArgs {
   double2* g;
   double tol;
@@ -315,9 +316,9 @@ __device__ inline void begin_cycle(const KrylovDims& dm, RhsState& s, int r, dou
 
 __global__ __launch_bounds__(256) void k_norm(KrylovDims dm, const double2* __restrict__ x,
                                               double2* __restrict__ part,
-                                              const RhsState* __restrict__ st, int only_active) {
+                                              const RhsState* __restrict__ st) {
   const int r = blockIdx.y;
-  if (only_active && !st[r].active) return;
+  if (!st[r].active) return;
   __shared__ double lds[2 * KMAXV * 4];
   double2 acc[1] = {make_double2(0, 0)};
   const double2* xr = x + r * dm.n;
@@ -331,7 +332,7 @@ __global__ __launch_bounds__(256) void k_norm(KrylovDims dm, const double2* __re
 __global__ __launch_bounds__(256) void k_cycle(KrylovDims dm, const double2* __restrict__ part,
                                                RhsState* __restrict__ st, int mode, CycleArgs ca) {
   const int r = blockIdx.x;
-  if (mode >= 2 && !st[r].active) return;
+  if (!st[r].active) return;
   __shared__ double2 nr[KMAXV], scratch[8 * KMAXV];
   sum_blocks(part + int64_t(r) * dm.nblk * KMAXV, dm.nblk, 1, nr, scratch);
   if (threadIdx.x != 0) return;
@@ -464,8 +465,18 @@ void arnoldi(hipStream_t s, const KrylovDims& d, const double2* p1, const double
 void norm_control(hipStream_t s, const KrylovDims& d, const double2* x, double2* part, RhsState* st,
                   int mode, double2* g, double tol, int max_iters, double2* hist, int hist_cap) {
   CycleArgs ca{g, tol, max_iters, hist, hist_cap};
-  hipLaunchKernelGGL(k_norm, dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, x, part, st, mode >= 2 ? 1 : 0);
+  hipLaunchKernelGGL(k_norm, dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, x, part, st);
   hipLaunchKernelGGL(k_cycle, dim3(d.nrhs), dim3(256), 0, s, d, part, st, mode, ca);
+}
+
+__global__ void k_merge_states(RhsState* __restrict__ st, const RhsState* __restrict__ st2,
+                               const int* __restrict__ admit, int cap) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < cap && admit[r]) st[r] = st2[r];
+}
+
+void merge_states(hipStream_t s, RhsState* st, const RhsState* st2, const int* admit, int cap) {
+  hipLaunchKernelGGL(k_merge_states, dim3((cap + 63) / 64), dim3(64), 0, s, st, st2, admit, cap);
 }
 
 void scale_next(hipStream_t s, const KrylovDims& d, const double2* w, double2* v, const RhsState* st) {

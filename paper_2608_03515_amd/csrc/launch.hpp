@@ -116,6 +116,8 @@ void norm_control(hipStream_t s, const KrylovDims& d, const double2* x, double2*
                   int mode, double2* g, double tol, int max_iters, double2* hist, int hist_cap);
 void scale_next(hipStream_t s, const KrylovDims& d, const double2* w, double2* v,
                 const RhsState* st);
+// st[r] = st2[r] for the slots with admit[r] != 0 (slots joining a running batch)
+void merge_states(hipStream_t s, RhsState* st, const RhsState* st2, const int* admit, int cap);
 void backsolve_update(hipStream_t s, const KrylovDims& d, RhsState* st, const double2* H,
                       const double2* g, double2* y, Real zprec, const void* Z,
                       int64_t zstride_j, double2* x);

@@ -1,6 +1,6 @@
-// Host runtime and C ABI of the AM-AMG library: handles, the GPU setup pipeline and the
-// FGMRES driver.  Every numerical step runs in the kernels of this directory; the host only
-// sequences launches, owns device memory and reads per-rhs status once per restart cycle.
+// Host runtime and C ABI of the AM-AMG library: handles, the GPU setup pipeline and the entry
+// points.  Every numerical step runs in the kernels of this directory; the host only sequences
+// launches, owns device memory and reads per-rhs status once per restart cycle.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -9,76 +9,12 @@
 #include <string>
 #include <vector>
 
-#include "../../include/amamg.h"
-#include "launch.hpp"
+#include "runtime.hpp"
 
 using namespace amamg;
+using namespace amamg::rt;
 
 namespace {
-
-struct Fail {
-  amamg_status code;
-  std::string msg;
-};
-
-#define HIPCHECK(expr)                                                                          \
-  do {                                                                                          \
-    hipError_t e_ = (expr);                                                                     \
-    if (e_ != hipSuccess) {                                                                     \
-      if (e_ == hipErrorOutOfMemory)                                                            \
-        throw Fail{AMAMG_ERR_OUT_OF_MEMORY, std::string(#expr) + ": out of device memory"};    \
-      throw Fail{AMAMG_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)};         \
-    }                                                                                           \
-  } while (0)
-
-#define REQUIRE(cond, code, msg) \
-  do {                           \
-    if (!(cond)) throw Fail{code, msg}; \
-  } while (0)
-
-// Device allocations owned by a handle, released together.
-struct Arena {
-  std::vector<void*> ptrs;
-  template <typename T> T* alloc(size_t count) {
-    if (count == 0) count = 1;
-    void* p = nullptr;
-    HIPCHECK(hipMalloc(&p, count * sizeof(T)));
-    ptrs.push_back(p);
-    return static_cast<T*>(p);
-  }
-  void release() {
-    for (void* p : ptrs) (void)hipFree(p);
-    ptrs.clear();
-  }
-  ~Arena() { release(); }
-};
-
-// Device buffers looked up by (name, level): allocated on first use, reused afterwards, so a
-// repeated setup on the same hierarchy allocates nothing.
-struct Pool {
-  struct Item { std::string key; void* p; size_t bytes; };
-  std::vector<Item> items;
-  template <typename T> T* get(const char* name, int level, size_t count) {
-    if (count == 0) count = 1;
-    const std::string key = std::string(name) + "#" + std::to_string(level);
-    for (Item& it : items)
-      if (it.key == key) {
-        if (it.bytes >= count * sizeof(T)) return static_cast<T*>(it.p);
-        (void)hipFree(it.p);
-        it.p = nullptr;
-        HIPCHECK(hipMalloc(&it.p, count * sizeof(T)));
-        it.bytes = count * sizeof(T);
-        return static_cast<T*>(it.p);
-      }
-    void* p = nullptr;
-    HIPCHECK(hipMalloc(&p, count * sizeof(T)));
-    items.push_back({key, p, count * sizeof(T)});
-    return static_cast<T*>(p);
-  }
-  ~Pool() {
-    for (Item& it : items) (void)hipFree(it.p);
-  }
-};
 
 int period_of(int L) {
   for (int d = 5; d <= L; ++d)
@@ -86,94 +22,11 @@ int period_of(int L) {
   return L;
 }
 
-}  // namespace
-
-// Benchmark timer: HIP events around every launch of one kernel family in the solve.  A
-// launch's algorithmic bytes are its per-rhs bytes times the right-hand sides it served,
-// which the host learns at the end of each restart cycle.
-struct KernelTimer {
-  static constexpr int NF = 8;
-  uint32_t mask = 0;
-  std::vector<hipEvent_t> events;
-  struct Rec { int e0, e1, step, family; double bytes_per_rhs; };
-  std::vector<Rec> pending;
-  int64_t launches[NF] = {};
-  double total_ms[NF] = {}, total_bytes[NF] = {};
-};
-
-struct amamg_context {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  std::string err;
-  KernelTimer timer;
-};
-
-struct amamg_gauge {
-  amamg_context* ctx = nullptr;
-  int nt = 0, nx = 0;
-  double m0 = 0;
-  int nhier = 0;
-  Arena mem;
-  double2* U = nullptr;     // [2][nt*nx]
-  float2* U32 = nullptr;
-  bf16c* U16 = nullptr;
-  int version = 0;          // bumped by amamg_gauge_update_links
-  int v32 = -1, v16 = -1;   // version the low-precision copies were made from
-};
-
-namespace {
-
-struct LevelData {
-  Geom g{};
-  bool coarsest = false;
-  // operator of this level (k >= 1)
-  double2* A = nullptr;      // stencil [nnode][25][b][b] (non-coarsest)
-  float2* A32 = nullptr;
-  double2* Dinv = nullptr;   // [nnode][b][b]
-  float2* Dinv32 = nullptr;
-  double2* Adense = nullptr; // coarsest [n][n]
-  double2* Ainv = nullptr;   // coarsest inverse [n][n]
-  // transfer to the next level (non-coarsest)
-  int8_t* kind = nullptr;
-  int* owner = nullptr;
-  int* node = nullptr;
-  double2* P = nullptr;      // [nnode][b][4 bc]
-  float2* P32 = nullptr;
-  double2* tv = nullptr;     // smoothed test vectors [nv][ndof]
-  int* tabs = nullptr;       // footprint tables: postab [fp] then fpos [nf]
-  int nf = 0;                // F positions per wirebasket footprint
-  int* rows = nullptr;       // owned fine rows per wirebasket [nW][nf*b]
-  int* nrows = nullptr;      // their counts [nW]
-  void* rpart = nullptr;     // restriction partial sums (solve workspace)
-  // solve workspace (k >= 1): right-hand side, iterate, scratch
-  void* f = nullptr;
-  void* x = nullptr;
-  void* tmp = nullptr;
-};
 
 }  // namespace
 
-struct amamg_hierarchy {
-  amamg_gauge* gauge = nullptr;
-  amamg_setup_params prm{};
-  double m0 = 0;
-  std::vector<LevelData> lv;
-  Pool mem;        // setup products and setup scratch
-  Arena ws;        // solve workspace
-  int ws_nrhs = 0, ws_m = 0, ws_hist = 0;
-  Real ws_prec = F64;
-  double2 *V = nullptr, *w = nullptr, *H = nullptr, *g = nullptr, *sn = nullptr, *y = nullptr;
-  double2 *part = nullptr, *hist = nullptr;
-  double* cs = nullptr;
-  void* Z = nullptr;
-  RhsState* st = nullptr;
-  std::vector<std::vector<double2>> history;
-};
-
-// ------------------------------------------------------------------------------- helpers
-
-namespace {
+namespace amamg {
+namespace rt {
 
 amamg_status fail(amamg_context* ctx, const Fail& f) {
   if (ctx) ctx->err = f.msg;
@@ -188,7 +41,7 @@ void check_launch() {
   if (e != hipSuccess) throw Fail{AMAMG_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e)};
 }
 
-int timer_event(KernelTimer& t, size_t idx) {
+static int timer_event(KernelTimer& t, size_t idx) {
   while (t.events.size() <= idx) {
     hipEvent_t e;
     HIPCHECK(hipEventCreate(&e));
@@ -197,34 +50,59 @@ int timer_event(KernelTimer& t, size_t idx) {
   return int(idx);
 }
 
-// Start / stop recording one launch of `family` at Arnoldi step `step`.
-int timer_start(amamg_context* ctx, int family, int step, double bytes_per_rhs) {
+// Start / stop recording one launch of `family` at Arnoldi step `step` of batch `group`.
+int timer_start(amamg_context* ctx, hipStream_t s, int family, int step, int group, double bytes_per_rhs) {
   KernelTimer& t = ctx->timer;
   if (!(t.mask & (1u << family))) return -1;
-  const int e0 = timer_event(t, 2 * t.pending.size()), e1 = timer_event(t, 2 * t.pending.size() + 1);
-  HIPCHECK(hipEventRecord(t.events[e0], ctx->stream));
-  t.pending.push_back({e0, e1, step, family, bytes_per_rhs});
+  // event pairs are reused once their records have been flushed
+  size_t slot = 0;
+  for (const auto& r : t.pending) slot = std::max(slot, size_t(r.e1) + 1);
+  const int e0 = timer_event(t, slot), e1 = timer_event(t, slot + 1);
+  HIPCHECK(hipEventRecord(t.events[e0], s));
+  t.pending.push_back({e0, e1, step, family, group, bytes_per_rhs});
   return int(t.pending.size()) - 1;
 }
-void timer_stop(amamg_context* ctx, int rec) {
+void timer_stop(amamg_context* ctx, hipStream_t s, int rec) {
   if (rec < 0) return;
   KernelTimer& t = ctx->timer;
-  HIPCHECK(hipEventRecord(t.events[t.pending[rec].e1], ctx->stream));
+  HIPCHECK(hipEventRecord(t.events[t.pending[rec].e1], s));
 }
-// After a synchronisation: account the pending launches; served(step) = rhs active at that step.
-template <typename F> void timer_flush(amamg_context* ctx, F served) {
-  KernelTimer& t = ctx->timer;
-  for (const auto& r : t.pending) {
-    const int n = served(r.step);
-    if (n <= 0) continue;
-    float ms = 0.f;
-    HIPCHECK(hipEventElapsedTime(&ms, t.events[r.e0], t.events[r.e1]));
-    t.launches[r.family] += 1;
-    t.total_ms[r.family] += ms;
-    t.total_bytes[r.family] += r.bytes_per_rhs * n;
+bool finite_all(const double* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+
+void ensure_links(amamg_gauge* gg, LinkStore ls) {
+  hipStream_t s = gg->ctx->stream;
+  const int64_t n = 2 * int64_t(gg->nt) * gg->nx;
+  if (ls == LINK_F32 && gg->v32 != gg->version) {
+    if (!gg->U32) gg->U32 = gg->mem.alloc<float2>(n);
+    links_to_f32(s, gg->U, gg->U32, n);
+    gg->v32 = gg->version;
   }
-  t.pending.clear();
+  if (ls == LINK_BF16 && gg->v16 != gg->version) {
+    if (!gg->U16) gg->U16 = gg->mem.alloc<bf16c>(n);
+    links_to_bf16(s, gg->U, gg->U16, n);
+    gg->v16 = gg->version;
+  }
 }
+
+const void* link0(amamg_gauge* g, LinkStore ls) {
+  return ls == LINK_F64 ? (const void*)g->U : ls == LINK_F32 ? (const void*)g->U32 : (const void*)g->U16;
+}
+const void* link1(amamg_gauge* g, LinkStore ls) {
+  const int64_t v = int64_t(g->nt) * g->nx;
+  return ls == LINK_F64 ? (const void*)(g->U + v) : ls == LINK_F32 ? (const void*)(g->U32 + v)
+                                                                      : (const void*)(g->U16 + v);
+}
+
+
+}  // namespace rt
+}  // namespace amamg
+
+namespace {
 
 // footprint tables: postab[pos] = F index or -(1 + vcol); followed by fpos[nf]
 std::vector<int> footprint_tables(int a, int o, int b, int* nf_out) {
@@ -299,6 +177,35 @@ Geom coarse_geom_of(const Geom& g) {
   Geom c{};
   c.Lt = g.nI; c.Lx = g.nJ; c.b = g.bc; c.a = g.a; c.o = g.o;
   return c;
+}
+
+}  // namespace
+
+namespace amamg {
+namespace rt {
+
+size_t setup_bytes(int nt, int nx, const amamg_setup_params& p) {
+  const auto plan = plan_levels(nt, nx, p);
+  const int K = int(plan.size());
+  const int a = p.agg_size, o = p.overlap;
+  const int nv = (p.norm == AMAMG_NORM_TESTVEC) ? p.n_test_vectors : 0;
+  const size_t c16 = sizeof(double2), c8 = sizeof(float2);
+  size_t b = size_t(nt) * nx * 5 * 4 * c16;
+  for (int k = 0; k + 1 < K; ++k) {
+    const Geom g = make_geom(plan[k], a, o, false);
+    const Geom gc = make_geom(plan[k + 1], a, o, k + 1 == K - 1);
+    const size_t nnode = g.nnode(), ndof = g.ndof(), ndc = gc.ndof(), nnc = gc.nnode();
+    int nf = 0;
+    const std::vector<int> tabs = footprint_tables(a, o, g.b, &nf);
+    const size_t nW = size_t(g.nI) * g.nJ, nfd = size_t(nf) * g.b, ncol = g.ncol(), bc = g.bc;
+    b += nnode * 9 + size_t(nv) * ndof * c16 + tabs.size() * 4 + nW * nf * g.b * 4 + nW * 8;
+    b += nW * nfd * (nfd + ncol) * c16 + ndof * ncol * (c16 + c8);
+    b += size_t(nv) * ndc * c16 * 2;
+    b += bc * (2 * ndc + 2 * ndof) * c16 + bc * nW * restrict_chunks(g, nf, F64) * ncol * c16;
+    if (k + 1 == K - 1) b += ndc * ndc * c16 * 4;
+    else b += nnc * 25 * bc * bc * (c16 + c8) + nnc * bc * bc * (3 * c16 + c8) + nnc * 4;
+  }
+  return b;
 }
 
 // ------------------------------------------------------------------------- GPU setup
@@ -494,289 +401,8 @@ void run_setup(amamg_hierarchy* h) {
   HIPCHECK(hipStreamSynchronize(s));
 }
 
-// ---------------------------------------------------------------------------- solve
-
-void ensure_links(amamg_gauge* gg, LinkStore ls) {
-  hipStream_t s = gg->ctx->stream;
-  const int64_t n = 2 * int64_t(gg->nt) * gg->nx;
-  if (ls == LINK_F32 && gg->v32 != gg->version) {
-    if (!gg->U32) gg->U32 = gg->mem.alloc<float2>(n);
-    links_to_f32(s, gg->U, gg->U32, n);
-    gg->v32 = gg->version;
-  }
-  if (ls == LINK_BF16 && gg->v16 != gg->version) {
-    if (!gg->U16) gg->U16 = gg->mem.alloc<bf16c>(n);
-    links_to_bf16(s, gg->U, gg->U16, n);
-    gg->v16 = gg->version;
-  }
-}
-
-// Blocks per right-hand side of the Gram-Schmidt and norm kernels: about 4096 blocks in all
-// (16 per compute unit), at least 8 elements per thread once that many blocks exist (the
-// per-block reduction of the previous pass's partials is then amortised), at most one block
-// per 256 elements and at most kMaxKrylovBlocks.
-constexpr int kMaxKrylovBlocks = 256;
-int krylov_blocks(int64_t n, int nrhs) {
-  const int64_t want = std::max<int64_t>(n / 2048, (4096 + nrhs - 1) / nrhs);
-  return int(std::max<int64_t>(1, std::min<int64_t>({int64_t(kMaxKrylovBlocks), n / 256, want})));
-}
-
-void ensure_workspace(amamg_hierarchy* h, int nrhs, int m, Real prec, int hist_cap) {
-  if (h->ws_nrhs >= nrhs && h->ws_m >= m && h->ws_prec == prec && h->ws_hist >= hist_cap) return;
-  h->ws.release();
-  const int64_t n = h->lv[0].g.ndof();
-  const size_t rs = prec == F64 ? sizeof(double2) : sizeof(float2);
-  h->V = h->ws.alloc<double2>(size_t(m + 1) * nrhs * n);
-  h->Z = h->ws.alloc<char>(size_t(m) * nrhs * n * rs);
-  h->w = h->ws.alloc<double2>(size_t(nrhs) * n);
-  h->H = h->ws.alloc<double2>(size_t(nrhs) * (m + 1) * m);
-  h->g = h->ws.alloc<double2>(size_t(nrhs) * (m + 1));
-  h->cs = h->ws.alloc<double>(size_t(nrhs) * m);
-  h->sn = h->ws.alloc<double2>(size_t(nrhs) * m);
-  h->y = h->ws.alloc<double2>(size_t(nrhs) * m);
-  h->part = h->ws.alloc<double2>(size_t(3) * nrhs * kMaxKrylovBlocks * 32);
-  h->st = h->ws.alloc<RhsState>(nrhs);
-  h->hist = h->ws.alloc<double2>(size_t(nrhs) * hist_cap);
-  for (size_t k = 1; k < h->lv.size(); ++k) {
-    LevelData& L = h->lv[k];
-    const int64_t nd = L.g.ndof();
-    L.f = h->ws.alloc<char>(size_t(nrhs) * nd * rs);
-    L.x = h->ws.alloc<char>(size_t(nrhs) * nd * rs);
-    L.tmp = h->ws.alloc<char>(size_t(nrhs) * nd * rs);
-  }
-  h->lv[0].tmp = h->ws.alloc<char>(size_t(nrhs) * n * rs);
-  for (size_t k = 0; k + 1 < h->lv.size(); ++k) {
-    LevelData& L = h->lv[k];
-    L.rpart = h->ws.alloc<char>(size_t(nrhs) * L.g.nI * L.g.nJ * restrict_chunks(L.g, L.nf, prec) * L.g.ncol() * rs);
-  }
-  h->ws_nrhs = nrhs;
-  h->ws_m = m;
-  h->ws_prec = prec;
-  h->ws_hist = hist_cap;
-}
-
-
-struct SolveCtx {
-  amamg_hierarchy* h;
-  hipStream_t s;
-  Real T;
-  LinkStore smooth_links, mat_links;
-  int nrhs;
-  int step;        // Arnoldi step of the current V-cycle (kernel timer)
-};
-
-const void* link0(amamg_gauge* g, LinkStore ls) {
-  return ls == LINK_F64 ? (const void*)g->U : ls == LINK_F32 ? (const void*)g->U32 : (const void*)g->U16;
-}
-const void* link1(amamg_gauge* g, LinkStore ls) {
-  const int64_t v = int64_t(g->nt) * g->nx;
-  return ls == LINK_F64 ? (const void*)(g->U + v) : ls == LINK_F32 ? (const void*)(g->U32 + v)
-                                                                      : (const void*)(g->U16 + v);
-}
-
-// x = M_k f (V-cycle of the paper's two-level scheme, recursively; start x = 0)
-void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x) {
-  amamg_hierarchy* h = c.h;
-  LevelData& L = h->lv[k];
-  const Geom& g = L.g;
-  const int64_t nd = g.ndof();
-  const RhsState* st = h->st;
-  const bool f64 = c.T == F64;
-  if (L.coarsest) {
-    dense_apply(c.s, c.T, L.Ainv, f, x, int(nd), c.nrhs, nd, st);
-    return;
-  }
-  LevelData& C = h->lv[k + 1];
-  const int64_t ndc = C.g.ndof();
-  const void* P = f64 ? (const void*)L.P : (const void*)L.P32;
-  const int pre = h->prm.pre_sweeps, post = h->prm.post_sweeps;
-  amamg_gauge* gg = h->gauge;
-  const void* U0 = link0(gg, c.smooth_links);
-  const void* U1 = link1(gg, c.smooth_links);
-  const void* Ak = f64 ? (const void*)L.A : (const void*)L.A32;
-  const void* Dk = f64 ? (const void*)L.Dinv : (const void*)L.Dinv32;
-  const double cb = f64 ? 16.0 : 8.0;   // bytes per complex value
-  if (pre > 0) {
-    HIPCHECK(hipMemsetAsync(x, 0, nd * c.nrhs * (f64 ? 16 : 8), c.s));
-    for (int sw = 0; sw < pre; ++sw) {
-      if (k == 0)
-        for (int col = 0; col < 2; ++col)
-          wilson_gs(c.s, c.smooth_links, U0, U1, c.T, x, (const double2*)f, g.Lt, g.Lx, h->m0, col, c.nrhs, nd, st);
-      else
-        for (int col = 0; col < 16; ++col)
-          stencil_gs(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, col, c.nrhs, nd, st);
-    }
-    if (k == 0)
-      wilson_apply(c.s, c.smooth_links, U0, U1, c.T, x, c.T, L.tmp, (const double2*)f, g.Lt, g.Lx, h->m0, c.nrhs, nd, st);
-    else
-      stencil_apply(c.s, c.T, Ak, x, L.tmp, f, g.Lt, g.Lx, g.b, c.nrhs, nd, st);
-    restrict_(c.s, c.T, P, L.rows, L.nrows, L.nf, c.T, L.tmp, C.f, L.rpart, g, c.nrhs, nd, ndc, st);
-  } else {
-    const double fb = fprec == F64 ? 16 : 8;
-    const double owned = double(nd) * (1.0 - double(g.o * g.o) / double(g.a * g.a));
-    const int rec = k == 0 ? timer_start(gg->ctx, AMAMG_KT_RESTRICT0, c.step,
-                                         owned * (g.ncol() * cb + fb) + double(g.nI) * g.nJ * restrict_chunks(g, L.nf, c.T) * g.ncol() * cb)
-                           : -1;
-    restrict_(c.s, c.T, P, L.rows, L.nrows, L.nf, fprec, f, C.f, L.rpart, g, c.nrhs, nd, ndc, st);
-    timer_stop(gg->ctx, rec);
-  }
-  vcycle(c, k + 1, c.T, C.f, C.x);
-  {
-    const double owned = double(nd) * (1.0 - double(g.o * g.o) / double(g.a * g.a));
-    const int rec = k == 0 ? timer_start(gg->ctx, AMAMG_KT_PROLONG0, c.step,
-                                         owned * g.ncol() * cb + double(nd) * cb + double(ndc) * cb)
-                           : -1;
-    prolong(c.s, c.T, P, L.rows, L.nrows, L.nf, C.x, x, g, pre > 0 ? 1 : 0, c.nrhs, nd, ndc, st);
-    timer_stop(gg->ctx, rec);
-  }
-  for (int sw = 0; sw < post; ++sw) {
-    if (k == 0) {
-      const double cl = c.smooth_links == LINK_F64 ? 16 : c.smooth_links == LINK_F32 ? 8 : 4;
-      for (int col = 0; col < 2; ++col) {
-        const int rec = timer_start(gg->ctx, AMAMG_KT_FINE_GS, c.step,
-                                    double(g.nnode()) * (2 * cb + 2 * cl + 16));
-        wilson_gs(c.s, c.smooth_links, U0, U1, c.T, x, (const double2*)f, g.Lt, g.Lx, h->m0, col, c.nrhs, nd, st);
-        timer_stop(gg->ctx, rec);
-      }
-    } else {
-      for (int col = 0; col < 16; ++col) {
-        const double ncn = double(g.nnode()) / 16.0;
-        const int rec = k == 1 ? timer_start(gg->ctx, AMAMG_KT_COARSE_GS, c.step,
-                                             ncn * 25.0 * g.b * g.b * cb + double(nd) * cb + 2.0 * ncn * g.b * cb)
-                               : -1;
-        stencil_gs(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, col, c.nrhs, nd, st);
-        timer_stop(gg->ctx, rec);
-      }
-    }
-  }
-}
-
-amamg_status run_solve(amamg_hierarchy* h, int nrhs, const double2* b, double2* x,
-                       const amamg_solve_params& p, amamg_solve_info* info) {
-  amamg_gauge* gg = h->gauge;
-  hipStream_t s = gg->ctx->stream;
-  REQUIRE(nrhs >= 1, AMAMG_ERR_INVALID_ARG, "nrhs must be >= 1");
-  REQUIRE(p.restart >= 1 && p.restart <= 31, AMAMG_ERR_INVALID_ARG, "restart must be in [1, 31]");
-  REQUIRE(p.max_iters >= 1, AMAMG_ERR_INVALID_ARG, "max_iters must be >= 1");
-  REQUIRE(p.rel_tol > 0 && std::isfinite(p.rel_tol), AMAMG_ERR_INVALID_ARG, "rel_tol must be > 0");
-  REQUIRE(p.precision >= 0 && p.precision <= 2, AMAMG_ERR_INVALID_ARG, "unknown precision");
-  const int m = p.restart;
-  const Real T = p.precision == AMAMG_FP64 ? F64 : F32;
-  const int hist_cap = 2 * p.max_iters + 2;
-  ensure_workspace(h, nrhs, m, T, hist_cap);
-  SolveCtx c{h, s, T, LINK_F64, LINK_F64, nrhs, 0};
-  if (p.precision == AMAMG_MIXED_FP32) { c.smooth_links = LINK_F32; c.mat_links = LINK_F32; }
-  if (p.precision == AMAMG_MIXED_FP32_BF16LINKS) { c.smooth_links = LINK_BF16; c.mat_links = LINK_F32; }
-  ensure_links(gg, c.smooth_links);
-  ensure_links(gg, c.mat_links);
-  const double inner_tol = T == F64 ? 0.0 : 1e-5;
-
-  const int64_t n = h->lv[0].g.ndof();
-  const int nt = gg->nt, nx = gg->nx;
-  const int nblk = krylov_blocks(n, nrhs);
-  KrylovDims kd{n, nrhs, nblk, m};
-  RhsState* st = h->st;
-  const size_t zs = T == F64 ? sizeof(double2) : sizeof(float2);
-  const int64_t vsj = int64_t(nrhs) * n;   // basis stride between j
-
-  double2* p1 = h->part;
-  double2* p2 = h->part + size_t(nrhs) * nblk * 32;
-  double2* p3 = h->part + size_t(2) * nrhs * nblk * 32;
-  // ||b||; refuse non-finite input before touching x
-  norm_control(s, kd, b, p1, st, 1, h->g, p.rel_tol, p.max_iters, h->hist, hist_cap);
-  check_launch();
-  std::vector<RhsState> hs(nrhs);
-  HIPCHECK(hipMemcpyAsync(hs.data(), st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipStreamSynchronize(s));
-  for (int r = 0; r < nrhs; ++r)
-    REQUIRE(!hs[r].nonfinite, AMAMG_ERR_NONFINITE, "non-finite value in right-hand side " + std::to_string(r));
-
-  if (!p.use_initial_guess) HIPCHECK(hipMemsetAsync(x, 0, sizeof(double2) * nrhs * n, s));
-  // r = b - D x into V_0, its norm, the first cycle start, V_0 = r / ||r||
-  wilson_apply(s, LINK_F64, gg->U, gg->U + int64_t(nt) * nx, F64, x, F64, h->V, b, nt, nx, h->m0, nrhs, n, st);
-  norm_control(s, kd, h->V, p1, st, 2, h->g, p.rel_tol, p.max_iters, h->hist, hist_cap);
-  scale_next(s, kd, h->V, h->V, st);
-  check_launch();
-
-  const void* Um0 = link0(gg, c.mat_links);
-  const void* Um1 = link1(gg, c.mat_links);
-  std::vector<int> cycle_in(nrhs, 0);
-  gg->ctx->timer.pending.clear();
-  for (;;) {
-    HIPCHECK(hipMemcpyAsync(hs.data(), st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    // kernel timer: rhs served at step j of the cycle that just ended
-    timer_flush(gg->ctx, [&](int step) {
-      int cnt = 0;
-      for (int r = 0; r < nrhs; ++r) cnt += (cycle_in[r] && hs[r].last_k > step) ? 1 : 0;
-      return cnt;
-    });
-    bool any = false;
-    for (int r = 0; r < nrhs; ++r) {
-      cycle_in[r] = hs[r].in_cycle;
-      any = any || hs[r].in_cycle;
-    }
-    if (!any) break;
-    const double cl = c.mat_links == LINK_F64 ? 16 : 8;
-    for (int j = 0; j < m; ++j) {
-      double2* vj = h->V + j * vsj;
-      void* zj = (char*)h->Z + size_t(j) * vsj * zs;
-      c.step = j;
-      vcycle(c, 0, F64, vj, zj);
-      int rec = timer_start(gg->ctx, AMAMG_KT_FINE_MATVEC, j, double(nt) * nx * (2 * zs + 2 * cl + 32));
-      wilson_apply(s, c.mat_links, Um0, Um1, T, zj, F64, h->w, nullptr, nt, nx, h->m0, nrhs, n, st);
-      timer_stop(gg->ctx, rec);
-      // Gram-Schmidt: family DOTS = every V^H w pass, family UPDATE = every w -= V h pass
-      const double dot_bytes = double(j + 2) * n * 16, upd_bytes = double(j + 3) * n * 16;
-      rec = timer_start(gg->ctx, AMAMG_KT_DOTS, j, dot_bytes);
-      dots(s, kd, h->V, vsj, j + 1, h->w, p1, st);
-      timer_stop(gg->ctx, rec);
-      rec = timer_start(gg->ctx, AMAMG_KT_UPDATE, j, upd_bytes);
-      update_dots(s, kd, h->V, vsj, j + 1, h->w, p1, p2, st);
-      timer_stop(gg->ctx, rec);
-      rec = timer_start(gg->ctx, AMAMG_KT_UPDATE, j, upd_bytes);
-      update_norm(s, kd, h->V, vsj, j + 1, h->w, p2, p3, st);
-      timer_stop(gg->ctx, rec);
-      arnoldi(s, kd, p1, p2, p3, st, h->H, h->cs, h->sn, h->g, j, p.rel_tol, inner_tol, p.max_iters,
-              h->hist, hist_cap);
-      if (j + 1 < m) scale_next(s, kd, h->w, h->V + (j + 1) * vsj, st);
-      check_launch();
-    }
-    backsolve_update(s, kd, st, h->H, h->g, h->y, T, h->Z, vsj, x);
-    wilson_apply(s, LINK_F64, gg->U, gg->U + int64_t(nt) * nx, F64, x, F64, h->V, b, nt, nx, h->m0, nrhs, n, st);
-    norm_control(s, kd, h->V, p1, st, 3, h->g, p.rel_tol, p.max_iters, h->hist, hist_cap);
-    scale_next(s, kd, h->V, h->V, st);
-    check_launch();
-  }
-  // results
-  h->history.assign(nrhs, {});
-  std::vector<double2> hh(size_t(nrhs) * hist_cap);
-  HIPCHECK(hipMemcpyAsync(hh.data(), h->hist, sizeof(double2) * hh.size(), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipStreamSynchronize(s));
-  bool all_conv = true, nonfinite = false;
-  for (int r = 0; r < nrhs; ++r) {
-    h->history[r].assign(hh.begin() + size_t(r) * hist_cap, hh.begin() + size_t(r) * hist_cap + hs[r].hist_len);
-    all_conv = all_conv && hs[r].converged;
-    nonfinite = nonfinite || hs[r].nonfinite;
-    if (info) {
-      info[r].iterations = hs[r].iters;
-      info[r].restarts = hs[r].restarts;
-      info[r].converged = hs[r].converged;
-      info[r].reserved = 0;
-      info[r].true_rel_residual = hs[r].true_res;
-    }
-  }
-  REQUIRE(!nonfinite, AMAMG_ERR_NONFINITE, "non-finite value during the solve");
-  return all_conv ? AMAMG_OK : AMAMG_NOT_CONVERGED;
-}
-
-bool finite_all(const double* v, size_t n) {
-  for (size_t i = 0; i < n; ++i)
-    if (!std::isfinite(v[i])) return false;
-  return true;
-}
-
-}  // namespace
+}  // namespace rt
+}  // namespace amamg
 
 // ---------------------------------------------------------------------------------- ABI
 
@@ -793,6 +419,8 @@ void amamg_default_solve_params(amamg_solve_params* p) {
   if (!p) return;
   p->restart = 20; p->max_iters = 10000; p->rel_tol = 1e-10; p->precision = AMAMG_FP64;
   p->use_initial_guess = 0;
+  p->groups = 1;
+  p->reserved = 0;
 }
 
 amamg_status amamg_context_create(int device, void* hip_stream, amamg_context** out) {

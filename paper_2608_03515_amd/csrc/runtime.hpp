@@ -1,0 +1,269 @@
+// Host runtime of the AM-AMG library: handle types, device memory, the setup pipeline, the
+// batched FGMRES driver and the request server.  Shared by the host translation units
+// (runtime.hip: handles, setup and the C ABI; solve.hip: V-cycle and FGMRES driver;
+// server.hip: continuous-batching server).
+#pragma once
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/amamg.h"
+#include "launch.hpp"
+
+namespace amamg {
+namespace rt {
+
+struct Fail {
+  amamg_status code;
+  std::string msg;
+};
+
+#define HIPCHECK(expr)                                                                          \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess) {                                                                     \
+      if (e_ == hipErrorOutOfMemory)                                                            \
+        throw ::amamg::rt::Fail{AMAMG_ERR_OUT_OF_MEMORY, std::string(#expr) + ": out of device memory"}; \
+      throw ::amamg::rt::Fail{AMAMG_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+    }                                                                                           \
+  } while (0)
+
+#define REQUIRE(cond, code, msg)                        \
+  do {                                                  \
+    if (!(cond)) throw ::amamg::rt::Fail{code, msg};    \
+  } while (0)
+
+// Device allocations owned by a handle, released together; `bytes` counts what is held.
+struct Arena {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  template <typename T> T* alloc(size_t count) {
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    HIPCHECK(hipMalloc(&p, count * sizeof(T)));
+    ptrs.push_back(p);
+    bytes += count * sizeof(T);
+    return static_cast<T*>(p);
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+  Arena() = default;
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
+  ~Arena() { release(); }
+};
+
+// Device buffers looked up by (name, level): allocated on first use, reused afterwards, so a
+// repeated setup on the same hierarchy allocates nothing.
+struct Pool {
+  struct Item { std::string key; void* p; size_t bytes; };
+  std::vector<Item> items;
+  template <typename T> T* get(const char* name, int level, size_t count) {
+    if (count == 0) count = 1;
+    const std::string key = std::string(name) + "#" + std::to_string(level);
+    for (Item& it : items)
+      if (it.key == key) {
+        if (it.bytes >= count * sizeof(T)) return static_cast<T*>(it.p);
+        (void)hipFree(it.p);
+        it.p = nullptr;
+        HIPCHECK(hipMalloc(&it.p, count * sizeof(T)));
+        it.bytes = count * sizeof(T);
+        return static_cast<T*>(it.p);
+      }
+    void* p = nullptr;
+    HIPCHECK(hipMalloc(&p, count * sizeof(T)));
+    items.push_back({key, p, count * sizeof(T)});
+    return static_cast<T*>(p);
+  }
+  size_t bytes() const {
+    size_t s = 0;
+    for (const Item& it : items) s += it.bytes;
+    return s;
+  }
+  Pool() = default;
+  Pool(const Pool&) = delete;
+  Pool& operator=(const Pool&) = delete;
+  ~Pool() {
+    for (Item& it : items) (void)hipFree(it.p);
+  }
+};
+
+// Benchmark timer: HIP events around every launch of one kernel family in the solve.  A
+// launch's algorithmic bytes are its per-rhs bytes times the right-hand sides it served,
+// which the host learns at the end of each restart cycle of the batch (group) that ran it.
+struct KernelTimer {
+  static constexpr int NF = 8;
+  uint32_t mask = 0;
+  std::vector<hipEvent_t> events;
+  struct Rec { int e0, e1, step, family, group; double bytes_per_rhs; };
+  std::vector<Rec> pending;
+  int64_t launches[NF] = {};
+  double total_ms[NF] = {}, total_bytes[NF] = {};
+};
+
+struct LevelData {
+  Geom g{};
+  bool coarsest = false;
+  // operator of this level (k >= 1)
+  double2* A = nullptr;      // stencil [nnode][25][b][b] (non-coarsest)
+  float2* A32 = nullptr;
+  double2* Dinv = nullptr;   // [nnode][b][b]
+  float2* Dinv32 = nullptr;
+  double2* Adense = nullptr; // coarsest [n][n]
+  double2* Ainv = nullptr;   // coarsest inverse [n][n]
+  // transfer to the next level (non-coarsest)
+  int8_t* kind = nullptr;
+  int* owner = nullptr;
+  int* node = nullptr;
+  double2* P = nullptr;      // [nnode][b][4 bc]
+  float2* P32 = nullptr;
+  double2* tv = nullptr;     // smoothed test vectors [nv][ndof]
+  int* tabs = nullptr;       // footprint tables: postab [fp] then fpos [nf]
+  int nf = 0;                // F positions per wirebasket footprint
+  int* rows = nullptr;       // owned fine rows per wirebasket [nW][nf*b]
+  int* nrows = nullptr;      // their counts [nW]
+};
+
+// Everything a running batched solve writes: Krylov basis and search directions, Hessenberg
+// and Givens data, per-rhs control state and residual history, the V-cycle's per-level
+// vectors, and pinned host mirrors of the state.  `cap` right-hand-side slots.
+struct Workspace {
+  int cap = 0, m = 0, hist_cap = 0;
+  Real prec = F64;
+  Arena mem;
+  double2 *V = nullptr, *w = nullptr, *H = nullptr, *g = nullptr, *sn = nullptr, *y = nullptr;
+  double2 *part = nullptr, *hist = nullptr;
+  double* cs = nullptr;
+  void* Z = nullptr;
+  RhsState* st = nullptr;     // control state of the running batch
+  RhsState* st2 = nullptr;    // state of slots being admitted
+  int* admit = nullptr;       // admission mask [cap]
+  struct Lev { void *f = nullptr, *x = nullptr, *tmp = nullptr, *rpart = nullptr; };
+  std::vector<Lev> lv;
+  RhsState* hst = nullptr;    // pinned mirrors
+  RhsState* hst2 = nullptr;
+  int* hadmit = nullptr;
+  double2* hhist = nullptr;
+  hipEvent_t ev = nullptr;
+  Workspace() = default;
+  Workspace(const Workspace&) = delete;
+  Workspace& operator=(const Workspace&) = delete;
+  ~Workspace();
+  void release();
+};
+
+}  // namespace rt
+}  // namespace amamg
+
+struct amamg_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  amamg::rt::KernelTimer timer;
+};
+
+struct amamg_gauge {
+  amamg_context* ctx = nullptr;
+  int nt = 0, nx = 0;
+  double m0 = 0;
+  int nhier = 0;
+  amamg::rt::Arena mem;
+  double2* U = nullptr;     // [2][nt*nx]
+  float2* U32 = nullptr;
+  amamg::bf16c* U16 = nullptr;
+  int version = 0;          // bumped by amamg_gauge_update_links
+  int v32 = -1, v16 = -1;   // version the low-precision copies were made from
+};
+
+struct amamg_hierarchy {
+  amamg_gauge* gauge = nullptr;
+  amamg_setup_params prm{};
+  double m0 = 0;
+  std::vector<amamg::rt::LevelData> lv;
+  amamg::rt::Pool mem;      // setup products and setup scratch
+  // workspaces and extra streams of the plain solve calls (one per right-hand-side group)
+  std::vector<amamg::rt::Workspace*> ws;
+  std::vector<hipStream_t> streams;
+  std::vector<std::vector<double2>> history;
+  ~amamg_hierarchy();
+};
+
+namespace amamg {
+namespace rt {
+
+amamg_status fail(amamg_context* ctx, const Fail& f);
+bool aligned16(const void* p);
+void check_launch();
+bool finite_all(const double* v, size_t n);
+
+// kernel timer (the family's events are recorded on the stream `s` of the launch)
+int timer_start(amamg_context* ctx, hipStream_t s, int family, int step, int group, double bytes_per_rhs);
+void timer_stop(amamg_context* ctx, hipStream_t s, int rec);
+
+// setup (on the context stream, synchronous) with the hierarchy's mass h->m0
+void run_setup(amamg_hierarchy* h);
+// device bytes a hierarchy of these parameters holds after setup (estimate, for admission)
+size_t setup_bytes(int nt, int nx, const amamg_setup_params& p);
+
+// low-precision link copies of a gauge (made on the context stream, once per link version)
+void ensure_links(amamg_gauge* gg, LinkStore ls);
+const void* link0(amamg_gauge* g, LinkStore ls);
+const void* link1(amamg_gauge* g, LinkStore ls);
+
+// workspaces
+void ensure_workspace(Workspace& ws, const amamg_hierarchy* h, int cap, int m, Real prec, int hist_cap);
+size_t workspace_bytes(const amamg_hierarchy* h, int cap, int m, Real prec, int hist_cap);
+
+// One batched FGMRES run over a workspace on one stream, driven from the host in steps:
+// admission of slots (two host round trips: the input check, then the first cycle start),
+// then one restart cycle per step.  The host never blocks inside: after every enqueued stage
+// it records the workspace event and waits for `ready()`.
+struct Batch {
+  amamg_hierarchy* h = nullptr;
+  Workspace* ws = nullptr;
+  hipStream_t s = nullptr;
+  amamg_solve_params p{};
+  int group = 0;                // kernel-timer group
+  const double2* b = nullptr;   // [cap][n] right-hand sides
+  double2* x = nullptr;         // [cap][n] iterates
+  // host view
+  std::vector<int> cycle_in;    // slots in the cycle that was enqueued last
+  std::vector<int> pending;     // slots whose admission awaits the input check
+  bool cycle_enqueued = false;
+
+  void init(amamg_hierarchy* h, Workspace* ws, hipStream_t s, const amamg_solve_params& p,
+            const double2* b, double2* x, int group);
+  // enqueue the input check of `slots` (||b||, non-finite and zero right-hand sides)
+  void admit_begin(const std::vector<int>& slots);
+  // after ready(): slots of the pending admission whose input is non-finite
+  std::vector<int> admit_nonfinite() const;
+  // enqueue the first cycle start of the pending slots except `reject` (x = 0 unless the
+  // initial guess is used, r = b - D x, V_0 = r / ||r||) and merge them into the batch state
+  void admit_finish(const std::vector<int>& reject, bool use_initial_guess);
+  // enqueue one restart cycle for every slot in a cycle (requires a state read first)
+  void enqueue_cycle();
+  // enqueue a copy of the state to the pinned mirror and record the event
+  void enqueue_state_read();
+  bool ready() const;
+  // after ready(): host copy of the batch state (valid after enqueue_state_read)
+  const RhsState& state(int slot) const { return ws->hst[slot]; }
+  // after a state read: flush the kernel timer and note which slots are in the next cycle;
+  // returns true when some slot is in a cycle
+  bool cycle_boundary();
+  // residual history of a slot (synchronous copy on the batch stream)
+  std::vector<double2> history(int slot) const;
+};
+
+// plain solve of nrhs right-hand sides (caller's device buffers), split into `groups`
+// batches on separate streams
+amamg_status run_solve(amamg_hierarchy* h, int nrhs, const double2* b, double2* x,
+                       const amamg_solve_params& p, amamg_solve_info* info);
+
+}  // namespace rt
+}  // namespace amamg

@@ -1,0 +1,525 @@
+// Solve phase of the host runtime: the V-cycle (paper's two-level scheme applied recursively)
+// and the batched, right-preconditioned FGMRES(m) driver (paper: FGMRES outer solver to a
+// relative residual of 1e-10).
+//
+// A batch is a workspace of `cap` right-hand-side slots on one stream.  Every kernel runs over
+// all slots and skips those whose device state is inactive, so slots can be admitted at any
+// restart-cycle boundary while the others keep iterating (the server admits requests this
+// way), and a right-hand side's arithmetic does not depend on the other slots.  The host
+// reads the per-slot state once per cycle through a pinned mirror and an event; it never
+// blocks inside a batch, so several batches on several streams are driven from one thread.
+#include <algorithm>
+#include <cstring>
+
+#include "runtime.hpp"
+
+namespace amamg {
+namespace rt {
+
+// Blocks per right-hand side of the Gram-Schmidt and norm kernels: about 4096 blocks in all
+// (16 per compute unit), at least 8 elements per thread once that many blocks exist (the
+// per-block reduction of the previous pass's partials is then amortised), at most one block
+// per 256 elements and at most kMaxKrylovBlocks.
+constexpr int kMaxKrylovBlocks = 256;
+static int krylov_blocks(int64_t n, int nrhs) {
+  const int64_t want = std::max<int64_t>(n / 2048, (4096 + nrhs - 1) / nrhs);
+  return int(std::max<int64_t>(1, std::min<int64_t>({int64_t(kMaxKrylovBlocks), n / 256, want})));
+}
+
+// ------------------------------------------------------------------------------ workspace
+
+Workspace::~Workspace() { release(); }
+
+void Workspace::release() {
+  mem.release();
+  if (hst) (void)hipHostFree(hst);
+  if (hst2) (void)hipHostFree(hst2);
+  if (hadmit) (void)hipHostFree(hadmit);
+  if (hhist) (void)hipHostFree(hhist);
+  if (ev) (void)hipEventDestroy(ev);
+  hst = hst2 = nullptr;
+  hadmit = nullptr;
+  hhist = nullptr;
+  ev = nullptr;
+  lv.clear();
+  cap = m = hist_cap = 0;
+}
+
+static size_t level_rpart_count(const LevelData& L, Real prec) {
+  return size_t(L.g.nI) * L.g.nJ * restrict_chunks(L.g, L.nf, prec) * L.g.ncol();
+}
+
+size_t workspace_bytes(const amamg_hierarchy* h, int cap, int m, Real prec, int hist_cap) {
+  const int64_t n = h->lv[0].g.ndof();
+  const size_t rs = prec == F64 ? sizeof(double2) : sizeof(float2);
+  size_t b = sizeof(double2) * size_t(m + 1) * cap * n + size_t(m) * cap * n * rs +
+             sizeof(double2) * size_t(cap) * n + sizeof(double2) * size_t(cap) * (3 * (m + 1) * m / 2 + 4 * m) +
+             sizeof(double2) * size_t(3) * cap * kMaxKrylovBlocks * 32 + sizeof(double2) * size_t(cap) * hist_cap;
+  for (size_t k = 1; k < h->lv.size(); ++k) b += 3 * size_t(cap) * h->lv[k].g.ndof() * rs;
+  b += size_t(cap) * n * rs;
+  for (size_t k = 0; k + 1 < h->lv.size(); ++k) b += size_t(cap) * level_rpart_count(h->lv[k], prec) * rs;
+  return b;
+}
+
+void ensure_workspace(Workspace& ws, const amamg_hierarchy* h, int cap, int m, Real prec, int hist_cap) {
+  if (ws.cap >= cap && ws.m >= m && ws.prec == prec && ws.hist_cap >= hist_cap &&
+      ws.lv.size() == h->lv.size())
+    return;
+  ws.release();
+  const int64_t n = h->lv[0].g.ndof();
+  const size_t rs = prec == F64 ? sizeof(double2) : sizeof(float2);
+  ws.V = ws.mem.alloc<double2>(size_t(m + 1) * cap * n);
+  ws.Z = ws.mem.alloc<char>(size_t(m) * cap * n * rs);
+  ws.w = ws.mem.alloc<double2>(size_t(cap) * n);
+  ws.H = ws.mem.alloc<double2>(size_t(cap) * (m + 1) * m);
+  ws.g = ws.mem.alloc<double2>(size_t(cap) * (m + 1));
+  ws.cs = ws.mem.alloc<double>(size_t(cap) * m);
+  ws.sn = ws.mem.alloc<double2>(size_t(cap) * m);
+  ws.y = ws.mem.alloc<double2>(size_t(cap) * m);
+  ws.part = ws.mem.alloc<double2>(size_t(3) * cap * kMaxKrylovBlocks * 32);
+  ws.st = ws.mem.alloc<RhsState>(cap);
+  ws.st2 = ws.mem.alloc<RhsState>(cap);
+  ws.admit = ws.mem.alloc<int>(cap);
+  ws.hist = ws.mem.alloc<double2>(size_t(cap) * hist_cap);
+  ws.lv.assign(h->lv.size(), Workspace::Lev{});
+  for (size_t k = 1; k < h->lv.size(); ++k) {
+    const int64_t nd = h->lv[k].g.ndof();
+    ws.lv[k].f = ws.mem.alloc<char>(size_t(cap) * nd * rs);
+    ws.lv[k].x = ws.mem.alloc<char>(size_t(cap) * nd * rs);
+    ws.lv[k].tmp = ws.mem.alloc<char>(size_t(cap) * nd * rs);
+  }
+  ws.lv[0].tmp = ws.mem.alloc<char>(size_t(cap) * n * rs);
+  for (size_t k = 0; k + 1 < h->lv.size(); ++k)
+    ws.lv[k].rpart = ws.mem.alloc<char>(size_t(cap) * level_rpart_count(h->lv[k], prec) * rs);
+  HIPCHECK(hipHostMalloc((void**)&ws.hst, sizeof(RhsState) * cap, hipHostMallocDefault));
+  HIPCHECK(hipHostMalloc((void**)&ws.hst2, sizeof(RhsState) * cap, hipHostMallocDefault));
+  HIPCHECK(hipHostMalloc((void**)&ws.hadmit, sizeof(int) * cap, hipHostMallocDefault));
+  HIPCHECK(hipHostMalloc((void**)&ws.hhist, sizeof(double2) * size_t(cap) * hist_cap, hipHostMallocDefault));
+  HIPCHECK(hipEventCreateWithFlags(&ws.ev, hipEventDisableTiming));
+  // every slot starts free (inactive, done)
+  std::memset(ws.hst, 0, sizeof(RhsState) * cap);
+  for (int r = 0; r < cap; ++r) ws.hst[r].done = 1;
+  HIPCHECK(hipMemcpy(ws.st, ws.hst, sizeof(RhsState) * cap, hipMemcpyHostToDevice));
+  ws.cap = cap;
+  ws.m = m;
+  ws.prec = prec;
+  ws.hist_cap = hist_cap;
+}
+
+// ------------------------------------------------------------------------------ V-cycle
+
+struct SolveCtx {
+  amamg_hierarchy* h;
+  Workspace* ws;
+  hipStream_t s;
+  Real T;
+  LinkStore smooth_links, mat_links;
+  int nrhs;        // slots (grid extent of every launch)
+  int step;        // Arnoldi step of the current V-cycle (kernel timer)
+  int group;       // kernel-timer group
+};
+
+// x = M_k f (V-cycle of the paper's two-level scheme, recursively; start x = 0)
+static void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x) {
+  amamg_hierarchy* h = c.h;
+  LevelData& L = h->lv[k];
+  Workspace::Lev& WL = c.ws->lv[k];
+  const Geom& g = L.g;
+  const int64_t nd = g.ndof();
+  const RhsState* st = c.ws->st;
+  const bool f64 = c.T == F64;
+  if (L.coarsest) {
+    dense_apply(c.s, c.T, L.Ainv, f, x, int(nd), c.nrhs, nd, st);
+    return;
+  }
+  LevelData& C = h->lv[k + 1];
+  Workspace::Lev& WC = c.ws->lv[k + 1];
+  const int64_t ndc = C.g.ndof();
+  const void* P = f64 ? (const void*)L.P : (const void*)L.P32;
+  const int pre = h->prm.pre_sweeps, post = h->prm.post_sweeps;
+  amamg_gauge* gg = h->gauge;
+  amamg_context* ctx = gg->ctx;
+  const void* U0 = link0(gg, c.smooth_links);
+  const void* U1 = link1(gg, c.smooth_links);
+  const void* Ak = f64 ? (const void*)L.A : (const void*)L.A32;
+  const void* Dk = f64 ? (const void*)L.Dinv : (const void*)L.Dinv32;
+  const double cb = f64 ? 16.0 : 8.0;   // bytes per complex value
+  if (pre > 0) {
+    HIPCHECK(hipMemsetAsync(x, 0, nd * c.nrhs * (f64 ? 16 : 8), c.s));
+    for (int sw = 0; sw < pre; ++sw) {
+      if (k == 0)
+        for (int col = 0; col < 2; ++col)
+          wilson_gs(c.s, c.smooth_links, U0, U1, c.T, x, (const double2*)f, g.Lt, g.Lx, h->m0, col, c.nrhs, nd, st);
+      else
+        for (int col = 0; col < 16; ++col)
+          stencil_gs(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, col, c.nrhs, nd, st);
+    }
+    if (k == 0)
+      wilson_apply(c.s, c.smooth_links, U0, U1, c.T, x, c.T, WL.tmp, (const double2*)f, g.Lt, g.Lx, h->m0, c.nrhs, nd, st);
+    else
+      stencil_apply(c.s, c.T, Ak, x, WL.tmp, f, g.Lt, g.Lx, g.b, c.nrhs, nd, st);
+    restrict_(c.s, c.T, P, L.rows, L.nrows, L.nf, c.T, WL.tmp, WC.f, WL.rpart, g, c.nrhs, nd, ndc, st);
+  } else {
+    const double fb = fprec == F64 ? 16 : 8;
+    const double owned = double(nd) * (1.0 - double(g.o * g.o) / double(g.a * g.a));
+    const int rec = k == 0 ? timer_start(ctx, c.s, AMAMG_KT_RESTRICT0, c.step, c.group,
+                                         owned * (g.ncol() * cb + fb) + double(g.nI) * g.nJ * restrict_chunks(g, L.nf, c.T) * g.ncol() * cb)
+                           : -1;
+    restrict_(c.s, c.T, P, L.rows, L.nrows, L.nf, fprec, f, WC.f, WL.rpart, g, c.nrhs, nd, ndc, st);
+    timer_stop(ctx, c.s, rec);
+  }
+  vcycle(c, k + 1, c.T, WC.f, WC.x);
+  {
+    const double owned = double(nd) * (1.0 - double(g.o * g.o) / double(g.a * g.a));
+    const int rec = k == 0 ? timer_start(ctx, c.s, AMAMG_KT_PROLONG0, c.step, c.group,
+                                         owned * g.ncol() * cb + double(nd) * cb + double(ndc) * cb)
+                           : -1;
+    prolong(c.s, c.T, P, L.rows, L.nrows, L.nf, WC.x, x, g, pre > 0 ? 1 : 0, c.nrhs, nd, ndc, st);
+    timer_stop(ctx, c.s, rec);
+  }
+  for (int sw = 0; sw < post; ++sw) {
+    if (k == 0) {
+      const double cl = c.smooth_links == LINK_F64 ? 16 : c.smooth_links == LINK_F32 ? 8 : 4;
+      for (int col = 0; col < 2; ++col) {
+        const int rec = timer_start(ctx, c.s, AMAMG_KT_FINE_GS, c.step, c.group,
+                                    double(g.nnode()) * (2 * cb + 2 * cl + 16));
+        wilson_gs(c.s, c.smooth_links, U0, U1, c.T, x, (const double2*)f, g.Lt, g.Lx, h->m0, col, c.nrhs, nd, st);
+        timer_stop(ctx, c.s, rec);
+      }
+    } else {
+      for (int col = 0; col < 16; ++col) {
+        const double ncn = double(g.nnode()) / 16.0;
+        const int rec = k == 1 ? timer_start(ctx, c.s, AMAMG_KT_COARSE_GS, c.step, c.group,
+                                             ncn * 25.0 * g.b * g.b * cb + double(nd) * cb + 2.0 * ncn * g.b * cb)
+                               : -1;
+        stencil_gs(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, col, c.nrhs, nd, st);
+        timer_stop(ctx, c.s, rec);
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------------------------- batch
+
+static void check_solve_params(const amamg_solve_params& p) {
+  REQUIRE(p.restart >= 1 && p.restart <= 31, AMAMG_ERR_INVALID_ARG, "restart must be in [1, 31]");
+  REQUIRE(p.max_iters >= 1, AMAMG_ERR_INVALID_ARG, "max_iters must be >= 1");
+  REQUIRE(p.rel_tol > 0 && std::isfinite(p.rel_tol), AMAMG_ERR_INVALID_ARG, "rel_tol must be > 0");
+  REQUIRE(p.precision >= 0 && p.precision <= 2, AMAMG_ERR_INVALID_ARG, "unknown precision");
+  REQUIRE(p.groups >= 0 && p.groups <= 16, AMAMG_ERR_INVALID_ARG, "groups must be in [0, 16]");
+}
+
+static SolveCtx make_ctx(const Batch& bt) {
+  SolveCtx c{bt.h, bt.ws, bt.s, bt.p.precision == AMAMG_FP64 ? F64 : F32, LINK_F64, LINK_F64,
+             bt.ws->cap, 0, bt.group};
+  if (bt.p.precision == AMAMG_MIXED_FP32) { c.smooth_links = LINK_F32; c.mat_links = LINK_F32; }
+  if (bt.p.precision == AMAMG_MIXED_FP32_BF16LINKS) { c.smooth_links = LINK_BF16; c.mat_links = LINK_F32; }
+  return c;
+}
+
+static KrylovDims dims(const Batch& bt) {
+  const int64_t n = bt.h->lv[0].g.ndof();
+  return KrylovDims{n, bt.ws->cap, krylov_blocks(n, bt.ws->cap), bt.p.restart};
+}
+
+void Batch::init(amamg_hierarchy* h_, Workspace* ws_, hipStream_t s_, const amamg_solve_params& p_,
+                 const double2* b_, double2* x_, int group_) {
+  h = h_; ws = ws_; s = s_; p = p_; b = b_; x = x_; group = group_;
+  cycle_in.assign(ws->cap, 0);
+  pending.clear();
+  cycle_enqueued = false;
+  const SolveCtx c = make_ctx(*this);
+  ensure_links(h->gauge, c.smooth_links);
+  ensure_links(h->gauge, c.mat_links);
+  // the links' copies are made on the context stream
+  if (s != h->gauge->ctx->stream) {
+    HIPCHECK(hipEventRecord(ws->ev, h->gauge->ctx->stream));
+    HIPCHECK(hipStreamWaitEvent(s, ws->ev, 0));
+  }
+}
+
+void Batch::admit_begin(const std::vector<int>& slots) {
+  const KrylovDims kd = dims(*this);
+  std::memset(ws->hst2, 0, sizeof(RhsState) * ws->cap);
+  for (int r = 0; r < ws->cap; ++r) ws->hadmit[r] = 0;
+  for (int r : slots) {
+    ws->hst2[r].active = 1;
+    ws->hadmit[r] = 1;
+  }
+  pending = slots;
+  HIPCHECK(hipMemcpyAsync(ws->st2, ws->hst2, sizeof(RhsState) * ws->cap, hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(ws->admit, ws->hadmit, sizeof(int) * ws->cap, hipMemcpyHostToDevice, s));
+  // ||b|| and fresh states of the admitted slots; non-finite input is refused before x is touched
+  norm_control(s, kd, b, ws->part, ws->st2, 1, ws->g, p.rel_tol, p.max_iters, ws->hist, ws->hist_cap);
+  check_launch();
+  HIPCHECK(hipMemcpyAsync(ws->hst2, ws->st2, sizeof(RhsState) * ws->cap, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipEventRecord(ws->ev, s));
+}
+
+std::vector<int> Batch::admit_nonfinite() const {
+  std::vector<int> out;
+  for (int r : pending)
+    if (ws->hst2[r].nonfinite) out.push_back(r);
+  return out;
+}
+
+void Batch::admit_finish(const std::vector<int>& reject, bool use_initial_guess) {
+  const KrylovDims kd = dims(*this);
+  const int64_t n = kd.n;
+  bool any = false;
+  for (int r : pending) {
+    if (std::find(reject.begin(), reject.end(), r) != reject.end()) {
+      ws->hst2[r].active = 0;     // excluded: the slot stays free
+      ws->hadmit[r] = 0;
+      continue;
+    }
+    any = true;
+    if (!use_initial_guess) HIPCHECK(hipMemsetAsync(x + int64_t(r) * n, 0, sizeof(double2) * n, s));
+  }
+  pending.clear();
+  if (!any) return;
+  if (!reject.empty()) {
+    HIPCHECK(hipMemcpyAsync(ws->st2, ws->hst2, sizeof(RhsState) * ws->cap, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(ws->admit, ws->hadmit, sizeof(int) * ws->cap, hipMemcpyHostToDevice, s));
+  }
+  amamg_gauge* gg = h->gauge;
+  // r = b - D x into V_0, its norm, the first cycle start, V_0 = r / ||r||
+  wilson_apply(s, LINK_F64, gg->U, gg->U + int64_t(gg->nt) * gg->nx, F64, x, F64, ws->V, b, gg->nt, gg->nx,
+               h->m0, ws->cap, n, ws->st2);
+  norm_control(s, kd, ws->V, ws->part, ws->st2, 2, ws->g, p.rel_tol, p.max_iters, ws->hist, ws->hist_cap);
+  scale_next(s, kd, ws->V, ws->V, ws->st2);
+  merge_states(s, ws->st, ws->st2, ws->admit, ws->cap);
+  check_launch();
+}
+
+void Batch::enqueue_state_read() {
+  HIPCHECK(hipMemcpyAsync(ws->hst, ws->st, sizeof(RhsState) * ws->cap, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipEventRecord(ws->ev, s));
+}
+
+bool Batch::ready() const {
+  const hipError_t e = hipEventQuery(ws->ev);
+  if (e == hipSuccess) return true;
+  if (e == hipErrorNotReady) return false;
+  throw Fail{AMAMG_ERR_DEVICE, std::string("hipEventQuery: ") + hipGetErrorString(e)};
+}
+
+// After a synchronisation: account the pending launches of this group; served(step) = rhs
+// active at that step.
+template <typename F> static void timer_flush(amamg_context* ctx, int group, F served) {
+  KernelTimer& t = ctx->timer;
+  size_t keep = 0;
+  for (size_t i = 0; i < t.pending.size(); ++i) {
+    const auto r = t.pending[i];
+    if (r.group != group) {
+      t.pending[keep++] = r;
+      continue;
+    }
+    const int n = served(r.step);
+    if (n <= 0) continue;
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, t.events[r.e0], t.events[r.e1]));
+    t.launches[r.family] += 1;
+    t.total_ms[r.family] += ms;
+    t.total_bytes[r.family] += r.bytes_per_rhs * n;
+  }
+  t.pending.resize(keep);
+}
+
+bool Batch::cycle_boundary() {
+  amamg_context* ctx = h->gauge->ctx;
+  if (cycle_enqueued)
+    timer_flush(ctx, group, [&](int step) {
+      int cnt = 0;
+      for (int r = 0; r < ws->cap; ++r) cnt += (cycle_in[r] && ws->hst[r].last_k > step) ? 1 : 0;
+      return cnt;
+    });
+  cycle_enqueued = false;
+  bool any = false;
+  for (int r = 0; r < ws->cap; ++r) {
+    cycle_in[r] = ws->hst[r].in_cycle;
+    any = any || ws->hst[r].in_cycle;
+  }
+  return any;
+}
+
+void Batch::enqueue_cycle() {
+  SolveCtx c = make_ctx(*this);
+  const KrylovDims kd = dims(*this);
+  const int64_t n = kd.n, vsj = int64_t(ws->cap) * n;
+  const int m = p.restart;
+  const Real T = c.T;
+  const size_t zs = T == F64 ? sizeof(double2) : sizeof(float2);
+  amamg_gauge* gg = h->gauge;
+  amamg_context* ctx = gg->ctx;
+  RhsState* st = ws->st;
+  const int nt = gg->nt, nx = gg->nx;
+  const double inner_tol = T == F64 ? 0.0 : 1e-5;
+  double2* p1 = ws->part;
+  double2* p2 = ws->part + size_t(ws->cap) * kd.nblk * 32;
+  double2* p3 = ws->part + size_t(2) * ws->cap * kd.nblk * 32;
+  const void* Um0 = link0(gg, c.mat_links);
+  const void* Um1 = link1(gg, c.mat_links);
+  const double cl = c.mat_links == LINK_F64 ? 16 : 8;
+  for (int j = 0; j < m; ++j) {
+    double2* vj = ws->V + j * vsj;
+    void* zj = (char*)ws->Z + size_t(j) * vsj * zs;
+    c.step = j;
+    vcycle(c, 0, F64, vj, zj);
+    int rec = timer_start(ctx, s, AMAMG_KT_FINE_MATVEC, j, group, double(nt) * nx * (2 * zs + 2 * cl + 32));
+    wilson_apply(s, c.mat_links, Um0, Um1, T, zj, F64, ws->w, nullptr, nt, nx, h->m0, ws->cap, n, st);
+    timer_stop(ctx, s, rec);
+    // Gram-Schmidt: family DOTS = every V^H w pass, family UPDATE = every w -= V h pass
+    const double dot_bytes = double(j + 2) * n * 16, upd_bytes = double(j + 3) * n * 16;
+    rec = timer_start(ctx, s, AMAMG_KT_DOTS, j, group, dot_bytes);
+    dots(s, kd, ws->V, vsj, j + 1, ws->w, p1, st);
+    timer_stop(ctx, s, rec);
+    rec = timer_start(ctx, s, AMAMG_KT_UPDATE, j, group, upd_bytes);
+    update_dots(s, kd, ws->V, vsj, j + 1, ws->w, p1, p2, st);
+    timer_stop(ctx, s, rec);
+    rec = timer_start(ctx, s, AMAMG_KT_UPDATE, j, group, upd_bytes);
+    update_norm(s, kd, ws->V, vsj, j + 1, ws->w, p2, p3, st);
+    timer_stop(ctx, s, rec);
+    arnoldi(s, kd, p1, p2, p3, st, ws->H, ws->cs, ws->sn, ws->g, j, p.rel_tol, inner_tol, p.max_iters,
+            ws->hist, ws->hist_cap);
+    if (j + 1 < m) scale_next(s, kd, ws->w, ws->V + (j + 1) * vsj, st);
+    check_launch();
+  }
+  backsolve_update(s, kd, st, ws->H, ws->g, ws->y, T, ws->Z, vsj, x);
+  wilson_apply(s, LINK_F64, gg->U, gg->U + int64_t(nt) * nx, F64, x, F64, ws->V, b, nt, nx, h->m0, ws->cap, n, st);
+  norm_control(s, kd, ws->V, p1, st, 3, ws->g, p.rel_tol, p.max_iters, ws->hist, ws->hist_cap);
+  scale_next(s, kd, ws->V, ws->V, st);
+  check_launch();
+  cycle_enqueued = true;
+}
+
+std::vector<double2> Batch::history(int slot) const {
+  const int len = std::min(ws->hst[slot].hist_len, ws->hist_cap);
+  std::vector<double2> out(len);
+  if (len > 0) {
+    HIPCHECK(hipMemcpyAsync(out.data(), ws->hist + int64_t(slot) * ws->hist_cap, sizeof(double2) * len,
+                            hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+  }
+  return out;
+}
+
+// --------------------------------------------------------------------------- plain solve
+
+// Drive the batches until every one has finished; blocks on the oldest outstanding event
+// when no batch can advance.
+amamg_status run_solve(amamg_hierarchy* h, int nrhs, const double2* b, double2* x,
+                       const amamg_solve_params& p, amamg_solve_info* info) {
+  REQUIRE(nrhs >= 1, AMAMG_ERR_INVALID_ARG, "nrhs must be >= 1");
+  check_solve_params(p);
+  amamg_context* ctx = h->gauge->ctx;
+  const int G = std::max(1, std::min(p.groups, nrhs));
+  const int64_t n = h->lv[0].g.ndof();
+  const Real T = p.precision == AMAMG_FP64 ? F64 : F32;
+  const int hist_cap = 2 * p.max_iters + 2;
+  while (int(h->ws.size()) < G) h->ws.push_back(new Workspace());
+  while (int(h->streams.size()) < G - 1) {
+    hipStream_t sx;
+    HIPCHECK(hipStreamCreateWithFlags(&sx, hipStreamNonBlocking));
+    h->streams.push_back(sx);
+  }
+  // group g: right-hand sides [off[g], off[g + 1])
+  std::vector<int> off(G + 1, 0);
+  for (int g = 0; g < G; ++g) off[g + 1] = off[g] + nrhs / G + (g < nrhs % G ? 1 : 0);
+  std::vector<Batch> bt(G);
+  ctx->timer.pending.clear();
+  for (int g = 0; g < G; ++g) {
+    const int q = off[g + 1] - off[g];
+    Workspace& ws = *h->ws[g];
+    // a workspace is reused only at exactly this slot count: the reduction blocking depends on it
+    if (ws.cap != q) ws.release();
+    ensure_workspace(ws, h, q, p.restart, T, hist_cap);
+  }
+  for (int g = 0; g < G; ++g) {
+    hipStream_t s = g == 0 ? ctx->stream : h->streams[g - 1];
+    bt[g].init(h, h->ws[g], s, p, b + int64_t(off[g]) * n, x + int64_t(off[g]) * n, g);
+  }
+  // phase 1: input check of every group; a non-finite right-hand side fails the whole call
+  // before any x is written
+  std::vector<int> all;
+  for (int g = 0; g < G; ++g) {
+    all.resize(off[g + 1] - off[g]);
+    for (size_t r = 0; r < all.size(); ++r) all[r] = int(r);
+    bt[g].admit_begin(all);
+  }
+  try {
+    for (int g = 0; g < G; ++g) HIPCHECK(hipEventSynchronize(h->ws[g]->ev));
+    for (int g = 0; g < G; ++g) {
+      const std::vector<int> bad = bt[g].admit_nonfinite();
+      REQUIRE(bad.empty(), AMAMG_ERR_NONFINITE,
+              "non-finite value in right-hand side " + std::to_string(off[g] + (bad.empty() ? 0 : bad[0])));
+    }
+    for (int g = 0; g < G; ++g) {
+      bt[g].admit_finish({}, p.use_initial_guess != 0);
+      bt[g].enqueue_state_read();
+    }
+    // phase 2: restart cycles, each batch advanced as soon as its last state read has landed
+    std::vector<int> done(G, 0);
+    std::vector<uint64_t> stamp(G, 0);
+    uint64_t clock = 0;
+    int left = G;
+    while (left > 0) {
+      bool progressed = false;
+      for (int g = 0; g < G; ++g) {
+        if (done[g] || !bt[g].ready()) continue;
+        progressed = true;
+        if (!bt[g].cycle_boundary()) {
+          done[g] = 1;
+          --left;
+          continue;
+        }
+        bt[g].enqueue_cycle();
+        bt[g].enqueue_state_read();
+        stamp[g] = ++clock;
+      }
+      if (!progressed) {
+        int oldest = -1;
+        for (int g = 0; g < G; ++g)
+          if (!done[g] && (oldest < 0 || stamp[g] < stamp[oldest])) oldest = g;
+        HIPCHECK(hipEventSynchronize(h->ws[oldest]->ev));
+      }
+    }
+  } catch (...) {
+    for (int g = 0; g < G; ++g) (void)hipStreamSynchronize(bt[g].s);
+    throw;
+  }
+  // results
+  h->history.assign(nrhs, {});
+  bool all_conv = true, nonfinite = false;
+  for (int g = 0; g < G; ++g) {
+    Workspace& ws = *h->ws[g];
+    const int q = off[g + 1] - off[g];
+    HIPCHECK(hipMemcpyAsync(ws.hhist, ws.hist, sizeof(double2) * size_t(q) * ws.hist_cap, hipMemcpyDeviceToHost, bt[g].s));
+    HIPCHECK(hipStreamSynchronize(bt[g].s));
+    for (int r = 0; r < q; ++r) {
+      const RhsState& s = ws.hst[r];
+      const double2* hh = ws.hhist + size_t(r) * ws.hist_cap;
+      h->history[off[g] + r].assign(hh, hh + std::min(s.hist_len, ws.hist_cap));
+      all_conv = all_conv && s.converged;
+      nonfinite = nonfinite || s.nonfinite;
+      if (info) {
+        amamg_solve_info& o = info[off[g] + r];
+        o.iterations = s.iters;
+        o.restarts = s.restarts;
+        o.converged = s.converged;
+        o.reserved = 0;
+        o.true_rel_residual = s.true_res;
+      }
+    }
+  }
+  REQUIRE(!nonfinite, AMAMG_ERR_NONFINITE, "non-finite value during the solve");
+  return all_conv ? AMAMG_OK : AMAMG_NOT_CONVERGED;
+}
+
+}  // namespace rt
+}  // namespace amamg
+
+amamg_hierarchy::~amamg_hierarchy() {
+  for (auto* w : ws) delete w;
+  for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+}

@@ -45,10 +45,39 @@ def test_default_params_and_no_device_errors():
             amamg.Context(0)
 
 
+def _c_layouts(structs):
+    """sizeof and field offsets of header structs, from a C program compiled against it."""
+    import subprocess
+    import tempfile
+    body = []
+    for cname, fields in structs:
+        body.append(f'printf("{cname} %zu", sizeof({cname}));')
+        for f in fields:
+            body.append(f'printf(" %zu", offsetof({cname}, {f}));')
+        body.append('printf("\\n");')
+    src = ("#include <stddef.h>\n#include <stdio.h>\n#include \"amamg.h\"\nint main(void) {\n"
+           + "\n".join(body) + "\nreturn 0;\n}\n")
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "layout.c"), os.path.join(d, "layout")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    return {ln.split()[0]: [int(v) for v in ln.split()[1:]] for ln in out.splitlines()}
+
+
 def test_struct_layouts_match_header():
+    """Every ctypes structure of the binding has the header's size and field offsets."""
+    import shutil
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
     from paper_2608_03515_amd import amamg
-    if not os.path.exists(LIB):
-        pytest.skip("library not built")
-    assert ctypes.sizeof(amamg.SetupParams) == 8 * 4 + 8
-    assert ctypes.sizeof(amamg.SolveParams) == 4 + 4 + 8 + 4 + 4
-    assert ctypes.sizeof(amamg.SolveInfo) == 16 + 8
+    pairs = [("amamg_setup_params", amamg.SetupParams), ("amamg_solve_params", amamg.SolveParams),
+             ("amamg_solve_info", amamg.SolveInfo)]
+    for extra in ("ServerParams", "RequestInfo"):
+        if hasattr(amamg, extra):
+            pairs.append(({"ServerParams": "amamg_server_params", "RequestInfo": "amamg_request_info"}[extra],
+                          getattr(amamg, extra)))
+    c = _c_layouts([(cname, [f[0] for f in cls._fields_]) for cname, cls in pairs])
+    for cname, cls in pairs:
+        want = [ctypes.sizeof(cls)] + [getattr(cls, f[0]).offset for f in cls._fields_]
+        assert c[cname] == want, (cname, c[cname], want)

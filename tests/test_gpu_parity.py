@@ -266,6 +266,30 @@ def test_batched_rhs_equal_to_single(lib, ctx):
     g.close()
 
 
+def test_grouped_streams_equal_to_one_batch(lib, ctx):
+    """groups > 1 splits the right-hand sides over batches on separate streams; each rhs's
+    arithmetic is independent of the others (same reduction blocking at this size), so the
+    solutions, iteration counts and histories are bitwise those of the single batch."""
+    w = synth.WORKLOADS["C2"]
+    m0 = synth.critical_masses()["C2"] + w.gaps[1]
+    psi = synth.gaussian_rhs(w.L, w.L, 91, nrhs=5)
+    g = make_gauge(lib, ctx, w.links(), m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=4, overlap=1, n_test_vectors=8))
+    for prec in (lib.FP64, lib.MIXED_FP32):
+        say("groups", prec)
+        x1, i1, _ = h.solve(synth.field_to_abi(psi), lib.default_solve_params(precision=prec, groups=1))
+        hist1 = [h.residual_history(r) for r in range(5)]
+        for G in (2, 3):
+            xg, ig, _ = h.solve(synth.field_to_abi(psi), lib.default_solve_params(precision=prec, groups=G))
+            assert [i.iterations for i in ig] == [i.iterations for i in i1]
+            assert np.array_equal(xg, x1)
+            for r in range(5):
+                v, f = h.residual_history(r)
+                assert np.array_equal(v, hist1[r][0]) and np.array_equal(f, hist1[r][1])
+    h.close()
+    g.close()
+
+
 def test_invalid_shapes_and_args(lib, ctx):
     U = np.ones((2, 16, 16), dtype=complex)
     g = make_gauge(lib, ctx, U, 0.1)
