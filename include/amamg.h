@@ -40,6 +40,7 @@ extern "C" {
 typedef enum {
   AMAMG_OK = 0,
   AMAMG_NOT_CONVERGED = 1,            /* iteration cap reached; outputs valid              */
+  AMAMG_PENDING = 2,                  /* server: requests still outstanding at the timeout */
   AMAMG_ERR_INVALID_ARG = -1,         /* null pointer, bad enum, handle misuse            */
   AMAMG_ERR_UNSUPPORTED_SHAPE = -2,   /* odd lattice, a does not divide L, o >= a, ...      */
   AMAMG_ERR_OUT_OF_MEMORY = -3,
@@ -202,6 +203,84 @@ amamg_status amamg_get_prolongator(const amamg_hierarchy *h, int32_t level, doub
 amamg_status amamg_get_coarse_operator(const amamg_hierarchy *h, int32_t level, double *out);
 /* Smoothed test vectors of level `level`: double [n_test_vectors][lt*lx*b][2]. */
 amamg_status amamg_get_test_vectors(const amamg_hierarchy *h, int32_t level, double *out);
+
+/* ---- serving: continuous batching of solve requests ------------------------------------
+ *
+ * A server owns its device objects (a context on `device`, the gauge fields added to it, the
+ * AM-AMG hierarchies it builds, solver instances) and one worker thread that drives them.
+ * A request asks for D(m0) x = psi on one of the server's gauge fields, with the given setup
+ * parameters (aggregate size, overlap, levels, ...; Multilevel approach and SM-AMG sections),
+ * for 1..slots right-hand sides; solve parameters (precision, restart, tolerance, cap) are the
+ * server's.  Hierarchies are built on first use per (gauge, m0, setup parameters), kept
+ * resident and evicted least recently used when the device-memory budget would be exceeded.
+ * Each solver instance is a batch of `slots` right-hand-side slots on its own HIP stream,
+ * bound to one hierarchy; requests join a running instance at its next restart-cycle
+ * boundary as slots free up (continuous batching), and instances bound to different
+ * hierarchies run concurrently.  A right-hand side's arithmetic does not depend on the other
+ * requests: results are bitwise the same alone and in any mix.
+ *
+ * Threading: every server call may be made from any thread.  Ownership: psi is copied at
+ * submission; x (host, [nrhs][nt][nx][2][2] double) must stay valid until the request is
+ * returned by amamg_server_poll.  Errors of one request (non-finite input, failed setup,
+ * budget too small for it) are reported in its amamg_request_info.status; a device failure
+ * fails every request in flight. */
+typedef struct amamg_server amamg_server;
+
+typedef struct {
+  int32_t slots;               /* right-hand-side slots per solver instance (default 16, <= 256) */
+  int32_t max_instances;       /* solver instances, one HIP stream each (default 4, <= 16)      */
+  int32_t precision;           /* amamg_precision of every solve (default AMAMG_MIXED_FP32)     */
+  int32_t restart;             /* FGMRES(m) (default 20)                                        */
+  int32_t max_iters;           /* Arnoldi steps per right-hand side (default 10000)             */
+  int32_t reserved;
+  double rel_tol;              /* default 1e-10                                                 */
+  uint64_t hbm_budget;         /* device bytes for hierarchies and instance workspaces;         */
+                               /* 0 = three quarters of the free memory at creation           */
+} amamg_server_params;
+
+typedef struct {
+  uint64_t id;                 /* from amamg_server_submit                                      */
+  int32_t status;              /* AMAMG_OK, AMAMG_NOT_CONVERGED or a negative error             */
+  int32_t nrhs;
+  int32_t iterations;          /* maximum over its right-hand sides                             */
+  int32_t converged;           /* 1 if every right-hand side converged                          */
+  double true_rel_residual;    /* maximum over its right-hand sides                             */
+  double t_submit, t_admit, t_done;   /* server clock, seconds                                  */
+  int32_t instance;            /* solver instance that ran it (-1: never admitted)              */
+  int32_t hierarchy_built;     /* 1 if its admission built a hierarchy                          */
+} amamg_request_info;
+
+typedef struct {
+  int64_t setups, evictions;   /* hierarchies built and evicted so far                         */
+  uint64_t resident_bytes;     /* hierarchies + instance workspaces now                        */
+  uint64_t hierarchy_bytes;    /* of which cached hierarchies                                  */
+  uint64_t peak_resident_bytes;
+  uint64_t budget_bytes;
+  int64_t outstanding;         /* submitted, not yet finished                                   */
+  double clock;                /* server clock now, seconds                                     */
+  uint64_t last_estimate_bytes;/* bytes reserved for the last hierarchy build (setup and         */
+                               /* instance workspace, before trimming the setup scratch)       */
+} amamg_server_counters;
+
+void amamg_server_default_params(amamg_server_params *p);
+amamg_status amamg_server_create(int32_t device, const amamg_server_params *params,
+                                 amamg_server **out);
+/* Finishes every submitted request, then releases everything. */
+amamg_status amamg_server_destroy(amamg_server *s);
+/* Copy a gauge field (layout above) to the device; gauge_id names it in requests. */
+amamg_status amamg_server_add_gauge(amamg_server *s, int32_t nt, int32_t nx, const double *links,
+                                    int32_t *gauge_id);
+/* Queue a request; setup NULL = amamg_default_setup_params. */
+amamg_status amamg_server_submit(amamg_server *s, int32_t gauge_id, double m0,
+                                 const amamg_setup_params *setup, int32_t nrhs, const double *psi,
+                                 double *x, uint64_t *request_id);
+/* Hand back up to `capacity` finished requests (oldest first); their x is written. */
+amamg_status amamg_server_poll(amamg_server *s, amamg_request_info *out, int32_t capacity,
+                               int32_t *n_written);
+/* Block until no request is outstanding (AMAMG_OK) or timeout_s passed (AMAMG_PENDING). */
+amamg_status amamg_server_wait(amamg_server *s, double timeout_s);
+amamg_status amamg_server_stats(amamg_server *s, amamg_server_counters *out);
+const char *amamg_server_last_error(amamg_server *s);
 
 #ifdef __cplusplus
 }

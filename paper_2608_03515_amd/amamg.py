@@ -20,12 +20,13 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2608_03515_amd.build")
 _lib = C.CDLL(LIB_PATH)
 
-OK, NOT_CONVERGED = 0, 1
+OK, NOT_CONVERGED, PENDING = 0, 1, 2
 FP64, MIXED_FP32, MIXED_FP32_BF16LINKS = 0, 1, 2
 NORM_TESTVEC, NORM_CONST, NORM_NONE = 0, 1, 2
-STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARG", -2: "UNSUPPORTED_SHAPE",
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "INVALID_ARG", -2: "UNSUPPORTED_SHAPE",
                 -3: "OUT_OF_MEMORY", -4: "DEVICE", -5: "SINGULAR_LOCAL",
                 -6: "SINGULAR_COARSEST", -7: "NONFINITE"}
+STATUS_CODES = {v: k for k, v in STATUS_NAMES.items()}
 
 EXPORTED = ["amamg_default_setup_params", "amamg_default_solve_params", "amamg_context_create",
             "amamg_context_destroy", "amamg_last_error", "amamg_gauge_load",
@@ -34,7 +35,10 @@ EXPORTED = ["amamg_default_setup_params", "amamg_default_solve_params", "amamg_c
             "amamg_residual_history", "amamg_apply_dirac", "amamg_apply_dirac_device",
             "amamg_level_info",
             "amamg_get_aggregates", "amamg_get_prolongator", "amamg_get_coarse_operator",
-            "amamg_get_test_vectors", "amamg_kernel_timer", "amamg_kernel_timer_read"]
+            "amamg_get_test_vectors", "amamg_kernel_timer", "amamg_kernel_timer_read",
+            "amamg_server_default_params", "amamg_server_create", "amamg_server_destroy",
+            "amamg_server_add_gauge", "amamg_server_submit", "amamg_server_poll", "amamg_server_wait",
+            "amamg_server_stats", "amamg_server_last_error"]
 KT = {"off": 0, "fine_matvec": 1, "fine_gs": 2, "restrict0": 3, "prolong0": 4, "coarse_gs": 5,
       "dots": 6, "update": 7}
 
@@ -55,6 +59,26 @@ class SolveParams(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
                 ("reserved", C.c_int32), ("true_rel_residual", C.c_double)]
+
+
+class ServerParams(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("max_instances", C.c_int32), ("precision", C.c_int32),
+                ("restart", C.c_int32), ("max_iters", C.c_int32), ("reserved", C.c_int32),
+                ("rel_tol", C.c_double), ("hbm_budget", C.c_uint64)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("status", C.c_int32), ("nrhs", C.c_int32),
+                ("iterations", C.c_int32), ("converged", C.c_int32), ("true_rel_residual", C.c_double),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("instance", C.c_int32), ("hierarchy_built", C.c_int32)]
+
+
+class ServerCounters(C.Structure):
+    _fields_ = [("setups", C.c_int64), ("evictions", C.c_int64), ("resident_bytes", C.c_uint64),
+                ("hierarchy_bytes", C.c_uint64),
+                ("peak_resident_bytes", C.c_uint64), ("budget_bytes", C.c_uint64),
+                ("outstanding", C.c_int64), ("clock", C.c_double), ("last_estimate_bytes", C.c_uint64)]
 
 
 _vp = C.c_void_p
@@ -84,6 +108,16 @@ _sig = {
     "amamg_get_test_vectors": (C.c_int, [_vp, C.c_int32, _vp]),
     "amamg_kernel_timer": (C.c_int, [_vp, C.c_uint32]),
     "amamg_kernel_timer_read": (C.c_int, [_vp, C.c_int32, _P(C.c_int64), _P(C.c_double), _P(C.c_double)]),
+    "amamg_server_default_params": (None, [_P(ServerParams)]),
+    "amamg_server_create": (C.c_int, [C.c_int32, _P(ServerParams), _P(_vp)]),
+    "amamg_server_destroy": (C.c_int, [_vp]),
+    "amamg_server_add_gauge": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _P(C.c_int32)]),
+    "amamg_server_submit": (C.c_int, [_vp, C.c_int32, C.c_double, _P(SetupParams), C.c_int32, _vp, _vp,
+                                      _P(C.c_uint64)]),
+    "amamg_server_poll": (C.c_int, [_vp, _P(RequestInfo), C.c_int32, _P(C.c_int32)]),
+    "amamg_server_wait": (C.c_int, [_vp, C.c_double]),
+    "amamg_server_stats": (C.c_int, [_vp, _P(ServerCounters)]),
+    "amamg_server_last_error": (C.c_char_p, [_vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -275,3 +309,68 @@ class Hierarchy:
         out = np.zeros((nv, lt * lx * b, 2))
         self.ctx.check(_lib.amamg_get_test_vectors(self.h, level, _ptr(out)))
         return out[..., 0] + 1j * out[..., 1]
+
+
+def default_server_params(**kw) -> ServerParams:
+    p = ServerParams()
+    _lib.amamg_server_default_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+class Server:
+    """amamg_server: continuous-batching solve server with its own device objects and worker
+    thread.  Output arrays handed to submit() are kept alive here until poll() returns them."""
+
+    def __init__(self, device: int = 0, params: ServerParams | None = None):
+        s = _vp()
+        st = _lib.amamg_server_create(device, C.byref(params) if params else None, C.byref(s))
+        if st != OK:
+            raise AmamgError(st, "amamg_server_create failed")
+        self.s = s
+        self._out = {}          # request id -> (x array, psi copy is made by the library)
+
+    def _check(self, st, ok=(OK,)):
+        if st not in ok:
+            raise AmamgError(st, (_lib.amamg_server_last_error(self.s) or b"").decode())
+        return st
+
+    def add_gauge(self, links: np.ndarray) -> int:
+        """links: float64 [2][nt][nx][2] (ABI layout); returns the gauge id."""
+        a = np.ascontiguousarray(links, dtype=np.float64)
+        gid = C.c_int32()
+        self._check(_lib.amamg_server_add_gauge(self.s, a.shape[1], a.shape[2], _ptr(a), C.byref(gid)))
+        return gid.value
+
+    def submit(self, gauge_id: int, m0: float, psi: np.ndarray, setup: SetupParams | None = None) -> int:
+        """psi: float64 [nrhs][nt][nx][2][2]; returns the request id.  The solution is returned
+        by poll()."""
+        a = np.ascontiguousarray(psi, dtype=np.float64)
+        x = np.zeros_like(a)
+        rid = C.c_uint64()
+        self._check(_lib.amamg_server_submit(self.s, gauge_id, m0, C.byref(setup) if setup else None,
+                                             a.shape[0], _ptr(a), _ptr(x), C.byref(rid)))
+        self._out[rid.value] = x
+        return rid.value
+
+    def poll(self, capacity: int = 256):
+        """Finished requests: list of (RequestInfo, x)."""
+        buf = (RequestInfo * capacity)()
+        n = C.c_int32()
+        self._check(_lib.amamg_server_poll(self.s, buf, capacity, C.byref(n)))
+        return [(buf[i], self._out.pop(buf[i].id)) for i in range(n.value)]
+
+    def wait(self, timeout_s: float = 600.0) -> bool:
+        """True when nothing is outstanding, False on timeout."""
+        return self._check(_lib.amamg_server_wait(self.s, timeout_s), ok=(OK, PENDING)) == OK
+
+    def stats(self) -> ServerCounters:
+        c = ServerCounters()
+        self._check(_lib.amamg_server_stats(self.s, C.byref(c)))
+        return c
+
+    def close(self):
+        if self.s:
+            _lib.amamg_server_destroy(self.s)
+            self.s = None

@@ -19,7 +19,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libamamg.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["fine.hip", "coarse.hip", "transfer.hip", "setup.hip", "krylov.hip", "runtime.hip",
-           "solve.hip"]
+           "solve.hip", "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-result",
@@ -44,7 +44,7 @@ def build(jobs: int = 6) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs]
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-pthread", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -1,0 +1,709 @@
+// Continuous-batching solve server.  Requests (a gauge field held by the server, a bare mass,
+// setup parameters, 1..slots right-hand sides) are admitted into solver instances: a batch
+// workspace of fixed slot count on its own HIP stream, bound to one AM-AMG hierarchy.
+// Admission happens at restart-cycle boundaries, while the instance's other slots keep
+// iterating, and instances bound to different hierarchies run concurrently on their streams.
+// Hierarchies are cached per (gauge, mass, setup parameters) and evicted least recently used
+// when the device-memory budget would be exceeded.
+//
+// One worker thread owns every device object of the server; the C entry points only queue
+// requests, read gauges in and hand back completed requests.  Because an instance's slot
+// count is fixed, a right-hand side's arithmetic (reduction blocking included) does not
+// depend on which other requests share the device: a request's result is bitwise the same
+// alone and in any mix.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+
+#include "runtime.hpp"
+
+using namespace amamg;
+using namespace amamg::rt;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+  uint64_t id = 0;
+  int gauge = 0;
+  double m0 = 0;
+  amamg_setup_params sp{};
+  int nrhs = 0;
+  std::vector<double> psi;     // copied at submission: [nrhs][n] complex
+  double* x = nullptr;         // caller's output
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  int status = AMAMG_OK;
+  int remaining = 0;           // right-hand sides still running
+  int iterations = 0, converged = 1, built = 0, instance = -1;
+  double residual = 0;
+};
+
+struct CachedH {
+  amamg_hierarchy* h = nullptr;
+  int gauge = 0;
+  double m0 = 0;
+  amamg_setup_params sp{};
+  uint64_t last_use = 0;
+  int users = 0;               // instances bound to it
+  size_t bytes = 0;
+};
+
+struct Instance {
+  int id = 0;
+  hipStream_t stream = nullptr;
+  Workspace ws;
+  Arena io;                    // right-hand sides B and iterates X, [slots][n]
+  int64_t n_io = 0;
+  double2 *B = nullptr, *X = nullptr;
+  Batch bt;
+  CachedH* ch = nullptr;
+  enum Phase { IDLE, CHECKING, RUNNING } phase = IDLE;
+  std::vector<Request*> slot_req;     // request in the slot (nullptr: free)
+  std::vector<int> slot_rhs;          // its right-hand-side index
+  std::vector<int> checking;          // slots under the input check
+  std::vector<Request*> reserved;     // requests waiting for this instance's next boundary
+  uint64_t stamp = 0;                 // order of the last enqueued stage
+  int free_slots() const {
+    int f = 0;
+    for (Request* r : slot_req) f += r ? 0 : 1;
+    for (Request* r : reserved) f -= r->nrhs;
+    return f;
+  }
+  bool busy() const { return phase != IDLE || !reserved.empty(); }
+};
+
+bool same_params(const amamg_setup_params& a, const amamg_setup_params& b) {
+  return a.levels == b.levels && a.agg_size == b.agg_size && a.overlap == b.overlap &&
+         a.n_test_vectors == b.n_test_vectors && a.test_vector_sweeps == b.test_vector_sweeps &&
+         a.pre_sweeps == b.pre_sweeps && a.post_sweeps == b.post_sweeps && a.norm == b.norm &&
+         a.seed == b.seed;
+}
+
+}  // namespace
+
+struct amamg_server {
+  amamg_context* ctx = nullptr;
+  amamg_server_params prm{};
+  Clock::time_point t0;
+  // shared with the callers (mu)
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request*> incoming;
+  std::deque<Request*> done;
+  std::vector<amamg_gauge*> gauges;
+  uint64_t next_id = 1;
+  int64_t outstanding = 0;
+  bool stop = false;
+  std::string err;
+  int64_t setups = 0, evictions = 0;
+  size_t resident = 0, peak_resident = 0, last_estimate = 0, hier_bytes = 0;
+  // worker only
+  std::thread worker;
+  std::deque<Request*> queue;
+  std::vector<std::unique_ptr<CachedH>> cache;
+  std::vector<std::unique_ptr<Instance>> inst;
+  uint64_t tick = 0;
+
+  double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+};
+
+namespace {
+
+amamg_solve_params solve_params(const amamg_server* S) {
+  amamg_solve_params p;
+  amamg_default_solve_params(&p);
+  p.restart = S->prm.restart;
+  p.max_iters = S->prm.max_iters;
+  p.rel_tol = S->prm.rel_tol;
+  p.precision = S->prm.precision;
+  return p;
+}
+
+size_t resident_bytes(const amamg_server* S) {
+  size_t b = 0;
+  for (const auto& c : S->cache) b += c->bytes;
+  for (const auto& I : S->inst) b += I->ws.mem.bytes + I->io.bytes;
+  return b;
+}
+
+void account(amamg_server* S) {
+  const size_t r = resident_bytes(S);
+  size_t hb = 0;
+  for (const auto& c : S->cache) hb += c->bytes;
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->resident = r;
+  S->hier_bytes = hb;
+  S->peak_resident = std::max(S->peak_resident, r);
+}
+
+void finish(amamg_server* S, Request* R) {
+  R->t_done = S->now();
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->done.push_back(R);
+  S->outstanding -= 1;
+  S->cv_done.notify_all();
+}
+
+// Setup scratch (local systems, probes, staging) is not needed by the solve; a cached
+// hierarchy keeps only its operators, interpolation and smoother blocks.
+void trim_setup_scratch(amamg_hierarchy* h) {
+  static const char* keep[] = {"L_kind", "L_owner", "L_node", "d_tabs", "L_rows", "L_nrows", "L_P",
+                               "C_A", "C_Dinv", "C_Ainv", "L_P32", "L_A32", "L_Dinv32"};
+  for (LevelData& L : h->lv) {
+    L.tv = nullptr;
+    L.Adense = nullptr;
+  }
+  auto& items = h->mem.items;
+  for (auto& it : items) {
+    const std::string name = it.key.substr(0, it.key.find('#'));
+    bool k = false;
+    for (const char* n : keep) k = k || name == n;
+    if (!k && it.p) {
+      (void)hipFree(it.p);
+      it.p = nullptr;
+      it.bytes = 0;
+    }
+  }
+  items.erase(std::remove_if(items.begin(), items.end(), [](const Pool::Item& it) { return !it.p; }),
+              items.end());
+}
+
+// Drop least recently used hierarchies that no instance holds until `need` more bytes fit.
+bool make_room(amamg_server* S, size_t need) {
+  for (;;) {
+    if (resident_bytes(S) + need <= S->prm.hbm_budget) return true;
+    CachedH* victim = nullptr;
+    for (const auto& c : S->cache)
+      if (c->users == 0 && (!victim || c->last_use < victim->last_use)) victim = c.get();
+    if (!victim) return false;
+    victim->h->gauge->nhier -= 1;
+    delete victim->h;
+    S->cache.erase(std::find_if(S->cache.begin(), S->cache.end(),
+                                [&](const std::unique_ptr<CachedH>& c) { return c.get() == victim; }));
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->evictions += 1;
+  }
+}
+
+// Estimated device bytes of an instance workspace bound to a lattice with n fine unknowns.
+size_t instance_estimate(const amamg_server* S, int64_t n) {
+  const int m = S->prm.restart;
+  const size_t zs = S->prm.precision == AMAMG_FP64 ? 16 : 8;
+  return size_t(S->prm.slots) * n * (16 * size_t(m + 1) + zs * (m + 3) + 16 * 3);
+}
+
+// Hierarchy for the request's key: cached, or built now (synchronous setup on the server
+// context stream).  nullptr when the budget cannot be met at the moment.
+CachedH* hierarchy_for(amamg_server* S, Request* R, bool* built) {
+  *built = false;
+  for (const auto& c : S->cache)
+    if (c->gauge == R->gauge && c->m0 == R->m0 && same_params(c->sp, R->sp)) return c.get();
+  amamg_gauge* g;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    g = S->gauges[R->gauge];
+  }
+  const size_t need = setup_bytes(g->nt, g->nx, R->sp) + instance_estimate(S, int64_t(2) * g->nt * g->nx);
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->last_estimate = need;
+  }
+  if (!make_room(S, need)) return nullptr;
+  auto c = std::make_unique<CachedH>();
+  c->gauge = R->gauge;
+  c->m0 = R->m0;
+  c->sp = R->sp;
+  amamg_hierarchy* h = new amamg_hierarchy();
+  h->gauge = g;
+  h->m0 = R->m0;
+  h->prm = R->sp;
+  try {
+    run_setup(h);
+  } catch (...) {
+    delete h;
+    throw;
+  }
+  trim_setup_scratch(h);
+  g->nhier += 1;
+  c->h = h;
+  c->bytes = h->mem.bytes();
+  *built = true;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->setups += 1;
+  }
+  S->cache.push_back(std::move(c));
+  return S->cache.back().get();
+}
+
+void bind(amamg_server* S, Instance* I, CachedH* c) {
+  if (I->ch == c) return;
+  if (I->ch) I->ch->users -= 1;
+  I->ch = c;
+  c->users += 1;
+  amamg_hierarchy* h = c->h;
+  const int64_t n = h->lv[0].g.ndof();
+  const amamg_solve_params p = solve_params(S);
+  ensure_workspace(I->ws, h, S->prm.slots, p.restart, p.precision == AMAMG_FP64 ? F64 : F32,
+                   2 * p.max_iters + 2);
+  if (I->n_io != n) {
+    I->io.release();
+    I->B = I->io.alloc<double2>(size_t(S->prm.slots) * n);
+    I->X = I->io.alloc<double2>(size_t(S->prm.slots) * n);
+    I->n_io = n;
+  }
+  I->bt.init(h, &I->ws, I->stream, p, I->B, I->X, I->id);
+}
+
+// Start the input check of the reserved requests (instance at a boundary or idle).
+void begin_admission(amamg_server* S, Instance* I) {
+  const int64_t n = I->ch->h->lv[0].g.ndof();
+  std::vector<int> slots;
+  for (Request* R : I->reserved) {
+    R->t_admit = S->now();
+    R->instance = I->id;
+    int k = 0;
+    for (int s = 0; s < S->prm.slots && k < R->nrhs; ++s) {
+      if (I->slot_req[s]) continue;
+      I->slot_req[s] = R;
+      I->slot_rhs[s] = k;
+      HIPCHECK(hipMemcpyAsync(I->B + int64_t(s) * n, R->psi.data() + size_t(k) * 2 * n, sizeof(double2) * n,
+                              hipMemcpyHostToDevice, I->stream));
+      slots.push_back(s);
+      ++k;
+    }
+    R->remaining = R->nrhs;
+  }
+  I->reserved.clear();
+  I->checking = slots;
+  I->ch->last_use = ++S->tick;
+  I->bt.admit_begin(slots);
+  I->phase = Instance::CHECKING;
+  I->stamp = ++S->tick;
+}
+
+void release_slot(Instance* I, int s) {
+  I->slot_req[s] = nullptr;
+  I->slot_rhs[s] = -1;
+}
+
+// Input check landed: refuse requests with a non-finite right-hand side, start the others and
+// enqueue the next cycle.
+void finish_admission(amamg_server* S, Instance* I) {
+  const std::vector<int> bad = I->bt.admit_nonfinite();
+  std::vector<Request*> failed;
+  for (int s : bad)
+    if (std::find(failed.begin(), failed.end(), I->slot_req[s]) == failed.end()) failed.push_back(I->slot_req[s]);
+  std::vector<int> reject;
+  for (int s : I->checking)
+    if (std::find(failed.begin(), failed.end(), I->slot_req[s]) != failed.end()) reject.push_back(s);
+  I->bt.admit_finish(reject, false);
+  for (int s : reject) release_slot(I, s);
+  for (Request* R : failed) {
+    R->status = AMAMG_ERR_NONFINITE;
+    finish(S, R);
+  }
+  I->checking.clear();
+  I->bt.enqueue_state_read();
+  I->phase = Instance::RUNNING;
+  I->stamp = ++S->tick;
+}
+
+// A state read landed: hand back finished right-hand sides and requests, admit what waits for
+// this instance, enqueue the next cycle.
+void cycle_end(amamg_server* S, Instance* I) {
+  const bool any = I->bt.cycle_boundary();
+  const int64_t n = I->ch->h->lv[0].g.ndof();
+  for (int s = 0; s < S->prm.slots; ++s) {
+    Request* R = I->slot_req[s];
+    if (!R) continue;
+    const RhsState& st = I->bt.state(s);
+    if (st.in_cycle) continue;
+    // finished: converged, capped or non-finite
+    R->iterations = std::max(R->iterations, st.iters);
+    R->converged = R->converged && st.converged;
+    R->residual = std::max(R->residual, st.true_res);
+    if (st.nonfinite) R->status = AMAMG_ERR_NONFINITE;
+    HIPCHECK(hipMemcpyAsync(R->x + size_t(I->slot_rhs[s]) * 2 * n, I->X + int64_t(s) * n,
+                            sizeof(double2) * n, hipMemcpyDeviceToHost, I->stream));
+    HIPCHECK(hipStreamSynchronize(I->stream));
+    release_slot(I, s);
+    if (--R->remaining == 0) {
+      if (R->status == AMAMG_OK && !R->converged) R->status = AMAMG_NOT_CONVERGED;
+      finish(S, R);
+    }
+  }
+  if (!I->reserved.empty()) {
+    begin_admission(S, I);
+    return;
+  }
+  if (any) {
+    I->bt.enqueue_cycle();
+    I->bt.enqueue_state_read();
+    I->stamp = ++S->tick;
+  } else {
+    I->phase = Instance::IDLE;
+  }
+}
+
+// Place queued requests: an instance bound to the request's hierarchy with room (joining at its
+// next boundary), else an idle or new instance rebound to it.
+bool place(amamg_server* S) {
+  bool did = false;
+  for (auto it = S->queue.begin(); it != S->queue.end();) {
+    Request* R = *it;
+    Instance* target = nullptr;
+    for (const auto& I : S->inst)
+      if (I->ch && I->ch->gauge == R->gauge && I->ch->m0 == R->m0 && same_params(I->ch->sp, R->sp) &&
+          I->free_slots() >= R->nrhs) {
+        target = I.get();
+        break;
+      }
+    if (!target) {
+      Instance* idle = nullptr;
+      for (const auto& I : S->inst)
+        if (!I->busy() && (!idle || (I->ch && idle->ch && I->ch->last_use < idle->ch->last_use))) idle = I.get();
+      if (!idle && int(S->inst.size()) < S->prm.max_instances) {
+        auto I = std::make_unique<Instance>();
+        I->id = int(S->inst.size());
+        HIPCHECK(hipStreamCreateWithFlags(&I->stream, hipStreamNonBlocking));
+        I->slot_req.assign(S->prm.slots, nullptr);
+        I->slot_rhs.assign(S->prm.slots, -1);
+        S->inst.push_back(std::move(I));
+        idle = S->inst.back().get();
+      }
+      if (idle) {
+        bool built = false;
+        // the idle instance's current hierarchy may be evicted to make room
+        if (idle->ch) {
+          idle->ch->users -= 1;
+          idle->ch = nullptr;
+        }
+        CachedH* c = nullptr;
+        try {
+          c = hierarchy_for(S, R, &built);
+        } catch (const Fail& f) {
+          if (f.code == AMAMG_ERR_DEVICE) throw;
+          // this request's setup failed (singular local system, no memory): only it fails
+          R->status = f.code;
+          {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->err = f.msg;
+          }
+          finish(S, R);
+          it = S->queue.erase(it);
+          did = true;
+          continue;
+        }
+        if (c) {
+          bind(S, idle, c);
+          R->built = built ? 1 : 0;
+          target = idle;
+        }
+      }
+    }
+    if (!target) {
+      const bool any_busy = std::any_of(S->inst.begin(), S->inst.end(),
+                                        [](const std::unique_ptr<Instance>& I) { return I->busy(); });
+      if (!any_busy && S->inst.size() > 0) {
+        // nothing running will free memory: this request cannot be served
+        R->status = AMAMG_ERR_OUT_OF_MEMORY;
+        finish(S, R);
+        it = S->queue.erase(it);
+        did = true;
+        continue;
+      }
+      ++it;
+      continue;
+    }
+    target->reserved.push_back(R);
+    if (target->phase == Instance::IDLE) begin_admission(S, target);
+    it = S->queue.erase(it);
+    did = true;
+  }
+  account(S);
+  return did;
+}
+
+bool progress(amamg_server* S) {
+  bool did = false;
+  for (const auto& I : S->inst) {
+    if (I->phase == Instance::IDLE || !I->bt.ready()) continue;
+    did = true;
+    if (I->phase == Instance::CHECKING) finish_admission(S, I.get());
+    else cycle_end(S, I.get());
+  }
+  return did;
+}
+
+// Device failure: every request in flight or queued fails with the error; instances restart
+// empty.
+void fail_all(amamg_server* S, const Fail& f) {
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->err = f.msg;
+  }
+  std::vector<Request*> victims(S->queue.begin(), S->queue.end());
+  S->queue.clear();
+  for (const auto& I : S->inst) {
+    (void)hipStreamSynchronize(I->stream);
+    for (Request* R : I->reserved) victims.push_back(R);
+    I->reserved.clear();
+    for (int s = 0; s < int(I->slot_req.size()); ++s)
+      if (I->slot_req[s]) {
+        if (std::find(victims.begin(), victims.end(), I->slot_req[s]) == victims.end())
+          victims.push_back(I->slot_req[s]);
+        release_slot(I.get(), s);
+      }
+    I->checking.clear();
+    I->phase = Instance::IDLE;
+    if (I->ch) {
+      I->ch->users -= 1;
+      I->ch = nullptr;
+    }
+    I->ws.release();
+  }
+  for (Request* R : victims) {
+    R->status = f.code;
+    finish(S, R);
+  }
+}
+
+void worker_main(amamg_server* S) {
+  (void)hipSetDevice(S->ctx->device);
+  for (;;) {
+    bool stopping;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      while (!S->incoming.empty()) {
+        S->queue.push_back(S->incoming.front());
+        S->incoming.pop_front();
+      }
+      stopping = S->stop;
+    }
+    const bool busy = std::any_of(S->inst.begin(), S->inst.end(),
+                                  [](const std::unique_ptr<Instance>& I) { return I->busy(); });
+    if (stopping && S->queue.empty() && !busy) break;
+    bool did = false;
+    try {
+      did = progress(S);
+      did = place(S) || did;
+    } catch (const Fail& f) {
+      fail_all(S, f);
+      did = true;
+    }
+    if (did) continue;
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (!S->incoming.empty() || (S->stop && S->queue.empty() && !busy)) continue;
+    if (busy) S->cv_work.wait_for(lk, std::chrono::microseconds(100));
+    else S->cv_work.wait(lk, [&] { return !S->incoming.empty() || S->stop; });
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------- ABI
+
+extern "C" {
+
+void amamg_server_default_params(amamg_server_params* p) {
+  if (!p) return;
+  p->slots = 16;
+  p->max_instances = 4;
+  p->precision = AMAMG_MIXED_FP32;
+  p->restart = 20;
+  p->max_iters = 10000;
+  p->reserved = 0;
+  p->rel_tol = 1e-10;
+  p->hbm_budget = 0;
+}
+
+amamg_status amamg_server_create(int32_t device, const amamg_server_params* params, amamg_server** out) {
+  if (!out) return AMAMG_ERR_INVALID_ARG;
+  *out = nullptr;
+  amamg_server_params p;
+  if (params) p = *params;
+  else amamg_server_default_params(&p);
+  if (p.slots < 1 || p.slots > 256 || p.max_instances < 1 || p.max_instances > 16 || p.restart < 1 ||
+      p.restart > 31 || p.max_iters < 1 || !(p.rel_tol > 0) || !std::isfinite(p.rel_tol) ||
+      p.precision < 0 || p.precision > 2)
+    return AMAMG_ERR_INVALID_ARG;
+  amamg_context* ctx = nullptr;
+  const amamg_status st = amamg_context_create(device, nullptr, &ctx);
+  if (st != AMAMG_OK) return st;
+  if (p.hbm_budget == 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      amamg_context_destroy(ctx);
+      return AMAMG_ERR_DEVICE;
+    }
+    p.hbm_budget = fr / 4 * 3;
+  }
+  amamg_server* S = new amamg_server();
+  S->ctx = ctx;
+  S->prm = p;
+  S->t0 = Clock::now();
+  S->worker = std::thread(worker_main, S);
+  *out = S;
+  return AMAMG_OK;
+}
+
+amamg_status amamg_server_add_gauge(amamg_server* S, int32_t nt, int32_t nx, const double* links,
+                                    int32_t* gauge_id) {
+  if (!S || !links || !gauge_id) return AMAMG_ERR_INVALID_ARG;
+  // a gauge of the server's context; the device copy is made here, on the caller's thread,
+  // with a synchronous copy that does not touch the worker's streams
+  amamg_gauge* g = new amamg_gauge();
+  try {
+    REQUIRE(nt >= 4 && nx >= 4 && nt % 2 == 0 && nx % 2 == 0, AMAMG_ERR_UNSUPPORTED_SHAPE,
+            "lattice sizes must be even and >= 4");
+    REQUIRE(int64_t(nt) * nx <= (int64_t(1) << 28), AMAMG_ERR_UNSUPPORTED_SHAPE, "lattice too large");
+    const size_t nval = size_t(2) * nt * nx * 2;
+    REQUIRE(finite_all(links, nval), AMAMG_ERR_NONFINITE, "non-finite link");
+    HIPCHECK(hipSetDevice(S->ctx->device));
+    g->ctx = S->ctx;
+    g->nt = nt;
+    g->nx = nx;
+    g->U = g->mem.alloc<double2>(size_t(2) * nt * nx);
+    HIPCHECK(hipMemcpy(g->U, links, sizeof(double) * nval, hipMemcpyHostToDevice));
+  } catch (const Fail& f) {
+    delete g;
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->err = f.msg;
+    return f.code;
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->gauges.push_back(g);
+  *gauge_id = int32_t(S->gauges.size()) - 1;
+  return AMAMG_OK;
+}
+
+amamg_status amamg_server_submit(amamg_server* S, int32_t gauge_id, double m0,
+                                 const amamg_setup_params* setup, int32_t nrhs, const double* psi,
+                                 double* x, uint64_t* request_id) {
+  if (!S || !psi || !x || !request_id) return AMAMG_ERR_INVALID_ARG;
+  auto R = std::make_unique<Request>();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (gauge_id < 0 || gauge_id >= int(S->gauges.size()) || nrhs < 1 || nrhs > S->prm.slots ||
+        !std::isfinite(m0) || S->stop) {
+      S->err = "bad request: unknown gauge, nrhs outside [1, slots], non-finite mass or stopped server";
+      return AMAMG_ERR_INVALID_ARG;
+    }
+    const amamg_gauge* g = S->gauges[gauge_id];
+    R->psi.assign(psi, psi + size_t(nrhs) * g->nt * g->nx * 4);
+  }
+  R->gauge = gauge_id;
+  R->m0 = m0;
+  if (setup) R->sp = *setup;
+  else amamg_default_setup_params(&R->sp);
+  R->nrhs = nrhs;
+  R->x = x;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    try {
+      const amamg_gauge* g = S->gauges[gauge_id];
+      (void)setup_bytes(g->nt, g->nx, R->sp);     // validates the setup parameters and shape
+    } catch (const Fail& f) {
+      S->err = f.msg;
+      return f.code;
+    }
+    R->id = S->next_id++;
+    R->t_submit = S->now();
+    *request_id = R->id;
+    S->outstanding += 1;
+    S->incoming.push_back(R.release());
+  }
+  S->cv_work.notify_one();
+  return AMAMG_OK;
+}
+
+amamg_status amamg_server_poll(amamg_server* S, amamg_request_info* out, int32_t capacity,
+                               int32_t* n_written) {
+  if (!S || (!out && capacity > 0) || !n_written) return AMAMG_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(S->mu);
+  int k = 0;
+  while (k < capacity && !S->done.empty()) {
+    Request* R = S->done.front();
+    S->done.pop_front();
+    amamg_request_info& o = out[k++];
+    o.id = R->id;
+    o.status = R->status;
+    o.nrhs = R->nrhs;
+    o.iterations = R->iterations;
+    o.converged = R->converged;
+    o.true_rel_residual = R->residual;
+    o.t_submit = R->t_submit;
+    o.t_admit = R->t_admit;
+    o.t_done = R->t_done;
+    o.instance = R->instance;
+    o.hierarchy_built = R->built;
+    delete R;
+  }
+  *n_written = k;
+  return AMAMG_OK;
+}
+
+amamg_status amamg_server_wait(amamg_server* S, double timeout_s) {
+  if (!S) return AMAMG_ERR_INVALID_ARG;
+  std::unique_lock<std::mutex> lk(S->mu);
+  const bool ok = S->cv_done.wait_for(lk, std::chrono::duration<double>(std::max(0.0, timeout_s)),
+                                      [&] { return S->outstanding == 0; });
+  return ok ? AMAMG_OK : AMAMG_PENDING;
+}
+
+amamg_status amamg_server_stats(amamg_server* S, amamg_server_counters* out) {
+  if (!S || !out) return AMAMG_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(S->mu);
+  out->setups = S->setups;
+  out->evictions = S->evictions;
+  out->resident_bytes = S->resident;
+  out->hierarchy_bytes = S->hier_bytes;
+  out->peak_resident_bytes = S->peak_resident;
+  out->budget_bytes = S->prm.hbm_budget;
+  out->outstanding = S->outstanding;
+  out->clock = S->now();
+  out->last_estimate_bytes = S->last_estimate;
+  return AMAMG_OK;
+}
+
+const char* amamg_server_last_error(amamg_server* S) {
+  if (!S) return "null server";
+  std::lock_guard<std::mutex> lk(S->mu);
+  return S->err.c_str();
+}
+
+amamg_status amamg_server_destroy(amamg_server* S) {
+  if (!S) return AMAMG_ERR_INVALID_ARG;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  S->worker.join();          // drains every submitted request first
+  for (auto& I : S->inst) {
+    (void)hipStreamSynchronize(I->stream);
+    I->ws.release();
+    I->io.release();
+    (void)hipStreamDestroy(I->stream);
+  }
+  S->inst.clear();
+  for (auto& c : S->cache) {
+    c->h->gauge->nhier -= 1;
+    delete c->h;
+  }
+  S->cache.clear();
+  for (Request* R : S->done) delete R;
+  for (amamg_gauge* g : S->gauges) delete g;
+  amamg_context_destroy(S->ctx);
+  delete S;
+  return AMAMG_OK;
+}
+
+}  // extern "C"

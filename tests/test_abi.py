@@ -73,10 +73,8 @@ def test_struct_layouts_match_header():
     from paper_2608_03515_amd import amamg
     pairs = [("amamg_setup_params", amamg.SetupParams), ("amamg_solve_params", amamg.SolveParams),
              ("amamg_solve_info", amamg.SolveInfo)]
-    for extra in ("ServerParams", "RequestInfo"):
-        if hasattr(amamg, extra):
-            pairs.append(({"ServerParams": "amamg_server_params", "RequestInfo": "amamg_request_info"}[extra],
-                          getattr(amamg, extra)))
+    pairs += [("amamg_server_params", amamg.ServerParams), ("amamg_request_info", amamg.RequestInfo),
+              ("amamg_server_counters", amamg.ServerCounters)]
     c = _c_layouts([(cname, [f[0] for f in cls._fields_]) for cname, cls in pairs])
     for cname, cls in pairs:
         want = [ctypes.sizeof(cls)] + [getattr(cls, f[0]).offset for f in cls._fields_]

@@ -1,0 +1,165 @@
+"""GPU tests of the continuous-batching server (amamg_server_*), through the C ABI.
+
+Bars: every request's solution matches the CPU oracle (FP64: relative error <= 1e-9 and the
+oracle's iteration count); a request's solution is bitwise the same alone and in a mix of
+requests on other lattices and masses that arrive while it runs; per-request failures stay
+with their request; hierarchies are evicted under a small memory budget and rebuilt on demand
+with unchanged results.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import amg
+from oracle.solve import solve as oracle_solve
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+SETUP = dict(levels=2, agg_size=4, overlap=1, n_test_vectors=4)
+
+
+def lattices():
+    """Two gauge fields: the 16^2 beta = 3 workload and a 32^2 beta = 4 field."""
+    return [synth.WORKLOADS["C1"].links(), synth.gen_links(32, 32, 4.0, 60, 321)]
+
+
+def requests():
+    """(gauge index, m0, right-hand sides [nrhs][nt][nx][2]) in submission order."""
+    out = []
+    for k, (gi, m0, nrhs) in enumerate([(0, 0.1, 2), (1, 0.15, 1), (0, 0.2, 3), (1, 0.15, 2),
+                                         (0, 0.1, 1), (1, 0.3, 1), (0, 0.2, 1)]):
+        L = 16 if gi == 0 else 32
+        out.append((gi, m0, synth.gaussian_rhs(L, L, 500 + k, nrhs=nrhs)))
+    return out
+
+
+def make_server(lib, **kw):
+    prm = lib.default_server_params(slots=4, max_instances=2, precision=lib.FP64)
+    for k, v in kw.items():
+        setattr(prm, k, v)
+    return lib.Server(0, prm)
+
+
+def run(lib, srv, gids, reqs, stagger=0.0):
+    sp = lib.default_setup_params(**SETUP)
+    ids = []
+    for i, (gi, m0, psi) in enumerate(reqs):
+        ids.append(srv.submit(gids[gi], m0, synth.field_to_abi(psi), sp))
+        if stagger and i % 2 == 1:
+            time.sleep(stagger)          # later requests arrive while earlier ones run
+    assert srv.wait(300)
+    done = {info.id: (info, synth.field_from_abi(x)) for info, x in srv.poll()}
+    return [done[i] for i in ids]
+
+
+def test_server_matches_oracle_and_is_the_same_alone_and_in_a_mix(lib):
+    Us = lattices()
+    reqs = requests()
+    # the mix: every request, staggered so that later ones join running instances
+    srv = make_server(lib)
+    gids = [srv.add_gauge(synth.links_to_abi(U)) for U in Us]
+    say("server mix")
+    mix = run(lib, srv, gids, reqs, stagger=0.02)
+    st = srv.stats()
+    assert st.outstanding == 0 and st.setups == 4          # (16, 0.1) (32, 0.15) (16, 0.2) (32, 0.3)
+    srv.close()
+    prm = amg.SetupParams(levels=2, agg=4, overlap=1, n_test_vectors=4)
+    for (gi, m0, psi), (info, x) in zip(reqs, mix):
+        assert info.status == lib.OK and info.converged and info.true_rel_residual <= 1e-10
+        assert info.t_submit <= info.t_admit <= info.t_done
+        its = []
+        levels = None
+        for r in range(psi.shape[0]):
+            xo, io, levels = oracle_solve(Us[gi], m0, psi[r], prm, levels=levels)
+            assert rel(x[r], xo) <= 1e-9
+            its.append(io.iterations)
+        assert info.iterations == max(its)
+    # each request alone on a fresh server: bitwise the same
+    for k in (0, 3, 6):
+        srv = make_server(lib)
+        gids = [srv.add_gauge(synth.links_to_abi(U)) for U in Us]
+        say("server alone", k)
+        (info, x), = run(lib, srv, gids, [reqs[k]])
+        srv.close()
+        assert info.iterations == mix[k][0].iterations
+        assert np.array_equal(x, mix[k][1])
+
+
+def test_server_request_errors_stay_with_their_request(lib):
+    Us = lattices()
+    srv = make_server(lib)
+    gids = [srv.add_gauge(synth.links_to_abi(U)) for U in Us]
+    sp = lib.default_setup_params(**SETUP)
+    bad = synth.field_to_abi(synth.gaussian_rhs(16, 16, 9, nrhs=2))
+    bad[1, 3, 4, 0, 1] = np.nan
+    good = synth.field_to_abi(synth.gaussian_rhs(16, 16, 10, nrhs=1))
+    zero = np.zeros_like(good)
+    with pytest.raises(lib.AmamgError):
+        srv.submit(7, 0.1, good, sp)                         # unknown gauge
+    with pytest.raises(lib.AmamgError):
+        srv.submit(gids[0], 0.1, np.zeros((5, 16, 16, 2, 2)), sp)   # more rhs than slots
+    with pytest.raises(lib.AmamgError):
+        srv.submit(gids[0], 0.1, good, lib.default_setup_params(levels=2, agg_size=5))  # 5 does not divide 16
+    r_bad = srv.submit(gids[0], 0.1, bad, sp)
+    r_good = srv.submit(gids[0], 0.1, good, sp)
+    r_zero = srv.submit(gids[0], 0.1, zero, sp)
+    assert srv.wait(120)
+    out = {info.id: (info, x) for info, x in srv.poll()}
+    srv.close()
+    assert out[r_bad][0].status == lib.STATUS_CODES["NONFINITE"]
+    assert out[r_good][0].status == lib.OK and out[r_good][0].converged
+    assert out[r_zero][0].status == lib.OK and np.all(out[r_zero][1] == 0)
+
+
+def test_server_evicts_under_a_small_budget_and_rebuilds(lib):
+    Us = lattices()
+    sp = lib.default_setup_params(**SETUP)
+    psi = synth.field_to_abi(synth.gaussian_rhs(32, 32, 33, nrhs=1))
+    masses = (0.15, 0.3, 0.15)
+    # reference: ample budget, one request at a time
+    srv = make_server(lib)
+    g = srv.add_gauge(synth.links_to_abi(Us[1]))
+    ref = []
+    for m0 in masses:
+        srv.submit(g, m0, psi, sp)
+        assert srv.wait(120)
+        (info, x), = srv.poll()
+        ref.append((info, x))
+    st = srv.stats()
+    assert st.setups == 2 and st.evictions == 0
+    work = st.resident_bytes - st.hierarchy_bytes            # the instance's workspace
+    one = st.hierarchy_bytes // 2                             # one cached hierarchy
+    srv.close()
+    # room for one hierarchy only: a build needs workspace + estimate, which fits only after
+    # the other hierarchy is evicted
+    budget = work + st.last_estimate_bytes + one // 2
+    srv = make_server(lib, hbm_budget=budget)
+    g = srv.add_gauge(synth.links_to_abi(Us[1]))
+    for k, m0 in enumerate(masses):
+        srv.submit(g, m0, psi, sp)
+        assert srv.wait(120)
+        (info, x), = srv.poll()
+        assert info.status == lib.OK and info.hierarchy_built == 1
+        assert info.iterations == ref[k][0].iterations and np.array_equal(x, ref[k][1])
+    st = srv.stats()
+    assert st.setups == 3 and st.evictions == 2 and st.peak_resident_bytes <= budget
+    srv.close()
+    # too small for any hierarchy: the request fails, the server stays usable
+    srv = make_server(lib, hbm_budget=1 << 20)
+    g = srv.add_gauge(synth.links_to_abi(Us[1]))
+    srv.submit(g, 0.15, psi, sp)
+    assert srv.wait(60)
+    (info, _), = srv.poll()
+    assert info.status == lib.STATUS_CODES["OUT_OF_MEMORY"]
+    srv.close()
