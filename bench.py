@@ -146,6 +146,85 @@ def cpu_baseline(w, m0, gpu_iterations, budget_s=25.0):
                       "NumPy/SciPy FP64, sparse matvecs single-threaded"}
 
 
+def serve_leg(lib, n_requests, qps, n_configs=16, slots=16, instances=4, log_every=100):
+    """Open-loop serving run on the continuous-batching server: Poisson arrivals at `qps`,
+    each request on one of n_configs resident gauge fields (L in 32..512) with a per-request
+    mass and 1..8 right-hand sides; mixed precision to 1e-10.  Latency = completion minus
+    submission on the server clock (queueing and the solve).  Every hierarchy is built (and
+    cached) before the timed stream starts."""
+    import threading
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    cfgs = synth.serving_configs(n_configs)
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=min(16, len(cfgs)), mp_context=mp.get_context("spawn")) as ex:
+        links = list(ex.map(synth.serving_links, cfgs))
+    t_gen = time.perf_counter() - t0
+    srv = lib.Server(0, lib.default_server_params(slots=slots, max_instances=instances,
+                                                  precision=lib.MIXED_FP32))
+    gids = [srv.add_gauge(synth.links_to_abi(U)) for U in links]
+    del links
+    setups = [lib.default_setup_params(**synth.serving_setup(c["L"])) for c in cfgs]
+    # right-hand-side pools (8 Gaussian fields per configuration); requests copy slices of them
+    pools = [synth.field_to_abi(synth.gaussian_rhs(c["L"], c["L"], c["seed"] + 77, nrhs=8)) for c in cfgs]
+    stream = synth.request_stream(n_requests, qps, len(cfgs))
+    # warm cache: one request per (configuration, mass) builds every hierarchy before timing
+    t0 = time.perf_counter()
+    for k, c in enumerate(cfgs):
+        for m0 in synth.SERVING_MASSES:
+            srv.submit(gids[k], m0, pools[k][:1], setups[k])
+    srv.wait(1800)
+    srv.poll(len(cfgs) * len(synth.SERVING_MASSES) + 1)
+    warm = srv.stats()
+    t_warm = time.perf_counter() - t0
+    log(f"serving: {warm.setups} hierarchies built in {t_warm:.1f} s (setup {warm.setup_seconds:.1f} s, "
+        f"longest {warm.setup_seconds_max:.2f} s)")
+    lag = [0.0]
+
+    def client():
+        start = time.perf_counter()
+        for k, rq in enumerate(stream):
+            delay = rq["t"] - (time.perf_counter() - start)
+            if delay > 0:
+                time.sleep(delay)
+            else:
+                lag[0] = max(lag[0], -delay)
+            rng = np.random.default_rng(rq["seed"])
+            pick = rng.choice(8, rq["nrhs"], replace=False)
+            srv.submit(gids[rq["config"]], rq["m0"], pools[rq["config"]][pick], setups[rq["config"]])
+            if log_every and (k + 1) % log_every == 0:
+                log(f"serving: submitted {k + 1}/{len(stream)}")
+    th = threading.Thread(target=client)
+    th.start()
+    th.join()
+    srv.wait(1800)
+    done = srv.poll(len(stream) + 1)
+    st = srv.stats()
+    srv.close()
+    infos = [i for i, _ in done]
+    lat = np.array([i.t_done - i.t_submit for i in infos])
+    queue = np.array([i.t_admit - i.t_submit for i in infos if i.instance >= 0] or [0.0])
+    ok = sum(1 for i in infos if i.status == lib.OK and i.converged)
+    rhs = sum(i.nrhs for i in infos)
+    span = max(i.t_done for i in infos) - min(i.t_submit for i in infos)
+    by_L = {}
+    for i, rq in zip(sorted(infos, key=lambda i: i.id), stream):
+        by_L.setdefault(cfgs[rq["config"]]["L"], []).append(i.t_done - i.t_submit)
+    return {"requests": len(infos), "ok": ok, "rhs": rhs, "qps": qps,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3), "queue_p50_ms": float(np.percentile(queue, 50) * 1e3),
+            "queue_p99_ms": float(np.percentile(queue, 99) * 1e3),
+            "solves_per_s": rhs / span, "span_s": span,
+            "p50_ms_by_L": {str(L): float(np.percentile(v, 50) * 1e3) for L, v in sorted(by_L.items())},
+            "p99_ms_by_L": {str(L): float(np.percentile(v, 99) * 1e3) for L, v in sorted(by_L.items())},
+            "max_rel_residual": max(i.true_rel_residual for i in infos),
+            "warmup_setups": warm.setups, "warmup_s": t_warm, "setup_s_max": st.setup_seconds_max,
+            "setups_during_stream": st.setups - warm.setups, "evictions": st.evictions,
+            "peak_resident_GB": st.peak_resident_bytes / 1e9, "client_max_lag_ms": lag[0] * 1e3,
+            "slots": slots, "instances": instances, "configs": len(cfgs),
+            "lattices": sorted({c["L"] for c in cfgs}), "gauge_generation_s": t_gen}
+
+
 # ------------------------------------------------------------------ profile summaries
 FAMILY_PATTERNS = {"update": "k_update_", "dots": "k_dots<"}
 TRAFFIC_MD = os.path.join(ROOT, "profiles", "gram_schmidt_256x256_64rhs_mixed_traffic.md")
@@ -246,6 +325,10 @@ def main():
     ap.add_argument("--nrhs", type=int, default=64)
     ap.add_argument("--groups", type=int, default=2,
                     help="right-hand-side batches run concurrently on separate streams")
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="requests of the serving leg (0: skip it)")
+    ap.add_argument("--serve-qps", type=float, default=8.0)
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving leg")
     ap.add_argument("--family", default=None, choices=FAMILIES,
                     help="kernel family of the roofline (default: the largest in an instrumented "
                          "one-stream step)")
@@ -273,6 +356,11 @@ def main():
 
     import torch
     from paper_2608_03515_amd import amamg as lib
+
+    if args.serve_only:
+        out = serve_leg(lib, args.serve_requests, args.serve_qps)
+        print(json.dumps({"serving": out}), flush=True)
+        return
 
     stream = torch.cuda.Stream()          # default priority; the library runs on it
     torch.cuda.set_stream(stream)

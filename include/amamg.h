@@ -211,8 +211,9 @@ amamg_status amamg_get_test_vectors(const amamg_hierarchy *h, int32_t level, dou
  * A request asks for D(m0) x = psi on one of the server's gauge fields, with the given setup
  * parameters (aggregate size, overlap, levels, ...; Multilevel approach and SM-AMG sections),
  * for 1..slots right-hand sides; solve parameters (precision, restart, tolerance, cap) are the
- * server's.  Hierarchies are built on first use per (gauge, m0, setup parameters), kept
- * resident and evicted least recently used when the device-memory budget would be exceeded.
+ * server's.  Hierarchies are built on first use per (gauge, m0, setup parameters) by a builder
+ * thread on its own stream (running instances keep iterating meanwhile), kept resident and
+ * evicted least recently used when the device-memory budget would be exceeded.
  * Each solver instance is a batch of `slots` right-hand-side slots on its own HIP stream,
  * bound to one hierarchy; requests join a running instance at its next restart-cycle
  * boundary as slots free up (continuous batching), and instances bound to different
@@ -232,7 +233,7 @@ typedef struct {
   int32_t precision;           /* amamg_precision of every solve (default AMAMG_MIXED_FP32)     */
   int32_t restart;             /* FGMRES(m) (default 20)                                        */
   int32_t max_iters;           /* Arnoldi steps per right-hand side (default 10000)             */
-  int32_t reserved;
+  int32_t builders;            /* hierarchy builder threads, one stream each (default 2, <= 8)  */
   double rel_tol;              /* default 1e-10                                                 */
   uint64_t hbm_budget;         /* device bytes for hierarchies and instance workspaces;         */
                                /* 0 = three quarters of the free memory at creation           */
@@ -259,7 +260,9 @@ typedef struct {
   int64_t outstanding;         /* submitted, not yet finished                                   */
   double clock;                /* server clock now, seconds                                     */
   uint64_t last_estimate_bytes;/* bytes reserved for the last hierarchy build (setup and         */
-                               /* instance workspace, before trimming the setup scratch)       */
+                               /* instance workspace)                                          */
+  double setup_seconds;        /* total and longest hierarchy build time                        */
+  double setup_seconds_max;
 } amamg_server_counters;
 
 void amamg_server_default_params(amamg_server_params *p);

@@ -63,7 +63,7 @@ class SolveInfo(C.Structure):
 
 class ServerParams(C.Structure):
     _fields_ = [("slots", C.c_int32), ("max_instances", C.c_int32), ("precision", C.c_int32),
-                ("restart", C.c_int32), ("max_iters", C.c_int32), ("reserved", C.c_int32),
+                ("restart", C.c_int32), ("max_iters", C.c_int32), ("builders", C.c_int32),
                 ("rel_tol", C.c_double), ("hbm_budget", C.c_uint64)]
 
 
@@ -78,7 +78,8 @@ class ServerCounters(C.Structure):
     _fields_ = [("setups", C.c_int64), ("evictions", C.c_int64), ("resident_bytes", C.c_uint64),
                 ("hierarchy_bytes", C.c_uint64),
                 ("peak_resident_bytes", C.c_uint64), ("budget_bytes", C.c_uint64),
-                ("outstanding", C.c_int64), ("clock", C.c_double), ("last_estimate_bytes", C.c_uint64)]
+                ("outstanding", C.c_int64), ("clock", C.c_double), ("last_estimate_bytes", C.c_uint64),
+                ("setup_seconds", C.c_double), ("setup_seconds_max", C.c_double)]
 
 
 _vp = C.c_void_p

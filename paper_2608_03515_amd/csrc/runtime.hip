@@ -210,9 +210,20 @@ size_t setup_bytes(int nt, int nx, const amamg_setup_params& p) {
 
 // ------------------------------------------------------------------------- GPU setup
 
-void run_setup(amamg_hierarchy* h) {
+// Buffers only the setup itself needs; with a scratch pool they live there (and are reused by
+// the next setup) instead of in the hierarchy.
+static bool setup_scratch(const char* name) {
+  static const char* names[] = {"A0", "d_offs5", "d_offs25", "L_tv", "Aug", "info", "Wc", "C_Adense",
+                                "pe", "py", "pz", "pu", "ppart", "Dg", "dinfo", "LUc", "cinfo", "keep"};
+  for (const char* n : names)
+    if (std::strcmp(n, name) == 0) return true;
+  return false;
+}
+
+void run_setup(amamg_hierarchy* h, hipStream_t stream, Pool* scratch) {
   amamg_gauge* gg = h->gauge;
-  hipStream_t s = gg->ctx->stream;
+  hipStream_t s = stream ? stream : gg->ctx->stream;
+  auto pool = [&](const char* name) -> Pool& { return scratch && setup_scratch(name) ? *scratch : h->mem; };
   const amamg_setup_params& p = h->prm;
   const auto plan = plan_levels(gg->nt, gg->nx, p);
   const int K = int(plan.size());
@@ -227,14 +238,14 @@ void run_setup(amamg_hierarchy* h) {
   const int nv = (p.norm == AMAMG_NORM_TESTVEC) ? p.n_test_vectors : 0;
 
   // fine operator in block-stencil form, used to gather the wirebasket systems
-  double2* A0 = h->mem.get<double2>("A0", -1, size_t(gg->nt) * gg->nx * 5 * 4);
+  double2* A0 = pool("A0").get<double2>("A0", -1, size_t(gg->nt) * gg->nx * 5 * 4);
   build_fine_stencil(s, U0, U1, gg->nt, gg->nx, h->m0, A0);
   const int offs5[10] = {0, 0, 1, 0, -1, 0, 0, 1, 0, -1};
   int offs25[50];
   for (int dt = -2, q = 0; dt <= 2; ++dt)
     for (int dx = -2; dx <= 2; ++dx, ++q) { offs25[2 * q] = dt; offs25[2 * q + 1] = dx; }
-  int* d_offs5 = h->mem.get<int>("d_offs5", -1, 10);
-  int* d_offs25 = h->mem.get<int>("d_offs25", -1, 50);
+  int* d_offs5 = pool("d_offs5").get<int>("d_offs5", -1, 10);
+  int* d_offs25 = pool("d_offs25").get<int>("d_offs25", -1, 50);
   HIPCHECK(hipMemcpyAsync(d_offs5, offs5, sizeof(offs5), hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(d_offs25, offs25, sizeof(offs25), hipMemcpyHostToDevice, s));
 
@@ -244,15 +255,15 @@ void run_setup(amamg_hierarchy* h) {
     const Geom& g = L.g;
     const int nnode = g.nnode();
     const int64_t ndof = g.ndof();
-    L.kind = h->mem.get<int8_t>("L_kind", k, nnode);
-    L.owner = h->mem.get<int>("L_owner", k, nnode);
-    L.node = h->mem.get<int>("L_node", k, nnode);
+    L.kind = pool("L_kind").get<int8_t>("L_kind", k, nnode);
+    L.owner = pool("L_owner").get<int>("L_owner", k, nnode);
+    L.node = pool("L_node").get<int>("L_node", k, nnode);
     classify(s, g, L.kind, L.owner, L.node);
     check_launch();
 
     // test vectors: random at level 0, injected from the finer level otherwise; nu sweeps
     if (nv > 0) {
-      L.tv = h->mem.get<double2>("L_tv", k, size_t(nv) * ndof);
+      L.tv = pool("L_tv").get<double2>("L_tv", k, size_t(nv) * ndof);
       if (k == 0) testvec_hash(s, p.seed, 0, nv, ndof, L.tv);
       else HIPCHECK(hipMemcpyAsync(L.tv, W, sizeof(double2) * nv * ndof, hipMemcpyDeviceToDevice, s));
       for (int sw = 0; sw < p.test_vector_sweeps; ++sw) {
@@ -270,16 +281,16 @@ void run_setup(amamg_hierarchy* h) {
     // local Schur-complement interpolation per wirebasket
     int nf = 0;
     const std::vector<int> tabs = footprint_tables(a, o, g.b, &nf);
-    int* d_tabs = h->mem.get<int>("d_tabs", k, tabs.size());
+    int* d_tabs = pool("d_tabs").get<int>("d_tabs", k, tabs.size());
     L.tabs = d_tabs;
     L.nf = nf;
-    L.rows = h->mem.get<int>("L_rows", k, size_t(g.nI) * g.nJ * nf * g.b);
-    L.nrows = h->mem.get<int>("L_nrows", k, size_t(g.nI) * g.nJ);
+    L.rows = pool("L_rows").get<int>("L_rows", k, size_t(g.nI) * g.nJ * nf * g.b);
+    L.nrows = pool("L_nrows").get<int>("L_nrows", k, size_t(g.nI) * g.nJ);
     HIPCHECK(hipMemcpyAsync(d_tabs, tabs.data(), sizeof(int) * tabs.size(), hipMemcpyHostToDevice, s));
     owned_rows(s, g, d_tabs + g.fp(), nf, L.owner, L.rows, L.nrows);
     const int nW = g.nI * g.nJ, nfd = nf * g.b, ncol = g.ncol();
-    double2* Aug = h->mem.get<double2>("Aug", k, size_t(nW) * nfd * (nfd + ncol));
-    int* info = h->mem.get<int>("info", k, nW);
+    double2* Aug = pool("Aug").get<double2>("Aug", k, size_t(nW) * nfd * (nfd + ncol));
+    int* info = pool("info").get<int>("info", k, nW);
     if (k == 0) gather_local(s, g, A0, 5, d_offs5, d_tabs, nf, Aug);
     else gather_local(s, g, L.A, 25, d_offs25, d_tabs, nf, Aug);
     dense_solve(s, Aug, nfd, ncol, nW, info);
@@ -290,7 +301,7 @@ void run_setup(amamg_hierarchy* h) {
     for (int w = 0; w < nW; ++w)
       REQUIRE(hinfo[w] == 0, AMAMG_ERR_SINGULAR_LOCAL,
               "zero pivot in the local system of wirebasket " + std::to_string(w) + " on level " + std::to_string(k));
-    L.P = h->mem.get<double2>("L_P", k, size_t(ndof) * ncol);
+    L.P = pool("L_P").get<double2>("L_P", k, size_t(ndof) * ncol);
     HIPCHECK(hipMemsetAsync(L.P, 0, sizeof(double2) * ndof * ncol, s));
     scatter_P(s, g, Aug, d_tabs, nf, L.owner, L.P);
     check_launch();
@@ -300,7 +311,7 @@ void run_setup(amamg_hierarchy* h) {
     const Geom gc = coarse_geom_of(g);
     const int64_t ndof_c = gc.ndof();
     if (nv > 0) {
-      Wc = h->mem.get<double2>("Wc", k, size_t(nv) * ndof_c);
+      Wc = pool("Wc").get<double2>("Wc", k, size_t(nv) * ndof_c);
       inject(s, g, L.node, L.kind, L.tv, Wc, nv);
     }
     normalise(s, g, L.P, L.owner, L.tv, Wc, nv, p.norm);
@@ -315,19 +326,19 @@ void run_setup(amamg_hierarchy* h) {
     const int pt = period_of(gc.Lt), px = period_of(gc.Lx);
     double2* out = nullptr;
     if (dense) {
-      C.Adense = h->mem.get<double2>("C_Adense", k, size_t(ndof_c) * ndof_c);
+      C.Adense = pool("C_Adense").get<double2>("C_Adense", k, size_t(ndof_c) * ndof_c);
       out = C.Adense;
       HIPCHECK(hipMemsetAsync(out, 0, sizeof(double2) * ndof_c * ndof_c, s));
     } else {
-      C.A = h->mem.get<double2>("C_A", k, size_t(nnc) * 25 * bc * bc);
+      C.A = pool("C_A").get<double2>("C_A", k, size_t(nnc) * 25 * bc * bc);
       out = C.A;
       HIPCHECK(hipMemsetAsync(out, 0, sizeof(double2) * nnc * 25 * bc * bc, s));
     }
-    double2* pe = h->mem.get<double2>("pe", k, size_t(bc) * ndof_c);
-    double2* py = h->mem.get<double2>("py", k, size_t(bc) * ndof);
-    double2* pz = h->mem.get<double2>("pz", k, size_t(bc) * ndof);
-    double2* pu = h->mem.get<double2>("pu", k, size_t(bc) * ndof_c);
-    double2* ppart = h->mem.get<double2>("ppart", k, size_t(bc) * g.nI * g.nJ * restrict_chunks(g, nf, F64) * g.ncol());
+    double2* pe = pool("pe").get<double2>("pe", k, size_t(bc) * ndof_c);
+    double2* py = pool("py").get<double2>("py", k, size_t(bc) * ndof);
+    double2* pz = pool("pz").get<double2>("pz", k, size_t(bc) * ndof);
+    double2* pu = pool("pu").get<double2>("pu", k, size_t(bc) * ndof_c);
+    double2* ppart = pool("ppart").get<double2>("ppart", k, size_t(bc) * g.nI * g.nJ * restrict_chunks(g, nf, F64) * g.ncol());
     for (int ct = 0; ct < pt; ++ct)
       for (int cx = 0; cx < px; ++cx) {
         probe_make(s, gc, pt, px, ct, cx, pe);
@@ -343,9 +354,9 @@ void run_setup(amamg_hierarchy* h) {
 
     // smoother blocks of the next level, or the coarsest inverse
     if (!dense) {
-      C.Dinv = h->mem.get<double2>("C_Dinv", k, size_t(nnc) * bc * bc);
-      double2* Dg = h->mem.get<double2>("Dg", k, size_t(nnc) * bc * 2 * bc);
-      int* dinfo = h->mem.get<int>("dinfo", k, nnc);
+      C.Dinv = pool("C_Dinv").get<double2>("C_Dinv", k, size_t(nnc) * bc * bc);
+      double2* Dg = pool("Dg").get<double2>("Dg", k, size_t(nnc) * bc * 2 * bc);
+      int* dinfo = pool("dinfo").get<int>("dinfo", k, nnc);
       aug_identity(s, C.A + 12 * bc * bc, int64_t(25) * bc * bc, bc, bc, Dg, nnc);
       dense_solve(s, Dg, bc, bc, nnc, dinfo);
       aug_extract(s, Dg, bc, bc, C.Dinv, nnc);
@@ -357,11 +368,11 @@ void run_setup(amamg_hierarchy* h) {
         REQUIRE(hd[n] == 0, AMAMG_ERR_SINGULAR_LOCAL, "singular diagonal block on level " + std::to_string(k + 1));
     } else {
       const int n = int(ndof_c);
-      double2* LUc = h->mem.get<double2>("LUc", k, size_t(n) * 2 * n);
-      int* cinfo = h->mem.get<int>("cinfo", k, 1);
+      double2* LUc = pool("LUc").get<double2>("LUc", k, size_t(n) * 2 * n);
+      int* cinfo = pool("cinfo").get<int>("cinfo", k, 1);
       aug_identity(s, C.Adense, 0, n, n, LUc, 1);
       dense_solve(s, LUc, n, n, 1, cinfo);
-      C.Ainv = h->mem.get<double2>("C_Ainv", k, size_t(n) * n);
+      C.Ainv = pool("C_Ainv").get<double2>("C_Ainv", k, size_t(n) * n);
       aug_extract(s, LUc, n, n, C.Ainv, 1);
       check_launch();
       int hc = 0;
@@ -372,7 +383,7 @@ void run_setup(amamg_hierarchy* h) {
     W = Wc;
     // the next level's test vectors must outlive this iteration's temporaries
     if (nv > 0 && !dense) {
-      double2* keep = h->mem.get<double2>("keep", k, size_t(nv) * ndof_c);
+      double2* keep = pool("keep").get<double2>("keep", k, size_t(nv) * ndof_c);
       HIPCHECK(hipMemcpyAsync(keep, Wc, sizeof(double2) * nv * ndof_c, hipMemcpyDeviceToDevice, s));
       W = keep;
     }
@@ -383,22 +394,27 @@ void run_setup(amamg_hierarchy* h) {
     LevelData& L = h->lv[k];
     if (L.P) {
       const int64_t n = L.g.ndof() * L.g.ncol();
-      L.P32 = h->mem.get<float2>("L_P32", k, n);
+      L.P32 = pool("L_P32").get<float2>("L_P32", k, n);
       cast_matrix(s, L.P, L.P32, n);
     }
     if (L.A) {
       const int64_t n = int64_t(L.g.nnode()) * 25 * L.g.b * L.g.b;
-      L.A32 = h->mem.get<float2>("L_A32", k, n);
+      L.A32 = pool("L_A32").get<float2>("L_A32", k, n);
       cast_matrix(s, L.A, L.A32, n);
     }
     if (L.Dinv) {
       const int64_t n = int64_t(L.g.nnode()) * L.g.b * L.g.b;
-      L.Dinv32 = h->mem.get<float2>("L_Dinv32", k, n);
+      L.Dinv32 = pool("L_Dinv32").get<float2>("L_Dinv32", k, n);
       cast_matrix(s, L.Dinv, L.Dinv32, n);
     }
   }
   check_launch();
   HIPCHECK(hipStreamSynchronize(s));
+  if (scratch)
+    for (LevelData& L : h->lv) {
+      L.tv = nullptr;
+      L.Adense = nullptr;
+    }
 }
 
 }  // namespace rt

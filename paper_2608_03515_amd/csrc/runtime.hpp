@@ -135,7 +135,12 @@ struct LevelData {
 struct Workspace {
   int cap = 0, m = 0, hist_cap = 0;
   Real prec = F64;
-  Arena mem;
+  std::vector<int64_t> shape;   // per-level unknowns and restriction partial counts it was sized for
+  // device buffers are carved from one block that only grows, so rebinding a workspace to
+  // another hierarchy frees nothing (hipFree would wait for the whole device)
+  void* block = nullptr;
+  size_t block_bytes = 0;
+  int host_cap = 0, host_hist = 0;   // sizes of the pinned mirrors
   double2 *V = nullptr, *w = nullptr, *H = nullptr, *g = nullptr, *sn = nullptr, *y = nullptr;
   double2 *part = nullptr, *hist = nullptr;
   double* cs = nullptr;
@@ -206,8 +211,10 @@ bool finite_all(const double* v, size_t n);
 int timer_start(amamg_context* ctx, hipStream_t s, int family, int step, int group, double bytes_per_rhs);
 void timer_stop(amamg_context* ctx, hipStream_t s, int rec);
 
-// setup (on the context stream, synchronous) with the hierarchy's mass h->m0
-void run_setup(amamg_hierarchy* h);
+// setup with the hierarchy's mass h->m0, synchronous on `stream` (null: the context stream);
+// with `scratch`, the setup's temporary buffers come from that pool (kept for the next setup)
+// and the hierarchy holds only what the solve uses
+void run_setup(amamg_hierarchy* h, hipStream_t stream = nullptr, Pool* scratch = nullptr);
 // device bytes a hierarchy of these parameters holds after setup (estimate, for admission)
 size_t setup_bytes(int nt, int nx, const amamg_setup_params& p);
 
@@ -217,7 +224,10 @@ const void* link0(amamg_gauge* g, LinkStore ls);
 const void* link1(amamg_gauge* g, LinkStore ls);
 
 // workspaces
+// (Re)allocate unless the workspace was sized for exactly this hierarchy shape, slot count,
+// restart length and precision (and at least this history length).
 void ensure_workspace(Workspace& ws, const amamg_hierarchy* h, int cap, int m, Real prec, int hist_cap);
+bool workspace_fits(const Workspace& ws, const amamg_hierarchy* h, int cap, int m, Real prec, int hist_cap);
 size_t workspace_bytes(const amamg_hierarchy* h, int cap, int m, Real prec, int hist_cap);
 
 // One batched FGMRES run over a workspace on one stream, driven from the host in steps:

@@ -51,7 +51,20 @@ struct CachedH {
   amamg_setup_params sp{};
   uint64_t last_use = 0;
   int users = 0;               // instances bound to it
+  bool fresh = true;           // built, not bound yet: not evicted before its requests run
   size_t bytes = 0;
+};
+
+// A hierarchy build handed to the builder thread, and its outcome.
+struct BuildJob {
+  int gauge = 0;
+  double m0 = 0;
+  amamg_setup_params sp{};
+  size_t need = 0;             // bytes reserved for it in the budget while it runs
+  amamg_hierarchy* h = nullptr;
+  amamg_status code = AMAMG_OK;
+  std::string msg;
+  double seconds = 0;
 };
 
 struct Instance {
@@ -91,24 +104,35 @@ struct amamg_server {
   amamg_context* ctx = nullptr;
   amamg_server_params prm{};
   Clock::time_point t0;
-  // shared with the callers (mu)
+  // shared with the callers and the builder (mu)
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_work, cv_done, cv_build;
   std::deque<Request*> incoming;
   std::deque<Request*> done;
   std::vector<amamg_gauge*> gauges;
+  std::deque<BuildJob> jobs, built;
   uint64_t next_id = 1;
   int64_t outstanding = 0;
-  bool stop = false;
+  bool stop = false, stop_builder = false;
   std::string err;
   int64_t setups = 0, evictions = 0;
   size_t resident = 0, peak_resident = 0, last_estimate = 0, hier_bytes = 0;
+  double setup_seconds = 0, setup_seconds_max = 0;
   // worker only
   std::thread worker;
   std::deque<Request*> queue;
   std::vector<std::unique_ptr<CachedH>> cache;
   std::vector<std::unique_ptr<Instance>> inst;
+  std::vector<BuildJob> building;     // builds in flight (keys and reserved bytes)
   uint64_t tick = 0;
+  // builders: one thread, stream and setup-scratch pool (reused from build to build) each
+  struct Builder {
+    std::thread th;
+    hipStream_t stream = nullptr;
+    Pool scratch;
+    size_t scratch_bytes = 0;   // (mu)
+  };
+  std::vector<std::unique_ptr<Builder>> builders;
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 };
@@ -125,10 +149,13 @@ amamg_solve_params solve_params(const amamg_server* S) {
   return p;
 }
 
-size_t resident_bytes(const amamg_server* S) {
+size_t resident_bytes(amamg_server* S) {
   size_t b = 0;
   for (const auto& c : S->cache) b += c->bytes;
-  for (const auto& I : S->inst) b += I->ws.mem.bytes + I->io.bytes;
+  for (const auto& I : S->inst) b += I->ws.block_bytes + I->io.bytes;
+  for (const BuildJob& j : S->building) b += j.need;
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (const auto& B : S->builders) b += B->scratch_bytes;
   return b;
 }
 
@@ -150,38 +177,23 @@ void finish(amamg_server* S, Request* R) {
   S->cv_done.notify_all();
 }
 
-// Setup scratch (local systems, probes, staging) is not needed by the solve; a cached
-// hierarchy keeps only its operators, interpolation and smoother blocks.
-void trim_setup_scratch(amamg_hierarchy* h) {
-  static const char* keep[] = {"L_kind", "L_owner", "L_node", "d_tabs", "L_rows", "L_nrows", "L_P",
-                               "C_A", "C_Dinv", "C_Ainv", "L_P32", "L_A32", "L_Dinv32"};
-  for (LevelData& L : h->lv) {
-    L.tv = nullptr;
-    L.Adense = nullptr;
-  }
-  auto& items = h->mem.items;
-  for (auto& it : items) {
-    const std::string name = it.key.substr(0, it.key.find('#'));
-    bool k = false;
-    for (const char* n : keep) k = k || name == n;
-    if (!k && it.p) {
-      (void)hipFree(it.p);
-      it.p = nullptr;
-      it.bytes = 0;
-    }
-  }
-  items.erase(std::remove_if(items.begin(), items.end(), [](const Pool::Item& it) { return !it.p; }),
-              items.end());
-}
-
 // Drop least recently used hierarchies that no instance holds until `need` more bytes fit.
 bool make_room(amamg_server* S, size_t need) {
   for (;;) {
     if (resident_bytes(S) + need <= S->prm.hbm_budget) return true;
     CachedH* victim = nullptr;
     for (const auto& c : S->cache)
-      if (c->users == 0 && (!victim || c->last_use < victim->last_use)) victim = c.get();
-    if (!victim) return false;
+      if (c->users == 0 && !c->fresh && (!victim || c->last_use < victim->last_use)) victim = c.get();
+    if (!victim) {
+      // release the hierarchy of the idle instance used least recently, then look again
+      Instance* idle = nullptr;
+      for (const auto& I : S->inst)
+        if (!I->busy() && I->ch && (!idle || I->ch->last_use < idle->ch->last_use)) idle = I.get();
+      if (!idle) return false;
+      idle->ch->users -= 1;
+      idle->ch = nullptr;
+      continue;
+    }
     victim->h->gauge->nhier -= 1;
     delete victim->h;
     S->cache.erase(std::find_if(S->cache.begin(), S->cache.end(),
@@ -198,12 +210,21 @@ size_t instance_estimate(const amamg_server* S, int64_t n) {
   return size_t(S->prm.slots) * n * (16 * size_t(m + 1) + zs * (m + 3) + 16 * 3);
 }
 
-// Hierarchy for the request's key: cached, or built now (synchronous setup on the server
-// context stream).  nullptr when the budget cannot be met at the moment.
-CachedH* hierarchy_for(amamg_server* S, Request* R, bool* built) {
-  *built = false;
+bool same_key(const CachedH& c, const Request* R) {
+  return c.gauge == R->gauge && c.m0 == R->m0 && same_params(c.sp, R->sp);
+}
+bool same_key(const BuildJob& j, const Request* R) {
+  return j.gauge == R->gauge && j.m0 == R->m0 && same_params(j.sp, R->sp);
+}
+
+CachedH* cached(amamg_server* S, const Request* R) {
   for (const auto& c : S->cache)
-    if (c->gauge == R->gauge && c->m0 == R->m0 && same_params(c->sp, R->sp)) return c.get();
+    if (same_key(*c, R)) return c.get();
+  return nullptr;
+}
+
+// Hand the request's hierarchy to the builder when the budget allows (false: not now).
+bool dispatch_build(amamg_server* S, Request* R) {
   amamg_gauge* g;
   {
     std::lock_guard<std::mutex> lk(S->mu);
@@ -214,32 +235,102 @@ CachedH* hierarchy_for(amamg_server* S, Request* R, bool* built) {
     std::lock_guard<std::mutex> lk(S->mu);
     S->last_estimate = need;
   }
-  if (!make_room(S, need)) return nullptr;
-  auto c = std::make_unique<CachedH>();
-  c->gauge = R->gauge;
-  c->m0 = R->m0;
-  c->sp = R->sp;
-  amamg_hierarchy* h = new amamg_hierarchy();
-  h->gauge = g;
-  h->m0 = R->m0;
-  h->prm = R->sp;
-  try {
-    run_setup(h);
-  } catch (...) {
-    delete h;
-    throw;
-  }
-  trim_setup_scratch(h);
-  g->nhier += 1;
-  c->h = h;
-  c->bytes = h->mem.bytes();
-  *built = true;
+  if (!make_room(S, need)) return false;
+  BuildJob j;
+  j.gauge = R->gauge;
+  j.m0 = R->m0;
+  j.sp = R->sp;
+  j.need = need;
+  S->building.push_back(j);
+  R->built = 1;
   {
     std::lock_guard<std::mutex> lk(S->mu);
-    S->setups += 1;
+    S->jobs.push_back(j);
   }
-  S->cache.push_back(std::move(c));
-  return S->cache.back().get();
+  S->cv_build.notify_one();
+  return true;
+}
+
+// Finished builds: cache the hierarchies, or fail the requests that wait for a failed one.
+bool collect_builds(amamg_server* S) {
+  std::deque<BuildJob> got;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    got.swap(S->built);
+  }
+  for (BuildJob& j : got) {
+    S->building.erase(std::find_if(S->building.begin(), S->building.end(), [&](const BuildJob& b) {
+      return b.gauge == j.gauge && b.m0 == j.m0 && same_params(b.sp, j.sp);
+    }));
+    if (j.h) {
+      auto c = std::make_unique<CachedH>();
+      c->h = j.h;
+      c->gauge = j.gauge;
+      c->m0 = j.m0;
+      c->sp = j.sp;
+      c->bytes = j.h->mem.bytes();
+      c->last_use = ++S->tick;
+      j.h->gauge->nhier += 1;
+      S->cache.push_back(std::move(c));
+      continue;
+    }
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->err = j.msg;
+    }
+    for (auto it = S->queue.begin(); it != S->queue.end();) {
+      Request* R = *it;
+      if (R->gauge == j.gauge && R->m0 == j.m0 && same_params(R->sp, j.sp)) {
+        R->status = j.code;
+        finish(S, R);
+        it = S->queue.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  return !got.empty();
+}
+
+void builder_main(amamg_server* S, amamg_server::Builder* B) {
+  (void)hipSetDevice(S->ctx->device);
+  for (;;) {
+    BuildJob j;
+    amamg_gauge* g;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_build.wait(lk, [&] { return !S->jobs.empty() || S->stop_builder; });
+      if (S->jobs.empty()) break;
+      j = S->jobs.front();
+      S->jobs.pop_front();
+      g = S->gauges[j.gauge];
+    }
+    const auto t0 = Clock::now();
+    amamg_hierarchy* h = new amamg_hierarchy();
+    h->gauge = g;
+    h->m0 = j.m0;
+    h->prm = j.sp;
+    try {
+      run_setup(h, B->stream, &B->scratch);
+      j.h = h;
+    } catch (const Fail& f) {
+      delete h;
+      j.code = f.code;
+      j.msg = f.msg;
+    }
+    j.seconds = std::chrono::duration<double>(Clock::now() - t0).count();
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (j.h) {
+        S->setups += 1;
+        S->setup_seconds += j.seconds;
+        S->setup_seconds_max = std::max(S->setup_seconds_max, j.seconds);
+      }
+      B->scratch_bytes = B->scratch.bytes();
+      S->built.push_back(j);
+    }
+    S->cv_work.notify_all();
+  }
 }
 
 void bind(amamg_server* S, Instance* I, CachedH* c) {
@@ -247,12 +338,13 @@ void bind(amamg_server* S, Instance* I, CachedH* c) {
   if (I->ch) I->ch->users -= 1;
   I->ch = c;
   c->users += 1;
+  c->fresh = false;
   amamg_hierarchy* h = c->h;
   const int64_t n = h->lv[0].g.ndof();
   const amamg_solve_params p = solve_params(S);
   ensure_workspace(I->ws, h, S->prm.slots, p.restart, p.precision == AMAMG_FP64 ? F64 : F32,
                    2 * p.max_iters + 2);
-  if (I->n_io != n) {
+  if (I->n_io < n) {
     I->io.release();
     I->B = I->io.alloc<double2>(size_t(S->prm.slots) * n);
     I->X = I->io.alloc<double2>(size_t(S->prm.slots) * n);
@@ -278,6 +370,7 @@ void begin_admission(amamg_server* S, Instance* I) {
       slots.push_back(s);
       ++k;
     }
+    REQUIRE(k == R->nrhs, AMAMG_ERR_INVALID_ARG, "internal: reserved slots are not free");
     R->remaining = R->nrhs;
   }
   I->reserved.clear();
@@ -353,22 +446,51 @@ void cycle_end(amamg_server* S, Instance* I) {
 }
 
 // Place queued requests: an instance bound to the request's hierarchy with room (joining at its
-// next boundary), else an idle or new instance rebound to it.
+// next boundary), else an idle or new instance rebound to it.  A request whose hierarchy is not
+// cached starts its build (if the budget allows) and waits for it.
 bool place(amamg_server* S) {
   bool did = false;
   for (auto it = S->queue.begin(); it != S->queue.end();) {
     Request* R = *it;
+    CachedH* c = cached(S, R);
+    if (!c) {
+      const bool in_flight = std::any_of(S->building.begin(), S->building.end(),
+                                         [&](const BuildJob& b) { return same_key(b, R); });
+      if (!in_flight) {
+        if (dispatch_build(S, R)) {
+          did = true;
+        } else if (S->building.empty() &&
+                   std::none_of(S->inst.begin(), S->inst.end(),
+                                [](const std::unique_ptr<Instance>& I) { return I->busy(); })) {
+          // nothing running or building will free memory: this request cannot be served
+          R->status = AMAMG_ERR_OUT_OF_MEMORY;
+          finish(S, R);
+          it = S->queue.erase(it);
+          did = true;
+          continue;
+        }
+      }
+      ++it;
+      continue;
+    }
     Instance* target = nullptr;
     for (const auto& I : S->inst)
-      if (I->ch && I->ch->gauge == R->gauge && I->ch->m0 == R->m0 && same_params(I->ch->sp, R->sp) &&
-          I->free_slots() >= R->nrhs) {
+      if (I->ch == c && I->free_slots() >= R->nrhs) {
         target = I.get();
         break;
       }
     if (!target) {
+      // an idle instance already bound to it, else the idle one used least recently
       Instance* idle = nullptr;
-      for (const auto& I : S->inst)
-        if (!I->busy() && (!idle || (I->ch && idle->ch && I->ch->last_use < idle->ch->last_use))) idle = I.get();
+      auto lru = [](const Instance* I) { return I->ch ? I->ch->last_use : uint64_t(0); };
+      for (const auto& I : S->inst) {
+        if (I->busy()) continue;
+        if (I->ch == c) {
+          idle = I.get();
+          break;
+        }
+        if (!idle || lru(I.get()) < lru(idle)) idle = I.get();
+      }
       if (!idle && int(S->inst.size()) < S->prm.max_instances) {
         auto I = std::make_unique<Instance>();
         I->id = int(S->inst.size());
@@ -379,50 +501,16 @@ bool place(amamg_server* S) {
         idle = S->inst.back().get();
       }
       if (idle) {
-        bool built = false;
-        // the idle instance's current hierarchy may be evicted to make room
-        if (idle->ch) {
-          idle->ch->users -= 1;
-          idle->ch = nullptr;
-        }
-        CachedH* c = nullptr;
-        try {
-          c = hierarchy_for(S, R, &built);
-        } catch (const Fail& f) {
-          if (f.code == AMAMG_ERR_DEVICE) throw;
-          // this request's setup failed (singular local system, no memory): only it fails
-          R->status = f.code;
-          {
-            std::lock_guard<std::mutex> lk(S->mu);
-            S->err = f.msg;
-          }
-          finish(S, R);
-          it = S->queue.erase(it);
-          did = true;
-          continue;
-        }
-        if (c) {
-          bind(S, idle, c);
-          R->built = built ? 1 : 0;
-          target = idle;
-        }
+        bind(S, idle, c);
+        target = idle;
       }
     }
     if (!target) {
-      const bool any_busy = std::any_of(S->inst.begin(), S->inst.end(),
-                                        [](const std::unique_ptr<Instance>& I) { return I->busy(); });
-      if (!any_busy && S->inst.size() > 0) {
-        // nothing running will free memory: this request cannot be served
-        R->status = AMAMG_ERR_OUT_OF_MEMORY;
-        finish(S, R);
-        it = S->queue.erase(it);
-        did = true;
-        continue;
-      }
       ++it;
       continue;
     }
     target->reserved.push_back(R);
+    c->last_use = ++S->tick;
     if (target->phase == Instance::IDLE) begin_admission(S, target);
     it = S->queue.erase(it);
     did = true;
@@ -487,12 +575,14 @@ void worker_main(amamg_server* S) {
       }
       stopping = S->stop;
     }
-    const bool busy = std::any_of(S->inst.begin(), S->inst.end(),
+    const bool busy = !S->building.empty() ||
+                      std::any_of(S->inst.begin(), S->inst.end(),
                                   [](const std::unique_ptr<Instance>& I) { return I->busy(); });
     if (stopping && S->queue.empty() && !busy) break;
     bool did = false;
     try {
-      did = progress(S);
+      did = collect_builds(S);
+      did = progress(S) || did;
       did = place(S) || did;
     } catch (const Fail& f) {
       fail_all(S, f);
@@ -500,9 +590,9 @@ void worker_main(amamg_server* S) {
     }
     if (did) continue;
     std::unique_lock<std::mutex> lk(S->mu);
-    if (!S->incoming.empty() || (S->stop && S->queue.empty() && !busy)) continue;
+    if (!S->incoming.empty() || !S->built.empty() || (S->stop && S->queue.empty() && !busy)) continue;
     if (busy) S->cv_work.wait_for(lk, std::chrono::microseconds(100));
-    else S->cv_work.wait(lk, [&] { return !S->incoming.empty() || S->stop; });
+    else S->cv_work.wait(lk, [&] { return !S->incoming.empty() || !S->built.empty() || S->stop; });
   }
 }
 
@@ -519,7 +609,7 @@ void amamg_server_default_params(amamg_server_params* p) {
   p->precision = AMAMG_MIXED_FP32;
   p->restart = 20;
   p->max_iters = 10000;
-  p->reserved = 0;
+  p->builders = 2;
   p->rel_tol = 1e-10;
   p->hbm_budget = 0;
 }
@@ -532,7 +622,7 @@ amamg_status amamg_server_create(int32_t device, const amamg_server_params* para
   else amamg_server_default_params(&p);
   if (p.slots < 1 || p.slots > 256 || p.max_instances < 1 || p.max_instances > 16 || p.restart < 1 ||
       p.restart > 31 || p.max_iters < 1 || !(p.rel_tol > 0) || !std::isfinite(p.rel_tol) ||
-      p.precision < 0 || p.precision > 2)
+      p.precision < 0 || p.precision > 2 || p.builders < 1 || p.builders > 8)
     return AMAMG_ERR_INVALID_ARG;
   amamg_context* ctx = nullptr;
   const amamg_status st = amamg_context_create(device, nullptr, &ctx);
@@ -549,6 +639,17 @@ amamg_status amamg_server_create(int32_t device, const amamg_server_params* para
   S->ctx = ctx;
   S->prm = p;
   S->t0 = Clock::now();
+  for (int k = 0; k < p.builders; ++k) {
+    auto B = std::make_unique<amamg_server::Builder>();
+    if (hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) != hipSuccess) {
+      for (auto& b : S->builders) (void)hipStreamDestroy(b->stream);
+      amamg_context_destroy(ctx);
+      delete S;
+      return AMAMG_ERR_DEVICE;
+    }
+    S->builders.push_back(std::move(B));
+  }
+  for (auto& B : S->builders) B->th = std::thread(builder_main, S, B.get());
   S->worker = std::thread(worker_main, S);
   *out = S;
   return AMAMG_OK;
@@ -670,6 +771,8 @@ amamg_status amamg_server_stats(amamg_server* S, amamg_server_counters* out) {
   out->outstanding = S->outstanding;
   out->clock = S->now();
   out->last_estimate_bytes = S->last_estimate;
+  out->setup_seconds = S->setup_seconds;
+  out->setup_seconds_max = S->setup_seconds_max;
   return AMAMG_OK;
 }
 
@@ -687,6 +790,17 @@ amamg_status amamg_server_destroy(amamg_server* S) {
   }
   S->cv_work.notify_all();
   S->worker.join();          // drains every submitted request first
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop_builder = true;
+  }
+  S->cv_build.notify_all();
+  for (auto& B : S->builders) B->th.join();
+  for (BuildJob& j : S->built)
+    if (j.h) delete j.h;
+  S->built.clear();
+  for (auto& B : S->builders) (void)hipStreamDestroy(B->stream);
+  S->builders.clear();         // frees the builders' scratch pools
   for (auto& I : S->inst) {
     (void)hipStreamSynchronize(I->stream);
     I->ws.release();

@@ -31,17 +31,21 @@ static int krylov_blocks(int64_t n, int nrhs) {
 Workspace::~Workspace() { release(); }
 
 void Workspace::release() {
-  mem.release();
+  if (block) (void)hipFree(block);
   if (hst) (void)hipHostFree(hst);
   if (hst2) (void)hipHostFree(hst2);
   if (hadmit) (void)hipHostFree(hadmit);
   if (hhist) (void)hipHostFree(hhist);
   if (ev) (void)hipEventDestroy(ev);
+  block = nullptr;
+  block_bytes = 0;
   hst = hst2 = nullptr;
   hadmit = nullptr;
   hhist = nullptr;
+  host_cap = host_hist = 0;
   ev = nullptr;
   lv.clear();
+  shape.clear();
   cap = m = hist_cap = 0;
 }
 
@@ -61,41 +65,91 @@ size_t workspace_bytes(const amamg_hierarchy* h, int cap, int m, Real prec, int 
   return b;
 }
 
-void ensure_workspace(Workspace& ws, const amamg_hierarchy* h, int cap, int m, Real prec, int hist_cap) {
-  if (ws.cap >= cap && ws.m >= m && ws.prec == prec && ws.hist_cap >= hist_cap &&
-      ws.lv.size() == h->lv.size())
-    return;
-  ws.release();
+static std::vector<int64_t> shape_of(const amamg_hierarchy* h, Real prec) {
+  std::vector<int64_t> s;
+  for (size_t k = 0; k < h->lv.size(); ++k) {
+    s.push_back(h->lv[k].g.ndof());
+    s.push_back(k + 1 < h->lv.size() ? int64_t(level_rpart_count(h->lv[k], prec)) : 0);
+  }
+  return s;
+}
+
+bool workspace_fits(const Workspace& ws, const amamg_hierarchy* h, int cap, int m, Real prec, int hist_cap) {
+  return ws.cap == cap && ws.m == m && ws.prec == prec && ws.hist_cap >= hist_cap &&
+         ws.shape == shape_of(h, prec);
+}
+
+// Device layout of a workspace; `take` hands out 256-byte aligned ranges of the block.
+template <typename Take>
+static void layout(Workspace& ws, const amamg_hierarchy* h, int cap, int m, Real prec, int hist_cap, Take take) {
   const int64_t n = h->lv[0].g.ndof();
   const size_t rs = prec == F64 ? sizeof(double2) : sizeof(float2);
-  ws.V = ws.mem.alloc<double2>(size_t(m + 1) * cap * n);
-  ws.Z = ws.mem.alloc<char>(size_t(m) * cap * n * rs);
-  ws.w = ws.mem.alloc<double2>(size_t(cap) * n);
-  ws.H = ws.mem.alloc<double2>(size_t(cap) * (m + 1) * m);
-  ws.g = ws.mem.alloc<double2>(size_t(cap) * (m + 1));
-  ws.cs = ws.mem.alloc<double>(size_t(cap) * m);
-  ws.sn = ws.mem.alloc<double2>(size_t(cap) * m);
-  ws.y = ws.mem.alloc<double2>(size_t(cap) * m);
-  ws.part = ws.mem.alloc<double2>(size_t(3) * cap * kMaxKrylovBlocks * 32);
-  ws.st = ws.mem.alloc<RhsState>(cap);
-  ws.st2 = ws.mem.alloc<RhsState>(cap);
-  ws.admit = ws.mem.alloc<int>(cap);
-  ws.hist = ws.mem.alloc<double2>(size_t(cap) * hist_cap);
+  ws.V = (double2*)take(sizeof(double2) * size_t(m + 1) * cap * n);
+  ws.Z = take(size_t(m) * cap * n * rs);
+  ws.w = (double2*)take(sizeof(double2) * size_t(cap) * n);
+  ws.H = (double2*)take(sizeof(double2) * size_t(cap) * (m + 1) * m);
+  ws.g = (double2*)take(sizeof(double2) * size_t(cap) * (m + 1));
+  ws.cs = (double*)take(sizeof(double) * size_t(cap) * m);
+  ws.sn = (double2*)take(sizeof(double2) * size_t(cap) * m);
+  ws.y = (double2*)take(sizeof(double2) * size_t(cap) * m);
+  ws.part = (double2*)take(sizeof(double2) * size_t(3) * cap * kMaxKrylovBlocks * 32);
+  ws.st = (RhsState*)take(sizeof(RhsState) * cap);
+  ws.st2 = (RhsState*)take(sizeof(RhsState) * cap);
+  ws.admit = (int*)take(sizeof(int) * cap);
+  ws.hist = (double2*)take(sizeof(double2) * size_t(cap) * hist_cap);
   ws.lv.assign(h->lv.size(), Workspace::Lev{});
   for (size_t k = 1; k < h->lv.size(); ++k) {
     const int64_t nd = h->lv[k].g.ndof();
-    ws.lv[k].f = ws.mem.alloc<char>(size_t(cap) * nd * rs);
-    ws.lv[k].x = ws.mem.alloc<char>(size_t(cap) * nd * rs);
-    ws.lv[k].tmp = ws.mem.alloc<char>(size_t(cap) * nd * rs);
+    ws.lv[k].f = take(size_t(cap) * nd * rs);
+    ws.lv[k].x = take(size_t(cap) * nd * rs);
+    ws.lv[k].tmp = take(size_t(cap) * nd * rs);
   }
-  ws.lv[0].tmp = ws.mem.alloc<char>(size_t(cap) * n * rs);
+  ws.lv[0].tmp = take(size_t(cap) * n * rs);
   for (size_t k = 0; k + 1 < h->lv.size(); ++k)
-    ws.lv[k].rpart = ws.mem.alloc<char>(size_t(cap) * level_rpart_count(h->lv[k], prec) * rs);
-  HIPCHECK(hipHostMalloc((void**)&ws.hst, sizeof(RhsState) * cap, hipHostMallocDefault));
-  HIPCHECK(hipHostMalloc((void**)&ws.hst2, sizeof(RhsState) * cap, hipHostMallocDefault));
-  HIPCHECK(hipHostMalloc((void**)&ws.hadmit, sizeof(int) * cap, hipHostMallocDefault));
-  HIPCHECK(hipHostMalloc((void**)&ws.hhist, sizeof(double2) * size_t(cap) * hist_cap, hipHostMallocDefault));
-  HIPCHECK(hipEventCreateWithFlags(&ws.ev, hipEventDisableTiming));
+    ws.lv[k].rpart = take(size_t(cap) * level_rpart_count(h->lv[k], prec) * rs);
+}
+
+void ensure_workspace(Workspace& ws, const amamg_hierarchy* h, int cap, int m, Real prec, int hist_cap) {
+  if (workspace_fits(ws, h, cap, m, prec, hist_cap)) return;
+  size_t off = 0;
+  char* base = nullptr;
+  auto take = [&](size_t bytes) -> void* {
+    off = (off + 255) & ~size_t(255);
+    void* p = base ? base + off : nullptr;
+    off += std::max<size_t>(bytes, 1);
+    return p;
+  };
+  layout(ws, h, cap, m, prec, hist_cap, take);      // sizes only
+  if (ws.block_bytes < off) {
+    if (ws.block) (void)hipFree(ws.block);
+    ws.block = nullptr;
+    ws.block_bytes = 0;
+    HIPCHECK(hipMalloc(&ws.block, off));
+    ws.block_bytes = off;
+  }
+  base = static_cast<char*>(ws.block);
+  off = 0;
+  layout(ws, h, cap, m, prec, hist_cap, take);
+  if (ws.host_cap < cap) {
+    if (ws.hst) (void)hipHostFree(ws.hst);
+    if (ws.hst2) (void)hipHostFree(ws.hst2);
+    if (ws.hadmit) (void)hipHostFree(ws.hadmit);
+    ws.hst = ws.hst2 = nullptr;
+    ws.hadmit = nullptr;
+    ws.host_cap = 0;
+    HIPCHECK(hipHostMalloc((void**)&ws.hst, sizeof(RhsState) * cap, hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc((void**)&ws.hst2, sizeof(RhsState) * cap, hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc((void**)&ws.hadmit, sizeof(int) * cap, hipHostMallocDefault));
+    ws.host_cap = cap;
+  }
+  if (size_t(ws.host_hist) < size_t(cap) * hist_cap) {
+    if (ws.hhist) (void)hipHostFree(ws.hhist);
+    ws.hhist = nullptr;
+    ws.host_hist = 0;
+    HIPCHECK(hipHostMalloc((void**)&ws.hhist, sizeof(double2) * size_t(cap) * hist_cap, hipHostMallocDefault));
+    ws.host_hist = cap * hist_cap;
+  }
+  if (!ws.ev) HIPCHECK(hipEventCreateWithFlags(&ws.ev, hipEventDisableTiming));
   // every slot starts free (inactive, done)
   std::memset(ws.hst, 0, sizeof(RhsState) * cap);
   for (int r = 0; r < cap; ++r) ws.hst[r].done = 1;
@@ -104,6 +158,7 @@ void ensure_workspace(Workspace& ws, const amamg_hierarchy* h, int cap, int m, R
   ws.m = m;
   ws.prec = prec;
   ws.hist_cap = hist_cap;
+  ws.shape = shape_of(h, prec);
 }
 
 // ------------------------------------------------------------------------------ V-cycle
@@ -225,6 +280,8 @@ static KrylovDims dims(const Batch& bt) {
 void Batch::init(amamg_hierarchy* h_, Workspace* ws_, hipStream_t s_, const amamg_solve_params& p_,
                  const double2* b_, double2* x_, int group_) {
   h = h_; ws = ws_; s = s_; p = p_; b = b_; x = x_; group = group_;
+  REQUIRE(workspace_fits(*ws, h, ws->cap, p.restart, p.precision == AMAMG_FP64 ? F64 : F32, 2 * p.max_iters + 2),
+          AMAMG_ERR_INVALID_ARG, "workspace does not match the hierarchy and solve parameters");
   cycle_in.assign(ws->cap, 0);
   pending.clear();
   cycle_enqueued = false;
@@ -431,8 +488,7 @@ amamg_status run_solve(amamg_hierarchy* h, int nrhs, const double2* b, double2* 
   for (int g = 0; g < G; ++g) {
     const int q = off[g + 1] - off[g];
     Workspace& ws = *h->ws[g];
-    // a workspace is reused only at exactly this slot count: the reduction blocking depends on it
-    if (ws.cap != q) ws.release();
+    // reused only at exactly this slot count (the reduction blocking depends on it) and shape
     ensure_workspace(ws, h, q, p.restart, T, hist_cap);
   }
   for (int g = 0; g < G; ++g) {

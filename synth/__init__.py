@@ -24,7 +24,8 @@ import numpy as np
 
 __all__ = ["gen_theta", "gen_links", "gaussian_rhs", "plaquette_angles",
            "Workload", "WORKLOADS", "critical_masses", "links_to_abi", "field_to_abi",
-           "field_from_abi"]
+           "field_from_abi", "SERVING_SIZES", "SERVING_MASSES", "serving_setup", "serving_configs",
+           "serving_links", "request_stream"]
 
 
 def plaquette_angles(theta: np.ndarray) -> np.ndarray:
@@ -148,3 +149,50 @@ def critical_masses() -> dict:
     """
     with open(_GOLDEN) as f:
         return json.load(f)
+
+
+# ------------------------------------------------------------------------- serving workload
+
+SERVING_SIZES = (32, 64, 128, 256, 512)
+SERVING_MASSES = (0.05, 0.1, 0.2)
+
+
+def serving_setup(L: int) -> dict:
+    """AM-AMG setup parameters used for an L x L serving lattice (the configurations above at
+    their sizes; 512 keeps a = 8, o = 2 with a 2048-unknown coarsest level)."""
+    if L <= 32:
+        return dict(levels=2, agg_size=4, overlap=1, n_test_vectors=4)
+    if L <= 64:
+        return dict(levels=3, agg_size=4, overlap=1, n_test_vectors=8)
+    return dict(levels=3, agg_size=8, overlap=2, n_test_vectors=8)
+
+
+def serving_configs(n: int = 16, seed: int = 5005, sweeps: int = 50) -> list:
+    """n gauge configurations: the first five cover every size once, the rest draw L uniformly;
+    beta uniform in [2, 10]; Metropolis from a cold start with its own seed."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n):
+        L = SERVING_SIZES[i] if i < len(SERVING_SIZES) else int(rng.choice(SERVING_SIZES))
+        out.append({"L": L, "beta": float(rng.uniform(2.0, 10.0)), "sweeps": sweeps,
+                    "seed": seed + 1 + i})
+    return out
+
+
+def serving_links(cfg: dict) -> np.ndarray:
+    return gen_links(cfg["L"], cfg["L"], cfg["beta"], cfg["sweeps"], cfg["seed"])
+
+
+def request_stream(n: int, qps: float, n_configs: int, seed: int = 6006, max_rhs: int = 8) -> list:
+    """Open-loop arrivals: exponential gaps of mean 1 / qps; per request a uniform configuration,
+    a mass from SERVING_MASSES and 1..max_rhs right-hand sides.  Returns dicts with the
+    arrival time, configuration index, mass, nrhs and a seed for its right-hand sides."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += float(rng.exponential(1.0 / qps))
+        out.append({"t": t, "config": int(rng.integers(n_configs)),
+                    "m0": float(rng.choice(SERVING_MASSES)), "nrhs": int(rng.integers(1, max_rhs + 1)),
+                    "seed": int(rng.integers(1 << 30))})
+    return out

@@ -127,8 +127,9 @@ def test_server_evicts_under_a_small_budget_and_rebuilds(lib):
     sp = lib.default_setup_params(**SETUP)
     psi = synth.field_to_abi(synth.gaussian_rhs(32, 32, 33, nrhs=1))
     masses = (0.15, 0.3, 0.15)
-    # reference: ample budget, one request at a time
-    srv = make_server(lib)
+    # reference: ample budget, one request at a time; one builder, so that the setup scratch
+    # held by the server is the same in both runs
+    srv = make_server(lib, builders=1)
     g = srv.add_gauge(synth.links_to_abi(Us[1]))
     ref = []
     for m0 in masses:
@@ -144,7 +145,7 @@ def test_server_evicts_under_a_small_budget_and_rebuilds(lib):
     # room for one hierarchy only: a build needs workspace + estimate, which fits only after
     # the other hierarchy is evicted
     budget = work + st.last_estimate_bytes + one // 2
-    srv = make_server(lib, hbm_budget=budget)
+    srv = make_server(lib, hbm_budget=budget, builders=1)
     g = srv.add_gauge(synth.links_to_abi(Us[1]))
     for k, m0 in enumerate(masses):
         srv.submit(g, m0, psi, sp)
@@ -162,4 +163,31 @@ def test_server_evicts_under_a_small_budget_and_rebuilds(lib):
     assert srv.wait(60)
     (info, _), = srv.poll()
     assert info.status == lib.STATUS_CODES["OUT_OF_MEMORY"]
+    srv.close()
+
+
+def test_one_instance_rebound_across_lattice_sizes(lib):
+    """A single solver instance serves requests on lattices of different sizes in turn (same
+    and different level counts): its workspace is resized for every hierarchy it is bound to."""
+    cases = [(synth.WORKLOADS["C1"].links(), 0.1, dict(levels=2, agg_size=4, overlap=1, n_test_vectors=4)),
+             (synth.gen_links(32, 32, 4.0, 60, 321), 0.15, dict(levels=2, agg_size=4, overlap=1, n_test_vectors=4)),
+             (synth.gen_links(64, 64, 6.0, 60, 654), 0.1, dict(levels=3, agg_size=4, overlap=1, n_test_vectors=8))]
+    srv = make_server(lib, max_instances=1)
+    gids = [srv.add_gauge(synth.links_to_abi(U)) for U, _, _ in cases]
+    for k in (0, 1, 2, 1, 0):
+        U, m0, sp = cases[k]
+        L = U.shape[1]
+        psi = synth.gaussian_rhs(L, L, 40 + k, nrhs=2)
+        say("rebind", L)
+        srv.submit(gids[k], m0, synth.field_to_abi(psi), lib.default_setup_params(**sp))
+        assert srv.wait(120)
+        (info, x), = srv.poll()
+        assert info.status == lib.OK and info.instance == 0
+        x = synth.field_from_abi(x)
+        prm = amg.SetupParams(levels=sp["levels"], agg=sp["agg_size"], overlap=sp["overlap"],
+                              n_test_vectors=sp["n_test_vectors"])
+        levels = None
+        for r in range(2):
+            xo, io, levels = oracle_solve(U, m0, psi[r], prm, levels=levels)
+            assert rel(x[r], xo) <= 1e-9
     srv.close()
