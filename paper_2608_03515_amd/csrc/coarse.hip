@@ -175,7 +175,7 @@ static void gs_b(hipStream_t s, const void* A, const void* D, void* x, const voi
                  int colour, int nrhs, int64_t stride, const RhsState* st) {
   const int ncn = (Lt / 4) * (Lx / 4);
   dim3 g(unsigned((ncn + Lanes<B>::NPB - 1) / Lanes<B>::NPB), unsigned(nrhs));
-  hipLaunchKernelGGL((k_stencil_gs<B, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
+  AMAMG_LAUNCH((k_stencil_gs<B, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
                      (const V*)f, Lt, Lx, colour, stride, st);
 }
 

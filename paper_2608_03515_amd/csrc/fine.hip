@@ -203,11 +203,11 @@ static void wilson_apply_t(hipStream_t s, const void* U0, const void* U1, const 
                            const RhsState* st) {
   if (nx >= 64) {
     dim3 g(unsigned(((nx + 63) / 64) * ((nt + 3) / 4)), unsigned(nrhs));
-    hipLaunchKernelGGL((k_wilson_apply<64, R, L, Vin, Vout>), g, dim3(256), 0, s, (const L*)U0,
+    AMAMG_LAUNCH((k_wilson_apply<64, R, L, Vin, Vout>), g, dim3(256), 0, s, (const L*)U0,
                        (const L*)U1, (const Vin*)x, (Vout*)y, b, nt, nx, R(m0 + 2.0), stride, st);
   } else {
     dim3 g(unsigned(((nx + 15) / 16) * ((nt + 15) / 16)), unsigned(nrhs));
-    hipLaunchKernelGGL((k_wilson_apply<16, R, L, Vin, Vout>), g, dim3(256), 0, s, (const L*)U0,
+    AMAMG_LAUNCH((k_wilson_apply<16, R, L, Vin, Vout>), g, dim3(256), 0, s, (const L*)U0,
                        (const L*)U1, (const Vin*)x, (Vout*)y, b, nt, nx, R(m0 + 2.0), stride, st);
   }
 }
@@ -236,11 +236,11 @@ static void wilson_gs_t(hipStream_t s, const void* U0, const void* U1, void* x, 
                         const RhsState* st) {
   if (nx >= 64) {
     dim3 g(unsigned(((nx + 63) / 64) * ((nt + 7) / 8)), unsigned(nrhs));
-    hipLaunchKernelGGL((k_wilson_gs<64, R, L, Vx>), g, dim3(256), 0, s, (const L*)U0, (const L*)U1,
+    AMAMG_LAUNCH((k_wilson_gs<64, R, L, Vx>), g, dim3(256), 0, s, (const L*)U0, (const L*)U1,
                        (Vx*)x, b, nt, nx, R(1.0 / (m0 + 2.0)), colour, stride, st);
   } else {
     dim3 g(unsigned(((nx + 15) / 16) * ((nt + 31) / 32)), unsigned(nrhs));
-    hipLaunchKernelGGL((k_wilson_gs<16, R, L, Vx>), g, dim3(256), 0, s, (const L*)U0, (const L*)U1,
+    AMAMG_LAUNCH((k_wilson_gs<16, R, L, Vx>), g, dim3(256), 0, s, (const L*)U0, (const L*)U1,
                        (Vx*)x, b, nt, nx, R(1.0 / (m0 + 2.0)), colour, stride, st);
   }
 }

@@ -410,18 +410,18 @@ using KFn = void (*)(hipStream_t, const KrylovDims&, const double2*, int64_t, do
 
 template <int NV> void launch_dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj,
                                    double2* w, const double2*, double2* part, const RhsState* st) {
-  hipLaunchKernelGGL((k_dots<NV>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, w, part, st);
+  AMAMG_LAUNCH((k_dots<NV>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, w, part, st);
 }
 template <int NV>
 void launch_update_norm(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, double2* w,
                         const double2* hpart, double2* part, const RhsState* st) {
-  hipLaunchKernelGGL((k_update_norm<NV>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, w, hpart,
+  AMAMG_LAUNCH((k_update_norm<NV>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, w, hpart,
                      part, st);
 }
 template <int NV>
 void launch_update_dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, double2* w,
                         const double2* hpart, double2* part, const RhsState* st) {
-  hipLaunchKernelGGL((k_update_dots<NV, update_lanes(NV)>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d,
+  AMAMG_LAUNCH((k_update_dots<NV, update_lanes(NV)>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d,
                      V, vsj, w, hpart, part, st);
 }
 template <int... I>

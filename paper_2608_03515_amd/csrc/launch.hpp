@@ -2,9 +2,32 @@
 // beside their kernels).  All launches are asynchronous on `s`.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 
 namespace amamg {
+
+// Kernel-timer hook (host side, per thread).  When `start` is set, the next launch through
+// AMAMG_LAUNCH stamps `start` and `stop` at that kernel's own begin and end (the times a kernel
+// trace reports, without the queueing a pair of stream events would also measure) and clears
+// the hook.
+struct TimedLaunch {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+TimedLaunch& timed_launch();
+
+#define AMAMG_LAUNCH(kernel, grid, block, shmem, stream, ...)                                   \
+  do {                                                                                          \
+    ::amamg::TimedLaunch& tl_ = ::amamg::timed_launch();                                        \
+    if (tl_.start) {                                                                            \
+      const ::amamg::TimedLaunch ev_ = tl_;                                                     \
+      tl_ = ::amamg::TimedLaunch{};                                                             \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ev_.start, ev_.stop, 0, __VA_ARGS__); \
+    } else {                                                                                    \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                      \
+    }                                                                                           \
+  } while (0)
 
 enum Real { F64 = 0, F32 = 1 };
 enum LinkStore { LINK_F64 = 0, LINK_F32 = 1, LINK_BF16 = 2 };

@@ -26,6 +26,12 @@ int period_of(int L) {
 }  // namespace
 
 namespace amamg {
+
+TimedLaunch& timed_launch() {
+  thread_local TimedLaunch t;
+  return t;
+}
+
 namespace rt {
 
 amamg_status fail(amamg_context* ctx, const Fail& f) {
@@ -51,6 +57,8 @@ static int timer_event(KernelTimer& t, size_t idx) {
 }
 
 // Start / stop recording one launch of `family` at Arnoldi step `step` of batch `group`.
+// Families launched by one kernel arm the launch hook (events stamped by the kernel itself);
+// the fine restriction (two kernels) is bracketed by stream events.
 int timer_start(amamg_context* ctx, hipStream_t s, int family, int step, int group, double bytes_per_rhs) {
   KernelTimer& t = ctx->timer;
   if (!(t.mask & (1u << family))) return -1;
@@ -58,15 +66,24 @@ int timer_start(amamg_context* ctx, hipStream_t s, int family, int step, int gro
   size_t slot = 0;
   for (const auto& r : t.pending) slot = std::max(slot, size_t(r.e1) + 1);
   const int e0 = timer_event(t, slot), e1 = timer_event(t, slot + 1);
-  HIPCHECK(hipEventRecord(t.events[e0], s));
+  if (family == AMAMG_KT_RESTRICT0) HIPCHECK(hipEventRecord(t.events[e0], s));
+  else timed_launch() = TimedLaunch{t.events[e0], t.events[e1]};
   t.pending.push_back({e0, e1, step, family, group, bytes_per_rhs});
   return int(t.pending.size()) - 1;
 }
 void timer_stop(amamg_context* ctx, hipStream_t s, int rec) {
   if (rec < 0) return;
   KernelTimer& t = ctx->timer;
-  HIPCHECK(hipEventRecord(t.events[t.pending[rec].e1], s));
+  const auto& r = t.pending[rec];
+  TimedLaunch& tl = timed_launch();
+  if (r.family == AMAMG_KT_RESTRICT0 || tl.start == t.events[r.e0]) {
+    // bracketing events (or a hook no launch consumed: the record then spans nothing)
+    if (tl.start == t.events[r.e0]) HIPCHECK(hipEventRecord(t.events[r.e0], s));
+    HIPCHECK(hipEventRecord(t.events[r.e1], s));
+  }
+  tl = TimedLaunch{};
 }
+
 bool finite_all(const double* v, size_t n) {
   for (size_t i = 0; i < n; ++i)
     if (!std::isfinite(v[i])) return false;

@@ -308,11 +308,11 @@ void prolong(hipStream_t s, Real prec, const void* P, const int* rows, const int
   dim3 grid(unsigned(g.nI * g.nJ * ts.nchunk));
   const size_t sm = tile_smem(ts, g.ncol(), cs);
   if (prec == F64)
-    hipLaunchKernelGGL((k_prolong<double, double2, double2, double2>), grid, dim3(256), sm, s,
+    AMAMG_LAUNCH((k_prolong<double, double2, double2, double2>), grid, dim3(256), sm, s,
                        (const double2*)P, rows, nrows, nf * g.b, (const double2*)e, (double2*)y, g,
                        ts, add, nrhs, stride_f, stride_c, st);
   else
-    hipLaunchKernelGGL((k_prolong<float, float2, float2, float2>), grid, dim3(256), sm, s,
+    AMAMG_LAUNCH((k_prolong<float, float2, float2, float2>), grid, dim3(256), sm, s,
                        (const float2*)P, rows, nrows, nf * g.b, (const float2*)e, (float2*)y, g,
                        ts, add, nrhs, stride_f, stride_c, st);
 }
