@@ -162,6 +162,135 @@ __global__ __launch_bounds__(256) void k_prolong(const M* __restrict__ P,
   }
 }
 
+// Register-tiled transfer for NCOL interpolation columns (NCOL divides 64: the fine level of
+// overlap 1 and 2), right-hand sides 32 per pass.  The generic kernels above read two LDS values
+// per complex multiply-add; these read each interpolation value once per row for several
+// right-hand sides and take the right-hand-side values as wave-wide broadcasts.
+// Tile shapes (measured at the 256^2, a = 8, o = 2 fine level): small enough for several
+// workgroups per compute unit, which hide the row gather's latency.
+template <typename R, int NCOL> struct TiledRows {
+  static constexpr int RESTRICT = sizeof(R) == 4 ? 60 : 30;    // rows per restriction chunk
+  static constexpr int PROLONG = sizeof(R) == 4 ? 64 : 32;     // rows per prolongation chunk
+  // right-hand sides per pass (the restriction's lane tiling needs 4 * 64 / NCOL at least)
+  static constexpr int RHS_R = NCOL == 8 ? 32 : (sizeof(R) == 4 ? 32 : 16);
+  static constexpr int RHS_P = sizeof(R) == 4 ? 32 : 16;
+};
+__host__ __device__ inline bool tiled_cols(int ncol) { return ncol == 8 || ncol == 32; }
+
+// Restriction pass 1 (same partial layout as k_restrict_partial): lane (sub, col) of wave wv
+// accumulates conj(P[k][col]) r[k] for the RB right-hand sides wv*SUB*RB + sub + SUB*j.
+template <int NCOL, int RCH, int NR, typename R, typename M, typename Vin>
+__global__ __launch_bounds__(256) void k_restrict_partial_tiled(
+    const M* __restrict__ P, const int* __restrict__ rows, const int* __restrict__ nrows, int maxrows,
+    const Vin* __restrict__ rin, cplx<R>* __restrict__ part, int nW, int nchunk, int nrhs,
+    int64_t stride_f, const RhsState* __restrict__ st) {
+  using C = cplx<R>;
+  constexpr int SUB = 64 / NCOL, RB = NR / (4 * SUB), RS = RCH + 1;
+  static_assert(RB >= 1 && 4 * SUB * RB == NR, "lane tiling must cover the pass");
+  __shared__ C Pl[RCH * NCOL];
+  __shared__ C Rl[NR * RS];             // row stride RCH + 1 against bank conflicts
+  __shared__ int ri[RCH];
+  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  const int w = bid / nchunk, chunk = bid - (bid / nchunk) * nchunk;
+  const int r0 = chunk * RCH, cnt = max(0, min(nrows[w] - r0, RCH));
+  for (int k = threadIdx.x; k < cnt; k += 256) ri[k] = rows[int64_t(w) * maxrows + r0 + k];
+  __syncthreads();
+  for (int q = threadIdx.x; q < cnt * NCOL; q += 256)
+    Pl[q] = cconv<C>(P[int64_t(ri[q / NCOL]) * NCOL + q % NCOL]);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = lane % NCOL, sub = lane / NCOL;
+  for (int g0 = 0; g0 < nrhs; g0 += NR) {
+    const int ng = min(NR, nrhs - g0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < NR * cnt; q += 256) {
+      const int rr = q / cnt, k = q - rr * cnt;
+      const bool live = rr < ng && (!st || st[g0 + rr].active);
+      Rl[rr * RS + k] = live ? cconv<C>(rin[(g0 + rr) * stride_f + ri[k]]) : czero<R>();
+    }
+    __syncthreads();
+    C acc[RB];
+#pragma unroll
+    for (int j = 0; j < RB; ++j) acc[j] = czero<R>();
+    const int rb0 = wv * SUB * RB + sub;
+    for (int k = 0; k < cnt; ++k) {
+      const C pk = Pl[k * NCOL + col];
+#pragma unroll
+      for (int j = 0; j < RB; ++j) acc[j] = cfmac(pk, Rl[(rb0 + SUB * j) * RS + k], acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      const int rr = rb0 + SUB * j;
+      if (rr < ng && (!st || st[g0 + rr].active))
+        part[((int64_t(g0 + rr) * nW + w) * nchunk + chunk) * NCOL + col] = acc[j];
+    }
+  }
+}
+
+// Prolongation y = P e (add: y += P e): thread (row k, h) keeps interpolation row k in registers
+// and serves the right-hand sides rr = h, h + H, ... of each pass; all lanes of a wave share rr,
+// so the coarse values are broadcast LDS reads.  Chunk 0 also writes the vertex rows of node
+// (I, J) (identity on corner 0).
+template <int NCOL, int RCH, int NR, typename R, typename M, typename Vin, typename Vout>
+__global__ __launch_bounds__(256) void k_prolong_tiled(
+    const M* __restrict__ P, const int* __restrict__ rows, const int* __restrict__ nrows, int maxrows,
+    const Vin* __restrict__ e, Vout* __restrict__ y, Geom g, int nchunk, int add, int nrhs,
+    int64_t stride_f, int64_t stride_c, const RhsState* __restrict__ st) {
+  using C = cplx<R>;
+  constexpr int H = 256 / RCH, PS = NCOL + 1;
+  __shared__ C Pl[RCH * PS];            // row stride NCOL + 1 against bank conflicts
+  __shared__ C El[NR * NCOL];
+  __shared__ int ri[RCH];
+  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  const int w = bid / nchunk, chunk = bid - (bid / nchunk) * nchunk;
+  const int I = w / g.nJ, J = w - (w / g.nJ) * g.nJ;
+  const int r0 = chunk * RCH, cnt = max(0, min(nrows[w] - r0, RCH));
+  const int nv_rows = chunk == 0 ? g.o * g.o * g.b : 0;
+  for (int k = threadIdx.x; k < cnt; k += 256) ri[k] = rows[int64_t(w) * maxrows + r0 + k];
+  __syncthreads();
+  for (int q = threadIdx.x; q < cnt * NCOL; q += 256)
+    Pl[(q / NCOL) * PS + q % NCOL] = cconv<C>(P[int64_t(ri[q / NCOL]) * NCOL + q % NCOL]);
+  __syncthreads();
+  const int k = threadIdx.x % RCH, h = threadIdx.x / RCH;
+  C pr[NCOL];
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) pr[c] = k < cnt ? Pl[k * PS + c] : czero<R>();
+  int cn[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) cn[c] = ((I + (c >> 1)) % g.nI) * g.nJ + (J + (c & 1)) % g.nJ;
+  const int row = k < cnt ? ri[k] : 0;
+  for (int g0 = 0; g0 < nrhs; g0 += NR) {
+    const int ng = min(NR, nrhs - g0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < NR * NCOL; q += 256) {
+      const int rr = q / NCOL, col = q % NCOL;
+      const int c = col / g.bc, j = col - (col / g.bc) * g.bc;
+      El[q] = rr < ng ? cconv<C>(e[(g0 + rr) * stride_c + int64_t(cn[c]) * g.bc + j]) : czero<R>();
+    }
+    __syncthreads();
+    if (k < cnt)
+      for (int rr = h; rr < ng; rr += H) {
+        if (st && !st[g0 + rr].active) continue;
+        C acc = czero<R>();
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) acc = cfma(pr[c], El[rr * NCOL + c], acc);
+        Vout* yr = y + (g0 + rr) * stride_f;
+        if (add) acc = cadd(acc, cconv<C>(yr[row]));
+        yr[row] = cconv<Vout>(acc);
+      }
+    for (int q = threadIdx.x; q < ng * nv_rows; q += 256) {
+      const int rr = q / nv_rows, v = q - rr * nv_rows;   // (pt*o + px)*b + qq of node (I, J)
+      if (st && !st[g0 + rr].active) continue;
+      const int qq = v % g.b, pp = v / g.b;
+      const int pt = pp / g.o, px = pp - (pp / g.o) * g.o;
+      const int64_t vrow = int64_t((g.a * I + pt) * g.Lx + (g.a * J + px)) * g.b + qq;
+      C acc = El[rr * NCOL + v];
+      Vout* yr = y + (g0 + rr) * stride_f;
+      if (add) acc = cadd(acc, cconv<C>(yr[vrow]));
+      yr[vrow] = cconv<Vout>(acc);
+    }
+  }
+}
+
 template <typename R, typename Vin, typename Vout>
 __global__ __launch_bounds__(256) void k_restrict_gather(const cplx<R>* __restrict__ part,
                                                          const Vin* __restrict__ rin,
@@ -291,7 +420,30 @@ static size_t tile_smem(const TileShape& t, int ncol, int cs) {
 }
 
 int restrict_chunks(const Geom& g, int nf, Real prec) {
+  if (tiled_cols(g.ncol())) {
+    const int rch = prec == F64 ? TiledRows<double, 32>::RESTRICT : TiledRows<float, 32>::RESTRICT;
+    return (nf * g.b + rch - 1) / rch;
+  }
   return tile_shape(g.ncol(), prec == F64 ? 16 : 8, nf * g.b).nchunk;
+}
+
+template <int NCOL, typename R, typename M, typename V>
+static void prolong_tiled(hipStream_t s, const void* P, const int* rows, const int* nrows, int maxrows,
+                          const void* e, void* y, const Geom& g, int add, int nrhs, int64_t stride_f,
+                          int64_t stride_c, const RhsState* st) {
+  const int nchunk = (maxrows + TiledRows<R, NCOL>::PROLONG - 1) / TiledRows<R, NCOL>::PROLONG;
+  AMAMG_LAUNCH((k_prolong_tiled<NCOL, TiledRows<R, NCOL>::PROLONG, TiledRows<R, NCOL>::RHS_P, R, M, V, V>), dim3(unsigned(g.nI * g.nJ * nchunk)), dim3(256), 0, s,
+               (const M*)P, rows, nrows, maxrows, (const V*)e, (V*)y, g, nchunk, add, nrhs, stride_f,
+               stride_c, st);
+}
+
+template <int NCOL, typename R, typename M, typename Vin>
+static void restrict_tiled(hipStream_t s, const void* P, const int* rows, const int* nrows, int maxrows,
+                           const void* r, void* part, int nW, int nchunk, int nrhs, int64_t stride_f,
+                           const RhsState* st) {
+  hipLaunchKernelGGL((k_restrict_partial_tiled<NCOL, TiledRows<R, NCOL>::RESTRICT, TiledRows<R, NCOL>::RHS_R, R, M, Vin>), dim3(unsigned(nW * nchunk)), dim3(256), 0,
+                     s, (const M*)P, rows, nrows, maxrows, (const Vin*)r, (cplx<R>*)part, nW, nchunk, nrhs,
+                     stride_f, st);
 }
 
 void owned_rows(hipStream_t s, const Geom& g, const int* fpos, int nf, const int* owner, int* rows,
@@ -304,6 +456,17 @@ void prolong(hipStream_t s, Real prec, const void* P, const int* rows, const int
              const void* e, void* y, const Geom& g, int add, int nrhs, int64_t stride_f,
              int64_t stride_c, const RhsState* st) {
   const int cs = prec == F64 ? 16 : 8;
+  const int maxrows = nf * g.b;
+  if (g.ncol() == 32) {
+    if (prec == F64) prolong_tiled<32, double, double2, double2>(s, P, rows, nrows, maxrows, e, y, g, add, nrhs, stride_f, stride_c, st);
+    else prolong_tiled<32, float, float2, float2>(s, P, rows, nrows, maxrows, e, y, g, add, nrhs, stride_f, stride_c, st);
+    return;
+  }
+  if (g.ncol() == 8) {
+    if (prec == F64) prolong_tiled<8, double, double2, double2>(s, P, rows, nrows, maxrows, e, y, g, add, nrhs, stride_f, stride_c, st);
+    else prolong_tiled<8, float, float2, float2>(s, P, rows, nrows, maxrows, e, y, g, add, nrhs, stride_f, stride_c, st);
+    return;
+  }
   const TileShape ts = tile_shape(g.ncol(), cs, nf * g.b);
   dim3 grid(unsigned(g.nI * g.nJ * ts.nchunk));
   const size_t sm = tile_smem(ts, g.ncol(), cs);
@@ -323,11 +486,37 @@ void restrict_(hipStream_t s, Real prec, const void* P, const int* rows, const i
   const int cs = prec == F64 ? 16 : 8;
   const TileShape ts = tile_shape(g.ncol(), cs, nf * g.b);
   const int maxrows = nf * g.b;
+  const int nchunk = restrict_chunks(g, nf, prec);
   int lanes = 1;
-  while (lanes < 16 && lanes < ts.nchunk) lanes <<= 1;
+  while (lanes < 16 && lanes < nchunk) lanes <<= 1;
   dim3 g1(unsigned(g.nI * g.nJ * ts.nchunk));
   dim3 g2(unsigned((int64_t(g.nI) * g.nJ * g.bc * lanes + 255) / 256), unsigned(nrhs));
   const size_t sm = tile_smem(ts, g.ncol(), cs);
+  const int nW = g.nI * g.nJ;
+  if (tiled_cols(g.ncol())) {
+    if (g.ncol() == 32) {
+      if (prec == F64) restrict_tiled<32, double, double2, double2>(s, P, rows, nrows, maxrows, r, part, nW, nchunk, nrhs, stride_f, st);
+      else if (rin == F64) restrict_tiled<32, float, float2, double2>(s, P, rows, nrows, maxrows, r, part, nW, nchunk, nrhs, stride_f, st);
+      else restrict_tiled<32, float, float2, float2>(s, P, rows, nrows, maxrows, r, part, nW, nchunk, nrhs, stride_f, st);
+    } else {
+      if (prec == F64) restrict_tiled<8, double, double2, double2>(s, P, rows, nrows, maxrows, r, part, nW, nchunk, nrhs, stride_f, st);
+      else if (rin == F64) restrict_tiled<8, float, float2, double2>(s, P, rows, nrows, maxrows, r, part, nW, nchunk, nrhs, stride_f, st);
+      else restrict_tiled<8, float, float2, float2>(s, P, rows, nrows, maxrows, r, part, nW, nchunk, nrhs, stride_f, st);
+    }
+    if (prec == F64)
+      hipLaunchKernelGGL((k_restrict_gather<double, double2, double2>), g2, dim3(256), 0, s,
+                         (const double2*)part, (const double2*)r, (double2*)rc, g, nchunk, lanes,
+                         stride_f, stride_c, st);
+    else if (rin == F64)
+      hipLaunchKernelGGL((k_restrict_gather<float, double2, float2>), g2, dim3(256), 0, s,
+                         (const float2*)part, (const double2*)r, (float2*)rc, g, nchunk, lanes,
+                         stride_f, stride_c, st);
+    else
+      hipLaunchKernelGGL((k_restrict_gather<float, float2, float2>), g2, dim3(256), 0, s,
+                         (const float2*)part, (const float2*)r, (float2*)rc, g, nchunk, lanes,
+                         stride_f, stride_c, st);
+    return;
+  }
   if (prec == F64) {
     hipLaunchKernelGGL((k_restrict_partial<double, double2, double2>), g1, dim3(256), sm, s,
                        (const double2*)P, rows, nrows, maxrows, (const double2*)r, (double2*)part, g,
