@@ -150,6 +150,75 @@ __global__ __launch_bounds__(256) void k_wilson_gs(const L* __restrict__ U0,
   xr[n] = sconv<Vx>(Spinor<C>{cscale(csub(f.s0, h.s0), inv_mp2), cscale(csub(f.s1, h.s1), inv_mp2)});
 }
 
+// NS red-black sweeps (colours 0 then 1, NS = 1 or 2) from xin into xout (distinct buffers:
+// workgroups read their halos from xin while others write xout).  A workgroup owns a
+// TR x TC tile and stages x on the tile plus a halo of HW = 2 NS sites and b on the tile plus
+// HW - 1 sites (periodic indices) in LDS.  Half-sweep h updates the sites of its colour that are
+// at least h + 1 sites inside the staged region: their neighbours there hold the values after
+// half-sweep h, so every value inside the tile is exactly the per-colour sweeps' value (halo
+// sites are recomputed by each workgroup that needs them, from the same inputs in the same
+// order).  Only the tile is written back.
+template <int NS, int TR, int TC, typename R, typename L, typename Vx>
+__global__ __launch_bounds__(256) void k_wilson_gs_fused(const L* __restrict__ U0,
+                                                         const L* __restrict__ U1,
+                                                         const Vx* __restrict__ xin,
+                                                         Vx* __restrict__ xout,
+                                                         const double2* __restrict__ b, int nt,
+                                                         int nx, R inv_mp2, int64_t stride,
+                                                         const RhsState* __restrict__ st) {
+  constexpr int HW = 2 * NS, RW = TC + 2 * HW, RH = TR + 2 * HW, BW = RW - 2, BH = RH - 2;
+  using C = cplx<R>;
+  const int r = blockIdx.y;
+  if (st && !st[r].active) return;
+  __shared__ Spinor<C> xs[RH * RW];
+  __shared__ Spinor<C> bs[BH * BW];
+  const int tiles_x = (nx + TC - 1) / TC;
+  const int ty = blockIdx.x / tiles_x, tx = blockIdx.x - ty * tiles_x;
+  const int t0 = ty * TR - HW, x0 = tx * TC - HW;   // region origin (global, may be negative)
+  const Spinor<Vx>* xr = reinterpret_cast<const Spinor<Vx>*>(xin + r * stride);
+  Spinor<Vx>* xw = reinterpret_cast<Spinor<Vx>*>(xout + r * stride);
+  for (int e = threadIdx.x; e < RH * RW; e += 256) {
+    const int rw = e / RW, c = e - rw * RW;
+    const int tt = ((t0 + rw) % nt + nt) % nt, xx = ((x0 + c) % nx + nx) % nx;
+    xs[e] = sconv<C>(xr[int64_t(tt) * nx + xx]);
+  }
+  for (int e = threadIdx.x; e < BH * BW; e += 256) {
+    const int rw = e / BW, c = e - rw * BW;
+    const int tt = ((t0 + 1 + rw) % nt + nt) % nt, xx = ((x0 + 1 + c) % nx + nx) % nx;
+    Spinor<C> f{czero<R>(), czero<R>()};
+    if (b) f = sconv<C>(reinterpret_cast<const Spinor<double2>*>(b + r * stride)[int64_t(tt) * nx + xx]);
+    bs[e] = f;
+  }
+  __syncthreads();
+  for (int hs = 0; hs < 2 * NS; ++hs) {
+    const int colour = hs & 1, lo = hs + 1;
+    const int rows = RH - 2 * lo, pairs = (RW - 2 * lo) / 2;   // RW - 2 lo is even
+    // region parity: t0 + x0 is even, so site (rw, c) has colour (rw + c) mod 2
+    for (int e = threadIdx.x; e < rows * pairs; e += 256) {
+      const int rw = lo + e / pairs;
+      const int c = lo + 2 * (e - (e / pairs) * pairs) + ((rw + lo + colour) & 1);
+      const int t = ((t0 + rw) % nt + nt) % nt, xc = ((x0 + c) % nx + nx) % nx;
+      const int n = t * nx + xc;
+      const int tb = t == 0 ? nt - 1 : t - 1, xb = xc == 0 ? nx - 1 : xc - 1;
+      const int q = rw * RW + c;
+      const Spinor<C> h = hops<C, R>(xs[q + RW], xs[q - RW], xs[q + 1], xs[q - 1], load_link<R>(U0, n),
+                                     load_link<R>(U0, int64_t(tb) * nx + xc), load_link<R>(U1, n),
+                                     load_link<R>(U1, int64_t(t) * nx + xb), t == nt - 1 ? R(-1) : R(1),
+                                     t == 0 ? R(-1) : R(1));
+      const Spinor<C> f = bs[(rw - 1) * BW + (c - 1)];
+      xs[q] = Spinor<C>{cscale(csub(f.s0, h.s0), inv_mp2), cscale(csub(f.s1, h.s1), inv_mp2)};
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < TR * TC; e += 256) {
+    const int rr = e / TC, cc = e - rr * TC;
+    const int t = ty * TR + rr, xc = tx * TC + cc;
+    if (t >= nt || xc >= nx) continue;
+    const Spinor<C> v = xs[(rr + HW) * RW + (cc + HW)];
+    xw[int64_t(t) * nx + xc] = Spinor<Vx>{cconv<Vx>(v.s0), cconv<Vx>(v.s1)};
+  }
+}
+
 __global__ void k_build_fine_stencil(const double2* __restrict__ U0, const double2* __restrict__ U1,
                                      int nt, int nx, double m0, double2* __restrict__ A) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -251,6 +320,37 @@ void wilson_gs(hipStream_t s, LinkStore ls, const void* U0, const void* U1, Real
   if (ls == LINK_F64 && vx == F64) wilson_gs_t<double, double2, double2>(s, U0, U1, x, b, nt, nx, m0, colour, nrhs, stride, st);
   else if (ls == LINK_F32) wilson_gs_t<float, float2, float2>(s, U0, U1, x, b, nt, nx, m0, colour, nrhs, stride, st);
   else wilson_gs_t<float, bf16c, float2>(s, U0, U1, x, b, nt, nx, m0, colour, nrhs, stride, st);
+}
+
+template <int NS, typename R, typename L, typename Vx>
+static void wilson_gs_fused_t(hipStream_t s, const void* U0, const void* U1, const void* xin, void* x,
+                              const double2* b, int nt, int nx, double m0, int nrhs, int64_t stride,
+                              const RhsState* st) {
+  // tiles: 16 x 64 sites (16 x 32 in FP64, for the LDS budget), 16 x 16 below 64 columns
+  constexpr int TCW = sizeof(R) == 4 ? 64 : 32;
+  if (nx >= TCW) {
+    dim3 g(unsigned(((nx + TCW - 1) / TCW) * ((nt + 15) / 16)), unsigned(nrhs));
+    AMAMG_LAUNCH((k_wilson_gs_fused<NS, 16, TCW, R, L, Vx>), g, dim3(256), 0, s, (const L*)U0, (const L*)U1,
+                 (const Vx*)xin, (Vx*)x, b, nt, nx, R(1.0 / (m0 + 2.0)), stride, st);
+  } else {
+    dim3 g(unsigned(((nx + 15) / 16) * ((nt + 15) / 16)), unsigned(nrhs));
+    AMAMG_LAUNCH((k_wilson_gs_fused<NS, 16, 16, R, L, Vx>), g, dim3(256), 0, s, (const L*)U0, (const L*)U1,
+                 (const Vx*)xin, (Vx*)x, b, nt, nx, R(1.0 / (m0 + 2.0)), stride, st);
+  }
+}
+
+void wilson_gs_sweeps(hipStream_t s, LinkStore ls, const void* U0, const void* U1, Real vx, const void* xin,
+                      void* x, const double2* b, int nt, int nx, double m0, int sweeps, int nrhs,
+                      int64_t stride, const RhsState* st) {
+  if (sweeps == 2) {
+    if (ls == LINK_F64 && vx == F64) wilson_gs_fused_t<2, double, double2, double2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st);
+    else if (ls == LINK_F32) wilson_gs_fused_t<2, float, float2, float2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st);
+    else wilson_gs_fused_t<2, float, bf16c, float2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st);
+  } else {
+    if (ls == LINK_F64 && vx == F64) wilson_gs_fused_t<1, double, double2, double2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st);
+    else if (ls == LINK_F32) wilson_gs_fused_t<1, float, float2, float2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st);
+    else wilson_gs_fused_t<1, float, bf16c, float2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st);
+  }
 }
 
 void build_fine_stencil(hipStream_t s, const double2* U0, const double2* U1, int nt, int nx,

@@ -84,24 +84,23 @@ struct ArnoldiArgs {
   int hist_cap;
 };
 
-// Arnoldi step j for one rhs, given hn = ||w|| after CGS2.
-__device__ inline void arnoldi_step(const KrylovDims& dm, RhsState& s, int r, double hn,
-                                    const double2* h1, const double2* h2, const ArnoldiArgs& a) {
+// Arnoldi step j for one rhs, given hn = ||w|| after CGS2: col[0..j] = h1 + h2 is the new
+// Hessenberg column and col[j + 1] = hn; the earlier rotations csl/snl (all in LDS).  Rotates
+// the column, forms rotation j and updates g; the caller writes the column back to H.
+__device__ inline void arnoldi_step(const KrylovDims& dm, RhsState& s, int r, double hn, double2* col,
+                                    const double* csl, const double2* snl, const ArnoldiArgs& a) {
   const int m = dm.m, j = a.j;
-  double2* Hr = a.H + int64_t(r) * (m + 1) * m;
   double* csr = a.cs + int64_t(r) * m;
   double2* snr = a.sn + int64_t(r) * m;
   double2* gr = a.g + int64_t(r) * (m + 1);
-  for (int i = 0; i <= j; ++i) Hr[i * m + j] = cadd(h1[i], h2[i]);
-  Hr[(j + 1) * m + j] = make_double2(hn, 0.0);
   for (int i = 0; i < j; ++i) {
-    const double2 x = Hr[i * m + j], y = Hr[(i + 1) * m + j];
-    const double c = csr[i];
-    const double2 sv = snr[i];
-    Hr[i * m + j] = cadd(cscale(x, c), cmul(sv, y));
-    Hr[(i + 1) * m + j] = csub(cscale(y, c), cmulc(sv, x));
+    const double2 x = col[i], y = col[i + 1];
+    const double c = csl[i];
+    const double2 sv = snl[i];
+    col[i] = cadd(cscale(x, c), cmul(sv, y));
+    col[i + 1] = csub(cscale(y, c), cmulc(sv, x));
   }
-  const double2 av = Hr[j * m + j], bv = Hr[(j + 1) * m + j];
+  const double2 av = col[j], bv = col[j + 1];
   double c;
   double2 sv;
   const double aa = sqrt(cabs2(av));
@@ -113,8 +112,8 @@ __device__ inline void arnoldi_step(const KrylovDims& dm, RhsState& s, int r, do
     c = aa / nu;
     sv = cscale(cmul(make_double2(av.x / aa, av.y / aa), cconj(bv)), 1.0 / nu);
   }
-  Hr[j * m + j] = cadd(cscale(av, c), cmul(sv, bv));
-  Hr[(j + 1) * m + j] = make_double2(0, 0);
+  col[j] = cadd(cscale(av, c), cmul(sv, bv));
+  col[j + 1] = make_double2(0, 0);
   csr[j] = c;
   snr[j] = sv;
   const double2 gj = gr[j];
@@ -264,13 +263,27 @@ __global__ __launch_bounds__(256) void k_arnoldi(KrylovDims dm, const double2* _
   const int r = blockIdx.x;
   if (!st[r].active) return;
   __shared__ double2 h1[KMAXV], h2[KMAXV], hn[KMAXV], scratch[8 * KMAXV];
+  __shared__ double2 col[KMAXV + 1], snl[KMAXV];
+  __shared__ double csl[KMAXV];
   sum_blocks(p1 + int64_t(r) * dm.nblk * KMAXV, dm.nblk, nv, h1, scratch);
   sum_blocks(p2 + int64_t(r) * dm.nblk * KMAXV, dm.nblk, nv, h2, scratch);
   sum_blocks(p3 + int64_t(r) * dm.nblk * KMAXV, dm.nblk, 1, hn, scratch);
-  if (threadIdx.x != 0) return;
-  RhsState s = st[r];
-  arnoldi_step(dm, s, r, sqrt(hn[0].x), h1, h2, aa);
-  st[r] = s;
+  const int m = dm.m, j = aa.j;
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = cadd(h1[i], h2[i]);
+  for (int i = threadIdx.x; i < j; i += blockDim.x) {
+    csl[i] = aa.cs[int64_t(r) * m + i];
+    snl[i] = aa.sn[int64_t(r) * m + i];
+  }
+  if (threadIdx.x == 0) col[j + 1] = make_double2(sqrt(hn[0].x), 0.0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    RhsState s = st[r];
+    arnoldi_step(dm, s, r, sqrt(hn[0].x), col, csl, snl, aa);
+    st[r] = s;
+  }
+  __syncthreads();
+  double2* Hr = aa.H + int64_t(r) * (m + 1) * m;
+  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) Hr[i * m + j] = col[i];
 }
 
 // ||x||^2 per rhs whose state is active, then: mode 1 fresh states (x = b; the host marks the

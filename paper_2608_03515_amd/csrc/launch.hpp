@@ -53,6 +53,12 @@ void wilson_apply(hipStream_t s, LinkStore ls, const void* U0, const void* U1, R
 void wilson_gs(hipStream_t s, LinkStore ls, const void* U0, const void* U1, Real vx, void* x,
                const double2* b, int nt, int nx, double m0, int colour, int nrhs, int64_t stride,
                const RhsState* st);
+// `sweeps` (1 or 2) full red-black sweeps (colour 0 then 1 each) in one launch, starting from xin
+// and writing x (distinct buffers); bitwise equal to the same sequence of wilson_gs colour
+// launches on x = xin
+void wilson_gs_sweeps(hipStream_t s, LinkStore ls, const void* U0, const void* U1, Real vx, const void* xin,
+                      void* x, const double2* b, int nt, int nx, double m0, int sweeps, int nrhs,
+                      int64_t stride, const RhsState* st);
 // A0 blocks of the fine operator in block-stencil form: [site][5][2][2], offsets
 // (0,0), (+1,0), (-1,0), (0,+1), (0,-1)
 void build_fine_stencil(hipStream_t s, const double2* U0, const double2* U1, int nt, int nx,

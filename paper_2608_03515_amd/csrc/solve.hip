@@ -224,13 +224,27 @@ static void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x)
     timer_stop(ctx, c.s, rec);
   }
   vcycle(c, k + 1, c.T, WC.f, WC.x);
+  // fine level without pre-smoothing: the post-sweeps run fused, from the prolongated
+  // correction in the level's scratch vector into x
+  const bool fused = k == 0 && pre == 0 && (post == 1 || post == 2);
   {
     const double owned = double(nd) * (1.0 - double(g.o * g.o) / double(g.a * g.a));
     const int rec = k == 0 ? timer_start(ctx, c.s, AMAMG_KT_PROLONG0, c.step, c.group,
                                          owned * g.ncol() * cb + double(nd) * cb + double(ndc) * cb)
                            : -1;
-    prolong(c.s, c.T, P, L.rows, L.nrows, L.nf, WC.x, x, g, pre > 0 ? 1 : 0, c.nrhs, nd, ndc, st);
+    prolong(c.s, c.T, P, L.rows, L.nrows, L.nf, WC.x, fused ? WL.tmp : x, g, pre > 0 ? 1 : 0, c.nrhs, nd,
+            ndc, st);
     timer_stop(ctx, c.s, rec);
+  }
+  if (fused) {
+    // per sweep: x (both colours in, own colours out) + b, FP64
+    const double cl = c.smooth_links == LINK_F64 ? 16 : c.smooth_links == LINK_F32 ? 8 : 4;
+    const int rec = timer_start(ctx, c.s, AMAMG_KT_FINE_GS, c.step, c.group,
+                                double(g.nnode()) * (2 * 2 * cb + 2 * cl + 32));
+    wilson_gs_sweeps(c.s, c.smooth_links, U0, U1, c.T, WL.tmp, x, (const double2*)f, g.Lt, g.Lx, h->m0, post,
+                     c.nrhs, nd, st);
+    timer_stop(ctx, c.s, rec);
+    return;
   }
   for (int sw = 0; sw < post; ++sw) {
     if (k == 0) {
