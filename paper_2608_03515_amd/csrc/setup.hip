@@ -63,49 +63,133 @@ __global__ __launch_bounds__(256) void k_gather_local(Geom g, const double2* __r
 #define LU_NB 16
 
 // M[r][c] -= sum_{q < kb} M[r][lc + q] * M[ur + q][c]  for r in [r0, r1), c in [c0, c1)
+// One 64 x 64 tile of M[r][c] -= sum_{q < kb} M[r][lc + q] * M[ur + q][c], rows [tr, min(tr + 64,
+// r1)), columns [tc, min(tc + 64, c1)); all 256 threads, staged in LDS.
+__device__ void tile_one(double2* __restrict__ M, int ld, int tr, int tc, int r1, int c1, int lc,
+                         int ur, int kb, double2 (*Ls)[LU_NB + 1], double2 (*Us)[64 + 1]) {
+  const int tid = threadIdx.x;
+  const int ty = tid >> 4, tx = tid & 15;
+  for (int e = tid; e < 64 * LU_NB; e += 256) {
+    const int rr = e / LU_NB, q = e - (e / LU_NB) * LU_NB;
+    Ls[rr][q] = (tr + rr < r1 && q < kb) ? M[int64_t(tr + rr) * ld + lc + q] : make_double2(0, 0);
+  }
+  for (int e = tid; e < LU_NB * 64; e += 256) {
+    const int q = e >> 6, cc = e & 63;
+    Us[q][cc] = (q < kb && tc + cc < c1) ? M[int64_t(ur + q) * ld + tc + cc] : make_double2(0, 0);
+  }
+  __syncthreads();
+  double2 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0, 0);
+  for (int q = 0; q < kb; ++q) {
+    double2 lv[4], uv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) lv[a] = Ls[ty * 4 + a][q];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) uv[b] = Us[q][tx + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = cfma(lv[a], uv[b], acc[a][b]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int r = tr + ty * 4 + a;
+    if (r >= r1) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int c = tc + tx + 16 * b;
+      if (c < c1) M[int64_t(r) * ld + c] = csub(M[int64_t(r) * ld + c], acc[a][b]);
+    }
+  }
+  __syncthreads();
+}
+
+// M[r][c] -= sum_{q < kb} M[r][lc + q] * M[ur + q][c]  for r in [r0, r1), c in [c0, c1)
 __device__ void tile_update(double2* __restrict__ M, int ld, int r0, int r1, int c0, int c1,
                             int lc, int ur, int kb, double2 (*Ls)[LU_NB + 1],
                             double2 (*Us)[64 + 1]) {
+  for (int tr = r0; tr < r1; tr += 64)
+    for (int tc = c0; tc < c1; tc += 64) tile_one(M, ld, tr, tc, r1, c1, lc, ur, kb, Ls, Us);
+}
+
+// Panel k0 of the LU with partial pivoting (one workgroup per system): pivot search (largest
+// |a|^2, lowest index on ties), full-row swap, column scaling and the in-panel update, then
+// U12 = L11^{-1} A12 for every column right of the panel.  Returns false on a zero or
+// non-finite pivot (info set).
+__device__ bool lu_panel(double2* __restrict__ M, int n, int ld, int k0, int sys, int* __restrict__ info,
+                         double* sv, int* si) {
   const int tid = threadIdx.x;
-  const int ty = tid >> 4, tx = tid & 15;
-  for (int tr = r0; tr < r1; tr += 64) {
-    for (int tc = c0; tc < c1; tc += 64) {
-      for (int e = tid; e < 64 * LU_NB; e += 256) {
-        const int rr = e / LU_NB, q = e - (e / LU_NB) * LU_NB;
-        Ls[rr][q] = (tr + rr < r1 && q < kb) ? M[int64_t(tr + rr) * ld + lc + q] : make_double2(0, 0);
-      }
-      for (int e = tid; e < LU_NB * 64; e += 256) {
-        const int q = e >> 6, cc = e & 63;
-        Us[q][cc] = (q < kb && tc + cc < c1) ? M[int64_t(ur + q) * ld + tc + cc] : make_double2(0, 0);
-      }
-      __syncthreads();
-      double2 acc[4][4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0, 0);
-      for (int q = 0; q < kb; ++q) {
-        double2 lv[4], uv[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) lv[a] = Ls[ty * 4 + a][q];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) uv[b] = Us[q][tx + 16 * b];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] = cfma(lv[a], uv[b], acc[a][b]);
-      }
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int r = tr + ty * 4 + a;
-        if (r >= r1) continue;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int c = tc + tx + 16 * b;
-          if (c < c1) M[int64_t(r) * ld + c] = csub(M[int64_t(r) * ld + c], acc[a][b]);
-        }
+  const int kb = min(LU_NB, n - k0);
+  for (int k = k0; k < k0 + kb; ++k) {
+    double best = -1.0;
+    int bi = n;
+    for (int i = k + tid; i < n; i += 256) {
+      const double v = cabs2(M[int64_t(i) * ld + k]);
+      if (v > best) { best = v; bi = i; }
+    }
+    sv[tid] = best;
+    si[tid] = bi;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (tid < off) {
+        const double v2 = sv[tid + off];
+        const int i2 = si[tid + off];
+        if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) { sv[tid] = v2; si[tid] = i2; }
       }
       __syncthreads();
+    }
+    const int p = si[0];
+    const double pmax = sv[0];
+    __syncthreads();
+    if (!(pmax > 0.0) || !(pmax < 1e300) || p >= n) {
+      if (tid == 0) info[sys] = k + 1;
+      return false;
+    }
+    if (p != k) {
+      for (int j = tid; j < ld; j += 256) {
+        const double2 t = M[int64_t(k) * ld + j];
+        M[int64_t(k) * ld + j] = M[int64_t(p) * ld + j];
+        M[int64_t(p) * ld + j] = t;
+      }
+      __syncthreads();
+    }
+    const double2 akk = M[int64_t(k) * ld + k];
+    const double den = cabs2(akk);
+    const double2 inv = make_double2(akk.x / den, -akk.y / den);
+    for (int i = k + 1 + tid; i < n; i += 256) {
+      double2* Mi = M + int64_t(i) * ld;
+      const double2 l = cmul(Mi[k], inv);
+      Mi[k] = l;
+      for (int j = k + 1; j < k0 + kb; ++j) Mi[j] = csub(Mi[j], cmul(l, M[int64_t(k) * ld + j]));
+    }
+    __syncthreads();
+  }
+  // U12 = L11^{-1} A12 for the columns right of the panel (unit lower triangle)
+  for (int c = k0 + kb + tid; c < ld; c += 256) {
+    for (int r = 1; r < kb; ++r) {
+      double2 acc = M[int64_t(k0 + r) * ld + c];
+      for (int q = 0; q < r; ++q) acc = csub(acc, cmul(M[int64_t(k0 + r) * ld + k0 + q], M[int64_t(k0 + q) * ld + c]));
+      M[int64_t(k0 + r) * ld + c] = acc;
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+// Diagonal block k0 of the back substitution U X = B' on the right-hand-side columns [n, ld):
+// X rows k0 .. k0 + kb for the columns c0 + tid, c0 + tid + stride, ...
+__device__ void back_diag(double2* __restrict__ M, int n, int ld, int k0, int c0, int cstride) {
+  const int kb = min(LU_NB, n - k0);
+  for (int c = n + c0 + threadIdx.x; c < ld; c += cstride) {
+    for (int r = kb - 1; r >= 0; --r) {
+      double2 acc = M[int64_t(k0 + r) * ld + c];
+      for (int q = r + 1; q < kb; ++q) acc = csub(acc, cmul(M[int64_t(k0 + r) * ld + k0 + q], M[int64_t(k0 + q) * ld + c]));
+      const double2 d = M[int64_t(k0 + r) * ld + k0 + r];
+      const double den = cabs2(d);
+      M[int64_t(k0 + r) * ld + c] = cmul(acc, make_double2(d.x / den, -d.y / den));
     }
   }
 }
@@ -118,63 +202,10 @@ __global__ __launch_bounds__(256) void k_dense_solve(double2* __restrict__ A, in
   __shared__ int si[256];
   __shared__ double2 Ls[64][LU_NB + 1];
   __shared__ double2 Us[LU_NB][64 + 1];
-  const int tid = threadIdx.x;
-  if (tid == 0) info[sys] = 0;
+  if (threadIdx.x == 0) info[sys] = 0;
   for (int k0 = 0; k0 < n; k0 += LU_NB) {
+    if (!lu_panel(M, n, ld, k0, sys, info, sv, si)) return;
     const int kb = min(LU_NB, n - k0);
-    for (int k = k0; k < k0 + kb; ++k) {
-      double best = -1.0;
-      int bi = n;
-      for (int i = k + tid; i < n; i += 256) {
-        const double v = cabs2(M[int64_t(i) * ld + k]);
-        if (v > best) { best = v; bi = i; }
-      }
-      sv[tid] = best;
-      si[tid] = bi;
-      __syncthreads();
-      for (int off = 128; off > 0; off >>= 1) {
-        if (tid < off) {
-          const double v2 = sv[tid + off];
-          const int i2 = si[tid + off];
-          if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) { sv[tid] = v2; si[tid] = i2; }
-        }
-        __syncthreads();
-      }
-      const int p = si[0];
-      const double pmax = sv[0];
-      __syncthreads();
-      if (!(pmax > 0.0) || !(pmax < 1e300) || p >= n) {
-        if (tid == 0) info[sys] = k + 1;
-        return;
-      }
-      if (p != k) {
-        for (int j = tid; j < ld; j += 256) {
-          const double2 t = M[int64_t(k) * ld + j];
-          M[int64_t(k) * ld + j] = M[int64_t(p) * ld + j];
-          M[int64_t(p) * ld + j] = t;
-        }
-        __syncthreads();
-      }
-      const double2 akk = M[int64_t(k) * ld + k];
-      const double den = cabs2(akk);
-      const double2 inv = make_double2(akk.x / den, -akk.y / den);
-      for (int i = k + 1 + tid; i < n; i += 256) {
-        double2* Mi = M + int64_t(i) * ld;
-        const double2 l = cmul(Mi[k], inv);
-        Mi[k] = l;
-        for (int j = k + 1; j < k0 + kb; ++j) Mi[j] = csub(Mi[j], cmul(l, M[int64_t(k) * ld + j]));
-      }
-      __syncthreads();
-    }
-    // U12 = L11^{-1} A12 for the columns right of the panel (unit lower triangle)
-    for (int c = k0 + kb + tid; c < ld; c += 256) {
-      for (int r = 1; r < kb; ++r) {
-        double2 acc = M[int64_t(k0 + r) * ld + c];
-        for (int q = 0; q < r; ++q) acc = csub(acc, cmul(M[int64_t(k0 + r) * ld + k0 + q], M[int64_t(k0 + q) * ld + c]));
-        M[int64_t(k0 + r) * ld + c] = acc;
-      }
-    }
-    __syncthreads();
     tile_update(M, ld, k0 + kb, n, k0 + kb, ld, k0, k0, kb, Ls, Us);
     __syncthreads();
   }
@@ -182,19 +213,47 @@ __global__ __launch_bounds__(256) void k_dense_solve(double2* __restrict__ A, in
   const int last = ((n - 1) / LU_NB) * LU_NB;
   for (int k0 = last; k0 >= 0; k0 -= LU_NB) {
     const int kb = min(LU_NB, n - k0);
-    for (int c = n + tid; c < ld; c += 256) {
-      for (int r = kb - 1; r >= 0; --r) {
-        double2 acc = M[int64_t(k0 + r) * ld + c];
-        for (int q = r + 1; q < kb; ++q) acc = csub(acc, cmul(M[int64_t(k0 + r) * ld + k0 + q], M[int64_t(k0 + q) * ld + c]));
-        const double2 d = M[int64_t(k0 + r) * ld + k0 + r];
-        const double den = cabs2(d);
-        M[int64_t(k0 + r) * ld + c] = cmul(acc, make_double2(d.x / den, -d.y / den));
-      }
-    }
+    back_diag(M, n, ld, k0, 0, 256);
     __syncthreads();
     if (k0 > 0) tile_update(M, ld, 0, k0, n, ld, k0, k0, kb, Ls, Us);
     __syncthreads();
   }
+}
+
+// The same factorisation and substitution split over launches for few, large systems: the
+// panels run on one workgroup per system, the trailing updates and the back substitution on
+// one workgroup per 64 x 64 tile (bitwise the same operations as k_dense_solve).
+__global__ __launch_bounds__(256) void k_lu_panel(double2* __restrict__ A, int n, int ld, int k0,
+                                                  int* __restrict__ info) {
+  const int sys = blockIdx.x;
+  if (info[sys]) return;
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  (void)lu_panel(A + int64_t(sys) * n * ld, n, ld, k0, sys, info, sv, si);
+}
+
+__global__ __launch_bounds__(256) void k_lu_tiles(double2* __restrict__ A, int n, int ld, int r0, int r1,
+                                                  int c0, int c1, int lc, int ur, int kb,
+                                                  const int* __restrict__ info) {
+  const int sys = blockIdx.y;
+  if (info[sys]) return;
+  __shared__ double2 Ls[64][LU_NB + 1];
+  __shared__ double2 Us[LU_NB][64 + 1];
+  const int ntc = (c1 - c0 + 63) / 64;
+  const int tr = r0 + (blockIdx.x / ntc) * 64, tc = c0 + (blockIdx.x % ntc) * 64;
+  tile_one(A + int64_t(sys) * n * ld, ld, tr, tc, r1, c1, lc, ur, kb, Ls, Us);
+}
+
+__global__ __launch_bounds__(256) void k_lu_back_diag(double2* __restrict__ A, int n, int ld, int k0,
+                                                      const int* __restrict__ info) {
+  const int sys = blockIdx.y;
+  if (info[sys]) return;
+  back_diag(A + int64_t(sys) * n * ld, n, ld, k0, blockIdx.x * 256, gridDim.x * 256);
+}
+
+__global__ void k_info_zero(int* __restrict__ info, int nsys) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nsys) info[i] = 0;
 }
 
 // out[sys][i][j] = Aug[sys][i][n + j]
@@ -345,7 +404,33 @@ void gather_local(hipStream_t s, const Geom& g, const double2* A, int noff, cons
 }
 
 void dense_solve(hipStream_t s, double2* Aug, int n, int nrhs, int nsys, int* info) {
-  hipLaunchKernelGGL(k_dense_solve, dim3(nsys), dim3(256), 0, s, Aug, n, n + nrhs, info);
+  const int ld = n + nrhs;
+  if (nsys >= 32 || n <= 64) {
+    hipLaunchKernelGGL(k_dense_solve, dim3(nsys), dim3(256), 0, s, Aug, n, ld, info);
+    return;
+  }
+  hipLaunchKernelGGL(k_info_zero, dim3((nsys + 63) / 64), dim3(64), 0, s, info, nsys);
+  for (int k0 = 0; k0 < n; k0 += LU_NB) {
+    const int kb = min(LU_NB, n - k0);
+    hipLaunchKernelGGL(k_lu_panel, dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info);
+    const int r0 = k0 + kb, c0 = k0 + kb;
+    if (r0 < n) {
+      const int tiles = ((n - r0 + 63) / 64) * ((ld - c0 + 63) / 64);
+      hipLaunchKernelGGL(k_lu_tiles, dim3(tiles, nsys), dim3(256), 0, s, Aug, n, ld, r0, n, c0, ld, k0, k0, kb,
+                         (const int*)info);
+    }
+  }
+  const int last = ((n - 1) / LU_NB) * LU_NB;
+  for (int k0 = last; k0 >= 0; k0 -= LU_NB) {
+    const int kb = min(LU_NB, n - k0);
+    hipLaunchKernelGGL(k_lu_back_diag, dim3((nrhs + 255) / 256, nsys), dim3(256), 0, s, Aug, n, ld, k0,
+                       (const int*)info);
+    if (k0 > 0) {
+      const int tiles = ((k0 + 63) / 64) * ((ld - n + 63) / 64);
+      hipLaunchKernelGGL(k_lu_tiles, dim3(tiles, nsys), dim3(256), 0, s, Aug, n, ld, 0, k0, n, ld, k0, k0, kb,
+                         (const int*)info);
+    }
+  }
 }
 
 void aug_extract(hipStream_t s, const double2* Aug, int n, int nrhs, double2* out, int nsys) {
