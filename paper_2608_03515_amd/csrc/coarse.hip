@@ -135,6 +135,97 @@ __global__ __launch_bounds__(256) void k_stencil_gs(const M* __restrict__ A,
   if (live && jl == 0) xr[int64_t(n) * B + i] = cconv<Vx>(out);
 }
 
+// One node's Gauss-Seidel update x_n <- Dinv_n (f_n - sum_{d != 0} A_nd x_{n+d}) for the lanes of
+// that node (the arithmetic of k_stencil_gs), returning out = row i of the new x_n (summed over
+// the node's lanes).  With sub >= 0 the neighbour at offset (0, -1) is taken from `sub_val`
+// (this lane's columns of it) instead of memory.
+template <int B, typename R, typename M, typename Vx>
+__device__ inline cplx<R> gs_node(const M* __restrict__ A, const M* __restrict__ Dinv, const Vx* xr,
+                                  const Vx* __restrict__ fr, int Lt, int Lx, int t, int xc, int i, int jl,
+                                  int node_lane0, bool live, bool sub, const cplx<R>* sub_val) {
+  using Ly = Lanes<B>;
+  using C = cplx<R>;
+  const int n = t * Lx + xc;
+  const M* An = A + int64_t(n) * 25 * B * B + i * B;
+  C acc = czero<R>();
+#pragma unroll
+  for (int dt = -2; dt <= 2; ++dt) {
+    const int tt = wrap1(t + dt, Lt) * Lx;
+#pragma unroll
+    for (int dx = -2; dx <= 2; ++dx) {
+      if (dt == 0 && dx == 0) continue;
+      const int m = tt + wrap1(xc + dx, Lx);
+      const M* blk = An + ((dt + 2) * 5 + (dx + 2)) * B * B;
+      const Vx* xm = xr + int64_t(m) * B;
+#pragma unroll
+      for (int c = 0; c < Ly::CPL; ++c) {
+        const int j = jl + Ly::LJ * c;
+        const C xv = (sub && dt == 0 && dx == -1) ? sub_val[c] : cconv<C>(xm[j]);
+        acc = cfma(cconv<C>(blk[j]), xv, acc);
+      }
+    }
+  }
+  acc.x = group_sum<Ly::LJ>(acc.x);
+  acc.y = group_sum<Ly::LJ>(acc.y);
+  C res = acc;
+  res.x = -res.x;
+  res.y = -res.y;
+  if (fr && live) res = cadd(res, cconv<C>(fr[int64_t(n) * B + i]));
+  const M* Dn = Dinv + int64_t(n) * B * B + i * B;
+  C out = czero<R>();
+#pragma unroll
+  for (int c = 0; c < Ly::CPL; ++c) {
+    const int j = jl + Ly::LJ * c;
+    const R re = __shfl(res.x, node_lane0 + j * Ly::LJ), im = __shfl(res.y, node_lane0 + j * Ly::LJ);
+    out = cfma(cconv<C>(Dn[j]), mk<R>(re, im), out);
+  }
+  out.x = group_sum<Ly::LJ>(out.x);
+  out.y = group_sum<Ly::LJ>(out.y);
+  return out;
+}
+
+// Colours c0 = 4 a + 2 q and c0 + 1 in one launch, exactly as two k_stencil_gs launches.  Node
+// (I, J) of colour c0 + 1 and node (I, J - 1) of colour c0 pair up one to one, and within the
+// stencil reach (2) each member of a pair couples to no other node of the two colours but its
+// partner.  One wave per pair updates (I, J - 1) from the values before the launch, writes it,
+// then updates (I, J) with that new value at offset (0, -1) and the values before the launch
+// elsewhere: no other wave reads or writes either node.
+template <int B, typename R, typename M, typename Vx>
+__global__ __launch_bounds__(256) void k_stencil_gs_pair(const M* __restrict__ A,
+                                                         const M* __restrict__ Dinv, Vx* x,
+                                                         const Vx* __restrict__ f, int Lt, int Lx,
+                                                         int c0, int64_t stride,
+                                                         const RhsState* __restrict__ st) {
+  using Ly = Lanes<B>;
+  using C = cplx<R>;
+  const int r = blockIdx.y;
+  if (st && !st[r].active) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int slot = lane / Ly::LPN, i = (lane / Ly::LJ) % B, jl = lane % Ly::LJ;
+  const int qx = Lx >> 2;
+  const int ncn = (Lt >> 2) * qx;
+  const int k = (blockIdx.x * 4 + wv) * Ly::NPW + slot;
+  const bool live = k < ncn;
+  const int kk = live ? k : 0;
+  const int colour = c0 + 1;
+  const int t = 4 * (kk / qx) + (colour >> 2), xc = 4 * (kk % qx) + (colour & 3);   // xc >= 1
+  Vx* xr = x + r * stride;
+  const Vx* fr = f ? f + r * stride : nullptr;
+  const int node_lane0 = slot * Ly::LPN;
+  C sub_val[Ly::CPL];
+  const C v = gs_node<B, R, M, Vx>(A, Dinv, xr, fr, Lt, Lx, t, xc - 1, i, jl, node_lane0, live, false, sub_val);
+  if (live && jl == 0) xr[int64_t(t * Lx + xc - 1) * B + i] = cconv<Vx>(v);
+#pragma unroll
+  for (int c = 0; c < Ly::CPL; ++c) {
+    const int j = jl + Ly::LJ * c;
+    // the partner's new value in the storage type, as the two-launch sequence reads it
+    const R re = __shfl(v.x, node_lane0 + j * Ly::LJ), im = __shfl(v.y, node_lane0 + j * Ly::LJ);
+    sub_val[c] = cconv<C>(cconv<Vx>(mk<R>(re, im)));
+  }
+  const C out = gs_node<B, R, M, Vx>(A, Dinv, xr, fr, Lt, Lx, t, xc, i, jl, node_lane0, live, true, sub_val);
+  if (live && jl == 0) xr[int64_t(t * Lx + xc) * B + i] = cconv<Vx>(out);
+}
+
 // y = Ainv v for the coarsest level (matrix FP64): 64 lanes per row, 4 rows per block.
 template <typename Vin, typename Vout>
 __global__ __launch_bounds__(256) void k_dense_apply(const double2* __restrict__ Ainv,
@@ -179,6 +270,15 @@ static void gs_b(hipStream_t s, const void* A, const void* D, void* x, const voi
                      (const V*)f, Lt, Lx, colour, stride, st);
 }
 
+template <int B, typename R, typename M, typename V>
+static void gs_pair_b(hipStream_t s, const void* A, const void* D, void* x, const void* f, int Lt, int Lx,
+                      int c0, int nrhs, int64_t stride, const RhsState* st) {
+  const int ncn = (Lt / 4) * (Lx / 4);
+  dim3 g(unsigned((ncn + Lanes<B>::NPB - 1) / Lanes<B>::NPB), unsigned(nrhs));
+  AMAMG_LAUNCH((k_stencil_gs_pair<B, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
+               (const V*)f, Lt, Lx, c0, stride, st);
+}
+
 #define AMAMG_B_DISPATCH(fn, prec, ...)                                                       \
   do {                                                                                        \
     if (prec == F64) {                                                                        \
@@ -212,6 +312,11 @@ void stencil_apply(hipStream_t s, Real prec, const void* A, const void* x, void*
 void stencil_gs(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
                 int Lt, int Lx, int b, int colour, int nrhs, int64_t stride, const RhsState* st) {
   AMAMG_B_DISPATCH(gs_b, prec, s, A, Dinv, x, f, Lt, Lx, colour, nrhs, stride, st);
+}
+
+void stencil_gs_pair(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
+                     int Lt, int Lx, int b, int c0, int nrhs, int64_t stride, const RhsState* st) {
+  AMAMG_B_DISPATCH(gs_pair_b, prec, s, A, Dinv, x, f, Lt, Lx, c0, nrhs, stride, st);
 }
 
 void dense_apply(hipStream_t s, Real prec, const double2* Ainv, const void* v, void* y, int n,

@@ -78,6 +78,10 @@ void stencil_apply(hipStream_t s, Real prec, const void* A, const void* x, void*
 // f may be null (zero right-hand side)
 void stencil_gs(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
                 int Lt, int Lx, int b, int colour, int nrhs, int64_t stride, const RhsState* st);
+// colours c0 and c0 + 1 (c0 even) of the same sweep in one launch, bitwise equal to two
+// stencil_gs launches
+void stencil_gs_pair(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
+                     int Lt, int Lx, int b, int c0, int nrhs, int64_t stride, const RhsState* st);
 // coarsest: y = Ainv v (matrix FP64 always; vectors in prec)
 void dense_apply(hipStream_t s, Real prec, const double2* Ainv, const void* v, void* y, int n,
                  int nrhs, int64_t stride, const RhsState* st);

@@ -256,12 +256,13 @@ static void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x)
         timer_stop(ctx, c.s, rec);
       }
     } else {
-      for (int col = 0; col < 16; ++col) {
+      // colour pairs (2q, 2q + 1): one launch each
+      for (int col = 0; col < 16; col += 2) {
         const double ncn = double(g.nnode()) / 16.0;
         const int rec = k == 1 ? timer_start(ctx, c.s, AMAMG_KT_COARSE_GS, c.step, c.group,
-                                             ncn * 25.0 * g.b * g.b * cb + double(nd) * cb + 2.0 * ncn * g.b * cb)
+                                             2.0 * (ncn * 25.0 * g.b * g.b * cb + 2.0 * ncn * g.b * cb) + double(nd) * cb)
                                : -1;
-        stencil_gs(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, col, c.nrhs, nd, st);
+        stencil_gs_pair(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, col, c.nrhs, nd, st);
         timer_stop(ctx, c.s, rec);
       }
     }
