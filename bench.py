@@ -39,8 +39,8 @@ def log(*a):
 FAMILIES = ["fine_matvec", "fine_gs", "restrict0", "prolong0", "coarse_gs", "dots", "update"]
 KERNEL_NAMES = {"fine_matvec": "k_wilson_apply", "fine_gs": "k_wilson_gs",
                 "restrict0": "k_restrict_partial (fine level)", "prolong0": "k_prolong (fine level)",
-                "coarse_gs": "k_stencil_gs (level 1)", "dots": "k_dots<nv> (all basis sizes)",
-                "update": "k_update_dots<nv, s> + k_update_norm<nv> (all basis sizes)"}
+                "coarse_gs": "k_stencil_gs (level 1)", "dots": "k_gram<nv, s, w> (all basis sizes)",
+                "update": "k_lag_update<nv, s> (all basis sizes)"}
 
 
 def run_steps(lib, torch, ctx, h, b, x, nrhs, precision, steps, warmup, timer=None, groups=1):
@@ -225,8 +225,62 @@ def serve_leg(lib, n_requests, qps, n_configs=16, slots=16, instances=4, log_eve
             "lattices": sorted({c["L"] for c in cfgs}), "gauge_generation_s": t_gen}
 
 
+def multi_lattice_leg(lib, torch, ctx, groups, instances=8, slots=8, nrhs_per=8):
+    """(1) 64 right-hand sides on the 128^2 beta = 8 lattice at m0 = m_c + 0.01 as one batched
+    solve (step = setup + solve, like the headline); (2) the 32 lattices of
+    synth.multi_lattice_configs() (L in 32..256, beta in [2, 10], m0 = m_c + gap), nrhs_per
+    right-hand sides each, submitted at once to the server in mixed precision: makespan cold
+    (hierarchy builds included) and warm (hierarchies cached)."""
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    out = {}
+    w = synth.WORKLOADS["C4"]
+    m0 = synth.critical_masses()["C4"] + w.gaps[0]
+    g = lib.Gauge(ctx, synth.links_to_abi(w.links()), m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=w.levels, agg_size=w.agg, overlap=w.overlap,
+                                                   n_test_vectors=w.n_test_vectors))
+    b = torch.from_numpy(synth.field_to_abi(synth.gaussian_rhs(w.L, w.L, w.rhs_seed, nrhs=64))).to("cuda")
+    x = torch.zeros_like(b)
+    dt, ts, infos, _ = run_steps(lib, torch, ctx, h, b, x, 64, lib.MIXED_FP32, 2, 1, groups=groups)
+    its = [i.iterations for i in infos]
+    out["one_lattice_128_64rhs"] = {"solves_per_s": 128 / dt, "s_per_step": dt / 2, "setup_s": ts / 2,
+                                    "iterations_min_max": [min(its), max(its)],
+                                    "converged": all(i.converged for i in infos)}
+    h.close()
+    g.close()
+    del b, x
+    cfgs = synth.multi_lattice_configs()
+    mcs = synth.multi_lattice_critical()
+    with ProcessPoolExecutor(max_workers=16, mp_context=mp.get_context("spawn")) as ex:
+        links = list(ex.map(synth.serving_links, cfgs))
+    srv = lib.Server(0, lib.default_server_params(slots=slots, max_instances=instances, precision=lib.MIXED_FP32))
+    gids = [srv.add_gauge(synth.links_to_abi(U)) for U in links]
+    del links
+    setups = [lib.default_setup_params(**synth.serving_setup(c["L"])) for c in cfgs]
+    rhs = [synth.field_to_abi(synth.gaussian_rhs(c["L"], c["L"], c["seed"] + 99, nrhs=nrhs_per)) for c in cfgs]
+    for phase in ("cold", "warm"):
+        t0 = time.perf_counter()
+        for k, c in enumerate(cfgs):
+            srv.submit(gids[k], mcs[k] + c["gap"], rhs[k], setups[k])
+        srv.wait(1800)
+        span = time.perf_counter() - t0
+        done = [i for i, _ in srv.poll(len(cfgs) + 1)]
+        out[f"lattices_32_{phase}"] = {
+            "makespan_s": span, "solves_per_s": len(cfgs) * nrhs_per / span,
+            "ok": sum(1 for i in done if i.status == lib.OK and i.converged),
+            "iterations_max": max(i.iterations for i in done),
+            "max_rel_residual": max(i.true_rel_residual for i in done)}
+    st = srv.stats()
+    out["lattices_32_setups"] = st.setups
+    out["lattices"] = {str(L): sum(1 for c in cfgs if c["L"] == L) for L in synth.MULTI_SIZES}
+    out["nrhs_per_lattice"] = nrhs_per
+    out["instances"], out["slots"] = instances, slots
+    srv.close()
+    return out
+
+
 # ------------------------------------------------------------------ profile summaries
-FAMILY_PATTERNS = {"update": "k_update_", "dots": "k_dots<"}
+FAMILY_PATTERNS = {"update": "k_lag_update<", "dots": "k_gram<"}
 TRAFFIC_MD = os.path.join(ROOT, "profiles", "gram_schmidt_256x256_64rhs_mixed_traffic.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2608_03515_amd", "csrc", "krylov.hip")
 
@@ -329,6 +383,10 @@ def main():
                     help="requests of the serving leg (0: skip it)")
     ap.add_argument("--serve-qps", type=float, default=8.0)
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg")
+    ap.add_argument("--no-multi", action="store_true", help="skip the multi-lattice leg")
+    ap.add_argument("--stencil-only", action="store_true",
+                    help="run only the 4096^2 fine-stencil bandwidth leg (for kernel traces)")
+    ap.add_argument("--multi-only", action="store_true", help="run only the multi-lattice leg")
     ap.add_argument("--family", default=None, choices=FAMILIES,
                     help="kernel family of the roofline (default: the largest in an instrumented "
                          "one-stream step)")
@@ -361,6 +419,18 @@ def main():
     if args.serve_only:
         out = serve_leg(lib, args.serve_requests, args.serve_qps)
         print(json.dumps({"serving": out}), flush=True)
+        return
+    if args.stencil_only:
+        stream = torch.cuda.Stream()
+        torch.cuda.set_stream(stream)
+        ctx = lib.Context(0, stream.cuda_stream)
+        print(json.dumps({"stencil_4096": stencil_bandwidth(lib, torch, ctx)}), flush=True)
+        return
+    if args.multi_only:
+        stream = torch.cuda.Stream()
+        torch.cuda.set_stream(stream)
+        ctx = lib.Context(0, stream.cuda_stream)
+        print(json.dumps({"multi_lattice": multi_lattice_leg(lib, torch, ctx, args.groups)}), flush=True)
         return
 
     stream = torch.cuda.Stream()          # default priority; the library runs on it
@@ -450,6 +520,17 @@ def main():
     stencil = None if args.no_stencil else stencil_bandwidth(lib, torch, ctx)
     if stencil:
         log("stencil", json.dumps(stencil))
+    multi = None
+    if not args.no_multi:
+        if not os.path.exists(synth.MULTI_CRITICAL_PATH):
+            log("multi-lattice leg skipped: critical masses not generated "
+                "(python tests/golden/make_golden.py --multi-only)")
+        else:
+            try:
+                multi = multi_lattice_leg(lib, torch, ctx, args.groups)
+            except Exception as e:          # an optional leg must not cost the headline line
+                multi = {"error": f"{type(e).__name__}: {e}"}
+            log("multi-lattice", json.dumps(multi))
     serving = None
     if args.serve_requests > 0:
         serving = serve_leg(lib, args.serve_requests, args.serve_qps)
@@ -478,6 +559,7 @@ def main():
         "roofline": roofline,
         "stencil_4096": stencil,
         "serving": serving,
+        "multi_lattice": multi,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline ...")

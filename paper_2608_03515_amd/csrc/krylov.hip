@@ -1,17 +1,34 @@
 // FGMRES(m) kernels, FP64 (paper: FGMRES outer solver, relative tolerance 1e-10).
 //
-// Right-preconditioned flexible Arnoldi with classical Gram-Schmidt applied twice.  Every
-// reduction is two-level and fixed-order: each block writes its partial sums, and the block
-// that finishes last (a device-scope counter decides which) adds the partials in block
-// order.  Results are therefore bitwise reproducible although blocks finish in any order.
-// The last block also runs the scalar bookkeeping that needs the reduced value (Hessenberg
-// column, Givens rotations, cycle start and end), so no extra launch is spent on it.
+// Right-preconditioned flexible Arnoldi, orthogonalised by classical Gram-Schmidt with a delayed
+// second pass (DCGS2: Bielich, Langou, Thomas, Swirydowicz, Yamazaki, Boman, "Low-synch
+// Gram-Schmidt with delayed reorthogonalization for Krylov solvers", Parallel Computing 112
+// (2022)).  Basis slot j holds u_j, the new direction projected once, until step j finalises it:
+//
+//   pass A (k_gram):        s = V_<j^H u_j, alpha = ||u_j||^2, t = V_<j^H w, beta = u_j^H w
+//                           (w = D z_j, z_j = M u_j), one read of slots 0..j and w;
+//   control (k_lag_control): rho_j = sqrt(alpha - ||s||^2); column j-1 of the Hessenberg
+//                           matrix gains s and h_{j,j-1} = rho_j, is rotated and tested; then
+//                           v_j = (u_j - V_<j s) / rho_j and, for z^_j = z_j / rho_j,
+//                           h_<j = t / rho_j, h_j = (beta - s^H t) / rho_j^2;
+//   pass B (k_lag_update):  v_j in place of u_j and u_{j+1} = w / rho_j - V_<j h_<j - v_j h_j
+//                           into slot j+1, one read of slots 0..j and w.
+//
+// A cycle of m steps ends with pass A on slots 0..m alone, which finalises column m-1.  In
+// exact arithmetic the basis, the Hessenberg matrix and hence the iterates are those of FGMRES
+// with classical Gram-Schmidt applied twice; the preconditioner sees u_j instead of v_j, which
+// FGMRES allows (its search directions are arbitrary) and which for the linear V-cycle spans
+// the same space.  The solution update uses z^_i = z_i / rho_i.  Slot 0 holds v_0 = r / ||r||
+// exactly (rho_0 = 1, s empty).
+//
+// Every reduction is two-level and fixed-order: each block writes its partial sums, and the
+// consumer adds them in block order, so results are bitwise reproducible.
 //
 // Givens rotation for (a, b) = (H_jj, H_{j+1,j}): nu = sqrt(|a|^2 + |b|^2), c = |a| / nu,
 // s = (a / |a|) conj(b) / nu (c = 0, s = 1 when a = 0); a rotation maps (x, y) to
 // (c x + s y, -conj(s) x + c y); g_{j+1} = -conj(s) g_j, g_j = c g_j.
 //
-// Vector layouts: basis V [j][rhs][n], search directions Z [j][rhs][n], w and x [rhs][n].
+// Vector layouts: basis V [slot][rhs][n], search directions Z [j][rhs][n], w and x [rhs][n].
 #include <array>
 #include <utility>
 
@@ -20,6 +37,8 @@
 namespace amamg {
 
 #define KMAXV 32
+// partial-sum slot of the Gram pass per block: dots with u at [0, nv), with w at [KMAXV, KMAXV + nv)
+#define KGRAM 64
 
 template <int NV>
 __device__ inline void block_partial(const double2 (&acc)[NV], int nv, double2* out, double* lds) {
@@ -40,10 +59,10 @@ __device__ inline void block_partial(const double2 (&acc)[NV], int nv, double2* 
   }
 }
 
-// fin[i] = sum over blocks of part_r[blk][i] for i < nv, added in a fixed order (8 strided
-// groups of blocks with eight independent partial sums each, then the groups in order).  Every
-// kernel that needs the total recomputes it with this routine, so all agree bitwise.  Must be
-// called by all 256 threads; fin and scratch are shared arrays.
+// fin[i] = sum over blocks of part_r[blk * STRIDE + i] for i < nv, added in a fixed order (8
+// strided groups of blocks with eight independent partial sums each, then the groups in order).
+// Must be called by all 256 threads; fin and scratch are shared arrays.
+template <int STRIDE>
 __device__ inline void sum_blocks(const double2* __restrict__ part_r, int nblk, int nv,
                                   double2* fin, double2* scratch) {
   const int i = threadIdx.x & (KMAXV - 1), c = threadIdx.x / KMAXV;
@@ -55,7 +74,7 @@ __device__ inline void sum_blocks(const double2* __restrict__ part_r, int nblk, 
     for (int b = c; b < nblk; b += 64) {
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (b + 8 * u < nblk) q[u] = cadd(q[u], part_r[int64_t(b + 8 * u) * KMAXV + i]);
+        if (b + 8 * u < nblk) q[u] = cadd(q[u], part_r[int64_t(b + 8 * u) * STRIDE + i]);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) s = cadd(s, q[u]);
@@ -84,9 +103,10 @@ struct ArnoldiArgs {
   int hist_cap;
 };
 
-// Arnoldi step j for one rhs, given hn = ||w|| after CGS2: col[0..j] = h1 + h2 is the new
-// Hessenberg column and col[j + 1] = hn; the earlier rotations csl/snl (all in LDS).  Rotates
-// the column, forms rotation j and updates g; the caller writes the column back to H.
+// Completes Hessenberg column j = a.j of one rhs: col[0..j] holds its projections and
+// col[j + 1] = hn = h_{j+1,j}; the earlier rotations csl/snl (all in LDS).  Rotates the
+// column, forms rotation j, updates g and tests the end of the cycle; the caller writes the
+// column back to H.
 __device__ inline void arnoldi_step(const KrylovDims& dm, RhsState& s, int r, double hn, double2* col,
                                     const double* csl, const double2* snl, const ArnoldiArgs& a) {
   const int m = dm.m, j = a.j;
@@ -131,86 +151,31 @@ __device__ inline void arnoldi_step(const KrylovDims& dm, RhsState& s, int r, do
   else s.inv_h = 1.0 / hn;
 }
 
-// partials of h = V^H w  (V_0 .. V_{NV-1}); NV is a compile-time count so the accumulators
-// fit the actual basis size
-template <int NV>
-__global__ __launch_bounds__(256) void k_dots(KrylovDims dm, const double2* __restrict__ V,
+// Lanes per element of the Gram and update passes: enough to keep the per-lane share of the
+// basis (and its accumulators or coefficients) in a few registers, few enough that the
+// shuffles stay cheap.  Lane `sub` holds the slots i = sub + S k.
+constexpr int gram_lanes(int nv) { return nv <= 2 ? 1 : nv <= 8 ? 2 : 4; }
+constexpr int update_lanes(int nv) { return nv <= 2 ? 1 : nv <= 12 ? 2 : 4; }
+
+// Pass A: partials of V^H u into part[.][0, NV) and (HAS_W) of V^H w into part[.][KMAXV,
+// KMAXV + NV), over slots 0..NV-1, where u is slot NV-1 itself.  Each basis value is read
+// from memory once; u and w are read once per element and shared by the element's lanes.
+template <int NV, int S, bool HAS_W>
+__global__ __launch_bounds__(256) void k_gram(KrylovDims dm, const double2* __restrict__ V,
                                               int64_t vsj, const double2* __restrict__ w,
                                               double2* __restrict__ part,
                                               const RhsState* __restrict__ st) {
-  const int r = blockIdx.y;
-  if (st && !st[r].active) return;
-  __shared__ double lds[2 * NV * 4];
-  double2 acc[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = make_double2(0, 0);
-  const double2* wr = w + r * dm.n;
-  const double2* Vr = V + r * dm.n;
-  for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < dm.n; d += int64_t(gridDim.x) * 256) {
-    const double2 wd = wr[d];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = cfmac(Vr[i * vsj + d], wd, acc[i]);
-  }
-  block_partial<NV>(acc, NV, part + (int64_t(r) * gridDim.x + blockIdx.x) * KMAXV, lds);
-}
-
-// w -= sum_i V_i h_i with h the total of the previous kernel's partials hpart; then partials
-// of ||w_new||^2 into part.
-template <int NV>
-__global__ __launch_bounds__(256) void k_update_norm(KrylovDims dm, const double2* __restrict__ V,
-                                                     int64_t vsj, double2* __restrict__ w,
-                                                     const double2* __restrict__ hpart,
-                                                     double2* __restrict__ part,
-                                                     const RhsState* __restrict__ st) {
-  const int r = blockIdx.y;
-  if (!st[r].active) return;
-  __shared__ double lds[2 * 4];
-  __shared__ double2 hs[KMAXV], scratch[8 * KMAXV];
-  sum_blocks(hpart + int64_t(r) * gridDim.x * KMAXV, gridDim.x, NV, hs, scratch);
-  double2 acc[1] = {make_double2(0, 0)};
-  double2* wr = w + r * dm.n;
-  const double2* Vr = V + r * dm.n;
-#pragma unroll 1
-  for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < dm.n; d += int64_t(gridDim.x) * 256) {
-    double2 wd = wr[d];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) wd = csub(wd, cmul(Vr[i * vsj + d], hs[i]));
-    wr[d] = wd;
-    acc[0].x += cabs2(wd);
-  }
-  block_partial<1>(acc, 1, part + (int64_t(r) * gridDim.x + blockIdx.x) * KMAXV, lds);
-}
-
-// Lanes per element of the fused update: enough to keep the per-lane share of the basis (and
-// its accumulators) in a few registers, few enough that the shuffles stay cheap.
-constexpr int update_lanes(int nv) { return nv <= 2 ? 1 : nv <= 12 ? 2 : 4; }
-
-// Fused first-projection update and second projection: w -= sum_i V_i h_i (h from hpart), then
-// partials of V^H w_new into part, in one pass over V.  S lanes share an element: lane `sub`
-// holds the basis vectors i = sub + S k in registers, the S partial sums of V_i h_i are added
-// with lane shuffles, and every lane then accumulates conj(V_i) w_new for its own vectors, so
-// each basis value is read from memory once.
-template <int NV, int S>
-__global__ __launch_bounds__(256) void k_update_dots(KrylovDims dm, const double2* __restrict__ V,
-                                                     int64_t vsj, double2* __restrict__ w,
-                                                     const double2* __restrict__ hpart,
-                                                     double2* __restrict__ part,
-                                                     const RhsState* __restrict__ st) {
   constexpr int K = (NV + S - 1) / S, EPB = 256 / S;
   const int r = blockIdx.y;
   if (!st[r].active) return;
-  __shared__ double2 hs[KMAXV], scratch[8 * KMAXV], red[4][KMAXV];
-  sum_blocks(hpart + int64_t(r) * gridDim.x * KMAXV, gridDim.x, NV, hs, scratch);
+  __shared__ double2 red[4][KGRAM];
   const int sub = threadIdx.x % S;
-  double2 hk[K], acc[K];
+  double2 au[K], aw[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = sub + S * k;
-    hk[k] = i < NV ? hs[i] : make_double2(0, 0);
-    acc[k] = make_double2(0, 0);
-  }
-  double2* wr = w + r * dm.n;
+  for (int k = 0; k < K; ++k) au[k] = aw[k] = make_double2(0, 0);
   const double2* Vr = V + r * dm.n;
+  const double2* ur = Vr + int64_t(NV - 1) * vsj;
+  const double2* wr = HAS_W ? w + r * dm.n : nullptr;
 #pragma unroll 1
   for (int64_t d = int64_t(blockIdx.x) * EPB + threadIdx.x / S; d < dm.n; d += int64_t(gridDim.x) * EPB) {
     double2 v[K];
@@ -219,71 +184,167 @@ __global__ __launch_bounds__(256) void k_update_dots(KrylovDims dm, const double
       const int i = sub + S * k;
       v[k] = i < NV ? Vr[i * vsj + d] : make_double2(0, 0);
     }
-    double2 p = make_double2(0, 0);
+    const double2 ud = ur[d];
 #pragma unroll
-    for (int k = 0; k < K; ++k) p = cfma(v[k], hk[k], p);
+    for (int k = 0; k < K; ++k) au[k] = cfmac(v[k], ud, au[k]);
+    if constexpr (HAS_W) {
+      const double2 wd = wr[d];
 #pragma unroll
-    for (int o = 1; o < S; o <<= 1) {
-      p.x += __shfl_xor(p.x, o);
-      p.y += __shfl_xor(p.y, o);
+      for (int k = 0; k < K; ++k) aw[k] = cfmac(v[k], wd, aw[k]);
     }
-    const double2 wd = csub(wr[d], p);
-    if (sub == 0) wr[d] = wd;
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = cfmac(v[k], wd, acc[k]);
   }
-  // block totals: lanes with equal `sub` hold the same basis vectors (xor offsets S .. 32 within
-  // a wave), then the four waves in order
+  // block totals: lanes with equal `sub` hold the same slots (xor offsets S .. 32 within a
+  // wave), then the four waves in order
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    double2 a = acc[k];
+    double2 a = au[k], b = aw[k];
 #pragma unroll
     for (int o = S; o < 64; o <<= 1) {
       a.x += __shfl_xor(a.x, o);
       a.y += __shfl_xor(a.y, o);
+      if constexpr (HAS_W) {
+        b.x += __shfl_xor(b.x, o);
+        b.y += __shfl_xor(b.y, o);
+      }
     }
     const int i = sub + S * k;
-    if (lane < S && i < NV) red[wv][i] = a;
+    if (lane < S && i < NV) {
+      red[wv][i] = a;
+      if constexpr (HAS_W) red[wv][KMAXV + i] = b;
+    }
   }
   __syncthreads();
-  if (threadIdx.x < NV) {
-    double2 t = red[0][threadIdx.x];
-    for (int q = 1; q < 4; ++q) t = cadd(t, red[q][threadIdx.x]);
-    part[(int64_t(r) * gridDim.x + blockIdx.x) * KMAXV + threadIdx.x] = t;
+  const int t = threadIdx.x;
+  if (t < NV || (HAS_W && t >= KMAXV && t < KMAXV + NV)) {
+    double2 a = red[0][t];
+    for (int q = 1; q < 4; ++q) a = cadd(a, red[q][t]);
+    part[(int64_t(r) * gridDim.x + blockIdx.x) * KGRAM + t] = a;
   }
 }
 
-// Arnoldi step j, one block per rhs: h1, h2 and ||w||^2 are the totals of the three partial
-// sets of the Gram-Schmidt kernels.
-__global__ __launch_bounds__(256) void k_arnoldi(KrylovDims dm, const double2* __restrict__ p1,
-                                                 const double2* __restrict__ p2,
-                                                 const double2* __restrict__ p3,
-                                                 RhsState* __restrict__ st, ArnoldiArgs aa, int nv) {
+// Pass B: v = sum_{i<NV} a_i V_i into slot NV-1 (when write_v; slot 0 is already final) and
+// u_next = inv w + sum_{i<NV} b_i V_i into slot NV, with a = coef[r][0, NV), b = coef[r][KMAXV,
+// KMAXV + NV) and inv = coef[r][KGRAM - 1].x.  Slot NV-1 is overwritten in place: each element
+// is read before it is written, by the same lanes.
+template <int NV, int S>
+__global__ __launch_bounds__(256) void k_lag_update(KrylovDims dm, double2* __restrict__ V, int64_t vsj,
+                                                    const double2* __restrict__ w,
+                                                    const double2* __restrict__ coef,
+                                                    const RhsState* __restrict__ st, int write_v) {
+  constexpr int K = (NV + S - 1) / S, EPB = 256 / S;
+  const int r = blockIdx.y;
+  if (!st[r].active) return;
+  const int sub = threadIdx.x % S;
+  const double2* cr = coef + int64_t(r) * KGRAM;
+  double2 ak[K], bk[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = sub + S * k;
+    ak[k] = i < NV ? cr[i] : make_double2(0, 0);
+    bk[k] = i < NV ? cr[KMAXV + i] : make_double2(0, 0);
+  }
+  const double inv = cr[KGRAM - 1].x;
+  double2* Vr = V + r * dm.n;
+  const double2* wr = w + r * dm.n;
+  double2* vo = Vr + int64_t(NV - 1) * vsj;
+  double2* uo = Vr + int64_t(NV) * vsj;
+#pragma unroll 1
+  for (int64_t d = int64_t(blockIdx.x) * EPB + threadIdx.x / S; d < dm.n; d += int64_t(gridDim.x) * EPB) {
+    double2 v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = sub + S * k;
+      v[k] = i < NV ? Vr[i * vsj + d] : make_double2(0, 0);
+    }
+    double2 pa = make_double2(0, 0), pb = make_double2(0, 0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      pa = cfma(v[k], ak[k], pa);
+      pb = cfma(v[k], bk[k], pb);
+    }
+#pragma unroll
+    for (int o = 1; o < S; o <<= 1) {
+      pa.x += __shfl_xor(pa.x, o);
+      pa.y += __shfl_xor(pa.y, o);
+      pb.x += __shfl_xor(pb.x, o);
+      pb.y += __shfl_xor(pb.y, o);
+    }
+    if (sub == 0) {
+      const double2 wd = wr[d];
+      if (write_v) vo[d] = pa;
+      uo[d] = cfma(wd, make_double2(inv, 0.0), pb);
+    }
+  }
+}
+
+// Control of step j, one block per rhs, after pass A over slots 0..j (with w when has_w): for
+// j > 0 finalises Hessenberg column j-1 (adds s, h_{j,j-1} = rho_j, rotations, convergence);
+// then, while the rhs goes on and w was given, writes the pass-B coefficients, column j's
+// projections onto slots 0..j and the search-direction scale 1 / rho_j.
+__global__ __launch_bounds__(256) void k_lag_control(KrylovDims dm, const double2* __restrict__ part,
+                                                     RhsState* __restrict__ st, ArnoldiArgs aa,
+                                                     double2* __restrict__ coef,
+                                                     double* __restrict__ zsc, int has_w) {
   const int r = blockIdx.x;
   if (!st[r].active) return;
-  __shared__ double2 h1[KMAXV], h2[KMAXV], hn[KMAXV], scratch[8 * KMAXV];
+  __shared__ double2 du[KMAXV], dw[KMAXV], scratch[8 * KMAXV];
   __shared__ double2 col[KMAXV + 1], snl[KMAXV];
   __shared__ double csl[KMAXV];
-  sum_blocks(p1 + int64_t(r) * dm.nblk * KMAXV, dm.nblk, nv, h1, scratch);
-  sum_blocks(p2 + int64_t(r) * dm.nblk * KMAXV, dm.nblk, nv, h2, scratch);
-  sum_blocks(p3 + int64_t(r) * dm.nblk * KMAXV, dm.nblk, 1, hn, scratch);
-  const int m = dm.m, j = aa.j;
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = cadd(h1[i], h2[i]);
-  for (int i = threadIdx.x; i < j; i += blockDim.x) {
-    csl[i] = aa.cs[int64_t(r) * m + i];
-    snl[i] = aa.sn[int64_t(r) * m + i];
-  }
-  if (threadIdx.x == 0) col[j + 1] = make_double2(sqrt(hn[0].x), 0.0);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    RhsState s = st[r];
-    arnoldi_step(dm, s, r, sqrt(hn[0].x), col, csl, snl, aa);
-    st[r] = s;
-  }
-  __syncthreads();
+  __shared__ double rho_sh;
+  __shared__ int go;
+  const int m = dm.m, j = aa.j, nv = j + 1;
+  const double2* pr = part + int64_t(r) * dm.nblk * KGRAM;
+  sum_blocks<KGRAM>(pr, dm.nblk, nv, du, scratch);
+  if (has_w) sum_blocks<KGRAM>(pr + KMAXV, dm.nblk, nv, dw, scratch);
   double2* Hr = aa.H + int64_t(r) * (m + 1) * m;
-  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) Hr[i * m + j] = col[i];
+  if (j > 0) {
+    for (int i = threadIdx.x; i < j; i += blockDim.x) col[i] = cadd(Hr[i * m + j - 1], du[i]);
+    for (int i = threadIdx.x; i < j - 1; i += blockDim.x) {
+      csl[i] = aa.cs[int64_t(r) * m + i];
+      snl[i] = aa.sn[int64_t(r) * m + i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double ssq = 0.0;
+      for (int i = 0; i < j; ++i) ssq += cabs2(du[i]);
+      const double rho = sqrt(fmax(du[j].x - ssq, 0.0));
+      col[j] = make_double2(rho, 0.0);
+      RhsState s = st[r];
+      ArnoldiArgs a1 = aa;
+      a1.j = j - 1;
+      arnoldi_step(dm, s, r, rho, col, csl, snl, a1);
+      st[r] = s;
+      rho_sh = rho;
+      go = s.active && has_w;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) Hr[i * m + j - 1] = col[i];
+  } else {
+    if (threadIdx.x == 0) {
+      rho_sh = 1.0;
+      go = has_w;
+    }
+    __syncthreads();
+  }
+  if (!go || threadIdx.x != 0) return;
+  const double inv = 1.0 / rho_sh;
+  double2 e = dw[j];                                   // beta - s^H t
+  for (int i = 0; i < j; ++i) e = csub(e, cmulc(du[i], dw[i]));
+  const double2 ce = cscale(e, inv * inv);             // h_j of z^_j
+  double2* cr = coef + int64_t(r) * KGRAM;
+  for (int i = 0; i < j; ++i) {
+    const double2 ai = cscale(du[i], -inv);
+    const double2 ct = cscale(dw[i], inv);
+    cr[i] = ai;
+    cr[KMAXV + i] = csub(cscale(ct, -1.0), cmul(ce, ai));
+    Hr[i * m + j] = ct;
+  }
+  cr[j] = make_double2(inv, 0.0);
+  cr[KMAXV + j] = cscale(ce, -inv);
+  cr[KGRAM - 1] = make_double2(inv, 0.0);
+  Hr[j * m + j] = ce;
+  zsc[int64_t(r) * m + j] = inv;
 }
 
 // ||x||^2 per rhs whose state is active, then: mode 1 fresh states (x = b; the host marks the
@@ -347,7 +408,7 @@ __global__ __launch_bounds__(256) void k_cycle(KrylovDims dm, const double2* __r
   const int r = blockIdx.x;
   if (!st[r].active) return;
   __shared__ double2 nr[KMAXV], scratch[8 * KMAXV];
-  sum_blocks(part + int64_t(r) * dm.nblk * KMAXV, dm.nblk, 1, nr, scratch);
+  sum_blocks<KMAXV>(part + int64_t(r) * dm.nblk * KMAXV, dm.nblk, 1, nr, scratch);
   if (threadIdx.x != 0) return;
   const double nrm = sqrt(nr[0].x);
   if (mode == 1) {
@@ -376,10 +437,12 @@ __global__ __launch_bounds__(256) void k_scale_next(KrylovDims dm, const double2
   if (d < dm.n) v[r * dm.n + d] = cscale(w[r * dm.n + d], inv);
 }
 
-// y = R^{-1} g (k x k upper triangle of the rotated Hessenberg matrix); marks the rhs for the
-// x update and the true residual (active = in_cycle).
+// y = R^{-1} g (k x k upper triangle of the rotated Hessenberg matrix), then y_i / rho_i for
+// the stored directions z_i = rho_i z^_i; marks the rhs for the x update and the true residual
+// (active = in_cycle).
 __global__ void k_backsolve(KrylovDims dm, RhsState* __restrict__ st, const double2* __restrict__ H,
-                            const double2* __restrict__ g, double2* __restrict__ y) {
+                            const double2* __restrict__ g, const double* __restrict__ zsc,
+                            double2* __restrict__ y) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= dm.nrhs) return;
   RhsState s = st[r];
@@ -387,6 +450,7 @@ __global__ void k_backsolve(KrylovDims dm, RhsState* __restrict__ st, const doub
   if (!s.in_cycle || s.k == 0 || s.nonfinite) { s.active = s.in_cycle && !s.nonfinite; st[r] = s; return; }
   const double2* Hr = H + int64_t(r) * (m + 1) * m;
   const double2* gr = g + int64_t(r) * (m + 1);
+  const double* zr = zsc + int64_t(r) * m;
   double2* yr = y + int64_t(r) * m;
   for (int i = s.k - 1; i >= 0; --i) {
     double2 acc = gr[i];
@@ -395,6 +459,7 @@ __global__ void k_backsolve(KrylovDims dm, RhsState* __restrict__ st, const doub
     const double den = cabs2(d);
     yr[i] = cmul(acc, make_double2(d.x / den, -d.y / den));
   }
+  for (int i = 0; i < s.k; ++i) yr[i] = cscale(yr[i], zr[i]);
   s.active = 1;
   st[r] = s;
 }
@@ -418,61 +483,52 @@ __global__ __launch_bounds__(256) void k_update_x(KrylovDims dm, const RhsState*
 
 // ------------------------------------------------------------------------------ launchers
 
-using KFn = void (*)(hipStream_t, const KrylovDims&, const double2*, int64_t, double2*,
-                    const double2*, double2*, const RhsState*);
-
-template <int NV> void launch_dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj,
-                                   double2* w, const double2*, double2* part, const RhsState* st) {
-  AMAMG_LAUNCH((k_dots<NV>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, w, part, st);
+template <int NV, bool HAS_W>
+void launch_gram(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, const double2* w,
+                 double2* part, const RhsState* st) {
+  AMAMG_LAUNCH((k_gram<NV, gram_lanes(NV), HAS_W>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj,
+               w, part, st);
 }
 template <int NV>
-void launch_update_norm(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, double2* w,
-                        const double2* hpart, double2* part, const RhsState* st) {
-  AMAMG_LAUNCH((k_update_norm<NV>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj, w, hpart,
-                     part, st);
+void launch_lag_update(hipStream_t s, const KrylovDims& d, double2* V, int64_t vsj, const double2* w,
+                       const double2* coef, const RhsState* st, int write_v) {
+  AMAMG_LAUNCH((k_lag_update<NV, update_lanes(NV)>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d, V, vsj,
+               w, coef, st, write_v);
 }
-template <int NV>
-void launch_update_dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, double2* w,
-                        const double2* hpart, double2* part, const RhsState* st) {
-  AMAMG_LAUNCH((k_update_dots<NV, update_lanes(NV)>), dim3(d.nblk, d.nrhs), dim3(256), 0, s, d,
-                     V, vsj, w, hpart, part, st);
-}
-template <int... I>
-static constexpr std::array<KFn, sizeof...(I)> table_dots(std::integer_sequence<int, I...>) {
-  return {&launch_dots<I + 1>...};
+using GramFn = void (*)(hipStream_t, const KrylovDims&, const double2*, int64_t, const double2*,
+                        double2*, const RhsState*);
+using LagFn = void (*)(hipStream_t, const KrylovDims&, double2*, int64_t, const double2*,
+                       const double2*, const RhsState*, int);
+template <bool HAS_W, int... I>
+static constexpr std::array<GramFn, sizeof...(I)> table_gram(std::integer_sequence<int, I...>) {
+  return {&launch_gram<I + 1, HAS_W>...};
 }
 template <int... I>
-static constexpr std::array<KFn, sizeof...(I)> table_update_dots(std::integer_sequence<int, I...>) {
-  return {&launch_update_dots<I + 1>...};
+static constexpr std::array<LagFn, sizeof...(I)> table_lag(std::integer_sequence<int, I...>) {
+  return {&launch_lag_update<I + 1>...};
 }
-template <int... I>
-static constexpr std::array<KFn, sizeof...(I)> table_update_norm(std::integer_sequence<int, I...>) {
-  return {&launch_update_norm<I + 1>...};
-}
-static const auto kDots = table_dots(std::make_integer_sequence<int, KMAXV>{});
-static const auto kUpdDots = table_update_dots(std::make_integer_sequence<int, KMAXV>{});
-static const auto kUpdNorm = table_update_norm(std::make_integer_sequence<int, KMAXV>{});
+static const auto kGramW = table_gram<true>(std::make_integer_sequence<int, KMAXV - 1>{});
+static const auto kGram = table_gram<false>(std::make_integer_sequence<int, KMAXV>{});
+static const auto kLag = table_lag(std::make_integer_sequence<int, KMAXV - 1>{});
 
-void dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
-          const double2* w, double2* part, const RhsState* st) {
-  kDots[nv - 1](s, d, V, vsj, const_cast<double2*>(w), nullptr, part, st);
-}
-
-void update_dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
-                 double2* w, const double2* hpart, double2* part, const RhsState* st) {
-  kUpdDots[nv - 1](s, d, V, vsj, w, hpart, part, st);
+// nv (slots 0..nv-1) is at most KMAXV - 1 with w and KMAXV without; the restart length is
+// limited to KMAXV - 1 where solves are configured.
+void gram(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv, const double2* w,
+          double2* part, const RhsState* st) {
+  if (w) kGramW[nv - 1](s, d, V, vsj, w, part, st);
+  else kGram[nv - 1](s, d, V, vsj, nullptr, part, st);
 }
 
-void update_norm(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
-                 double2* w, const double2* hpart, double2* part, const RhsState* st) {
-  kUpdNorm[nv - 1](s, d, V, vsj, w, hpart, part, st);
-}
-
-void arnoldi(hipStream_t s, const KrylovDims& d, const double2* p1, const double2* p2,
-             const double2* p3, RhsState* st, double2* H, double* cs, double2* sn, double2* g,
-             int j, double tol, double inner_tol, int max_iters, double2* hist, int hist_cap) {
+void lag_control(hipStream_t s, const KrylovDims& d, const double2* part, RhsState* st, double2* H,
+                 double* cs, double2* sn, double2* g, double2* coef, double* zsc, int j, int has_w,
+                 double tol, double inner_tol, int max_iters, double2* hist, int hist_cap) {
   ArnoldiArgs aa{H, cs, sn, g, j, tol, inner_tol, max_iters, hist, hist_cap};
-  hipLaunchKernelGGL(k_arnoldi, dim3(d.nrhs), dim3(256), 0, s, d, p1, p2, p3, st, aa, j + 1);
+  hipLaunchKernelGGL(k_lag_control, dim3(d.nrhs), dim3(256), 0, s, d, part, st, aa, coef, zsc, has_w);
+}
+
+void lag_update(hipStream_t s, const KrylovDims& d, double2* V, int64_t vsj, int nv, const double2* w,
+                const double2* coef, const RhsState* st, int write_v) {
+  kLag[nv - 1](s, d, V, vsj, w, coef, st, write_v);
 }
 
 void norm_control(hipStream_t s, const KrylovDims& d, const double2* x, double2* part, RhsState* st,
@@ -497,9 +553,9 @@ void scale_next(hipStream_t s, const KrylovDims& d, const double2* w, double2* v
 }
 
 void backsolve_update(hipStream_t s, const KrylovDims& d, RhsState* st, const double2* H,
-                      const double2* g, double2* y, Real zprec, const void* Z, int64_t zsj,
-                      double2* x) {
-  hipLaunchKernelGGL(k_backsolve, dim3((d.nrhs + 63) / 64), dim3(64), 0, s, d, st, H, g, y);
+                      const double2* g, const double* zsc, double2* y, Real zprec, const void* Z,
+                      int64_t zsj, double2* x) {
+  hipLaunchKernelGGL(k_backsolve, dim3((d.nrhs + 63) / 64), dim3(64), 0, s, d, st, H, g, zsc, y);
   dim3 grid(unsigned((d.n + 255) / 256), d.nrhs);
   if (zprec == F64)
     hipLaunchKernelGGL((k_update_x<double2>), grid, dim3(256), 0, s, d, st, y, (const double2*)Z, zsj, x);

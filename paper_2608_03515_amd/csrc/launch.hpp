@@ -127,22 +127,22 @@ void probe_extract(hipStream_t s, const Geom& gc, int pt, int px, int ct, int cx
 void cast_matrix(hipStream_t s, const double2* A, float2* out, int64_t n);
 
 // ---- Krylov (FP64) -----------------------------------------------------------------------
-// Reductions are per-block partials [rhs][nblk][32]; the consumer of a reduction adds them in a
-// fixed order itself.
+// Reductions are per-block partials [rhs][nblk][32] (Gram pass: [rhs][nblk][64]); the consumer
+// of a reduction adds them in a fixed order itself.  Arnoldi step j with delayed
+// reorthogonalisation: gram (slots 0..j with w), lag_control (step j), lag_update; a cycle of m
+// steps ends with gram over slots 0..m without w and lag_control for step m.
 struct KrylovDims { int64_t n; int nrhs; int nblk; int m; };
-// partials of V^H w (V_0 .. V_{nv-1})
-void dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
-          const double2* w, double2* part, const RhsState* st);
-// w -= V h (h = total of hpart); partials of V^H w_new into part
-void update_dots(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
-                 double2* w, const double2* hpart, double2* part, const RhsState* st);
-// w -= V h (h = total of hpart); partials of ||w_new||^2 into part
-void update_norm(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv,
-                 double2* w, const double2* hpart, double2* part, const RhsState* st);
-// Arnoldi step j from the three partial sets: Hessenberg column, rotations, end-of-cycle test
-void arnoldi(hipStream_t s, const KrylovDims& d, const double2* p1, const double2* p2,
-             const double2* p3, RhsState* st, double2* H, double* cs, double2* sn, double2* g,
-             int j, double tol, double inner_tol, int max_iters, double2* hist, int hist_cap);
+// partials of V^H u (u = slot nv-1) and, when w is given, of V^H w, over slots 0..nv-1
+void gram(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv, const double2* w,
+          double2* part, const RhsState* st);
+// finalises Hessenberg column j-1 (rotations, end-of-cycle test) and, with has_w, writes the
+// coefficients of lag_update, column j's projections and the direction scale zsc[r][j]
+void lag_control(hipStream_t s, const KrylovDims& d, const double2* part, RhsState* st, double2* H,
+                 double* cs, double2* sn, double2* g, double2* coef, double* zsc, int j, int has_w,
+                 double tol, double inner_tol, int max_iters, double2* hist, int hist_cap);
+// slot nv-1 <- final v (when write_v), slot nv <- next direction u, from coef
+void lag_update(hipStream_t s, const KrylovDims& d, double2* V, int64_t vsj, int nv, const double2* w,
+                const double2* coef, const RhsState* st, int write_v);
 // ||x|| then mode 1: fresh states (x = b); 2: first cycle start (x = r_0); 3: cycle end and
 // restart (x = b - D x)
 void norm_control(hipStream_t s, const KrylovDims& d, const double2* x, double2* part, RhsState* st,
@@ -152,7 +152,7 @@ void scale_next(hipStream_t s, const KrylovDims& d, const double2* w, double2* v
 // st[r] = st2[r] for the slots with admit[r] != 0 (slots joining a running batch)
 void merge_states(hipStream_t s, RhsState* st, const RhsState* st2, const int* admit, int cap);
 void backsolve_update(hipStream_t s, const KrylovDims& d, RhsState* st, const double2* H,
-                      const double2* g, double2* y, Real zprec, const void* Z,
+                      const double2* g, const double* zsc, double2* y, Real zprec, const void* Z,
                       int64_t zstride_j, double2* x);
 
 }  // namespace amamg

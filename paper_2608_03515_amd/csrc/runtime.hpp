@@ -143,7 +143,9 @@ struct Workspace {
   int host_cap = 0, host_hist = 0;   // sizes of the pinned mirrors
   double2 *V = nullptr, *w = nullptr, *H = nullptr, *g = nullptr, *sn = nullptr, *y = nullptr;
   double2 *part = nullptr, *hist = nullptr;
+  double2* coef = nullptr;    // Gram update coefficients [cap][64]
   double* cs = nullptr;
+  double* zsc = nullptr;      // search-direction scales 1 / rho_j [cap][m]
   void* Z = nullptr;
   RhsState* st = nullptr;     // control state of the running batch
   RhsState* st2 = nullptr;    // state of slots being admitted

@@ -58,7 +58,8 @@ size_t workspace_bytes(const amamg_hierarchy* h, int cap, int m, Real prec, int 
   const size_t rs = prec == F64 ? sizeof(double2) : sizeof(float2);
   size_t b = sizeof(double2) * size_t(m + 1) * cap * n + size_t(m) * cap * n * rs +
              sizeof(double2) * size_t(cap) * n + sizeof(double2) * size_t(cap) * (3 * (m + 1) * m / 2 + 4 * m) +
-             sizeof(double2) * size_t(3) * cap * kMaxKrylovBlocks * 32 + sizeof(double2) * size_t(cap) * hist_cap;
+             sizeof(double2) * size_t(3) * cap * kMaxKrylovBlocks * 32 + sizeof(double2) * size_t(cap) * hist_cap +
+             sizeof(double2) * size_t(cap) * 64 + sizeof(double) * size_t(cap) * m + 2 * 256;
   for (size_t k = 1; k < h->lv.size(); ++k) b += 3 * size_t(cap) * h->lv[k].g.ndof() * rs;
   b += size_t(cap) * n * rs;
   for (size_t k = 0; k + 1 < h->lv.size(); ++k) b += size_t(cap) * level_rpart_count(h->lv[k], prec) * rs;
@@ -93,6 +94,8 @@ static void layout(Workspace& ws, const amamg_hierarchy* h, int cap, int m, Real
   ws.sn = (double2*)take(sizeof(double2) * size_t(cap) * m);
   ws.y = (double2*)take(sizeof(double2) * size_t(cap) * m);
   ws.part = (double2*)take(sizeof(double2) * size_t(3) * cap * kMaxKrylovBlocks * 32);
+  ws.coef = (double2*)take(sizeof(double2) * size_t(cap) * 64);
+  ws.zsc = (double*)take(sizeof(double) * size_t(cap) * m);
   ws.st = (RhsState*)take(sizeof(RhsState) * cap);
   ws.st2 = (RhsState*)take(sizeof(RhsState) * cap);
   ws.admit = (int*)take(sizeof(int) * cap);
@@ -428,36 +431,39 @@ void Batch::enqueue_cycle() {
   const int nt = gg->nt, nx = gg->nx;
   const double inner_tol = T == F64 ? 0.0 : 1e-5;
   double2* p1 = ws->part;
-  double2* p2 = ws->part + size_t(ws->cap) * kd.nblk * 32;
-  double2* p3 = ws->part + size_t(2) * ws->cap * kd.nblk * 32;
   const void* Um0 = link0(gg, c.mat_links);
   const void* Um1 = link1(gg, c.mat_links);
   const double cl = c.mat_links == LINK_F64 ? 16 : 8;
+  // Timer steps: served(step) counts the rhs whose cycle reached more than `step` columns.
+  // The V-cycle, matvec and Gram pass of step j run for every rhs still active at step j
+  // (> j - 1 columns); the update runs for those that go on after column j - 1 (> j).
   for (int j = 0; j < m; ++j) {
-    double2* vj = ws->V + j * vsj;
+    double2* uj = ws->V + j * vsj;
     void* zj = (char*)ws->Z + size_t(j) * vsj * zs;
-    c.step = j;
-    vcycle(c, 0, F64, vj, zj);
-    int rec = timer_start(ctx, s, AMAMG_KT_FINE_MATVEC, j, group, double(nt) * nx * (2 * zs + 2 * cl + 32));
+    c.step = j - 1;
+    vcycle(c, 0, F64, uj, zj);
+    int rec = timer_start(ctx, s, AMAMG_KT_FINE_MATVEC, j - 1, group, double(nt) * nx * (2 * zs + 2 * cl + 32));
     wilson_apply(s, c.mat_links, Um0, Um1, T, zj, F64, ws->w, nullptr, nt, nx, h->m0, ws->cap, n, st);
     timer_stop(ctx, s, rec);
-    // Gram-Schmidt: family DOTS = every V^H w pass, family UPDATE = every w -= V h pass
-    const double dot_bytes = double(j + 2) * n * 16, upd_bytes = double(j + 3) * n * 16;
-    rec = timer_start(ctx, s, AMAMG_KT_DOTS, j, group, dot_bytes);
-    dots(s, kd, ws->V, vsj, j + 1, ws->w, p1, st);
+    // Gram-Schmidt: family DOTS = the Gram passes (slots 0..j and w), family UPDATE = the
+    // updates (read slots 0..j and w; write slot j + 1 and, for j > 0, slot j)
+    rec = timer_start(ctx, s, AMAMG_KT_DOTS, j - 1, group, double(j + 2) * n * 16);
+    gram(s, kd, ws->V, vsj, j + 1, ws->w, p1, st);
     timer_stop(ctx, s, rec);
-    rec = timer_start(ctx, s, AMAMG_KT_UPDATE, j, group, upd_bytes);
-    update_dots(s, kd, ws->V, vsj, j + 1, ws->w, p1, p2, st);
+    lag_control(s, kd, p1, st, ws->H, ws->cs, ws->sn, ws->g, ws->coef, ws->zsc, j, 1, p.rel_tol, inner_tol,
+                p.max_iters, ws->hist, ws->hist_cap);
+    rec = timer_start(ctx, s, AMAMG_KT_UPDATE, j, group, double(j + (j > 0 ? 4 : 3)) * n * 16);
+    lag_update(s, kd, ws->V, vsj, j + 1, ws->w, ws->coef, st, j > 0);
     timer_stop(ctx, s, rec);
-    rec = timer_start(ctx, s, AMAMG_KT_UPDATE, j, group, upd_bytes);
-    update_norm(s, kd, ws->V, vsj, j + 1, ws->w, p2, p3, st);
-    timer_stop(ctx, s, rec);
-    arnoldi(s, kd, p1, p2, p3, st, ws->H, ws->cs, ws->sn, ws->g, j, p.rel_tol, inner_tol, p.max_iters,
-            ws->hist, ws->hist_cap);
-    if (j + 1 < m) scale_next(s, kd, ws->w, ws->V + (j + 1) * vsj, st);
     check_launch();
   }
-  backsolve_update(s, kd, st, ws->H, ws->g, ws->y, T, ws->Z, vsj, x);
+  // the rhs that ran all m steps: last column from the reorthogonalisation of slot m
+  int rec = timer_start(ctx, s, AMAMG_KT_DOTS, m - 1, group, double(m + 1) * n * 16);
+  gram(s, kd, ws->V, vsj, m + 1, nullptr, p1, st);
+  timer_stop(ctx, s, rec);
+  lag_control(s, kd, p1, st, ws->H, ws->cs, ws->sn, ws->g, ws->coef, ws->zsc, m, 0, p.rel_tol, inner_tol,
+              p.max_iters, ws->hist, ws->hist_cap);
+  backsolve_update(s, kd, st, ws->H, ws->g, ws->zsc, ws->y, T, ws->Z, vsj, x);
   wilson_apply(s, LINK_F64, gg->U, gg->U + int64_t(nt) * nx, F64, x, F64, ws->V, b, nt, nx, h->m0, ws->cap, n, st);
   norm_control(s, kd, ws->V, p1, st, 3, ws->g, p.rel_tol, p.max_iters, ws->hist, ws->hist_cap);
   scale_next(s, kd, ws->V, ws->V, st);

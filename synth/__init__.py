@@ -25,7 +25,8 @@ import numpy as np
 __all__ = ["gen_theta", "gen_links", "gaussian_rhs", "plaquette_angles",
            "Workload", "WORKLOADS", "critical_masses", "links_to_abi", "field_to_abi",
            "field_from_abi", "SERVING_SIZES", "SERVING_MASSES", "serving_setup", "serving_configs",
-           "serving_links", "request_stream"]
+           "serving_links", "request_stream", "MULTI_SIZES", "MULTI_GAPS", "multi_lattice_configs",
+           "multi_lattice_critical", "MULTI_CRITICAL_PATH"]
 
 
 def plaquette_angles(theta: np.ndarray) -> np.ndarray:
@@ -196,3 +197,31 @@ def request_stream(n: int, qps: float, n_configs: int, seed: int = 6006, max_rhs
                     "m0": float(rng.choice(SERVING_MASSES)), "nrhs": int(rng.integers(1, max_rhs + 1)),
                     "seed": int(rng.integers(1 << 30))})
     return out
+
+
+# ------------------------------------------------------------------- multi-lattice workload
+
+MULTI_SIZES = (32, 64, 128, 256)
+MULTI_GAPS = (0.01, 0.02, 0.05)
+
+
+def multi_lattice_configs(n: int = 32, seed: int = 4004, sweeps: int = 100) -> list:
+    """n independent lattices: the first four cover every size once, the rest draw L uniformly;
+    beta uniform in [2, 10]; a gap above the lattice's critical mass from MULTI_GAPS."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n):
+        L = MULTI_SIZES[i] if i < len(MULTI_SIZES) else int(rng.choice(MULTI_SIZES))
+        out.append({"L": L, "beta": float(rng.uniform(2.0, 10.0)), "sweeps": sweeps,
+                    "seed": seed + 1 + i, "gap": float(rng.choice(MULTI_GAPS))})
+    return out
+
+
+MULTI_CRITICAL_PATH = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests",
+                                   "golden", "multi_lattice_critical.json")
+
+
+def multi_lattice_critical() -> list:
+    """Critical masses of multi_lattice_configs() (tests/golden/multi_lattice_critical.json)."""
+    with open(MULTI_CRITICAL_PATH) as f:
+        return json.load(f)["m_c"]

@@ -370,3 +370,34 @@ def test_c3_full_size_setup_sampled_parity(lib, ctx):
     assert rel(A2, olev[2].A.toarray()) < 1e-10
     h.close()
     g.close()
+
+
+def test_c4_two_wirebaskets_per_direction(lib, ctx):
+    """128^2, a = 8, o = 2, 3 levels: level 1 is 16 x 16 nodes with only 2 wirebaskets per
+    direction (each overlap strip is shared with the same neighbour on both sides).  Full setup
+    parity (classification, interpolation rows, level-1 operator, dense coarsest operator) and an
+    FP64 solve with the oracle's iteration count."""
+    w = synth.WORKLOADS["C4"]
+    m0 = synth.critical_masses()["C4"] + w.gaps[0]
+    U = w.links()
+    say("C4 setup parity")
+    prm = amg.SetupParams(levels=3, agg=8, overlap=2, n_test_vectors=8)
+    olev = amg.setup(U, m0, prm)
+    g = make_gauge(lib, ctx, U, m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=8, overlap=2, n_test_vectors=8))
+    for k in range(2):
+        lev = olev[k]
+        kind, owner, node = h.aggregates(k)
+        assert np.array_equal(kind, lev.cls["kind"]) and np.array_equal(owner, lev.cls["owner"])
+        assert np.array_equal(node, lev.cls["node"])
+        assert rel(h.prolongator_rows(k, 2), oracle_rows(lev, 8, 2)) < 1e-10
+    assert rel(h.coarse_operator(1, coarsest=False), oracle_stencil(olev[1].A, 16, 16, 8)) < 1e-10
+    assert rel(h.coarse_operator(2, coarsest=True), olev[2].A.toarray()) < 1e-10
+    h.close()
+    g.close()
+    say("C4 solve")
+    psi = synth.gaussian_rhs(w.L, w.L, w.rhs_seed)[0]
+    xo, io, x, ig, st, _, _, _ = run_pair(lib, ctx, U, m0, psi, 3, 8, 2, 8, olevels=olev)
+    assert st == lib.OK and ig.converged and io.converged
+    assert ig.iterations == io.iterations
+    assert rel(x, xo) <= 1e-9
