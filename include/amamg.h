@@ -201,6 +201,16 @@ amamg_status amamg_get_prolongator(const amamg_hierarchy *h, int32_t level, doub
  * offset (dt, dx) in [-2,2]^2 at index (dt+2)*5 + (dx+2) couples node n to node n+(dt,dx);
  * at the coarsest level the dense matrix double [n][n][2], n = lt*lx*b. */
 amamg_status amamg_get_coarse_operator(const amamg_hierarchy *h, int32_t level, double *out);
+/* Transfers between level `level` and the next coarser one (Multilevel approach: restriction
+ * P^H, prolongation P) for nrhs vectors on host buffers, with the kernels the V-cycle of the
+ * given precision runs (AMAMG_FP64, or AMAMG_MIXED_FP32 with FP32 interpolation weights and
+ * FP32 accumulation).  direction 0: out = P^H in, in double [nrhs][n_level][2] (read as FP64, as
+ * the fine level's restriction reads the Krylov vector), out double [nrhs][n_coarse][2];
+ * direction 1: out = P in, in double [nrhs][n_coarse][2] (rounded to the precision's type),
+ * out double [nrhs][n_level][2].  n = lt*lx*b of the level.  Synchronous; allocates its
+ * device buffers.  AMAMG_ERR_INVALID_ARG for the coarsest level or a bad direction. */
+amamg_status amamg_apply_transfer(amamg_hierarchy *h, int32_t level, int32_t precision,
+                                  int32_t direction, int32_t nrhs, const double *in, double *out);
 /* Smoothed test vectors of level `level`: double [n_test_vectors][lt*lx*b][2]. */
 amamg_status amamg_get_test_vectors(const amamg_hierarchy *h, int32_t level, double *out);
 

@@ -35,7 +35,7 @@ EXPORTED = ["amamg_default_setup_params", "amamg_default_solve_params", "amamg_c
             "amamg_residual_history", "amamg_apply_dirac", "amamg_apply_dirac_device",
             "amamg_level_info",
             "amamg_get_aggregates", "amamg_get_prolongator", "amamg_get_coarse_operator",
-            "amamg_get_test_vectors", "amamg_kernel_timer", "amamg_kernel_timer_read",
+            "amamg_get_test_vectors", "amamg_apply_transfer", "amamg_kernel_timer", "amamg_kernel_timer_read",
             "amamg_server_default_params", "amamg_server_create", "amamg_server_destroy",
             "amamg_server_add_gauge", "amamg_server_submit", "amamg_server_poll", "amamg_server_wait",
             "amamg_server_stats", "amamg_server_last_error"]
@@ -107,6 +107,7 @@ _sig = {
     "amamg_get_prolongator": (C.c_int, [_vp, C.c_int32, _vp]),
     "amamg_get_coarse_operator": (C.c_int, [_vp, C.c_int32, _vp]),
     "amamg_get_test_vectors": (C.c_int, [_vp, C.c_int32, _vp]),
+    "amamg_apply_transfer": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp, _vp]),
     "amamg_kernel_timer": (C.c_int, [_vp, C.c_uint32]),
     "amamg_kernel_timer_read": (C.c_int, [_vp, C.c_int32, _P(C.c_int64), _P(C.c_double), _P(C.c_double)]),
     "amamg_server_default_params": (None, [_P(ServerParams)]),
@@ -303,6 +304,22 @@ class Hierarchy:
         else:
             out = np.zeros((lt * lx, 25, b, b, 2))
         self.ctx.check(_lib.amamg_get_coarse_operator(self.h, level, _ptr(out)))
+        return out[..., 0] + 1j * out[..., 1]
+
+    def transfer(self, level: int, vecs: np.ndarray, direction: int, precision: int = 0) -> np.ndarray:
+        """direction 0: P^H vecs (vecs complex [nrhs][n_level]); 1: P vecs (vecs complex
+        [nrhs][n_coarse]); the kernels of the given precision's V-cycle."""
+        lt, lx, b = self.level_info(level)
+        ltc, lxc, bcn = self.level_info(level + 1)
+        n, nc = lt * lx * b, ltc * lxc * bcn
+        vecs = np.asarray(vecs, dtype=complex)
+        nrhs = vecs.shape[0]
+        if vecs.shape != (nrhs, n if direction == 0 else nc):
+            raise ValueError("vector shape does not match the level")
+        src = np.ascontiguousarray(np.stack([vecs.real, vecs.imag], axis=-1))
+        out = np.zeros((nrhs, nc if direction == 0 else n, 2))
+        self.ctx.check(_lib.amamg_apply_transfer(self.h, level, precision, direction, nrhs, _ptr(src),
+                                                 _ptr(out)))
         return out[..., 0] + 1j * out[..., 1]
 
     def test_vectors(self, level: int, nv: int) -> np.ndarray:

@@ -758,6 +758,63 @@ amamg_status amamg_get_coarse_operator(const amamg_hierarchy* h, int32_t level, 
   return copy_out(h, out, L.A, sizeof(double2) * L.g.nnode() * 25 * L.g.b * L.g.b);
 }
 
+amamg_status amamg_apply_transfer(amamg_hierarchy* h, int32_t level, int32_t precision, int32_t direction,
+                                  int32_t nrhs, const double* in, double* out) {
+  if (!h || !in || !out || nrhs < 1) return h ? fail(h->gauge->ctx, {AMAMG_ERR_INVALID_ARG, "bad argument"}) : AMAMG_ERR_INVALID_ARG;
+  amamg_context* ctx = h->gauge->ctx;
+  try {
+    REQUIRE(precision == AMAMG_FP64 || precision == AMAMG_MIXED_FP32, AMAMG_ERR_INVALID_ARG,
+            "precision must be FP64 or MIXED_FP32");
+    REQUIRE(level >= 0 && level + 1 < int(h->lv.size()), AMAMG_ERR_INVALID_ARG,
+            "level must have a coarser level");
+    REQUIRE(direction == 0 || direction == 1, AMAMG_ERR_INVALID_ARG, "direction must be 0 or 1");
+    HIPCHECK(hipSetDevice(ctx->device));
+    const LevelData& L = h->lv[level];
+    const Geom& g = L.g;
+    const int64_t nd = g.ndof(), ndc = h->lv[level + 1].g.ndof();
+    const bool f64 = precision == AMAMG_FP64;
+    const Real T = f64 ? F64 : F32;
+    const void* P = f64 ? (const void*)L.P : (const void*)L.P32;
+    const size_t cs = f64 ? sizeof(double2) : sizeof(float2);
+    const int64_t nin = direction == 0 ? nd : ndc, nout = direction == 0 ? ndc : nd;
+    hipStream_t s = ctx->stream;
+    Arena io;
+    // inputs: FP64 for the restriction (the fine level's restriction reads the FP64 Krylov
+    // vector), the level's precision for the prolongation; outputs in the level's precision
+    std::vector<float2> h32;
+    void* din = nullptr;
+    if (direction == 0 || f64) {
+      din = io.alloc<double2>(size_t(nrhs) * nin);
+      HIPCHECK(hipMemcpyAsync(din, in, sizeof(double2) * nrhs * nin, hipMemcpyHostToDevice, s));
+    } else {
+      h32.resize(size_t(nrhs) * nin);
+      for (size_t i = 0; i < h32.size(); ++i) h32[i] = make_float2(float(in[2 * i]), float(in[2 * i + 1]));
+      din = io.alloc<float2>(h32.size());
+      HIPCHECK(hipMemcpyAsync(din, h32.data(), sizeof(float2) * h32.size(), hipMemcpyHostToDevice, s));
+    }
+    void* dout = io.alloc<char>(cs * nrhs * nout);
+    if (direction == 0) {
+      void* part = io.alloc<char>(cs * nrhs * g.nI * g.nJ * restrict_chunks(g, L.nf, T) * g.ncol());
+      restrict_(s, T, P, L.rows, L.nrows, L.nf, F64, din, dout, part, g, nrhs, nd, ndc, nullptr);
+    } else {
+      prolong(s, T, P, L.rows, L.nrows, L.nf, din, dout, g, 0, nrhs, nd, ndc, nullptr);
+    }
+    check_launch();
+    if (f64) {
+      HIPCHECK(hipMemcpyAsync(out, dout, sizeof(double2) * nrhs * nout, hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+    } else {
+      std::vector<float2> o32(size_t(nrhs) * nout);
+      HIPCHECK(hipMemcpyAsync(o32.data(), dout, sizeof(float2) * o32.size(), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      for (size_t i = 0; i < o32.size(); ++i) { out[2 * i] = o32[i].x; out[2 * i + 1] = o32[i].y; }
+    }
+  } catch (const Fail& f) {
+    return fail(ctx, f);
+  }
+  return AMAMG_OK;
+}
+
 amamg_status amamg_get_test_vectors(const amamg_hierarchy* h, int32_t level, double* out) {
   if (!h || !out || level < 0 || level >= int(h->lv.size()) - 1) return AMAMG_ERR_INVALID_ARG;
   const LevelData& L = h->lv[level];

@@ -291,6 +291,158 @@ __global__ __launch_bounds__(256) void k_prolong_tiled(
   }
 }
 
+// Matrix-core transfers (FP32, NCOL = 128 interpolation columns, 64 right-hand sides per
+// workgroup).  Per wirebasket the transfer is a dense complex product between the chunk's
+// interpolation rows and the right-hand sides; it runs as real 16x16x4 FP32 MFMA tiles
+// (v_mfma_f32_16x16x4f32: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+// D[4 (l / 16) + i][l % 16], i < 4), four real products per complex one.  D is oriented with the
+// right-hand side as its row index, so a lane's results run along interpolation columns
+// (restriction) or fine rows (prolongation) and the stores are contiguous.  Wave w owns the
+// right-hand sides 16 w .. 16 w + 15 of the workgroup's group of 64.
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+__device__ inline mfma_f4 mfma16(float a, float b, mfma_f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <int NCOL> struct MfmaRows;                   // fine rows per chunk
+template <> struct MfmaRows<128> { static constexpr int RESTRICT = 16, PROLONG = 32; };
+constexpr int kMfmaRhs = 64;
+// The matrix-core path serves 128 columns (coarse levels of a = 8, o = 2); with 32 columns (the
+// fine level) the register-tiled kernels above are faster: their smaller LDS footprint keeps
+// more workgroups per compute unit to hide the row gather, which dominates there.
+__host__ __device__ inline bool mfma_cols(int ncol) { return ncol == 128; }
+
+// Restriction pass 1 (same partial layout as k_restrict_partial):
+// D[rhs][col] = sum over the chunk's rows of r_rhs[row] conj(P[row][col]).
+template <int NCOL, int RCH, typename Vin>
+__global__ __launch_bounds__(256) void k_restrict_mfma(
+    const float2* __restrict__ P, const int* __restrict__ rows, const int* __restrict__ nrows, int maxrows,
+    const Vin* __restrict__ rin, float2* __restrict__ part, int nW, int nchunk, int nrhs, int64_t stride_f,
+    const RhsState* __restrict__ st) {
+  static_assert(RCH % 4 == 0 && NCOL % 16 == 0, "tile shape");
+  constexpr int RS = RCH + 1, PS = NCOL + 1, CT = NCOL / 16;
+  __shared__ float2 Pl[RCH * PS];
+  __shared__ float2 Rl[kMfmaRhs * RS];
+  __shared__ int ri[RCH];
+  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  const int w = bid / nchunk, chunk = bid - (bid / nchunk) * nchunk;
+  const int g0 = blockIdx.y * kMfmaRhs, ng = min(kMfmaRhs, nrhs - g0);
+  const int r0 = chunk * RCH, cnt = max(0, min(nrows[w] - r0, RCH));
+  for (int k = threadIdx.x; k < RCH; k += 256) ri[k] = k < cnt ? rows[int64_t(w) * maxrows + r0 + k] : 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < RCH * NCOL; q += 256) {
+    const int k = q / NCOL, c = q - (q / NCOL) * NCOL;
+    Pl[k * PS + c] = k < cnt ? P[int64_t(ri[k]) * NCOL + c] : make_float2(0.f, 0.f);
+  }
+  for (int q = threadIdx.x; q < kMfmaRhs * RCH; q += 256) {
+    const int rr = q / RCH, k = q - (q / RCH) * RCH;
+    const bool live = rr < ng && k < cnt && (!st || st[g0 + rr].active);
+    Rl[rr * RS + k] = live ? cconv<float2>(rin[(g0 + rr) * stride_f + ri[k]]) : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+  mfma_f4 re[CT], im[CT];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) re[t] = im[t] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+  for (int kk = 0; kk < RCH; kk += 4) {
+    const float2 a = Rl[(wv * 16 + lr) * RS + kk + lk];            // A[rhs][row] = r
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const float2 b = Pl[(kk + lk) * PS + t * 16 + lr];            // B[row][col] = P
+      re[t] = mfma16(a.x, b.x, re[t]);
+      re[t] = mfma16(a.y, b.y, re[t]);
+      im[t] = mfma16(a.y, b.x, im[t]);
+      im[t] = mfma16(-a.x, b.y, im[t]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rr = wv * 16 + 4 * lk + i;
+    if (rr < ng && (!st || st[g0 + rr].active)) {
+      float2* out = part + ((int64_t(g0 + rr) * nW + w) * nchunk + chunk) * NCOL + lr;
+#pragma unroll
+      for (int t = 0; t < CT; ++t) out[t * 16] = make_float2(re[t][i], im[t][i]);
+    }
+  }
+}
+
+// Prolongation y = P e (add: y += P e): D[rhs][row] = sum_col e_rhs[col] P[row][col] over the
+// chunk's rows; chunk 0 also writes the vertex rows of node (I, J) (identity on corner 0).
+template <int NCOL, int RCH>
+__global__ __launch_bounds__(256) void k_prolong_mfma(
+    const float2* __restrict__ P, const int* __restrict__ rows, const int* __restrict__ nrows, int maxrows,
+    const float2* __restrict__ e, float2* __restrict__ y, Geom g, int nchunk, int add, int nrhs,
+    int64_t stride_f, int64_t stride_c, const RhsState* __restrict__ st) {
+  static_assert(RCH % 16 == 0 && NCOL % 4 == 0, "tile shape");
+  constexpr int PS = NCOL + 1, ES = NCOL + 1, RT = RCH / 16;
+  __shared__ float2 Pl[RCH * PS];
+  __shared__ float2 El[kMfmaRhs * ES];
+  __shared__ int ri[RCH];
+  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  const int w = bid / nchunk, chunk = bid - (bid / nchunk) * nchunk;
+  const int I = w / g.nJ, J = w - (w / g.nJ) * g.nJ;
+  const int g0 = blockIdx.y * kMfmaRhs, ng = min(kMfmaRhs, nrhs - g0);
+  const int r0 = chunk * RCH, cnt = max(0, min(nrows[w] - r0, RCH));
+  const int nv_rows = chunk == 0 ? g.o * g.o * g.b : 0;
+  for (int k = threadIdx.x; k < RCH; k += 256) ri[k] = k < cnt ? rows[int64_t(w) * maxrows + r0 + k] : 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < RCH * NCOL; q += 256) {
+    const int k = q / NCOL, c = q - (q / NCOL) * NCOL;
+    Pl[k * PS + c] = k < cnt ? P[int64_t(ri[k]) * NCOL + c] : make_float2(0.f, 0.f);
+  }
+  int cn[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) cn[c] = ((I + (c >> 1)) % g.nI) * g.nJ + (J + (c & 1)) % g.nJ;
+  for (int q = threadIdx.x; q < kMfmaRhs * NCOL; q += 256) {
+    const int rr = q / NCOL, col = q - (q / NCOL) * NCOL;
+    const int c = col / g.bc, j = col - (col / g.bc) * g.bc;
+    El[rr * ES + col] = rr < ng ? e[(g0 + rr) * stride_c + int64_t(cn[c]) * g.bc + j] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+  mfma_f4 re[RT], im[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) re[t] = im[t] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+  for (int kc = 0; kc < NCOL; kc += 4) {
+    const float2 a = El[(wv * 16 + lr) * ES + kc + lk];            // A[rhs][col] = e
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const float2 b = Pl[(t * 16 + lr) * PS + kc + lk];            // B[col][row] = P[row][col]
+      re[t] = mfma16(a.x, b.x, re[t]);
+      re[t] = mfma16(-a.y, b.y, re[t]);
+      im[t] = mfma16(a.x, b.y, im[t]);
+      im[t] = mfma16(a.y, b.x, im[t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    const int k = t * 16 + lr;
+    if (k >= cnt) continue;
+    const int row = ri[k];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rr = wv * 16 + 4 * lk + i;
+      if (rr >= ng || (st && !st[g0 + rr].active)) continue;
+      float2* yr = y + (g0 + rr) * stride_f;
+      float2 v = make_float2(re[t][i], im[t][i]);
+      if (add) v = cadd(v, yr[row]);
+      yr[row] = v;
+    }
+  }
+  for (int q = threadIdx.x; q < ng * nv_rows; q += 256) {
+    const int rr = q / nv_rows, v = q - rr * nv_rows;   // (pt*o + px)*b + qq of node (I, J)
+    if (st && !st[g0 + rr].active) continue;
+    const int qq = v % g.b, pp = v / g.b;
+    const int pt = pp / g.o, px = pp - (pp / g.o) * g.o;
+    const int64_t vrow = int64_t((g.a * I + pt) * g.Lx + (g.a * J + px)) * g.b + qq;
+    float2 acc = El[rr * ES + v];
+    float2* yr = y + (g0 + rr) * stride_f;
+    if (add) acc = cadd(acc, yr[vrow]);
+    yr[vrow] = acc;
+  }
+}
+
 template <typename R, typename Vin, typename Vout>
 __global__ __launch_bounds__(256) void k_restrict_gather(const cplx<R>* __restrict__ part,
                                                          const Vin* __restrict__ rin,
@@ -420,6 +572,9 @@ static size_t tile_smem(const TileShape& t, int ncol, int cs) {
 }
 
 int restrict_chunks(const Geom& g, int nf, Real prec) {
+  if (prec == F32 && mfma_cols(g.ncol())) {
+    return (nf * g.b + MfmaRows<128>::RESTRICT - 1) / MfmaRows<128>::RESTRICT;
+  }
   if (tiled_cols(g.ncol())) {
     const int rch = prec == F64 ? TiledRows<double, 32>::RESTRICT : TiledRows<float, 32>::RESTRICT;
     return (nf * g.b + rch - 1) / rch;
@@ -435,6 +590,27 @@ static void prolong_tiled(hipStream_t s, const void* P, const int* rows, const i
   AMAMG_LAUNCH((k_prolong_tiled<NCOL, TiledRows<R, NCOL>::PROLONG, TiledRows<R, NCOL>::RHS_P, R, M, V, V>), dim3(unsigned(g.nI * g.nJ * nchunk)), dim3(256), 0, s,
                (const M*)P, rows, nrows, maxrows, (const V*)e, (V*)y, g, nchunk, add, nrhs, stride_f,
                stride_c, st);
+}
+
+template <int NCOL>
+static void prolong_mfma(hipStream_t s, const void* P, const int* rows, const int* nrows, int maxrows,
+                         const void* e, void* y, const Geom& g, int add, int nrhs, int64_t stride_f,
+                         int64_t stride_c, const RhsState* st) {
+  constexpr int RCH = MfmaRows<NCOL>::PROLONG;
+  const int nchunk = (maxrows + RCH - 1) / RCH;
+  const dim3 grid(unsigned(g.nI * g.nJ * nchunk), unsigned((nrhs + kMfmaRhs - 1) / kMfmaRhs));
+  AMAMG_LAUNCH((k_prolong_mfma<NCOL, RCH>), grid, dim3(256), 0, s, (const float2*)P, rows, nrows, maxrows,
+               (const float2*)e, (float2*)y, g, nchunk, add, nrhs, stride_f, stride_c, st);
+}
+
+template <int NCOL, typename Vin>
+static void restrict_mfma(hipStream_t s, const void* P, const int* rows, const int* nrows, int maxrows,
+                          const void* r, void* part, int nW, int nchunk, int nrhs, int64_t stride_f,
+                          const RhsState* st) {
+  const dim3 grid(unsigned(nW * nchunk), unsigned((nrhs + kMfmaRhs - 1) / kMfmaRhs));
+  hipLaunchKernelGGL((k_restrict_mfma<NCOL, MfmaRows<NCOL>::RESTRICT, Vin>), grid, dim3(256), 0, s,
+                     (const float2*)P, rows, nrows, maxrows, (const Vin*)r, (float2*)part, nW, nchunk, nrhs,
+                     stride_f, st);
 }
 
 template <int NCOL, typename R, typename M, typename Vin>
@@ -457,6 +633,10 @@ void prolong(hipStream_t s, Real prec, const void* P, const int* rows, const int
              int64_t stride_c, const RhsState* st) {
   const int cs = prec == F64 ? 16 : 8;
   const int maxrows = nf * g.b;
+  if (prec == F32 && mfma_cols(g.ncol())) {
+    prolong_mfma<128>(s, P, rows, nrows, maxrows, e, y, g, add, nrhs, stride_f, stride_c, st);
+    return;
+  }
   if (g.ncol() == 32) {
     if (prec == F64) prolong_tiled<32, double, double2, double2>(s, P, rows, nrows, maxrows, e, y, g, add, nrhs, stride_f, stride_c, st);
     else prolong_tiled<32, float, float2, float2>(s, P, rows, nrows, maxrows, e, y, g, add, nrhs, stride_f, stride_c, st);
@@ -493,6 +673,19 @@ void restrict_(hipStream_t s, Real prec, const void* P, const int* rows, const i
   dim3 g2(unsigned((int64_t(g.nI) * g.nJ * g.bc * lanes + 255) / 256), unsigned(nrhs));
   const size_t sm = tile_smem(ts, g.ncol(), cs);
   const int nW = g.nI * g.nJ;
+  if (prec == F32 && mfma_cols(g.ncol())) {
+    if (rin == F64) restrict_mfma<128, double2>(s, P, rows, nrows, maxrows, r, part, nW, nchunk, nrhs, stride_f, st);
+    else restrict_mfma<128, float2>(s, P, rows, nrows, maxrows, r, part, nW, nchunk, nrhs, stride_f, st);
+    if (rin == F64)
+      hipLaunchKernelGGL((k_restrict_gather<float, double2, float2>), g2, dim3(256), 0, s,
+                         (const float2*)part, (const double2*)r, (float2*)rc, g, nchunk, lanes,
+                         stride_f, stride_c, st);
+    else
+      hipLaunchKernelGGL((k_restrict_gather<float, float2, float2>), g2, dim3(256), 0, s,
+                         (const float2*)part, (const float2*)r, (float2*)rc, g, nchunk, lanes,
+                         stride_f, stride_c, st);
+    return;
+  }
   if (tiled_cols(g.ncol())) {
     if (g.ncol() == 32) {
       if (prec == F64) restrict_tiled<32, double, double2, double2>(s, P, rows, nrows, maxrows, r, part, nW, nchunk, nrhs, stride_f, st);

@@ -8,9 +8,15 @@ multi_lattice_critical.json: the same for the 32 lattices of synth.multi_lattice
 
 Run from the repository root:  python tests/golden/make_golden.py [--multi-only]
 """
-import json
 import os
-import sys
+
+# one BLAS thread per process, set before numpy loads: the multi-lattice pool runs one process per
+# core, and threads inherited by its forked workers would oversubscribe the cores many times over
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_v, "1")
+
+import json  # noqa: E402
+import sys  # noqa: E402
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
@@ -24,11 +30,8 @@ def _mc(cfg):
 
 
 def multi(workers=8):
-    """One process per lattice, one BLAS thread each (the sparse factorisations of eight
-    processes would otherwise oversubscribe the cores)."""
+    """One process per lattice (one BLAS thread each, see the top of this file)."""
     from concurrent.futures import ProcessPoolExecutor
-    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
-        os.environ[v] = "1"
     cfgs = synth.multi_lattice_configs()
     # largest lattices first, so that the pool's tail holds the short jobs
     order = sorted(range(len(cfgs)), key=lambda i: -cfgs[i]["L"])

@@ -372,17 +372,24 @@ def test_c3_full_size_setup_sampled_parity(lib, ctx):
     g.close()
 
 
-def test_c4_two_wirebaskets_per_direction(lib, ctx):
+@pytest.fixture(scope="module")
+def c4_oracle():
+    """The 128^2 workload's links, mass and oracle hierarchy (a = 8, o = 2, 3 levels)."""
+    w = synth.WORKLOADS["C4"]
+    m0 = synth.critical_masses()["C4"] + w.gaps[0]
+    U = w.links()
+    prm = amg.SetupParams(levels=3, agg=8, overlap=2, n_test_vectors=8)
+    return U, m0, amg.setup(U, m0, prm)
+
+
+def test_c4_two_wirebaskets_per_direction(lib, ctx, c4_oracle):
     """128^2, a = 8, o = 2, 3 levels: level 1 is 16 x 16 nodes with only 2 wirebaskets per
     direction (each overlap strip is shared with the same neighbour on both sides).  Full setup
     parity (classification, interpolation rows, level-1 operator, dense coarsest operator) and an
     FP64 solve with the oracle's iteration count."""
     w = synth.WORKLOADS["C4"]
-    m0 = synth.critical_masses()["C4"] + w.gaps[0]
-    U = w.links()
+    U, m0, olev = c4_oracle
     say("C4 setup parity")
-    prm = amg.SetupParams(levels=3, agg=8, overlap=2, n_test_vectors=8)
-    olev = amg.setup(U, m0, prm)
     g = make_gauge(lib, ctx, U, m0)
     h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=8, overlap=2, n_test_vectors=8))
     for k in range(2):
@@ -401,3 +408,78 @@ def test_c4_two_wirebaskets_per_direction(lib, ctx):
     assert st == lib.OK and ig.converged and io.converged
     assert ig.iterations == io.iterations
     assert rel(x, xo) <= 1e-9
+
+
+def _transfer_case(lib, h, olev, level, rng, nrhs, precision):
+    """Restriction and prolongation of `level` against the oracle's P (vertex rows included),
+    element by element within an error bound of the arithmetic: FP64 to 1e-9 of |P|^H |d| (the
+    interpolation weights agree with the oracle's to ~1e-12), FP32 to 2 (K + 2) 2^-24 of it, K
+    the number of terms of the longest row or column (rounded inputs and weights, K-term sums)."""
+    P = olev[level].P.tocsr()
+    absP = abs(P)
+    n, nc = P.shape
+    u32 = 2.0 ** -24
+    kmax = max(int(np.diff(P.indptr).max()), int(np.diff(P.tocsc().indptr).max()))
+    tol = 1e-9 if precision == lib.FP64 else 2 * (kmax + 2) * u32
+    d = rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))
+    rc = h.transfer(level, d, 0, precision)
+    ref = (P.conj().T @ d.T).T
+    bound = tol * (absP.T @ abs(d).T).T + 1e-300
+    assert np.all(abs(rc - ref) <= bound), (level, nrhs, precision, float(np.max(abs(rc - ref) / bound)))
+    e = rng.standard_normal((nrhs, nc)) + 1j * rng.standard_normal((nrhs, nc))
+    y = h.transfer(level, e, 1, precision)
+    ref = (P @ e.T).T
+    bound = tol * (absP @ abs(e).T).T + 1e-300
+    assert np.all(abs(y - ref) <= bound), (level, nrhs, precision, float(np.max(abs(y - ref) / bound)))
+
+
+def test_transfers_match_oracle(lib, ctx, c4_oracle):
+    """Restriction P^H and prolongation P of the 128^2 a = 8, o = 2 hierarchy (32 interpolation
+    columns on the fine level: register tiles; 128 on level 1: the mixed V-cycle's matrix-core
+    tiles, 64 right-hand sides a workgroup) and of the 64^2 a = 4, o = 1 one (8 columns), FP64
+    and FP32, for 1, 17, 64 and 70 right-hand sides (a partial tile, a full group, a second
+    group)."""
+    rng = np.random.default_rng(8080)
+    U, m0, olev = c4_oracle
+    g = make_gauge(lib, ctx, U, m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=8, overlap=2, n_test_vectors=8))
+    for level in (0, 1):
+        for nrhs in (1, 17, 64, 70):
+            for precision in (lib.FP64, lib.MIXED_FP32):
+                say("transfer C4", level, nrhs, precision)
+                _transfer_case(lib, h, olev, level, rng, nrhs, precision)
+    h.close()
+    g.close()
+    w = synth.WORKLOADS["C2"]
+    m0 = synth.critical_masses()["C2"] + w.gaps[1]
+    U = w.links()
+    olev = amg.setup(U, m0, amg.SetupParams(levels=3, agg=4, overlap=1, n_test_vectors=8))
+    g = make_gauge(lib, ctx, U, m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=4, overlap=1, n_test_vectors=8))
+    for level in (0, 1):
+        for precision in (lib.FP64, lib.MIXED_FP32):
+            say("transfer C2", level, precision)
+            _transfer_case(lib, h, olev, level, rng, 17, precision)
+    h.close()
+    g.close()
+
+
+def test_c4_mixed_batch_within_bound(lib, ctx):
+    """Mixed precision on the 128^2 a = 8, o = 2 workload (matrix-core level-1 transfers) for 20
+    right-hand sides: every solution within the FP32 mode's bound of the FP64 solve, iteration
+    counts within 10 % of FP64's (a wrong transfer weakens the preconditioner)."""
+    w = synth.WORKLOADS["C4"]
+    m0 = synth.critical_masses()["C4"] + w.gaps[0]
+    psi = synth.gaussian_rhs(w.L, w.L, 4242, nrhs=20)
+    g = make_gauge(lib, ctx, w.links(), m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=8, overlap=2, n_test_vectors=8))
+    say("C4 mixed batch")
+    x64, i64, st64 = h.solve(synth.field_to_abi(psi), lib.default_solve_params(precision=lib.FP64))
+    x32, i32, st32 = h.solve(synth.field_to_abi(psi), lib.default_solve_params(precision=lib.MIXED_FP32))
+    h.close()
+    g.close()
+    assert st64 == lib.OK and st32 == lib.OK
+    for r in range(20):
+        assert i32[r].converged and i32[r].true_rel_residual <= 1e-10
+        assert rel(synth.field_from_abi(x32)[r], synth.field_from_abi(x64)[r]) <= 1e-9
+        assert abs(i32[r].iterations - i64[r].iterations) <= max(5, i64[r].iterations // 10)
