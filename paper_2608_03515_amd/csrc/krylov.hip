@@ -151,11 +151,11 @@ __device__ inline void arnoldi_step(const KrylovDims& dm, RhsState& s, int r, do
   else s.inv_h = 1.0 / hn;
 }
 
-// Lanes per element of the Gram and update passes: enough to keep the per-lane share of the
-// basis (and its accumulators or coefficients) in a few registers, few enough that the
-// shuffles stay cheap.  Lane `sub` holds the slots i = sub + S k.
-constexpr int gram_lanes(int nv) { return nv <= 2 ? 1 : nv <= 8 ? 2 : 4; }
-constexpr int update_lanes(int nv) { return nv <= 2 ? 1 : nv <= 12 ? 2 : 4; }
+// Lanes per element of the Gram and update passes; lane `sub` holds the slots i = sub + S k.
+// Measured cache-cold at 64 rhs x 131072 unknowns: S = 2 is within 2 % of the fastest choice
+// from 3 to 20 slots (S = 8 is up to 2x slower); above 24 slots S = 4 bounds the registers.
+constexpr int gram_lanes(int nv) { return nv <= 2 ? 1 : nv <= 24 ? 2 : 4; }
+constexpr int update_lanes(int nv) { return nv <= 2 ? 1 : nv <= 24 ? 2 : 4; }
 
 // Pass A: partials of V^H u into part[.][0, NV) and (HAS_W) of V^H w into part[.][KMAXV,
 // KMAXV + NV), over slots 0..NV-1, where u is slot NV-1 itself.  Each basis value is read
