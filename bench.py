@@ -279,6 +279,36 @@ def multi_lattice_leg(lib, torch, ctx, groups, instances=8, slots=8, nrhs_per=8)
     return out
 
 
+AGG_SWEEP = ((3, 4, 1), (3, 8, 1), (3, 8, 2), (2, 16, 2))      # (levels, a, o)
+
+
+def agg_sweep_leg(lib, torch, ctx, groups, nrhs=64):
+    """Sensitivity to the wirebasket size (the paper's parameter spread): the 256^2 workload's
+    field and mass, 64 right-hand sides, mixed precision, setup + solve per (levels, a, o)."""
+    w = synth.WORKLOADS["C3"]
+    m0 = synth.critical_masses()["C3"] + w.gaps[0]
+    g = lib.Gauge(ctx, synth.links_to_abi(w.links()), m0)
+    b = torch.from_numpy(synth.field_to_abi(synth.gaussian_rhs(w.L, w.L, w.rhs_seed, nrhs=nrhs))).to("cuda")
+    x = torch.zeros_like(b)
+    out = []
+    for levels, a, o in AGG_SWEEP:
+        t0 = time.perf_counter()
+        h = lib.Hierarchy(g, lib.default_setup_params(levels=levels, agg_size=a, overlap=o,
+                                                       n_test_vectors=w.n_test_vectors))
+        torch.cuda.synchronize()
+        t_first = time.perf_counter() - t0
+        dt, ts, infos, _ = run_steps(lib, torch, ctx, h, b, x, nrhs, lib.MIXED_FP32, 1, 1, groups=groups)
+        its = [i.iterations for i in infos]
+        rec = {"levels": levels, "a": a, "o": o, "solves_per_s": nrhs / dt, "setup_s": ts,
+               "first_setup_s": t_first, "iterations_min_max": [min(its), max(its)],
+               "converged": all(i.converged for i in infos)}
+        log("agg sweep", json.dumps(rec))
+        out.append(rec)
+        h.close()
+    g.close()
+    return out
+
+
 # ------------------------------------------------------------------ profile summaries
 FAMILY_PATTERNS = {"update": "k_lag_update<", "dots": "k_gram<"}
 TRAFFIC_MD = os.path.join(ROOT, "profiles", "gram_schmidt_256x256_64rhs_mixed_traffic.md")
@@ -384,6 +414,7 @@ def main():
     ap.add_argument("--serve-qps", type=float, default=8.0)
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg")
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-lattice leg")
+    ap.add_argument("--no-agg-sweep", action="store_true", help="skip the aggregate-size sweep")
     ap.add_argument("--stencil-only", action="store_true",
                     help="run only the 4096^2 fine-stencil bandwidth leg (for kernel traces)")
     ap.add_argument("--multi-only", action="store_true", help="run only the multi-lattice leg")
@@ -531,6 +562,12 @@ def main():
             except Exception as e:          # an optional leg must not cost the headline line
                 multi = {"error": f"{type(e).__name__}: {e}"}
             log("multi-lattice", json.dumps(multi))
+    agg = None
+    if not args.no_agg_sweep:
+        try:
+            agg = agg_sweep_leg(lib, torch, ctx, args.groups)
+        except Exception as e:              # an optional leg must not cost the headline line
+            agg = {"error": f"{type(e).__name__}: {e}"}
     serving = None
     if args.serve_requests > 0:
         serving = serve_leg(lib, args.serve_requests, args.serve_qps)
@@ -560,6 +597,8 @@ def main():
         "stencil_4096": stencil,
         "serving": serving,
         "multi_lattice": multi,
+        "aggregate_sweep": agg,
+        "autotuner": ctx.tuning_entries(),
     }
     if not args.no_cpu_baseline:
         log("cpu baseline ...")

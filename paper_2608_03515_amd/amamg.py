@@ -35,7 +35,8 @@ EXPORTED = ["amamg_default_setup_params", "amamg_default_solve_params", "amamg_c
             "amamg_residual_history", "amamg_apply_dirac", "amamg_apply_dirac_device",
             "amamg_level_info",
             "amamg_get_aggregates", "amamg_get_prolongator", "amamg_get_coarse_operator",
-            "amamg_get_test_vectors", "amamg_apply_transfer", "amamg_kernel_timer", "amamg_kernel_timer_read",
+            "amamg_get_test_vectors", "amamg_apply_transfer", "amamg_context_set_tuning",
+            "amamg_tuning_entries", "amamg_kernel_timer", "amamg_kernel_timer_read",
             "amamg_server_default_params", "amamg_server_create", "amamg_server_destroy",
             "amamg_server_add_gauge", "amamg_server_submit", "amamg_server_poll", "amamg_server_wait",
             "amamg_server_stats", "amamg_server_last_error"]
@@ -74,6 +75,16 @@ class RequestInfo(C.Structure):
                 ("instance", C.c_int32), ("hierarchy_built", C.c_int32)]
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("lt", C.c_int32), ("lx", C.c_int32), ("b", C.c_int32),
+                ("precision", C.c_int32), ("nrhs", C.c_int32), ("choice", C.c_int32),
+                ("ncand", C.c_int32), ("cand", C.c_int32 * 4), ("us", C.c_double * 4)]
+
+
+TUNE_AUTO, TUNE_OFF, TUNE_FORCE = 0, 1, 2
+TUNE_KINDS = {0: "fine_smoother_tile", 1: "block_smoother_rhs_per_wave"}
+
+
 class ServerCounters(C.Structure):
     _fields_ = [("setups", C.c_int64), ("evictions", C.c_int64), ("resident_bytes", C.c_uint64),
                 ("hierarchy_bytes", C.c_uint64),
@@ -108,6 +119,8 @@ _sig = {
     "amamg_get_coarse_operator": (C.c_int, [_vp, C.c_int32, _vp]),
     "amamg_get_test_vectors": (C.c_int, [_vp, C.c_int32, _vp]),
     "amamg_apply_transfer": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp, _vp]),
+    "amamg_context_set_tuning": (C.c_int, [_vp, C.c_int32, C.c_int32]),
+    "amamg_tuning_entries": (C.c_int, [_vp, _vp, C.c_int32, _P(C.c_int32)]),
     "amamg_kernel_timer": (C.c_int, [_vp, C.c_uint32]),
     "amamg_kernel_timer_read": (C.c_int, [_vp, C.c_int32, _P(C.c_int64), _P(C.c_double), _P(C.c_double)]),
     "amamg_server_default_params": (None, [_P(ServerParams)]),
@@ -180,6 +193,24 @@ class Context:
         n, ms, by = C.c_int64(), C.c_double(), C.c_double()
         self.check(_lib.amamg_kernel_timer_read(self.h, KT[family], C.byref(n), C.byref(ms), C.byref(by)))
         return n.value, ms.value, by.value
+
+    def set_tuning(self, mode: int, force: int = 0):
+        """TUNE_AUTO (default), TUNE_OFF or TUNE_FORCE with candidate number `force`."""
+        self.check(_lib.amamg_context_set_tuning(self.h, mode, force))
+
+    def tuning_entries(self) -> list:
+        """The launch shapes tuned so far: dicts with kind, grid, b, precision, nrhs, choice and
+        the candidates' times (microseconds)."""
+        n = C.c_int32()
+        self.check(_lib.amamg_tuning_entries(self.h, None, 0, C.byref(n)))
+        arr = (TuneEntry * max(1, n.value))()
+        self.check(_lib.amamg_tuning_entries(self.h, arr, n.value, C.byref(n)))
+        out = []
+        for e in arr[:n.value]:
+            out.append({"kind": TUNE_KINDS.get(e.kind, e.kind), "lt": e.lt, "lx": e.lx, "b": e.b,
+                        "precision": e.precision, "nrhs": e.nrhs, "choice": e.choice,
+                        "candidates_us": {int(e.cand[q]): round(e.us[q], 2) for q in range(e.ncand)}})
+        return out
 
     def close(self):
         if self.h:

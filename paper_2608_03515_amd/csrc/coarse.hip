@@ -358,18 +358,24 @@ static void gs_b(hipStream_t s, const void* A, const void* D, void* x, const voi
                      (const V*)f, Lt, Lx, colour, stride, st);
 }
 
+// rb = right-hand sides per wave of the paired sweep for FP32 8 x 8 blocks (1, 2 or 4; 0 = the
+// default 2; bitwise the same results for every choice), measured at 32 x 32 nodes, 64 rhs: 11.0
+// us per launch with 2 against 14.7 with 1, 11.6 with 4, 19.3 with 8.  FP64 would not fit the
+// registers; other block sizes take one right-hand side per wave.
 template <int B, typename R, typename M, typename V>
 static void gs_pair_b(hipStream_t s, const void* A, const void* D, void* x, const void* f, int Lt, int Lx,
-                      int c0, int nrhs, int64_t stride, const RhsState* st) {
+                      int c0, int nrhs, int64_t stride, const RhsState* st, int rb) {
   const int ncn = (Lt / 4) * (Lx / 4);
   if constexpr (B == 8 && sizeof(R) == 4) {
-    // two right-hand sides per wave (measured at 32 x 32 nodes, 64 rhs: 11.0 us per launch
-    // against 14.7 with one, 11.6 with four, 19.3 with eight); FP64 would not fit the registers
-    constexpr int RB = 2;
-    if (nrhs >= RB) {
-      dim3 g(unsigned((ncn + 3) / 4), unsigned((nrhs + RB - 1) / RB));
-      AMAMG_LAUNCH((k_stencil_gs_pair_mr<RB, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
-                   (const V*)f, Lt, Lx, c0, nrhs, stride, st);
+    if (rb == 0) rb = 2;
+    if (rb > 1 && nrhs >= rb) {
+      const dim3 g(unsigned((ncn + 3) / 4), unsigned((nrhs + rb - 1) / rb));
+      if (rb == 4)
+        AMAMG_LAUNCH((k_stencil_gs_pair_mr<4, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
+                     (const V*)f, Lt, Lx, c0, nrhs, stride, st);
+      else
+        AMAMG_LAUNCH((k_stencil_gs_pair_mr<2, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
+                     (const V*)f, Lt, Lx, c0, nrhs, stride, st);
       return;
     }
   }
@@ -414,8 +420,8 @@ void stencil_gs(hipStream_t s, Real prec, const void* A, const void* Dinv, void*
 }
 
 void stencil_gs_pair(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
-                     int Lt, int Lx, int b, int c0, int nrhs, int64_t stride, const RhsState* st) {
-  AMAMG_B_DISPATCH(gs_pair_b, prec, s, A, Dinv, x, f, Lt, Lx, c0, nrhs, stride, st);
+                     int Lt, int Lx, int b, int c0, int nrhs, int64_t stride, const RhsState* st, int rb) {
+  AMAMG_B_DISPATCH(gs_pair_b, prec, s, A, Dinv, x, f, Lt, Lx, c0, nrhs, stride, st, rb);
 }
 
 void dense_apply(hipStream_t s, Real prec, const double2* Ainv, const void* v, void* y, int n,

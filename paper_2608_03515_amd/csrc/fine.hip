@@ -322,34 +322,43 @@ void wilson_gs(hipStream_t s, LinkStore ls, const void* U0, const void* U1, Real
   else wilson_gs_t<float, bf16c, float2>(s, U0, U1, x, b, nt, nx, m0, colour, nrhs, stride, st);
 }
 
+// Tile widths of the fused smoother (16 rows each): every site's update is the same arithmetic
+// whatever the tile, so the width is a free launch parameter.  FP64 stops at 32 columns for the
+// LDS budget.  tc = 0 takes the default: the widest that fits the lattice.
+template <typename R> constexpr int fused_max_tc() { return sizeof(R) == 4 ? 64 : 32; }
+
 template <int NS, typename R, typename L, typename Vx>
 static void wilson_gs_fused_t(hipStream_t s, const void* U0, const void* U1, const void* xin, void* x,
                               const double2* b, int nt, int nx, double m0, int nrhs, int64_t stride,
-                              const RhsState* st) {
-  // tiles: 16 x 64 sites (16 x 32 in FP64, for the LDS budget), 16 x 16 below 64 columns
-  constexpr int TCW = sizeof(R) == 4 ? 64 : 32;
-  if (nx >= TCW) {
-    dim3 g(unsigned(((nx + TCW - 1) / TCW) * ((nt + 15) / 16)), unsigned(nrhs));
-    AMAMG_LAUNCH((k_wilson_gs_fused<NS, 16, TCW, R, L, Vx>), g, dim3(256), 0, s, (const L*)U0, (const L*)U1,
-                 (const Vx*)xin, (Vx*)x, b, nt, nx, R(1.0 / (m0 + 2.0)), stride, st);
+                              const RhsState* st, int tc) {
+  if (tc == 0) tc = nx >= fused_max_tc<R>() ? fused_max_tc<R>() : 16;
+  if (tc > fused_max_tc<R>() || nx < tc) tc = 16;
+  const R inv = R(1.0 / (m0 + 2.0));
+  dim3 g(unsigned(((nx + tc - 1) / tc) * ((nt + 15) / 16)), unsigned(nrhs));
+  if (tc == 64) {
+    if constexpr (fused_max_tc<R>() >= 64)
+      AMAMG_LAUNCH((k_wilson_gs_fused<NS, 16, 64, R, L, Vx>), g, dim3(256), 0, s, (const L*)U0, (const L*)U1,
+                   (const Vx*)xin, (Vx*)x, b, nt, nx, inv, stride, st);
+  } else if (tc == 32) {
+    AMAMG_LAUNCH((k_wilson_gs_fused<NS, 16, 32, R, L, Vx>), g, dim3(256), 0, s, (const L*)U0, (const L*)U1,
+                 (const Vx*)xin, (Vx*)x, b, nt, nx, inv, stride, st);
   } else {
-    dim3 g(unsigned(((nx + 15) / 16) * ((nt + 15) / 16)), unsigned(nrhs));
     AMAMG_LAUNCH((k_wilson_gs_fused<NS, 16, 16, R, L, Vx>), g, dim3(256), 0, s, (const L*)U0, (const L*)U1,
-                 (const Vx*)xin, (Vx*)x, b, nt, nx, R(1.0 / (m0 + 2.0)), stride, st);
+                 (const Vx*)xin, (Vx*)x, b, nt, nx, inv, stride, st);
   }
 }
 
 void wilson_gs_sweeps(hipStream_t s, LinkStore ls, const void* U0, const void* U1, Real vx, const void* xin,
                       void* x, const double2* b, int nt, int nx, double m0, int sweeps, int nrhs,
-                      int64_t stride, const RhsState* st) {
+                      int64_t stride, const RhsState* st, int tc) {
   if (sweeps == 2) {
-    if (ls == LINK_F64 && vx == F64) wilson_gs_fused_t<2, double, double2, double2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st);
-    else if (ls == LINK_F32) wilson_gs_fused_t<2, float, float2, float2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st);
-    else wilson_gs_fused_t<2, float, bf16c, float2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st);
+    if (ls == LINK_F64 && vx == F64) wilson_gs_fused_t<2, double, double2, double2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st, tc);
+    else if (ls == LINK_F32) wilson_gs_fused_t<2, float, float2, float2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st, tc);
+    else wilson_gs_fused_t<2, float, bf16c, float2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st, tc);
   } else {
-    if (ls == LINK_F64 && vx == F64) wilson_gs_fused_t<1, double, double2, double2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st);
-    else if (ls == LINK_F32) wilson_gs_fused_t<1, float, float2, float2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st);
-    else wilson_gs_fused_t<1, float, bf16c, float2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st);
+    if (ls == LINK_F64 && vx == F64) wilson_gs_fused_t<1, double, double2, double2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st, tc);
+    else if (ls == LINK_F32) wilson_gs_fused_t<1, float, float2, float2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st, tc);
+    else wilson_gs_fused_t<1, float, bf16c, float2>(s, U0, U1, xin, x, b, nt, nx, m0, nrhs, stride, st, tc);
   }
 }
 

@@ -55,10 +55,11 @@ void wilson_gs(hipStream_t s, LinkStore ls, const void* U0, const void* U1, Real
                const RhsState* st);
 // `sweeps` (1 or 2) full red-black sweeps (colour 0 then 1 each) in one launch, starting from xin
 // and writing x (distinct buffers); bitwise equal to the same sequence of wilson_gs colour
-// launches on x = xin
+// launches on x = xin.  tc = tile width in sites (16, 32, 64 FP32; 16, 32 FP64; 0 = default):
+// a launch parameter only, the results do not depend on it
 void wilson_gs_sweeps(hipStream_t s, LinkStore ls, const void* U0, const void* U1, Real vx, const void* xin,
                       void* x, const double2* b, int nt, int nx, double m0, int sweeps, int nrhs,
-                      int64_t stride, const RhsState* st);
+                      int64_t stride, const RhsState* st, int tc = 0);
 // A0 blocks of the fine operator in block-stencil form: [site][5][2][2], offsets
 // (0,0), (+1,0), (-1,0), (0,+1), (0,-1)
 void build_fine_stencil(hipStream_t s, const double2* U0, const double2* U1, int nt, int nx,
@@ -79,9 +80,10 @@ void stencil_apply(hipStream_t s, Real prec, const void* A, const void* x, void*
 void stencil_gs(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
                 int Lt, int Lx, int b, int colour, int nrhs, int64_t stride, const RhsState* st);
 // colours c0 and c0 + 1 (c0 even) of the same sweep in one launch, bitwise equal to two
-// stencil_gs launches
+// stencil_gs launches.  rb = right-hand sides per wave for FP32 8 x 8 blocks (1, 2, 4; 0 =
+// default): a launch parameter only, the results do not depend on it
 void stencil_gs_pair(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
-                     int Lt, int Lx, int b, int c0, int nrhs, int64_t stride, const RhsState* st);
+                     int Lt, int Lx, int b, int c0, int nrhs, int64_t stride, const RhsState* st, int rb = 0);
 // coarsest: y = Ainv v (matrix FP64 always; vectors in prec)
 void dense_apply(hipStream_t s, Real prec, const double2* Ainv, const void* v, void* y, int n,
                  int nrhs, int64_t stride, const RhsState* st);

@@ -639,6 +639,38 @@ amamg_status amamg_residual_history(const amamg_hierarchy* h, int32_t rhs, doubl
   return AMAMG_OK;
 }
 
+amamg_status amamg_context_set_tuning(amamg_context* ctx, int32_t mode, int32_t force) {
+  if (!ctx) return AMAMG_ERR_INVALID_ARG;
+  if (mode < AMAMG_TUNE_AUTO || mode > AMAMG_TUNE_FORCE) return fail(ctx, {AMAMG_ERR_INVALID_ARG, "unknown tuning mode"});
+  std::lock_guard<std::mutex> lk(ctx->tuner.mu);
+  ctx->tuner.mode = mode;
+  ctx->tuner.force = force;
+  return AMAMG_OK;
+}
+
+amamg_status amamg_tuning_entries(amamg_context* ctx, amamg_tune_entry* out, int32_t cap, int32_t* count) {
+  if (!ctx || !count || cap < 0 || (cap > 0 && !out)) return AMAMG_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(ctx->tuner.mu);
+  int32_t i = 0;
+  for (const auto& kv : ctx->tuner.entries) {
+    if (i < cap) {
+      amamg_tune_entry& e = out[i];
+      e = amamg_tune_entry{};
+      e.kind = kv.first[0]; e.lt = kv.first[1]; e.lx = kv.first[2]; e.b = kv.first[3];
+      e.precision = kv.first[4]; e.nrhs = kv.first[5];
+      e.choice = kv.second.choice;
+      e.ncand = int32_t(std::min<size_t>(4, kv.second.cand.size()));
+      for (int q = 0; q < e.ncand; ++q) {
+        e.cand[q] = kv.second.cand[q];
+        e.us[q] = q < int(kv.second.us.size()) ? kv.second.us[q] : 0.0;
+      }
+    }
+    ++i;
+  }
+  *count = i;
+  return AMAMG_OK;
+}
+
 amamg_status amamg_apply_dirac(amamg_gauge* g, int32_t precision, int32_t nrhs, const double* in,
                                double* out) {
   if (!g || !in || !out || nrhs < 1) return g ? fail(g->ctx, {AMAMG_ERR_INVALID_ARG, "bad argument"}) : AMAMG_ERR_INVALID_ARG;

@@ -4,8 +4,11 @@
 // server.hip: continuous-batching server).
 #pragma once
 
+#include <array>
 #include <cmath>
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -96,6 +99,22 @@ struct Pool {
 // Benchmark timer: HIP events around every launch of one kernel family in the solve.  A
 // launch's algorithmic bytes are its per-rhs bytes times the right-hand sides it served,
 // which the host learns at the end of each restart cycle of the batch (group) that ran it.
+// Launch-shape autotuner for kernels whose arithmetic does not depend on the launch shape (the
+// results are bitwise the same for every candidate).  Entries are keyed by what decides the best
+// shape: the tunable, the grid, block size, precision and batch size.
+struct Tuner {
+  enum Kind { FINE_GS_TILE = 0, COARSE_GS_RHS = 1 };
+  struct Entry {
+    int choice = 0;                  // the chosen candidate value
+    std::vector<int> cand;           // candidate values
+    std::vector<double> us;          // their measured times (empty when not timed)
+  };
+  std::mutex mu;
+  int mode = 0;                      // amamg_tune_mode
+  int force = 0;
+  std::map<std::array<int, 6>, Entry> entries;   // {kind, lt, lx, b, precision, nrhs}
+};
+
 struct KernelTimer {
   static constexpr int NF = 8;
   uint32_t mask = 0;
@@ -173,6 +192,7 @@ struct amamg_context {
   bool own_stream = false;
   std::string err;
   amamg::rt::KernelTimer timer;
+  amamg::rt::Tuner tuner;
 };
 
 struct amamg_gauge {
@@ -248,6 +268,10 @@ struct Batch {
   std::vector<int> cycle_in;    // slots in the cycle that was enqueued last
   std::vector<int> pending;     // slots whose admission awaits the input check
   bool cycle_enqueued = false;
+  // launch shapes from the context's tuner: fine smoother tile width, right-hand sides per
+  // wave of each level's paired block smoother (0 = default)
+  int fine_tc = 0;
+  std::vector<int> gs_rb;
 
   void init(amamg_hierarchy* h, Workspace* ws, hipStream_t s, const amamg_solve_params& p,
             const double2* b, double2* x, int group);

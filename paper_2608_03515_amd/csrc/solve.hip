@@ -175,6 +175,8 @@ struct SolveCtx {
   int nrhs;        // slots (grid extent of every launch)
   int step;        // Arnoldi step of the current V-cycle (kernel timer)
   int group;       // kernel-timer group
+  int fine_tc;     // launch shapes chosen by the tuner (0 = default)
+  const int* gs_rb;
 };
 
 // x = M_k f (V-cycle of the paper's two-level scheme, recursively; start x = 0)
@@ -245,7 +247,7 @@ static void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x)
     const int rec = timer_start(ctx, c.s, AMAMG_KT_FINE_GS, c.step, c.group,
                                 double(g.nnode()) * (2 * 2 * cb + 2 * cl + 32));
     wilson_gs_sweeps(c.s, c.smooth_links, U0, U1, c.T, WL.tmp, x, (const double2*)f, g.Lt, g.Lx, h->m0, post,
-                     c.nrhs, nd, st);
+                     c.nrhs, nd, st, c.fine_tc);
     timer_stop(ctx, c.s, rec);
     return;
   }
@@ -265,7 +267,7 @@ static void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x)
         const int rec = k == 1 ? timer_start(ctx, c.s, AMAMG_KT_COARSE_GS, c.step, c.group,
                                              2.0 * (ncn * 25.0 * g.b * g.b * cb + 2.0 * ncn * g.b * cb) + double(nd) * cb)
                                : -1;
-        stencil_gs_pair(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, col, c.nrhs, nd, st);
+        stencil_gs_pair(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, col, c.nrhs, nd, st, c.gs_rb ? c.gs_rb[k] : 0);
         timer_stop(ctx, c.s, rec);
       }
     }
@@ -284,7 +286,7 @@ static void check_solve_params(const amamg_solve_params& p) {
 
 static SolveCtx make_ctx(const Batch& bt) {
   SolveCtx c{bt.h, bt.ws, bt.s, bt.p.precision == AMAMG_FP64 ? F64 : F32, LINK_F64, LINK_F64,
-             bt.ws->cap, 0, bt.group};
+             bt.ws->cap, 0, bt.group, bt.fine_tc, bt.gs_rb.empty() ? nullptr : bt.gs_rb.data()};
   if (bt.p.precision == AMAMG_MIXED_FP32) { c.smooth_links = LINK_F32; c.mat_links = LINK_F32; }
   if (bt.p.precision == AMAMG_MIXED_FP32_BF16LINKS) { c.smooth_links = LINK_BF16; c.mat_links = LINK_F32; }
   return c;
@@ -293,6 +295,94 @@ static SolveCtx make_ctx(const Batch& bt) {
 static KrylovDims dims(const Batch& bt) {
   const int64_t n = bt.h->lv[0].g.ndof();
   return KrylovDims{n, bt.ws->cap, krylov_blocks(n, bt.ws->cap), bt.p.restart};
+}
+
+// ------------------------------------------------------------------------------ autotuning
+
+// Mean time in microseconds of `run` on stream s (one untimed run, then three timed).
+template <typename F> static double time_us(hipStream_t s, F run) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  run();
+  HIPCHECK(hipEventRecord(e0, s));
+  for (int q = 0; q < 3; ++q) run();
+  HIPCHECK(hipEventRecord(e1, s));
+  HIPCHECK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return double(ms) * 1000.0 / 3.0;
+}
+
+// The tuned value for `key`: cached, or (mode AUTO) the fastest candidate by `measure`, or
+// (mode FORCE) candidate `force`, or (mode OFF) 0 = the kernel's default.
+template <typename F>
+static int tuned(Tuner& t, const std::array<int, 6>& key, const std::vector<int>& cand, F measure) {
+  std::lock_guard<std::mutex> lk(t.mu);
+  if (t.mode == AMAMG_TUNE_OFF) return 0;
+  if (t.mode == AMAMG_TUNE_FORCE) return cand[std::min<size_t>(std::max(t.force, 0), cand.size() - 1)];
+  auto it = t.entries.find(key);
+  if (it != t.entries.end()) return it->second.choice;
+  Tuner::Entry e;
+  e.cand = cand;
+  for (int v : cand) e.us.push_back(measure(v));
+  e.choice = cand[std::min_element(e.us.begin(), e.us.end()) - e.us.begin()];
+  t.entries[key] = e;
+  return e.choice;
+}
+
+// Launch shapes of this batch's smoothers.  Runs before any right-hand side is admitted: the
+// candidates are timed on the workspace's own vectors, zeroed, which hold nothing yet.
+static void tune_batch(Batch& bt) {
+  amamg_hierarchy* h = bt.h;
+  Workspace* ws = bt.ws;
+  amamg_context* ctx = h->gauge->ctx;
+  const SolveCtx c = make_ctx(bt);
+  const int prec = int(bt.p.precision), cap = ws->cap;
+  const size_t rs = c.T == F64 ? sizeof(double2) : sizeof(float2);
+  bt.fine_tc = 0;
+  bt.gs_rb.assign(h->lv.size(), 0);
+  amamg_gauge* gg = h->gauge;
+  const Geom& g0 = h->lv[0].g;
+  if (h->lv.size() > 1 && h->prm.pre_sweeps == 0 && (h->prm.post_sweeps == 1 || h->prm.post_sweeps == 2)) {
+    std::vector<int> cand = {16};
+    if (g0.Lx >= 32) cand.push_back(32);
+    if (g0.Lx >= 64 && c.T == F32) cand.push_back(64);
+    const int64_t nd = g0.ndof();
+    void* xin = ws->lv[0].tmp;
+    void* xo = ws->Z;
+    const double2* b = ws->V;
+    bt.fine_tc = tuned(ctx->tuner, {Tuner::FINE_GS_TILE, g0.Lt, g0.Lx, g0.b, prec, cap}, cand, [&](int tc) {
+      HIPCHECK(hipMemsetAsync(xin, 0, rs * cap * nd, bt.s));
+      HIPCHECK(hipMemsetAsync(xo, 0, rs * cap * nd, bt.s));
+      HIPCHECK(hipMemsetAsync(ws->V, 0, sizeof(double2) * cap * nd, bt.s));
+      return time_us(bt.s, [&] {
+        wilson_gs_sweeps(bt.s, c.smooth_links, link0(gg, c.smooth_links), link1(gg, c.smooth_links), c.T, xin, xo,
+                         b, g0.Lt, g0.Lx, h->m0, h->prm.post_sweeps, cap, nd, nullptr, tc);
+      });
+    });
+  }
+  for (size_t k = 1; k + 1 < h->lv.size(); ++k) {
+    const Geom& g = h->lv[k].g;
+    if (!(g.b == 8 && c.T == F32 && cap >= 2)) continue;
+    std::vector<int> cand = {1, 2};
+    if (cap >= 4) cand.push_back(4);
+    const int64_t nd = g.ndof();
+    Workspace::Lev& WL = ws->lv[k];
+    const void* Ak = h->lv[k].A32;
+    const void* Dk = h->lv[k].Dinv32;
+    bt.gs_rb[k] = tuned(ctx->tuner, {Tuner::COARSE_GS_RHS, g.Lt, g.Lx, g.b, prec, cap}, cand, [&](int rb) {
+      HIPCHECK(hipMemsetAsync(WL.x, 0, rs * cap * nd, bt.s));
+      HIPCHECK(hipMemsetAsync(WL.f, 0, rs * cap * nd, bt.s));
+      return time_us(bt.s, [&] {
+        for (int col = 0; col < 16; col += 2)
+          stencil_gs_pair(bt.s, F32, Ak, Dk, WL.x, WL.f, g.Lt, g.Lx, g.b, col, cap, nd, nullptr, rb);
+      });
+    });
+  }
+  check_launch();
 }
 
 void Batch::init(amamg_hierarchy* h_, Workspace* ws_, hipStream_t s_, const amamg_solve_params& p_,
@@ -311,6 +401,7 @@ void Batch::init(amamg_hierarchy* h_, Workspace* ws_, hipStream_t s_, const amam
     HIPCHECK(hipEventRecord(ws->ev, h->gauge->ctx->stream));
     HIPCHECK(hipStreamWaitEvent(s, ws->ev, 0));
   }
+  tune_batch(*this);
 }
 
 void Batch::admit_begin(const std::vector<int>& slots) {

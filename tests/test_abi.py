@@ -74,7 +74,7 @@ def test_struct_layouts_match_header():
     pairs = [("amamg_setup_params", amamg.SetupParams), ("amamg_solve_params", amamg.SolveParams),
              ("amamg_solve_info", amamg.SolveInfo)]
     pairs += [("amamg_server_params", amamg.ServerParams), ("amamg_request_info", amamg.RequestInfo),
-              ("amamg_server_counters", amamg.ServerCounters)]
+              ("amamg_server_counters", amamg.ServerCounters), ("amamg_tune_entry", amamg.TuneEntry)]
     c = _c_layouts([(cname, [f[0] for f in cls._fields_]) for cname, cls in pairs])
     for cname, cls in pairs:
         want = [ctypes.sizeof(cls)] + [getattr(cls, f[0]).offset for f in cls._fields_]

@@ -488,3 +488,35 @@ def test_c4_mixed_batch_within_bound(lib, ctx):
         assert i32[r].converged and i32[r].true_rel_residual <= 1e-10
         assert rel(synth.field_from_abi(x32)[r], synth.field_from_abi(x64)[r]) <= 1e-9
         assert abs(i32[r].iterations - i64[r].iterations) <= max(5, i64[r].iterations // 10)
+
+
+def test_tuned_launch_shapes_do_not_change_results(lib):
+    """The autotuner's launch shapes (fine smoother tile width 16/32/64, block-smoother right-hand
+    sides per wave 1/2/4 on the 128^2 workload's level 1) give bitwise the same mixed solve of 20
+    right-hand sides, forced one by one and chosen by timing; the timed entries are recorded."""
+    w = synth.WORKLOADS["C4"]
+    m0 = synth.critical_masses()["C4"] + w.gaps[0]
+    psi = synth.field_to_abi(synth.gaussian_rhs(w.L, w.L, 5151, nrhs=20))
+    ctx = lib.Context(0)                 # its own context: the tuner state is per context
+    g = make_gauge(lib, ctx, w.links(), m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=8, overlap=2, n_test_vectors=8))
+    sp = lib.default_solve_params(precision=lib.MIXED_FP32)
+    runs = []
+    for mode, force in ((lib.TUNE_FORCE, 0), (lib.TUNE_FORCE, 1), (lib.TUNE_FORCE, 2), (lib.TUNE_AUTO, 0)):
+        say("tuning", mode, force)
+        ctx.set_tuning(mode, force)
+        x, infos, st = h.solve(psi, sp)
+        assert st == lib.OK
+        runs.append((x, [i.iterations for i in infos]))
+    entries = ctx.tuning_entries()
+    h.close()
+    g.close()
+    ctx.close()
+    for x, its in runs[1:]:
+        assert its == runs[0][1] and np.array_equal(x, runs[0][0])
+    kinds = {e["kind"]: e for e in entries}
+    assert set(kinds) == {"fine_smoother_tile", "block_smoother_rhs_per_wave"}
+    assert set(kinds["fine_smoother_tile"]["candidates_us"]) == {16, 32, 64}
+    assert set(kinds["block_smoother_rhs_per_wave"]["candidates_us"]) == {1, 2, 4}
+    for e in entries:
+        assert e["choice"] in e["candidates_us"] and all(t > 0 for t in e["candidates_us"].values())
