@@ -314,28 +314,58 @@ __global__ __launch_bounds__(256) void k_stencil_gs_pair_mr(const M* __restrict_
   }
 }
 
-// y = Ainv v for the coarsest level (matrix FP64): 64 lanes per row, 4 rows per block.
+// y = Ainv v for the coarsest level on FP64 matrix cores: a dense complex product of the
+// inverse with the right-hand sides, D[rhs][row] = sum_k v_rhs[k] Ainv[row][k], as real
+// v_mfma_f64_16x16x4f64 tiles (lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+// D[4 i + l / 16][l % 16], i < 4).  A workgroup owns 16 right-hand sides x 16 rows; its four
+// waves take a quarter of k each (a multiple of 4; padding contributes zeros) and the quarters
+// are added in order through LDS.  The inverse is read once per 16 right-hand sides.  A single
+// right-hand side pads its tile (about 3 % slower there than a vector kernel), which keeps each
+// right-hand side's arithmetic the same in every batch.
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+__device__ inline mfma_d4 mfma_f64(double a, double b, mfma_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 template <typename Vin, typename Vout>
-__global__ __launch_bounds__(256) void k_dense_apply(const double2* __restrict__ Ainv,
-                                                     const Vin* __restrict__ v,
-                                                     Vout* __restrict__ y, int n,
-                                                     int64_t stride,
-                                                     const RhsState* __restrict__ st) {
-  const int r = blockIdx.y;
-  if (st && !st[r].active) return;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  double re = 0, im = 0;
-  if (row < n) {
-    const double2* Ar = Ainv + int64_t(row) * n;
-    const Vin* vr = v + r * stride;
-    double2 acc = make_double2(0, 0);
-    for (int j = lane; j < n; j += 64) acc = cfma(Ar[j], cconv<double2>(vr[j]), acc);
-    re = acc.x; im = acc.y;
+__global__ __launch_bounds__(256) void k_dense_apply_mfma(const double2* __restrict__ Ainv,
+                                                          const Vin* __restrict__ v, Vout* __restrict__ y,
+                                                          int n, int nrhs, int64_t stride,
+                                                          const RhsState* __restrict__ st) {
+  __shared__ double2 red[4][256];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+  const int row0 = blockIdx.x * 16, r0 = blockIdx.y * 16;
+  const int ra = r0 + lr;                                  // right-hand side of this lane's A values
+  const bool alive = ra < nrhs && (!st || st[ra].active);
+  const int rb = row0 + lr;                                // row of this lane's B values
+  const bool blive = rb < n;
+  const int kq = (((n + 3) / 4 + 3) / 4) * 4;              // k per wave
+  const int k0 = wv * kq, k1 = min(n, k0 + kq);
+  const Vin* va = v + int64_t(alive ? ra : 0) * stride;
+  const double2* Ab = Ainv + int64_t(blive ? rb : 0) * n;
+  mfma_d4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+#pragma unroll 4
+  for (int kk = k0; kk < k1; kk += 4) {
+    const int k = kk + lk;
+    const bool kin = k < k1;
+    const double2 a = (alive && kin) ? cconv<double2>(va[k]) : make_double2(0, 0);
+    const double2 b = (blive && kin) ? Ab[k] : make_double2(0, 0);
+    re = mfma_f64(a.x, b.x, re);
+    re = mfma_f64(-a.y, b.y, re);
+    im = mfma_f64(a.x, b.y, im);
+    im = mfma_f64(a.y, b.x, im);
   }
-  re = wave_sum(re);
-  im = wave_sum(im);
-  if (row < n && lane == 0) y[r * stride + row] = cconv<Vout>(make_double2(re, im));
+#pragma unroll
+  for (int i = 0; i < 4; ++i) red[wv][i * 64 + lane] = make_double2(re[i], im[i]);
+  __syncthreads();
+  if (wv != 0) return;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double2 acc = red[0][i * 64 + lane];
+    for (int q = 1; q < 4; ++q) acc = cadd(acc, red[q][i * 64 + lane]);
+    const int r = r0 + 4 * i + lk, row = row0 + lr;
+    if (r < nrhs && row < n && (!st || st[r].active)) y[r * stride + row] = cconv<Vout>(acc);
+  }
 }
 
 // ------------------------------------------------------------------------------ launchers
@@ -426,13 +456,14 @@ void stencil_gs_pair(hipStream_t s, Real prec, const void* A, const void* Dinv, 
 
 void dense_apply(hipStream_t s, Real prec, const double2* Ainv, const void* v, void* y, int n,
                  int nrhs, int64_t stride, const RhsState* st) {
-  dim3 g(unsigned((n + 3) / 4), unsigned(nrhs));
+  // one kernel for every batch size: a right-hand side's result must not depend on the batch
+  const dim3 g(unsigned((n + 15) / 16), unsigned((nrhs + 15) / 16));
   if (prec == F64)
-    hipLaunchKernelGGL((k_dense_apply<double2, double2>), g, dim3(256), 0, s, Ainv,
-                       (const double2*)v, (double2*)y, n, stride, st);
+    hipLaunchKernelGGL((k_dense_apply_mfma<double2, double2>), g, dim3(256), 0, s, Ainv,
+                       (const double2*)v, (double2*)y, n, nrhs, stride, st);
   else
-    hipLaunchKernelGGL((k_dense_apply<float2, float2>), g, dim3(256), 0, s, Ainv,
-                       (const float2*)v, (float2*)y, n, stride, st);
+    hipLaunchKernelGGL((k_dense_apply_mfma<float2, float2>), g, dim3(256), 0, s, Ainv,
+                       (const float2*)v, (float2*)y, n, nrhs, stride, st);
 }
 
 }  // namespace amamg
