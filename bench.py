@@ -387,6 +387,47 @@ def pmc_summary(fetch_csv, write_csv, out_md, command, timer_json):
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
+MFMA_KERNELS = ("k_restrict_mfma", "k_prolong_mfma", "k_dense_apply_mfma")
+MFMA_PEAK_TFLOPS = {"F32": 157.3, "F64": 78.6}
+SIMD_NUM = 1024
+
+
+def mfma_summary(pmc_csv, stats_csv, out_md, command, trace_command):
+    """Matrix-core use of the MFMA kernels: one rocprofv3 --pmc pass (SQ_VALU_MFMA_BUSY_CYCLES,
+    SQ_INSTS_VALU_MFMA_MOPS_F32/F64, GRBM_GUI_ACTIVE) and the kernel trace's mean durations.
+    Utilisation = busy cycles / (active cycles x SIMDs), the vendor's MfmaUtil; flops = MOPS x 512."""
+    import csv
+    from collections import defaultdict
+    per = defaultdict(lambda: defaultdict(list))
+    with open(pmc_csv) as f:
+        for row in csv.DictReader(f):
+            name = row["Kernel_Name"]
+            for k in MFMA_KERNELS:
+                if k in name:
+                    per[name][row["Counter_Name"]].append(float(row["Counter_Value"]))
+    dur = {r["Name"]: float(r["AverageNs"]) for r in csv.DictReader(open(stats_csv))}
+    lines = [f"# Matrix-core use, {os.path.basename(out_md)[:-3]}", "",
+             "Counter pass and kernel trace, from the repository root:", "", f"    {command}",
+             f"    {trace_command}", "",
+             "| kernel | dispatches | MFMA util % (mean) | GFLOP / dispatch | mean us (trace) | TFLOP/s | peak | % of peak |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for name, c in sorted(per.items()):
+        n = len(c.get("GRBM_GUI_ACTIVE", []))
+        if not n:
+            continue
+        util = [100.0 * b / (a * SIMD_NUM) for b, a in zip(c["SQ_VALU_MFMA_BUSY_CYCLES"], c["GRBM_GUI_ACTIVE"]) if a > 0]
+        f32 = sum(c.get("SQ_INSTS_VALU_MFMA_MOPS_F32", [0])) * 512 / n
+        f64 = sum(c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", [0])) * 512 / n
+        kind = "F64" if f64 > f32 else "F32"
+        flops = max(f32, f64)
+        us = next((v / 1e3 for k, v in dur.items() if k.split("(")[0] == name.split("(")[0]), float("nan"))
+        tf = flops / (us * 1e-6) / 1e12 if us == us and us > 0 else float("nan")
+        short = name.split("(")[0].replace("|", "/")[:80]
+        lines.append(f"| `{short}` | {n} | {sum(util) / max(1, len(util)):.1f} | {flops / 1e9:.3f} | {us:.2f} | "
+                     f"{tf:.1f} | {MFMA_PEAK_TFLOPS[kind]} ({kind}) | {100 * tf / MFMA_PEAK_TFLOPS[kind]:.1f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
 def committed_traffic(family):
     """Per-launch HBM bytes of `family` from the committed counter summary, or None when the
     summary is missing, covers another family, or the kernel source changed since."""
@@ -426,6 +467,7 @@ def main():
     ap.add_argument("--no-stencil", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="skip the single-rhs FP64 path")
     ap.add_argument("--trace-summary", nargs=3, metavar=("STATS_CSV", "OUT_MD", "COMMAND"))
+    ap.add_argument("--mfma-summary", nargs=5, metavar=("PMC_CSV", "STATS_CSV", "OUT_MD", "COMMAND", "TRACE_COMMAND"))
     ap.add_argument("--pmc-summary", nargs=5,
                     metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD", "COMMAND", "TIMER_JSON"))
     ap.add_argument("--profile-mixed", action="store_true",
@@ -435,6 +477,9 @@ def main():
     args = ap.parse_args()
     if args.trace_summary:
         trace_summary(*args.trace_summary)
+        return
+    if args.mfma_summary:
+        mfma_summary(*args.mfma_summary)
         return
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)

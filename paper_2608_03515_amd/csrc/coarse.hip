@@ -348,8 +348,11 @@ __global__ __launch_bounds__(256) void k_dense_apply_mfma(const double2* __restr
   for (int kk = k0; kk < k1; kk += 4) {
     const int k = kk + lk;
     const bool kin = k < k1;
-    const double2 a = (alive && kin) ? cconv<double2>(va[k]) : make_double2(0, 0);
-    const double2 b = (blive && kin) ? Ab[k] : make_double2(0, 0);
+    // unconditional loads from valid addresses, then selects: no branch separates the loads
+    const Vin av = va[kin ? k : k0];
+    const double2 bv = Ab[kin ? k : k0];
+    const double2 a = alive && kin ? cconv<double2>(av) : make_double2(0, 0);
+    const double2 b = blive && kin ? bv : make_double2(0, 0);
     re = mfma_f64(a.x, b.x, re);
     re = mfma_f64(-a.y, b.y, re);
     im = mfma_f64(a.x, b.y, im);

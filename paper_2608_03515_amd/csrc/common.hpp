@@ -92,6 +92,30 @@ template <typename T> __device__ inline T wave_sum(T v) {
   return v;
 }
 
+// Global-to-LDS staging with U loads in flight per thread.  For every index q < total (thread
+// t takes q = t, t + NT, ...), fetch(q) is issued for U indices before store(q, value) runs for
+// them.  A plain loop of load-then-store lets each load wait for the previous iteration's LDS
+// store (the next address often comes from LDS too), one memory round trip per element; here one
+// round trip covers U elements.  fetch must only load (no arithmetic on the loaded value, which
+// would wait for it) and runs unconditionally, for indices past the end clamped to total - 1, so
+// that no branch separates the loads; the stores are guarded.  Call with all NT threads.
+template <int U, int NT, typename T, typename Fetch, typename Store>
+__device__ inline void stage(int total, Fetch fetch, Store store) {
+  for (int q0 = int(threadIdx.x); q0 < total; q0 += NT * U) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + NT * u;
+      v[u] = fetch(q < total ? q : total - 1);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + NT * u;
+      if (q < total) store(q, v[u]);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ device structures
 
 // Per right-hand-side FGMRES state (device resident).

@@ -177,17 +177,21 @@ __global__ __launch_bounds__(256) void k_wilson_gs_fused(const L* __restrict__ U
   const int t0 = ty * TR - HW, x0 = tx * TC - HW;   // region origin (global, may be negative)
   const Spinor<Vx>* xr = reinterpret_cast<const Spinor<Vx>*>(xin + r * stride);
   Spinor<Vx>* xw = reinterpret_cast<Spinor<Vx>*>(xout + r * stride);
-  for (int e = threadIdx.x; e < RH * RW; e += 256) {
+  // staging with several loads in flight per thread (see stage())
+  stage<4, 256, Spinor<Vx>>(RH * RW, [&](int e) {
     const int rw = e / RW, c = e - rw * RW;
     const int tt = ((t0 + rw) % nt + nt) % nt, xx = ((x0 + c) % nx + nx) % nx;
-    xs[e] = sconv<C>(xr[int64_t(tt) * nx + xx]);
-  }
-  for (int e = threadIdx.x; e < BH * BW; e += 256) {
-    const int rw = e / BW, c = e - rw * BW;
-    const int tt = ((t0 + 1 + rw) % nt + nt) % nt, xx = ((x0 + 1 + c) % nx + nx) % nx;
-    Spinor<C> f{czero<R>(), czero<R>()};
-    if (b) f = sconv<C>(reinterpret_cast<const Spinor<double2>*>(b + r * stride)[int64_t(tt) * nx + xx]);
-    bs[e] = f;
+    return xr[int64_t(tt) * nx + xx];
+  }, [&](int e, Spinor<Vx> v) { xs[e] = sconv<C>(v); });
+  if (b) {
+    const Spinor<double2>* br = reinterpret_cast<const Spinor<double2>*>(b + r * stride);
+    stage<4, 256, Spinor<double2>>(BH * BW, [&](int e) {
+      const int rw = e / BW, c = e - rw * BW;
+      const int tt = ((t0 + 1 + rw) % nt + nt) % nt, xx = ((x0 + 1 + c) % nx + nx) % nx;
+      return br[int64_t(tt) * nx + xx];
+    }, [&](int e, Spinor<double2> v) { bs[e] = sconv<C>(v); });
+  } else {
+    for (int e = threadIdx.x; e < BH * BW; e += 256) bs[e] = Spinor<C>{czero<R>(), czero<R>()};
   }
   __syncthreads();
   for (int hs = 0; hs < 2 * NS; ++hs) {

@@ -190,23 +190,30 @@ __global__ __launch_bounds__(256) void k_restrict_partial_tiled(
   __shared__ C Pl[RCH * NCOL];
   __shared__ C Rl[NR * RS];             // row stride RCH + 1 against bank conflicts
   __shared__ int ri[RCH];
+  __shared__ int live[NR];
   const int bid = xcd_block(blockIdx.x, gridDim.x);
   const int w = bid / nchunk, chunk = bid - (bid / nchunk) * nchunk;
   const int r0 = chunk * RCH, cnt = max(0, min(nrows[w] - r0, RCH));
   for (int k = threadIdx.x; k < cnt; k += 256) ri[k] = rows[int64_t(w) * maxrows + r0 + k];
   __syncthreads();
-  for (int q = threadIdx.x; q < cnt * NCOL; q += 256)
-    Pl[q] = cconv<C>(P[int64_t(ri[q / NCOL]) * NCOL + q % NCOL]);
+  stage<8, 256, M>(cnt * NCOL, [&](int q) { return P[int64_t(ri[q / NCOL]) * NCOL + q % NCOL]; },
+                   [&](int q, M v) { Pl[q] = cconv<C>(v); });
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int col = lane % NCOL, sub = lane / NCOL;
   for (int g0 = 0; g0 < nrhs; g0 += NR) {
     const int ng = min(NR, nrhs - g0);
     __syncthreads();
-    for (int q = threadIdx.x; q < NR * cnt; q += 256) {
+    for (int rr = threadIdx.x; rr < NR; rr += 256) live[rr] = rr < ng && (!st || st[g0 + rr].active);
+    __syncthreads();
+    // the fetch only loads (from a clamped address); conversion and masking happen at the store,
+    // so that the loads of a batch stay in flight together
+    stage<8, 256, Vin>(NR * cnt, [&](int q) {
       const int rr = q / cnt, k = q - rr * cnt;
-      const bool live = rr < ng && (!st || st[g0 + rr].active);
-      Rl[rr * RS + k] = live ? cconv<C>(rin[(g0 + rr) * stride_f + ri[k]]) : czero<R>();
-    }
+      return rin[(g0 + (live[rr] ? rr : 0)) * stride_f + ri[k]];
+    }, [&](int q, Vin v) {
+      const int rr = q / cnt, k = q - rr * cnt;
+      Rl[rr * RS + k] = live[rr] ? cconv<C>(v) : czero<R>();
+    });
     __syncthreads();
     C acc[RB];
 #pragma unroll
@@ -247,8 +254,8 @@ __global__ __launch_bounds__(256) void k_prolong_tiled(
   const int nv_rows = chunk == 0 ? g.o * g.o * g.b : 0;
   for (int k = threadIdx.x; k < cnt; k += 256) ri[k] = rows[int64_t(w) * maxrows + r0 + k];
   __syncthreads();
-  for (int q = threadIdx.x; q < cnt * NCOL; q += 256)
-    Pl[(q / NCOL) * PS + q % NCOL] = cconv<C>(P[int64_t(ri[q / NCOL]) * NCOL + q % NCOL]);
+  stage<8, 256, M>(cnt * NCOL, [&](int q) { return P[int64_t(ri[q / NCOL]) * NCOL + q % NCOL]; },
+                   [&](int q, M v) { Pl[(q / NCOL) * PS + q % NCOL] = cconv<C>(v); });
   __syncthreads();
   const int k = threadIdx.x % RCH, h = threadIdx.x / RCH;
   C pr[NCOL];
@@ -261,11 +268,11 @@ __global__ __launch_bounds__(256) void k_prolong_tiled(
   for (int g0 = 0; g0 < nrhs; g0 += NR) {
     const int ng = min(NR, nrhs - g0);
     __syncthreads();
-    for (int q = threadIdx.x; q < NR * NCOL; q += 256) {
+    stage<8, 256, Vin>(NR * NCOL, [&](int q) {
       const int rr = q / NCOL, col = q % NCOL;
       const int c = col / g.bc, j = col - (col / g.bc) * g.bc;
-      El[q] = rr < ng ? cconv<C>(e[(g0 + rr) * stride_c + int64_t(cn[c]) * g.bc + j]) : czero<R>();
-    }
+      return e[(g0 + (rr < ng ? rr : 0)) * stride_c + int64_t(cn[c]) * g.bc + j];
+    }, [&](int q, Vin v) { El[q] = q / NCOL < ng ? cconv<C>(v) : czero<R>(); });
     __syncthreads();
     if (k < cnt)
       for (int rr = h; rr < ng; rr += H) {
@@ -327,17 +334,22 @@ __global__ __launch_bounds__(256) void k_restrict_mfma(
   const int w = bid / nchunk, chunk = bid - (bid / nchunk) * nchunk;
   const int g0 = blockIdx.y * kMfmaRhs, ng = min(kMfmaRhs, nrhs - g0);
   const int r0 = chunk * RCH, cnt = max(0, min(nrows[w] - r0, RCH));
+  __shared__ int live[kMfmaRhs];
   for (int k = threadIdx.x; k < RCH; k += 256) ri[k] = k < cnt ? rows[int64_t(w) * maxrows + r0 + k] : 0;
+  for (int rr = threadIdx.x; rr < kMfmaRhs; rr += 256) live[rr] = rr < ng && (!st || st[g0 + rr].active);
   __syncthreads();
-  for (int q = threadIdx.x; q < RCH * NCOL; q += 256) {
-    const int k = q / NCOL, c = q - (q / NCOL) * NCOL;
-    Pl[k * PS + c] = k < cnt ? P[int64_t(ri[k]) * NCOL + c] : make_float2(0.f, 0.f);
-  }
-  for (int q = threadIdx.x; q < kMfmaRhs * RCH; q += 256) {
+  // the fetches only load, from valid addresses (ri[k] = 0 past the chunk's rows, rhs 0 of the
+  // group for dead ones); conversion and masking happen at the store, so that the loads of a
+  // batch stay in flight together
+  stage<8, 256, float2>(RCH * NCOL, [&](int q) { return P[int64_t(ri[q / NCOL]) * NCOL + q % NCOL]; },
+                        [&](int q, float2 v) { Pl[(q / NCOL) * PS + q % NCOL] = q / NCOL < cnt ? v : make_float2(0.f, 0.f); });
+  stage<8, 256, Vin>(kMfmaRhs * RCH, [&](int q) {
     const int rr = q / RCH, k = q - (q / RCH) * RCH;
-    const bool live = rr < ng && k < cnt && (!st || st[g0 + rr].active);
-    Rl[rr * RS + k] = live ? cconv<float2>(rin[(g0 + rr) * stride_f + ri[k]]) : make_float2(0.f, 0.f);
-  }
+    return rin[(g0 + (live[rr] ? rr : 0)) * stride_f + ri[k]];
+  }, [&](int q, Vin v) {
+    const int rr = q / RCH, k = q - (q / RCH) * RCH;
+    Rl[rr * RS + k] = live[rr] && k < cnt ? cconv<float2>(v) : make_float2(0.f, 0.f);
+  });
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
   mfma_f4 re[CT], im[CT];
@@ -386,18 +398,16 @@ __global__ __launch_bounds__(256) void k_prolong_mfma(
   const int nv_rows = chunk == 0 ? g.o * g.o * g.b : 0;
   for (int k = threadIdx.x; k < RCH; k += 256) ri[k] = k < cnt ? rows[int64_t(w) * maxrows + r0 + k] : 0;
   __syncthreads();
-  for (int q = threadIdx.x; q < RCH * NCOL; q += 256) {
-    const int k = q / NCOL, c = q - (q / NCOL) * NCOL;
-    Pl[k * PS + c] = k < cnt ? P[int64_t(ri[k]) * NCOL + c] : make_float2(0.f, 0.f);
-  }
+  stage<8, 256, float2>(RCH * NCOL, [&](int q) { return P[int64_t(ri[q / NCOL]) * NCOL + q % NCOL]; },
+                        [&](int q, float2 v) { Pl[(q / NCOL) * PS + q % NCOL] = q / NCOL < cnt ? v : make_float2(0.f, 0.f); });
   int cn[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) cn[c] = ((I + (c >> 1)) % g.nI) * g.nJ + (J + (c & 1)) % g.nJ;
-  for (int q = threadIdx.x; q < kMfmaRhs * NCOL; q += 256) {
+  stage<8, 256, float2>(kMfmaRhs * NCOL, [&](int q) {
     const int rr = q / NCOL, col = q - (q / NCOL) * NCOL;
     const int c = col / g.bc, j = col - (col / g.bc) * g.bc;
-    El[rr * ES + col] = rr < ng ? e[(g0 + rr) * stride_c + int64_t(cn[c]) * g.bc + j] : make_float2(0.f, 0.f);
-  }
+    return e[(g0 + (rr < ng ? rr : 0)) * stride_c + int64_t(cn[c]) * g.bc + j];
+  }, [&](int q, float2 v) { El[(q / NCOL) * ES + q % NCOL] = q / NCOL < ng ? v : make_float2(0.f, 0.f); });
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
   mfma_f4 re[RT], im[RT];
