@@ -72,19 +72,17 @@ __global__ __launch_bounds__(256) void k_restrict_partial(const M* __restrict__ 
   const int r0 = chunk * ts.rch, cnt = max(0, min(nr - r0, ts.rch));
   for (int k = threadIdx.x; k < cnt; k += 256) ri[k] = rows[int64_t(w) * maxrows + r0 + k];
   __syncthreads();
-  for (int e = threadIdx.x; e < cnt * ncol; e += 256) {
-    const int k = e / ncol, col = e - (e / ncol) * ncol;
-    Pl[k * pld + col] = cconv<C>(P[int64_t(ri[k]) * ncol + col]);
-  }
+  stage<8, 256, M>(cnt * ncol, [&](int e) { return P[int64_t(ri[e / ncol]) * ncol + e % ncol]; },
+                   [&](int e, M v) { Pl[(e / ncol) * pld + e % ncol] = cconv<C>(v); });
   const int nW = g.nI * g.nJ;
   for (int g0 = 0; g0 < nrhs; g0 += ts.rg) {
     const int ng = min(ts.rg, nrhs - g0);
     __syncthreads();
-    for (int e = threadIdx.x; e < ng * cnt; e += 256) {
-      const int rr = e / cnt, k = e - (e / cnt) * cnt;
-      const bool live = !st || st[g0 + rr].active;
-      Rl[rr * ts.rch + k] = live ? cconv<C>(rin[(g0 + rr) * stride_f + ri[k]]) : czero<R>();
-    }
+    stage<8, 256, Vin>(ng * cnt, [&](int e) { return rin[(g0 + e / cnt) * stride_f + ri[e % cnt]]; },
+                       [&](int e, Vin v) {
+                         const int rr = e / cnt;
+                         Rl[rr * ts.rch + e % cnt] = !st || st[g0 + rr].active ? cconv<C>(v) : czero<R>();
+                       });
     __syncthreads();
     for (int q = threadIdx.x; q < ng * ncol; q += 256) {
       const int rr = q / ncol, col = q - (q / ncol) * ncol;
@@ -121,10 +119,8 @@ __global__ __launch_bounds__(256) void k_prolong(const M* __restrict__ P,
   const int nv_rows = chunk == 0 ? g.o * g.o * g.b : 0;     // vertex rows of node (I, J)
   for (int k = threadIdx.x; k < cnt; k += 256) ri[k] = rows[int64_t(w) * maxrows + r0 + k];
   __syncthreads();
-  for (int q = threadIdx.x; q < cnt * ncol; q += 256) {
-    const int k = q / ncol, col = q - (q / ncol) * ncol;
-    Pl[k * pld + col] = cconv<C>(P[int64_t(ri[k]) * ncol + col]);
-  }
+  stage<8, 256, M>(cnt * ncol, [&](int q) { return P[int64_t(ri[q / ncol]) * ncol + q % ncol]; },
+                   [&](int q, M v) { Pl[(q / ncol) * pld + q % ncol] = cconv<C>(v); });
   int cn[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) cn[c] = ((I + (c >> 1)) % g.nI) * g.nJ + (J + (c & 1)) % g.nJ;
@@ -132,11 +128,11 @@ __global__ __launch_bounds__(256) void k_prolong(const M* __restrict__ P,
   for (int g0 = 0; g0 < nrhs; g0 += ts.rg) {
     const int ng = min(ts.rg, nrhs - g0);
     __syncthreads();
-    for (int q = threadIdx.x; q < ng * ncol; q += 256) {
+    stage<8, 256, Vin>(ng * ncol, [&](int q) {
       const int rr = q / ncol, col = q - (q / ncol) * ncol;
       const int c = col / g.bc, j = col - (col / g.bc) * g.bc;
-      El[rr * ncol + col] = cconv<C>(e[(g0 + rr) * stride_c + int64_t(cn[c]) * g.bc + j]);
-    }
+      return e[(g0 + rr) * stride_c + int64_t(cn[c]) * g.bc + j];
+    }, [&](int q, Vin v) { El[q] = cconv<C>(v); });
     __syncthreads();
     for (int q = threadIdx.x; q < ng * nout; q += 256) {
       const int rr = q / nout, k = q - (q / nout) * nout;
@@ -471,22 +467,40 @@ __global__ __launch_bounds__(256) void k_restrict_gather(const cplx<R>* __restri
   const int N = int(gg / g.bc), j = int(gg - int64_t(N) * g.bc);
   const int I = N / g.nJ, J = N - (N / g.nJ) * g.nJ;
   const int ncol = g.ncol();
-  C sum = czero<R>();
+  // all loads first (from valid addresses: chunk 0 past the end), then the sums in the order
+  // corner, chunk, so that the loads are in flight together
+  const int q = j % g.b, pp = j / g.b;
+  const int pt = pp / g.o, px = pp - (pp / g.o) * g.o;
+  const int p = (g.a * I + pt) * g.Lx + (g.a * J + px);
+  const Vin rv = rin[r * stride_f + int64_t(p) * g.b + q];
+  constexpr int CHL = 2;                       // chunks per lane held in registers
+  const C* pw[4];
+  C pv[4][CHL];
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int WI = I - (c >> 1), WJ = J - (c & 1);
     const int w = (WI < 0 ? WI + g.nI : WI) * g.nJ + (WJ < 0 ? WJ + g.nJ : WJ);
-    const C* pw = part + (int64_t(r) * nW + w) * nchunk * ncol + c * g.bc + j;
-    for (int ch = ln; ch < nchunk; ch += lanes) sum = cadd(sum, pw[int64_t(ch) * ncol]);
+    pw[c] = part + (int64_t(r) * nW + w) * nchunk * ncol + c * g.bc + j;
+#pragma unroll
+    for (int u = 0; u < CHL; ++u) {
+      const int ch = ln + u * lanes;
+      pv[c][u] = pw[c][int64_t(ch < nchunk ? ch : 0) * ncol];
+    }
+  }
+  C sum = czero<R>();
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int u = 0; u < CHL; ++u)
+      if (ln + u * lanes < nchunk) sum = cadd(sum, pv[c][u]);
+    for (int ch = ln + CHL * lanes; ch < nchunk; ch += lanes) sum = cadd(sum, pw[c][int64_t(ch) * ncol]);
   }
   for (int off = lanes >> 1; off > 0; off >>= 1) {
     sum.x += __shfl_xor(sum.x, off);
     sum.y += __shfl_xor(sum.y, off);
   }
   if (!live || ln != 0) return;
-  const int q = j % g.b, pp = j / g.b;
-  const int pt = pp / g.o, px = pp - (pp / g.o) * g.o;
-  const int p = (g.a * I + pt) * g.Lx + (g.a * J + px);
-  sum = cadd(sum, cconv<C>(rin[r * stride_f + int64_t(p) * g.b + q]));
+  sum = cadd(sum, cconv<C>(rv));
   rc[r * stride_c + gid] = cconv<Vout>(sum);
 }
 
