@@ -177,22 +177,22 @@ amamg_status amamg_kernel_timer_read(const amamg_context *ctx, int32_t family, i
 
 /* ---- launch-shape autotuning ----------------------------------------------------------
  * Some kernels take a launch shape that does not change their arithmetic: the fine smoother's
- * tile width (16, 32 or 64 sites) and the right-hand sides per wave of the FP32 paired block
- * smoother on levels with 8 x 8 blocks (1, 2 or 4).  Results are bitwise the same for every
- * choice.  AMAMG_TUNE_AUTO (default): the first solve with a new (grid, block size, precision,
+ * tile width (16, 32 or 64 sites) and, for the FP32 block smoother on levels with 8 x 8 blocks,
+ * colour-pair launches with 1, 2 or 4 right-hand sides per wave or one launch per 2 x 2 colour
+ * block with 1 or 2 (reported as -1, -2).  Results are bitwise the same for every choice.  AMAMG_TUNE_AUTO (default): the first solve with a new (grid, block size, precision,
  * batch size) times the candidates on its workspace vectors before any right-hand side is
  * admitted and keeps the fastest in the context; AMAMG_TUNE_OFF: fixed defaults;
  * AMAMG_TUNE_FORCE: candidate number `force` of each tunable (clamped), for tests. */
 typedef enum { AMAMG_TUNE_AUTO = 0, AMAMG_TUNE_OFF = 1, AMAMG_TUNE_FORCE = 2 } amamg_tune_mode;
 typedef struct {
-  int32_t kind;          /* 0 fine smoother tile width, 1 block-smoother rhs per wave          */
+  int32_t kind;          /* 0 fine smoother tile width, 1 block-smoother launch shape          */
   int32_t lt, lx, b;     /* grid and dofs per node of the level                                */
   int32_t precision;     /* amamg_precision of the solve                                      */
   int32_t nrhs;          /* batch size (right-hand-side slots)                                */
   int32_t choice;        /* chosen candidate value                                            */
-  int32_t ncand;         /* candidates timed (at most 4)                                      */
-  int32_t cand[4];
-  double us[4];          /* their measured times in microseconds                              */
+  int32_t ncand;         /* candidates timed (at most 8)                                      */
+  int32_t cand[8];
+  double us[8];          /* their measured times in microseconds                              */
 } amamg_tune_entry;
 amamg_status amamg_context_set_tuning(amamg_context *ctx, int32_t mode, int32_t force);
 /* Copies up to `cap` of the context's tuned entries to out (may be NULL with cap 0) and

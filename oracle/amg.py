@@ -16,8 +16,10 @@ Readings where the paper is silent (all also used by the GPU library):
   scale that best reproduces smoothed random test vectors; equal to CONST for one test
   vector that is constant) and NONE;
 * smoother ("block solver as a smoother", 0 pre and 2 post sweeps): multicolour point-block
-  Gauss-Seidel; colours (t + x) mod 2 on the fine lattice, (I mod 4) * 4 + (J mod 4) on
-  coarse grids; one sweep visits the colours in increasing order and sets
+  Gauss-Seidel; colours (t + x) mod 2 on the fine lattice, visited in increasing order, and
+  (I mod 4) * 4 + (J mod 4) on coarse grids, visited in the order COARSE_ORDER, which takes the
+  colours of each 2 x 2 block of the 4 x 4 colour pattern in a row (0, 1, 4, 5, then 2, 3, 6, 7,
+  ...; any order is a valid multicolour sweep, the paper fixes none); a colour sets
   x_n <- x_n + A_nn^{-1} (f - A x)_n for all nodes n of the colour at once;
 * test vectors: level 0 starts from the splitmix64 vectors of ``oracle.rng``; level k+1 starts
   from level k's smoothed vectors injected at the vertices; each level relaxes them with nu
@@ -80,18 +82,21 @@ class Level:
 
 # ----------------------------------------------------------------------------- smoother
 
+COARSE_ORDER = (0, 1, 4, 5, 2, 3, 6, 7, 8, 9, 12, 13, 10, 11, 14, 15)
+
+
 def colouring(Lt: int, Lx: int, fine: bool) -> list:
-    """Node index arrays per colour, colours in increasing order."""
+    """Node index arrays per colour in sweep order: colours 0, 1 on the fine lattice, the coarse
+    colours in COARSE_ORDER."""
     T, X = np.meshgrid(np.arange(Lt), np.arange(Lx), indexing="ij")
     if fine:
         col = ((T + X) % 2).ravel()
-        ncol = 2
     else:
         if Lt % 4 or Lx % 4:
             raise ValueError("coarse-level colouring needs grid sizes divisible by 4")
         col = ((T % 4) * 4 + (X % 4)).ravel()
-        ncol = 16
-    return [np.nonzero(col == c)[0] for c in range(ncol)]
+    order = range(2) if fine else COARSE_ORDER
+    return [np.nonzero(col == c)[0] for c in order]
 
 
 def diagonal_block_inverses(A: sp.csr_matrix, nnode: int, b: int) -> np.ndarray:

@@ -78,11 +78,11 @@ class RequestInfo(C.Structure):
 class TuneEntry(C.Structure):
     _fields_ = [("kind", C.c_int32), ("lt", C.c_int32), ("lx", C.c_int32), ("b", C.c_int32),
                 ("precision", C.c_int32), ("nrhs", C.c_int32), ("choice", C.c_int32),
-                ("ncand", C.c_int32), ("cand", C.c_int32 * 4), ("us", C.c_double * 4)]
+                ("ncand", C.c_int32), ("cand", C.c_int32 * 8), ("us", C.c_double * 8)]
 
 
 TUNE_AUTO, TUNE_OFF, TUNE_FORCE = 0, 1, 2
-TUNE_KINDS = {0: "fine_smoother_tile", 1: "block_smoother_rhs_per_wave"}
+TUNE_KINDS = {0: "fine_smoother_tile", 1: "block_smoother_launch"}
 
 
 class ServerCounters(C.Structure):

@@ -314,6 +314,113 @@ __global__ __launch_bounds__(256) void k_stencil_gs_pair_mr(const M* __restrict_
   }
 }
 
+// One colour block qb of the coarse sweep (coarse_colour(4 qb) .. coarse_colour(4 qb + 3)) for
+// B = 8 in one launch: the block's nodes form 2 x 2 groups (rows I0, I0 + 1, columns J0, J0 + 1)
+// that do not couple with each other, and the four updates of a group run in colour order.  Two
+// waves per group: the lower wave updates (I0, J0) then (I0, J0 + 1) exactly as
+// k_stencil_gs_pair_mr does, and leaves their new values (in the storage type, as a launch per
+// colour pair would read them) in LDS; the upper wave then updates (I0 + 1, J0) and (I0 + 1,
+// J0 + 1) with those values for its in-group neighbours above.  Per right-hand side the upper
+// wave runs one phase behind the lower one; every thread passes the same RB + 1 barriers.
+// The results are bitwise those of the two colour-pair launches.
+template <int RB, typename R, typename M, typename Vx>
+__global__ __launch_bounds__(256) void k_stencil_gs_quad_mr(const M* __restrict__ A,
+                                                            const M* __restrict__ Dinv, Vx* x,
+                                                            const Vx* __restrict__ f, int Lt, int Lx,
+                                                            int qb, int nrhs, int64_t stride,
+                                                            const RhsState* __restrict__ st) {
+  constexpr int B = 8, NB = 24;
+  // neighbour slots (loop order dt, dx = -2..2 without (0, 0)) of the in-group offsets
+  constexpr int UPL = 6, UP = 7, UPR = 8, LEFT = 11;   // (-1,-1), (-1,0), (-1,+1), (0,-1)
+  using C = cplx<R>;
+  __shared__ C lower[2][RB][2][B];                    // [group slot][rhs][node][row]
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = lane >> 3, jl = lane & 7;
+  const int gs = wv >> 1, hi = wv & 1;
+  const int qx = Lx >> 2, ngr = (Lt >> 2) * qx;
+  const int k = blockIdx.x * 2 + gs;
+  const bool valid = k < ngr;
+  const int kk = valid ? k : 0;
+  const int t = 4 * (kk / qx) + 2 * (qb >> 1) + hi, xc = 4 * (kk % qx) + 2 * (qb & 1);
+  const int n1 = t * Lx + xc, n2 = n1 + 1;
+  int m1[NB], m2[NB];
+  C a1[NB], a2[NB];
+  {
+    int q = 0;
+#pragma unroll
+    for (int dt = -2; dt <= 2; ++dt) {
+      const int tt = wrap1(t + dt, Lt) * Lx;
+#pragma unroll
+      for (int dx = -2; dx <= 2; ++dx) {
+        if (dt == 0 && dx == 0) continue;
+        const int d = (dt + 2) * 5 + (dx + 2);
+        m1[q] = tt + wrap1(xc + dx, Lx);
+        m2[q] = tt + wrap1(xc + 1 + dx, Lx);
+        a1[q] = cconv<C>(A[(int64_t(n1) * 25 + d) * B * B + i * B + jl]);
+        a2[q] = cconv<C>(A[(int64_t(n2) * 25 + d) * B * B + i * B + jl]);
+        ++q;
+      }
+    }
+  }
+  const C d1 = cconv<C>(Dinv[int64_t(n1) * B * B + i * B + jl]);
+  const C d2 = cconv<C>(Dinv[int64_t(n2) * B * B + i * B + jl]);
+  const int r0 = blockIdx.y * RB;
+  for (int ph = 0; ph <= RB; ++ph) {
+    const int rr = ph - hi;
+    const int r = r0 + rr;
+    const bool work = valid && rr >= 0 && rr < RB && r < nrhs && (!st || st[r].active);
+    if (work) {
+      Vx* xr = x + r * stride;
+      C v1[NB], v2[NB];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const bool up1 = hi && (q == UP || q == UPR);
+        const bool up2 = hi && (q == UPL || q == UP);
+        if (!up1) v1[q] = cconv<C>(xr[int64_t(m1[q]) * B + jl]);
+        if (!up2 && q != LEFT) v2[q] = cconv<C>(xr[int64_t(m2[q]) * B + jl]);
+      }
+      if (hi) {
+        v1[UP] = lower[gs][rr][0][jl];
+        v1[UPR] = lower[gs][rr][1][jl];
+        v2[UPL] = lower[gs][rr][0][jl];
+        v2[UP] = lower[gs][rr][1][jl];
+      }
+      const C f1 = f ? cconv<C>(f[r * stride + int64_t(n1) * B + i]) : czero<R>();
+      const C f2 = f ? cconv<C>(f[r * stride + int64_t(n2) * B + i]) : czero<R>();
+      C acc = czero<R>();
+#pragma unroll
+      for (int q = 0; q < NB; ++q) acc = cfma(a1[q], v1[q], acc);
+      acc.x = group_sum<8>(acc.x);
+      acc.y = group_sum<8>(acc.y);
+      C res = mk<R>(-acc.x, -acc.y);
+      if (f) res = cadd(res, f1);
+      C out = cfma(d1, mk<R>(__shfl(res.x, jl * 8), __shfl(res.y, jl * 8)), czero<R>());
+      out.x = group_sum<8>(out.x);
+      out.y = group_sum<8>(out.y);
+      if (jl == 0) {
+        xr[int64_t(n1) * B + i] = cconv<Vx>(out);
+        if (!hi) lower[gs][rr][0][i] = cconv<C>(cconv<Vx>(out));
+      }
+      v2[LEFT] = cconv<C>(cconv<Vx>(mk<R>(__shfl(out.x, jl * 8), __shfl(out.y, jl * 8))));
+      acc = czero<R>();
+#pragma unroll
+      for (int q = 0; q < NB; ++q) acc = cfma(a2[q], v2[q], acc);
+      acc.x = group_sum<8>(acc.x);
+      acc.y = group_sum<8>(acc.y);
+      res = mk<R>(-acc.x, -acc.y);
+      if (f) res = cadd(res, f2);
+      out = cfma(d2, mk<R>(__shfl(res.x, jl * 8), __shfl(res.y, jl * 8)), czero<R>());
+      out.x = group_sum<8>(out.x);
+      out.y = group_sum<8>(out.y);
+      if (jl == 0) {
+        xr[int64_t(n2) * B + i] = cconv<Vx>(out);
+        if (!hi) lower[gs][rr][1][i] = cconv<C>(cconv<Vx>(out));
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // y = Ainv v for the coarsest level on FP64 matrix cores: a dense complex product of the
 // inverse with the right-hand sides, D[rhs][row] = sum_k v_rhs[k] Ainv[row][k], as real
 // v_mfma_f64_16x16x4f64 tiles (lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
@@ -417,6 +524,32 @@ static void gs_pair_b(hipStream_t s, const void* A, const void* D, void* x, cons
                (const V*)f, Lt, Lx, c0, stride, st);
 }
 
+// Colour block qb of the coarse sweep.  variant > 0: two colour-pair launches with that many
+// right-hand sides per wave (0 = default); variant < 0: one k_stencil_gs_quad_mr launch with
+// -variant right-hand sides per wave (FP32 8 x 8 blocks; otherwise colour pairs).  Every
+// variant gives bitwise the same results.
+template <int B, typename R, typename M, typename V>
+static void gs_block_b(hipStream_t s, const void* A, const void* D, void* x, const void* f, int Lt, int Lx,
+                       int qb, int nrhs, int64_t stride, const RhsState* st, int variant) {
+  if constexpr (B == 8 && sizeof(R) == 4) {
+    const int rb = -variant;
+    if ((rb == 1 || rb == 2) && nrhs >= rb) {
+      const int ngr = (Lt / 4) * (Lx / 4);
+      const dim3 g(unsigned((ngr + 1) / 2), unsigned((nrhs + rb - 1) / rb));
+      if (rb == 2)
+        AMAMG_LAUNCH((k_stencil_gs_quad_mr<2, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
+                     (const V*)f, Lt, Lx, qb, nrhs, stride, st);
+      else
+        AMAMG_LAUNCH((k_stencil_gs_quad_mr<1, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
+                     (const V*)f, Lt, Lx, qb, nrhs, stride, st);
+      return;
+    }
+  }
+  const int rb = variant > 0 ? variant : 0;
+  gs_pair_b<B, R, M, V>(s, A, D, x, f, Lt, Lx, coarse_colour(4 * qb), nrhs, stride, st, rb);
+  gs_pair_b<B, R, M, V>(s, A, D, x, f, Lt, Lx, coarse_colour(4 * qb + 2), nrhs, stride, st, rb);
+}
+
 #define AMAMG_B_DISPATCH(fn, prec, ...)                                                       \
   do {                                                                                        \
     if (prec == F64) {                                                                        \
@@ -455,6 +588,11 @@ void stencil_gs(hipStream_t s, Real prec, const void* A, const void* Dinv, void*
 void stencil_gs_pair(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
                      int Lt, int Lx, int b, int c0, int nrhs, int64_t stride, const RhsState* st, int rb) {
   AMAMG_B_DISPATCH(gs_pair_b, prec, s, A, Dinv, x, f, Lt, Lx, c0, nrhs, stride, st, rb);
+}
+
+void stencil_gs_block(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
+                      int Lt, int Lx, int b, int qb, int nrhs, int64_t stride, const RhsState* st, int variant) {
+  AMAMG_B_DISPATCH(gs_block_b, prec, s, A, Dinv, x, f, Lt, Lx, qb, nrhs, stride, st, variant);
 }
 
 void dense_apply(hipStream_t s, Real prec, const double2* Ainv, const void* v, void* y, int n,

@@ -92,6 +92,13 @@ template <typename T> __device__ inline T wave_sum(T v) {
   return v;
 }
 
+// Sweep order of the 16 coarse colours c = (I mod 4) 4 + (J mod 4): the four colours of each
+// 2 x 2 block of the colour pattern in a row.  Block qb (0..3) holds (a, 2q), (a, 2q + 1),
+// (a + 1, 2q), (a + 1, 2q + 1) with a = 2 (qb >> 1), q = qb & 1.
+__host__ __device__ constexpr int coarse_colour(int i) {
+  return 4 * (2 * ((i >> 2) >> 1) + ((i >> 1) & 1)) + 2 * ((i >> 2) & 1) + (i & 1);
+}
+
 // Global-to-LDS staging with U loads in flight per thread.  For every index q < total (thread
 // t takes q = t, t + NT, ...), fetch(q) is issued for U indices before store(q, value) runs for
 // them.  A plain loop of load-then-store lets each load wait for the previous iteration's LDS

@@ -84,6 +84,12 @@ void stencil_gs(hipStream_t s, Real prec, const void* A, const void* Dinv, void*
 // default): a launch parameter only, the results do not depend on it
 void stencil_gs_pair(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
                      int Lt, int Lx, int b, int c0, int nrhs, int64_t stride, const RhsState* st, int rb = 0);
+// colour block qb (0..3) of the coarse sweep order (coarse_colour(4 qb) .. coarse_colour(4 qb +
+// 3)), bitwise equal to four stencil_gs launches in that order.  variant: > 0 colour-pair
+// launches with that many right-hand sides per wave (FP32 8 x 8 blocks), < 0 one launch per
+// block with -variant right-hand sides per wave, 0 default: a launch parameter only
+void stencil_gs_block(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
+                      int Lt, int Lx, int b, int qb, int nrhs, int64_t stride, const RhsState* st, int variant = 0);
 // coarsest: y = Ainv v (matrix FP64 always; vectors in prec)
 void dense_apply(hipStream_t s, Real prec, const double2* Ainv, const void* v, void* y, int n,
                  int nrhs, int64_t stride, const RhsState* st);

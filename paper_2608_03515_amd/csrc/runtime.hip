@@ -58,7 +58,9 @@ static int timer_event(KernelTimer& t, size_t idx) {
 
 // Start / stop recording one launch of `family` at Arnoldi step `step` of batch `group`.
 // Families launched by one kernel arm the launch hook (events stamped by the kernel itself);
-// the fine restriction (two kernels) is bracketed by stream events.
+// the fine restriction (two kernels) and the level-1 smoother's colour blocks (one or two
+// kernels) are bracketed by stream events.
+static bool bracketed(int family) { return family == AMAMG_KT_RESTRICT0 || family == AMAMG_KT_COARSE_GS; }
 int timer_start(amamg_context* ctx, hipStream_t s, int family, int step, int group, double bytes_per_rhs) {
   KernelTimer& t = ctx->timer;
   if (!(t.mask & (1u << family))) return -1;
@@ -66,7 +68,7 @@ int timer_start(amamg_context* ctx, hipStream_t s, int family, int step, int gro
   size_t slot = 0;
   for (const auto& r : t.pending) slot = std::max(slot, size_t(r.e1) + 1);
   const int e0 = timer_event(t, slot), e1 = timer_event(t, slot + 1);
-  if (family == AMAMG_KT_RESTRICT0) HIPCHECK(hipEventRecord(t.events[e0], s));
+  if (bracketed(family)) HIPCHECK(hipEventRecord(t.events[e0], s));
   else timed_launch() = TimedLaunch{t.events[e0], t.events[e1]};
   t.pending.push_back({e0, e1, step, family, group, bytes_per_rhs});
   return int(t.pending.size()) - 1;
@@ -76,7 +78,7 @@ void timer_stop(amamg_context* ctx, hipStream_t s, int rec) {
   KernelTimer& t = ctx->timer;
   const auto& r = t.pending[rec];
   TimedLaunch& tl = timed_launch();
-  if (r.family == AMAMG_KT_RESTRICT0 || tl.start == t.events[r.e0]) {
+  if (bracketed(r.family) || tl.start == t.events[r.e0]) {
     // bracketing events (or a hook no launch consumed: the record then spans nothing)
     if (tl.start == t.events[r.e0]) HIPCHECK(hipEventRecord(t.events[r.e0], s));
     HIPCHECK(hipEventRecord(t.events[r.e1], s));
@@ -289,7 +291,7 @@ void run_setup(amamg_hierarchy* h, hipStream_t stream, Pool* scratch) {
             wilson_gs(s, LINK_F64, U0, U1, F64, L.tv, nullptr, g.Lt, g.Lx, h->m0, c, nv, ndof, nullptr);
         } else {
           for (int c = 0; c < 16; ++c)
-            stencil_gs(s, F64, L.A, L.Dinv, L.tv, nullptr, g.Lt, g.Lx, g.b, c, nv, ndof, nullptr);
+            stencil_gs(s, F64, L.A, L.Dinv, L.tv, nullptr, g.Lt, g.Lx, g.b, coarse_colour(c), nv, ndof, nullptr);
         }
       }
       check_launch();
@@ -659,7 +661,7 @@ amamg_status amamg_tuning_entries(amamg_context* ctx, amamg_tune_entry* out, int
       e.kind = kv.first[0]; e.lt = kv.first[1]; e.lx = kv.first[2]; e.b = kv.first[3];
       e.precision = kv.first[4]; e.nrhs = kv.first[5];
       e.choice = kv.second.choice;
-      e.ncand = int32_t(std::min<size_t>(4, kv.second.cand.size()));
+      e.ncand = int32_t(std::min<size_t>(8, kv.second.cand.size()));
       for (int q = 0; q < e.ncand; ++q) {
         e.cand[q] = kv.second.cand[q];
         e.us[q] = q < int(kv.second.us.size()) ? kv.second.us[q] : 0.0;

@@ -212,7 +212,7 @@ static void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x)
           wilson_gs(c.s, c.smooth_links, U0, U1, c.T, x, (const double2*)f, g.Lt, g.Lx, h->m0, col, c.nrhs, nd, st);
       else
         for (int col = 0; col < 16; ++col)
-          stencil_gs(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, col, c.nrhs, nd, st);
+          stencil_gs(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, coarse_colour(col), c.nrhs, nd, st);
     }
     if (k == 0)
       wilson_apply(c.s, c.smooth_links, U0, U1, c.T, x, c.T, WL.tmp, (const double2*)f, g.Lt, g.Lx, h->m0, c.nrhs, nd, st);
@@ -261,13 +261,13 @@ static void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x)
         timer_stop(ctx, c.s, rec);
       }
     } else {
-      // colour pairs (2q, 2q + 1): one launch each
-      for (int col = 0; col < 16; col += 2) {
+      // the four colour blocks of the sweep order (four colours each)
+      for (int qb = 0; qb < 4; ++qb) {
         const double ncn = double(g.nnode()) / 16.0;
         const int rec = k == 1 ? timer_start(ctx, c.s, AMAMG_KT_COARSE_GS, c.step, c.group,
-                                             2.0 * (ncn * 25.0 * g.b * g.b * cb + 2.0 * ncn * g.b * cb) + double(nd) * cb)
+                                             4.0 * (ncn * 25.0 * g.b * g.b * cb + 2.0 * ncn * g.b * cb) + double(nd) * cb)
                                : -1;
-        stencil_gs_pair(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, col, c.nrhs, nd, st, c.gs_rb ? c.gs_rb[k] : 0);
+        stencil_gs_block(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, qb, c.nrhs, nd, st, c.gs_rb ? c.gs_rb[k] : 0);
         timer_stop(ctx, c.s, rec);
       }
     }
@@ -367,8 +367,11 @@ static void tune_batch(Batch& bt) {
   for (size_t k = 1; k + 1 < h->lv.size(); ++k) {
     const Geom& g = h->lv[k].g;
     if (!(g.b == 8 && c.T == F32 && cap >= 2)) continue;
+    // > 0: colour-pair launches with that many rhs per wave; < 0: one launch per colour block
     std::vector<int> cand = {1, 2};
     if (cap >= 4) cand.push_back(4);
+    cand.push_back(-1);
+    cand.push_back(-2);
     const int64_t nd = g.ndof();
     Workspace::Lev& WL = ws->lv[k];
     const void* Ak = h->lv[k].A32;
@@ -377,8 +380,8 @@ static void tune_batch(Batch& bt) {
       HIPCHECK(hipMemsetAsync(WL.x, 0, rs * cap * nd, bt.s));
       HIPCHECK(hipMemsetAsync(WL.f, 0, rs * cap * nd, bt.s));
       return time_us(bt.s, [&] {
-        for (int col = 0; col < 16; col += 2)
-          stencil_gs_pair(bt.s, F32, Ak, Dk, WL.x, WL.f, g.Lt, g.Lx, g.b, col, cap, nd, nullptr, rb);
+        for (int qb = 0; qb < 4; ++qb)
+          stencil_gs_block(bt.s, F32, Ak, Dk, WL.x, WL.f, g.Lt, g.Lx, g.b, qb, cap, nd, nullptr, rb);
       });
     });
   }

@@ -491,8 +491,9 @@ def test_c4_mixed_batch_within_bound(lib, ctx):
 
 
 def test_tuned_launch_shapes_do_not_change_results(lib):
-    """The autotuner's launch shapes (fine smoother tile width 16/32/64, block-smoother right-hand
-    sides per wave 1/2/4 on the 128^2 workload's level 1) give bitwise the same mixed solve of 20
+    """The autotuner's launch shapes (fine smoother tile width 16/32/64; on the 128^2 workload's
+    level 1 the block smoother as colour-pair launches with 1/2/4 right-hand sides per wave or as
+    one launch per 2 x 2 colour block with 1/2) give bitwise the same mixed solve of 20
     right-hand sides, forced one by one and chosen by timing; the timed entries are recorded."""
     w = synth.WORKLOADS["C4"]
     m0 = synth.critical_masses()["C4"] + w.gaps[0]
@@ -502,7 +503,7 @@ def test_tuned_launch_shapes_do_not_change_results(lib):
     h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=8, overlap=2, n_test_vectors=8))
     sp = lib.default_solve_params(precision=lib.MIXED_FP32)
     runs = []
-    for mode, force in ((lib.TUNE_FORCE, 0), (lib.TUNE_FORCE, 1), (lib.TUNE_FORCE, 2), (lib.TUNE_AUTO, 0)):
+    for mode, force in [(lib.TUNE_FORCE, q) for q in range(5)] + [(lib.TUNE_AUTO, 0)]:
         say("tuning", mode, force)
         ctx.set_tuning(mode, force)
         x, infos, st = h.solve(psi, sp)
@@ -515,8 +516,8 @@ def test_tuned_launch_shapes_do_not_change_results(lib):
     for x, its in runs[1:]:
         assert its == runs[0][1] and np.array_equal(x, runs[0][0])
     kinds = {e["kind"]: e for e in entries}
-    assert set(kinds) == {"fine_smoother_tile", "block_smoother_rhs_per_wave"}
+    assert set(kinds) == {"fine_smoother_tile", "block_smoother_launch"}
     assert set(kinds["fine_smoother_tile"]["candidates_us"]) == {16, 32, 64}
-    assert set(kinds["block_smoother_rhs_per_wave"]["candidates_us"]) == {1, 2, 4}
+    assert set(kinds["block_smoother_launch"]["candidates_us"]) == {1, 2, 4, -1, -2}
     for e in entries:
         assert e["choice"] in e["candidates_us"] and all(t > 0 for t in e["candidates_us"].values())

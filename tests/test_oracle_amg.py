@@ -334,3 +334,32 @@ def test_splitmix64_published_stream():
         4593380528125082431, 16408922859458223821]
     states = np.array([1234567, 99, 2 ** 63 + 5], dtype=np.uint64)
     assert [int(v) for v in rng.splitmix64_np(states)] == [rng.splitmix64_int(int(s)) for s in states]
+
+
+def test_coarse_sweep_order_groups_are_uncoupled():
+    """The coarse sweep order takes the four colours of each 2 x 2 block of the colour pattern in
+    a row; the nodes of those colours form 2 x 2 node groups, and no two groups couple (the
+    stencil reaches 2 nodes, groups are 3 apart), so a group's four updates can run in order while
+    every other group of the block runs alongside."""
+    prm = amg.SetupParams(levels=3, agg=4, overlap=1, n_test_vectors=4)
+    U = synth.gen_links(64, 64, 6.0, 20, 5)
+    levs = amg.setup(U, 0.1, prm)
+    lev = levs[1]
+    assert sorted(amg.COARSE_ORDER) == list(range(16))
+    C = lev.A.tocoo()
+    n1, n2 = C.row // lev.b, C.col // lev.b
+    nz = (np.abs(C.data) > 0) & (n1 != n2)
+    for blk in range(4):
+        cols = amg.COARSE_ORDER[4 * blk: 4 * blk + 4]
+        # the block's colours are (a, 2q), (a, 2q + 1), (a + 1, 2q), (a + 1, 2q + 1)
+        a, q2 = cols[0] // 4, cols[0] % 4
+        assert cols == (4 * a + q2, 4 * a + q2 + 1, 4 * (a + 1) + q2, 4 * (a + 1) + q2 + 1)
+        members = np.zeros(lev.nnode, dtype=bool)
+        for c in range(4):
+            members[lev.colour_nodes[4 * blk + c]] = True
+        t, x = np.divmod(np.arange(lev.nnode), lev.Lx)
+        group = (t // 4) * (lev.Lx // 4) + (x // 4)
+        both = nz & members[n1] & members[n2]
+        assert np.all(group[n1[both]] == group[n2[both]])
+        # and inside a group the four nodes do couple (so their order matters)
+        assert both.any()
