@@ -85,7 +85,12 @@ typedef struct {
                                /* batch's latency-bound coarse levels with another's          */
                                /* bandwidth-bound work; 0 or 1 = one batch on the context     */
                                /* stream (default 1, at most 16)                              */
-  int32_t reserved;
+  int32_t graphs;              /* nonzero: each batch captures its restart cycle (the same   */
+                               /* kernels every cycle) into a HIP graph and replays it, also  */
+                               /* in later calls while the hierarchy's setup, the buffers,   */
+                               /* the stream and these parameters are unchanged; bitwise the */
+                               /* same results.  Ignored on the null stream, while the kernel */
+                               /* timer runs and with pre-smoothing (default 0)               */
 } amamg_solve_params;
 
 typedef struct {
@@ -269,6 +274,8 @@ typedef struct {
   int32_t restart;             /* FGMRES(m) (default 20)                                        */
   int32_t max_iters;           /* Arnoldi steps per right-hand side (default 10000)             */
   int32_t builders;            /* hierarchy builder threads, one stream each (default 2, <= 8)  */
+  int32_t graphs;              /* nonzero: instances replay their restart cycle from a HIP      */
+                               /* graph captured once per hierarchy binding (default 0)       */
   double rel_tol;              /* default 1e-10                                                 */
   uint64_t hbm_budget;         /* device bytes for hierarchies and instance workspaces;         */
                                /* 0 = three quarters of the free memory at creation           */

@@ -54,7 +54,7 @@ class SetupParams(C.Structure):
 class SolveParams(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iters", C.c_int32), ("rel_tol", C.c_double),
                 ("precision", C.c_int32), ("use_initial_guess", C.c_int32), ("groups", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("graphs", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -65,7 +65,7 @@ class SolveInfo(C.Structure):
 class ServerParams(C.Structure):
     _fields_ = [("slots", C.c_int32), ("max_instances", C.c_int32), ("precision", C.c_int32),
                 ("restart", C.c_int32), ("max_iters", C.c_int32), ("builders", C.c_int32),
-                ("rel_tol", C.c_double), ("hbm_budget", C.c_uint64)]
+                ("graphs", C.c_int32), ("rel_tol", C.c_double), ("hbm_budget", C.c_uint64)]
 
 
 class RequestInfo(C.Structure):

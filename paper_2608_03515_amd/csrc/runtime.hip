@@ -1,6 +1,7 @@
 // Host runtime and C ABI of the AM-AMG library: handles, the GPU setup pipeline and the entry
 // points.  Every numerical step runs in the kernels of this directory; the host only sequences
 // launches, owns device memory and reads per-rhs status once per restart cycle.
+#include <atomic>
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -429,6 +430,8 @@ void run_setup(amamg_hierarchy* h, hipStream_t stream, Pool* scratch) {
   }
   check_launch();
   HIPCHECK(hipStreamSynchronize(s));
+  static std::atomic<uint64_t> setups{0};   // unique over every hierarchy of the process
+  h->generation = ++setups;
   if (scratch)
     for (LevelData& L : h->lv) {
       L.tv = nullptr;
@@ -455,7 +458,7 @@ void amamg_default_solve_params(amamg_solve_params* p) {
   p->restart = 20; p->max_iters = 10000; p->rel_tol = 1e-10; p->precision = AMAMG_FP64;
   p->use_initial_guess = 0;
   p->groups = 1;
-  p->reserved = 0;
+  p->graphs = 0;
 }
 
 amamg_status amamg_context_create(int device, void* hip_stream, amamg_context** out) {

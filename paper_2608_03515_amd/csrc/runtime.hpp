@@ -176,6 +176,10 @@ struct Workspace {
   int* hadmit = nullptr;
   double2* hhist = nullptr;
   hipEvent_t ev = nullptr;
+  // restart cycle captured into a HIP graph (solve param `graphs`) and the launch it was
+  // captured for: every pointer and value the kernels receive; replayed while that matches
+  hipGraphExec_t graph = nullptr;
+  std::vector<uint64_t> graph_key;
   Workspace() = default;
   Workspace(const Workspace&) = delete;
   Workspace& operator=(const Workspace&) = delete;
@@ -218,6 +222,7 @@ struct amamg_hierarchy {
   std::vector<amamg::rt::Workspace*> ws;
   std::vector<hipStream_t> streams;
   std::vector<std::vector<double2>> history;
+  uint64_t generation = 0;  // number of its last setup, unique in the process (graphs key on it)
   ~amamg_hierarchy();
 };
 
@@ -282,8 +287,10 @@ struct Batch {
   // enqueue the first cycle start of the pending slots except `reject` (x = 0 unless the
   // initial guess is used, r = b - D x, V_0 = r / ||r||) and merge them into the batch state
   void admit_finish(const std::vector<int>& reject, bool use_initial_guess);
-  // enqueue one restart cycle for every slot in a cycle (requires a state read first)
+  // enqueue one restart cycle for every slot in a cycle (requires a state read first); with
+  // p.graphs the cycle is captured into a HIP graph on first use and replayed
   void enqueue_cycle();
+  void enqueue_cycle_kernels();
   // enqueue a copy of the state to the pinned mirror and record the event
   void enqueue_state_read();
   bool ready() const;

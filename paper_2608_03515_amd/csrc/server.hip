@@ -146,6 +146,7 @@ amamg_solve_params solve_params(const amamg_server* S) {
   p.max_iters = S->prm.max_iters;
   p.rel_tol = S->prm.rel_tol;
   p.precision = S->prm.precision;
+  p.graphs = S->prm.graphs;
   return p;
 }
 
@@ -610,6 +611,7 @@ void amamg_server_default_params(amamg_server_params* p) {
   p->restart = 20;
   p->max_iters = 10000;
   p->builders = 2;
+  p->graphs = 0;
   p->rel_tol = 1e-10;
   p->hbm_budget = 0;
 }

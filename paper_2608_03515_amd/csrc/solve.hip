@@ -31,6 +31,9 @@ static int krylov_blocks(int64_t n, int nrhs) {
 Workspace::~Workspace() { release(); }
 
 void Workspace::release() {
+  if (graph) (void)hipGraphExecDestroy(graph);
+  graph = nullptr;
+  graph_key.clear();
   if (block) (void)hipFree(block);
   if (hst) (void)hipHostFree(hst);
   if (hst2) (void)hipHostFree(hst2);
@@ -512,7 +515,68 @@ bool Batch::cycle_boundary() {
   return any;
 }
 
+// Everything a captured cycle bakes in: buffer addresses, launch shapes, the stream and the
+// values passed by value (mass, tolerances, tuned choices), and the hierarchy's setup count.
+static std::vector<uint64_t> graph_key(const Batch& bt) {
+  uint64_t tol;
+  std::memcpy(&tol, &bt.p.rel_tol, sizeof tol);
+  uint64_t m0;
+  std::memcpy(&m0, &bt.h->m0, sizeof m0);
+  std::vector<uint64_t> k{uint64_t(uintptr_t(bt.h)), bt.h->generation, m0, uint64_t(uintptr_t(bt.s)),
+                          uint64_t(uintptr_t(bt.b)), uint64_t(uintptr_t(bt.x)),
+                          uint64_t(uintptr_t(bt.ws->block)), uint64_t(bt.ws->cap),
+                          uint64_t(bt.ws->hist_cap), uint64_t(uint32_t(bt.p.precision)),
+                          uint64_t(uint32_t(bt.p.restart)), uint64_t(uint32_t(bt.p.max_iters)), tol,
+                          uint64_t(uint32_t(bt.group)), uint64_t(uint32_t(bt.fine_tc))};
+  for (int v : bt.gs_rb) k.push_back(uint64_t(uint32_t(v)));
+  const amamg_gauge* gg = bt.h->gauge;
+  const Workspace& w = *bt.ws;
+  for (const void* q : {(const void*)gg->U, (const void*)gg->U32, (const void*)gg->U16, (const void*)w.V,
+                        (const void*)w.Z, (const void*)w.st, (const void*)w.part, (const void*)w.coef,
+                        (const void*)w.hist})
+    k.push_back(uint64_t(uintptr_t(q)));
+  for (const Workspace::Lev& l : w.lv)
+    for (const void* q : {l.f, l.x, l.tmp, l.rpart}) k.push_back(uint64_t(uintptr_t(q)));
+  return k;
+}
+
 void Batch::enqueue_cycle() {
+  // (the legacy null stream cannot be captured; the kernel timer and pre-smoothing record
+  // event and memset nodes, which stay out of graphs)
+  const bool use_graph = p.graphs != 0 && s != nullptr && h->gauge->ctx->timer.mask == 0 &&
+                         h->prm.pre_sweeps == 0;
+  if (!use_graph) {
+    enqueue_cycle_kernels();
+    return;
+  }
+  std::vector<uint64_t> key = graph_key(*this);
+  if (!ws->graph || key != ws->graph_key) {
+    if (ws->graph) (void)hipGraphExecDestroy(ws->graph);
+    ws->graph = nullptr;
+    ws->graph_key.clear();
+    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipGraph_t g = nullptr;
+    try {
+      enqueue_cycle_kernels();
+    } catch (...) {
+      (void)hipStreamEndCapture(s, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHECK(hipStreamEndCapture(s, &g));
+    const hipError_t e = hipGraphInstantiate(&ws->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      ws->graph = nullptr;
+      throw Fail{AMAMG_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+    }
+    ws->graph_key = std::move(key);
+  }
+  HIPCHECK(hipGraphLaunch(ws->graph, s));
+  cycle_enqueued = true;
+}
+
+void Batch::enqueue_cycle_kernels() {
   SolveCtx c = make_ctx(*this);
   const KrylovDims kd = dims(*this);
   const int64_t n = kd.n, vsj = int64_t(ws->cap) * n;

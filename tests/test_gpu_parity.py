@@ -521,3 +521,35 @@ def test_tuned_launch_shapes_do_not_change_results(lib):
     assert set(kinds["block_smoother_launch"]["candidates_us"]) == {1, 2, 4, -1, -2}
     for e in entries:
         assert e["choice"] in e["candidates_us"] and all(t > 0 for t in e["candidates_us"].values())
+
+
+def test_graph_replayed_cycles_equal_eager(lib):
+    """Restart cycles captured into a HIP graph and replayed (once per cycle, with the host's
+    state reads and the stream groups' own work between replays) give bitwise the eager
+    launches' solutions, iteration counts and residual histories, in FP64 and mixed precision,
+    on one stream and on two stream groups, and again on a second solve with a new capture."""
+    w = synth.WORKLOADS["C2"]
+    m0 = synth.critical_masses()["C2"] + w.gaps[1]
+    psi = synth.field_to_abi(synth.gaussian_rhs(w.L, w.L, 97, nrhs=6))
+    stream = __import__("torch").cuda.Stream()
+    ctx = lib.Context(0, stream.cuda_stream)         # graphs need a capturable (non-null) stream
+    g = make_gauge(lib, ctx, w.links(), m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=4, overlap=1, n_test_vectors=8))
+    for prec in (lib.FP64, lib.MIXED_FP32):
+        for groups in (1, 2):
+            say("graphs", prec, groups)
+            runs = []
+            for graphs in (0, 1, 1):
+                sp = lib.default_solve_params(precision=prec, groups=groups, graphs=graphs)
+                x, infos, st = h.solve(psi, sp)
+                assert st == lib.OK
+                hist = [h.residual_history(r) for r in range(6)]
+                runs.append((x, [(i.iterations, i.restarts) for i in infos], hist))
+            for x, its, hist in runs[1:]:
+                assert its == runs[0][1] and np.array_equal(x, runs[0][0])
+                for (v, f), (v0, f0) in zip(hist, runs[0][2]):
+                    assert np.array_equal(v, v0) and np.array_equal(f, f0)
+            assert max(r for _, r in runs[0][1]) >= 1          # several cycles: several replays
+    h.close()
+    g.close()
+    ctx.close()

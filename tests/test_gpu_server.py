@@ -94,6 +94,15 @@ def test_server_matches_oracle_and_is_the_same_alone_and_in_a_mix(lib):
         srv.close()
         assert info.iterations == mix[k][0].iterations
         assert np.array_equal(x, mix[k][1])
+    # the mix again with every instance replaying its captured restart cycle: bitwise the same
+    srv = make_server(lib, graphs=1)
+    gids = [srv.add_gauge(synth.links_to_abi(U)) for U in Us]
+    say("server mix, graphs")
+    mixg = run(lib, srv, gids, reqs, stagger=0.02)
+    srv.close()
+    for (info, x), (info0, x0) in zip(mixg, mix):
+        assert info.status == lib.OK and info.iterations == info0.iterations
+        assert np.array_equal(x, x0)
 
 
 def test_server_request_errors_stay_with_their_request(lib):
@@ -166,19 +175,21 @@ def test_server_evicts_under_a_small_budget_and_rebuilds(lib):
     srv.close()
 
 
-def test_one_instance_rebound_across_lattice_sizes(lib):
+@pytest.mark.parametrize("graphs", [0, 1])
+def test_one_instance_rebound_across_lattice_sizes(lib, graphs):
     """A single solver instance serves requests on lattices of different sizes in turn (same
-    and different level counts): its workspace is resized for every hierarchy it is bound to."""
+    and different level counts): its workspace is resized for every hierarchy it is bound to,
+    and with graphs on, the restart cycle is captured again for every binding."""
     cases = [(synth.WORKLOADS["C1"].links(), 0.1, dict(levels=2, agg_size=4, overlap=1, n_test_vectors=4)),
              (synth.gen_links(32, 32, 4.0, 60, 321), 0.15, dict(levels=2, agg_size=4, overlap=1, n_test_vectors=4)),
              (synth.gen_links(64, 64, 6.0, 60, 654), 0.1, dict(levels=3, agg_size=4, overlap=1, n_test_vectors=8))]
-    srv = make_server(lib, max_instances=1)
+    srv = make_server(lib, max_instances=1, graphs=graphs)
     gids = [srv.add_gauge(synth.links_to_abi(U)) for U, _, _ in cases]
     for k in (0, 1, 2, 1, 0):
         U, m0, sp = cases[k]
         L = U.shape[1]
         psi = synth.gaussian_rhs(L, L, 40 + k, nrhs=2)
-        say("rebind", L)
+        say("rebind", L, "graphs", graphs)
         srv.submit(gids[k], m0, synth.field_to_abi(psi), lib.default_setup_params(**sp))
         assert srv.wait(120)
         (info, x), = srv.poll()
