@@ -24,7 +24,9 @@ Readings where the paper is silent (all also used by the GPU library):
 * test vectors: level 0 starts from the splitmix64 vectors of ``oracle.rng``; level k+1 starts
   from level k's smoothed vectors injected at the vertices; each level relaxes them with nu
   smoother sweeps on A w = 0;
-* the coarsest level is solved exactly by LU with partial pivoting;
+* the coarsest level is solved exactly by LU with partial pivoting (coarsest_tol = 0), or, as
+  in the paper's experiments, by unpreconditioned GMRES from x = 0 to the relative tolerance
+  coarsest_tol (0.1 there) with at most coarsest_max_iters steps (``fgmres.gmres``);
 * every level uses the same aggregate size a and overlap o.
 """
 from __future__ import annotations
@@ -37,6 +39,7 @@ import scipy.sparse as sp
 
 from . import rng
 from .dirac import dirac_matrix
+from .fgmres import gmres
 from .wirebasket import KIND_V, classify, coarse_dof_of_vertex, footprint
 
 NORM_TESTVEC, NORM_CONST, NORM_NONE = 0, 1, 2
@@ -53,6 +56,8 @@ class SetupParams:
     post_sweeps: int = 2
     norm: int = NORM_TESTVEC
     seed: int = 0
+    coarsest_tol: float = 0.0          # 0: exact solve; > 0: GMRES to this relative tolerance
+    coarsest_max_iters: int = 32
 
 
 @dataclass
@@ -235,6 +240,8 @@ def vcycle(levels: list, k: int, f: np.ndarray, prm: SetupParams) -> np.ndarray:
     """M_k f: the two-level scheme of the paper applied recursively, started at x = 0."""
     lev = levels[k]
     if lev.coarsest:
+        if prm.coarsest_tol > 0:
+            return gmres(lambda v: lev.A @ v, f, prm.coarsest_tol, prm.coarsest_max_iters)[0]
         return sla.lu_solve(lev.lu, f)
     x = np.zeros_like(f)
     for _ in range(prm.pre_sweeps):

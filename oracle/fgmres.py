@@ -107,3 +107,51 @@ def fgmres(apply_A, b: np.ndarray, precond, m: int = 20, tol: float = 1e-10,
         if info.iterations >= max_iters:
             return x, info
         info.restarts += 1
+
+
+def gmres(apply_A, b: np.ndarray, tol: float, max_steps: int):
+    """Unpreconditioned GMRES from x0 = 0, one cycle of at most max_steps Arnoldi steps (the
+    paper's coarsest-level solver, run there to relative tolerance 0.1; Numerical Results).
+    The reading used here (and by the GPU library): the Arnoldi, rotation and stopping rules of
+    one FGMRES cycle above with M = I (so z_j = v_j); the cycle stops when |g_{j+1}| <= tol ||b||,
+    on breakdown or after max_steps steps, and x = V_k R^{-1} g is returned without a restart or
+    a true-residual test.  Returns (x, steps); b = 0 gives x = 0 after no step."""
+    n = b.shape[0]
+    beta = np.linalg.norm(b)
+    if beta == 0:
+        return np.zeros_like(b, dtype=complex), 0
+    V = np.zeros((max_steps + 1, n), dtype=complex)
+    V[0] = b / beta
+    R = np.zeros((max_steps, max_steps), dtype=complex)
+    cs = np.zeros(max_steps)
+    sn = np.zeros(max_steps, dtype=complex)
+    g = np.zeros(max_steps + 1, dtype=complex)
+    g[0] = beta
+    k = 0
+    for j in range(max_steps):
+        w = apply_A(V[j])
+        # classical Gram-Schmidt, applied twice
+        h = V[: j + 1].conj() @ w
+        w = w - V[: j + 1].T @ h
+        h2 = V[: j + 1].conj() @ w
+        w = w - V[: j + 1].T @ h2
+        h = h + h2
+        hn = np.linalg.norm(w)
+        col = np.append(h, hn)
+        for i in range(j):                       # earlier rotations
+            t1 = cs[i] * col[i] + sn[i] * col[i + 1]
+            t2 = -np.conj(sn[i]) * col[i] + cs[i] * col[i + 1]
+            col[i], col[i + 1] = t1, t2
+        c, s = givens(col[j], col[j + 1])
+        col[j] = c * col[j] + s * col[j + 1]
+        cs[j], sn[j] = c, s
+        R[: j + 1, j] = col[: j + 1]
+        g[j + 1] = -np.conj(s) * g[j]
+        g[j] = c * g[j]
+        k = j + 1
+        if abs(g[j + 1]) <= tol * beta or hn <= 1e-300 * beta:
+            break
+        V[j + 1] = w / hn
+    y = sla.solve_triangular(R[:k, :k], g[:k])
+    return V[:k].T @ y, k
+
