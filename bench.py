@@ -309,6 +309,36 @@ def agg_sweep_leg(lib, torch, ctx, groups, nrhs=64):
     return out
 
 
+# the paper's own settings beside this library's defaults, on the headline workload
+VARIANTS = (("coarsest GMRES to 0.1 (the paper's coarsest solver)", dict(coarsest_tol=0.1)),
+            ("normalisation CONST (the paper's literal rule)", dict(norm=1)),
+            ("normalisation NONE", dict(norm=2)))
+
+
+def variants_leg(lib, torch, ctx, groups, nrhs=64):
+    """The 256^2 workload's field and mass, 64 right-hand sides, mixed precision, setup + solve,
+    with one setup parameter changed per record."""
+    w = synth.WORKLOADS["C3"]
+    m0 = synth.critical_masses()["C3"] + w.gaps[0]
+    g = lib.Gauge(ctx, synth.links_to_abi(w.links()), m0)
+    b = torch.from_numpy(synth.field_to_abi(synth.gaussian_rhs(w.L, w.L, w.rhs_seed, nrhs=nrhs))).to("cuda")
+    x = torch.zeros_like(b)
+    out = []
+    for name, kw in VARIANTS:
+        h = lib.Hierarchy(g, lib.default_setup_params(levels=w.levels, agg_size=w.agg, overlap=w.overlap,
+                                                       n_test_vectors=w.n_test_vectors, **kw))
+        dt, ts, infos, _ = run_steps(lib, torch, ctx, h, b, x, nrhs, lib.MIXED_FP32, 1, 1, groups=groups)
+        its = [i.iterations for i in infos]
+        rec = {"variant": name, "setup": kw, "solves_per_s": nrhs / dt, "setup_s": ts,
+               "iterations_min_max": [min(its), max(its)], "converged": all(i.converged for i in infos),
+               "max_rel_residual": max(i.true_rel_residual for i in infos)}
+        log("variant", json.dumps(rec))
+        out.append(rec)
+        h.close()
+    g.close()
+    return out
+
+
 # ------------------------------------------------------------------ profile summaries
 FAMILY_PATTERNS = {"update": "k_lag_update<", "dots": "k_gram<"}
 TRAFFIC_MD = os.path.join(ROOT, "profiles", "gram_schmidt_256x256_64rhs_mixed_traffic.md")
@@ -456,6 +486,8 @@ def main():
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg")
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-lattice leg")
     ap.add_argument("--no-agg-sweep", action="store_true", help="skip the aggregate-size sweep")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the paper-setting variants (coarsest GMRES, CONST/NONE normalisation)")
     ap.add_argument("--stencil-only", action="store_true",
                     help="run only the 4096^2 fine-stencil bandwidth leg (for kernel traces)")
     ap.add_argument("--multi-only", action="store_true", help="run only the multi-lattice leg")
@@ -613,6 +645,12 @@ def main():
             agg = agg_sweep_leg(lib, torch, ctx, args.groups)
         except Exception as e:              # an optional leg must not cost the headline line
             agg = {"error": f"{type(e).__name__}: {e}"}
+    variants = None
+    if not args.no_variants:
+        try:
+            variants = variants_leg(lib, torch, ctx, args.groups)
+        except Exception as e:              # an optional leg must not cost the headline line
+            variants = {"error": f"{type(e).__name__}: {e}"}
     serving = None
     if args.serve_requests > 0:
         serving = serve_leg(lib, args.serve_requests, args.serve_qps)
@@ -643,6 +681,7 @@ def main():
         "serving": serving,
         "multi_lattice": multi,
         "aggregate_sweep": agg,
+        "paper_variants": variants,
         "autotuner": ctx.tuning_entries(),
     }
     if not args.no_cpu_baseline:

@@ -63,7 +63,7 @@ typedef enum {
 } amamg_norm;
 
 typedef struct {
-  int32_t levels;              /* >= 2; the last level is solved directly (default 2)        */
+  int32_t levels;              /* >= 2; the last level is the coarsest (default 2)          */
   int32_t agg_size;            /* a: wirebasket spacing (default 4)                          */
   int32_t overlap;             /* o: shared border width, 1 <= o < a (default 1)             */
   int32_t n_test_vectors;      /* N_v for AMAMG_NORM_TESTVEC, 1..16 (default 4)              */
@@ -72,6 +72,11 @@ typedef struct {
   int32_t post_sweeps;         /* default 2                                                  */
   int32_t norm;                /* amamg_norm (default AMAMG_NORM_TESTVEC)                    */
   uint64_t seed;               /* test-vector hash seed (default 0)                          */
+  double coarsest_tol;         /* 0: the coarsest level is solved exactly (LU inverse,       */
+                               /* default); > 0: unpreconditioned GMRES from 0 to this        */
+                               /* relative tolerance, FP64, as in the paper's experiments     */
+                               /* (Numerical Results: 0.1); needs <= 2048 coarsest unknowns   */
+  int32_t coarsest_max_iters;  /* GMRES steps at most, 1..32 (default 32)                    */
 } amamg_setup_params;
 
 typedef struct {

@@ -478,6 +478,245 @@ __global__ __launch_bounds__(256) void k_dense_apply_mfma(const double2* __restr
   }
 }
 
+// Unpreconditioned GMRES from x = 0 on the coarsest level (the paper's coarsest-level solver,
+// run there to relative tolerance 0.1), FP64 throughout, one workgroup per right-hand side, so
+// that a right-hand side's arithmetic is the same in every batch.  Arnoldi with classical
+// Gram-Schmidt applied twice and the FGMRES rotation rule; the cycle stops when
+// |g_{j+1}| <= tol ||f||, on breakdown (h_{j+1,j} <= 1e-300 ||f||) or after `steps` steps, and
+// x = V R^{-1} g.  Thread t owns rows t and t + 1024 of every vector; the basis is kept in
+// `basis` [rhs][steps + 1][n] (each thread reads back only the rows it wrote).  The product
+// with the column-major matrix Acm[k][row] is latency-bound on one CU, so it keeps many loads
+// in flight: the 1024 threads form S = 1024 / RT segments of k (RT = row threads, a power of
+// two >= n up to 1024), each reading coalesced column pieces, and the segment sums of a row
+// are added in segment order.  Block sums: butterfly within each wave, then the 16 wave sums
+// in order.
+constexpr int kCgThreads = 1024, kCgWaves = kCgThreads / 64, kCgRows = 2, kCgMaxSteps = 32;
+
+__device__ inline void cg_wave_part(double2 v, double2 (*part)[kCgWaves], int i, int lane, int wv) {
+  v.x = wave_sum(v.x);
+  v.y = wave_sum(v.y);
+  if (lane == 0) part[i][wv] = v;
+}
+
+__device__ inline double2 cg_part_total(const double2* p) {
+  double2 s = p[0];
+  for (int q = 1; q < kCgWaves; ++q) s = cadd(s, p[q]);
+  return s;
+}
+
+template <typename Vin, typename Vout>
+__global__ __launch_bounds__(kCgThreads) void k_coarsest_gmres(const double2* __restrict__ Acm,
+                                                               const Vin* __restrict__ f, Vout* __restrict__ x,
+                                                               int n, int64_t stride, const RhsState* __restrict__ st,
+                                                               double tol, int steps, double2* __restrict__ basis) {
+  extern __shared__ double2 dyn[];                      // xs [n], then segment sums [1024] if n < 1024
+  __shared__ double2 part[kCgMaxSteps + 1][kCgWaves];
+  __shared__ double2 hp[kCgMaxSteps + 1];               // this pass's projections, then y
+  __shared__ double2 hsum[kCgMaxSteps + 2];             // Hessenberg column
+  __shared__ double2 R[kCgMaxSteps * (kCgMaxSteps + 1) / 2];
+  __shared__ double2 g[kCgMaxSteps + 1], sn[kCgMaxSteps];
+  __shared__ double cs[kCgMaxSteps];
+  __shared__ double beta_s, hn_s;
+  __shared__ int stop_s, k_s;
+  const int r = blockIdx.x;
+  if (st && !st[r].active) return;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  double2* xs = dyn;
+  double2* seg_sum = dyn + n;
+  int RT = 64;
+  while (RT < n && RT < kCgThreads) RT <<= 1;
+  const int S = kCgThreads / RT, rl = t % RT, seg = t / RT;
+  const int q0 = int(int64_t(n) * seg / S), q1 = int(int64_t(n) * (seg + 1) / S);
+  double2* Vb = basis + int64_t(r) * (steps + 1) * n;
+  const Vin* fr = f + int64_t(r) * stride;
+  Vout* xr = x + int64_t(r) * stride;
+  double2 w[kCgRows];
+  // beta = ||f||
+  double2 acc = make_double2(0, 0);
+#pragma unroll
+  for (int i = 0; i < kCgRows; ++i) {
+    const int row = t + kCgThreads * i;
+    w[i] = row < n ? cconv<double2>(fr[row]) : make_double2(0, 0);
+    acc.x += cabs2(w[i]);
+  }
+  cg_wave_part(acc, part, 0, lane, wv);
+  __syncthreads();
+  if (t == 0) {
+    beta_s = sqrt(cg_part_total(part[0]).x);
+    g[0] = make_double2(beta_s, 0);
+  }
+  __syncthreads();
+  const double beta = beta_s;
+  if (beta == 0) {
+#pragma unroll
+    for (int i = 0; i < kCgRows; ++i) {
+      const int row = t + kCgThreads * i;
+      if (row < n) xr[row] = cconv<Vout>(make_double2(0, 0));
+    }
+    return;
+  }
+  const double ib = 1.0 / beta;
+#pragma unroll
+  for (int i = 0; i < kCgRows; ++i) {
+    const int row = t + kCgThreads * i;
+    if (row < n) {
+      const double2 v = cscale(w[i], ib);
+      Vb[row] = v;
+      xs[row] = v;
+    }
+  }
+  int k = 0;
+  for (int j = 0; j < steps; ++j) {
+    __syncthreads();                                     // xs holds v_j
+    // w = A v_j: this thread's segment of k for rows rl (+ 1024 when RT = 1024)
+    double2 a[kCgRows];
+#pragma unroll
+    for (int i = 0; i < kCgRows; ++i) a[i] = make_double2(0, 0);
+#pragma unroll 8
+    for (int q = q0; q < q1; ++q) {
+      const double2 xq = xs[q];
+      const double2* col = Acm + int64_t(q) * n;
+#pragma unroll
+      for (int i = 0; i < kCgRows; ++i) {
+        const int row = rl + RT * i;
+        if (row < n) a[i] = cfma(col[row], xq, a[i]);
+      }
+    }
+    if (S == 1) {                                        // RT = 1024: rl = t, rows are the owned ones
+#pragma unroll
+      for (int i = 0; i < kCgRows; ++i) w[i] = a[i];
+    } else {                                             // n <= RT <= 512: one row per thread
+      seg_sum[seg * RT + rl] = a[0];
+      __syncthreads();
+      if (t < n) {
+        double2 v = seg_sum[t];
+        for (int q = 1; q < S; ++q) v = cadd(v, seg_sum[q * RT + t]);
+        w[0] = v;
+      }
+    }
+    // classical Gram-Schmidt, applied twice: h = V^H w, w -= V h
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int l = 0; l <= j; ++l) {
+        const double2* vl = Vb + int64_t(l) * n;
+        double2 p = make_double2(0, 0);
+#pragma unroll
+        for (int i = 0; i < kCgRows; ++i) {
+          const int row = t + kCgThreads * i;
+          if (row < n) p = cfmac(vl[row], w[i], p);
+        }
+        cg_wave_part(p, part, l, lane, wv);
+      }
+      __syncthreads();
+      if (t <= j) {
+        const double2 h = cg_part_total(part[t]);
+        hp[t] = h;
+        hsum[t] = pass == 0 ? h : cadd(hsum[t], h);
+      }
+      __syncthreads();
+      for (int l = 0; l <= j; ++l) {
+        const double2* vl = Vb + int64_t(l) * n;
+        const double2 h = hp[l];
+#pragma unroll
+        for (int i = 0; i < kCgRows; ++i) {
+          const int row = t + kCgThreads * i;
+          if (row < n) w[i] = cfma(vl[row], make_double2(-h.x, -h.y), w[i]);
+        }
+      }
+      __syncthreads();                                   // hp and part are rewritten next
+    }
+    // h_{j+1,j} = ||w||
+    acc = make_double2(0, 0);
+#pragma unroll
+    for (int i = 0; i < kCgRows; ++i) acc.x += cabs2(w[i]);
+    cg_wave_part(acc, part, 0, lane, wv);
+    __syncthreads();
+    if (t == 0) {
+      const double hn = sqrt(cg_part_total(part[0]).x);
+      hn_s = hn;
+      hsum[j + 1] = make_double2(hn, 0);
+      for (int i = 0; i < j; ++i) {                      // earlier rotations
+        const double2 a0 = hsum[i], b0 = hsum[i + 1];
+        const double2 s0 = sn[i];
+        const double c0 = cs[i];
+        // (c a + s b, -conj(s) a + c b)
+        hsum[i] = cfma(s0, b0, cscale(a0, c0));
+        hsum[i + 1] = cfma(make_double2(-s0.x, s0.y), a0, cscale(b0, c0));
+      }
+      const double2 a0 = hsum[j], b0 = hsum[j + 1];
+      double c0;
+      double2 s0;
+      if (a0.x == 0 && a0.y == 0) {
+        c0 = 0;
+        s0 = make_double2(1, 0);
+      } else {
+        const double aa = sqrt(cabs2(a0));
+        const double nu = sqrt(cabs2(a0) + cabs2(b0));
+        c0 = aa / nu;
+        // (a / |a|) conj(b) / nu
+        s0 = cscale(cmul(a0, cconj(b0)), 1.0 / (aa * nu));
+      }
+      cs[j] = c0;
+      sn[j] = s0;
+      hsum[j] = cfma(s0, b0, cscale(a0, c0));
+      for (int i = 0; i <= j; ++i) R[j * (j + 1) / 2 + i] = hsum[i];
+      const double2 gj = g[j];
+      g[j + 1] = cmul(make_double2(-s0.x, s0.y), gj);
+      g[j] = cscale(gj, c0);
+      k_s = j + 1;
+      stop_s = sqrt(cabs2(g[j + 1])) <= tol * beta || hn <= 1e-300 * beta;
+    }
+    __syncthreads();
+    k = k_s;
+    if (stop_s) break;
+    const double ih = 1.0 / hn_s;
+#pragma unroll
+    for (int i = 0; i < kCgRows; ++i) {
+      const int row = t + kCgThreads * i;
+      if (row < n) {
+        const double2 v = cscale(w[i], ih);
+        Vb[int64_t(j + 1) * n + row] = v;
+        xs[row] = v;
+      }
+    }
+  }
+  // y = R^{-1} g (back substitution), x = V y
+  if (t == 0) {
+    for (int i = k - 1; i >= 0; --i) {
+      double2 v = g[i];
+      for (int l = i + 1; l < k; ++l) v = cfma(R[l * (l + 1) / 2 + i], make_double2(-hp[l].x, -hp[l].y), v);
+      hp[i] = cdiv(v, R[i * (i + 1) / 2 + i]);
+    }
+  }
+  __syncthreads();
+  double2 xv[kCgRows];
+#pragma unroll
+  for (int i = 0; i < kCgRows; ++i) xv[i] = make_double2(0, 0);
+  for (int l = 0; l < k; ++l) {
+    const double2* vl = Vb + int64_t(l) * n;
+    const double2 y = hp[l];
+#pragma unroll
+    for (int i = 0; i < kCgRows; ++i) {
+      const int row = t + kCgThreads * i;
+      if (row < n) xv[i] = cfma(vl[row], y, xv[i]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kCgRows; ++i) {
+    const int row = t + kCgThreads * i;
+    if (row < n) xr[row] = cconv<Vout>(xv[i]);
+  }
+}
+
+// Acm[k][row] = A[row][k] (dense n x n)
+__global__ void k_transpose_dense(const double2* __restrict__ A, double2* __restrict__ At, int n) {
+  __shared__ double2 tile[16][17];
+  const int bx = blockIdx.x * 16, by = blockIdx.y * 16;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  if (by + ty < n && bx + tx < n) tile[ty][tx] = A[int64_t(by + ty) * n + bx + tx];
+  __syncthreads();
+  if (bx + ty < n && by + tx < n) At[int64_t(bx + ty) * n + by + tx] = tile[tx][ty];
+}
+
 // ------------------------------------------------------------------------------ launchers
 
 template <int B, typename R, typename M, typename V>
@@ -607,4 +846,21 @@ void dense_apply(hipStream_t s, Real prec, const double2* Ainv, const void* v, v
                        (const float2*)v, (float2*)y, n, nrhs, stride, st);
 }
 
+void coarsest_gmres(hipStream_t s, Real prec, const double2* Acm, const void* f, void* x, int n, int nrhs,
+                    int64_t stride, const RhsState* st, double tol, int steps, double2* basis) {
+  const size_t lds = sizeof(double2) * (size_t(n) + (n < kCgThreads ? kCgThreads : 0));
+  if (prec == F64)
+    hipLaunchKernelGGL((k_coarsest_gmres<double2, double2>), dim3(unsigned(nrhs)), dim3(kCgThreads), lds, s, Acm,
+                       (const double2*)f, (double2*)x, n, stride, st, tol, steps, basis);
+  else
+    hipLaunchKernelGGL((k_coarsest_gmres<float2, float2>), dim3(unsigned(nrhs)), dim3(kCgThreads), lds, s, Acm,
+                       (const float2*)f, (float2*)x, n, stride, st, tol, steps, basis);
+}
+
+void transpose_dense(hipStream_t s, const double2* A, double2* At, int n) {
+  const dim3 g(unsigned((n + 15) / 16), unsigned((n + 15) / 16));
+  hipLaunchKernelGGL(k_transpose_dense, g, dim3(256), 0, s, A, At, n);
+}
+
 }  // namespace amamg
+

@@ -39,6 +39,11 @@ template <typename V> __device__ __host__ inline V cfmac(V a, V b, V acc) {
 }
 template <typename V, typename R> __device__ __host__ inline V cscale(V a, R s) { V z; z.x = a.x * s; z.y = a.y * s; return z; }
 template <typename V> __device__ __host__ inline V cconj(V a) { V z; z.x = a.x; z.y = -a.y; return z; }
+// a / b = a conj(b) / |b|^2
+template <typename V> __device__ __host__ inline V cdiv(V a, V b) {
+  const auto d = 1 / (b.x * b.x + b.y * b.y);
+  V z; z.x = (a.x * b.x + a.y * b.y) * d; z.y = (a.y * b.x - a.x * b.y) * d; return z;
+}
 template <typename V> __device__ __host__ inline V ctimes_i(V a) { V z; z.x = -a.y; z.y = a.x; return z; }
 template <typename V> __device__ __host__ inline auto cabs2(V a) { return a.x * a.x + a.y * a.y; }
 

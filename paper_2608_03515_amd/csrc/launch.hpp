@@ -90,6 +90,12 @@ void stencil_gs_pair(hipStream_t s, Real prec, const void* A, const void* Dinv, 
 // block with -variant right-hand sides per wave, 0 default: a launch parameter only
 void stencil_gs_block(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
                       int Lt, int Lx, int b, int qb, int nrhs, int64_t stride, const RhsState* st, int variant = 0);
+// coarsest, GMRES variant: x = unpreconditioned GMRES(A, f) from 0 to relative tolerance tol in
+// at most `steps` (<= 32) steps, n <= 2048; Acm column-major FP64; basis [nrhs][steps + 1][n]
+void coarsest_gmres(hipStream_t s, Real prec, const double2* Acm, const void* f, void* x, int n, int nrhs,
+                    int64_t stride, const RhsState* st, double tol, int steps, double2* basis);
+void transpose_dense(hipStream_t s, const double2* A, double2* At, int n);
+constexpr int kCoarsestGmresMaxSteps = 32, kCoarsestGmresMaxN = 2048;
 // coarsest: y = Ainv v (matrix FP64 always; vectors in prec)
 void dense_apply(hipStream_t s, Real prec, const double2* Ainv, const void* v, void* y, int n,
                  int nrhs, int64_t stride, const RhsState* st);

@@ -159,6 +159,10 @@ std::vector<LevelPlan> plan_levels(int nt, int nx, const amamg_setup_params& p) 
           AMAMG_ERR_INVALID_ARG, "n_test_vectors must be in [1, 16]");
   REQUIRE(p.test_vector_sweeps >= 0 && p.pre_sweeps >= 0 && p.post_sweeps >= 0,
           AMAMG_ERR_INVALID_ARG, "sweep counts must be >= 0");
+  REQUIRE(std::isfinite(p.coarsest_tol) && p.coarsest_tol >= 0 && p.coarsest_tol < 1, AMAMG_ERR_INVALID_ARG,
+          "coarsest_tol must be in [0, 1)");
+  REQUIRE(p.coarsest_tol == 0 || (p.coarsest_max_iters >= 1 && p.coarsest_max_iters <= kCoarsestGmresMaxSteps),
+          AMAMG_ERR_INVALID_ARG, "coarsest_max_iters must be in [1, 32]");
   std::vector<LevelPlan> out;
   int Lt = nt, Lx = nx, b = 2;
   const int a = p.agg_size, o = p.overlap;
@@ -181,6 +185,8 @@ std::vector<LevelPlan> plan_levels(int nt, int nx, const amamg_setup_params& p) 
   const LevelPlan& c = out.back();
   REQUIRE(int64_t(c.Lt) * c.Lx * c.b <= 4096, AMAMG_ERR_UNSUPPORTED_SHAPE,
           "coarsest level above 4096 unknowns (add a level)");
+  REQUIRE(p.coarsest_tol == 0 || int64_t(c.Lt) * c.Lx * c.b <= kCoarsestGmresMaxN, AMAMG_ERR_UNSUPPORTED_SHAPE,
+          "coarsest GMRES needs at most 2048 coarsest unknowns (add a level)");
   return out;
 }
 
@@ -222,7 +228,7 @@ size_t setup_bytes(int nt, int nx, const amamg_setup_params& p) {
     b += nW * nfd * (nfd + ncol) * c16 + ndof * ncol * (c16 + c8);
     b += size_t(nv) * ndc * c16 * 2;
     b += bc * (2 * ndc + 2 * ndof) * c16 + bc * nW * restrict_chunks(g, nf, F64) * ncol * c16;
-    if (k + 1 == K - 1) b += ndc * ndc * c16 * 4;
+    if (k + 1 == K - 1) b += ndc * ndc * c16 * (p.coarsest_tol > 0 ? 5 : 4);
     else b += nnc * 25 * bc * bc * (c16 + c8) + nnc * bc * bc * (3 * c16 + c8) + nnc * 4;
   }
   return b;
@@ -399,6 +405,11 @@ void run_setup(amamg_hierarchy* h, hipStream_t stream, Pool* scratch) {
       HIPCHECK(hipMemcpyAsync(&hc, cinfo, sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHECK(hipStreamSynchronize(s));
       REQUIRE(hc == 0, AMAMG_ERR_SINGULAR_COARSEST, "zero pivot in the coarsest factorisation");
+      if (p.coarsest_tol > 0) {
+        C.Acm = h->mem.get<double2>("C_Acm", k, size_t(n) * n);
+        transpose_dense(s, C.Adense, C.Acm, n);
+        check_launch();
+      }
     }
     W = Wc;
     // the next level's test vectors must outlive this iteration's temporaries
@@ -451,6 +462,7 @@ void amamg_default_setup_params(amamg_setup_params* p) {
   p->levels = 2; p->agg_size = 4; p->overlap = 1; p->n_test_vectors = 4;
   p->test_vector_sweeps = 4; p->pre_sweeps = 0; p->post_sweeps = 2;
   p->norm = AMAMG_NORM_TESTVEC; p->seed = 0;
+  p->coarsest_tol = 0; p->coarsest_max_iters = 32;
 }
 
 void amamg_default_solve_params(amamg_solve_params* p) {

@@ -135,6 +135,7 @@ struct LevelData {
   float2* Dinv32 = nullptr;
   double2* Adense = nullptr; // coarsest [n][n]
   double2* Ainv = nullptr;   // coarsest inverse [n][n]
+  double2* Acm = nullptr;    // coarsest matrix, column-major [k][row] (GMRES variant only)
   // transfer to the next level (non-coarsest)
   int8_t* kind = nullptr;
   int* owner = nullptr;
@@ -169,7 +170,7 @@ struct Workspace {
   RhsState* st = nullptr;     // control state of the running batch
   RhsState* st2 = nullptr;    // state of slots being admitted
   int* admit = nullptr;       // admission mask [cap]
-  struct Lev { void *f = nullptr, *x = nullptr, *tmp = nullptr, *rpart = nullptr; };
+  struct Lev { void *f = nullptr, *x = nullptr, *tmp = nullptr, *rpart = nullptr; double2* kry = nullptr; };
   std::vector<Lev> lv;
   RhsState* hst = nullptr;    // pinned mirrors
   RhsState* hst2 = nullptr;

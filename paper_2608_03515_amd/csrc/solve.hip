@@ -52,6 +52,12 @@ void Workspace::release() {
   cap = m = hist_cap = 0;
 }
 
+// complex entries per right-hand side of the coarsest GMRES basis (0 for the exact solve)
+static size_t coarsest_basis(const amamg_hierarchy* h) {
+  if (!(h->prm.coarsest_tol > 0)) return 0;
+  return size_t(h->prm.coarsest_max_iters + 1) * size_t(h->lv.back().g.ndof());
+}
+
 static size_t level_rpart_count(const LevelData& L, Real prec) {
   return size_t(L.g.nI) * L.g.nJ * restrict_chunks(L.g, L.nf, prec) * L.g.ncol();
 }
@@ -66,6 +72,7 @@ size_t workspace_bytes(const amamg_hierarchy* h, int cap, int m, Real prec, int 
   for (size_t k = 1; k < h->lv.size(); ++k) b += 3 * size_t(cap) * h->lv[k].g.ndof() * rs;
   b += size_t(cap) * n * rs;
   for (size_t k = 0; k + 1 < h->lv.size(); ++k) b += size_t(cap) * level_rpart_count(h->lv[k], prec) * rs;
+  b += sizeof(double2) * size_t(cap) * coarsest_basis(h) + 256;
   return b;
 }
 
@@ -75,6 +82,7 @@ static std::vector<int64_t> shape_of(const amamg_hierarchy* h, Real prec) {
     s.push_back(h->lv[k].g.ndof());
     s.push_back(k + 1 < h->lv.size() ? int64_t(level_rpart_count(h->lv[k], prec)) : 0);
   }
+  s.push_back(int64_t(coarsest_basis(h)));
   return s;
 }
 
@@ -113,6 +121,7 @@ static void layout(Workspace& ws, const amamg_hierarchy* h, int cap, int m, Real
   ws.lv[0].tmp = take(size_t(cap) * n * rs);
   for (size_t k = 0; k + 1 < h->lv.size(); ++k)
     ws.lv[k].rpart = take(size_t(cap) * level_rpart_count(h->lv[k], prec) * rs);
+  if (coarsest_basis(h) > 0) ws.lv.back().kry = (double2*)take(sizeof(double2) * size_t(cap) * coarsest_basis(h));
 }
 
 void ensure_workspace(Workspace& ws, const amamg_hierarchy* h, int cap, int m, Real prec, int hist_cap) {
@@ -192,7 +201,11 @@ static void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x)
   const RhsState* st = c.ws->st;
   const bool f64 = c.T == F64;
   if (L.coarsest) {
-    dense_apply(c.s, c.T, L.Ainv, f, x, int(nd), c.nrhs, nd, st);
+    if (h->prm.coarsest_tol > 0)
+      coarsest_gmres(c.s, c.T, L.Acm, f, x, int(nd), c.nrhs, nd, st, h->prm.coarsest_tol,
+                     h->prm.coarsest_max_iters, WL.kry);
+    else
+      dense_apply(c.s, c.T, L.Ainv, f, x, int(nd), c.nrhs, nd, st);
     return;
   }
   LevelData& C = h->lv[k + 1];
@@ -536,7 +549,7 @@ static std::vector<uint64_t> graph_key(const Batch& bt) {
                         (const void*)w.hist})
     k.push_back(uint64_t(uintptr_t(q)));
   for (const Workspace::Lev& l : w.lv)
-    for (const void* q : {l.f, l.x, l.tmp, l.rpart}) k.push_back(uint64_t(uintptr_t(q)));
+    for (const void* q : {l.f, l.x, l.tmp, l.rpart, (void*)l.kry}) k.push_back(uint64_t(uintptr_t(q)));
   return k;
 }
 

@@ -251,6 +251,66 @@ def test_c2_mixed_precision_within_bound(lib, ctx, precision, bound):
     assert abs(ig.iterations - io.iterations) <= max(5, io.iterations // 10)
 
 
+@pytest.mark.parametrize("wl,precision,bound", [("C1", 0, 1e-9), ("C2", 0, 1e-9), ("C2", 1, 1e-9)])
+def test_coarsest_gmres_variant_matches_oracle(lib, ctx, wl, precision, bound):
+    """The paper's coarsest-level solver, unpreconditioned GMRES to relative tolerance 0.1, in
+    place of the exact solve: in FP64 the iteration counts equal the oracle's and the solutions
+    agree to 1e-9; in mixed precision the solution is within the bound; in a batch each
+    right-hand side gets bitwise its single solve (one workgroup per right-hand side)."""
+    w = synth.WORKLOADS[wl]
+    U = w.links()
+    m0 = w.m0 if wl == "C1" else synth.critical_masses()[wl] + 0.02
+    psi = synth.gaussian_rhs(w.L, w.L, w.rhs_seed + 5, nrhs=3)
+    say("coarsest GMRES", wl, precision)
+    prm = amg.SetupParams(levels=w.levels, agg=w.agg, overlap=w.overlap, n_test_vectors=w.n_test_vectors,
+                          coarsest_tol=0.1, coarsest_max_iters=32)
+    g = make_gauge(lib, ctx, U, m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=w.levels, agg_size=w.agg, overlap=w.overlap,
+                                                   n_test_vectors=w.n_test_vectors, coarsest_tol=0.1,
+                                                   coarsest_max_iters=32))
+    sp = lib.default_solve_params(precision=precision)
+    xb, ib, st = h.solve(synth.field_to_abi(psi), sp)
+    assert st == lib.OK
+    xb = synth.field_from_abi(xb)
+    hists = [h.residual_history(r) for r in range(3)]
+    exact = amg.SetupParams(levels=w.levels, agg=w.agg, overlap=w.overlap, n_test_vectors=w.n_test_vectors)
+    olevels = None
+    for r in range(3):
+        xo, io, olevels = oracle_solve(U, m0, psi[r], prm, levels=olevels)
+        assert ib[r].converged and ib[r].true_rel_residual <= 1e-10
+        if precision == 0:
+            assert ib[r].iterations == io.iterations, (r, ib[r].iterations, io.iterations)
+            # the residual history follows the GMRES variant's, and that differs from the
+            # exact coarsest solve's by more than the tolerance used here
+            oh = np.array([v for v, _ in io.history])
+            hist, flags = hists[r]
+            assert np.array_equal(flags, np.array([f for _, f in io.history]))
+            assert np.allclose(hist, oh, rtol=1e-6, atol=1e-14)
+            _, ie, _ = oracle_solve(U, m0, psi[r], exact, levels=olevels)
+            he = np.array([v for v, _ in ie.history])
+            nn = min(len(he), len(oh))
+            assert not np.allclose(he[:nn], oh[:nn], rtol=1e-6, atol=1e-14)
+        else:
+            assert abs(ib[r].iterations - io.iterations) <= max(5, io.iterations // 10)
+        assert rel(xb[r], xo) <= bound
+        x1, i1, _ = h.solve(synth.field_to_abi(psi[r:r + 1]), sp)
+        assert i1[0].iterations == ib[r].iterations
+        assert np.array_equal(synth.field_from_abi(x1)[0], xb[r])
+    h.close()
+    g.close()
+
+
+def test_coarsest_gmres_parameter_checks(lib, ctx):
+    U = synth.WORKLOADS["C1"].links()
+    g = make_gauge(lib, ctx, U, 0.1)
+    for kw in (dict(coarsest_tol=1.5), dict(coarsest_tol=-0.1), dict(coarsest_tol=0.1, coarsest_max_iters=0),
+               dict(coarsest_tol=0.1, coarsest_max_iters=33)):
+        with pytest.raises(lib.AmamgError) as e:
+            lib.Hierarchy(g, lib.default_setup_params(**kw))
+        assert e.value.status == lib.STATUS_CODES["INVALID_ARG"], kw
+    g.close()
+
+
 def test_batched_rhs_equal_to_single(lib, ctx):
     w = synth.WORKLOADS["C1"]
     U = w.links()
