@@ -339,6 +339,30 @@ def variants_leg(lib, torch, ctx, groups, nrhs=64):
     return out
 
 
+def flop_summary(w, iterations, s_per_step):
+    """Operation count of one step (setup + the batch's solves) from the geometry model, the
+    rate it implies, and the paper's AM-AMG counts at 256^2 for context (another coarsening,
+    the real K-formulation, other ensembles: not a like-for-like target)."""
+    from paper_2608_03515_amd import flops
+    geo = flops.levels_of(w.L, w.L, w.levels, w.agg, w.overlap)
+    st = flops.setup(geo, w.agg, w.overlap, w.n_test_vectors)
+    sv = [flops.solve(geo, w.agg, w.overlap, it, restart=w.restart) for it in iterations]
+    total = st["total"] + sum(v["total"] for v in sv)
+    mean_solve = sum(v["total"] for v in sv) / len(sv)
+    return {"model": "paper_2608_03515_amd.flops (real operations; algorithmic, setup included)",
+            "setup_gflop": st["total"] / 1e9,
+            "setup_parts_gflop": {k: v / 1e9 for k, v in st.items() if k != "total"},
+            "solve_gflop_per_rhs_mean": mean_solve / 1e9,
+            "gflop_per_solve_setup_per_rhs": st["total"] / 1e9 + mean_solve / 1e9,
+            "gflop_per_solve_setup_shared": st["total"] / len(sv) / 1e9 + mean_solve / 1e9,
+            "flop_per_site_per_iteration": sum(v["per_iteration_per_site"] for v in sv) / len(sv),
+            "achieved_tflops": total / s_per_step / 1e12,
+            "paper_am_amg_256": {"setup_gflop": 1.1, "kflop_per_site_per_iteration_range": [17.4, 17.6],
+                                 "gflop_per_solve_range": [11.1, 1003.5],
+                                 "note": "two-level algebraic AM-AMG, 9-point wirebaskets, beta 2-6, "
+                                         "gaps 0.001-0.1; setup repeated per right-hand side"}}
+
+
 # ------------------------------------------------------------------ profile summaries
 FAMILY_PATTERNS = {"update": "k_lag_update<", "dots": "k_gram<"}
 TRAFFIC_MD = os.path.join(ROOT, "profiles", "gram_schmidt_256x256_64rhs_mixed_traffic.md")
@@ -598,6 +622,7 @@ def main():
     res["mixed"] = summarize(dt, ts, infos, args.nrhs, args.steps)
     res["mixed"]["rel_diff_vs_fp64"] = float((x - x64).norm() / x64.norm())
     log("mixed", json.dumps(res["mixed"]))
+    op_count = flop_summary(w, [i.iterations for i in infos], res["mixed"]["s_per_step"])
     # roofline: the same step on one stream with the dominant family timed by the kernels' own
     # begin/end stamps (with two streams a kernel's duration includes sharing the GPU with the
     # other batch, which says nothing about the kernel)
@@ -681,6 +706,7 @@ def main():
         "serving": serving,
         "multi_lattice": multi,
         "aggregate_sweep": agg,
+        "operation_count": op_count,
         "paper_variants": variants,
         "autotuner": ctx.tuning_entries(),
     }
