@@ -6,17 +6,24 @@ m0 = m_c + gap.
 multi_lattice_critical.json: the same for the 32 lattices of synth.multi_lattice_configs()
 (computed in a process pool).
 
-Run from the repository root:  python tests/golden/make_golden.py [--multi-only]
+c3_solve.json: the oracle's FP64 solve of the 256^2 workload's first right-hand side (the one
+the benchmark's batch starts with): iteration and restart counts, the true relative residual,
+||x||, 64 sampled solution entries and the first 40 residual-history values.
+
+Run from the repository root:
+    python tests/golden/make_golden.py [--multi-only | --c3-solve]
 """
 import os
+import sys
 
 # one BLAS thread per process, set before numpy loads: the multi-lattice pool runs one process per
 # core, and threads inherited by its forked workers would oversubscribe the cores many times over
-for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
-    os.environ.setdefault(_v, "1")
+# (the single-process 256^2 solve keeps the default)
+if "--c3-solve" not in sys.argv:
+    for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ.setdefault(_v, "1")
 
 import json  # noqa: E402
-import sys  # noqa: E402
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
@@ -46,9 +53,37 @@ def multi(workers=8):
         f.write("\n")
 
 
+def c3_solve():
+    import numpy as np
+    from oracle.amg import SetupParams
+    from oracle.solve import solve
+    w = synth.WORKLOADS["C3"]
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "critical_mass.json")) as f:
+        m0 = json.load(f)["C3"] + w.gaps[0]
+    psi = synth.gaussian_rhs(w.L, w.L, w.rhs_seed, nrhs=1)[0]
+    prm = SetupParams(levels=w.levels, agg=w.agg, overlap=w.overlap, n_test_vectors=w.n_test_vectors)
+    x, info, _ = solve(w.links(), m0, psi, prm, restart=w.restart, tol=1e-10)
+    rng = np.random.default_rng(0)
+    sites = sorted(int(s) for s in rng.choice(w.L * w.L, 64, replace=False))
+    xf = x.reshape(-1, 2)
+    out = {"workload": "C3", "m0": m0, "rhs_seed": w.rhs_seed, "iterations": info.iterations,
+           "restarts": info.restarts, "converged": bool(info.converged),
+           "true_rel_residual": float(info.true_rel_residual), "x_norm": float(np.linalg.norm(x)),
+           "samples": [[s, q, float(xf[s, q].real), float(xf[s, q].imag)] for s in sites for q in range(2)],
+           "history": [[float(v), bool(t)] for v, t in info.history[:40]]}
+    print("C3", info.iterations, info.restarts, info.true_rel_residual, flush=True)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c3_solve.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+
+
 def main():
     if "--multi-only" in sys.argv:
         multi()
+        return
+    if "--c3-solve" in sys.argv:
+        c3_solve()
         return
     out = {}
     for name in ("C2", "C3", "C4"):

@@ -613,3 +613,55 @@ def test_graph_replayed_cycles_equal_eager(lib):
     h.close()
     g.close()
     ctx.close()
+
+
+def test_c3_full_size_solve_in_bench_configuration(lib):
+    """The 256^2 workload in the benchmark's launch configuration: 64 right-hand sides in two
+    stream groups on a non-null stream, FP64 and mixed.  Right-hand side 0 against the oracle's
+    stored FP64 solve (tests/golden/c3_solve.json, written by make_golden.py from the oracle
+    alone): iteration and restart counts exact, sampled solution entries and the first residual
+    history values within the FP64 bars.  Every right-hand side: the true residual recomputed on
+    the CPU with the oracle's operator <= 1e-10, and mixed within 1e-9 of FP64."""
+    import json
+    import os
+    import torch
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c3_solve.json")) as fh:
+        gold = json.load(fh)
+    w = synth.WORKLOADS["C3"]
+    m0 = gold["m0"]
+    assert m0 == synth.critical_masses()["C3"] + w.gaps[0]
+    U = w.links()
+    psi = synth.gaussian_rhs(w.L, w.L, w.rhs_seed, nrhs=64)
+    stream = torch.cuda.Stream()
+    ctx = lib.Context(0, stream.cuda_stream)
+    g = make_gauge(lib, ctx, U, m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=w.levels, agg_size=w.agg, overlap=w.overlap,
+                                                   n_test_vectors=w.n_test_vectors))
+    out = {}
+    for prec in (lib.FP64, lib.MIXED_FP32):
+        say("C3 full size", prec)
+        x, infos, st = h.solve(synth.field_to_abi(psi), lib.default_solve_params(precision=prec, groups=2))
+        assert st == lib.OK
+        out[prec] = (synth.field_from_abi(x), infos, h.residual_history(0))
+    h.close()
+    g.close()
+    ctx.close()
+    x64, i64, (hist, flags) = out[lib.FP64]
+    assert i64[0].iterations == gold["iterations"] and i64[0].restarts == gold["restarts"]
+    xf = x64[0].reshape(-1, 2)
+    ref = np.array([complex(re, im) for _, _, re, im in gold["samples"]])
+    got = np.array([xf[s, q] for s, q, _, _ in gold["samples"]])
+    assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max()
+    assert abs(np.linalg.norm(x64[0]) - gold["x_norm"]) <= 1e-9 * gold["x_norm"]
+    gh = np.array([v for v, _ in gold["history"]])
+    assert np.array_equal(flags[:len(gh)], np.array([t for _, t in gold["history"]]))
+    assert np.allclose(hist[:len(gh)], gh, rtol=1e-6, atol=1e-14)
+    D = dirac_matrix(U, m0)
+    x32, i32, _ = out[lib.MIXED_FP32]
+    for r in range(64):
+        b = psi[r].reshape(-1)
+        for x, info in ((x64[r], i64[r]), (x32[r], i32[r])):
+            res = np.linalg.norm(b - D @ x.reshape(-1)) / np.linalg.norm(b)
+            assert info.converged and res <= 1e-10 * (1 + 1e-6), (r, res)
+            assert abs(res - info.true_rel_residual) <= 1e-2 * res      # rounding of b - D x
+        assert rel(x32[r], x64[r]) <= 1e-9
