@@ -12,7 +12,8 @@
  *     normalisation, restriction P^H, Galerkin coarse operator P^H A P.
  *   - Solve: FGMRES right-preconditioned by a V-cycle of the two-level scheme algorithm with
  *     0 pre- and 2 post-smoothing sweeps of a block smoother (Numerical Results section),
- *     relative tolerance 1e-10; the coarsest level is solved directly.
+ *     relative tolerance 1e-10; the coarsest level is solved directly, or, as in the paper's
+ *     experiments (Numerical Results), by unpreconditioned GMRES to a relative tolerance.
  *
  * Conventions
  *   Layout at the boundary (host and device pointers alike):
@@ -102,7 +103,7 @@ typedef struct {
   int32_t iterations;          /* Arnoldi steps                                              */
   int32_t restarts;            /* completed cycles that did not converge                     */
   int32_t converged;           /* 1 if the true relative residual met rel_tol                */
-  int32_t reserved;
+  int32_t reserved;            /* padding, written as 0                                      */
   double true_rel_residual;    /* ||psi - D x|| / ||psi|| in FP64 at the end                 */
 } amamg_solve_info;
 
