@@ -69,6 +69,25 @@ def run_steps(lib, torch, ctx, h, b, x, nrhs, precision, steps, warmup, timer=No
     return dt, t_setup, infos, timed
 
 
+def copy_bandwidth(torch, gib=2.0, reps=10):
+    """Device bandwidth of a plain elementwise kernel (y = -x, FP64, gib GiB each way), the
+    practical ceiling the roofline fraction is read against beside the 8 TB/s data-sheet peak."""
+    n = int(gib * 2 ** 30 / 8)
+    a = torch.empty(n, dtype=torch.float64, device="cuda").normal_()
+    y = torch.empty_like(a)
+    torch.neg(a, out=y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        torch.neg(a, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, y
+    return gbs
+
+
 def dominant_family(lib, torch, ctx, h, b, x, nrhs, precision, groups=1):
     """One instrumented step with every family timed; returns (family, {family: ms})."""
     ctx.kernel_timer(FAMILIES)
@@ -641,6 +660,9 @@ def main():
                 "family_ms_instrumented_step": {k: round(v, 3) for k, v in fam_ms.items()}}
     roofline["frac"] = roofline["achieved"] / HBM_PEAK_GBS
     roofline["timed_pass"] = "mixed_one_stream (same workload and steps, one stream)"
+    copy_gbs = copy_bandwidth(torch)
+    roofline["measured_copy_GBs"] = copy_gbs
+    roofline["frac_of_measured_copy"] = roofline["achieved"] / copy_gbs
     if not args.no_single:
         h1 = lib.Hierarchy(g, lib.default_setup_params(levels=w.levels, agg_size=w.agg, overlap=w.overlap,
                                                         n_test_vectors=w.n_test_vectors))
