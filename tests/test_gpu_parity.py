@@ -587,17 +587,27 @@ def test_graph_replayed_cycles_equal_eager(lib):
     """Restart cycles captured into a HIP graph and replayed (once per cycle, with the host's
     state reads and the stream groups' own work between replays) give bitwise the eager
     launches' solutions, iteration counts and residual histories, in FP64 and mixed precision,
-    on one stream and on two stream groups, and again on a second solve with a new capture."""
+    on one stream and on two stream groups, and again on a second solve that replays the kept
+    graph; with the exact coarsest solve and with the coarsest-level GMRES variant."""
     w = synth.WORKLOADS["C2"]
     m0 = synth.critical_masses()["C2"] + w.gaps[1]
     psi = synth.field_to_abi(synth.gaussian_rhs(w.L, w.L, 97, nrhs=6))
     stream = __import__("torch").cuda.Stream()
     ctx = lib.Context(0, stream.cuda_stream)         # graphs need a capturable (non-null) stream
     g = make_gauge(lib, ctx, w.links(), m0)
-    h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=4, overlap=1, n_test_vectors=8))
+    for coarsest_tol in (0.0, 0.1):
+        h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=4, overlap=1, n_test_vectors=8,
+                                                       coarsest_tol=coarsest_tol))
+        graph_runs(lib, h, psi, coarsest_tol)
+        h.close()
+    g.close()
+    ctx.close()
+
+
+def graph_runs(lib, h, psi, coarsest_tol):
     for prec in (lib.FP64, lib.MIXED_FP32):
         for groups in (1, 2):
-            say("graphs", prec, groups)
+            say("graphs", prec, groups, "coarsest_tol", coarsest_tol)
             runs = []
             for graphs in (0, 1, 1):
                 sp = lib.default_solve_params(precision=prec, groups=groups, graphs=graphs)
@@ -610,9 +620,6 @@ def test_graph_replayed_cycles_equal_eager(lib):
                 for (v, f), (v0, f0) in zip(hist, runs[0][2]):
                     assert np.array_equal(v, v0) and np.array_equal(f, f0)
             assert max(r for _, r in runs[0][1]) >= 1          # several cycles: several replays
-    h.close()
-    g.close()
-    ctx.close()
 
 
 def test_c3_full_size_solve_in_bench_configuration(lib):

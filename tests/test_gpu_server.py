@@ -202,3 +202,32 @@ def test_one_instance_rebound_across_lattice_sizes(lib, graphs):
             xo, io, levels = oracle_solve(U, m0, psi[r], prm, levels=levels)
             assert rel(x[r], xo) <= 1e-9
     srv.close()
+
+
+def test_server_coarsest_gmres_requests(lib):
+    """Requests whose setup asks for the paper's coarsest-level GMRES (to 0.1) get their own
+    cached hierarchy beside the exact-coarsest one on the same gauge field and mass, and match
+    the oracle's variant."""
+    U = synth.WORKLOADS["C1"].links()
+    srv = make_server(lib)
+    gid = srv.add_gauge(synth.links_to_abi(U))
+    psi = synth.gaussian_rhs(16, 16, 808, nrhs=2)
+    ids = []
+    for tol in (0.1, 0.0, 0.1):
+        sp = lib.default_setup_params(**SETUP, coarsest_tol=tol)
+        ids.append(srv.submit(gid, 0.1, synth.field_to_abi(psi), sp))
+    assert srv.wait(120)
+    done = {info.id: (info, synth.field_from_abi(x)) for info, x in srv.poll()}
+    assert srv.stats().setups == 2
+    srv.close()
+    for k, tol in enumerate((0.1, 0.0, 0.1)):
+        info, x = done[ids[k]]
+        assert info.status == lib.OK and info.converged
+        prm = amg.SetupParams(levels=2, agg=4, overlap=1, n_test_vectors=4, coarsest_tol=tol)
+        its, levels = [], None
+        for r in range(2):
+            xo, io, levels = oracle_solve(U, 0.1, psi[r], prm, levels=levels)
+            assert rel(x[r], xo) <= 1e-9
+            its.append(io.iterations)
+        assert info.iterations == max(its)
+    assert np.array_equal(done[ids[0]][1], done[ids[2]][1])
