@@ -188,9 +188,9 @@ amamg_status amamg_kernel_timer_read(const amamg_context *ctx, int32_t family, i
 
 /* ---- launch-shape autotuning ----------------------------------------------------------
  * Some kernels take a launch shape that does not change their arithmetic: the fine smoother's
- * tile width (16, 32 or 64 sites) and, for the FP32 block smoother on levels with 8 x 8 blocks,
- * colour-pair launches with 1, 2 or 4 right-hand sides per wave or one launch per 2 x 2 colour
- * block with 1 or 2 (reported as -1, -2).  Results are bitwise the same for every choice.  AMAMG_TUNE_AUTO (default): the first solve with a new (grid, block size, precision,
+ * tile width (16, 32 or 64 sites) and, for the FP32 block smoother on levels with 8 x 8 blocks
+ * (matrix cores), the stencil offsets per load batch (8, 12 or 24).  Results are bitwise the
+ * same for every choice.  AMAMG_TUNE_AUTO (default): the first solve with a new (grid, block size, precision,
  * batch size) times the candidates on its workspace vectors before any right-hand side is
  * admitted and keeps the fastest in the context; AMAMG_TUNE_OFF: fixed defaults;
  * AMAMG_TUNE_FORCE: candidate number `force` of each tunable (clamped), for tests. */
@@ -247,6 +247,15 @@ amamg_status amamg_get_coarse_operator(const amamg_hierarchy *h, int32_t level, 
  * device buffers.  AMAMG_ERR_INVALID_ARG for the coarsest level or a bad direction. */
 amamg_status amamg_apply_transfer(amamg_hierarchy *h, int32_t level, int32_t precision,
                                   int32_t direction, int32_t nrhs, const double *in, double *out);
+/* Post-smoothing sweeps of level `level` (not the coarsest) with the kernels the V-cycle of the
+ * given precision runs (Numerical Results: block smoother; point-block multicolour Gauss-Seidel,
+ * the fine level red-black, coarse levels 16 colours in the sweep order), in place:
+ * x <- sweeps of x_n += A_nn^{-1} (f - A x)_n.  f, x double [nrhs][n_level][2]; x is rounded
+ * to the precision's type on entry, f too below the fine level (where the V-cycle's right-hand
+ * side is the FP64 Krylov vector).  Default launch shapes (the tuner is not consulted).
+ * Synchronous; allocates its device buffers.  sweeps in [1, 16]. */
+amamg_status amamg_apply_smoother(amamg_hierarchy *h, int32_t level, int32_t precision, int32_t nrhs,
+                                  int32_t sweeps, const double *f, double *x);
 /* Smoothed test vectors of level `level`: double [n_test_vectors][lt*lx*b][2]. */
 amamg_status amamg_get_test_vectors(const amamg_hierarchy *h, int32_t level, double *out);
 

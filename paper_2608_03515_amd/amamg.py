@@ -35,7 +35,7 @@ EXPORTED = ["amamg_default_setup_params", "amamg_default_solve_params", "amamg_c
             "amamg_residual_history", "amamg_apply_dirac", "amamg_apply_dirac_device",
             "amamg_level_info",
             "amamg_get_aggregates", "amamg_get_prolongator", "amamg_get_coarse_operator",
-            "amamg_get_test_vectors", "amamg_apply_transfer", "amamg_context_set_tuning",
+            "amamg_get_test_vectors", "amamg_apply_transfer", "amamg_apply_smoother", "amamg_context_set_tuning",
             "amamg_tuning_entries", "amamg_kernel_timer", "amamg_kernel_timer_read",
             "amamg_server_default_params", "amamg_server_create", "amamg_server_destroy",
             "amamg_server_add_gauge", "amamg_server_submit", "amamg_server_poll", "amamg_server_wait",
@@ -119,6 +119,7 @@ _sig = {
     "amamg_get_coarse_operator": (C.c_int, [_vp, C.c_int32, _vp]),
     "amamg_get_test_vectors": (C.c_int, [_vp, C.c_int32, _vp]),
     "amamg_apply_transfer": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp, _vp]),
+    "amamg_apply_smoother": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp, _vp]),
     "amamg_context_set_tuning": (C.c_int, [_vp, C.c_int32, C.c_int32]),
     "amamg_tuning_entries": (C.c_int, [_vp, _vp, C.c_int32, _P(C.c_int32)]),
     "amamg_kernel_timer": (C.c_int, [_vp, C.c_uint32]),
@@ -336,6 +337,21 @@ class Hierarchy:
             out = np.zeros((lt * lx, 25, b, b, 2))
         self.ctx.check(_lib.amamg_get_coarse_operator(self.h, level, _ptr(out)))
         return out[..., 0] + 1j * out[..., 1]
+
+    def smooth(self, level: int, f: np.ndarray, x: np.ndarray, sweeps: int = 1, precision: int = 0) -> np.ndarray:
+        """`sweeps` post-smoothing sweeps of level `level` on complex [nrhs][n_level] vectors with
+        the kernels of the given precision's V-cycle; returns the new x."""
+        lt, lx, b = self.level_info(level)
+        n = lt * lx * b
+        f = np.asarray(f, dtype=complex)
+        x = np.asarray(x, dtype=complex)
+        nrhs = f.shape[0]
+        if f.shape != (nrhs, n) or x.shape != (nrhs, n):
+            raise ValueError("vector shape does not match the level")
+        fs = np.ascontiguousarray(np.stack([f.real, f.imag], axis=-1))
+        xs = np.ascontiguousarray(np.stack([x.real, x.imag], axis=-1))
+        self.ctx.check(_lib.amamg_apply_smoother(self.h, level, precision, nrhs, sweeps, _ptr(fs), _ptr(xs)))
+        return xs[..., 0] + 1j * xs[..., 1]
 
     def transfer(self, level: int, vecs: np.ndarray, direction: int, precision: int = 0) -> np.ndarray:
         """direction 0: P^H vecs (vecs complex [nrhs][n_level]); 1: P vecs (vecs complex

@@ -9,6 +9,8 @@
 // LJ lanes per row; lane (i, jl) handles columns jl, jl + LJ, ...  With B*B <= 64 one wave
 // holds 64 / (B*B) nodes and reads whole B x B blocks per offset in one coalesced access;
 // otherwise one node per wave.  Row sums are finished with xor shuffles inside the LJ lanes.
+#include <type_traits>
+
 #include "launch.hpp"
 
 namespace amamg {
@@ -226,198 +228,141 @@ __global__ __launch_bounds__(256) void k_stencil_gs_pair(const M* __restrict__ A
   if (live && jl == 0) xr[int64_t(t * Lx + xc) * B + i] = cconv<Vx>(out);
 }
 
-// k_stencil_gs_pair for B = 8 (one node per wave, lane (i, j) = row i, column j) over RB
-// right-hand sides per wave: the wave loads both nodes' 24 neighbour blocks and inverse diagonal
-// blocks once into registers and runs its right-hand sides through them, so the operator is read
-// once per RB right-hand sides.  Per right-hand side all neighbour values of both nodes are
-// loaded before the first node is written (the second node's only coupling to the first is the
-// partner at (0, -1), which comes from the first node's new value); the arithmetic and its order
-// are those of k_stencil_gs_pair, so the results are bitwise the same.
-template <int RB, typename R, typename M, typename Vx>
-__global__ __launch_bounds__(256) void k_stencil_gs_pair_mr(const M* __restrict__ A,
-                                                            const M* __restrict__ Dinv, Vx* x,
-                                                            const Vx* __restrict__ f, int Lt, int Lx,
-                                                            int c0, int nrhs, int64_t stride,
-                                                            const RhsState* __restrict__ st) {
-  constexpr int B = 8, NB = 24;
-  using C = cplx<R>;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int i = lane >> 3, jl = lane & 7;
-  const int qx = Lx >> 2, ncn = (Lt >> 2) * qx;
-  const int k = blockIdx.x * 4 + wv;
-  if (k >= ncn) return;                       // whole waves; the kernel has no block barrier
-  const int colour = c0 + 1;
-  const int t = 4 * (k / qx) + (colour >> 2), xc = 4 * (k % qx) + (colour & 3);   // xc >= 1
-  const int n1 = t * Lx + xc - 1, n2 = t * Lx + xc;
-  int m1[NB], m2[NB];
-  C a1[NB], a2[NB];
-  {
-    int q = 0;
-#pragma unroll
-    for (int dt = -2; dt <= 2; ++dt) {
-      const int tt = wrap1(t + dt, Lt) * Lx;
-#pragma unroll
-      for (int dx = -2; dx <= 2; ++dx) {
-        if (dt == 0 && dx == 0) continue;
-        const int d = (dt + 2) * 5 + (dx + 2);
-        m1[q] = tt + wrap1(xc - 1 + dx, Lx);
-        m2[q] = tt + wrap1(xc + dx, Lx);
-        a1[q] = cconv<C>(A[(int64_t(n1) * 25 + d) * B * B + i * B + jl]);
-        a2[q] = cconv<C>(A[(int64_t(n2) * 25 + d) * B * B + i * B + jl]);
-        ++q;
-      }
-    }
-  }
-  const C d1 = cconv<C>(Dinv[int64_t(n1) * B * B + i * B + jl]);
-  const C d2 = cconv<C>(Dinv[int64_t(n2) * B * B + i * B + jl]);
-  constexpr int PARTNER = 2 * 5 + 1;          // index q of offset (0, -1): rows dt = -2, -1 (q 0..9), then dx = -2 (q 10)
-  const int r0 = blockIdx.y * RB;
-  for (int rr = 0; rr < RB; ++rr) {
-    const int r = r0 + rr;
-    if (r >= nrhs) break;
-    if (st && !st[r].active) continue;
-    Vx* xr = x + r * stride;
-    C v1[NB], v2[NB];
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      v1[q] = cconv<C>(xr[int64_t(m1[q]) * B + jl]);
-      if (q != PARTNER) v2[q] = cconv<C>(xr[int64_t(m2[q]) * B + jl]);
-    }
-    const C f1 = f ? cconv<C>(f[r * stride + int64_t(n1) * B + i]) : czero<R>();
-    const C f2 = f ? cconv<C>(f[r * stride + int64_t(n2) * B + i]) : czero<R>();
-    // first node
-    C acc = czero<R>();
-#pragma unroll
-    for (int q = 0; q < NB; ++q) acc = cfma(a1[q], v1[q], acc);
-    acc.x = group_sum<8>(acc.x);
-    acc.y = group_sum<8>(acc.y);
-    C res = mk<R>(-acc.x, -acc.y);
-    if (f) res = cadd(res, f1);
-    C out = cfma(d1, mk<R>(__shfl(res.x, jl * 8), __shfl(res.y, jl * 8)), czero<R>());
-    out.x = group_sum<8>(out.x);
-    out.y = group_sum<8>(out.y);
-    if (jl == 0) xr[int64_t(n1) * B + i] = cconv<Vx>(out);
-    // the partner's new value in the storage type, as the two-launch sequence reads it
-    v2[PARTNER] = cconv<C>(cconv<Vx>(mk<R>(__shfl(out.x, jl * 8), __shfl(out.y, jl * 8))));
-    // second node
-    acc = czero<R>();
-#pragma unroll
-    for (int q = 0; q < NB; ++q) acc = cfma(a2[q], v2[q], acc);
-    acc.x = group_sum<8>(acc.x);
-    acc.y = group_sum<8>(acc.y);
-    res = mk<R>(-acc.x, -acc.y);
-    if (f) res = cadd(res, f2);
-    out = cfma(d2, mk<R>(__shfl(res.x, jl * 8), __shfl(res.y, jl * 8)), czero<R>());
-    out.x = group_sum<8>(out.x);
-    out.y = group_sum<8>(out.y);
-    if (jl == 0) xr[int64_t(n2) * B + i] = cconv<Vx>(out);
-  }
+// One colour block qb of the coarse sweep for FP32 8 x 8 blocks on matrix cores.  A workgroup
+// takes one 2 x 2 group of the block and a tile of 16 right-hand sides; wave v owns node v of
+// the group in sweep order (I0, J0), (I0, J0 + 1), (I0 + 1, J0),
+// (I0 + 1, J0 + 1).  An 8 x 8 complex block product for 16 right-hand sides is one real 16 x 16
+// product, [Re y; Im y] = [[Re A, -Im A], [Im A, Re A]] [Re x; Im x], in four
+// v_mfma_f32_16x16x4f32 steps (lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+// D[4 (l / 16) + i][l % 16]).  Phase 1, all waves at once: a wave sums its node's neighbour
+// blocks whose values this launch does not change (all but the group's earlier nodes), even and
+// odd stencil offsets in two accumulators added at the end.  Phase 2, node by node: the owning
+// wave adds the earlier nodes' new values (stencil order) from LDS, forms f - sum and applies
+// the inverse diagonal block; the new values stay in LDS for the later nodes and are stored at
+// the end.  The groups of a colour block do not couple, and every value read from memory is
+// read before any store of the launch.  A right-hand side's arithmetic does not depend on the
+// other columns of its tile, so results are the same in every batch and for every NB.
+typedef float gs_mf4 __attribute__((ext_vector_type(4)));
+__device__ inline gs_mf4 gs_mfma(float a, float b, gs_mf4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// One colour block qb of the coarse sweep (coarse_colour(4 qb) .. coarse_colour(4 qb + 3)) for
-// B = 8 in one launch: the block's nodes form 2 x 2 groups (rows I0, I0 + 1, columns J0, J0 + 1)
-// that do not couple with each other, and the four updates of a group run in colour order.  Two
-// waves per group: the lower wave updates (I0, J0) then (I0, J0 + 1) exactly as
-// k_stencil_gs_pair_mr does, and leaves their new values (in the storage type, as a launch per
-// colour pair would read them) in LDS; the upper wave then updates (I0 + 1, J0) and (I0 + 1,
-// J0 + 1) with those values for its in-group neighbours above.  Per right-hand side the upper
-// wave runs one phase behind the lower one; every thread passes the same RB + 1 barriers.
-// The results are bitwise those of the two colour-pair launches.
-template <int RB, typename R, typename M, typename Vx>
-__global__ __launch_bounds__(256) void k_stencil_gs_quad_mr(const M* __restrict__ A,
-                                                            const M* __restrict__ Dinv, Vx* x,
-                                                            const Vx* __restrict__ f, int Lt, int Lx,
-                                                            int qb, int nrhs, int64_t stride,
-                                                            const RhsState* __restrict__ st) {
-  constexpr int B = 8, NB = 24;
-  // neighbour slots (loop order dt, dx = -2..2 without (0, 0)) of the in-group offsets
-  constexpr int UPL = 6, UP = 7, UPR = 8, LEFT = 11;   // (-1,-1), (-1,0), (-1,+1), (0,-1)
-  using C = cplx<R>;
-  __shared__ C lower[2][RB][2][B];                    // [group slot][rhs][node][row]
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int i = lane >> 3, jl = lane & 7;
-  const int gs = wv >> 1, hi = wv & 1;
-  const int qx = Lx >> 2, ngr = (Lt >> 2) * qx;
-  const int k = blockIdx.x * 2 + gs;
-  const bool valid = k < ngr;
-  const int kk = valid ? k : 0;
-  const int t = 4 * (kk / qx) + 2 * (qb >> 1) + hi, xc = 4 * (kk % qx) + 2 * (qb & 1);
-  const int n1 = t * Lx + xc, n2 = n1 + 1;
-  int m1[NB], m2[NB];
-  C a1[NB], a2[NB];
-  {
-    int q = 0;
+// acc += block (lane's two complex entries aL = A[l % 8][l / 16], aH = A[l % 8][4 + l / 16]) times
+// the right-hand-side values (bL, bH: dofs l / 16 and 4 + l / 16 of column l % 16)
+__device__ inline gs_mf4 gs_block_mfma(float2 aL, float2 aH, float2 bL, float2 bH, bool im_row, gs_mf4 acc) {
+  acc = gs_mfma(im_row ? aL.y : aL.x, bL.x, acc);
+  acc = gs_mfma(im_row ? aH.y : aH.x, bH.x, acc);
+  acc = gs_mfma(im_row ? aL.x : -aL.y, bL.y, acc);
+  acc = gs_mfma(im_row ? aH.x : -aH.y, bH.y, acc);
+  return acc;
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_stencil_gs_quad_mfma(const float2* __restrict__ A,
+                                                                  const float2* __restrict__ Dinv, float2* x,
+                                                                  const float2* __restrict__ f, int Lt, int Lx,
+                                                                  int qb, int nrhs, int64_t stride,
+                                                                  const RhsState* __restrict__ st) {
+  static_assert(24 % NB == 0, "batches must cover the 24 offsets");
+  __shared__ float res[4][16][17];        // [node][row][rhs]: f - sum
+  __shared__ float nx[4][16][17];         // new values: rows 0..7 Re, 8..15 Im
+  const int lane = threadIdx.x & 63, v = threadIdx.x >> 6;
+  const int rl = lane & 15, kq = lane >> 4, row8 = lane & 7;
+  const bool im_row = (lane >> 3) & 1;
+  const int qx = Lx >> 2;
+  const int grp = blockIdx.x;
+  const int t0 = 4 * (grp / qx) + 2 * (qb >> 1), x0 = 4 * (grp % qx) + 2 * (qb & 1);
+  const int tn = t0 + (v >> 1), xn = x0 + (v & 1), n = tn * Lx + xn;
+  const int rhs = blockIdx.y * 16 + rl;
+  const bool live = rhs < nrhs && (!st || st[rhs].active);
+  const float2* xr = x + int64_t(live ? rhs : 0) * stride;
+  const float2* Ab = A + int64_t(n) * 25 * 64 + row8 * 8 + kq;
+  const float2 z2 = make_float2(0.f, 0.f);
+  // phase 1, batches of NB offsets (stencil order without the centre): all loads of a batch are
+  // issued before its products.  An earlier node's block gets zero right-hand-side values,
+  // which leaves the sums unchanged bit for bit; the batch size does not change them either.
+  gs_mf4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int dt = -2; dt <= 2; ++dt) {
-      const int tt = wrap1(t + dt, Lt) * Lx;
+  for (int bt = 0; bt < 24 / NB; ++bt) {
+    float2 aL[NB], aH[NB], bL[NB], bH[NB];
 #pragma unroll
-      for (int dx = -2; dx <= 2; ++dx) {
-        if (dt == 0 && dx == 0) continue;
-        const int d = (dt + 2) * 5 + (dx + 2);
-        m1[q] = tt + wrap1(xc + dx, Lx);
-        m2[q] = tt + wrap1(xc + 1 + dx, Lx);
-        a1[q] = cconv<C>(A[(int64_t(n1) * 25 + d) * B * B + i * B + jl]);
-        a2[q] = cconv<C>(A[(int64_t(n2) * 25 + d) * B * B + i * B + jl]);
-        ++q;
-      }
+    for (int j = 0; j < NB; ++j) {
+      const int q = NB * bt + j, d = q < 12 ? q : q + 1;
+      const int dt = d / 5 - 2, dx = d % 5 - 2;
+      const int ga = (v >> 1) + dt, gb = (v & 1) + dx;
+      const bool earlier = ga >= 0 && ga <= 1 && gb >= 0 && gb <= 1 && 2 * ga + gb < v;
+      const int m = wrap1(tn + dt, Lt) * Lx + wrap1(xn + dx, Lx);
+      aL[j] = Ab[d * 64];
+      aH[j] = Ab[d * 64 + 4];
+      bL[j] = xr[int64_t(m) * 8 + kq];
+      bH[j] = xr[int64_t(m) * 8 + 4 + kq];
+      if (earlier || !live) bL[j] = bH[j] = z2;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int q = NB * bt + j, d = q < 12 ? q : q + 1;
+      if (d & 1) acc1 = gs_block_mfma(aL[j], aH[j], bL[j], bH[j], im_row, acc1);
+      else acc0 = gs_block_mfma(aL[j], aH[j], bL[j], bH[j], im_row, acc0);
     }
   }
-  const C d1 = cconv<C>(Dinv[int64_t(n1) * B * B + i * B + jl]);
-  const C d2 = cconv<C>(Dinv[int64_t(n2) * B * B + i * B + jl]);
-  const int r0 = blockIdx.y * RB;
-  for (int ph = 0; ph <= RB; ++ph) {
-    const int rr = ph - hi;
-    const int r = r0 + rr;
-    const bool work = valid && rr >= 0 && rr < RB && r < nrhs && (!st || st[r].active);
-    if (work) {
-      Vx* xr = x + r * stride;
-      C v1[NB], v2[NB];
+  gs_mf4 tot = acc0 + acc1;
+  // the earlier nodes' blocks (stencil offsets 6, 7, 8, 11 are (-1,-1), (-1,0), (-1,+1), (0,-1)),
+  // the inverse diagonal block and this lane's f values (rows 4 kq + i)
+  constexpr int kEarly[4] = {6, 7, 8, 11};
+  float2 eL[4], eH[4];
+  int ep[4];
+  bool eu[4];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const bool up1 = hi && (q == UP || q == UPR);
-        const bool up2 = hi && (q == UPL || q == UP);
-        if (!up1) v1[q] = cconv<C>(xr[int64_t(m1[q]) * B + jl]);
-        if (!up2 && q != LEFT) v2[q] = cconv<C>(xr[int64_t(m2[q]) * B + jl]);
-      }
-      if (hi) {
-        v1[UP] = lower[gs][rr][0][jl];
-        v1[UPR] = lower[gs][rr][1][jl];
-        v2[UPL] = lower[gs][rr][0][jl];
-        v2[UP] = lower[gs][rr][1][jl];
-      }
-      const C f1 = f ? cconv<C>(f[r * stride + int64_t(n1) * B + i]) : czero<R>();
-      const C f2 = f ? cconv<C>(f[r * stride + int64_t(n2) * B + i]) : czero<R>();
-      C acc = czero<R>();
+  for (int k = 0; k < 4; ++k) {
+    const int d = kEarly[k];
+    const int dt = d / 5 - 2, dx = d % 5 - 2;
+    const int ga = (v >> 1) + dt, gb = (v & 1) + dx;
+    eu[k] = ga >= 0 && ga <= 1 && gb >= 0 && gb <= 1 && 2 * ga + gb < v;
+    ep[k] = eu[k] ? 2 * ga + gb : 0;
+    eL[k] = eu[k] ? Ab[d * 64] : z2;
+    eH[k] = eu[k] ? Ab[d * 64 + 4] : z2;
+  }
+  const float2* Db = Dinv + int64_t(n) * 64 + row8 * 8 + kq;
+  const float2 dL = Db[0], dH = Db[4];
+  float fv[4];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) acc = cfma(a1[q], v1[q], acc);
-      acc.x = group_sum<8>(acc.x);
-      acc.y = group_sum<8>(acc.y);
-      C res = mk<R>(-acc.x, -acc.y);
-      if (f) res = cadd(res, f1);
-      C out = cfma(d1, mk<R>(__shfl(res.x, jl * 8), __shfl(res.y, jl * 8)), czero<R>());
-      out.x = group_sum<8>(out.x);
-      out.y = group_sum<8>(out.y);
-      if (jl == 0) {
-        xr[int64_t(n1) * B + i] = cconv<Vx>(out);
-        if (!hi) lower[gs][rr][0][i] = cconv<C>(cconv<Vx>(out));
-      }
-      v2[LEFT] = cconv<C>(cconv<Vx>(mk<R>(__shfl(out.x, jl * 8), __shfl(out.y, jl * 8))));
-      acc = czero<R>();
+  for (int i = 0; i < 4; ++i) {
+    const float2 q = f && live ? f[int64_t(rhs) * stride + int64_t(n) * 8 + 4 * (kq & 1) + i] : z2;
+    fv[i] = kq < 2 ? q.x : q.y;
+  }
+  // phase 2
+  for (int s = 0; s < 4; ++s) {
+    __syncthreads();                                   // new values of the nodes before s
+    if (v == s) {
 #pragma unroll
-      for (int q = 0; q < NB; ++q) acc = cfma(a2[q], v2[q], acc);
-      acc.x = group_sum<8>(acc.x);
-      acc.y = group_sum<8>(acc.y);
-      res = mk<R>(-acc.x, -acc.y);
-      if (f) res = cadd(res, f2);
-      out = cfma(d2, mk<R>(__shfl(res.x, jl * 8), __shfl(res.y, jl * 8)), czero<R>());
-      out.x = group_sum<8>(out.x);
-      out.y = group_sum<8>(out.y);
-      if (jl == 0) {
-        xr[int64_t(n2) * B + i] = cconv<Vx>(out);
-        if (!hi) lower[gs][rr][1][i] = cconv<C>(cconv<Vx>(out));
+      for (int k = 0; k < 4; ++k) {
+        if (!eu[k]) continue;
+        const float (*src)[17] = nx[ep[k]];
+        const float2 bL = make_float2(src[kq][rl], src[8 + kq][rl]);
+        const float2 bH = make_float2(src[4 + kq][rl], src[12 + kq][rl]);
+        tot = gs_block_mfma(eL[k], eH[k], bL, bH, im_row, tot);
       }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) res[s][4 * kq + i][rl] = fv[i] - tot[i];
     }
     __syncthreads();
+    if (v == s) {
+      const float (*src)[17] = res[s];
+      const float2 bL = make_float2(src[kq][rl], src[8 + kq][rl]);
+      const float2 bH = make_float2(src[4 + kq][rl], src[12 + kq][rl]);
+      const gs_mf4 o = gs_block_mfma(dL, dH, bL, bH, im_row, gs_mf4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+      for (int i = 0; i < 4; ++i) nx[s][4 * kq + i][rl] = o[i];
+    }
+  }
+  __syncthreads();
+  if (live) {
+    float2* xw = x + int64_t(rhs) * stride + int64_t(n) * 8;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int dof = 2 * kq + j;
+      xw[dof] = make_float2(nx[v][dof][rl], nx[v][dof + 8][rl]);
+    }
   }
 }
 
@@ -737,56 +682,37 @@ static void gs_b(hipStream_t s, const void* A, const void* D, void* x, const voi
                      (const V*)f, Lt, Lx, colour, stride, st);
 }
 
-// rb = right-hand sides per wave of the paired sweep for FP32 8 x 8 blocks (1, 2 or 4; 0 = the
-// default 2; bitwise the same results for every choice), measured at 32 x 32 nodes, 64 rhs: 11.0
-// us per launch with 2 against 14.7 with 1, 11.6 with 4, 19.3 with 8.  FP64 would not fit the
-// registers; other block sizes take one right-hand side per wave.
 template <int B, typename R, typename M, typename V>
 static void gs_pair_b(hipStream_t s, const void* A, const void* D, void* x, const void* f, int Lt, int Lx,
-                      int c0, int nrhs, int64_t stride, const RhsState* st, int rb) {
+                      int c0, int nrhs, int64_t stride, const RhsState* st) {
   const int ncn = (Lt / 4) * (Lx / 4);
-  if constexpr (B == 8 && sizeof(R) == 4) {
-    if (rb == 0) rb = 2;
-    if (rb > 1 && nrhs >= rb) {
-      const dim3 g(unsigned((ncn + 3) / 4), unsigned((nrhs + rb - 1) / rb));
-      if (rb == 4)
-        AMAMG_LAUNCH((k_stencil_gs_pair_mr<4, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
-                     (const V*)f, Lt, Lx, c0, nrhs, stride, st);
-      else
-        AMAMG_LAUNCH((k_stencil_gs_pair_mr<2, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
-                     (const V*)f, Lt, Lx, c0, nrhs, stride, st);
-      return;
-    }
-  }
   dim3 g(unsigned((ncn + Lanes<B>::NPB - 1) / Lanes<B>::NPB), unsigned(nrhs));
   AMAMG_LAUNCH((k_stencil_gs_pair<B, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
                (const V*)f, Lt, Lx, c0, stride, st);
 }
 
-// Colour block qb of the coarse sweep.  variant > 0: two colour-pair launches with that many
-// right-hand sides per wave (0 = default); variant < 0: one k_stencil_gs_quad_mr launch with
-// -variant right-hand sides per wave (FP32 8 x 8 blocks; otherwise colour pairs).  Every
-// variant gives bitwise the same results.
+// Colour block qb of the coarse sweep: for FP32 8 x 8 blocks one matrix-core launch (variant =
+// offsets per load batch, 8, 12 or 24, 0 = 12; every choice gives bitwise the same results),
+// otherwise two colour-pair launches.
 template <int B, typename R, typename M, typename V>
 static void gs_block_b(hipStream_t s, const void* A, const void* D, void* x, const void* f, int Lt, int Lx,
                        int qb, int nrhs, int64_t stride, const RhsState* st, int variant) {
-  if constexpr (B == 8 && sizeof(R) == 4) {
-    const int rb = -variant;
-    if ((rb == 1 || rb == 2) && nrhs >= rb) {
-      const int ngr = (Lt / 4) * (Lx / 4);
-      const dim3 g(unsigned((ngr + 1) / 2), unsigned((nrhs + rb - 1) / rb));
-      if (rb == 2)
-        AMAMG_LAUNCH((k_stencil_gs_quad_mr<2, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
-                     (const V*)f, Lt, Lx, qb, nrhs, stride, st);
-      else
-        AMAMG_LAUNCH((k_stencil_gs_quad_mr<1, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
-                     (const V*)f, Lt, Lx, qb, nrhs, stride, st);
-      return;
-    }
+  if constexpr (B == 8 && std::is_same<R, float>::value && std::is_same<V, float2>::value &&
+                std::is_same<M, float2>::value) {
+    const int ngr = (Lt / 4) * (Lx / 4);
+    const dim3 g(unsigned(ngr), unsigned((nrhs + 15) / 16));
+#define AMAMG_GS_MFMA(NB)                                                                      \
+  AMAMG_LAUNCH((k_stencil_gs_quad_mfma<NB>), g, dim3(256), 0, s, (const float2*)A, (const float2*)D, \
+               (float2*)x, (const float2*)f, Lt, Lx, qb, nrhs, stride, st)
+    if (variant == 8) AMAMG_GS_MFMA(8);
+    else if (variant == 24) AMAMG_GS_MFMA(24);
+    else AMAMG_GS_MFMA(12);
+#undef AMAMG_GS_MFMA
+  } else {
+    (void)variant;
+    gs_pair_b<B, R, M, V>(s, A, D, x, f, Lt, Lx, coarse_colour(4 * qb), nrhs, stride, st);
+    gs_pair_b<B, R, M, V>(s, A, D, x, f, Lt, Lx, coarse_colour(4 * qb + 2), nrhs, stride, st);
   }
-  const int rb = variant > 0 ? variant : 0;
-  gs_pair_b<B, R, M, V>(s, A, D, x, f, Lt, Lx, coarse_colour(4 * qb), nrhs, stride, st, rb);
-  gs_pair_b<B, R, M, V>(s, A, D, x, f, Lt, Lx, coarse_colour(4 * qb + 2), nrhs, stride, st, rb);
 }
 
 #define AMAMG_B_DISPATCH(fn, prec, ...)                                                       \
@@ -824,10 +750,6 @@ void stencil_gs(hipStream_t s, Real prec, const void* A, const void* Dinv, void*
   AMAMG_B_DISPATCH(gs_b, prec, s, A, Dinv, x, f, Lt, Lx, colour, nrhs, stride, st);
 }
 
-void stencil_gs_pair(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
-                     int Lt, int Lx, int b, int c0, int nrhs, int64_t stride, const RhsState* st, int rb) {
-  AMAMG_B_DISPATCH(gs_pair_b, prec, s, A, Dinv, x, f, Lt, Lx, c0, nrhs, stride, st, rb);
-}
 
 void stencil_gs_block(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
                       int Lt, int Lx, int b, int qb, int nrhs, int64_t stride, const RhsState* st, int variant) {

@@ -79,15 +79,10 @@ void stencil_apply(hipStream_t s, Real prec, const void* A, const void* x, void*
 // f may be null (zero right-hand side)
 void stencil_gs(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
                 int Lt, int Lx, int b, int colour, int nrhs, int64_t stride, const RhsState* st);
-// colours c0 and c0 + 1 (c0 even) of the same sweep in one launch, bitwise equal to two
-// stencil_gs launches.  rb = right-hand sides per wave for FP32 8 x 8 blocks (1, 2, 4; 0 =
-// default): a launch parameter only, the results do not depend on it
-void stencil_gs_pair(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
-                     int Lt, int Lx, int b, int c0, int nrhs, int64_t stride, const RhsState* st, int rb = 0);
 // colour block qb (0..3) of the coarse sweep order (coarse_colour(4 qb) .. coarse_colour(4 qb +
-// 3)), bitwise equal to four stencil_gs launches in that order.  variant: > 0 colour-pair
-// launches with that many right-hand sides per wave (FP32 8 x 8 blocks), < 0 one launch per
-// block with -variant right-hand sides per wave, 0 default: a launch parameter only
+// 3)).  FP32 8 x 8 blocks: one matrix-core launch, variant = offsets per load batch (8, 12 or 24;
+// 0 = 12), a launch parameter only.  Other block sizes and FP64: two colour-pair launches,
+// bitwise equal to four stencil_gs launches in that order
 void stencil_gs_block(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
                       int Lt, int Lx, int b, int qb, int nrhs, int64_t stride, const RhsState* st, int variant = 0);
 // coarsest, GMRES variant: x = unpreconditioned GMRES(A, f) from 0 to relative tolerance tol in

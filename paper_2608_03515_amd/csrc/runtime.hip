@@ -864,6 +864,75 @@ amamg_status amamg_apply_transfer(amamg_hierarchy* h, int32_t level, int32_t pre
   return AMAMG_OK;
 }
 
+amamg_status amamg_apply_smoother(amamg_hierarchy* h, int32_t level, int32_t precision, int32_t nrhs,
+                                  int32_t sweeps, const double* f, double* x) {
+  if (!h || !f || !x || nrhs < 1) return h ? fail(h->gauge->ctx, {AMAMG_ERR_INVALID_ARG, "bad argument"}) : AMAMG_ERR_INVALID_ARG;
+  amamg_context* ctx = h->gauge->ctx;
+  try {
+    REQUIRE(precision == AMAMG_FP64 || precision == AMAMG_MIXED_FP32, AMAMG_ERR_INVALID_ARG,
+            "precision must be FP64 or MIXED_FP32");
+    REQUIRE(level >= 0 && level + 1 < int(h->lv.size()), AMAMG_ERR_INVALID_ARG,
+            "level must have a coarser level");
+    REQUIRE(sweeps >= 1 && sweeps <= 16, AMAMG_ERR_INVALID_ARG, "sweeps must be in [1, 16]");
+    HIPCHECK(hipSetDevice(ctx->device));
+    amamg_gauge* gg = h->gauge;
+    const LevelData& L = h->lv[level];
+    const Geom& g = L.g;
+    const int64_t nd = g.ndof();
+    const bool f64 = precision == AMAMG_FP64;
+    const Real T = f64 ? F64 : F32;
+    const size_t cs = f64 ? sizeof(double2) : sizeof(float2);
+    hipStream_t s = ctx->stream;
+    Arena io;
+    const size_t nval = size_t(nrhs) * nd;
+    // x in the level's precision; f as the V-cycle holds it (FP64 on the fine level, whose
+    // right-hand side is the Krylov vector, the level's precision below)
+    auto upload = [&](const double* src, bool as64) -> void* {
+      if (as64) {
+        void* d = io.alloc<double2>(nval);
+        HIPCHECK(hipMemcpyAsync(d, src, sizeof(double2) * nval, hipMemcpyHostToDevice, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        return d;
+      }
+      std::vector<float2> h32(nval);
+      for (size_t i = 0; i < nval; ++i) h32[i] = make_float2(float(src[2 * i]), float(src[2 * i + 1]));
+      void* d = io.alloc<float2>(nval);
+      HIPCHECK(hipMemcpyAsync(d, h32.data(), sizeof(float2) * nval, hipMemcpyHostToDevice, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      return d;
+    };
+    void* dx = upload(x, f64);
+    void* df = upload(f, f64 || level == 0);
+    if (level == 0) {
+      const LinkStore ls = f64 ? LINK_F64 : LINK_F32;
+      ensure_links(gg, ls);
+      void* dy = io.alloc<char>(cs * nval);
+      wilson_gs_sweeps(s, ls, link0(gg, ls), link1(gg, ls), T, dx, dy, (const double2*)df, g.Lt, g.Lx, h->m0,
+                       sweeps, nrhs, nd, nullptr);
+      dx = dy;
+    } else {
+      const void* Ak = f64 ? (const void*)L.A : (const void*)L.A32;
+      const void* Dk = f64 ? (const void*)L.Dinv : (const void*)L.Dinv32;
+      for (int sw = 0; sw < sweeps; ++sw)
+        for (int qb = 0; qb < 4; ++qb)
+          stencil_gs_block(s, T, Ak, Dk, dx, df, g.Lt, g.Lx, g.b, qb, nrhs, nd, nullptr);
+    }
+    check_launch();
+    if (f64) {
+      HIPCHECK(hipMemcpyAsync(x, dx, sizeof(double2) * nval, hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+    } else {
+      std::vector<float2> o32(nval);
+      HIPCHECK(hipMemcpyAsync(o32.data(), dx, sizeof(float2) * nval, hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      for (size_t i = 0; i < nval; ++i) { x[2 * i] = o32[i].x; x[2 * i + 1] = o32[i].y; }
+    }
+  } catch (const Fail& f) {
+    return fail(ctx, f);
+  }
+  return AMAMG_OK;
+}
+
 amamg_status amamg_get_test_vectors(const amamg_hierarchy* h, int32_t level, double* out) {
   if (!h || !out || level < 0 || level >= int(h->lv.size()) - 1) return AMAMG_ERR_INVALID_ARG;
   const LevelData& L = h->lv[level];

@@ -493,6 +493,45 @@ def _transfer_case(lib, h, olev, level, rng, nrhs, precision):
     assert np.all(abs(y - ref) <= bound), (level, nrhs, precision, float(np.max(abs(y - ref) / bound)))
 
 
+@pytest.mark.parametrize("nrhs", [1, 20])
+def test_smoothers_match_oracle(lib, ctx, c4_oracle, nrhs):
+    """Two post-smoothing sweeps with the V-cycle's kernels against the oracle's multicolour
+    Gauss-Seidel on the 128^2, a = 8, o = 2 hierarchy: the fine level's fused red-black sweeps
+    and level 1's 16-colour block sweep (8 x 8 blocks; FP32 on matrix cores, 16 right-hand
+    sides per tile, so 20 spans two tiles with a ragged tail).  FP64 within the setup's
+    agreement (1e-9), FP32 within 2e-5 of the oracle (a few FP32 roundings per block sum, the
+    inverse diagonal blocks amplify them by their condition); a sweep in the wrong colour order
+    or with a stale in-group value is off by O(0.1)."""
+    U, m0, olev = c4_oracle
+    w = synth.WORKLOADS["C4"]
+    g = make_gauge(lib, ctx, U, m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=8, overlap=2, n_test_vectors=8))
+    rng = np.random.default_rng(7 + nrhs)
+    for k in (0, 1):
+        lev = olev[k]
+        n = lev.A.shape[0]
+        f = rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))
+        x0 = rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))
+        ref = x0.copy()
+        for r in range(nrhs):
+            for _ in range(2):
+                amg.gs_sweep(lev, ref[r], f[r])
+        say("smoother level", k, "nrhs", nrhs)
+        x64 = h.smooth(k, f, x0, sweeps=2, precision=lib.FP64)
+        x32 = h.smooth(k, f, x0, sweeps=2, precision=lib.MIXED_FP32)
+        for r in range(nrhs):
+            assert rel(x64[r], ref[r]) <= 1e-9, (k, r, rel(x64[r], ref[r]))
+            assert rel(x32[r], ref[r]) <= 2e-5, (k, r, rel(x32[r], ref[r]))
+        # one sweep differs from two by far more than the bars
+        x1 = h.smooth(k, f, x0, sweeps=1, precision=lib.FP64)
+        assert rel(x1[0], ref[0]) > 1e-3
+        if nrhs > 1:                     # a right-hand side alone gets bitwise its batch result
+            xs = h.smooth(k, f[3:4], x0[3:4], sweeps=2, precision=lib.MIXED_FP32)
+            assert np.array_equal(xs[0], x32[3])
+    h.close()
+    g.close()
+
+
 def test_transfers_match_oracle(lib, ctx, c4_oracle):
     """Restriction P^H and prolongation P of the 128^2 a = 8, o = 2 hierarchy (32 interpolation
     columns on the fine level: register tiles; 128 on level 1: the mixed V-cycle's matrix-core
@@ -552,9 +591,9 @@ def test_c4_mixed_batch_within_bound(lib, ctx):
 
 def test_tuned_launch_shapes_do_not_change_results(lib):
     """The autotuner's launch shapes (fine smoother tile width 16/32/64; on the 128^2 workload's
-    level 1 the block smoother as colour-pair launches with 1/2/4 right-hand sides per wave or as
-    one launch per 2 x 2 colour block with 1/2) give bitwise the same mixed solve of 20
-    right-hand sides, forced one by one and chosen by timing; the timed entries are recorded."""
+    level 1 the matrix-core block sweep with 8, 12 or 24 stencil offsets per load batch) give bitwise
+    the same mixed solve of 20 right-hand sides, forced one by one and chosen by timing; the
+    timed entries are recorded."""
     w = synth.WORKLOADS["C4"]
     m0 = synth.critical_masses()["C4"] + w.gaps[0]
     psi = synth.field_to_abi(synth.gaussian_rhs(w.L, w.L, 5151, nrhs=20))
@@ -563,7 +602,7 @@ def test_tuned_launch_shapes_do_not_change_results(lib):
     h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=8, overlap=2, n_test_vectors=8))
     sp = lib.default_solve_params(precision=lib.MIXED_FP32)
     runs = []
-    for mode, force in [(lib.TUNE_FORCE, q) for q in range(5)] + [(lib.TUNE_AUTO, 0)]:
+    for mode, force in [(lib.TUNE_FORCE, q) for q in range(3)] + [(lib.TUNE_AUTO, 0)]:
         say("tuning", mode, force)
         ctx.set_tuning(mode, force)
         x, infos, st = h.solve(psi, sp)
@@ -578,7 +617,7 @@ def test_tuned_launch_shapes_do_not_change_results(lib):
     kinds = {e["kind"]: e for e in entries}
     assert set(kinds) == {"fine_smoother_tile", "block_smoother_launch"}
     assert set(kinds["fine_smoother_tile"]["candidates_us"]) == {16, 32, 64}
-    assert set(kinds["block_smoother_launch"]["candidates_us"]) == {1, 2, 4, -1, -2}
+    assert set(kinds["block_smoother_launch"]["candidates_us"]) == {8, 12, 24}
     for e in entries:
         assert e["choice"] in e["candidates_us"] and all(t > 0 for t in e["candidates_us"].values())
 
