@@ -228,6 +228,201 @@ __global__ __launch_bounds__(256) void k_stencil_gs_pair(const M* __restrict__ A
   if (live && jl == 0) xr[int64_t(t * Lx + xc) * B + i] = cconv<Vx>(out);
 }
 
+// k_stencil_gs_pair for B = 8 (one node per wave, lane (i, j) = row i, column j) over RB
+// right-hand sides per wave: the wave loads both nodes' 24 neighbour blocks and inverse diagonal
+// blocks once into registers and runs its right-hand sides through them, so the operator is read
+// once per RB right-hand sides.  Per right-hand side all neighbour values of both nodes are
+// loaded before the first node is written (the second node's only coupling to the first is the
+// partner at (0, -1), which comes from the first node's new value); the arithmetic and its order
+// are those of k_stencil_gs_pair, so the results are bitwise the same.
+template <int RB, typename R, typename M, typename Vx>
+__global__ __launch_bounds__(256) void k_stencil_gs_pair_mr(const M* __restrict__ A,
+                                                            const M* __restrict__ Dinv, Vx* x,
+                                                            const Vx* __restrict__ f, int Lt, int Lx,
+                                                            int c0, int nrhs, int64_t stride,
+                                                            const RhsState* __restrict__ st) {
+  constexpr int B = 8, NB = 24;
+  using C = cplx<R>;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = lane >> 3, jl = lane & 7;
+  const int qx = Lx >> 2, ncn = (Lt >> 2) * qx;
+  const int k = blockIdx.x * 4 + wv;
+  if (k >= ncn) return;                       // whole waves; the kernel has no block barrier
+  const int colour = c0 + 1;
+  const int t = 4 * (k / qx) + (colour >> 2), xc = 4 * (k % qx) + (colour & 3);   // xc >= 1
+  const int n1 = t * Lx + xc - 1, n2 = t * Lx + xc;
+  int m1[NB], m2[NB];
+  C a1[NB], a2[NB];
+  {
+    int q = 0;
+#pragma unroll
+    for (int dt = -2; dt <= 2; ++dt) {
+      const int tt = wrap1(t + dt, Lt) * Lx;
+#pragma unroll
+      for (int dx = -2; dx <= 2; ++dx) {
+        if (dt == 0 && dx == 0) continue;
+        const int d = (dt + 2) * 5 + (dx + 2);
+        m1[q] = tt + wrap1(xc - 1 + dx, Lx);
+        m2[q] = tt + wrap1(xc + dx, Lx);
+        a1[q] = cconv<C>(A[(int64_t(n1) * 25 + d) * B * B + i * B + jl]);
+        a2[q] = cconv<C>(A[(int64_t(n2) * 25 + d) * B * B + i * B + jl]);
+        ++q;
+      }
+    }
+  }
+  const C d1 = cconv<C>(Dinv[int64_t(n1) * B * B + i * B + jl]);
+  const C d2 = cconv<C>(Dinv[int64_t(n2) * B * B + i * B + jl]);
+  constexpr int PARTNER = 2 * 5 + 1;          // index q of offset (0, -1): rows dt = -2, -1 (q 0..9), then dx = -2 (q 10)
+  const int r0 = blockIdx.y * RB;
+  for (int rr = 0; rr < RB; ++rr) {
+    const int r = r0 + rr;
+    if (r >= nrhs) break;
+    if (st && !st[r].active) continue;
+    Vx* xr = x + r * stride;
+    C v1[NB], v2[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      v1[q] = cconv<C>(xr[int64_t(m1[q]) * B + jl]);
+      if (q != PARTNER) v2[q] = cconv<C>(xr[int64_t(m2[q]) * B + jl]);
+    }
+    const C f1 = f ? cconv<C>(f[r * stride + int64_t(n1) * B + i]) : czero<R>();
+    const C f2 = f ? cconv<C>(f[r * stride + int64_t(n2) * B + i]) : czero<R>();
+    // first node
+    C acc = czero<R>();
+#pragma unroll
+    for (int q = 0; q < NB; ++q) acc = cfma(a1[q], v1[q], acc);
+    acc.x = group_sum<8>(acc.x);
+    acc.y = group_sum<8>(acc.y);
+    C res = mk<R>(-acc.x, -acc.y);
+    if (f) res = cadd(res, f1);
+    C out = cfma(d1, mk<R>(__shfl(res.x, jl * 8), __shfl(res.y, jl * 8)), czero<R>());
+    out.x = group_sum<8>(out.x);
+    out.y = group_sum<8>(out.y);
+    if (jl == 0) xr[int64_t(n1) * B + i] = cconv<Vx>(out);
+    // the partner's new value in the storage type, as the two-launch sequence reads it
+    v2[PARTNER] = cconv<C>(cconv<Vx>(mk<R>(__shfl(out.x, jl * 8), __shfl(out.y, jl * 8))));
+    // second node
+    acc = czero<R>();
+#pragma unroll
+    for (int q = 0; q < NB; ++q) acc = cfma(a2[q], v2[q], acc);
+    acc.x = group_sum<8>(acc.x);
+    acc.y = group_sum<8>(acc.y);
+    res = mk<R>(-acc.x, -acc.y);
+    if (f) res = cadd(res, f2);
+    out = cfma(d2, mk<R>(__shfl(res.x, jl * 8), __shfl(res.y, jl * 8)), czero<R>());
+    out.x = group_sum<8>(out.x);
+    out.y = group_sum<8>(out.y);
+    if (jl == 0) xr[int64_t(n2) * B + i] = cconv<Vx>(out);
+  }
+}
+
+// One colour block qb of the coarse sweep (coarse_colour(4 qb) .. coarse_colour(4 qb + 3)) for
+// B = 8 in one launch: the block's nodes form 2 x 2 groups (rows I0, I0 + 1, columns J0, J0 + 1)
+// that do not couple with each other, and the four updates of a group run in colour order.  Two
+// waves per group: the lower wave updates (I0, J0) then (I0, J0 + 1) exactly as
+// k_stencil_gs_pair_mr does, and leaves their new values (in the storage type, as a launch per
+// colour pair would read them) in LDS; the upper wave then updates (I0 + 1, J0) and (I0 + 1,
+// J0 + 1) with those values for its in-group neighbours above.  Per right-hand side the upper
+// wave runs one phase behind the lower one; every thread passes the same RB + 1 barriers.
+// The results are bitwise those of the two colour-pair launches.
+template <int RB, typename R, typename M, typename Vx>
+__global__ __launch_bounds__(256) void k_stencil_gs_quad_mr(const M* __restrict__ A,
+                                                            const M* __restrict__ Dinv, Vx* x,
+                                                            const Vx* __restrict__ f, int Lt, int Lx,
+                                                            int qb, int nrhs, int64_t stride,
+                                                            const RhsState* __restrict__ st) {
+  constexpr int B = 8, NB = 24;
+  // neighbour slots (loop order dt, dx = -2..2 without (0, 0)) of the in-group offsets
+  constexpr int UPL = 6, UP = 7, UPR = 8, LEFT = 11;   // (-1,-1), (-1,0), (-1,+1), (0,-1)
+  using C = cplx<R>;
+  __shared__ C lower[2][RB][2][B];                    // [group slot][rhs][node][row]
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = lane >> 3, jl = lane & 7;
+  const int gs = wv >> 1, hi = wv & 1;
+  const int qx = Lx >> 2, ngr = (Lt >> 2) * qx;
+  const int k = blockIdx.x * 2 + gs;
+  const bool valid = k < ngr;
+  const int kk = valid ? k : 0;
+  const int t = 4 * (kk / qx) + 2 * (qb >> 1) + hi, xc = 4 * (kk % qx) + 2 * (qb & 1);
+  const int n1 = t * Lx + xc, n2 = n1 + 1;
+  int m1[NB], m2[NB];
+  C a1[NB], a2[NB];
+  {
+    int q = 0;
+#pragma unroll
+    for (int dt = -2; dt <= 2; ++dt) {
+      const int tt = wrap1(t + dt, Lt) * Lx;
+#pragma unroll
+      for (int dx = -2; dx <= 2; ++dx) {
+        if (dt == 0 && dx == 0) continue;
+        const int d = (dt + 2) * 5 + (dx + 2);
+        m1[q] = tt + wrap1(xc + dx, Lx);
+        m2[q] = tt + wrap1(xc + 1 + dx, Lx);
+        a1[q] = cconv<C>(A[(int64_t(n1) * 25 + d) * B * B + i * B + jl]);
+        a2[q] = cconv<C>(A[(int64_t(n2) * 25 + d) * B * B + i * B + jl]);
+        ++q;
+      }
+    }
+  }
+  const C d1 = cconv<C>(Dinv[int64_t(n1) * B * B + i * B + jl]);
+  const C d2 = cconv<C>(Dinv[int64_t(n2) * B * B + i * B + jl]);
+  const int r0 = blockIdx.y * RB;
+  for (int ph = 0; ph <= RB; ++ph) {
+    const int rr = ph - hi;
+    const int r = r0 + rr;
+    const bool work = valid && rr >= 0 && rr < RB && r < nrhs && (!st || st[r].active);
+    if (work) {
+      Vx* xr = x + r * stride;
+      C v1[NB], v2[NB];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const bool up1 = hi && (q == UP || q == UPR);
+        const bool up2 = hi && (q == UPL || q == UP);
+        if (!up1) v1[q] = cconv<C>(xr[int64_t(m1[q]) * B + jl]);
+        if (!up2 && q != LEFT) v2[q] = cconv<C>(xr[int64_t(m2[q]) * B + jl]);
+      }
+      if (hi) {
+        v1[UP] = lower[gs][rr][0][jl];
+        v1[UPR] = lower[gs][rr][1][jl];
+        v2[UPL] = lower[gs][rr][0][jl];
+        v2[UP] = lower[gs][rr][1][jl];
+      }
+      const C f1 = f ? cconv<C>(f[r * stride + int64_t(n1) * B + i]) : czero<R>();
+      const C f2 = f ? cconv<C>(f[r * stride + int64_t(n2) * B + i]) : czero<R>();
+      C acc = czero<R>();
+#pragma unroll
+      for (int q = 0; q < NB; ++q) acc = cfma(a1[q], v1[q], acc);
+      acc.x = group_sum<8>(acc.x);
+      acc.y = group_sum<8>(acc.y);
+      C res = mk<R>(-acc.x, -acc.y);
+      if (f) res = cadd(res, f1);
+      C out = cfma(d1, mk<R>(__shfl(res.x, jl * 8), __shfl(res.y, jl * 8)), czero<R>());
+      out.x = group_sum<8>(out.x);
+      out.y = group_sum<8>(out.y);
+      if (jl == 0) {
+        xr[int64_t(n1) * B + i] = cconv<Vx>(out);
+        if (!hi) lower[gs][rr][0][i] = cconv<C>(cconv<Vx>(out));
+      }
+      v2[LEFT] = cconv<C>(cconv<Vx>(mk<R>(__shfl(out.x, jl * 8), __shfl(out.y, jl * 8))));
+      acc = czero<R>();
+#pragma unroll
+      for (int q = 0; q < NB; ++q) acc = cfma(a2[q], v2[q], acc);
+      acc.x = group_sum<8>(acc.x);
+      acc.y = group_sum<8>(acc.y);
+      res = mk<R>(-acc.x, -acc.y);
+      if (f) res = cadd(res, f2);
+      out = cfma(d2, mk<R>(__shfl(res.x, jl * 8), __shfl(res.y, jl * 8)), czero<R>());
+      out.x = group_sum<8>(out.x);
+      out.y = group_sum<8>(out.y);
+      if (jl == 0) {
+        xr[int64_t(n2) * B + i] = cconv<Vx>(out);
+        if (!hi) lower[gs][rr][1][i] = cconv<C>(cconv<Vx>(out));
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // One colour block qb of the coarse sweep for FP32 8 x 8 blocks on matrix cores.  A workgroup
 // takes one 2 x 2 group of the block and a tile of 16 right-hand sides; wave v owns node v of
 // the group in sweep order (I0, J0), (I0, J0 + 1), (I0 + 1, J0),
@@ -682,37 +877,74 @@ static void gs_b(hipStream_t s, const void* A, const void* D, void* x, const voi
                      (const V*)f, Lt, Lx, colour, stride, st);
 }
 
+// rb = right-hand sides per wave of the paired sweep for FP32 8 x 8 blocks (1, 2 or 4; 0 = the
+// default 2; bitwise the same results for every choice), measured at 32 x 32 nodes, 64 rhs: 11.0
+// us per launch with 2 against 14.7 with 1, 11.6 with 4, 19.3 with 8.  FP64 would not fit the
+// registers; other block sizes take one right-hand side per wave.
 template <int B, typename R, typename M, typename V>
 static void gs_pair_b(hipStream_t s, const void* A, const void* D, void* x, const void* f, int Lt, int Lx,
-                      int c0, int nrhs, int64_t stride, const RhsState* st) {
+                      int c0, int nrhs, int64_t stride, const RhsState* st, int rb) {
   const int ncn = (Lt / 4) * (Lx / 4);
+  if constexpr (B == 8 && sizeof(R) == 4) {
+    if (rb == 0) rb = 2;
+    if (rb > 1 && nrhs >= rb) {
+      const dim3 g(unsigned((ncn + 3) / 4), unsigned((nrhs + rb - 1) / rb));
+      if (rb == 4)
+        AMAMG_LAUNCH((k_stencil_gs_pair_mr<4, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
+                     (const V*)f, Lt, Lx, c0, nrhs, stride, st);
+      else
+        AMAMG_LAUNCH((k_stencil_gs_pair_mr<2, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
+                     (const V*)f, Lt, Lx, c0, nrhs, stride, st);
+      return;
+    }
+  }
   dim3 g(unsigned((ncn + Lanes<B>::NPB - 1) / Lanes<B>::NPB), unsigned(nrhs));
   AMAMG_LAUNCH((k_stencil_gs_pair<B, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
                (const V*)f, Lt, Lx, c0, stride, st);
 }
 
-// Colour block qb of the coarse sweep: for FP32 8 x 8 blocks one matrix-core launch (variant =
-// offsets per load batch, 8, 12 or 24, 0 = 12; every choice gives bitwise the same results),
-// otherwise two colour-pair launches.
+// Colour block qb of the coarse sweep.  FP32 8 x 8 blocks on grids of at least 32 x 32 nodes:
+// one matrix-core launch, variant = stencil offsets per load batch (8, 12 or 24; 0 = 12).
+// Smaller grids and other blocks: variant > 0 colour-pair launches with that many
+// right-hand sides per wave (FP32 8 x 8 blocks), < 0 one k_stencil_gs_quad_mr launch with
+// -variant right-hand sides per wave (FP32 8 x 8 blocks; otherwise colour pairs).  Within
+// each of the two paths every variant gives bitwise the same results; which path runs depends
+// on the grid only, so a right-hand side's result does not depend on its batch.
 template <int B, typename R, typename M, typename V>
 static void gs_block_b(hipStream_t s, const void* A, const void* D, void* x, const void* f, int Lt, int Lx,
                        int qb, int nrhs, int64_t stride, const RhsState* st, int variant) {
   if constexpr (B == 8 && std::is_same<R, float>::value && std::is_same<V, float2>::value &&
                 std::is_same<M, float2>::value) {
-    const int ngr = (Lt / 4) * (Lx / 4);
-    const dim3 g(unsigned(ngr), unsigned((nrhs + 15) / 16));
+    if (gs_on_matrix_cores(Lt, Lx)) {
+      const int ngr = (Lt / 4) * (Lx / 4);
+      const dim3 g(unsigned(ngr), unsigned((nrhs + 15) / 16));
 #define AMAMG_GS_MFMA(NB)                                                                      \
   AMAMG_LAUNCH((k_stencil_gs_quad_mfma<NB>), g, dim3(256), 0, s, (const float2*)A, (const float2*)D, \
                (float2*)x, (const float2*)f, Lt, Lx, qb, nrhs, stride, st)
-    if (variant == 8) AMAMG_GS_MFMA(8);
-    else if (variant == 24) AMAMG_GS_MFMA(24);
-    else AMAMG_GS_MFMA(12);
+      if (variant == 8) AMAMG_GS_MFMA(8);
+      else if (variant == 24) AMAMG_GS_MFMA(24);
+      else AMAMG_GS_MFMA(12);
 #undef AMAMG_GS_MFMA
-  } else {
-    (void)variant;
-    gs_pair_b<B, R, M, V>(s, A, D, x, f, Lt, Lx, coarse_colour(4 * qb), nrhs, stride, st);
-    gs_pair_b<B, R, M, V>(s, A, D, x, f, Lt, Lx, coarse_colour(4 * qb + 2), nrhs, stride, st);
+      return;
+    }
   }
+  if constexpr (B == 8 && sizeof(R) == 4) {
+    const int rb = -variant;
+    if ((rb == 1 || rb == 2) && nrhs >= rb) {
+      const int ngr = (Lt / 4) * (Lx / 4);
+      const dim3 g(unsigned((ngr + 1) / 2), unsigned((nrhs + rb - 1) / rb));
+      if (rb == 2)
+        AMAMG_LAUNCH((k_stencil_gs_quad_mr<2, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
+                     (const V*)f, Lt, Lx, qb, nrhs, stride, st);
+      else
+        AMAMG_LAUNCH((k_stencil_gs_quad_mr<1, R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
+                     (const V*)f, Lt, Lx, qb, nrhs, stride, st);
+      return;
+    }
+  }
+  const int rb = variant > 0 ? variant : 0;
+  gs_pair_b<B, R, M, V>(s, A, D, x, f, Lt, Lx, coarse_colour(4 * qb), nrhs, stride, st, rb);
+  gs_pair_b<B, R, M, V>(s, A, D, x, f, Lt, Lx, coarse_colour(4 * qb + 2), nrhs, stride, st, rb);
 }
 
 #define AMAMG_B_DISPATCH(fn, prec, ...)                                                       \

@@ -383,8 +383,17 @@ static void tune_batch(Batch& bt) {
   for (size_t k = 1; k + 1 < h->lv.size(); ++k) {
     const Geom& g = h->lv[k].g;
     if (!(g.b == 8 && c.T == F32)) continue;
-    // offsets per load batch of the matrix-core block sweep
-    std::vector<int> cand = {8, 12, 24};
+    std::vector<int> cand;
+    if (gs_on_matrix_cores(g.Lt, g.Lx)) {
+      cand = {8, 12, 24};                   // offsets per load batch of the matrix-core sweep
+    } else {
+      if (cap < 2) continue;
+      // > 0: colour-pair launches with that many rhs per wave; < 0: one launch per colour block
+      cand = {1, 2};
+      if (cap >= 4) cand.push_back(4);
+      cand.push_back(-1);
+      cand.push_back(-2);
+    }
     const int64_t nd = g.ndof();
     Workspace::Lev& WL = ws->lv[k];
     const void* Ak = h->lv[k].A32;

@@ -493,19 +493,34 @@ def _transfer_case(lib, h, olev, level, rng, nrhs, precision):
     assert np.all(abs(y - ref) <= bound), (level, nrhs, precision, float(np.max(abs(y - ref) / bound)))
 
 
+@pytest.fixture(scope="module")
+def a4o2_oracle():
+    """A 128^2 field with a = 4, o = 2, 3 levels: level 1 is 32 x 32 nodes of 8 x 8 blocks, the
+    grid size from which the FP32 block sweep runs on matrix cores."""
+    U = synth.gen_links(128, 128, 6.0, 60, 4321)
+    prm = amg.SetupParams(levels=3, agg=4, overlap=2, n_test_vectors=8)
+    return U, 0.08, amg.setup(U, 0.08, prm), dict(levels=3, agg_size=4, overlap=2, n_test_vectors=8)
+
+
+@pytest.mark.parametrize("hier", ["c4", "a4o2"])
 @pytest.mark.parametrize("nrhs", [1, 20])
-def test_smoothers_match_oracle(lib, ctx, c4_oracle, nrhs):
+def test_smoothers_match_oracle(lib, ctx, c4_oracle, a4o2_oracle, hier, nrhs):
     """Two post-smoothing sweeps with the V-cycle's kernels against the oracle's multicolour
-    Gauss-Seidel on the 128^2, a = 8, o = 2 hierarchy: the fine level's fused red-black sweeps
-    and level 1's 16-colour block sweep (8 x 8 blocks; FP32 on matrix cores, 16 right-hand
-    sides per tile, so 20 spans two tiles with a ragged tail).  FP64 within the setup's
-    agreement (1e-9), FP32 within 2e-5 of the oracle (a few FP32 roundings per block sum, the
-    inverse diagonal blocks amplify them by their condition); a sweep in the wrong colour order
-    or with a stale in-group value is off by O(0.1)."""
-    U, m0, olev = c4_oracle
-    w = synth.WORKLOADS["C4"]
+    Gauss-Seidel: the fine level's fused red-black sweeps and level 1's 16-colour block sweep
+    of 8 x 8 blocks, on 16 x 16 nodes (128^2, a = 8, o = 2: FP32 vector kernels) and on 32 x 32
+    nodes (128^2, a = 4, o = 2: FP32 on matrix cores, 16 right-hand sides per tile, so 20 spans
+    two tiles with a ragged tail).  FP64 within the setup's agreement (1e-9), FP32 within 2e-5
+    of the oracle (a few FP32 roundings per block sum, the inverse diagonal blocks amplify them
+    by their condition); a sweep in the wrong colour order or with a stale in-group value is
+    off by O(0.1)."""
+    if hier == "c4":
+        U, m0, olev = c4_oracle
+        sp = dict(levels=3, agg_size=8, overlap=2, n_test_vectors=8)
+    else:
+        U, m0, olev, sp = a4o2_oracle
     g = make_gauge(lib, ctx, U, m0)
-    h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=8, overlap=2, n_test_vectors=8))
+    h = lib.Hierarchy(g, lib.default_setup_params(**sp))
+    assert h.level_info(1) == (olev[1].Lt, olev[1].Lx, 8)
     rng = np.random.default_rng(7 + nrhs)
     for k in (0, 1):
         lev = olev[k]
@@ -589,20 +604,26 @@ def test_c4_mixed_batch_within_bound(lib, ctx):
         assert abs(i32[r].iterations - i64[r].iterations) <= max(5, i64[r].iterations // 10)
 
 
-def test_tuned_launch_shapes_do_not_change_results(lib):
-    """The autotuner's launch shapes (fine smoother tile width 16/32/64; on the 128^2 workload's
-    level 1 the matrix-core block sweep with 8, 12 or 24 stencil offsets per load batch) give bitwise
-    the same mixed solve of 20 right-hand sides, forced one by one and chosen by timing; the
-    timed entries are recorded."""
+@pytest.mark.parametrize("a,block_cands", [(8, {1, 2, 4, -1, -2}), (4, {8, 12, 24})])
+def test_tuned_launch_shapes_do_not_change_results(lib, a, block_cands):
+    """The autotuner's launch shapes give bitwise the same mixed solve of 20 right-hand sides,
+    forced one by one and chosen by timing; the timed entries are recorded.  Fine smoother tile
+    width 16/32/64; level 1 with 16 x 16 nodes (128^2 workload, a = 8, o = 2): the vector block
+    sweep as colour-pair launches with 1/2/4 right-hand sides per wave or one launch per 2 x 2
+    colour block with 1/2; with 32 x 32 nodes (a = 4, o = 2): the matrix-core sweep with 8, 12
+    or 24 stencil offsets per load batch."""
     w = synth.WORKLOADS["C4"]
-    m0 = synth.critical_masses()["C4"] + w.gaps[0]
     psi = synth.field_to_abi(synth.gaussian_rhs(w.L, w.L, 5151, nrhs=20))
+    if a == 8:
+        U, m0 = w.links(), synth.critical_masses()["C4"] + w.gaps[0]
+    else:
+        U, m0 = synth.gen_links(128, 128, 6.0, 60, 4321), 0.08
     ctx = lib.Context(0)                 # its own context: the tuner state is per context
-    g = make_gauge(lib, ctx, w.links(), m0)
-    h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=8, overlap=2, n_test_vectors=8))
+    g = make_gauge(lib, ctx, U, m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=a, overlap=2, n_test_vectors=8))
     sp = lib.default_solve_params(precision=lib.MIXED_FP32)
     runs = []
-    for mode, force in [(lib.TUNE_FORCE, q) for q in range(3)] + [(lib.TUNE_AUTO, 0)]:
+    for mode, force in [(lib.TUNE_FORCE, q) for q in range(len(block_cands))] + [(lib.TUNE_AUTO, 0)]:
         say("tuning", mode, force)
         ctx.set_tuning(mode, force)
         x, infos, st = h.solve(psi, sp)
@@ -617,7 +638,7 @@ def test_tuned_launch_shapes_do_not_change_results(lib):
     kinds = {e["kind"]: e for e in entries}
     assert set(kinds) == {"fine_smoother_tile", "block_smoother_launch"}
     assert set(kinds["fine_smoother_tile"]["candidates_us"]) == {16, 32, 64}
-    assert set(kinds["block_smoother_launch"]["candidates_us"]) == {8, 12, 24}
+    assert set(kinds["block_smoother_launch"]["candidates_us"]) == block_cands
     for e in entries:
         assert e["choice"] in e["candidates_us"] and all(t > 0 for t in e["candidates_us"].values())
 
