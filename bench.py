@@ -460,7 +460,7 @@ def pmc_summary(fetch_csv, write_csv, out_md, command, timer_json):
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
-MFMA_KERNELS = ("k_restrict_mfma", "k_prolong_mfma", "k_dense_apply_mfma")
+MFMA_KERNELS = ("k_restrict_mfma", "k_prolong_mfma", "k_dense_apply_mfma", "k_stencil_gs_quad_mfma")
 MFMA_PEAK_TFLOPS = {"F32": 157.3, "F64": 78.6}
 SIMD_NUM = 1024
 
