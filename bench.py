@@ -460,6 +460,60 @@ def pmc_summary(fetch_csv, write_csv, out_md, command, timer_json):
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
+STENCIL_L = 4096
+STENCIL_BYTES_PER_SITE = {"fp64": 96, "fp32": 48, "fp32_bf16links": 40}
+
+
+def stencil_traffic_summary(fetch_csv, write_csv, stats_csv, out_md, command, trace_command):
+    """HBM bytes per launch of the fine stencil at 4096^2 (bench.py --stencil-only) from two
+    rocprofv3 --pmc runs, scaled by the same counters on a 1 GiB elementwise copy, beside the
+    algorithmic bytes (per site: 2 spinor reads, 2 links, 1 spinor write) and the rate over the
+    kernel trace's mean duration."""
+    import csv
+    from collections import defaultdict
+
+    def load(path):
+        per = defaultdict(list)
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                per[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+        return per
+    fe, wr = load(fetch_csv), load(write_csv)
+    cal = [k for k in fe if "neg_kernel" in k]
+    f_fac = fe[cal[0]][0] * 1024 / 2 ** 30
+    w_fac = wr[cal[0]][0] * 1024 / 2 ** 30
+    dur = {r["Name"].split("(")[0]: float(r["AverageNs"]) for r in csv.DictReader(open(stats_csv))}
+
+    def mode(name):
+        # template arguments: tile, compute type, link storage, ...
+        args = [a.strip() for a in name.split("k_wilson_apply<", 1)[1].split(",")]
+        if "bf16" in args[2]:
+            return "fp32_bf16links"
+        return "fp64" if args[1] == "double" else "fp32"
+    lines = [f"# HBM traffic, {os.path.basename(out_md)[:-3]}", "",
+             "Two counter passes (one counter each) and a kernel trace, from the repository root:", ""]
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        lines.append(f"    {command.replace('COUNTER', c)}")
+    lines += [f"    {trace_command}", "",
+              f"Calibration: a 1 GiB elementwise copy (`neg`) reads as {fe[cal[0]][0]:.0f} KiB of "
+              f"FETCH_SIZE and writes as {wr[cal[0]][0]:.0f} KiB of WRITE_SIZE: scale factors "
+              f"{f_fac:.4f} (fetch) and {w_fac:.4f} (write) counter bytes per byte.", "",
+              "| kernel | mode | dispatches | read MB | written MB | algorithmic MB | traffic / algorithmic "
+              "| mean us (trace) | algorithmic GB/s | measured GB/s |",
+              "|---|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for name in sorted(k for k in fe if "k_wilson_apply" in k):
+        m = mode(name)
+        n = len(fe[name])
+        rd = sum(fe[name]) * 1024 / f_fac / n
+        wt = sum(wr.get(name, [0.0])) * 1024 / w_fac / max(1, len(wr.get(name, [])))
+        alg = STENCIL_BYTES_PER_SITE[m] * STENCIL_L * STENCIL_L
+        us = dur.get(name.split("(")[0], float("nan")) / 1e3
+        short = name.split("(")[0].replace("|", "/")[:70]
+        lines.append(f"| `{short}` | {m} | {n} | {rd / 1e6:.1f} | {wt / 1e6:.1f} | {alg / 1e6:.1f} | "
+                     f"{(rd + wt) / alg:.3f} | {us:.1f} | {alg / (us * 1e3):.0f} | {(rd + wt) / (us * 1e3):.0f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
 MFMA_KERNELS = ("k_restrict_mfma", "k_prolong_mfma", "k_dense_apply_mfma", "k_stencil_gs_quad_mfma")
 MFMA_PEAK_TFLOPS = {"F32": 157.3, "F64": 78.6}
 SIMD_NUM = 1024
@@ -543,6 +597,8 @@ def main():
     ap.add_argument("--no-single", action="store_true", help="skip the single-rhs FP64 path")
     ap.add_argument("--trace-summary", nargs=3, metavar=("STATS_CSV", "OUT_MD", "COMMAND"))
     ap.add_argument("--mfma-summary", nargs=5, metavar=("PMC_CSV", "STATS_CSV", "OUT_MD", "COMMAND", "TRACE_COMMAND"))
+    ap.add_argument("--stencil-traffic-summary", nargs=6,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "STATS_CSV", "OUT_MD", "COMMAND", "TRACE_COMMAND"))
     ap.add_argument("--pmc-summary", nargs=5,
                     metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD", "COMMAND", "TIMER_JSON"))
     ap.add_argument("--profile-mixed", action="store_true",
@@ -558,6 +614,9 @@ def main():
         return
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)
+        return
+    if args.stencil_traffic_summary:
+        stencil_traffic_summary(*args.stencil_traffic_summary)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -575,7 +634,14 @@ def main():
         stream = torch.cuda.Stream()
         torch.cuda.set_stream(stream)
         ctx = lib.Context(0, stream.cuda_stream)
-        print(json.dumps({"stencil_4096": stencil_bandwidth(lib, torch, ctx)}), flush=True)
+        st = stencil_bandwidth(lib, torch, ctx)
+        # traffic-counter calibration: a plain elementwise copy of known size
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").normal_()
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)          # one elementwise kernel: 1 GiB read, 1 GiB written
+        torch.cuda.synchronize()
+        print(json.dumps({"stencil_4096": st}), flush=True)
         return
     if args.multi_only:
         stream = torch.cuda.Stream()
