@@ -235,6 +235,29 @@ def test_c2_fp64_mass_sweep_matches_oracle(lib, ctx):
         assert rel(x, xo) <= 1e-9
 
 
+@pytest.mark.parametrize("norm", [amg.NORM_CONST, amg.NORM_NONE])
+def test_c2_normalisation_modes_match_oracle(lib, ctx, norm):
+    """The paper's literal normalisation (CONST: interpolated constants stay constant) and none
+    at all, on the 64^2 workload at m_c + 0.02 in FP64: iteration counts equal the oracle's,
+    solutions within 1e-9."""
+    w = synth.WORKLOADS["C2"]
+    m0 = synth.critical_masses()["C2"] + 0.02
+    U = w.links()
+    psi = synth.gaussian_rhs(w.L, w.L, w.rhs_seed + 7)[0]
+    say("C2 norm", norm)
+    prm = amg.SetupParams(levels=w.levels, agg=w.agg, overlap=w.overlap, n_test_vectors=w.n_test_vectors, norm=norm)
+    xo, io, _ = oracle_solve(U, m0, psi, prm)
+    g = make_gauge(lib, ctx, U, m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=w.levels, agg_size=w.agg, overlap=w.overlap,
+                                                   n_test_vectors=w.n_test_vectors, norm=norm))
+    x, infos, st = h.solve(synth.field_to_abi(psi[None]))
+    h.close()
+    g.close()
+    assert st == lib.OK and infos[0].converged and io.converged
+    assert infos[0].iterations == io.iterations, (infos[0].iterations, io.iterations)
+    assert rel(synth.field_from_abi(x)[0], xo) <= 1e-9
+
+
 @pytest.mark.parametrize("precision,bound", [(1, 1e-9), (2, 1e-8)])
 def test_c2_mixed_precision_within_bound(lib, ctx, precision, bound):
     w = synth.WORKLOADS["C2"]
