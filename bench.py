@@ -328,6 +328,29 @@ def agg_sweep_leg(lib, torch, ctx, groups, nrhs=64):
     return out
 
 
+BATCH_SWEEP = (1, 8, 32, 64, 128)
+
+
+def batch_sweep_leg(lib, torch, ctx, h, w, groups):
+    """Setup + solve of the 256^2 workload's first nrhs Gaussian right-hand sides per step, mixed
+    precision (stream groups of at least 16 rhs), and the BF16-link mode at 64."""
+    out = []
+    for nrhs, prec in [(n, lib.MIXED_FP32) for n in BATCH_SWEEP] + [(64, lib.MIXED_FP32_BF16LINKS)]:
+        psi = synth.gaussian_rhs(w.L, w.L, w.rhs_seed, nrhs=nrhs)
+        b = torch.from_numpy(synth.field_to_abi(psi)).to("cuda")
+        x = torch.zeros_like(b)
+        gr = max(1, min(groups, nrhs // 16))
+        dt, ts, infos, _ = run_steps(lib, torch, ctx, h, b, x, nrhs, prec, 1, 1, groups=gr)
+        its = [i.iterations for i in infos]
+        rec = {"nrhs": nrhs, "precision": {lib.MIXED_FP32: "mixed", lib.MIXED_FP32_BF16LINKS: "mixed_bf16links"}[prec],
+               "groups": gr, "solves_per_s": nrhs / dt, "s_per_step": dt, "iterations_min_max": [min(its), max(its)],
+               "converged": all(i.converged for i in infos)}
+        log("batch sweep", json.dumps(rec))
+        out.append(rec)
+        del b, x
+    return out
+
+
 # the paper's own settings beside this library's defaults, on the headline workload
 VARIANTS = (("coarsest GMRES to 0.1 (the paper's coarsest solver)", dict(coarsest_tol=0.1)),
             ("normalisation CONST (the paper's literal rule)", dict(norm=1)),
@@ -583,6 +606,8 @@ def main():
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg")
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-lattice leg")
     ap.add_argument("--no-agg-sweep", action="store_true", help="skip the aggregate-size sweep")
+    ap.add_argument("--no-batch-sweep", action="store_true",
+                    help="skip the right-hand-side count sweep (1..128, mixed; BF16 links at 64)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the paper-setting variants (coarsest GMRES, CONST/NONE normalisation)")
     ap.add_argument("--stencil-only", action="store_true",
@@ -758,6 +783,12 @@ def main():
             agg = agg_sweep_leg(lib, torch, ctx, args.groups)
         except Exception as e:              # an optional leg must not cost the headline line
             agg = {"error": f"{type(e).__name__}: {e}"}
+    batches = None
+    if not args.no_batch_sweep:
+        try:
+            batches = batch_sweep_leg(lib, torch, ctx, h, w, args.groups)
+        except Exception as e:              # an optional leg must not cost the headline line
+            batches = {"error": f"{type(e).__name__}: {e}"}
     variants = None
     if not args.no_variants:
         try:
@@ -796,6 +827,7 @@ def main():
         "aggregate_sweep": agg,
         "operation_count": op_count,
         "paper_variants": variants,
+        "batch_sweep": batches,
         "autotuner": ctx.tuning_entries(),
     }
     if not args.no_cpu_baseline:
