@@ -266,6 +266,15 @@ def multi_lattice_leg(lib, torch, ctx, groups, instances=8, slots=8, nrhs_per=8)
                                     "iterations_min_max": [min(its), max(its)],
                                     "converged": all(i.converged for i in infos)}
     h.close()
+    # the same with level 1 (16 x 16 nodes of 8 x 8 blocks) swept on matrix cores
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=w.levels, agg_size=w.agg, overlap=w.overlap,
+                                                   n_test_vectors=w.n_test_vectors, block_smoother=1))
+    dt, ts, infos, _ = run_steps(lib, torch, ctx, h, b, x, 64, lib.MIXED_FP32, 2, 1, groups=groups)
+    its = [i.iterations for i in infos]
+    out["one_lattice_128_64rhs_matrix_core_smoother"] = {"solves_per_s": 128 / dt, "s_per_step": dt / 2,
+                                                          "iterations_min_max": [min(its), max(its)],
+                                                          "converged": all(i.converged for i in infos)}
+    h.close()
     g.close()
     del b, x
     cfgs = synth.multi_lattice_configs()

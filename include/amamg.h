@@ -78,6 +78,10 @@ typedef struct {
                                /* relative tolerance, FP64, as in the paper's experiments     */
                                /* (Numerical Results: 0.1); needs <= 2048 coarsest unknowns   */
   int32_t coarsest_max_iters;  /* GMRES steps at most, 1..32 (default 32)                    */
+  int32_t block_smoother;      /* FP32 sweeps of levels with 8 x 8 blocks: 0 matrix cores     */
+                               /* from 32 x 32 nodes, vector kernels below (default); 1 matrix */
+                               /* cores; 2 vector kernels.  Fixed per hierarchy, so results do */
+                               /* not depend on the batch                                      */
 } amamg_setup_params;
 
 typedef struct {

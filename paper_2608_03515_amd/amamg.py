@@ -48,7 +48,8 @@ class SetupParams(C.Structure):
     _fields_ = [("levels", C.c_int32), ("agg_size", C.c_int32), ("overlap", C.c_int32),
                 ("n_test_vectors", C.c_int32), ("test_vector_sweeps", C.c_int32),
                 ("pre_sweeps", C.c_int32), ("post_sweeps", C.c_int32), ("norm", C.c_int32),
-                ("seed", C.c_uint64), ("coarsest_tol", C.c_double), ("coarsest_max_iters", C.c_int32)]
+                ("seed", C.c_uint64), ("coarsest_tol", C.c_double), ("coarsest_max_iters", C.c_int32),
+                ("block_smoother", C.c_int32)]
 
 
 class SolveParams(C.Structure):

@@ -903,7 +903,7 @@ static void gs_pair_b(hipStream_t s, const void* A, const void* D, void* x, cons
                (const V*)f, Lt, Lx, c0, stride, st);
 }
 
-// Colour block qb of the coarse sweep.  FP32 8 x 8 blocks on grids of at least 32 x 32 nodes:
+// Colour block qb of the coarse sweep.  FP32 8 x 8 blocks with gs_on_matrix_cores(mode):
 // one matrix-core launch, variant = stencil offsets per load batch (8, 12 or 24; 0 = 12).
 // Smaller grids and other blocks: variant > 0 colour-pair launches with that many
 // right-hand sides per wave (FP32 8 x 8 blocks), < 0 one k_stencil_gs_quad_mr launch with
@@ -912,10 +912,10 @@ static void gs_pair_b(hipStream_t s, const void* A, const void* D, void* x, cons
 // on the grid only, so a right-hand side's result does not depend on its batch.
 template <int B, typename R, typename M, typename V>
 static void gs_block_b(hipStream_t s, const void* A, const void* D, void* x, const void* f, int Lt, int Lx,
-                       int qb, int nrhs, int64_t stride, const RhsState* st, int variant) {
+                       int qb, int nrhs, int64_t stride, const RhsState* st, int variant, int mode) {
   if constexpr (B == 8 && std::is_same<R, float>::value && std::is_same<V, float2>::value &&
                 std::is_same<M, float2>::value) {
-    if (gs_on_matrix_cores(Lt, Lx)) {
+    if (gs_on_matrix_cores(Lt, Lx, mode)) {
       const int ngr = (Lt / 4) * (Lx / 4);
       const dim3 g(unsigned(ngr), unsigned((nrhs + 15) / 16));
 #define AMAMG_GS_MFMA(NB)                                                                      \
@@ -984,8 +984,9 @@ void stencil_gs(hipStream_t s, Real prec, const void* A, const void* Dinv, void*
 
 
 void stencil_gs_block(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
-                      int Lt, int Lx, int b, int qb, int nrhs, int64_t stride, const RhsState* st, int variant) {
-  AMAMG_B_DISPATCH(gs_block_b, prec, s, A, Dinv, x, f, Lt, Lx, qb, nrhs, stride, st, variant);
+                      int Lt, int Lx, int b, int qb, int nrhs, int64_t stride, const RhsState* st, int variant,
+                      int mode) {
+  AMAMG_B_DISPATCH(gs_block_b, prec, s, A, Dinv, x, f, Lt, Lx, qb, nrhs, stride, st, variant, mode);
 }
 
 void dense_apply(hipStream_t s, Real prec, const double2* Ainv, const void* v, void* y, int n,

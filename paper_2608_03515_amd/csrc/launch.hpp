@@ -79,17 +79,21 @@ void stencil_apply(hipStream_t s, Real prec, const void* A, const void* x, void*
 // f may be null (zero right-hand side)
 void stencil_gs(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
                 int Lt, int Lx, int b, int colour, int nrhs, int64_t stride, const RhsState* st);
-// FP32 8 x 8 block sweeps run on matrix cores on grids of at least 32 x 32 nodes (enough 2 x 2
-// groups per launch); smaller grids keep the vector kernels.  Depends on the grid only.
-inline bool gs_on_matrix_cores(int Lt, int Lx) { return Lt * Lx >= 1024; }
+// FP32 8 x 8 block sweeps run on matrix cores (mode 1), on the vector kernels (mode 2) or, by
+// default (mode 0), on matrix cores from 32 x 32 nodes up (enough 2 x 2 groups per launch).
+// Fixed per hierarchy level, so a right-hand side's result never depends on its batch.
+inline bool gs_on_matrix_cores(int Lt, int Lx, int mode) {
+  return mode == 1 || (mode == 0 && Lt * Lx >= 1024);
+}
 // colour block qb (0..3) of the coarse sweep order (coarse_colour(4 qb) .. coarse_colour(4 qb +
-// 3)).  FP32 8 x 8 blocks with gs_on_matrix_cores: one matrix-core launch, variant = offsets
+// 3)).  FP32 8 x 8 blocks with gs_on_matrix_cores(mode): one matrix-core launch, variant = offsets
 // per load batch (8, 12 or 24; 0 = 12).  Otherwise bitwise equal to four stencil_gs launches
 // in that order; variant (FP32 8 x 8 blocks): > 0 colour-pair launches with that many
 // right-hand sides per wave, < 0 one launch per block with -variant right-hand sides per wave.
 // The variant is a launch parameter only
 void stencil_gs_block(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
-                      int Lt, int Lx, int b, int qb, int nrhs, int64_t stride, const RhsState* st, int variant = 0);
+                      int Lt, int Lx, int b, int qb, int nrhs, int64_t stride, const RhsState* st, int variant = 0,
+                      int mode = 0);
 // coarsest, GMRES variant: x = unpreconditioned GMRES(A, f) from 0 to relative tolerance tol in
 // at most `steps` (<= 32) steps, n <= 2048; Acm column-major FP64; basis [nrhs][steps + 1][n]
 void coarsest_gmres(hipStream_t s, Real prec, const double2* Acm, const void* f, void* x, int n, int nrhs,

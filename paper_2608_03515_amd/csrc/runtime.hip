@@ -163,6 +163,7 @@ std::vector<LevelPlan> plan_levels(int nt, int nx, const amamg_setup_params& p) 
           "coarsest_tol must be in [0, 1)");
   REQUIRE(p.coarsest_tol == 0 || (p.coarsest_max_iters >= 1 && p.coarsest_max_iters <= kCoarsestGmresMaxSteps),
           AMAMG_ERR_INVALID_ARG, "coarsest_max_iters must be in [1, 32]");
+  REQUIRE(p.block_smoother >= 0 && p.block_smoother <= 2, AMAMG_ERR_INVALID_ARG, "block_smoother must be 0, 1 or 2");
   std::vector<LevelPlan> out;
   int Lt = nt, Lx = nx, b = 2;
   const int a = p.agg_size, o = p.overlap;
@@ -462,7 +463,7 @@ void amamg_default_setup_params(amamg_setup_params* p) {
   p->levels = 2; p->agg_size = 4; p->overlap = 1; p->n_test_vectors = 4;
   p->test_vector_sweeps = 4; p->pre_sweeps = 0; p->post_sweeps = 2;
   p->norm = AMAMG_NORM_TESTVEC; p->seed = 0;
-  p->coarsest_tol = 0; p->coarsest_max_iters = 32;
+  p->coarsest_tol = 0; p->coarsest_max_iters = 32; p->block_smoother = 0;
 }
 
 void amamg_default_solve_params(amamg_solve_params* p) {
@@ -915,7 +916,7 @@ amamg_status amamg_apply_smoother(amamg_hierarchy* h, int32_t level, int32_t pre
       const void* Dk = f64 ? (const void*)L.Dinv : (const void*)L.Dinv32;
       for (int sw = 0; sw < sweeps; ++sw)
         for (int qb = 0; qb < 4; ++qb)
-          stencil_gs_block(s, T, Ak, Dk, dx, df, g.Lt, g.Lx, g.b, qb, nrhs, nd, nullptr);
+          stencil_gs_block(s, T, Ak, Dk, dx, df, g.Lt, g.Lx, g.b, qb, nrhs, nd, nullptr, 0, h->prm.block_smoother);
     }
     check_launch();
     if (f64) {

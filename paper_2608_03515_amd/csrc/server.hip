@@ -95,7 +95,7 @@ bool same_params(const amamg_setup_params& a, const amamg_setup_params& b) {
   return a.levels == b.levels && a.agg_size == b.agg_size && a.overlap == b.overlap &&
          a.n_test_vectors == b.n_test_vectors && a.test_vector_sweeps == b.test_vector_sweeps &&
          a.pre_sweeps == b.pre_sweeps && a.post_sweeps == b.post_sweeps && a.norm == b.norm &&
-         a.seed == b.seed && a.coarsest_tol == b.coarsest_tol &&
+         a.seed == b.seed && a.coarsest_tol == b.coarsest_tol && a.block_smoother == b.block_smoother &&
          (a.coarsest_tol == 0 || a.coarsest_max_iters == b.coarsest_max_iters);
 }
 

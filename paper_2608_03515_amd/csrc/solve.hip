@@ -283,7 +283,8 @@ static void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x)
         const int rec = k == 1 ? timer_start(ctx, c.s, AMAMG_KT_COARSE_GS, c.step, c.group,
                                              4.0 * (ncn * 25.0 * g.b * g.b * cb + 2.0 * ncn * g.b * cb) + double(nd) * cb)
                                : -1;
-        stencil_gs_block(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, qb, c.nrhs, nd, st, c.gs_rb ? c.gs_rb[k] : 0);
+        stencil_gs_block(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, qb, c.nrhs, nd, st, c.gs_rb ? c.gs_rb[k] : 0,
+                         h->prm.block_smoother);
         timer_stop(ctx, c.s, rec);
       }
     }
@@ -384,7 +385,7 @@ static void tune_batch(Batch& bt) {
     const Geom& g = h->lv[k].g;
     if (!(g.b == 8 && c.T == F32)) continue;
     std::vector<int> cand;
-    if (gs_on_matrix_cores(g.Lt, g.Lx)) {
+    if (gs_on_matrix_cores(g.Lt, g.Lx, h->prm.block_smoother)) {
       cand = {8, 12, 24};                   // offsets per load batch of the matrix-core sweep
     } else {
       if (cap < 2) continue;
@@ -403,7 +404,8 @@ static void tune_batch(Batch& bt) {
       HIPCHECK(hipMemsetAsync(WL.f, 0, rs * cap * nd, bt.s));
       return time_us(bt.s, [&] {
         for (int qb = 0; qb < 4; ++qb)
-          stencil_gs_block(bt.s, F32, Ak, Dk, WL.x, WL.f, g.Lt, g.Lx, g.b, qb, cap, nd, nullptr, rb);
+          stencil_gs_block(bt.s, F32, Ak, Dk, WL.x, WL.f, g.Lt, g.Lx, g.b, qb, cap, nd, nullptr, rb,
+                           h->prm.block_smoother);
       });
     });
   }

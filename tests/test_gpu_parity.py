@@ -525,7 +525,7 @@ def a4o2_oracle():
     return U, 0.08, amg.setup(U, 0.08, prm), dict(levels=3, agg_size=4, overlap=2, n_test_vectors=8)
 
 
-@pytest.mark.parametrize("hier", ["c4", "a4o2"])
+@pytest.mark.parametrize("hier", ["c4", "c4_matrix_cores", "a4o2"])
 @pytest.mark.parametrize("nrhs", [1, 20])
 def test_smoothers_match_oracle(lib, ctx, c4_oracle, a4o2_oracle, hier, nrhs):
     """Two post-smoothing sweeps with the V-cycle's kernels against the oracle's multicolour
@@ -536,9 +536,9 @@ def test_smoothers_match_oracle(lib, ctx, c4_oracle, a4o2_oracle, hier, nrhs):
     of the oracle (a few FP32 roundings per block sum, the inverse diagonal blocks amplify them
     by their condition); a sweep in the wrong colour order or with a stale in-group value is
     off by O(0.1)."""
-    if hier == "c4":
+    if hier.startswith("c4"):
         U, m0, olev = c4_oracle
-        sp = dict(levels=3, agg_size=8, overlap=2, n_test_vectors=8)
+        sp = dict(levels=3, agg_size=8, overlap=2, n_test_vectors=8, block_smoother=1 if hier != "c4" else 0)
     else:
         U, m0, olev, sp = a4o2_oracle
     g = make_gauge(lib, ctx, U, m0)
@@ -601,19 +601,22 @@ def test_transfers_match_oracle(lib, ctx, c4_oracle):
     g.close()
 
 
-def test_c4_mixed_batch_within_bound(lib, ctx):
+@pytest.mark.parametrize("block_smoother", [0, 1])
+def test_c4_mixed_batch_within_bound(lib, ctx, block_smoother):
     """Mixed precision on the 128^2 a = 8, o = 2 workload (matrix-core level-1 transfers) for 20
     right-hand sides: every solution within the FP32 mode's bound of the FP64 solve, iteration
     counts within 10 % of FP64's (a wrong transfer weakens the preconditioner).  The first
     right-hand side solved alone (level-1 smoother with one right-hand side per wave) is bitwise
     the batch's (two per wave): every other stage's arithmetic per right-hand side does not
-    depend on the batch at this size."""
+    depend on the batch at this size.  Level 1 (16 x 16 nodes of 8 x 8 blocks) runs the vector
+    sweep by default and the matrix-core sweep when the setup asks for it."""
     w = synth.WORKLOADS["C4"]
     m0 = synth.critical_masses()["C4"] + w.gaps[0]
     psi = synth.gaussian_rhs(w.L, w.L, 4242, nrhs=20)
     g = make_gauge(lib, ctx, w.links(), m0)
-    h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=8, overlap=2, n_test_vectors=8))
-    say("C4 mixed batch")
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=8, overlap=2, n_test_vectors=8,
+                                                   block_smoother=block_smoother))
+    say("C4 mixed batch, block smoother", block_smoother)
     x64, i64, st64 = h.solve(synth.field_to_abi(psi), lib.default_solve_params(precision=lib.FP64))
     x32, i32, st32 = h.solve(synth.field_to_abi(psi), lib.default_solve_params(precision=lib.MIXED_FP32))
     x1, i1, st1 = h.solve(synth.field_to_abi(psi[:1]), lib.default_solve_params(precision=lib.MIXED_FP32))
