@@ -1,0 +1,76 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU contract, the operation-count summary and
+the rocprofv3 summary writers on small synthetic counter and trace files."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+import synth  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stdout + r.stderr
+
+
+def test_operation_count_summary():
+    w = synth.WORKLOADS["C3"]
+    s = bench.flop_summary(w, [600] * 64, 0.8)
+    assert s["setup_gflop"] > 0 and s["solve_gflop_per_rhs_mean"] > 0
+    # the setup is shared by the batch: per-solve cost with it shared lies between the solve
+    # alone and the solve plus a whole setup
+    assert s["solve_gflop_per_rhs_mean"] < s["gflop_per_solve_setup_shared"] < s["gflop_per_solve_setup_per_rhs"]
+    assert s["achieved_tflops"] == pytest.approx((s["setup_gflop"] + 64 * s["solve_gflop_per_rhs_mean"]) / 0.8 / 1e3)
+
+
+def _write_csv(path, header, rows):
+    with open(path, "w", newline="") as f:
+        wr = csv.writer(f)
+        wr.writerow(header)
+        wr.writerows(rows)
+
+
+def test_trace_summary(tmp_path):
+    stats = tmp_path / "stats.csv"
+    _write_csv(stats, ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"],
+               [["void amamg::k_lag_update<20, 2>(double*)", 10, 3000000, 300000, 60.0],
+                ["void amamg::k_gram<20, 2, true>(double*)", 10, 2000000, 200000, 40.0]])
+    out = tmp_path / "summary.md"
+    bench.trace_summary(str(stats), str(out), "CMD")
+    text = out.read_text()
+    assert "Total kernel time 5.0 ms over 20 dispatches" in text
+    assert "| update (`k_lag_update<*`) | 10 | 300.00 | 3.00 |" in text
+
+
+def test_traffic_summaries_scale_by_the_calibration_copy(tmp_path):
+    # calibration: 1 GiB copy reads as 2^19 KiB of FETCH_SIZE (factor 0.5) and 2^20 KiB written
+    cal = "void at::native::neg_kernel(...)"
+    upd = "void amamg::k_lag_update<20, 2>(...)"
+    fetch, write = tmp_path / "f.csv", tmp_path / "w.csv"
+    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    _write_csv(fetch, hdr, [[cal, "FETCH_SIZE", 2 ** 19], [upd, "FETCH_SIZE", 1000.0 * 0.5 * 1e6 / 1024]])
+    _write_csv(write, hdr, [[cal, "WRITE_SIZE", 2 ** 20], [upd, "WRITE_SIZE", 200.0 * 1e6 / 1024]])
+    out = tmp_path / "traffic.md"
+    timer = json.dumps({"family": "update", "algorithmic_bytes_per_launch": 1200e6})
+    bench.pmc_summary(str(fetch), str(write), str(out), "rocprofv3 --pmc COUNTER -- x", timer)
+    text = out.read_text()
+    assert "| update | 1 | 1000.0 | 200.0 | 1200.0 | 1.000 |" in text
+    # the stencil's summary on the same calibration, with a kernel trace for the duration
+    st = "void amamg::k_wilson_apply<64, double, HIP_vector_type<double, 2u>, HIP_vector_type<double, 2u> >(...)"
+    alg = bench.STENCIL_BYTES_PER_SITE["fp64"] * bench.STENCIL_L ** 2
+    _write_csv(fetch, hdr, [[cal, "FETCH_SIZE", 2 ** 19], [st, "FETCH_SIZE", alg * 0.5 / 1024]])
+    _write_csv(write, hdr, [[cal, "WRITE_SIZE", 2 ** 20], [st, "WRITE_SIZE", 0.0]])
+    stats = tmp_path / "stats.csv"
+    _write_csv(stats, ["Name", "AverageNs"], [[st, 1e6]])
+    bench.stencil_traffic_summary(str(fetch), str(write), str(stats), str(out), "CMD COUNTER", "TRACE")
+    row = [ln for ln in out.read_text().splitlines() if "k_wilson_apply" in ln][0]
+    assert "| fp64 | 1 |" in row and "| 1.000 |" in row and f"| {alg / 1e6:.0f} |" in row
