@@ -480,24 +480,27 @@ __global__ __launch_bounds__(256) void k_stencil_gs_quad_mfma(const float2* __re
 #pragma unroll
   for (int bt = 0; bt < 24 / NB; ++bt) {
     float2 aL[NB], aH[NB], bL[NB], bH[NB];
+    bool zero[NB];
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int q = NB * bt + j, d = q < 12 ? q : q + 1;
       const int dt = d / 5 - 2, dx = d % 5 - 2;
       const int ga = (v >> 1) + dt, gb = (v & 1) + dx;
-      const bool earlier = ga >= 0 && ga <= 1 && gb >= 0 && gb <= 1 && 2 * ga + gb < v;
+      zero[j] = (ga >= 0 && ga <= 1 && gb >= 0 && gb <= 1 && 2 * ga + gb < v) || !live;
       const int m = wrap1(tn + dt, Lt) * Lx + wrap1(xn + dx, Lx);
       aL[j] = Ab[d * 64];
       aH[j] = Ab[d * 64 + 4];
       bL[j] = xr[int64_t(m) * 8 + kq];
       bH[j] = xr[int64_t(m) * 8 + 4 + kq];
-      if (earlier || !live) bL[j] = bH[j] = z2;
     }
+    // the mask is applied where the values are used: overwriting a load's destination register
+    // in a branch would make every load of the batch wait for the one before it
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int q = NB * bt + j, d = q < 12 ? q : q + 1;
-      if (d & 1) acc1 = gs_block_mfma(aL[j], aH[j], bL[j], bH[j], im_row, acc1);
-      else acc0 = gs_block_mfma(aL[j], aH[j], bL[j], bH[j], im_row, acc0);
+      const float2 cL = zero[j] ? z2 : bL[j], cH = zero[j] ? z2 : bH[j];
+      if (d & 1) acc1 = gs_block_mfma(aL[j], aH[j], cL, cH, im_row, acc1);
+      else acc0 = gs_block_mfma(aL[j], aH[j], cL, cH, im_row, acc0);
     }
   }
   gs_mf4 tot = acc0 + acc1;
