@@ -243,6 +243,7 @@ __global__ __launch_bounds__(256) void k_prolong_tiled(
   __shared__ C Pl[RCH * PS];            // row stride NCOL + 1 against bank conflicts
   __shared__ C El[NR * NCOL];
   __shared__ int ri[RCH];
+  __shared__ int live[NR];              // this pass's active flags, read once per workgroup
   const int bid = xcd_block(blockIdx.x, gridDim.x);
   const int w = bid / nchunk, chunk = bid - (bid / nchunk) * nchunk;
   const int I = w / g.nJ, J = w - (w / g.nJ) * g.nJ;
@@ -269,10 +270,11 @@ __global__ __launch_bounds__(256) void k_prolong_tiled(
       const int c = col / g.bc, j = col - (col / g.bc) * g.bc;
       return e[(g0 + (rr < ng ? rr : 0)) * stride_c + int64_t(cn[c]) * g.bc + j];
     }, [&](int q, Vin v) { El[q] = q / NCOL < ng ? cconv<C>(v) : czero<R>(); });
+    for (int rr = threadIdx.x; rr < NR; rr += 256) live[rr] = rr < ng && (!st || st[g0 + rr].active);
     __syncthreads();
     if (k < cnt)
       for (int rr = h; rr < ng; rr += H) {
-        if (st && !st[g0 + rr].active) continue;
+        if (!live[rr]) continue;
         C acc = czero<R>();
 #pragma unroll
         for (int c = 0; c < NCOL; ++c) acc = cfma(pr[c], El[rr * NCOL + c], acc);
@@ -282,7 +284,7 @@ __global__ __launch_bounds__(256) void k_prolong_tiled(
       }
     for (int q = threadIdx.x; q < ng * nv_rows; q += 256) {
       const int rr = q / nv_rows, v = q - rr * nv_rows;   // (pt*o + px)*b + qq of node (I, J)
-      if (st && !st[g0 + rr].active) continue;
+      if (!live[rr]) continue;
       const int qq = v % g.b, pp = v / g.b;
       const int pt = pp / g.o, px = pp - (pp / g.o) * g.o;
       const int64_t vrow = int64_t((g.a * I + pt) * g.Lx + (g.a * J + px)) * g.b + qq;
