@@ -40,6 +40,12 @@ namespace amamg {
 // partial-sum slot of the Gram pass per block: dots with u at [0, nv), with w at [KMAXV, KMAXV + nv)
 #define KGRAM 64
 
+// Basis slots are streamed: the basis of a batch is far larger than the caches, so its loads
+// are marked non-temporal and leave L2 and the last-level cache to the vectors that are reused.
+__device__ inline double2 stream_load(const double2* p) {
+  return make_double2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+}
+
 template <int NV>
 __device__ inline void block_partial(const double2 (&acc)[NV], int nv, double2* out, double* lds) {
   // lds: NV * 4 * 2 doubles; writes nv block totals to out[0..nv)
@@ -182,7 +188,7 @@ __global__ __launch_bounds__(256) void k_gram(KrylovDims dm, const double2* __re
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int i = sub + S * k;
-      v[k] = i < NV ? Vr[i * vsj + d] : make_double2(0, 0);
+      v[k] = i < NV ? stream_load(Vr + i * vsj + d) : make_double2(0, 0);
     }
     const double2 ud = ur[d];
 #pragma unroll
@@ -255,7 +261,7 @@ __global__ __launch_bounds__(256) void k_lag_update(KrylovDims dm, double2* __re
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int i = sub + S * k;
-      v[k] = i < NV ? Vr[i * vsj + d] : make_double2(0, 0);
+      v[k] = i < NV ? stream_load(Vr + i * vsj + d) : make_double2(0, 0);
     }
     double2 pa = make_double2(0, 0), pb = make_double2(0, 0);
 #pragma unroll
