@@ -45,6 +45,11 @@ namespace amamg {
 __device__ inline double2 stream_load(const double2* p) {
   return make_double2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
 }
+// The finished basis vector v_j is read again only by later steps' passes over the basis.
+__device__ inline void stream_store(double2* p, double2 v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
 
 template <int NV>
 __device__ inline void block_partial(const double2 (&acc)[NV], int nv, double2* out, double* lds) {
@@ -278,7 +283,7 @@ __global__ __launch_bounds__(256) void k_lag_update(KrylovDims dm, double2* __re
     }
     if (sub == 0) {
       const double2 wd = wr[d];
-      if (write_v) vo[d] = pa;
+      if (write_v) stream_store(vo + d, pa);
       uo[d] = cfma(wd, make_double2(inv, 0.0), pb);
     }
   }
