@@ -40,10 +40,14 @@ namespace amamg {
 // partial-sum slot of the Gram pass per block: dots with u at [0, nv), with w at [KMAXV, KMAXV + nv)
 #define KGRAM 64
 
-// Basis slots are streamed: the basis of a batch is far larger than the caches, so its loads
-// are marked non-temporal and leave L2 and the last-level cache to the vectors that are reused.
+// Basis slots and search directions are streamed: a batch's basis is far larger than the
+// caches, so their loads are marked non-temporal and leave L2 and the last-level cache to the
+// vectors that are reused.
 __device__ inline double2 stream_load(const double2* p) {
   return make_double2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+}
+__device__ inline float2 stream_load(const float2* p) {
+  return make_float2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
 }
 // The finished basis vector v_j is read again only by later steps' passes over the basis.
 __device__ inline void stream_store(double2* p, double2 v) {
@@ -488,7 +492,17 @@ __global__ __launch_bounds__(256) void k_update_x(KrylovDims dm, const RhsState*
   if (d >= dm.n) return;
   double2 acc = x[r * dm.n + d];
   const double2* yr = y + int64_t(r) * dm.m;
-  for (int i = 0; i < s.k; ++i) acc = cfma(cconv<double2>(Z[i * zsj + r * dm.n + d]), yr[i], acc);
+  const Vz* zr = Z + r * dm.n + d;
+  // four search directions' loads in flight at a time; the sum keeps its order
+  int i = 0;
+  for (; i + 4 <= s.k; i += 4) {
+    Vz zv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) zv[u] = stream_load(zr + (i + u) * zsj);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = cfma(cconv<double2>(zv[u]), yr[i + u], acc);
+  }
+  for (; i < s.k; ++i) acc = cfma(cconv<double2>(stream_load(zr + i * zsj)), yr[i], acc);
   x[r * dm.n + d] = acc;
 }
 
