@@ -51,8 +51,9 @@ def run_steps(lib, torch, ctx, h, b, x, nrhs, precision, steps, warmup, timer=No
         h.update()
         infos, _ = h.solve_device(b.data_ptr(), x.data_ptr(), nrhs, sp)
     torch.cuda.synchronize()
-    if timer:
-        ctx.kernel_timer([timer])
+    fams = [timer] if isinstance(timer, str) else list(timer or [])
+    if fams:
+        ctx.kernel_timer(fams)
     t_setup = 0.0
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -63,8 +64,9 @@ def run_steps(lib, torch, ctx, h, b, x, nrhs, precision, steps, warmup, timer=No
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     timed = None
-    if timer:
-        timed = ctx.kernel_timer_read(timer)
+    if fams:
+        timed = {f: ctx.kernel_timer_read(f) for f in fams}
+        timed = timed[timer] if isinstance(timer, str) else timed
         ctx.kernel_timer([])
     return dt, t_setup, infos, timed
 
@@ -448,6 +450,14 @@ def trace_summary(stats_csv, out_md, command, top=25):
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
+def timer_families(t):
+    """{family: {launches, avg_launch_us, algorithmic_bytes_per_launch}} from the JSON line of
+    --profile-mixed (one family under "family", or several under "families")."""
+    if "families" in t:
+        return t["families"]
+    return {t["family"]: t} if "family" in t else {}
+
+
 def pmc_summary(fetch_csv, write_csv, out_md, command, timer_json):
     """Traffic per launch of the Gram-Schmidt families from two rocprofv3 --pmc runs, scaled by
     the same counters on a plain 1 GiB elementwise copy in the same run."""
@@ -481,14 +491,15 @@ def pmc_summary(fetch_csv, write_csv, out_md, command, timer_json):
         nwork = sum(1 for v in fv if v * 1024 / f_fac > 1e6)
         rd = sum(fv) * 1024 / f_fac / max(1, nwork)
         wt = sum(wv) * 1024 / w_fac / max(1, nwork)
-        alg = t.get("algorithmic_bytes_per_launch") if t.get("family") == fam else None
+        alg = timer_families(t).get(fam, {}).get("algorithmic_bytes_per_launch")
         rec[fam] = (rd, wt, nwork)
         lines.append(f"| {fam} | {nwork} | {rd / 1e6:.1f} | {wt / 1e6:.1f} | "
                      f"{alg / 1e6 if alg else float('nan'):.1f} | "
                      f"{(rd + wt) / alg if alg else float('nan'):.3f} |")
-    fam = t["family"]
-    lines += ["", f"<!-- traffic family={fam} source_sha={_sha(KERNEL_SRC)} "
-                  f"bytes_per_launch={rec[fam][0] + rec[fam][1]:.0f} -->"]
+    lines.append("")
+    for fam in timer_families(t):
+        lines.append(f"<!-- traffic family={fam} source_sha={_sha(KERNEL_SRC)} "
+                     f"bytes_per_launch={rec[fam][0] + rec[fam][1]:.0f} -->")
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
@@ -595,10 +606,10 @@ def committed_traffic(family):
         text = open(TRAFFIC_MD).read()
     except OSError:
         return None
-    m = re.search(r"<!-- traffic family=(\w+) source_sha=(\w+) bytes_per_launch=([0-9.]+) -->", text)
-    if not m or m.group(1) != family or m.group(2) != _sha(KERNEL_SRC):
-        return None
-    return float(m.group(3))
+    for m in re.finditer(r"<!-- traffic family=(\w+) source_sha=(\w+) bytes_per_launch=([0-9.]+) -->", text):
+        if m.group(1) == family and m.group(2) == _sha(KERNEL_SRC):
+            return float(m.group(3))
+    return None
 
 
 def main():
@@ -710,10 +721,11 @@ def main():
 
     res = {}
     if args.profile_mixed:
-        fam = "update"
+        # both Gram-Schmidt families are timed: they take nearly equal time, and the roofline
+        # reports whichever the instrumented step finds dominant
+        fams = list(FAMILY_PATTERNS)
         dt, ts, infos, timed = run_steps(lib, torch, ctx, h, b, x, args.nrhs, lib.MIXED_FP32, args.steps,
-                                         args.warmup, timer=fam, groups=1)
-        launches, ms, nbytes = timed
+                                         args.warmup, timer=fams, groups=1)
         # traffic-counter calibration: a plain elementwise copy of known size
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").normal_()
         dst = torch.empty_like(src)
@@ -721,8 +733,9 @@ def main():
         torch.neg(src, out=dst)          # one elementwise kernel: 1 GiB read, 1 GiB written
         torch.cuda.synchronize()
         print(json.dumps({"profile_mixed": summarize(dt, ts, infos, args.nrhs, args.steps),
-                          "family": fam, "launches": launches, "avg_launch_us": ms * 1e3 / max(1, launches),
-                          "algorithmic_bytes_per_launch": nbytes / max(1, launches),
+                          "families": {f: {"launches": n, "avg_launch_us": ms * 1e3 / max(1, n),
+                                           "algorithmic_bytes_per_launch": nb / max(1, n)}
+                                       for f, (n, ms, nb) in timed.items()},
                           "copy_bytes_each_way": src.numel() * 8}), flush=True)
         return
     dt, ts, infos, _ = run_steps(lib, torch, ctx, h, b, x, args.nrhs, lib.FP64, args.steps, args.warmup,

@@ -64,6 +64,28 @@ def test_traffic_summaries_scale_by_the_calibration_copy(tmp_path):
     bench.pmc_summary(str(fetch), str(write), str(out), "rocprofv3 --pmc COUNTER -- x", timer)
     text = out.read_text()
     assert "| update | 1 | 1000.0 | 200.0 | 1200.0 | 1.000 |" in text
+    # both Gram-Schmidt families timed in one profiling pass: one marker each, and the roofline
+    # finds the per-launch traffic of whichever family it reports
+    dots = "void amamg::k_gram<20, 2, true>(...)"
+    _write_csv(fetch, hdr, [[cal, "FETCH_SIZE", 2 ** 19], [upd, "FETCH_SIZE", 1000.0 * 0.5 * 1e6 / 1024],
+                            [dots, "FETCH_SIZE", 1500.0 * 0.5 * 1e6 / 1024]])
+    _write_csv(write, hdr, [[cal, "WRITE_SIZE", 2 ** 20], [upd, "WRITE_SIZE", 200.0 * 1e6 / 1024],
+                            [dots, "WRITE_SIZE", 0.0]])
+    timer = json.dumps({"profile_mixed": {}, "families": {
+        "update": {"launches": 3, "avg_launch_us": 1.0, "algorithmic_bytes_per_launch": 1200e6},
+        "dots": {"launches": 3, "avg_launch_us": 1.0, "algorithmic_bytes_per_launch": 1500e6}}})
+    bench.pmc_summary(str(fetch), str(write), str(out), "rocprofv3 --pmc COUNTER -- x", timer)
+    text = out.read_text()
+    assert "| update | 1 | 1000.0 | 200.0 | 1200.0 | 1.000 |" in text
+    assert "| dots | 1 | 1500.0 | 0.0 | 1500.0 | 1.000 |" in text
+    saved = bench.TRAFFIC_MD
+    try:
+        bench.TRAFFIC_MD = str(out)
+        assert bench.committed_traffic("update") == pytest.approx(1200e6)
+        assert bench.committed_traffic("dots") == pytest.approx(1500e6)
+        assert bench.committed_traffic("fine_gs") is None
+    finally:
+        bench.TRAFFIC_MD = saved
     # the stencil's summary on the same calibration, with a kernel trace for the duration
     st = "void amamg::k_wilson_apply<64, double, HIP_vector_type<double, 2u>, HIP_vector_type<double, 2u> >(...)"
     alg = bench.STENCIL_BYTES_PER_SITE["fp64"] * bench.STENCIL_L ** 2
