@@ -193,17 +193,20 @@ __global__ __launch_bounds__(256) void k_gram(KrylovDims dm, const double2* __re
   const double2* wr = HAS_W ? w + r * dm.n : nullptr;
 #pragma unroll 1
   for (int64_t d = int64_t(blockIdx.x) * EPB + threadIdx.x / S; d < dm.n; d += int64_t(gridDim.x) * EPB) {
+    // every lane loads, slots past the last clamped to it: their sums are never stored (only
+    // slots i < NV are), and a masked load would become a branch that waits for every load in
+    // flight.  The scheduling barrier keeps all of the element's loads ahead of the products, so
+    // that they are in flight together.
     double2 v[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int i = sub + S * k;
-      v[k] = i < NV ? stream_load(Vr + i * vsj + d) : make_double2(0, 0);
-    }
+    for (int k = 0; k < K; ++k)
+      v[k] = stream_load(Vr + (k + 1 < K ? sub + S * k : min(sub + S * k, NV - 1)) * vsj + d);
     const double2 ud = ur[d];
+    const double2 wd = HAS_W ? wr[d] : make_double2(0, 0);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k = 0; k < K; ++k) au[k] = cfmac(v[k], ud, au[k]);
     if constexpr (HAS_W) {
-      const double2 wd = wr[d];
 #pragma unroll
       for (int k = 0; k < K; ++k) aw[k] = cfmac(v[k], wd, aw[k]);
     }
