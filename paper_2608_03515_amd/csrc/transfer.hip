@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void k_restrict_partial_tiled(
 #pragma unroll
     for (int j = 0; j < RB; ++j) {
       const int rr = rb0 + SUB * j;
-      if (rr < ng && (!st || st[g0 + rr].active))
+      if (live[rr])
         part[((int64_t(g0 + rr) * nW + w) * nchunk + chunk) * NCOL + col] = acc[j];
     }
   }
@@ -368,7 +368,7 @@ __global__ __launch_bounds__(256) void k_restrict_mfma(
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int rr = wv * 16 + 4 * lk + i;
-    if (rr < ng && (!st || st[g0 + rr].active)) {
+    if (live[rr]) {
       float2* out = part + ((int64_t(g0 + rr) * nW + w) * nchunk + chunk) * NCOL + lr;
 #pragma unroll
       for (int t = 0; t < CT; ++t) out[t * 16] = make_float2(re[t][i], im[t][i]);
@@ -388,6 +388,7 @@ __global__ __launch_bounds__(256) void k_prolong_mfma(
   __shared__ float2 Pl[RCH * PS];
   __shared__ float2 El[kMfmaRhs * ES];
   __shared__ int ri[RCH];
+  __shared__ int live[kMfmaRhs];
   const int bid = xcd_block(blockIdx.x, gridDim.x);
   const int w = bid / nchunk, chunk = bid - (bid / nchunk) * nchunk;
   const int I = w / g.nJ, J = w - (w / g.nJ) * g.nJ;
@@ -395,6 +396,7 @@ __global__ __launch_bounds__(256) void k_prolong_mfma(
   const int r0 = chunk * RCH, cnt = max(0, min(nrows[w] - r0, RCH));
   const int nv_rows = chunk == 0 ? g.o * g.o * g.b : 0;
   for (int k = threadIdx.x; k < RCH; k += 256) ri[k] = k < cnt ? rows[int64_t(w) * maxrows + r0 + k] : 0;
+  for (int rr = threadIdx.x; rr < kMfmaRhs; rr += 256) live[rr] = rr < ng && (!st || st[g0 + rr].active);
   __syncthreads();
   stage<8, 256, float2>(RCH * NCOL, [&](int q) { return P[int64_t(ri[q / NCOL]) * NCOL + q % NCOL]; },
                         [&](int q, float2 v) { Pl[(q / NCOL) * PS + q % NCOL] = q / NCOL < cnt ? v : make_float2(0.f, 0.f); });
@@ -431,7 +433,7 @@ __global__ __launch_bounds__(256) void k_prolong_mfma(
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int rr = wv * 16 + 4 * lk + i;
-      if (rr >= ng || (st && !st[g0 + rr].active)) continue;
+      if (!live[rr]) continue;
       float2* yr = y + (g0 + rr) * stride_f;
       float2 v = make_float2(re[t][i], im[t][i]);
       if (add) v = cadd(v, yr[row]);
@@ -440,7 +442,7 @@ __global__ __launch_bounds__(256) void k_prolong_mfma(
   }
   for (int q = threadIdx.x; q < ng * nv_rows; q += 256) {
     const int rr = q / nv_rows, v = q - rr * nv_rows;   // (pt*o + px)*b + qq of node (I, J)
-    if (st && !st[g0 + rr].active) continue;
+    if (!live[rr]) continue;
     const int qq = v % g.b, pp = v / g.b;
     const int pt = pp / g.o, px = pp - (pp / g.o) * g.o;
     const int64_t vrow = int64_t((g.a * I + pt) * g.Lx + (g.a * J + px)) * g.b + qq;
