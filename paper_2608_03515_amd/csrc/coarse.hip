@@ -583,10 +583,12 @@ __global__ __launch_bounds__(256) void k_dense_apply_mfma(const double2* __restr
                                                           int n, int nrhs, int64_t stride,
                                                           const RhsState* __restrict__ st) {
   __shared__ double2 red[4][256];
+  __shared__ int live[16];                                 // the 16 rhs' flags, for the stores
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
   const int row0 = blockIdx.x * 16, r0 = blockIdx.y * 16;
   const int ra = r0 + lr;                                  // right-hand side of this lane's A values
   const bool alive = ra < nrhs && (!st || st[ra].active);
+  if (threadIdx.x < 16) live[threadIdx.x] = alive;
   const int rb = row0 + lr;                                // row of this lane's B values
   const bool blive = rb < n;
   const int kq = (((n + 3) / 4 + 3) / 4) * 4;              // k per wave
@@ -617,7 +619,7 @@ __global__ __launch_bounds__(256) void k_dense_apply_mfma(const double2* __restr
     double2 acc = red[0][i * 64 + lane];
     for (int q = 1; q < 4; ++q) acc = cadd(acc, red[q][i * 64 + lane]);
     const int r = r0 + 4 * i + lk, row = row0 + lr;
-    if (r < nrhs && row < n && (!st || st[r].active)) y[r * stride + row] = cconv<Vout>(acc);
+    if (live[4 * i + lk] && row < n) y[r * stride + row] = cconv<Vout>(acc);
   }
 }
 
