@@ -349,6 +349,42 @@ def test_batched_rhs_equal_to_single(lib, ctx):
     g.close()
 
 
+def test_zero_and_empty_right_hand_sides(lib, ctx):
+    """A zero right-hand side is solved by x = 0 with no iteration (the oracle's FGMRES stops
+    there too, before any step) and leaves the other right-hand sides of its batch bitwise as
+    they are alone; an empty batch is an argument error."""
+    w = synth.WORKLOADS["C1"]
+    g = make_gauge(lib, ctx, w.links(), w.m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=2, agg_size=4, overlap=1, n_test_vectors=4))
+    psi = synth.gaussian_rhs(w.L, w.L, 78, nrhs=3)
+    psi[1] = 0
+    _, oinfo = oracle_solve_zero(w)
+    assert oinfo.converged and oinfo.iterations == 0
+    for prec in (lib.FP64, lib.MIXED_FP32):
+        say("zero rhs", prec)
+        x, infos, st = h.solve(synth.field_to_abi(psi), lib.default_solve_params(precision=prec))
+        assert st == lib.OK
+        assert infos[1].converged and infos[1].iterations == 0 and infos[1].true_rel_residual == 0.0
+        assert not np.any(x[1])
+        for r in (0, 2):
+            x1, i1, _ = h.solve(synth.field_to_abi(psi[r:r + 1]), lib.default_solve_params(precision=prec))
+            assert i1[0].iterations == infos[r].iterations
+            assert np.array_equal(x1[0], x[r])
+    with pytest.raises(lib.AmamgError) as e:
+        h.solve(synth.field_to_abi(psi[:0]))
+    assert e.value.status == -1
+    h.close()
+    g.close()
+
+
+def oracle_solve_zero(w):
+    """The oracle's FGMRES on a zero right-hand side of workload w's lattice (no setup needed:
+    it returns before applying the operator or the preconditioner)."""
+    from oracle.fgmres import fgmres
+    n = w.L * w.L * 2
+    return fgmres(lambda v: v, np.zeros(n, dtype=complex), lambda v: v)
+
+
 def test_grouped_streams_equal_to_one_batch(lib, ctx):
     """groups > 1 splits the right-hand sides over batches on separate streams; each rhs's
     arithmetic is independent of the others (same reduction blocking at this size), so the
