@@ -221,6 +221,36 @@ def test_c1_fp64_solve_matches_oracle(lib, ctx):
     assert np.linalg.norm(r) / np.linalg.norm(psi) <= 1e-10
 
 
+def test_initial_guess_matches_oracle(lib, ctx):
+    """use_initial_guess: FGMRES starts from the caller's x0 (first residual b - D x0) on the GPU
+    as in the oracle: same iteration count and restarts, solution within 1e-9. A guess that
+    already meets the tolerance returns after no step, unchanged."""
+    from oracle.fgmres import fgmres
+    w = synth.WORKLOADS["C1"]
+    say("C1 initial guess")
+    U = w.links()
+    psi = synth.gaussian_rhs(w.L, w.L, w.rhs_seed)[0]
+    x0 = 0.25 * synth.gaussian_rhs(w.L, w.L, 4242)[0]
+    prm = amg.SetupParams(levels=w.levels, agg=w.agg, overlap=w.overlap, n_test_vectors=w.n_test_vectors)
+    _, _, olevels = oracle_solve(U, w.m0, psi, prm)
+    xo, io = fgmres(lambda v: olevels[0].A @ v, psi.reshape(-1), lambda v: amg.vcycle(olevels, 0, v, prm),
+                    m=20, tol=1e-10, x0=x0.reshape(-1))
+    assert io.converged and io.iterations > 0
+    g = make_gauge(lib, ctx, U, w.m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=w.levels, agg_size=w.agg, overlap=w.overlap,
+                                                   n_test_vectors=w.n_test_vectors))
+    x, infos, st = h.solve(synth.field_to_abi(psi[None]), x0=synth.field_to_abi(x0[None]))
+    assert st == lib.OK and infos[0].converged
+    assert infos[0].iterations == io.iterations and infos[0].restarts == io.restarts
+    assert rel(synth.field_from_abi(x)[0], xo.reshape(psi.shape)) <= 1e-9
+    # the converged solution as the guess: nothing to do
+    x2, infos2, st2 = h.solve(synth.field_to_abi(psi[None]), x0=x)
+    assert st2 == lib.OK and infos2[0].converged and infos2[0].iterations == 0
+    assert np.array_equal(x2, x)
+    h.close()
+    g.close()
+
+
 def test_c2_fp64_mass_sweep_matches_oracle(lib, ctx):
     w = synth.WORKLOADS["C2"]
     mc = synth.critical_masses()["C2"]
