@@ -251,6 +251,39 @@ def test_initial_guess_matches_oracle(lib, ctx):
     g.close()
 
 
+def test_link_and_mass_update_then_resetup_equals_a_fresh_hierarchy(lib, ctx):
+    """amamg_gauge_update_links + amamg_gauge_set_mass + amamg_hierarchy_update on a live gauge
+    and hierarchy give bitwise the solve of a new gauge and hierarchy built from the new links
+    and mass (no state of the old field survives), which matches the oracle's solve."""
+    w = synth.WORKLOADS["C1"]
+    say("link and mass update")
+    U1 = w.links()
+    U2 = synth.gen_links(w.L, w.L, 2.0, 50, 777)
+    m2 = 0.15
+    psi = synth.gaussian_rhs(w.L, w.L, 91, nrhs=2)
+    sp = dict(levels=w.levels, agg_size=w.agg, overlap=w.overlap, n_test_vectors=w.n_test_vectors)
+    g = make_gauge(lib, ctx, U1, w.m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(**sp))
+    h.solve(synth.field_to_abi(psi))
+    g.update_links(synth.links_to_abi(U2))
+    g.set_mass(m2)
+    h.update()
+    x, infos, st = h.solve(synth.field_to_abi(psi))
+    g2 = make_gauge(lib, ctx, U2, m2)
+    h2 = lib.Hierarchy(g2, lib.default_setup_params(**sp))
+    x2, infos2, _ = h2.solve(synth.field_to_abi(psi))
+    assert st == lib.OK
+    assert [i.iterations for i in infos] == [i.iterations for i in infos2]
+    assert np.array_equal(x, x2)
+    prm = amg.SetupParams(levels=w.levels, agg=w.agg, overlap=w.overlap, n_test_vectors=w.n_test_vectors)
+    xo, io, _ = oracle_solve(U2, m2, psi[0], prm)
+    assert infos[0].iterations == io.iterations
+    assert rel(synth.field_from_abi(x)[0], xo) <= 1e-9
+    for hh, gg in ((h, g), (h2, g2)):
+        hh.close()
+        gg.close()
+
+
 def test_c2_fp64_mass_sweep_matches_oracle(lib, ctx):
     w = synth.WORKLOADS["C2"]
     mc = synth.critical_masses()["C2"]
