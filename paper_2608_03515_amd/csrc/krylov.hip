@@ -86,7 +86,17 @@ __device__ inline void sum_blocks(const double2* __restrict__ part_r, int nblk, 
     double2 q[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) q[u] = make_double2(0, 0);
-    for (int b = c; b < nblk; b += 64) {
+    // groups of 64 blocks that are all present take their eight loads at once; the last,
+    // partial group masks them (each q[u] still adds its blocks in increasing order)
+    int b = c;
+    for (; b + 56 < nblk; b += 64) {
+      double2 pv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) pv[u] = part_r[int64_t(b + 8 * u) * STRIDE + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) q[u] = cadd(q[u], pv[u]);
+    }
+    if (b < nblk) {
 #pragma unroll
       for (int u = 0; u < 8; ++u)
         if (b + 8 * u < nblk) q[u] = cadd(q[u], part_r[int64_t(b + 8 * u) * STRIDE + i]);
