@@ -676,6 +676,17 @@ __global__ __launch_bounds__(kCgThreads) void k_coarsest_gmres(const double2* __
   const Vin* fr = f + int64_t(r) * stride;
   Vout* xr = x + int64_t(r) * stride;
   double2 w[kCgRows];
+  // Loads in the loops below are unconditional, from clamped rows, so that no branch separates
+  // them; the entries of rows past n are set to zero after each loop and never stored.
+  int crow[kCgRows], mrow[kCgRows];
+  bool own[kCgRows], mown[kCgRows];
+#pragma unroll
+  for (int i = 0; i < kCgRows; ++i) {
+    own[i] = t + kCgThreads * i < n;
+    crow[i] = own[i] ? t + kCgThreads * i : n - 1;
+    mown[i] = rl + RT * i < n;
+    mrow[i] = mown[i] ? rl + RT * i : n - 1;
+  }
   // beta = ||f||
   double2 acc = make_double2(0, 0);
 #pragma unroll
@@ -717,16 +728,30 @@ __global__ __launch_bounds__(kCgThreads) void k_coarsest_gmres(const double2* __
     double2 a[kCgRows];
 #pragma unroll
     for (int i = 0; i < kCgRows; ++i) a[i] = make_double2(0, 0);
-#pragma unroll 8
-    for (int q = q0; q < q1; ++q) {
-      const double2 xq = xs[q];
-      const double2* col = Acm + int64_t(q) * n;
+    // four columns' loads at a time, then their products in column order
+    int q = q0;
+    for (; q + 4 <= q1; q += 4) {
+      double2 cv[4][kCgRows];
 #pragma unroll
-      for (int i = 0; i < kCgRows; ++i) {
-        const int row = rl + RT * i;
-        if (row < n) a[i] = cfma(col[row], xq, a[i]);
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int i = 0; i < kCgRows; ++i) cv[u][i] = Acm[int64_t(q + u) * n + mrow[i]];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double2 xq = xs[q + u];
+#pragma unroll
+        for (int i = 0; i < kCgRows; ++i) a[i] = cfma(cv[u][i], xq, a[i]);
       }
     }
+    for (; q < q1; ++q) {
+      const double2 xq = xs[q];
+#pragma unroll
+      for (int i = 0; i < kCgRows; ++i) a[i] = cfma(Acm[int64_t(q) * n + mrow[i]], xq, a[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < kCgRows; ++i)
+      if (!mown[i]) a[i] = make_double2(0, 0);
     if (S == 1) {                                        // RT = 1024: rl = t, rows are the owned ones
 #pragma unroll
       for (int i = 0; i < kCgRows; ++i) w[i] = a[i];
@@ -745,10 +770,7 @@ __global__ __launch_bounds__(kCgThreads) void k_coarsest_gmres(const double2* __
         const double2* vl = Vb + int64_t(l) * n;
         double2 p = make_double2(0, 0);
 #pragma unroll
-        for (int i = 0; i < kCgRows; ++i) {
-          const int row = t + kCgThreads * i;
-          if (row < n) p = cfmac(vl[row], w[i], p);
-        }
+        for (int i = 0; i < kCgRows; ++i) p = cfmac(vl[crow[i]], w[i], p);   // w = 0 past n
         cg_wave_part(p, part, l, lane, wv);
       }
       __syncthreads();
@@ -762,11 +784,11 @@ __global__ __launch_bounds__(kCgThreads) void k_coarsest_gmres(const double2* __
         const double2* vl = Vb + int64_t(l) * n;
         const double2 h = hp[l];
 #pragma unroll
-        for (int i = 0; i < kCgRows; ++i) {
-          const int row = t + kCgThreads * i;
-          if (row < n) w[i] = cfma(vl[row], make_double2(-h.x, -h.y), w[i]);
-        }
+        for (int i = 0; i < kCgRows; ++i) w[i] = cfma(vl[crow[i]], make_double2(-h.x, -h.y), w[i]);
       }
+#pragma unroll
+      for (int i = 0; i < kCgRows; ++i)
+        if (!own[i]) w[i] = make_double2(0, 0);
       __syncthreads();                                   // hp and part are rewritten next
     }
     // h_{j+1,j} = ||w||
@@ -840,10 +862,7 @@ __global__ __launch_bounds__(kCgThreads) void k_coarsest_gmres(const double2* __
     const double2* vl = Vb + int64_t(l) * n;
     const double2 y = hp[l];
 #pragma unroll
-    for (int i = 0; i < kCgRows; ++i) {
-      const int row = t + kCgThreads * i;
-      if (row < n) xv[i] = cfma(vl[row], y, xv[i]);
-    }
+    for (int i = 0; i < kCgRows; ++i) xv[i] = cfma(vl[crow[i]], y, xv[i]);
   }
 #pragma unroll
   for (int i = 0; i < kCgRows; ++i) {
