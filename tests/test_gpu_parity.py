@@ -809,11 +809,12 @@ def graph_runs(lib, h, psi, coarsest_tol):
 
 def test_c3_full_size_solve_in_bench_configuration(lib):
     """The 256^2 workload in the benchmark's launch configuration: 64 right-hand sides in two
-    stream groups on a non-null stream, FP64 and mixed.  Right-hand side 0 against the oracle's
-    stored FP64 solve (tests/golden/c3_solve.json, written by make_golden.py from the oracle
-    alone): iteration and restart counts exact, sampled solution entries and the first residual
-    history values within the FP64 bars.  Every right-hand side: the true residual recomputed on
-    the CPU with the oracle's operator <= 1e-10, and mixed within 1e-9 of FP64."""
+    stream groups on a non-null stream, FP64, mixed and mixed with BF16 smoother links.
+    Right-hand side 0 against the oracle's stored FP64 solve (tests/golden/c3_solve.json,
+    written by make_golden.py from the oracle alone): iteration and restart counts exact, sampled
+    solution entries and the first residual history values within the FP64 bars.  Every
+    right-hand side: the true residual recomputed on the CPU with the oracle's operator <= 1e-10,
+    mixed within 1e-9 and BF16 links within 1e-8 of FP64."""
     import json
     import os
     import torch
@@ -830,7 +831,7 @@ def test_c3_full_size_solve_in_bench_configuration(lib):
     h = lib.Hierarchy(g, lib.default_setup_params(levels=w.levels, agg_size=w.agg, overlap=w.overlap,
                                                    n_test_vectors=w.n_test_vectors))
     out = {}
-    for prec in (lib.FP64, lib.MIXED_FP32):
+    for prec in (lib.FP64, lib.MIXED_FP32, lib.MIXED_FP32_BF16LINKS):
         say("C3 full size", prec)
         x, infos, st = h.solve(synth.field_to_abi(psi), lib.default_solve_params(precision=prec, groups=2))
         assert st == lib.OK
@@ -850,10 +851,12 @@ def test_c3_full_size_solve_in_bench_configuration(lib):
     assert np.allclose(hist[:len(gh)], gh, rtol=1e-6, atol=1e-14)
     D = dirac_matrix(U, m0)
     x32, i32, _ = out[lib.MIXED_FP32]
+    x16, i16, _ = out[lib.MIXED_FP32_BF16LINKS]
     for r in range(64):
         b = psi[r].reshape(-1)
-        for x, info in ((x64[r], i64[r]), (x32[r], i32[r])):
+        for x, info in ((x64[r], i64[r]), (x32[r], i32[r]), (x16[r], i16[r])):
             res = np.linalg.norm(b - D @ x.reshape(-1)) / np.linalg.norm(b)
             assert info.converged and res <= 1e-10 * (1 + 1e-6), (r, res)
             assert abs(res - info.true_rel_residual) <= 1e-2 * res      # rounding of b - D x
         assert rel(x32[r], x64[r]) <= 1e-9
+        assert rel(x16[r], x64[r]) <= 1e-8
