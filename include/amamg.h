@@ -147,26 +147,35 @@ amamg_status amamg_setup(amamg_gauge *g, const amamg_setup_params *params, amamg
 amamg_status amamg_hierarchy_update(amamg_hierarchy *h);
 amamg_status amamg_hierarchy_destroy(amamg_hierarchy *h);
 
-/* Solve D x = psi for nrhs right-hand sides (host pointers, layout above).  info: array of
- * nrhs entries (may be NULL).  Returns AMAMG_NOT_CONVERGED if any right-hand side hit the
- * iteration cap. */
+/* Solve D x = psi (Schwinger Model subsection: the Wilson-Dirac system) for nrhs right-hand
+ * sides with FGMRES right-preconditioned by the AM-AMG V-cycle (Multilevel approach: two-level
+ * scheme algorithm, applied recursively; Numerical Results: FGMRES to the relative tolerance,
+ * 2 post-smoothing steps).  psi, x: host pointers, layout above; x holds x0 on entry when
+ * params->use_initial_guess is set, else it is only written.  info: array of nrhs entries
+ * (may be NULL).  Returns AMAMG_NOT_CONVERGED if any right-hand side hit the iteration cap
+ * (x, info and the history are still written), AMAMG_ERR_NONFINITE for a non-finite psi
+ * (nothing written).  Blocks until the solve has finished. */
 amamg_status amamg_solve(amamg_hierarchy *h, int32_t nrhs, const double *psi, double *x,
                          const amamg_solve_params *params, amamg_solve_info *info);
-/* Same with device pointers (resident in HBM, same layout, 16-byte aligned, else
- * AMAMG_ERR_INVALID_ARG); runs on the context stream (and, with groups > 1, on streams the
- * hierarchy creates, ordered after the work already queued on the context stream) and
- * returns after the solve has finished. */
+/* Same solve on device pointers (resident in HBM, same layout, 16-byte aligned, else
+ * AMAMG_ERR_INVALID_ARG; they stay the caller's).  hip_stream: a hipStream_t whose queued work
+ * the solve must follow (it reads psi and x0 after that work), or NULL; the kernels run on
+ * the context stream (and, with groups > 1, on streams the hierarchy creates, ordered after
+ * the context stream).  Returns after the solve has finished, so work the caller queues on
+ * hip_stream afterwards sees x. */
 amamg_status amamg_solve_device(amamg_hierarchy *h, int32_t nrhs, const void *psi_dev,
                                 void *x_dev, const amamg_solve_params *params,
-                                amamg_solve_info *info);
+                                amamg_solve_info *info, void *hip_stream);
 
-/* Residual history of right-hand side `rhs` of the last solve: one entry per Arnoldi step
- * (the FGMRES estimate |g_{j+1}| / ||psi||) and one per cycle end (the true relative
- * residual, flagged 1 in is_true_residual).  Writes min(capacity, length) entries;
- * n_written receives the full length. */
+/* Residual history of right-hand side `rhs` of the last solve (FGMRES, Numerical Results:
+ * relative residual of the outer solver): one entry per Arnoldi step (the FGMRES estimate
+ * |g_{j+1}| / ||psi||) and one per cycle end (the true relative residual ||psi - D x|| /
+ * ||psi||, flagged 1 in is_true_residual).  Writes min(capacity, length) entries of out and
+ * of is_true_residual (either may be NULL); n_written (may be NULL) receives the full length.
+ * AMAMG_ERR_INVALID_ARG for an rhs outside the last solve. */
 amamg_status amamg_residual_history(const amamg_hierarchy *h, int32_t rhs, double *out,
-                                    int32_t *is_true_residual, int32_t capacity,
-                                    int32_t *n_written);
+                                    int32_t capacity, int32_t *n_written,
+                                    int32_t *is_true_residual);
 
 /* ---- measurement ------------------------------------------------------------------------- */
 typedef enum {
@@ -182,8 +191,9 @@ typedef enum {
 } amamg_kernel_family;
 /* Benchmark hook: from now on, bracket every solve-phase launch of the families whose bits
  * (1 << family) are set in family_mask (0 stops) with HIP events on the context stream, and
- * count algorithmic bytes: the bytes the operation must move once, per right-hand side it
- * served.  Resets all totals. */
+ * count algorithmic bytes: the bytes the operation must move once -- its fields per
+ * right-hand side it served, plus once per launch the operators all of them share (links,
+ * interpolation weights, coarse blocks).  Resets all totals. */
 amamg_status amamg_kernel_timer(amamg_context *ctx, uint32_t family_mask);
 /* Totals of one family since the last amamg_kernel_timer call: launches that served at least
  * one right-hand side, their summed event time in ms and their summed algorithmic bytes. */

@@ -110,8 +110,8 @@ _sig = {
     "amamg_hierarchy_update": (C.c_int, [_vp]),
     "amamg_hierarchy_destroy": (C.c_int, [_vp]),
     "amamg_solve": (C.c_int, [_vp, C.c_int32, _vp, _vp, _P(SolveParams), _P(SolveInfo)]),
-    "amamg_solve_device": (C.c_int, [_vp, C.c_int32, _vp, _vp, _P(SolveParams), _P(SolveInfo)]),
-    "amamg_residual_history": (C.c_int, [_vp, C.c_int32, _vp, _vp, C.c_int32, _P(C.c_int32)]),
+    "amamg_solve_device": (C.c_int, [_vp, C.c_int32, _vp, _vp, _P(SolveParams), _P(SolveInfo), _vp]),
+    "amamg_residual_history": (C.c_int, [_vp, C.c_int32, _vp, C.c_int32, _P(C.c_int32), _vp]),
     "amamg_apply_dirac": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _vp]),
     "amamg_apply_dirac_device": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _vp]),
     "amamg_level_info": (C.c_int, [_vp, C.c_int32, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32)]),
@@ -291,21 +291,24 @@ class Hierarchy:
         self.ctx.check(st, ok=(OK, NOT_CONVERGED))
         return x, list(infos), st
 
-    def solve_device(self, psi_ptr: int, x_ptr: int, nrhs: int, params: SolveParams | None = None):
-        """Device solve on raw device pointers (e.g. torch ``data_ptr()``)."""
+    def solve_device(self, psi_ptr: int, x_ptr: int, nrhs: int, params: SolveParams | None = None,
+                     stream: int | None = None):
+        """Device solve on raw device pointers (e.g. torch ``data_ptr()``), after the work queued
+        on `stream` (a raw hipStream_t handle, or None)."""
         infos = (SolveInfo * nrhs)()
         st = _lib.amamg_solve_device(self.h, nrhs, _vp(psi_ptr), _vp(x_ptr),
-                                     C.byref(params) if params else None, infos)
+                                     C.byref(params) if params else None, infos,
+                                     _vp(stream) if stream else None)
         self.ctx.check(st, ok=(OK, NOT_CONVERGED))
         return list(infos), st
 
     def residual_history(self, rhs: int = 0):
         n = C.c_int32()
-        self.ctx.check(_lib.amamg_residual_history(self.h, rhs, None, None, 0, C.byref(n)))
+        self.ctx.check(_lib.amamg_residual_history(self.h, rhs, None, 0, C.byref(n), None))
         vals = np.zeros(n.value)
         flags = np.zeros(n.value, dtype=np.int32)
-        self.ctx.check(_lib.amamg_residual_history(self.h, rhs, _ptr(vals), _ptr(flags), n.value,
-                                                   C.byref(n)))
+        self.ctx.check(_lib.amamg_residual_history(self.h, rhs, _ptr(vals), n.value, C.byref(n),
+                                                   _ptr(flags)))
         return vals, flags.astype(bool)
 
     def level_info(self, level: int):

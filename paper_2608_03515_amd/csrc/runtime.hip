@@ -62,7 +62,8 @@ static int timer_event(KernelTimer& t, size_t idx) {
 // the fine restriction (two kernels) and the level-1 smoother's colour blocks (one or two
 // kernels) are bracketed by stream events.
 static bool bracketed(int family) { return family == AMAMG_KT_RESTRICT0 || family == AMAMG_KT_COARSE_GS; }
-int timer_start(amamg_context* ctx, hipStream_t s, int family, int step, int group, double bytes_per_rhs) {
+int timer_start(amamg_context* ctx, hipStream_t s, int family, int step, int group, double bytes_per_rhs,
+                double bytes_per_launch) {
   KernelTimer& t = ctx->timer;
   if (!(t.mask & (1u << family))) return -1;
   // event pairs are reused once their records have been flushed
@@ -71,7 +72,7 @@ int timer_start(amamg_context* ctx, hipStream_t s, int family, int step, int gro
   const int e0 = timer_event(t, slot), e1 = timer_event(t, slot + 1);
   if (bracketed(family)) HIPCHECK(hipEventRecord(t.events[e0], s));
   else timed_launch() = TimedLaunch{t.events[e0], t.events[e1]};
-  t.pending.push_back({e0, e1, step, family, group, bytes_per_rhs});
+  t.pending.push_back({e0, e1, step, family, group, bytes_per_rhs, bytes_per_launch});
   return int(t.pending.size()) - 1;
 }
 void timer_stop(amamg_context* ctx, hipStream_t s, int rec) {
@@ -603,19 +604,31 @@ amamg_status amamg_hierarchy_destroy(amamg_hierarchy* h) {
 }
 
 amamg_status amamg_solve_device(amamg_hierarchy* h, int32_t nrhs, const void* psi_dev, void* x_dev,
-                                const amamg_solve_params* params, amamg_solve_info* info) {
+                                const amamg_solve_params* params, amamg_solve_info* info, void* hip_stream) {
   if (!h) return AMAMG_ERR_INVALID_ARG;
-  if (!psi_dev || !x_dev) return fail(h->gauge->ctx, {AMAMG_ERR_INVALID_ARG, "null field pointer"});
+  amamg_context* ctx = h->gauge->ctx;
+  if (!psi_dev || !x_dev) return fail(ctx, {AMAMG_ERR_INVALID_ARG, "null field pointer"});
   if (!aligned16(psi_dev) || !aligned16(x_dev))
-    return fail(h->gauge->ctx, {AMAMG_ERR_INVALID_ARG, "field pointers must be 16-byte aligned"});
+    return fail(ctx, {AMAMG_ERR_INVALID_ARG, "field pointers must be 16-byte aligned"});
   amamg_solve_params p;
   if (params) p = *params;
   else amamg_default_solve_params(&p);
+  hipEvent_t ready = nullptr;
   try {
-    HIPCHECK(hipSetDevice(h->gauge->ctx->device));
-    return run_solve(h, nrhs, static_cast<const double2*>(psi_dev), static_cast<double2*>(x_dev), p, info);
+    HIPCHECK(hipSetDevice(ctx->device));
+    const hipStream_t caller = static_cast<hipStream_t>(hip_stream);
+    if (caller && caller != ctx->stream) {
+      // the solve reads psi and x0 after the work the caller queued on its stream
+      HIPCHECK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+      HIPCHECK(hipEventRecord(ready, caller));
+      HIPCHECK(hipStreamWaitEvent(ctx->stream, ready, 0));
+    }
+    const amamg_status st = run_solve(h, nrhs, static_cast<const double2*>(psi_dev), static_cast<double2*>(x_dev), p, info);
+    if (ready) (void)hipEventDestroy(ready);
+    return st;
   } catch (const Fail& f) {
-    return fail(h->gauge->ctx, f);
+    if (ready) (void)hipEventDestroy(ready);
+    return fail(ctx, f);
   }
 }
 
@@ -644,8 +657,8 @@ amamg_status amamg_solve(amamg_hierarchy* h, int32_t nrhs, const double* psi, do
   }
 }
 
-amamg_status amamg_residual_history(const amamg_hierarchy* h, int32_t rhs, double* out,
-                                    int32_t* is_true, int32_t capacity, int32_t* n_written) {
+amamg_status amamg_residual_history(const amamg_hierarchy* h, int32_t rhs, double* out, int32_t capacity,
+                                    int32_t* n_written, int32_t* is_true) {
   if (!h || rhs < 0 || rhs >= int(h->history.size())) return AMAMG_ERR_INVALID_ARG;
   const auto& v = h->history[rhs];
   if (n_written) *n_written = int32_t(v.size());
