@@ -97,8 +97,10 @@ struct Pool {
 };
 
 // Benchmark timer: HIP events around every launch of one kernel family in the solve.  A
-// launch's algorithmic bytes are its per-rhs bytes times the right-hand sides it served,
-// which the host learns at the end of each restart cycle of the batch (group) that ran it.
+// launch's algorithmic bytes are its per-rhs bytes (the fields it reads and writes) times the
+// right-hand sides it served, which the host learns at the end of each restart cycle of the
+// batch (group) that ran it, plus its per-launch bytes (operators every right-hand side shares:
+// links, interpolation weights, coarse blocks), counted once.
 // Launch-shape autotuner for kernels whose arithmetic does not depend on the launch shape (the
 // results are bitwise the same for every candidate).  Entries are keyed by what decides the best
 // shape: the tunable, the grid, block size, precision and batch size.
@@ -119,7 +121,7 @@ struct KernelTimer {
   static constexpr int NF = 8;
   uint32_t mask = 0;
   std::vector<hipEvent_t> events;
-  struct Rec { int e0, e1, step, family, group; double bytes_per_rhs; };
+  struct Rec { int e0, e1, step, family, group; double bytes_per_rhs, bytes_per_launch; };
   std::vector<Rec> pending;
   int64_t launches[NF] = {};
   double total_ms[NF] = {}, total_bytes[NF] = {};
@@ -236,7 +238,8 @@ void check_launch();
 bool finite_all(const double* v, size_t n);
 
 // kernel timer (the family's events are recorded on the stream `s` of the launch)
-int timer_start(amamg_context* ctx, hipStream_t s, int family, int step, int group, double bytes_per_rhs);
+int timer_start(amamg_context* ctx, hipStream_t s, int family, int step, int group, double bytes_per_rhs,
+                double bytes_per_launch = 0.0);
 void timer_stop(amamg_context* ctx, hipStream_t s, int rec);
 
 // setup with the hierarchy's mass h->m0, synchronous on `stream` (null: the context stream);

@@ -236,10 +236,11 @@ static void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x)
       stencil_apply(c.s, c.T, Ak, x, WL.tmp, f, g.Lt, g.Lx, g.b, c.nrhs, nd, st);
     restrict_(c.s, c.T, P, L.rows, L.nrows, L.nf, c.T, WL.tmp, WC.f, WL.rpart, g, c.nrhs, nd, ndc, st);
   } else {
+    // per rhs: the fine vector in, the coarse vector out; per launch: the owned rows' weights
     const double fb = fprec == F64 ? 16 : 8;
     const double owned = double(nd) * (1.0 - double(g.o * g.o) / double(g.a * g.a));
     const int rec = k == 0 ? timer_start(ctx, c.s, AMAMG_KT_RESTRICT0, c.step, c.group,
-                                         owned * (g.ncol() * cb + fb) + double(g.nI) * g.nJ * restrict_chunks(g, L.nf, c.T) * g.ncol() * cb)
+                                         double(nd) * fb + double(ndc) * cb, owned * g.ncol() * cb)
                            : -1;
     restrict_(c.s, c.T, P, L.rows, L.nrows, L.nf, fprec, f, WC.f, WL.rpart, g, c.nrhs, nd, ndc, st);
     timer_stop(ctx, c.s, rec);
@@ -250,18 +251,19 @@ static void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x)
   const bool fused = k == 0 && pre == 0 && (post == 1 || post == 2);
   {
     const double owned = double(nd) * (1.0 - double(g.o * g.o) / double(g.a * g.a));
+    // per rhs: the coarse vector in, the fine vector out; per launch: the owned rows' weights
     const int rec = k == 0 ? timer_start(ctx, c.s, AMAMG_KT_PROLONG0, c.step, c.group,
-                                         owned * g.ncol() * cb + double(nd) * cb + double(ndc) * cb)
+                                         double(nd) * cb + double(ndc) * cb, owned * g.ncol() * cb)
                            : -1;
     prolong(c.s, c.T, P, L.rows, L.nrows, L.nf, WC.x, fused ? WL.tmp : x, g, pre > 0 ? 1 : 0, c.nrhs, nd,
             ndc, st);
     timer_stop(ctx, c.s, rec);
   }
   if (fused) {
-    // per sweep: x (both colours in, own colours out) + b, FP64
+    // per rhs: the prolongated correction in, x out, b (FP64) in; per launch: the links
     const double cl = c.smooth_links == LINK_F64 ? 16 : c.smooth_links == LINK_F32 ? 8 : 4;
     const int rec = timer_start(ctx, c.s, AMAMG_KT_FINE_GS, c.step, c.group,
-                                double(g.nnode()) * (2 * 2 * cb + 2 * cl + 32));
+                                double(g.nnode()) * (2 * 2 * cb + 32), double(g.nnode()) * 2 * cl);
     wilson_gs_sweeps(c.s, c.smooth_links, U0, U1, c.T, WL.tmp, x, (const double2*)f, g.Lt, g.Lx, h->m0, post,
                      c.nrhs, nd, st, c.fine_tc);
     timer_stop(ctx, c.s, rec);
@@ -272,16 +274,19 @@ static void vcycle(const SolveCtx& c, int k, Real fprec, const void* f, void* x)
       const double cl = c.smooth_links == LINK_F64 ? 16 : c.smooth_links == LINK_F32 ? 8 : 4;
       for (int col = 0; col < 2; ++col) {
         const int rec = timer_start(ctx, c.s, AMAMG_KT_FINE_GS, c.step, c.group,
-                                    double(g.nnode()) * (2 * cb + 2 * cl + 16));
+                                    double(g.nnode()) * (2 * cb + 16), double(g.nnode()) * 2 * cl);
         wilson_gs(c.s, c.smooth_links, U0, U1, c.T, x, (const double2*)f, g.Lt, g.Lx, h->m0, col, c.nrhs, nd, st);
         timer_stop(ctx, c.s, rec);
       }
     } else {
       // the four colour blocks of the sweep order (four colours each)
       for (int qb = 0; qb < 4; ++qb) {
+        // per rhs: x of the whole level in, f in and x out at the block's four colours; per
+        // launch: those nodes' 25 stencil blocks and diagonal-block inverses
         const double ncn = double(g.nnode()) / 16.0;
         const int rec = k == 1 ? timer_start(ctx, c.s, AMAMG_KT_COARSE_GS, c.step, c.group,
-                                             4.0 * (ncn * 25.0 * g.b * g.b * cb + 2.0 * ncn * g.b * cb) + double(nd) * cb)
+                                             4.0 * 2.0 * ncn * g.b * cb + double(nd) * cb,
+                                             4.0 * ncn * 26.0 * g.b * g.b * cb)
                                : -1;
         stencil_gs_block(c.s, c.T, Ak, Dk, x, f, g.Lt, g.Lx, g.b, qb, c.nrhs, nd, st, c.gs_rb ? c.gs_rb[k] : 0,
                          h->prm.block_smoother);
@@ -514,7 +519,7 @@ template <typename F> static void timer_flush(amamg_context* ctx, int group, F s
     HIPCHECK(hipEventElapsedTime(&ms, t.events[r.e0], t.events[r.e1]));
     t.launches[r.family] += 1;
     t.total_ms[r.family] += ms;
-    t.total_bytes[r.family] += r.bytes_per_rhs * n;
+    t.total_bytes[r.family] += r.bytes_per_rhs * n + r.bytes_per_launch;
   }
   t.pending.resize(keep);
 }
@@ -621,7 +626,8 @@ void Batch::enqueue_cycle_kernels() {
     void* zj = (char*)ws->Z + size_t(j) * vsj * zs;
     c.step = j - 1;
     vcycle(c, 0, F64, uj, zj);
-    int rec = timer_start(ctx, s, AMAMG_KT_FINE_MATVEC, j - 1, group, double(nt) * nx * (2 * zs + 2 * cl + 32));
+    int rec = timer_start(ctx, s, AMAMG_KT_FINE_MATVEC, j - 1, group, double(nt) * nx * (2 * zs + 32),
+                          double(nt) * nx * 2 * cl);
     wilson_apply(s, c.mat_links, Um0, Um1, T, zj, F64, ws->w, nullptr, nt, nx, h->m0, ws->cap, n, st);
     timer_stop(ctx, s, rec);
     // Gram-Schmidt: family DOTS = the Gram passes (slots 0..j and w), family UPDATE = the
