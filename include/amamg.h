@@ -261,6 +261,22 @@ amamg_status amamg_get_coarse_operator(const amamg_hierarchy *h, int32_t level, 
  * device buffers.  AMAMG_ERR_INVALID_ARG for the coarsest level or a bad direction. */
 amamg_status amamg_apply_transfer(amamg_hierarchy *h, int32_t level, int32_t precision,
                                   int32_t direction, int32_t nrhs, const double *in, double *out);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): amamg_apply_transfer on device buffers, allocating
+ * nothing.  in_dev, out_dev: caller-owned device buffers, 16-byte aligned, [nrhs][n][2];
+ * direction 0 (out = P^H in): in double (FP64, as the V-cycle's fine restriction reads it),
+ * out in the precision's type (double for AMAMG_FP64, float for AMAMG_MIXED_FP32);
+ * direction 1 (out = P in): in and out in the precision's type.  Asynchronous on the context
+ * stream; the same kernels as amamg_apply_transfer, so bitwise its results.  The restriction's
+ * partial sums (bytes: complex size x nrhs x wirebaskets x row chunks x 4 o^2 b) go to a fixed
+ * library array of AMAMG_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; a call
+ * that needs more is refused with AMAMG_ERR_INVALID_ARG before any device work (split the
+ * right-hand sides).  Calls that overlap on one GPU (other contexts or streams) share that
+ * array and race: order them on one stream. */
+#define AMAMG_NOALLOC_SCRATCH_BYTES (64u << 20)
+amamg_status amamg_apply_transfer_noalloc(amamg_hierarchy *h, int32_t level, int32_t precision,
+                                          int32_t direction, int32_t nrhs, const void *in_dev,
+                                          void *out_dev);
 /* Post-smoothing sweeps of level `level` (not the coarsest) with the kernels the V-cycle of the
  * given precision runs (Numerical Results: block smoother; point-block multicolour Gauss-Seidel,
  * the fine level red-black, coarse levels 16 colours in the sweep order), in place:

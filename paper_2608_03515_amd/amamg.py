@@ -35,7 +35,7 @@ EXPORTED = ["amamg_default_setup_params", "amamg_default_solve_params", "amamg_c
             "amamg_residual_history", "amamg_apply_dirac", "amamg_apply_dirac_device",
             "amamg_level_info",
             "amamg_get_aggregates", "amamg_get_prolongator", "amamg_get_coarse_operator",
-            "amamg_get_test_vectors", "amamg_apply_transfer", "amamg_apply_smoother", "amamg_context_set_tuning",
+            "amamg_get_test_vectors", "amamg_apply_transfer", "amamg_apply_transfer_noalloc", "amamg_apply_smoother", "amamg_context_set_tuning",
             "amamg_tuning_entries", "amamg_kernel_timer", "amamg_kernel_timer_read",
             "amamg_server_default_params", "amamg_server_create", "amamg_server_destroy",
             "amamg_server_add_gauge", "amamg_server_submit", "amamg_server_poll", "amamg_server_wait",
@@ -120,6 +120,7 @@ _sig = {
     "amamg_get_coarse_operator": (C.c_int, [_vp, C.c_int32, _vp]),
     "amamg_get_test_vectors": (C.c_int, [_vp, C.c_int32, _vp]),
     "amamg_apply_transfer": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp, _vp]),
+    "amamg_apply_transfer_noalloc": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp, _vp]),
     "amamg_apply_smoother": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp, _vp]),
     "amamg_context_set_tuning": (C.c_int, [_vp, C.c_int32, C.c_int32]),
     "amamg_tuning_entries": (C.c_int, [_vp, _vp, C.c_int32, _P(C.c_int32)]),
@@ -372,6 +373,12 @@ class Hierarchy:
         self.ctx.check(_lib.amamg_apply_transfer(self.h, level, precision, direction, nrhs, _ptr(src),
                                                  _ptr(out)))
         return out[..., 0] + 1j * out[..., 1]
+
+    def transfer_noalloc(self, level: int, in_ptr: int, out_ptr: int, nrhs: int, direction: int,
+                         precision: int = 0):
+        """amamg_apply_transfer_noalloc on raw device pointers (asynchronous, allocates nothing)."""
+        self.ctx.check(_lib.amamg_apply_transfer_noalloc(self.h, level, precision, direction, nrhs,
+                                                         _vp(in_ptr), _vp(out_ptr)))
 
     def test_vectors(self, level: int, nv: int) -> np.ndarray:
         lt, lx, b = self.level_info(level)

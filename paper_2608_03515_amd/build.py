@@ -19,7 +19,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libamamg.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["fine.hip", "coarse.hip", "transfer.hip", "setup.hip", "krylov.hip", "runtime.hip",
-           "solve.hip", "server.hip"]
+           "solve.hip", "server.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-result",

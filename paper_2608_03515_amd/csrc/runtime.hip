@@ -485,6 +485,7 @@ amamg_status amamg_context_create(int device, void* hip_stream, amamg_context** 
     REQUIRE(device >= 0 && device < ndev, AMAMG_ERR_INVALID_ARG, "no such device");
     HIPCHECK(hipSetDevice(device));
     c->device = device;
+    noalloc_init(device);
     if (hip_stream) {
       c->stream = static_cast<hipStream_t>(hip_stream);
     } else {

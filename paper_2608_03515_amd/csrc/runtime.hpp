@@ -233,6 +233,8 @@ namespace amamg {
 namespace rt {
 
 amamg_status fail(amamg_context* ctx, const Fail& f);
+// device address of the no-allocation scratch array on `device` (current), looked up once
+void noalloc_init(int device);
 bool aligned16(const void* p);
 void check_launch();
 bool finite_all(const double* v, size_t n);
