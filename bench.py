@@ -167,20 +167,32 @@ def cpu_baseline(w, m0, gpu_iterations, budget_s=25.0):
                       "NumPy/SciPy FP64, sparse matvecs single-threaded"}
 
 
-def serve_leg(lib, n_requests, qps, n_configs=16, slots=16, instances=4, log_every=100):
+def generate_links(cfgs):
+    """Gauge fields of `cfgs` (Metropolis on the host cores), generated by forked workers.
+    Called before anything touches the GPU: a forked child of a process that has initialised
+    HIP is not allowed, and a fork-context pool leaves no helper process behind."""
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=min(16, len(cfgs)), mp_context=mp.get_context("fork")) as ex:
+        links = list(ex.map(synth.serving_links, cfgs))
+    return links, time.perf_counter() - t0
+
+
+def serve_leg(lib, n_requests, qps, n_configs=16, slots=16, instances=4, log_every=100, links=None):
     """Open-loop serving run on the continuous-batching server: Poisson arrivals at `qps`,
     each request on one of n_configs resident gauge fields (L in 32..512) with a per-request
     mass and 1..8 right-hand sides; mixed precision to 1e-10.  Latency = completion minus
     submission on the server clock (queueing and the solve).  Every hierarchy is built (and
     cached) before the timed stream starts."""
     import threading
-    from concurrent.futures import ProcessPoolExecutor
-    import multiprocessing as mp
     cfgs = synth.serving_configs(n_configs)
-    t0 = time.perf_counter()
-    with ProcessPoolExecutor(max_workers=min(16, len(cfgs)), mp_context=mp.get_context("spawn")) as ex:
-        links = list(ex.map(synth.serving_links, cfgs))
-    t_gen = time.perf_counter() - t0
+    if links is None:
+        t0 = time.perf_counter()                      # GPU already live: no fork, one process
+        links = [synth.serving_links(c) for c in cfgs]
+        t_gen = time.perf_counter() - t0
+    else:
+        links, t_gen = links
     srv = lib.Server(0, lib.default_server_params(slots=slots, max_instances=instances,
                                                   precision=lib.MIXED_FP32))
     gids = [srv.add_gauge(synth.links_to_abi(U)) for U in links]
@@ -246,14 +258,12 @@ def serve_leg(lib, n_requests, qps, n_configs=16, slots=16, instances=4, log_eve
             "lattices": sorted({c["L"] for c in cfgs}), "gauge_generation_s": t_gen}
 
 
-def multi_lattice_leg(lib, torch, ctx, groups, instances=8, slots=8, nrhs_per=8):
+def multi_lattice_leg(lib, torch, ctx, groups, instances=8, slots=8, nrhs_per=8, links=None):
     """(1) 64 right-hand sides on the 128^2 beta = 8 lattice at m0 = m_c + 0.01 as one batched
     solve (step = setup + solve, like the headline); (2) the 32 lattices of
     synth.multi_lattice_configs() (L in 32..256, beta in [2, 10], m0 = m_c + gap), nrhs_per
     right-hand sides each, submitted at once to the server in mixed precision: makespan cold
     (hierarchy builds included) and warm (hierarchies cached)."""
-    from concurrent.futures import ProcessPoolExecutor
-    import multiprocessing as mp
     out = {}
     w = synth.WORKLOADS["C4"]
     m0 = synth.critical_masses()["C4"] + w.gaps[0]
@@ -281,8 +291,7 @@ def multi_lattice_leg(lib, torch, ctx, groups, instances=8, slots=8, nrhs_per=8)
     del b, x
     cfgs = synth.multi_lattice_configs()
     mcs = synth.multi_lattice_critical()
-    with ProcessPoolExecutor(max_workers=16, mp_context=mp.get_context("spawn")) as ex:
-        links = list(ex.map(synth.serving_links, cfgs))
+    links = [synth.serving_links(c) for c in cfgs] if links is None else links[0]
     srv = lib.Server(0, lib.default_server_params(slots=slots, max_instances=instances, precision=lib.MIXED_FP32))
     gids = [srv.add_gauge(synth.links_to_abi(U)) for U in links]
     del links
@@ -668,11 +677,19 @@ def main():
               "(independent lattices and requests would run one per GPU).", file=sys.stderr)
         sys.exit(2)
 
+    # host-generated gauge fields of the serving and multi-lattice legs, before the GPU is touched
+    full = not (args.stencil_only or args.profile_mixed or args.serve_only or args.multi_only)
+    serve_links = multi_links = None
+    if args.serve_requests > 0 and (full or args.serve_only):
+        serve_links = generate_links(synth.serving_configs(16))
+    if (full and not args.no_multi and os.path.exists(synth.MULTI_CRITICAL_PATH)) or args.multi_only:
+        multi_links = generate_links(synth.multi_lattice_configs())
+
     import torch
     from paper_2608_03515_amd import amamg as lib
 
     if args.serve_only:
-        out = serve_leg(lib, args.serve_requests, args.serve_qps)
+        out = serve_leg(lib, args.serve_requests, args.serve_qps, links=serve_links)
         print(json.dumps({"serving": out}), flush=True)
         return
     if args.stencil_only:
@@ -692,7 +709,8 @@ def main():
         stream = torch.cuda.Stream()
         torch.cuda.set_stream(stream)
         ctx = lib.Context(0, stream.cuda_stream)
-        print(json.dumps({"multi_lattice": multi_lattice_leg(lib, torch, ctx, args.groups)}), flush=True)
+        print(json.dumps({"multi_lattice": multi_lattice_leg(lib, torch, ctx, args.groups, links=multi_links)}),
+              flush=True)
         return
 
     stream = torch.cuda.Stream()          # default priority; the library runs on it
@@ -795,7 +813,7 @@ def main():
                 "(python tests/golden/make_golden.py --multi-only)")
         else:
             try:
-                multi = multi_lattice_leg(lib, torch, ctx, args.groups)
+                multi = multi_lattice_leg(lib, torch, ctx, args.groups, links=multi_links)
             except Exception as e:          # an optional leg must not cost the headline line
                 multi = {"error": f"{type(e).__name__}: {e}"}
             log("multi-lattice", json.dumps(multi))
@@ -819,7 +837,7 @@ def main():
             variants = {"error": f"{type(e).__name__}: {e}"}
     serving = None
     if args.serve_requests > 0:
-        serving = serve_leg(lib, args.serve_requests, args.serve_qps)
+        serving = serve_leg(lib, args.serve_requests, args.serve_qps, links=serve_links)
         log("serving", json.dumps({k: serving[k] for k in ("p50_ms", "p99_ms", "solves_per_s", "ok")}))
     head = res["mixed"]
     line = {

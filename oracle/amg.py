@@ -11,11 +11,11 @@ Readings where the paper is silent (all also used by the GPU library):
   complement formulas (pinned in the tests); a row of P comes from the row's primary
   wirebasket, vertex rows are the identity onto their coarse node;
 * restriction is P^H (the complex form of the transpose used by the real K-formulation);
-* normalisation N, "a constant vector is interpolated as a constant vector", has three
-  modes: CONST (row sums of P equal 1, the literal rule), TESTVEC (the least-squares row
+* normalisation N (the paper scales the interpolation rows so that constants are reproduced)
+  has three modes: CONST (row sums of P equal 1, the literal rule), TESTVEC (the least-squares row
   scale that best reproduces smoothed random test vectors; equal to CONST for one test
   vector that is constant) and NONE;
-* smoother ("block solver as a smoother", 0 pre and 2 post sweeps): multicolour point-block
+* smoother (the paper smooths with its block solver, 0 pre and 2 post sweeps): multicolour point-block
   Gauss-Seidel; colours (t + x) mod 2 on the fine lattice, visited in increasing order, and
   (I mod 4) * 4 + (J mod 4) on coarse grids, visited in the order COARSE_ORDER, which takes the
   colours of each 2 x 2 block of the 4 x 4 colour pattern in a row (0, 1, 4, 5, then 2, 3, 6, 7,
