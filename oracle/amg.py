@@ -31,7 +31,7 @@ Readings where the paper is silent (all also used by the GPU library):
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 import scipy.linalg as sla
@@ -234,6 +234,28 @@ def setup(U: np.ndarray, m0: float, prm: SetupParams) -> list:
         A = (lev.P.conj().T @ lev.A @ lev.P).tocsr()
         Lt, Lx, b = Lt // a, Lx // a, o * o * b
     return levels
+
+
+def shift_mass(levels: list, U: np.ndarray, m0: float) -> list:
+    """The hierarchy `levels` (built at another bare mass) with its operators at bare mass m0.
+
+    Everything the setup derived from the old operator stays: the wirebaskets, the test vectors
+    and the interpolation P of every level.  The operators follow their definitions at the new
+    mass (Schwinger Model subsection for D; Multilevel approach section for the Galerkin
+    products): A_0 = D(m0), A_{k+1} = P_k^H A_k P_k with the kept P_k; the smoother blocks and
+    the coarsest factorisation are recomputed from them.
+    """
+    A = dirac_matrix(U, m0).tocsr()
+    out = []
+    for lev in levels:
+        new = replace(lev, A=A)
+        if lev.coarsest:
+            new.lu = sla.lu_factor(A.toarray())
+        else:
+            new.Dinv = diagonal_block_inverses(A, lev.nnode, lev.b)
+            A = (lev.P.conj().T @ A @ lev.P).tocsr()
+        out.append(new)
+    return out
 
 
 def vcycle(levels: list, k: int, f: np.ndarray, prm: SetupParams) -> np.ndarray:
