@@ -135,7 +135,7 @@ def cpu_baseline(w, m0, gpu_iterations, budget_s=25.0):
     from oracle.amg import SetupParams, setup, vcycle
     U = w.links()
     psi = synth.gaussian_rhs(w.L, w.L, w.rhs_seed)[0].reshape(-1)
-    prm = SetupParams(levels=w.levels, agg=w.agg, overlap=w.overlap, n_test_vectors=w.n_test_vectors)
+    prm = SetupParams(**w.oracle_kw())
     t0 = time.perf_counter()
     levs = setup(U, m0, prm)
     t_setup = time.perf_counter() - t0
@@ -179,12 +179,19 @@ def generate_links(cfgs):
     return links, time.perf_counter() - t0
 
 
-def serve_leg(lib, n_requests, qps, n_configs=16, slots=16, instances=4, log_every=100, links=None):
-    """Open-loop serving run on the continuous-batching server: Poisson arrivals at `qps`,
-    each request on one of n_configs resident gauge fields (L in 32..512) with a per-request
-    mass and 1..8 right-hand sides; mixed precision to 1e-10.  Latency = completion minus
-    submission on the server clock (queueing and the solve).  Every hierarchy is built (and
-    cached) before the timed stream starts."""
+def serve_leg(lib, n_requests, qps=None, n_configs=16, slots=16, instances=4, builders=4, load=0.7,
+              capacity_requests=200, log_every=250, links=None):
+    """Open-loop serving run on the continuous-batching server, mixed precision to 1e-10.
+
+    16 resident gauge fields (L_j = 32..512 by j mod 5, beta_j from 2 to 10), each with a
+    reference mass m_c + 0.0316 (the log-middle of the gap range) at which its hierarchy is set
+    up before timing; each request draws a field, m0 = m_c + gap with the gap log-uniform in
+    [0.01, 0.1] and 1..8 right-hand sides, and is solved with a hierarchy derived at its mass.
+    Capacity is measured first: `capacity_requests` requests of the same distribution
+    submitted at once, requests per second over their makespan.  Then n_requests Poisson
+    arrivals at load x capacity (or at `qps` when given).  Latency = completion minus
+    submission on the server clock (queueing, the derivation of the request's hierarchy and
+    the solve)."""
     import threading
     cfgs = synth.serving_configs(n_configs)
     if links is None:
@@ -193,25 +200,47 @@ def serve_leg(lib, n_requests, qps, n_configs=16, slots=16, instances=4, log_eve
         t_gen = time.perf_counter() - t0
     else:
         links, t_gen = links
-    srv = lib.Server(0, lib.default_server_params(slots=slots, max_instances=instances,
+    m_c = synth.serving_critical()
+    ref_gap = float(np.exp(0.5 * (np.log(synth.SERVING_GAPS[0]) + np.log(synth.SERVING_GAPS[1]))))
+    srv = lib.Server(0, lib.default_server_params(slots=slots, max_instances=instances, builders=builders,
                                                   precision=lib.MIXED_FP32))
     gids = [srv.add_gauge(synth.links_to_abi(U)) for U in links]
     del links
+    for k in range(len(cfgs)):
+        srv.set_reference_mass(gids[k], m_c[k] + ref_gap)
     setups = [lib.default_setup_params(**synth.serving_setup(c["L"])) for c in cfgs]
     # right-hand-side pools (8 Gaussian fields per configuration); requests copy slices of them
     pools = [synth.field_to_abi(synth.gaussian_rhs(c["L"], c["L"], c["seed"] + 77, nrhs=8)) for c in cfgs]
-    stream = synth.request_stream(n_requests, qps, len(cfgs))
-    # warm cache: one request per (configuration, mass) builds every hierarchy before timing
+
+    def submit(rq):
+        rng = np.random.default_rng(rq["seed"])
+        pick = rng.choice(8, rq["nrhs"], replace=False)
+        return srv.submit(gids[rq["config"]], rq["m0"], pools[rq["config"]][pick], setups[rq["config"]])
+
+    # warm cache: each field's hierarchy at its reference mass, built before timing
     t0 = time.perf_counter()
-    for k, c in enumerate(cfgs):
-        for m0 in synth.SERVING_MASSES:
-            srv.submit(gids[k], m0, pools[k][:1], setups[k])
+    for k in range(len(cfgs)):
+        srv.submit(gids[k], m_c[k] + ref_gap, pools[k][:1], setups[k])
     srv.wait(1800)
-    srv.poll(len(cfgs) * len(synth.SERVING_MASSES) + 1)
+    srv.poll(len(cfgs) + 1)
     warm = srv.stats()
     t_warm = time.perf_counter() - t0
     log(f"serving: {warm.setups} hierarchies built in {t_warm:.1f} s (setup {warm.setup_seconds:.1f} s, "
         f"longest {warm.setup_seconds_max:.2f} s)")
+    # capacity: a burst of requests of the same distribution, all submitted at once
+    burst = synth.near_critical_stream(capacity_requests, 1.0, m_c, seed=6007)
+    t0 = time.perf_counter()
+    for rq in burst:
+        submit(rq)
+    srv.wait(1800)
+    cap_done = [i for i, _ in srv.poll(len(burst) + 1)]
+    cap_span = max(i.t_done for i in cap_done) - min(i.t_submit for i in cap_done)
+    capacity = len(burst) / cap_span
+    rate = qps if qps else load * capacity
+    log(f"serving: capacity {capacity:.1f} requests/s ({sum(i.nrhs for i in cap_done) / cap_span:.1f} solves/s); "
+        f"stream at {rate:.1f} requests/s")
+    before = srv.stats()
+    stream = synth.near_critical_stream(n_requests, rate, m_c)
     lag = [0.0]
 
     def client():
@@ -222,9 +251,7 @@ def serve_leg(lib, n_requests, qps, n_configs=16, slots=16, instances=4, log_eve
                 time.sleep(delay)
             else:
                 lag[0] = max(lag[0], -delay)
-            rng = np.random.default_rng(rq["seed"])
-            pick = rng.choice(8, rq["nrhs"], replace=False)
-            srv.submit(gids[rq["config"]], rq["m0"], pools[rq["config"]][pick], setups[rq["config"]])
+            submit(rq)
             if log_every and (k + 1) % log_every == 0:
                 log(f"serving: submitted {k + 1}/{len(stream)}")
     th = threading.Thread(target=client)
@@ -243,18 +270,27 @@ def serve_leg(lib, n_requests, qps, n_configs=16, slots=16, instances=4, log_eve
     by_L = {}
     for i, rq in zip(sorted(infos, key=lambda i: i.id), stream):
         by_L.setdefault(cfgs[rq["config"]]["L"], []).append(i.t_done - i.t_submit)
-    return {"requests": len(infos), "ok": ok, "rhs": rhs, "qps": qps,
+    gaps = np.array([rq["m0"] - m_c[rq["config"]] for rq in stream])
+    return {"requests": len(infos), "ok": ok, "rhs": rhs,
+            "capacity_requests_per_s": capacity, "capacity_solves_per_s": sum(i.nrhs for i in cap_done) / cap_span,
+            "load": rate / capacity, "qps": rate,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_ms": float(lat.mean() * 1e3), "queue_p50_ms": float(np.percentile(queue, 50) * 1e3),
             "queue_p99_ms": float(np.percentile(queue, 99) * 1e3),
             "solves_per_s": rhs / span, "span_s": span,
             "p50_ms_by_L": {str(L): float(np.percentile(v, 50) * 1e3) for L, v in sorted(by_L.items())},
             "p99_ms_by_L": {str(L): float(np.percentile(v, 99) * 1e3) for L, v in sorted(by_L.items())},
+            "iterations_max": max(i.iterations for i in infos),
             "max_rel_residual": max(i.true_rel_residual for i in infos),
+            "gap_min_max": [float(gaps.min()), float(gaps.max())], "reference_gap": ref_gap,
             "warmup_setups": warm.setups, "warmup_s": t_warm, "setup_s_max": st.setup_seconds_max,
-            "setups_during_stream": st.setups - warm.setups, "evictions": st.evictions,
-            "peak_resident_GB": st.peak_resident_bytes / 1e9, "client_max_lag_ms": lag[0] * 1e3,
-            "slots": slots, "instances": instances, "configs": len(cfgs),
+            "setups_during_stream": st.setups - before.setups,
+            "derivations_during_stream": st.derivations - before.derivations,
+            "derive_s_mean": (st.derive_seconds - before.derive_seconds) / max(1, st.derivations - before.derivations),
+            "derive_s_max": st.derive_seconds_max, "evictions": st.evictions,
+            "peak_resident_GB": st.peak_resident_bytes / 1e9, "budget_GB": st.budget_bytes / 1e9,
+            "client_max_lag_ms": lag[0] * 1e3,
+            "slots": slots, "instances": instances, "builders": builders, "configs": len(cfgs),
             "lattices": sorted({c["L"] for c in cfgs}), "gauge_generation_s": t_gen}
 
 
@@ -268,8 +304,7 @@ def multi_lattice_leg(lib, torch, ctx, groups, instances=8, slots=8, nrhs_per=8,
     w = synth.WORKLOADS["C4"]
     m0 = synth.critical_masses()["C4"] + w.gaps[0]
     g = lib.Gauge(ctx, synth.links_to_abi(w.links()), m0)
-    h = lib.Hierarchy(g, lib.default_setup_params(levels=w.levels, agg_size=w.agg, overlap=w.overlap,
-                                                   n_test_vectors=w.n_test_vectors))
+    h = lib.Hierarchy(g, lib.default_setup_params(**w.setup_kw()))
     b = torch.from_numpy(synth.field_to_abi(synth.gaussian_rhs(w.L, w.L, w.rhs_seed, nrhs=64))).to("cuda")
     x = torch.zeros_like(b)
     dt, ts, infos, _ = run_steps(lib, torch, ctx, h, b, x, 64, lib.MIXED_FP32, 2, 1, groups=groups)
@@ -279,8 +314,7 @@ def multi_lattice_leg(lib, torch, ctx, groups, instances=8, slots=8, nrhs_per=8,
                                     "converged": all(i.converged for i in infos)}
     h.close()
     # the same with level 1 (16 x 16 nodes of 8 x 8 blocks) swept on matrix cores
-    h = lib.Hierarchy(g, lib.default_setup_params(levels=w.levels, agg_size=w.agg, overlap=w.overlap,
-                                                   n_test_vectors=w.n_test_vectors, block_smoother=1))
+    h = lib.Hierarchy(g, lib.default_setup_params(**w.setup_kw(block_smoother=1)))
     dt, ts, infos, _ = run_steps(lib, torch, ctx, h, b, x, 64, lib.MIXED_FP32, 2, 1, groups=groups)
     its = [i.iterations for i in infos]
     out["one_lattice_128_64rhs_matrix_core_smoother"] = {"solves_per_s": 128 / dt, "s_per_step": dt / 2,
@@ -333,7 +367,8 @@ def agg_sweep_leg(lib, torch, ctx, groups, nrhs=64):
     for levels, a, o in AGG_SWEEP:
         t0 = time.perf_counter()
         h = lib.Hierarchy(g, lib.default_setup_params(levels=levels, agg_size=a, overlap=o,
-                                                       n_test_vectors=w.n_test_vectors))
+                                                       n_test_vectors=w.n_test_vectors,
+                                                       test_vector_sweeps=w.test_vector_sweeps))
         torch.cuda.synchronize()
         t_first = time.perf_counter() - t0
         dt, ts, infos, _ = run_steps(lib, torch, ctx, h, b, x, nrhs, lib.MIXED_FP32, 1, 1, groups=groups)
@@ -342,6 +377,32 @@ def agg_sweep_leg(lib, torch, ctx, groups, nrhs=64):
                "first_setup_s": t_first, "iterations_min_max": [min(its), max(its)],
                "converged": all(i.converged for i in infos)}
         log("agg sweep", json.dumps(rec))
+        out.append(rec)
+        h.close()
+    g.close()
+    return out
+
+
+TV_SWEEPS = (4, 16, 32, 64, 128)
+
+
+def tv_sweep_leg(lib, torch, ctx, groups, nrhs=64):
+    """The smoother sweeps that relax the test vectors (the paper leaves their number open): the
+    256^2 workload's field and mass, 64 right-hand sides, mixed precision, setup + solve per
+    value."""
+    w = synth.WORKLOADS["C3"]
+    m0 = synth.critical_masses()["C3"] + w.gaps[0]
+    g = lib.Gauge(ctx, synth.links_to_abi(w.links()), m0)
+    b = torch.from_numpy(synth.field_to_abi(synth.gaussian_rhs(w.L, w.L, w.rhs_seed, nrhs=nrhs))).to("cuda")
+    x = torch.zeros_like(b)
+    out = []
+    for nu in TV_SWEEPS:
+        h = lib.Hierarchy(g, lib.default_setup_params(**w.setup_kw(test_vector_sweeps=nu)))
+        dt, ts, infos, _ = run_steps(lib, torch, ctx, h, b, x, nrhs, lib.MIXED_FP32, 1, 1, groups=groups)
+        its = [i.iterations for i in infos]
+        rec = {"test_vector_sweeps": nu, "solves_per_s": nrhs / dt, "setup_s": ts,
+               "iterations_min_max": [min(its), max(its)], "converged": all(i.converged for i in infos)}
+        log("test-vector sweeps", json.dumps(rec))
         out.append(rec)
         h.close()
     g.close()
@@ -387,8 +448,7 @@ def variants_leg(lib, torch, ctx, groups, nrhs=64):
     x = torch.zeros_like(b)
     out = []
     for name, kw in VARIANTS:
-        h = lib.Hierarchy(g, lib.default_setup_params(levels=w.levels, agg_size=w.agg, overlap=w.overlap,
-                                                       n_test_vectors=w.n_test_vectors, **kw))
+        h = lib.Hierarchy(g, lib.default_setup_params(**w.setup_kw(**kw)))
         dt, ts, infos, _ = run_steps(lib, torch, ctx, h, b, x, nrhs, lib.MIXED_FP32, 1, 1, groups=groups)
         its = [i.iterations for i in infos]
         rec = {"variant": name, "setup": kw, "solves_per_s": nrhs / dt, "setup_s": ts,
@@ -407,7 +467,7 @@ def flop_summary(w, iterations, s_per_step):
     the real K-formulation, other ensembles: not a like-for-like target)."""
     from paper_2608_03515_amd import flops
     geo = flops.levels_of(w.L, w.L, w.levels, w.agg, w.overlap)
-    st = flops.setup(geo, w.agg, w.overlap, w.n_test_vectors)
+    st = flops.setup(geo, w.agg, w.overlap, w.n_test_vectors, w.test_vector_sweeps)
     sv = [flops.solve(geo, w.agg, w.overlap, it, restart=w.restart) for it in iterations]
     total = st["total"] + sum(v["total"] for v in sv)
     mean_solve = sum(v["total"] for v in sv) / len(sv)
@@ -629,9 +689,10 @@ def main():
     ap.add_argument("--nrhs", type=int, default=64)
     ap.add_argument("--groups", type=int, default=2,
                     help="right-hand-side batches run concurrently on separate streams")
-    ap.add_argument("--serve-requests", type=int, default=300,
+    ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving leg (0: skip it)")
-    ap.add_argument("--serve-qps", type=float, default=8.0)
+    ap.add_argument("--serve-qps", type=float, default=None,
+                    help="arrival rate of the serving leg (default: 0.7 x its measured capacity)")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg")
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-lattice leg")
     ap.add_argument("--no-agg-sweep", action="store_true", help="skip the aggregate-size sweep")
@@ -646,6 +707,8 @@ def main():
                     help="kernel family of the roofline (default: the largest in an instrumented "
                          "one-stream step)")
     ap.add_argument("--workload", default="C3")
+    ap.add_argument("--tv-sweeps", type=int, default=None,
+                    help="smoother sweeps that relax the test vectors (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stencil", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="skip the single-rhs FP64 path")
@@ -716,14 +779,16 @@ def main():
     stream = torch.cuda.Stream()          # default priority; the library runs on it
     torch.cuda.set_stream(stream)
     w = synth.WORKLOADS[args.workload]
+    if args.tv_sweeps is not None:
+        import dataclasses
+        w = dataclasses.replace(w, test_vector_sweeps=args.tv_sweeps)
     m0 = synth.critical_masses()[w.name] + w.gaps[0] if w.m0 is None else w.m0
     log(f"workload {w.name}: L={w.L} beta={w.beta} m0={m0:.6f} levels={w.levels} a={w.agg} "
-        f"o={w.overlap} nrhs={args.nrhs}")
+        f"o={w.overlap} nu={w.test_vector_sweeps} nrhs={args.nrhs}")
     U = w.links()
     ctx = lib.Context(0, stream.cuda_stream)
     g = lib.Gauge(ctx, synth.links_to_abi(U), m0)
-    h = lib.Hierarchy(g, lib.default_setup_params(levels=w.levels, agg_size=w.agg, overlap=w.overlap,
-                                                   n_test_vectors=w.n_test_vectors))
+    h = lib.Hierarchy(g, lib.default_setup_params(**w.setup_kw()))
     psi = synth.gaussian_rhs(w.L, w.L, w.rhs_seed, nrhs=args.nrhs)
     b = torch.from_numpy(synth.field_to_abi(psi)).to("cuda")
     x = torch.zeros_like(b)
@@ -795,8 +860,7 @@ def main():
     roofline["measured_copy_GBs"] = copy_gbs
     roofline["frac_of_measured_copy"] = roofline["achieved"] / copy_gbs
     if not args.no_single:
-        h1 = lib.Hierarchy(g, lib.default_setup_params(levels=w.levels, agg_size=w.agg, overlap=w.overlap,
-                                                        n_test_vectors=w.n_test_vectors))
+        h1 = lib.Hierarchy(g, lib.default_setup_params(**w.setup_kw()))
         b1, x1 = b[:1].contiguous(), torch.zeros_like(b[:1])
         dt, ts, infos, _ = run_steps(lib, torch, ctx, h1, b1, x1, 1, lib.FP64, args.steps, args.warmup)
         res["fp64_single_rhs"] = summarize(dt, ts, infos, 1, args.steps)
@@ -829,6 +893,12 @@ def main():
             batches = batch_sweep_leg(lib, torch, ctx, h, w, args.groups)
         except Exception as e:              # an optional leg must not cost the headline line
             batches = {"error": f"{type(e).__name__}: {e}"}
+    tvs = None
+    if not args.no_variants:
+        try:
+            tvs = tv_sweep_leg(lib, torch, ctx, args.groups)
+        except Exception as e:              # an optional leg must not cost the headline line
+            tvs = {"error": f"{type(e).__name__}: {e}"}
     variants = None
     if not args.no_variants:
         try:
@@ -837,8 +907,12 @@ def main():
             variants = {"error": f"{type(e).__name__}: {e}"}
     serving = None
     if args.serve_requests > 0:
-        serving = serve_leg(lib, args.serve_requests, args.serve_qps, links=serve_links)
-        log("serving", json.dumps({k: serving[k] for k in ("p50_ms", "p99_ms", "solves_per_s", "ok")}))
+        try:
+            serving = serve_leg(lib, args.serve_requests, args.serve_qps, links=serve_links)
+            log("serving", json.dumps({k: serving[k] for k in ("p50_ms", "p99_ms", "solves_per_s", "ok",
+                                                                "capacity_requests_per_s")}))
+        except Exception as e:              # an optional leg must not cost the headline line
+            serving = {"error": f"{type(e).__name__}: {e}"}
     head = res["mixed"]
     line = {
         "metric": "solves/s to rel. residual 1e-10 at L=256 (mixed vs FP64); stencil GB/s; p99",
@@ -850,7 +924,7 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic quenched U(1) links (Metropolis), Gaussian right-hand sides",
         "config": {"workload": f"{w.L}x{w.L} beta={w.beta} m0=m_c+{w.gaps[0] if w.gaps else 0}, "
-                               f"{w.levels} levels a={w.agg} o={w.overlap} Nv={w.n_test_vectors}, "
+                               f"{w.levels} levels a={w.agg} o={w.overlap} Nv={w.n_test_vectors} nu={w.test_vector_sweeps}, "
                                f"FGMRES({w.restart}) to 1e-10; step = AM-AMG setup + solve of "
                                f"{args.nrhs} right-hand sides",
                    "nrhs": args.nrhs, "stream_groups": args.groups,
@@ -867,6 +941,7 @@ def main():
         "aggregate_sweep": agg,
         "operation_count": op_count,
         "paper_variants": variants,
+        "test_vector_sweeps": tvs,
         "batch_sweep": batches,
         "autotuner": ctx.tuning_entries(),
     }

@@ -145,6 +145,30 @@ amamg_status amamg_setup(amamg_gauge *g, const amamg_setup_params *params, amamg
  * first setup it allocates nothing.  Same errors as amamg_setup; on error the hierarchy must
  * not be used for solves until an update succeeds. */
 amamg_status amamg_hierarchy_update(amamg_hierarchy *h);
+/* Move a built hierarchy to bare mass m0 without a new setup.  The wirebaskets, test vectors
+ * and interpolation P_k built at the old mass are kept; the operators become those of the new
+ * mass: D(m0) on the fine level (Schwinger Model subsection: m0 enters D only on the diagonal)
+ * and A_{k+1} = P_k^H A_k P_k above (Multilevel approach: Galerkin operator), computed exactly
+ * as A_{k+1} + (m0 - m0_old) G_{k+1} with G_1 = P_0^H P_0 and G_{k+1} = P_k^H G_k P_k (built on
+ * the first call and kept with the hierarchy).  The smoother blocks, the coarsest inverse and
+ * the FP32 copies are recomputed; solves afterwards use m0.  The gauge's own mass is not
+ * changed.  Synchronous on the context stream; must not overlap a solve on this hierarchy.
+ * Errors: AMAMG_ERR_INVALID_ARG for a non-finite m0 (nothing changed); AMAMG_ERR_SINGULAR_LOCAL
+ * / AMAMG_ERR_SINGULAR_COARSEST when a diagonal block or the coarsest matrix is singular at
+ * m0: the hierarchy then holds the new operators and must be moved again (or updated) before
+ * the next solve. */
+amamg_status amamg_hierarchy_set_mass(amamg_hierarchy *h, double m0);
+/* A new hierarchy at bare mass m0 derived from `base` (same passages as set_mass): it shares
+ * base's wirebaskets, test vectors, interpolation and mass terms (read only; no copy) and owns
+ * its operators, smoother blocks, coarsest inverse and FP32 copies, so several masses of one
+ * gauge field can be solved at once for about the memory of their coarse operators.  Equal to
+ * a copy of base moved by amamg_hierarchy_set_mass(m0).  base must be a hierarchy made by
+ * amamg_setup; while derived hierarchies exist it cannot be destroyed, updated or moved
+ * (AMAMG_ERR_INVALID_ARG).  A derived hierarchy can be moved with set_mass, solved and
+ * destroyed, but not updated.  Synchronous on the context stream.  Errors as set_mass (on
+ * error nothing is created). */
+amamg_status amamg_hierarchy_derive_mass(amamg_hierarchy *base, double m0, amamg_hierarchy **out);
+/* INVALID_ARG while hierarchies derived from h exist. */
 amamg_status amamg_hierarchy_destroy(amamg_hierarchy *h);
 
 /* Solve D x = psi (Schwinger Model subsection: the Wilson-Dirac system) for nrhs right-hand
@@ -350,6 +374,9 @@ typedef struct {
                                /* instance workspace)                                          */
   double setup_seconds;        /* total and longest hierarchy build time                        */
   double setup_seconds_max;
+  int64_t derivations;         /* hierarchies derived at another mass (not counted in setups)  */
+  double derive_seconds;       /* total and longest derivation time                             */
+  double derive_seconds_max;
 } amamg_server_counters;
 
 void amamg_server_default_params(amamg_server_params *p);
@@ -360,6 +387,14 @@ amamg_status amamg_server_destroy(amamg_server *s);
 /* Copy a gauge field (layout above) to the device; gauge_id names it in requests. */
 amamg_status amamg_server_add_gauge(amamg_server *s, int32_t nt, int32_t nx, const double *links,
                                     int32_t *gauge_id);
+/* Give gauge gauge_id a reference mass: requests submitted on it afterwards are solved with a
+ * hierarchy set up once at m_ref and derived from it at each request's mass
+ * (amamg_hierarchy_derive_mass: interpolation from m_ref, operators at the request's mass,
+ * Multilevel approach section) instead of a setup per mass.  Which hierarchy a request gets
+ * depends only on its gauge, mass, setup parameters and this reference mass, so results stay
+ * bitwise the same alone and in any mix.  m_ref = NaN restores setups per mass (the default).
+ * INVALID_ARG for an unknown gauge or an infinite m_ref. */
+amamg_status amamg_server_set_reference_mass(amamg_server *s, int32_t gauge_id, double m_ref);
 /* Queue a request; setup NULL = amamg_default_setup_params. */
 amamg_status amamg_server_submit(amamg_server *s, int32_t gauge_id, double m0,
                                  const amamg_setup_params *setup, int32_t nrhs, const double *psi,

@@ -31,14 +31,14 @@ STATUS_CODES = {v: k for k, v in STATUS_NAMES.items()}
 EXPORTED = ["amamg_default_setup_params", "amamg_default_solve_params", "amamg_context_create",
             "amamg_context_destroy", "amamg_last_error", "amamg_gauge_load",
             "amamg_gauge_set_mass", "amamg_gauge_update_links", "amamg_gauge_destroy",
-            "amamg_setup", "amamg_hierarchy_update", "amamg_hierarchy_destroy", "amamg_solve", "amamg_solve_device",
+            "amamg_setup", "amamg_hierarchy_update", "amamg_hierarchy_set_mass", "amamg_hierarchy_derive_mass", "amamg_hierarchy_destroy", "amamg_solve", "amamg_solve_device",
             "amamg_residual_history", "amamg_apply_dirac", "amamg_apply_dirac_device",
             "amamg_level_info",
             "amamg_get_aggregates", "amamg_get_prolongator", "amamg_get_coarse_operator",
             "amamg_get_test_vectors", "amamg_apply_transfer", "amamg_apply_transfer_noalloc", "amamg_apply_smoother", "amamg_context_set_tuning",
             "amamg_tuning_entries", "amamg_kernel_timer", "amamg_kernel_timer_read",
             "amamg_server_default_params", "amamg_server_create", "amamg_server_destroy",
-            "amamg_server_add_gauge", "amamg_server_submit", "amamg_server_poll", "amamg_server_wait",
+            "amamg_server_add_gauge", "amamg_server_set_reference_mass", "amamg_server_submit", "amamg_server_poll", "amamg_server_wait",
             "amamg_server_stats", "amamg_server_last_error"]
 KT = {"off": 0, "fine_matvec": 1, "fine_gs": 2, "restrict0": 3, "prolong0": 4, "coarse_gs": 5,
       "dots": 6, "update": 7}
@@ -91,7 +91,8 @@ class ServerCounters(C.Structure):
                 ("hierarchy_bytes", C.c_uint64),
                 ("peak_resident_bytes", C.c_uint64), ("budget_bytes", C.c_uint64),
                 ("outstanding", C.c_int64), ("clock", C.c_double), ("last_estimate_bytes", C.c_uint64),
-                ("setup_seconds", C.c_double), ("setup_seconds_max", C.c_double)]
+                ("setup_seconds", C.c_double), ("setup_seconds_max", C.c_double),
+                ("derivations", C.c_int64), ("derive_seconds", C.c_double), ("derive_seconds_max", C.c_double)]
 
 
 _vp = C.c_void_p
@@ -108,6 +109,8 @@ _sig = {
     "amamg_gauge_destroy": (C.c_int, [_vp]),
     "amamg_setup": (C.c_int, [_vp, _P(SetupParams), _P(_vp)]),
     "amamg_hierarchy_update": (C.c_int, [_vp]),
+    "amamg_hierarchy_set_mass": (C.c_int, [_vp, C.c_double]),
+    "amamg_hierarchy_derive_mass": (C.c_int, [_vp, C.c_double, C.POINTER(_vp)]),
     "amamg_hierarchy_destroy": (C.c_int, [_vp]),
     "amamg_solve": (C.c_int, [_vp, C.c_int32, _vp, _vp, _P(SolveParams), _P(SolveInfo)]),
     "amamg_solve_device": (C.c_int, [_vp, C.c_int32, _vp, _vp, _P(SolveParams), _P(SolveInfo), _vp]),
@@ -130,6 +133,7 @@ _sig = {
     "amamg_server_create": (C.c_int, [C.c_int32, _P(ServerParams), _P(_vp)]),
     "amamg_server_destroy": (C.c_int, [_vp]),
     "amamg_server_add_gauge": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _P(C.c_int32)]),
+    "amamg_server_set_reference_mass": (C.c_int, [_vp, C.c_int32, C.c_double]),
     "amamg_server_submit": (C.c_int, [_vp, C.c_int32, C.c_double, _P(SetupParams), C.c_int32, _vp, _vp,
                                       _P(C.c_uint64)]),
     "amamg_server_poll": (C.c_int, [_vp, _P(RequestInfo), C.c_int32, _P(C.c_int32)]),
@@ -273,6 +277,18 @@ class Hierarchy:
     def update(self):
         """Re-run the setup in place from the gauge's current links and mass."""
         self.ctx.check(_lib.amamg_hierarchy_update(self.h))
+
+    def set_mass(self, m0: float):
+        """Move the hierarchy to bare mass m0, keeping its interpolation (no new setup)."""
+        self.ctx.check(_lib.amamg_hierarchy_set_mass(self.h, C.c_double(m0)))
+
+    def derive_mass(self, m0: float) -> "Hierarchy":
+        """A hierarchy at bare mass m0 sharing this one's interpolation (close it first)."""
+        h = _vp()
+        self.ctx.check(_lib.amamg_hierarchy_derive_mass(self.h, C.c_double(m0), C.byref(h)))
+        out = Hierarchy.__new__(Hierarchy)
+        out.gauge, out.ctx, out.h = self.gauge, self.ctx, h
+        return out
 
     def close(self):
         if self.h:
@@ -418,6 +434,11 @@ class Server:
         gid = C.c_int32()
         self._check(_lib.amamg_server_add_gauge(self.s, a.shape[1], a.shape[2], _ptr(a), C.byref(gid)))
         return gid.value
+
+    def set_reference_mass(self, gauge_id: int, m_ref: float):
+        """Later requests on the gauge use hierarchies derived from one set up at m_ref (NaN:
+        a setup per mass)."""
+        self._check(_lib.amamg_server_set_reference_mass(self.s, gauge_id, C.c_double(m_ref)))
 
     def submit(self, gauge_id: int, m0: float, psi: np.ndarray, setup: SetupParams | None = None) -> int:
         """psi: float64 [nrhs][nt][nx][2][2]; returns the request id.  The solution is returned

@@ -143,6 +143,8 @@ void probe_make(hipStream_t s, const Geom& gc, int pt, int px, int ct, int cx, d
 void probe_extract(hipStream_t s, const Geom& gc, int pt, int px, int ct, int cx,
                    const double2* u, double2* out, int dense);
 void cast_matrix(hipStream_t s, const double2* A, float2* out, int64_t n);
+// y += a x (complex arrays, real a)
+void axpy_real(hipStream_t s, double2* y, double a, const double2* x, int64_t n);
 
 // ---- Krylov (FP64) -----------------------------------------------------------------------
 // Reductions are per-block partials [rhs][nblk][32] (Gram pass: [rhs][nblk][64]); the consumer

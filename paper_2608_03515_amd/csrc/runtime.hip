@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -241,11 +242,111 @@ size_t setup_bytes(int nt, int nx, const amamg_setup_params& p) {
 // Buffers only the setup itself needs; with a scratch pool they live there (and are reused by
 // the next setup) instead of in the hierarchy.
 static bool setup_scratch(const char* name) {
-  static const char* names[] = {"A0", "d_offs5", "d_offs25", "L_tv", "Aug", "info", "Wc", "C_Adense",
+  static const char* names[] = {"A0", "d_offs5", "d_offs25", "L_tv", "Aug", "info", "Wc",
                                 "pe", "py", "pz", "pu", "ppart", "Dg", "dinfo", "LUc", "cinfo", "keep"};
   for (const char* n : names)
     if (std::strcmp(n, name) == 0) return true;
   return false;
+}
+
+uint64_t next_generation() {
+  static std::atomic<uint64_t> setups{0};   // unique over every hierarchy of the process
+  return ++setups;
+}
+
+// Galerkin product of level k's operator (mass = false) or of its mass term (mass = true: the
+// identity on level 0, G_k above) into `out` (level k + 1's stencil, or dense at the coarsest),
+// by probing: for every colour class of coarse nodes (periods >= 5), P^H (Op (P e)) with unit
+// vectors e on that class yields the blocks of the class's columns.
+static void probe_galerkin(amamg_hierarchy* h, int k, bool mass, double2* out, hipStream_t s, Pool& tmp) {
+  LevelData& L = h->lv[k];
+  LevelData& C = h->lv[k + 1];
+  const Geom& g = L.g;
+  const Geom& gc = C.g;
+  const bool dense = C.coarsest;
+  const int bc = g.bc;
+  const int64_t ndof = g.ndof(), ndof_c = gc.ndof();
+  const int pt = period_of(gc.Lt), px = period_of(gc.Lx);
+  amamg_gauge* gg = h->gauge;
+  const double2* U0 = gg->U;
+  const double2* U1 = gg->U + int64_t(gg->nt) * gg->nx;
+  if (dense) HIPCHECK(hipMemsetAsync(out, 0, sizeof(double2) * ndof_c * ndof_c, s));
+  else HIPCHECK(hipMemsetAsync(out, 0, sizeof(double2) * gc.nnode() * 25 * bc * bc, s));
+  double2* pe = tmp.get<double2>("pe", k, size_t(bc) * ndof_c);
+  double2* py = tmp.get<double2>("py", k, size_t(bc) * ndof);
+  double2* pz = tmp.get<double2>("pz", k, size_t(bc) * ndof);
+  double2* pu = tmp.get<double2>("pu", k, size_t(bc) * ndof_c);
+  double2* ppart = tmp.get<double2>("ppart", k, size_t(bc) * g.nI * g.nJ * restrict_chunks(g, L.nf, F64) * g.ncol());
+  for (int ct = 0; ct < pt; ++ct)
+    for (int cx = 0; cx < px; ++cx) {
+      probe_make(s, gc, pt, px, ct, cx, pe);
+      prolong(s, F64, L.P, L.rows, L.nrows, L.nf, pe, py, g, 0, bc, ndof, ndof_c, nullptr);
+      const double2* r = pz;
+      if (k == 0 && mass) r = py;
+      else if (k == 0)
+        wilson_apply(s, LINK_F64, U0, U1, F64, py, F64, pz, nullptr, g.Lt, g.Lx, h->m0, bc, ndof, nullptr);
+      else
+        stencil_apply(s, F64, mass ? L.G : L.A, py, pz, nullptr, g.Lt, g.Lx, g.b, bc, ndof, nullptr);
+      restrict_(s, F64, L.P, L.rows, L.nrows, L.nf, F64, r, pu, ppart, g, bc, ndof, ndof_c, nullptr);
+      probe_extract(s, gc, pt, px, ct, cx, pu, out, dense ? 1 : 0);
+    }
+  check_launch();
+}
+
+// Level k >= 1 from its operator: smoother blocks A_nn^-1 (non-coarsest) or the coarsest
+// inverse (and its column-major copy for the GMRES variant).  Temporaries from `tmp`, the
+// results from `keep` (where they are first allocated).
+static void finish_level(amamg_hierarchy* h, int k, hipStream_t s, Pool& tmp, Pool& keep) {
+  LevelData& C = h->lv[k];
+  const Geom& gc = C.g;
+  if (!C.coarsest) {
+    const int bc = gc.b, nnc = gc.nnode();
+    C.Dinv = keep.get<double2>("C_Dinv", k - 1, size_t(nnc) * bc * bc);
+    double2* Dg = tmp.get<double2>("Dg", k - 1, size_t(nnc) * bc * 2 * bc);
+    int* dinfo = tmp.get<int>("dinfo", k - 1, nnc);
+    aug_identity(s, C.A + 12 * bc * bc, int64_t(25) * bc * bc, bc, bc, Dg, nnc);
+    dense_solve(s, Dg, bc, bc, nnc, dinfo);
+    aug_extract(s, Dg, bc, bc, C.Dinv, nnc);
+    check_launch();
+    std::vector<int> hd(nnc);
+    HIPCHECK(hipMemcpyAsync(hd.data(), dinfo, sizeof(int) * nnc, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    for (int n = 0; n < nnc; ++n)
+      REQUIRE(hd[n] == 0, AMAMG_ERR_SINGULAR_LOCAL, "singular diagonal block on level " + std::to_string(k));
+  } else {
+    const int n = int(gc.ndof());
+    double2* LUc = tmp.get<double2>("LUc", k - 1, size_t(n) * 2 * n);
+    int* cinfo = tmp.get<int>("cinfo", k - 1, 1);
+    aug_identity(s, C.Adense, 0, n, n, LUc, 1);
+    dense_solve(s, LUc, n, n, 1, cinfo);
+    C.Ainv = h->mem.get<double2>("C_Ainv", k - 1, size_t(n) * n);
+    aug_extract(s, LUc, n, n, C.Ainv, 1);
+    check_launch();
+    int hc = 0;
+    HIPCHECK(hipMemcpyAsync(&hc, cinfo, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    REQUIRE(hc == 0, AMAMG_ERR_SINGULAR_COARSEST, "zero pivot in the coarsest factorisation");
+    if (h->prm.coarsest_tol > 0) {
+      C.Acm = h->mem.get<double2>("C_Acm", k - 1, size_t(n) * n);
+      transpose_dense(s, C.Adense, C.Acm, n);
+      check_launch();
+    }
+  }
+}
+
+// FP32 copies of level k's stencil and smoother blocks
+static void cast_level(amamg_hierarchy* h, int k, hipStream_t s) {
+  LevelData& L = h->lv[k];
+  if (L.A) {
+    const int64_t n = int64_t(L.g.nnode()) * 25 * L.g.b * L.g.b;
+    L.A32 = h->mem.get<float2>("L_A32", k, n);
+    cast_matrix(s, L.A, L.A32, n);
+  }
+  if (L.Dinv) {
+    const int64_t n = int64_t(L.g.nnode()) * L.g.b * L.g.b;
+    L.Dinv32 = h->mem.get<float2>("L_Dinv32", k, n);
+    cast_matrix(s, L.Dinv, L.Dinv32, n);
+  }
 }
 
 void run_setup(amamg_hierarchy* h, hipStream_t stream, Pool* scratch) {
@@ -345,74 +446,15 @@ void run_setup(amamg_hierarchy* h, hipStream_t stream, Pool* scratch) {
     normalise(s, g, L.P, L.owner, L.tv, Wc, nv, p.norm);
     check_launch();
 
-    // Galerkin operator by probing: for every colour class of coarse nodes (periods >= 5),
-    // A_c e = P^H (A (P e)) with unit vectors on that class yields the blocks of its columns.
+    // Galerkin operator by probing
     LevelData& C = h->lv[k + 1];
     const bool dense = C.coarsest;
     const int bc = g.bc;
     const int nnc = gc.nnode();
-    const int pt = period_of(gc.Lt), px = period_of(gc.Lx);
-    double2* out = nullptr;
-    if (dense) {
-      C.Adense = pool("C_Adense").get<double2>("C_Adense", k, size_t(ndof_c) * ndof_c);
-      out = C.Adense;
-      HIPCHECK(hipMemsetAsync(out, 0, sizeof(double2) * ndof_c * ndof_c, s));
-    } else {
-      C.A = pool("C_A").get<double2>("C_A", k, size_t(nnc) * 25 * bc * bc);
-      out = C.A;
-      HIPCHECK(hipMemsetAsync(out, 0, sizeof(double2) * nnc * 25 * bc * bc, s));
-    }
-    double2* pe = pool("pe").get<double2>("pe", k, size_t(bc) * ndof_c);
-    double2* py = pool("py").get<double2>("py", k, size_t(bc) * ndof);
-    double2* pz = pool("pz").get<double2>("pz", k, size_t(bc) * ndof);
-    double2* pu = pool("pu").get<double2>("pu", k, size_t(bc) * ndof_c);
-    double2* ppart = pool("ppart").get<double2>("ppart", k, size_t(bc) * g.nI * g.nJ * restrict_chunks(g, nf, F64) * g.ncol());
-    for (int ct = 0; ct < pt; ++ct)
-      for (int cx = 0; cx < px; ++cx) {
-        probe_make(s, gc, pt, px, ct, cx, pe);
-        prolong(s, F64, L.P, L.rows, L.nrows, L.nf, pe, py, g, 0, bc, ndof, ndof_c, nullptr);
-        if (k == 0)
-          wilson_apply(s, LINK_F64, U0, U1, F64, py, F64, pz, nullptr, g.Lt, g.Lx, h->m0, bc, ndof, nullptr);
-        else
-          stencil_apply(s, F64, L.A, py, pz, nullptr, g.Lt, g.Lx, g.b, bc, ndof, nullptr);
-        restrict_(s, F64, L.P, L.rows, L.nrows, L.nf, F64, pz, pu, ppart, g, bc, ndof, ndof_c, nullptr);
-        probe_extract(s, gc, pt, px, ct, cx, pu, out, dense ? 1 : 0);
-      }
-    check_launch();
-
-    // smoother blocks of the next level, or the coarsest inverse
-    if (!dense) {
-      C.Dinv = pool("C_Dinv").get<double2>("C_Dinv", k, size_t(nnc) * bc * bc);
-      double2* Dg = pool("Dg").get<double2>("Dg", k, size_t(nnc) * bc * 2 * bc);
-      int* dinfo = pool("dinfo").get<int>("dinfo", k, nnc);
-      aug_identity(s, C.A + 12 * bc * bc, int64_t(25) * bc * bc, bc, bc, Dg, nnc);
-      dense_solve(s, Dg, bc, bc, nnc, dinfo);
-      aug_extract(s, Dg, bc, bc, C.Dinv, nnc);
-      check_launch();
-      std::vector<int> hd(nnc);
-      HIPCHECK(hipMemcpyAsync(hd.data(), dinfo, sizeof(int) * nnc, hipMemcpyDeviceToHost, s));
-      HIPCHECK(hipStreamSynchronize(s));
-      for (int n = 0; n < nnc; ++n)
-        REQUIRE(hd[n] == 0, AMAMG_ERR_SINGULAR_LOCAL, "singular diagonal block on level " + std::to_string(k + 1));
-    } else {
-      const int n = int(ndof_c);
-      double2* LUc = pool("LUc").get<double2>("LUc", k, size_t(n) * 2 * n);
-      int* cinfo = pool("cinfo").get<int>("cinfo", k, 1);
-      aug_identity(s, C.Adense, 0, n, n, LUc, 1);
-      dense_solve(s, LUc, n, n, 1, cinfo);
-      C.Ainv = pool("C_Ainv").get<double2>("C_Ainv", k, size_t(n) * n);
-      aug_extract(s, LUc, n, n, C.Ainv, 1);
-      check_launch();
-      int hc = 0;
-      HIPCHECK(hipMemcpyAsync(&hc, cinfo, sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHECK(hipStreamSynchronize(s));
-      REQUIRE(hc == 0, AMAMG_ERR_SINGULAR_COARSEST, "zero pivot in the coarsest factorisation");
-      if (p.coarsest_tol > 0) {
-        C.Acm = h->mem.get<double2>("C_Acm", k, size_t(n) * n);
-        transpose_dense(s, C.Adense, C.Acm, n);
-        check_launch();
-      }
-    }
+    if (dense) C.Adense = h->mem.get<double2>("C_Adense", k, size_t(ndof_c) * ndof_c);
+    else C.A = pool("C_A").get<double2>("C_A", k, size_t(nnc) * 25 * bc * bc);
+    probe_galerkin(h, k, false, dense ? C.Adense : C.A, s, pool("pe"));
+    finish_level(h, k + 1, s, pool("Dg"), pool("C_Dinv"));
     W = Wc;
     // the next level's test vectors must outlive this iteration's temporaries
     if (nv > 0 && !dense) {
@@ -430,26 +472,103 @@ void run_setup(amamg_hierarchy* h, hipStream_t stream, Pool* scratch) {
       L.P32 = pool("L_P32").get<float2>("L_P32", k, n);
       cast_matrix(s, L.P, L.P32, n);
     }
-    if (L.A) {
-      const int64_t n = int64_t(L.g.nnode()) * 25 * L.g.b * L.g.b;
-      L.A32 = pool("L_A32").get<float2>("L_A32", k, n);
-      cast_matrix(s, L.A, L.A32, n);
-    }
-    if (L.Dinv) {
-      const int64_t n = int64_t(L.g.nnode()) * L.g.b * L.g.b;
-      L.Dinv32 = pool("L_Dinv32").get<float2>("L_Dinv32", k, n);
-      cast_matrix(s, L.Dinv, L.Dinv32, n);
-    }
+    cast_level(h, k, s);
   }
   check_launch();
   HIPCHECK(hipStreamSynchronize(s));
-  static std::atomic<uint64_t> setups{0};   // unique over every hierarchy of the process
-  h->generation = ++setups;
+  h->generation = next_generation();
+  h->mass_terms = false;
   if (scratch)
-    for (LevelData& L : h->lv) {
-      L.tv = nullptr;
-      L.Adense = nullptr;
+    for (LevelData& L : h->lv) L.tv = nullptr;
+}
+
+void ensure_mass_terms(amamg_hierarchy* h, hipStream_t stream) {
+  if (h->mass_terms) return;
+  hipStream_t s = stream ? stream : h->gauge->ctx->stream;
+  const int K = int(h->lv.size());
+  Pool tmp;   // probing temporaries, freed on return
+  // G_{k+1} = P_k^H G_k P_k with G_0 = I: the Galerkin images of the mass term
+  for (int k = 0; k + 1 < K; ++k) {
+    LevelData& C = h->lv[k + 1];
+    const Geom& gc = C.g;
+    const size_t cnt = C.coarsest ? size_t(gc.ndof()) * gc.ndof() : size_t(gc.nnode()) * 25 * gc.b * gc.b;
+    C.G = h->mem.get<double2>("C_G", k, cnt);
+    probe_galerkin(h, k, true, C.G, s, tmp);
+  }
+  HIPCHECK(hipStreamSynchronize(s));
+  h->mass_terms = true;
+}
+
+size_t derive_bytes(const amamg_hierarchy* h) {
+  size_t b = 0;
+  for (size_t k = 1; k < h->lv.size(); ++k) {
+    const Geom& gc = h->lv[k].g;
+    if (h->lv[k].coarsest) {
+      const size_t n = size_t(gc.ndof());
+      // matrix, inverse, column-major copy (GMRES variant), LU workspace [n][2n]
+      b += n * n * 16 * (h->prm.coarsest_tol > 0 ? 5 : 4);
+    } else {
+      const size_t nb = size_t(gc.nnode()) * gc.b * gc.b;
+      b += nb * 25 * (16 + 8) + nb * (16 + 8) + nb * 2 * 16 + size_t(gc.nnode()) * 4;
     }
+  }
+  return b;
+}
+
+amamg_hierarchy* derive_mass(amamg_hierarchy* base, double m0, hipStream_t stream) {
+  REQUIRE(base->mass_terms, AMAMG_ERR_INVALID_ARG, "internal: derive_mass needs the base's mass terms");
+  hipStream_t s = stream ? stream : base->gauge->ctx->stream;
+  std::unique_ptr<amamg_hierarchy> h(new amamg_hierarchy());
+  h->gauge = base->gauge;
+  h->prm = base->prm;
+  h->m0 = base->m0;
+  h->lv = base->lv;            // wirebaskets, interpolation, mass terms: shared
+  h->mass_terms = true;
+  // own copies of the operators at the base's mass; everything derived from them is rebuilt
+  for (size_t k = 1; k < h->lv.size(); ++k) {
+    LevelData& C = h->lv[k];
+    const Geom& gc = C.g;
+    if (C.coarsest) {
+      const size_t cnt = size_t(gc.ndof()) * gc.ndof();
+      C.Adense = h->mem.get<double2>("C_Adense", int(k) - 1, cnt);
+      HIPCHECK(hipMemcpyAsync(C.Adense, base->lv[k].Adense, sizeof(double2) * cnt, hipMemcpyDeviceToDevice, s));
+      C.Ainv = C.Acm = nullptr;
+    } else {
+      const size_t cnt = size_t(gc.nnode()) * 25 * gc.b * gc.b;
+      C.A = h->mem.get<double2>("C_A", int(k) - 1, cnt);
+      HIPCHECK(hipMemcpyAsync(C.A, base->lv[k].A, sizeof(double2) * cnt, hipMemcpyDeviceToDevice, s));
+      C.A32 = nullptr;
+      C.Dinv = nullptr;
+      C.Dinv32 = nullptr;
+    }
+  }
+  shift_mass(h.get(), m0, s);
+  h->base = base;                 // the caller counts it in base->derived and gauge->nhier
+  return h.release();
+}
+
+void shift_mass(amamg_hierarchy* h, double m0, hipStream_t stream) {
+  hipStream_t s = stream ? stream : h->gauge->ctx->stream;
+  const int K = int(h->lv.size());
+  Pool tmp;   // factorisation temporaries, freed on return
+  ensure_mass_terms(h, s);
+  const double dm = m0 - h->m0;
+  h->m0 = m0;
+  // the fine operator takes m0 directly; every coarser one moves by dm times its mass term
+  for (int k = 1; k < K; ++k) {
+    LevelData& C = h->lv[k];
+    const Geom& gc = C.g;
+    if (C.coarsest) axpy_real(s, C.Adense, dm, C.G, int64_t(gc.ndof()) * gc.ndof());
+    else axpy_real(s, C.A, dm, C.G, int64_t(gc.nnode()) * 25 * gc.b * gc.b);
+  }
+  check_launch();
+  h->generation = next_generation();     // before the checks: a failed move still invalidates graphs
+  for (int k = 1; k < K; ++k) {
+    finish_level(h, k, s, tmp, h->mem);
+    cast_level(h, k, s);
+  }
+  check_launch();
+  HIPCHECK(hipStreamSynchronize(s));
 }
 
 }  // namespace rt
@@ -587,6 +706,8 @@ amamg_status amamg_setup(amamg_gauge* g, const amamg_setup_params* params, amamg
 amamg_status amamg_hierarchy_update(amamg_hierarchy* h) {
   if (!h) return AMAMG_ERR_INVALID_ARG;
   amamg_gauge* g = h->gauge;
+  if (h->derived > 0) return fail(g->ctx, {AMAMG_ERR_INVALID_ARG, "hierarchies derived from this one still exist"});
+  if (h->base) return fail(g->ctx, {AMAMG_ERR_INVALID_ARG, "a derived hierarchy follows its base: derive it again"});
   try {
     HIPCHECK(hipSetDevice(g->ctx->device));
     h->m0 = g->m0;
@@ -597,8 +718,42 @@ amamg_status amamg_hierarchy_update(amamg_hierarchy* h) {
   return AMAMG_OK;
 }
 
+amamg_status amamg_hierarchy_set_mass(amamg_hierarchy* h, double m0) {
+  if (!h) return AMAMG_ERR_INVALID_ARG;
+  amamg_gauge* g = h->gauge;
+  if (!std::isfinite(m0)) return fail(g->ctx, {AMAMG_ERR_INVALID_ARG, "mass must be finite"});
+  if (h->derived > 0) return fail(g->ctx, {AMAMG_ERR_INVALID_ARG, "hierarchies derived from this one still exist"});
+  try {
+    HIPCHECK(hipSetDevice(g->ctx->device));
+    shift_mass(h, m0);
+  } catch (const Fail& f) {
+    return fail(g->ctx, f);
+  }
+  return AMAMG_OK;
+}
+
+amamg_status amamg_hierarchy_derive_mass(amamg_hierarchy* base, double m0, amamg_hierarchy** out) {
+  if (!base || !out) return base ? fail(base->gauge->ctx, {AMAMG_ERR_INVALID_ARG, "null argument"}) : AMAMG_ERR_INVALID_ARG;
+  *out = nullptr;
+  amamg_gauge* g = base->gauge;
+  if (!std::isfinite(m0)) return fail(g->ctx, {AMAMG_ERR_INVALID_ARG, "mass must be finite"});
+  if (base->base) return fail(g->ctx, {AMAMG_ERR_INVALID_ARG, "derive from the base hierarchy, not a derived one"});
+  try {
+    HIPCHECK(hipSetDevice(g->ctx->device));
+    ensure_mass_terms(base);
+    *out = derive_mass(base, m0);
+    base->derived += 1;
+    g->nhier += 1;
+  } catch (const Fail& f) {
+    return fail(g->ctx, f);
+  }
+  return AMAMG_OK;
+}
+
 amamg_status amamg_hierarchy_destroy(amamg_hierarchy* h) {
   if (!h) return AMAMG_ERR_INVALID_ARG;
+  if (h->derived > 0) return fail(h->gauge->ctx, {AMAMG_ERR_INVALID_ARG, "hierarchies derived from this one still exist"});
+  if (h->base) h->base->derived -= 1;
   h->gauge->nhier -= 1;
   delete h;
   return AMAMG_OK;

@@ -138,6 +138,8 @@ struct LevelData {
   double2* Adense = nullptr; // coarsest [n][n]
   double2* Ainv = nullptr;   // coarsest inverse [n][n]
   double2* Acm = nullptr;    // coarsest matrix, column-major [k][row] (GMRES variant only)
+  double2* G = nullptr;      // mass term: G_k = P^H G_{k-1} P, G_0 = I (stencil, or dense at the
+                             // coarsest; made by the first mass shift)
   // transfer to the next level (non-coarsest)
   int8_t* kind = nullptr;
   int* owner = nullptr;
@@ -225,7 +227,14 @@ struct amamg_hierarchy {
   std::vector<amamg::rt::Workspace*> ws;
   std::vector<hipStream_t> streams;
   std::vector<std::vector<double2>> history;
-  uint64_t generation = 0;  // number of its last setup, unique in the process (graphs key on it)
+  uint64_t generation = 0;  // number of its last setup or mass shift, unique in the process
+                            // (graphs key on it)
+  bool mass_terms = false;  // LevelData::G of every coarse level is current
+  // A derived hierarchy (derive_mass) shares its base's wirebaskets, interpolation and mass
+  // terms and owns only its operators; the base counts its derived hierarchies and may not be
+  // set up again, moved or destroyed while any exists.
+  amamg_hierarchy* base = nullptr;
+  int derived = 0;
   ~amamg_hierarchy();
 };
 
@@ -248,6 +257,21 @@ void timer_stop(amamg_context* ctx, hipStream_t s, int rec);
 // with `scratch`, the setup's temporary buffers come from that pool (kept for the next setup)
 // and the hierarchy holds only what the solve uses
 void run_setup(amamg_hierarchy* h, hipStream_t stream = nullptr, Pool* scratch = nullptr);
+// moves a built hierarchy to bare mass m0, keeping its wirebaskets, test vectors and
+// interpolation (A_k += (m0 - m0_old) G_k on every coarse level, then the smoother blocks, the
+// coarsest inverse and the FP32 copies again); synchronous on `stream` (null: context stream)
+void shift_mass(amamg_hierarchy* h, double m0, hipStream_t stream = nullptr);
+uint64_t next_generation();
+// the mass terms G_k of every coarse level (once per setup; shift_mass calls it too)
+void ensure_mass_terms(amamg_hierarchy* h, hipStream_t stream = nullptr);
+// a new hierarchy at bare mass m0 that shares base's wirebaskets, interpolation and mass terms
+// and owns its operators, smoother blocks and coarsest inverse; synchronous on `stream`.  base
+// must have its mass terms (ensure_mass_terms) and is only read; the caller adds the result to
+// base->derived and gauge->nhier.
+amamg_hierarchy* derive_mass(amamg_hierarchy* base, double m0, hipStream_t stream = nullptr);
+// device bytes a hierarchy derived from h holds (its operators, smoother blocks, coarsest
+// inverse and FP32 copies) plus the temporaries of its factorisations
+size_t derive_bytes(const amamg_hierarchy* h);
 // device bytes a hierarchy of these parameters holds after setup (estimate, for admission)
 size_t setup_bytes(int nt, int nx, const amamg_setup_params& p);
 

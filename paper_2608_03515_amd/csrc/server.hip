@@ -33,6 +33,7 @@ struct Request {
   uint64_t id = 0;
   int gauge = 0;
   double m0 = 0;
+  double ref = NAN;            // the gauge's reference mass at submission (NaN: none)
   amamg_setup_params sp{};
   int nrhs = 0;
   std::vector<double> psi;     // copied at submission: [nrhs][n] complex
@@ -48,18 +49,26 @@ struct CachedH {
   amamg_hierarchy* h = nullptr;
   int gauge = 0;
   double m0 = 0;
+  double ref = NAN;            // mass its interpolation was built at, when a reference mass
+                               // applies (NaN: a setup at m0 for requests without one)
   amamg_setup_params sp{};
   uint64_t last_use = 0;
   int users = 0;               // instances bound to it
   bool fresh = true;           // built, not bound yet: not evicted before its requests run
   size_t bytes = 0;
+  CachedH* base = nullptr;     // derived at another mass from this full setup (shares its data)
+  int derived = 0;             // cached hierarchies derived from this one
+  int pending = 0;             // derivations from this one in flight
 };
 
 // A hierarchy build handed to the builder thread, and its outcome.
 struct BuildJob {
+  uint64_t id = 0;
   int gauge = 0;
   double m0 = 0;
+  double ref = NAN;
   amamg_setup_params sp{};
+  CachedH* base = nullptr;     // non-null: derive from this hierarchy instead of a setup
   size_t need = 0;             // bytes reserved for it in the budget while it runs
   amamg_hierarchy* h = nullptr;
   amamg_status code = AMAMG_OK;
@@ -91,6 +100,8 @@ struct Instance {
   bool busy() const { return phase != IDLE || !reserved.empty(); }
 };
 
+bool same_ref(double a, double b) { return (std::isnan(a) && std::isnan(b)) || a == b; }
+
 bool same_params(const amamg_setup_params& a, const amamg_setup_params& b) {
   return a.levels == b.levels && a.agg_size == b.agg_size && a.overlap == b.overlap &&
          a.n_test_vectors == b.n_test_vectors && a.test_vector_sweeps == b.test_vector_sweeps &&
@@ -111,14 +122,16 @@ struct amamg_server {
   std::deque<Request*> incoming;
   std::deque<Request*> done;
   std::vector<amamg_gauge*> gauges;
+  std::vector<double> refs;           // reference mass per gauge (NaN: none)
+  uint64_t next_job = 1;
   std::deque<BuildJob> jobs, built;
   uint64_t next_id = 1;
   int64_t outstanding = 0;
   bool stop = false, stop_builder = false;
   std::string err;
-  int64_t setups = 0, evictions = 0;
+  int64_t setups = 0, evictions = 0, derivations = 0;
   size_t resident = 0, peak_resident = 0, last_estimate = 0, hier_bytes = 0;
-  double setup_seconds = 0, setup_seconds_max = 0;
+  double setup_seconds = 0, setup_seconds_max = 0, derive_seconds = 0, derive_seconds_max = 0;
   // worker only
   std::thread worker;
   std::deque<Request*> queue;
@@ -179,29 +192,53 @@ void finish(amamg_server* S, Request* R) {
   S->cv_done.notify_all();
 }
 
-// Drop least recently used hierarchies that no instance holds until `need` more bytes fit.
-bool make_room(amamg_server* S, size_t need) {
+void drop(amamg_server* S, CachedH* victim) {
+  if (victim->base) {
+    victim->base->derived -= 1;
+    victim->h->base->derived -= 1;
+  }
+  victim->h->gauge->nhier -= 1;
+  delete victim->h;
+  S->cache.erase(std::find_if(S->cache.begin(), S->cache.end(),
+                              [&](const std::unique_ptr<CachedH>& c) { return c.get() == victim; }));
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->evictions += 1;
+}
+
+// Make `need` more bytes fit the budget: drop least recently used hierarchies that nothing
+// holds (no instance bound, no derived hierarchy or derivation depending on them), unbinding
+// idle instances and finally releasing idle instances' workspaces when nothing else is left.
+// `keep` (if any) is never released.
+bool make_room(amamg_server* S, size_t need, const Instance* keep = nullptr) {
   for (;;) {
     if (resident_bytes(S) + need <= S->prm.hbm_budget) return true;
     CachedH* victim = nullptr;
     for (const auto& c : S->cache)
-      if (c->users == 0 && !c->fresh && (!victim || c->last_use < victim->last_use)) victim = c.get();
-    if (!victim) {
-      // release the hierarchy of the idle instance used least recently, then look again
-      Instance* idle = nullptr;
-      for (const auto& I : S->inst)
-        if (!I->busy() && I->ch && (!idle || I->ch->last_use < idle->ch->last_use)) idle = I.get();
-      if (!idle) return false;
+      if (c->users == 0 && !c->fresh && c->derived == 0 && c->pending == 0 &&
+          (!victim || c->last_use < victim->last_use))
+        victim = c.get();
+    if (victim) {
+      drop(S, victim);
+      continue;
+    }
+    // release the hierarchy of the idle instance used least recently, then look again
+    Instance* idle = nullptr;
+    for (const auto& I : S->inst)
+      if (I.get() != keep && !I->busy() && I->ch && (!idle || I->ch->last_use < idle->ch->last_use))
+        idle = I.get();
+    if (idle) {
       idle->ch->users -= 1;
       idle->ch = nullptr;
       continue;
     }
-    victim->h->gauge->nhier -= 1;
-    delete victim->h;
-    S->cache.erase(std::find_if(S->cache.begin(), S->cache.end(),
-                                [&](const std::unique_ptr<CachedH>& c) { return c.get() == victim; }));
-    std::lock_guard<std::mutex> lk(S->mu);
-    S->evictions += 1;
+    // then the device memory of an unbound idle instance
+    Instance* empty = nullptr;
+    for (const auto& I : S->inst)
+      if (I.get() != keep && !I->busy() && !I->ch && (I->ws.block_bytes > 0 || I->io.bytes > 0)) empty = I.get();
+    if (!empty) return false;
+    empty->ws.release();
+    empty->io.release();
+    empty->n_io = 0;
   }
 }
 
@@ -212,11 +249,12 @@ size_t instance_estimate(const amamg_server* S, int64_t n) {
   return size_t(S->prm.slots) * n * (16 * size_t(m + 1) + zs * (m + 3) + 16 * 3);
 }
 
+bool has_ref(const Request* R) { return !std::isnan(R->ref); }
+
+// the hierarchy that solves R: built at R's mass (no reference mass), the base at the reference
+// mass (R at that mass) or derived from it
 bool same_key(const CachedH& c, const Request* R) {
-  return c.gauge == R->gauge && c.m0 == R->m0 && same_params(c.sp, R->sp);
-}
-bool same_key(const BuildJob& j, const Request* R) {
-  return j.gauge == R->gauge && j.m0 == R->m0 && same_params(j.sp, R->sp);
+  return c.gauge == R->gauge && c.m0 == R->m0 && same_ref(c.ref, R->ref) && same_params(c.sp, R->sp);
 }
 
 CachedH* cached(amamg_server* S, const Request* R) {
@@ -225,8 +263,67 @@ CachedH* cached(amamg_server* S, const Request* R) {
   return nullptr;
 }
 
-// Hand the request's hierarchy to the builder when the budget allows (false: not now).
-bool dispatch_build(amamg_server* S, Request* R) {
+// The base hierarchy R's would be derived from: built at R's reference mass.
+CachedH* base_for(amamg_server* S, const Request* R) {
+  for (const auto& c : S->cache)
+    if (!c->base && c->gauge == R->gauge && c->m0 == R->ref && same_ref(c->ref, R->ref) &&
+        same_params(c->sp, R->sp))
+      return c.get();
+  return nullptr;
+}
+
+// A build in flight that makes R's hierarchy, or the base R's hierarchy is derived from.
+bool waiting_on_build(const amamg_server* S, const Request* R) {
+  return std::any_of(S->building.begin(), S->building.end(), [&](const BuildJob& j) {
+    if (j.gauge != R->gauge || !same_ref(j.ref, R->ref) || !same_params(j.sp, R->sp)) return false;
+    return j.m0 == R->m0 || (has_ref(R) && !j.base && j.m0 == R->ref);
+  });
+}
+
+// Queued requests that job j was building for (its hierarchy, or its base)
+bool waits_for(const BuildJob& j, const Request* R) {
+  if (j.gauge != R->gauge || !same_ref(j.ref, R->ref) || !same_params(j.sp, R->sp)) return false;
+  return j.m0 == R->m0 || (!j.base && has_ref(R));
+}
+
+void queue_job(amamg_server* S, BuildJob& j, Request* R) {
+  j.id = S->next_job++;
+  S->building.push_back(j);
+  R->built = 1;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->jobs.push_back(j);
+  }
+  S->cv_build.notify_one();
+}
+
+// Hand a derivation of the request's hierarchy from `base` to a builder when the budget allows.
+bool dispatch_derive(amamg_server* S, Request* R, CachedH* base) {
+  const amamg_hierarchy* h = base->h;
+  const size_t need = derive_bytes(h) + instance_estimate(S, h->lv[0].g.ndof());
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->last_estimate = need;
+  }
+  base->pending += 1;             // not evicted meanwhile
+  if (!make_room(S, need)) {
+    base->pending -= 1;
+    return false;
+  }
+  BuildJob j;
+  j.gauge = R->gauge;
+  j.m0 = R->m0;
+  j.ref = R->ref;
+  j.sp = R->sp;
+  j.base = base;
+  j.need = need;
+  queue_job(S, j, R);
+  return true;
+}
+
+// Hand a setup at mass `at` (R's mass, or its reference mass) to a builder when the budget
+// allows (false: not now).
+bool dispatch_build(amamg_server* S, Request* R, double at) {
   amamg_gauge* g;
   {
     std::lock_guard<std::mutex> lk(S->mu);
@@ -240,16 +337,11 @@ bool dispatch_build(amamg_server* S, Request* R) {
   if (!make_room(S, need)) return false;
   BuildJob j;
   j.gauge = R->gauge;
-  j.m0 = R->m0;
+  j.m0 = at;
+  j.ref = R->ref;
   j.sp = R->sp;
   j.need = need;
-  S->building.push_back(j);
-  R->built = 1;
-  {
-    std::lock_guard<std::mutex> lk(S->mu);
-    S->jobs.push_back(j);
-  }
-  S->cv_build.notify_one();
+  queue_job(S, j, R);
   return true;
 }
 
@@ -261,17 +353,23 @@ bool collect_builds(amamg_server* S) {
     got.swap(S->built);
   }
   for (BuildJob& j : got) {
-    S->building.erase(std::find_if(S->building.begin(), S->building.end(), [&](const BuildJob& b) {
-      return b.gauge == j.gauge && b.m0 == j.m0 && same_params(b.sp, j.sp);
-    }));
+    S->building.erase(std::find_if(S->building.begin(), S->building.end(),
+                                   [&](const BuildJob& b) { return b.id == j.id; }));
+    if (j.base) j.base->pending -= 1;
     if (j.h) {
       auto c = std::make_unique<CachedH>();
       c->h = j.h;
       c->gauge = j.gauge;
       c->m0 = j.m0;
+      c->ref = j.ref;
       c->sp = j.sp;
       c->bytes = j.h->mem.bytes();
       c->last_use = ++S->tick;
+      c->base = j.base;
+      if (j.base) {
+        j.base->derived += 1;
+        j.h->base->derived += 1;
+      }
       j.h->gauge->nhier += 1;
       S->cache.push_back(std::move(c));
       continue;
@@ -282,7 +380,7 @@ bool collect_builds(amamg_server* S) {
     }
     for (auto it = S->queue.begin(); it != S->queue.end();) {
       Request* R = *it;
-      if (R->gauge == j.gauge && R->m0 == j.m0 && same_params(R->sp, j.sp)) {
+      if (waits_for(j, R)) {
         R->status = j.code;
         finish(S, R);
         it = S->queue.erase(it);
@@ -308,22 +406,37 @@ void builder_main(amamg_server* S, amamg_server::Builder* B) {
       g = S->gauges[j.gauge];
     }
     const auto t0 = Clock::now();
-    amamg_hierarchy* h = new amamg_hierarchy();
-    h->gauge = g;
-    h->m0 = j.m0;
-    h->prm = j.sp;
-    try {
-      run_setup(h, B->stream, &B->scratch);
-      j.h = h;
-    } catch (const Fail& f) {
-      delete h;
-      j.code = f.code;
-      j.msg = f.msg;
+    if (j.base) {
+      // the base stays cached while this runs (pending) and is only read
+      try {
+        j.h = derive_mass(j.base->h, j.m0, B->stream);
+      } catch (const Fail& f) {
+        j.code = f.code;
+        j.msg = f.msg;
+      }
+    } else {
+      amamg_hierarchy* h = new amamg_hierarchy();
+      h->gauge = g;
+      h->m0 = j.m0;
+      h->prm = j.sp;
+      try {
+        run_setup(h, B->stream, &B->scratch);
+        if (!std::isnan(j.ref)) ensure_mass_terms(h, B->stream);   // a base: for derivations
+        j.h = h;
+      } catch (const Fail& f) {
+        delete h;
+        j.code = f.code;
+        j.msg = f.msg;
+      }
     }
     j.seconds = std::chrono::duration<double>(Clock::now() - t0).count();
     {
       std::lock_guard<std::mutex> lk(S->mu);
-      if (j.h) {
+      if (j.h && j.base) {
+        S->derivations += 1;
+        S->derive_seconds += j.seconds;
+        S->derive_seconds_max = std::max(S->derive_seconds_max, j.seconds);
+      } else if (j.h) {
         S->setups += 1;
         S->setup_seconds += j.seconds;
         S->setup_seconds_max = std::max(S->setup_seconds_max, j.seconds);
@@ -447,6 +560,18 @@ void cycle_end(amamg_server* S, Instance* I) {
   }
 }
 
+// Device bytes that binding instance I (nullptr: a new one) to hierarchy c adds: its workspace
+// and right-hand-side buffers grow to c's size and are never shrunk.
+size_t bind_bytes(const amamg_server* S, const Instance* I, const CachedH* c) {
+  const amamg_solve_params p = solve_params(S);
+  const size_t ws = workspace_bytes(c->h, S->prm.slots, p.restart, p.precision == AMAMG_FP64 ? F64 : F32,
+                                    2 * p.max_iters + 2);
+  const size_t io = sizeof(double2) * 2 * size_t(S->prm.slots) * c->h->lv[0].g.ndof();
+  const size_t have_ws = I ? I->ws.block_bytes : 0;
+  const size_t have_io = I ? I->io.bytes : 0;
+  return (ws > have_ws ? ws - have_ws : 0) + (io > have_io ? io - have_io : 0);
+}
+
 // Place queued requests: an instance bound to the request's hierarchy with room (joining at its
 // next boundary), else an idle or new instance rebound to it.  A request whose hierarchy is not
 // cached starts its build (if the budget allows) and waits for it.
@@ -456,10 +581,12 @@ bool place(amamg_server* S) {
     Request* R = *it;
     CachedH* c = cached(S, R);
     if (!c) {
-      const bool in_flight = std::any_of(S->building.begin(), S->building.end(),
-                                         [&](const BuildJob& b) { return same_key(b, R); });
-      if (!in_flight) {
-        if (dispatch_build(S, R)) {
+      if (!waiting_on_build(S, R)) {
+        // with a reference mass: the base at that mass first, then R's hierarchy derived from it
+        CachedH* base = has_ref(R) && R->m0 != R->ref ? base_for(S, R) : nullptr;
+        const bool started = base ? dispatch_derive(S, R, base)
+                                  : dispatch_build(S, R, has_ref(R) ? R->ref : R->m0);
+        if (started) {
           did = true;
         } else if (S->building.empty() &&
                    std::none_of(S->inst.begin(), S->inst.end(),
@@ -493,18 +620,39 @@ bool place(amamg_server* S) {
         }
         if (!idle || lru(I.get()) < lru(idle)) idle = I.get();
       }
+      // a new instance, or the rebound one, grows its workspace and buffers to the hierarchy's
+      // size: that has to fit the budget first
+      bool blocked = false;
+      c->users += 1;              // make_room must not drop the hierarchy to bind
       if (!idle && int(S->inst.size()) < S->prm.max_instances) {
-        auto I = std::make_unique<Instance>();
-        I->id = int(S->inst.size());
-        HIPCHECK(hipStreamCreateWithFlags(&I->stream, hipStreamNonBlocking));
-        I->slot_req.assign(S->prm.slots, nullptr);
-        I->slot_rhs.assign(S->prm.slots, -1);
-        S->inst.push_back(std::move(I));
-        idle = S->inst.back().get();
+        if (make_room(S, bind_bytes(S, nullptr, c))) {
+          auto I = std::make_unique<Instance>();
+          I->id = int(S->inst.size());
+          HIPCHECK(hipStreamCreateWithFlags(&I->stream, hipStreamNonBlocking));
+          I->slot_req.assign(S->prm.slots, nullptr);
+          I->slot_rhs.assign(S->prm.slots, -1);
+          S->inst.push_back(std::move(I));
+          idle = S->inst.back().get();
+        } else {
+          blocked = true;
+        }
+      } else if (idle && idle->ch != c && !make_room(S, bind_bytes(S, idle, c), idle)) {
+        idle = nullptr;
+        blocked = true;
       }
+      c->users -= 1;
       if (idle) {
         bind(S, idle, c);
         target = idle;
+      } else if (blocked && S->building.empty() &&
+                 std::none_of(S->inst.begin(), S->inst.end(),
+                              [](const std::unique_ptr<Instance>& I) { return I->busy(); })) {
+        // nothing running or building will free memory: this request cannot be served
+        R->status = AMAMG_ERR_OUT_OF_MEMORY;
+        finish(S, R);
+        it = S->queue.erase(it);
+        did = true;
+        continue;
       }
     }
     if (!target) {
@@ -684,7 +832,19 @@ amamg_status amamg_server_add_gauge(amamg_server* S, int32_t nt, int32_t nx, con
   }
   std::lock_guard<std::mutex> lk(S->mu);
   S->gauges.push_back(g);
+  S->refs.push_back(NAN);
   *gauge_id = int32_t(S->gauges.size()) - 1;
+  return AMAMG_OK;
+}
+
+amamg_status amamg_server_set_reference_mass(amamg_server* S, int32_t gauge_id, double m_ref) {
+  if (!S) return AMAMG_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (gauge_id < 0 || gauge_id >= int(S->gauges.size()) || std::isinf(m_ref)) {
+    S->err = "unknown gauge or infinite reference mass";
+    return AMAMG_ERR_INVALID_ARG;
+  }
+  S->refs[gauge_id] = m_ref;
   return AMAMG_OK;
 }
 
@@ -702,6 +862,7 @@ amamg_status amamg_server_submit(amamg_server* S, int32_t gauge_id, double m0,
     }
     const amamg_gauge* g = S->gauges[gauge_id];
     R->psi.assign(psi, psi + size_t(nrhs) * g->nt * g->nx * 4);
+    R->ref = S->refs[gauge_id];
   }
   R->gauge = gauge_id;
   R->m0 = m0;
@@ -776,6 +937,9 @@ amamg_status amamg_server_stats(amamg_server* S, amamg_server_counters* out) {
   out->last_estimate_bytes = S->last_estimate;
   out->setup_seconds = S->setup_seconds;
   out->setup_seconds_max = S->setup_seconds_max;
+  out->derivations = S->derivations;
+  out->derive_seconds = S->derive_seconds;
+  out->derive_seconds_max = S->derive_seconds_max;
   return AMAMG_OK;
 }
 
@@ -811,7 +975,7 @@ amamg_status amamg_server_destroy(amamg_server* S) {
     (void)hipStreamDestroy(I->stream);
   }
   S->inst.clear();
-  for (auto& c : S->cache) {
+  for (auto& c : S->cache) {     // derived hierarchies own nothing of their base
     c->h->gauge->nhier -= 1;
     delete c->h;
   }

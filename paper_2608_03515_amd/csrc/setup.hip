@@ -471,4 +471,16 @@ void cast_matrix(hipStream_t s, const double2* A, float2* out, int64_t n) {
   hipLaunchKernelGGL(k_cast_matrix, g1(n), dim3(256), 0, s, A, out, n);
 }
 
+// y += a x for complex arrays and a real scale (the mass term of the coarse operators)
+__global__ void k_axpy_real(double2* __restrict__ y, double a, const double2* __restrict__ x, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const double2 v = x[i], w = y[i];
+    y[i] = make_double2(fma(a, v.x, w.x), fma(a, v.y, w.y));
+  }
+}
+
+void axpy_real(hipStream_t s, double2* y, double a, const double2* x, int64_t n) {
+  hipLaunchKernelGGL(k_axpy_real, g1(n), dim3(256), 0, s, y, a, x, n);
+}
+
 }  // namespace amamg

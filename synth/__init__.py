@@ -24,9 +24,10 @@ import numpy as np
 
 __all__ = ["gen_theta", "gen_links", "gaussian_rhs", "plaquette_angles",
            "Workload", "WORKLOADS", "critical_masses", "links_to_abi", "field_to_abi",
-           "field_from_abi", "SERVING_SIZES", "SERVING_MASSES", "serving_setup", "serving_configs",
-           "serving_links", "request_stream", "MULTI_SIZES", "MULTI_GAPS", "multi_lattice_configs",
-           "multi_lattice_critical", "MULTI_CRITICAL_PATH"]
+           "field_from_abi", "SERVING_SIZES", "serving_setup", "serving_configs",
+           "serving_links", "MULTI_SIZES", "MULTI_GAPS", "multi_lattice_configs",
+           "multi_lattice_critical", "MULTI_CRITICAL_PATH", "SERVING_CRITICAL_PATH", "SERVING_GAPS",
+           "serving_critical", "near_critical_stream"]
 
 
 def plaquette_angles(theta: np.ndarray) -> np.ndarray:
@@ -125,6 +126,20 @@ class Workload:
     def links(self) -> np.ndarray:
         return gen_links(self.L, self.L, self.beta, self.sweeps, self.link_seed)
 
+    def setup_kw(self, **extra) -> dict:
+        """Hierarchy parameters as keyword arguments of the library's setup parameters."""
+        kw = dict(levels=self.levels, agg_size=self.agg, overlap=self.overlap,
+                  n_test_vectors=self.n_test_vectors, test_vector_sweeps=self.test_vector_sweeps)
+        kw.update(extra)
+        return kw
+
+    def oracle_kw(self, **extra) -> dict:
+        """The same parameters as keyword arguments of the oracle's setup parameters."""
+        kw = dict(levels=self.levels, agg=self.agg, overlap=self.overlap,
+                  n_test_vectors=self.n_test_vectors, test_vector_sweeps=self.test_vector_sweeps)
+        kw.update(extra)
+        return kw
+
 
 WORKLOADS = {
     # two levels, FP64, 16x16
@@ -133,9 +148,9 @@ WORKLOADS = {
     "C2": Workload("C2", 64, 6.0, 200, 1002, 2002, 3, 4, 1, 8,
                    gaps=(0.1, 0.05, 0.02, 0.01, 0.005)),
     # three levels, 256x256, mixed precision vs FP64
-    "C3": Workload("C3", 256, 10.0, 200, 1003, 2003, 3, 8, 2, 8, gaps=(0.01,)),
+    "C3": Workload("C3", 256, 10.0, 200, 1003, 2003, 3, 8, 2, 8, test_vector_sweeps=64, gaps=(0.01,)),
     # one 128x128 lattice for many right-hand sides
-    "C4": Workload("C4", 128, 8.0, 200, 1004, 2004, 3, 8, 2, 8, gaps=(0.01,)),
+    "C4": Workload("C4", 128, 8.0, 200, 1004, 2004, 3, 8, 2, 8, test_vector_sweeps=64, gaps=(0.01,)),
 }
 
 _GOLDEN = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
@@ -155,48 +170,28 @@ def critical_masses() -> dict:
 # ------------------------------------------------------------------------- serving workload
 
 SERVING_SIZES = (32, 64, 128, 256, 512)
-SERVING_MASSES = (0.05, 0.1, 0.2)
-
-
 def serving_setup(L: int) -> dict:
     """AM-AMG setup parameters used for an L x L serving lattice (the configurations above at
     their sizes; 512 keeps a = 8, o = 2 with a 2048-unknown coarsest level)."""
     if L <= 32:
-        return dict(levels=2, agg_size=4, overlap=1, n_test_vectors=4)
+        return dict(levels=2, agg_size=4, overlap=1, n_test_vectors=4, test_vector_sweeps=64)
     if L <= 64:
-        return dict(levels=3, agg_size=4, overlap=1, n_test_vectors=8)
-    return dict(levels=3, agg_size=8, overlap=2, n_test_vectors=8)
+        return dict(levels=3, agg_size=4, overlap=1, n_test_vectors=8, test_vector_sweeps=64)
+    return dict(levels=3, agg_size=8, overlap=2, n_test_vectors=8, test_vector_sweeps=64)
 
 
 def serving_configs(n: int = 16, seed: int = 5005, sweeps: int = 50) -> list:
-    """n gauge configurations: the first five cover every size once, the rest draw L uniformly;
-    beta uniform in [2, 10]; Metropolis from a cold start with its own seed."""
-    rng = np.random.Generator(np.random.PCG64(seed))
+    """n gauge configurations: L_j = SERVING_SIZES[j mod 5], beta_j = 2 + 8 j / (n - 1) (from 2
+    to 10); Metropolis from a cold start with its own seed."""
     out = []
     for i in range(n):
-        L = SERVING_SIZES[i] if i < len(SERVING_SIZES) else int(rng.choice(SERVING_SIZES))
-        out.append({"L": L, "beta": float(rng.uniform(2.0, 10.0)), "sweeps": sweeps,
-                    "seed": seed + 1 + i})
+        out.append({"L": SERVING_SIZES[i % len(SERVING_SIZES)],
+                    "beta": 2.0 + 8.0 * i / max(1, n - 1), "sweeps": sweeps, "seed": seed + 1 + i})
     return out
 
 
 def serving_links(cfg: dict) -> np.ndarray:
     return gen_links(cfg["L"], cfg["L"], cfg["beta"], cfg["sweeps"], cfg["seed"])
-
-
-def request_stream(n: int, qps: float, n_configs: int, seed: int = 6006, max_rhs: int = 8) -> list:
-    """Open-loop arrivals: exponential gaps of mean 1 / qps; per request a uniform configuration,
-    a mass from SERVING_MASSES and 1..max_rhs right-hand sides.  Returns dicts with the
-    arrival time, configuration index, mass, nrhs and a seed for its right-hand sides."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    t = 0.0
-    out = []
-    for i in range(n):
-        t += float(rng.exponential(1.0 / qps))
-        out.append({"t": t, "config": int(rng.integers(n_configs)),
-                    "m0": float(rng.choice(SERVING_MASSES)), "nrhs": int(rng.integers(1, max_rhs + 1)),
-                    "seed": int(rng.integers(1 << 30))})
-    return out
 
 
 # ------------------------------------------------------------------- multi-lattice workload
@@ -225,3 +220,30 @@ def multi_lattice_critical() -> list:
     """Critical masses of multi_lattice_configs() (tests/golden/multi_lattice_critical.json)."""
     with open(MULTI_CRITICAL_PATH) as f:
         return json.load(f)["m_c"]
+
+
+SERVING_CRITICAL_PATH = os.path.join(os.path.dirname(MULTI_CRITICAL_PATH), "serving_critical.json")
+SERVING_GAPS = (0.01, 0.1)      # per-request gap above m_c: log-uniform in this range
+
+
+def serving_critical() -> list:
+    """Critical masses of serving_configs() (tests/golden/serving_critical.json)."""
+    with open(SERVING_CRITICAL_PATH) as f:
+        data = json.load(f)
+    assert data["configs"] == serving_configs(len(data["configs"])), "serving configurations changed"
+    return data["m_c"]
+
+
+def near_critical_stream(n: int, qps: float, m_c: list, seed: int = 6006, max_rhs: int = 8) -> list:
+    """Open-loop arrivals at rate qps (exponential gaps); per request a uniform configuration,
+    m0 = m_c + gap with the gap log-uniform in SERVING_GAPS, and 1..max_rhs right-hand sides."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo, hi = np.log(SERVING_GAPS[0]), np.log(SERVING_GAPS[1])
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += float(rng.exponential(1.0 / qps))
+        c = int(rng.integers(len(m_c)))
+        out.append({"t": t, "config": c, "m0": float(m_c[c] + np.exp(rng.uniform(lo, hi))),
+                    "nrhs": int(rng.integers(1, max_rhs + 1)), "seed": int(rng.integers(1 << 30))})
+    return out

@@ -5,6 +5,8 @@ oracle's shift-invert Arnoldi (spectrum module).  The near-critical workloads us
 m0 = m_c + gap.
 multi_lattice_critical.json: the same for the 32 lattices of synth.multi_lattice_configs()
 (computed in a process pool).
+serving_critical.json: the same for the 16 gauge fields of synth.serving_configs() (the
+serving workload draws each request's mass near its field's m_c).
 
 c3_solve.json: the oracle's FP64 solve of the 256^2 workload's first right-hand side (the one
 the benchmark's batch starts with): iteration and restart counts, the true relative residual,
@@ -17,7 +19,7 @@ the 256^2 workload's first right-hand side.  The paper fixes no colour order; th
 evidence that the order does not change the convergence.
 
 Run from the repository root:
-    python tests/golden/make_golden.py [--multi-only | --c3-solve | --sweep-order]
+    python tests/golden/make_golden.py [--multi-only | --serving | --c3-solve | --sweep-order]
 """
 import os
 import sys
@@ -59,6 +61,21 @@ def multi(workers=8):
         f.write("\n")
 
 
+def serving(workers=8):
+    """Critical masses of the 16 serving configurations, one process per configuration."""
+    from concurrent.futures import ProcessPoolExecutor
+    cfgs = synth.serving_configs(16)
+    order = sorted(range(len(cfgs)), key=lambda i: -cfgs[i]["L"])
+    mcs = [None] * len(cfgs)
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        for i, mc in zip(order, ex.map(_mc, [cfgs[i] for i in order])):
+            mcs[i] = mc
+            print(i, cfgs[i]["L"], mc, flush=True)
+    with open(synth.SERVING_CRITICAL_PATH, "w") as f:
+        json.dump({"configs": cfgs, "m_c": mcs}, f, indent=1)
+        f.write("\n")
+
+
 def c3_solve():
     import numpy as np
     from oracle.amg import SetupParams
@@ -67,12 +84,13 @@ def c3_solve():
     with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "critical_mass.json")) as f:
         m0 = json.load(f)["C3"] + w.gaps[0]
     psi = synth.gaussian_rhs(w.L, w.L, w.rhs_seed, nrhs=1)[0]
-    prm = SetupParams(levels=w.levels, agg=w.agg, overlap=w.overlap, n_test_vectors=w.n_test_vectors)
+    prm = SetupParams(**w.oracle_kw())
     x, info, _ = solve(w.links(), m0, psi, prm, restart=w.restart, tol=1e-10)
     rng = np.random.default_rng(0)
     sites = sorted(int(s) for s in rng.choice(w.L * w.L, 64, replace=False))
     xf = x.reshape(-1, 2)
-    out = {"workload": "C3", "m0": m0, "rhs_seed": w.rhs_seed, "iterations": info.iterations,
+    out = {"workload": "C3", "m0": m0, "rhs_seed": w.rhs_seed, "test_vector_sweeps": w.test_vector_sweeps,
+           "iterations": info.iterations,
            "restarts": info.restarts, "converged": bool(info.converged),
            "true_rel_residual": float(info.true_rel_residual), "x_norm": float(np.linalg.norm(x)),
            "samples": [[s, q, float(xf[s, q].real), float(xf[s, q].imag)] for s in sites for q in range(2)],
@@ -123,6 +141,9 @@ def main():
         return
     if "--multi-only" in sys.argv:
         multi()
+        return
+    if "--serving" in sys.argv:
+        serving()
         return
     if "--c3-solve" in sys.argv:
         c3_solve()

@@ -515,16 +515,17 @@ def test_invalid_shapes_and_args(lib, ctx):
 
 
 def test_c3_full_size_setup_sampled_parity(lib, ctx):
-    """256x256, a = 8, o = 2, 3 levels: classification bit-exact, sampled interpolation rows and
-    coarse blocks against the oracle's setup."""
+    """256x256, a = 8, o = 2, 3 levels, the benchmark's hierarchy parameters (64 test-vector
+    sweeps): classification bit-exact, sampled interpolation rows and coarse blocks against the
+    oracle's setup."""
     w = synth.WORKLOADS["C3"]
     m0 = synth.critical_masses()["C3"] + w.gaps[0]
     U = w.links()
     say("C3 setup parity")
-    prm = amg.SetupParams(levels=3, agg=8, overlap=2, n_test_vectors=8)
+    prm = amg.SetupParams(**w.oracle_kw())
     olev = amg.setup(U, m0, prm)
     g = make_gauge(lib, ctx, U, m0)
-    h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=8, overlap=2, n_test_vectors=8))
+    h = lib.Hierarchy(g, lib.default_setup_params(**w.setup_kw()))
     kind, owner, node = h.aggregates(0)
     assert np.array_equal(kind, olev[0].cls["kind"]) and np.array_equal(owner, olev[0].cls["owner"])
     rows = h.prolongator_rows(0, 2)
@@ -828,8 +829,8 @@ def test_c3_full_size_solve_in_bench_configuration(lib):
     stream = torch.cuda.Stream()
     ctx = lib.Context(0, stream.cuda_stream)
     g = make_gauge(lib, ctx, U, m0)
-    h = lib.Hierarchy(g, lib.default_setup_params(levels=w.levels, agg_size=w.agg, overlap=w.overlap,
-                                                   n_test_vectors=w.n_test_vectors))
+    h = lib.Hierarchy(g, lib.default_setup_params(**w.setup_kw()))
+    assert gold["test_vector_sweeps"] == w.test_vector_sweeps
     out = {}
     for prec in (lib.FP64, lib.MIXED_FP32, lib.MIXED_FP32_BF16LINKS):
         say("C3 full size", prec)

@@ -44,8 +44,9 @@ def requests():
     return out
 
 
-def make_server(lib, **kw):
-    prm = lib.default_server_params(slots=4, max_instances=2, precision=lib.FP64)
+def make_server(lib, precision=None, **kw):
+    prm = lib.default_server_params(slots=4, max_instances=2,
+                                    precision=lib.FP64 if precision is None else precision)
     for k, v in kw.items():
         setattr(prm, k, v)
     return lib.Server(0, prm)
@@ -63,11 +64,16 @@ def run(lib, srv, gids, reqs, stagger=0.0):
     return [done[i] for i in ids]
 
 
-def test_server_matches_oracle_and_is_the_same_alone_and_in_a_mix(lib):
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_server_matches_oracle_and_is_the_same_alone_and_in_a_mix(lib, prec):
+    """FP64: the oracle's iteration counts and <= 1e-9; mixed precision (the serving default:
+    FP32 V-cycle inside FP64 FGMRES): <= 1e-9 of the oracle.  Both: bitwise the same alone, in
+    the mix and with captured cycles."""
+    precision = lib.FP64 if prec == "fp64" else lib.MIXED_FP32
     Us = lattices()
     reqs = requests()
     # the mix: every request, staggered so that later ones join running instances
-    srv = make_server(lib)
+    srv = make_server(lib, precision)
     gids = [srv.add_gauge(synth.links_to_abi(U)) for U in Us]
     say("server mix")
     mix = run(lib, srv, gids, reqs, stagger=0.02)
@@ -84,10 +90,11 @@ def test_server_matches_oracle_and_is_the_same_alone_and_in_a_mix(lib):
             xo, io, levels = oracle_solve(Us[gi], m0, psi[r], prm, levels=levels)
             assert rel(x[r], xo) <= 1e-9
             its.append(io.iterations)
-        assert info.iterations == max(its)
+        if precision == lib.FP64:
+            assert info.iterations == max(its)
     # each request alone on a fresh server: bitwise the same
     for k in (0, 3, 6):
-        srv = make_server(lib)
+        srv = make_server(lib, precision)
         gids = [srv.add_gauge(synth.links_to_abi(U)) for U in Us]
         say("server alone", k)
         (info, x), = run(lib, srv, gids, [reqs[k]])
@@ -95,7 +102,7 @@ def test_server_matches_oracle_and_is_the_same_alone_and_in_a_mix(lib):
         assert info.iterations == mix[k][0].iterations
         assert np.array_equal(x, mix[k][1])
     # the mix again with every instance replaying its captured restart cycle: bitwise the same
-    srv = make_server(lib, graphs=1)
+    srv = make_server(lib, precision, graphs=1)
     gids = [srv.add_gauge(synth.links_to_abi(U)) for U in Us]
     say("server mix, graphs")
     mixg = run(lib, srv, gids, reqs, stagger=0.02)
@@ -231,3 +238,80 @@ def test_server_coarsest_gmres_requests(lib):
             its.append(io.iterations)
         assert info.iterations == max(its)
     assert np.array_equal(done[ids[0]][1], done[ids[2]][1])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_reference_mass_requests_use_derived_hierarchies(lib, prec):
+    """A gauge with a reference mass: one setup at that mass, and each other mass gets a
+    hierarchy derived from it (interpolation from the reference mass, operators at the
+    request's).  Every request matches the oracle's shift of the reference setup (FP64: its
+    iteration counts); alone on a fresh server it is bitwise its result in the staggered mix."""
+    precision = lib.FP64 if prec == "fp64" else lib.MIXED_FP32
+    U = synth.gen_links(32, 32, 4.0, 60, 321)
+    m_ref = 0.12
+    masses = (0.05, 0.12, 0.3, 0.05, 0.08)
+    reqs = [(0, m, synth.gaussian_rhs(32, 32, 700 + k, nrhs=1 + k % 2)) for k, m in enumerate(masses)]
+
+    def serve(rs, stagger):
+        srv = make_server(lib, precision)
+        gid = srv.add_gauge(synth.links_to_abi(U))
+        srv.set_reference_mass(gid, m_ref)
+        out = run(lib, srv, [gid], rs, stagger=stagger)
+        st = srv.stats()
+        srv.close()
+        return out, st
+
+    mix, st = serve(reqs, 0.02)
+    assert st.setups == 1 and st.derivations == 3             # 0.05, 0.3, 0.08 from 0.12
+    prm = amg.SetupParams(levels=2, agg=4, overlap=1, n_test_vectors=4)
+    base = amg.setup(U, m_ref, prm)
+    for (gi, m0, psi), (info, x) in zip(reqs, mix):
+        assert info.status == lib.OK and info.converged and info.true_rel_residual <= 1e-10
+        olev = amg.shift_mass(base, U, m0)
+        its = []
+        for r in range(psi.shape[0]):
+            xo, io, _ = oracle_solve(U, m0, psi[r], prm, levels=olev)
+            assert rel(x[r], xo) <= 1e-9
+            its.append(io.iterations)
+        if precision == lib.FP64:
+            assert info.iterations == max(its)
+    for k in (0, 2):
+        (info, x), = serve([reqs[k]], 0.0)[0]
+        assert info.iterations == mix[k][0].iterations and np.array_equal(x, mix[k][1])
+
+
+def test_budget_holds_when_instances_are_rebound_across_lattice_sizes(lib):
+    """Requests on a 16^2 and a 64^2 lattice, submitted together to a server with two instances
+    whose budget is the peak of serving them one at a time with one instance: the server binds,
+    creates and rebinds instances only when their workspace growth fits (releasing idle
+    instances' memory and evicting when needed), so the peak stays within the budget and the
+    results are bitwise those of the one-at-a-time run."""
+    cases = [(synth.WORKLOADS["C1"].links(), 0.1, dict(levels=2, agg_size=4, overlap=1, n_test_vectors=4)),
+             (synth.gen_links(64, 64, 6.0, 60, 654), 0.1, dict(levels=3, agg_size=4, overlap=1, n_test_vectors=8))]
+    order = (0, 1, 0, 1)
+    psis = [synth.field_to_abi(synth.gaussian_rhs(cases[k][0].shape[1], cases[k][0].shape[1], 60 + i, nrhs=2))
+            for i, k in enumerate(order)]
+    srv = make_server(lib, max_instances=1, builders=1)
+    gids = [srv.add_gauge(synth.links_to_abi(U)) for U, _, _ in cases]
+    ref = []
+    for i, k in enumerate(order):
+        srv.submit(gids[k], cases[k][1], psis[i], lib.default_setup_params(**cases[k][2]))
+        assert srv.wait(120)
+        (info, x), = srv.poll()
+        assert info.status == lib.OK
+        ref.append((info, x))
+    budget = srv.stats().peak_resident_bytes
+    srv.close()
+    srv = make_server(lib, max_instances=2, builders=1, hbm_budget=budget)
+    gids = [srv.add_gauge(synth.links_to_abi(U)) for U, _, _ in cases]
+    ids = [srv.submit(gids[k], cases[k][1], psis[i], lib.default_setup_params(**cases[k][2]))
+           for i, k in enumerate(order)]
+    assert srv.wait(300)
+    done = {info.id: (info, x) for info, x in srv.poll()}
+    st = srv.stats()
+    srv.close()
+    assert st.peak_resident_bytes <= budget
+    for i, rid in enumerate(ids):
+        info, x = done[rid]
+        assert info.status == lib.OK
+        assert info.iterations == ref[i][0].iterations and np.array_equal(x, ref[i][1])
