@@ -486,9 +486,26 @@ def flop_summary(w, iterations, s_per_step):
 
 
 # ------------------------------------------------------------------ profile summaries
-FAMILY_PATTERNS = {"update": "k_lag_update<", "dots": "k_gram<"}
-TRAFFIC_MD = os.path.join(ROOT, "profiles", "gram_schmidt_256x256_64rhs_mixed_traffic.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2608_03515_amd", "csrc", "krylov.hip")
+# Kernel-name patterns of each timed family in the mixed step (the first pattern is the family's
+# main kernel, one dispatch per timed launch; further patterns are kernels the same launch
+# record covers), and the source file each is built from.
+FAMILY_PATTERNS = {
+    "fine_matvec": ("k_wilson_apply<64, float",),
+    "fine_gs": ("k_wilson_gs_fused<",),
+    "restrict0": ("k_restrict_partial_tiled<32, 60, 32, float", "k_restrict_gather<float, HIP_vector_type<double"),
+    "prolong0": ("k_prolong_tiled<32, 64, 32, float",),
+    "coarse_gs": ("k_stencil_gs_quad_mfma<",),
+    "dots": ("k_gram<",),
+    "update": ("k_lag_update<",),
+}
+_CSRC = os.path.join(ROOT, "paper_2608_03515_amd", "csrc")
+FAMILY_SRC = {"fine_matvec": "fine.hip", "fine_gs": "fine.hip", "restrict0": "transfer.hip",
+              "prolong0": "transfer.hip", "coarse_gs": "coarse.hip", "dots": "krylov.hip", "update": "krylov.hip"}
+TRAFFIC_MD = os.path.join(ROOT, "profiles", "solve_families_256x256_64rhs_mixed_traffic.md")
+
+
+def family_src_sha(fam):
+    return _sha(os.path.join(_CSRC, FAMILY_SRC[fam]))
 
 
 def _sha(path):
@@ -510,12 +527,13 @@ def trace_summary(stats_csv, out_md, command, top=25):
         lines.append(f"| {float(r['TotalDurationNs']) / 1e6:.2f} | {r['Calls']} | "
                      f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} | `{name}` |")
     lines += ["", "Families (all instantiations):", "", "| family | calls | avg us | total ms |", "|---|---:|---:|---:|"]
-    for fam, pat in FAMILY_PATTERNS.items():
-        sel = [r for r in rows if pat in r["Name"]]
-        n = sum(int(r["Calls"]) for r in sel)
-        t = sum(float(r["TotalDurationNs"]) for r in sel)
-        if n:
-            lines.append(f"| {fam} (`{pat}*`) | {n} | {t / n / 1e3:.2f} | {t / 1e6:.2f} |")
+    for fam, pats in FAMILY_PATTERNS.items():
+        for pat in pats:
+            sel = [r for r in rows if pat in r["Name"]]
+            n = sum(int(r["Calls"]) for r in sel)
+            t = sum(float(r["TotalDurationNs"]) for r in sel)
+            if n:
+                lines.append(f"| {fam} (`{pat}*`) | {n} | {t / n / 1e3:.2f} | {t / 1e6:.2f} |")
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
@@ -527,48 +545,76 @@ def timer_families(t):
     return {t["family"]: t} if "family" in t else {}
 
 
-def pmc_summary(fetch_csv, write_csv, out_md, command, timer_json):
-    """Traffic per launch of the Gram-Schmidt families from two rocprofv3 --pmc runs, scaled by
-    the same counters on a plain 1 GiB elementwise copy in the same run."""
+def pmc_summary(fetch_csv, write_csv, out_md, command, timer_json, wait_csv=None):
+    """HBM traffic per launch of the step's kernel families from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE), scaled by the same counters on a plain 1 GiB elementwise copy in
+    the same run, beside the kernel timer's algorithmic bytes and launch times.  With wait_csv
+    (a pass over SQ_WAIT_ANY, SQ_ACTIVE_INST_VALU, SQ_WAVES) also the cycles a wave waits per
+    VALU-active cycle."""
     import csv
     from collections import defaultdict
 
-    def load(path):
+    def load(path, counter=None):
         per = defaultdict(list)
         with open(path) as f:
             for row in csv.DictReader(f):
-                per[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+                if counter is None or row.get("Counter_Name") == counter:
+                    per[row["Kernel_Name"]].append(float(row["Counter_Value"]))
         return per
     fe, wr = load(fetch_csv), load(write_csv)
     cal = [k for k in fe if "neg_kernel" in k]
     f_fac = fe[cal[0]][0] * 1024 / 2 ** 30          # counter bytes per byte read
     w_fac = wr[cal[0]][0] * 1024 / 2 ** 30          # counter bytes per byte written
     t = json.loads(timer_json)
+    fams = timer_families(t)
     lines = [f"# HBM traffic, {os.path.basename(out_md)[:-3]}", "",
-             "Two counter passes (one counter each), from the repository root:", ""]
+             "Counter passes (one counter each for the traffic), from the repository root:", ""]
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
         lines.append(f"    {command.replace('COUNTER', c)}")
+    if wait_csv:
+        lines.append(f"    {command.replace('COUNTER', 'SQ_WAIT_ANY SQ_ACTIVE_INST_VALU SQ_WAVES')}")
     lines += ["", f"Calibration: a 1 GiB elementwise copy (`neg`) reads as {fe[cal[0]][0]:.0f} KiB of "
               f"FETCH_SIZE and writes as {wr[cal[0]][0]:.0f} KiB of WRITE_SIZE: scale factors "
               f"{f_fac:.4f} (fetch) and {w_fac:.4f} (write) counter bytes per byte.", "",
+              "Per launch of each timed family (its kernels' traffic summed; algorithmic bytes and mean "
+              "launch time from the library's kernel timer in the same command, one stream):", "",
               "| family | dispatches with traffic | read MB / launch | written MB / launch | "
-              "algorithmic MB / launch (timer) | traffic / algorithmic |", "|---|---:|---:|---:|---:|---:|"]
+              "algorithmic MB / launch (timer) | traffic / algorithmic | us / launch (timer) | "
+              "algorithmic GB/s | % of 8 TB/s |", "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
     rec = {}
-    for fam, pat in FAMILY_PATTERNS.items():
-        fv = [v for k, vs in fe.items() if pat in k for v in vs]
-        wv = [v for k, vs in wr.items() if pat in k for v in vs]
-        nwork = sum(1 for v in fv if v * 1024 / f_fac > 1e6)
-        rd = sum(fv) * 1024 / f_fac / max(1, nwork)
-        wt = sum(wv) * 1024 / w_fac / max(1, nwork)
-        alg = timer_families(t).get(fam, {}).get("algorithmic_bytes_per_launch")
+    for fam, pats in FAMILY_PATTERNS.items():
+        fv0 = [v for k, vs in fe.items() if pats[0] in k for v in vs]
+        nwork = sum(1 for v in fv0 if v * 1024 / f_fac > 1e6)
+        if not nwork:
+            continue
+        fv = [v for k, vs in fe.items() if any(p in k for p in pats) for v in vs]
+        wv = [v for k, vs in wr.items() if any(p in k for p in pats) for v in vs]
+        rd = sum(fv) * 1024 / f_fac / nwork
+        wt = sum(wv) * 1024 / w_fac / nwork
+        ft = fams.get(fam, {})
+        alg, us = ft.get("algorithmic_bytes_per_launch"), ft.get("avg_launch_us")
         rec[fam] = (rd, wt, nwork)
+        gbs = alg / (us * 1e3) if alg and us else float("nan")
         lines.append(f"| {fam} | {nwork} | {rd / 1e6:.1f} | {wt / 1e6:.1f} | "
                      f"{alg / 1e6 if alg else float('nan'):.1f} | "
-                     f"{(rd + wt) / alg if alg else float('nan'):.3f} |")
+                     f"{(rd + wt) / alg if alg else float('nan'):.3f} | {us if us else float('nan'):.1f} | "
+                     f"{gbs:.0f} | {100 * gbs / HBM_PEAK_GBS:.1f} |")
+    if wait_csv:
+        wa, va, wv_ = (load(wait_csv, c) for c in ("SQ_WAIT_ANY", "SQ_ACTIVE_INST_VALU", "SQ_WAVES"))
+        lines += ["", "Latency: wave-cycles waiting on anything per VALU-active wave-cycle, summed over the "
+                  "family's main kernel:", "", "| family | SQ_WAIT_ANY / SQ_ACTIVE_INST_VALU | waves / dispatch |",
+                  "|---|---:|---:|"]
+        for fam, pats in FAMILY_PATTERNS.items():
+            w = sum(v for k, vs in wa.items() if pats[0] in k for v in vs)
+            a = sum(v for k, vs in va.items() if pats[0] in k for v in vs)
+            nw = [v for k, vs in wv_.items() if pats[0] in k for v in vs]
+            if a > 0:
+                lines.append(f"| {fam} | {w / a:.2f} | {sum(nw) / max(1, len(nw)):.0f} |")
     lines.append("")
-    for fam in timer_families(t):
-        lines.append(f"<!-- traffic family={fam} source_sha={_sha(KERNEL_SRC)} "
-                     f"bytes_per_launch={rec[fam][0] + rec[fam][1]:.0f} -->")
+    for fam in fams:
+        if fam in rec:
+            lines.append(f"<!-- traffic family={fam} source_sha={family_src_sha(fam)} "
+                         f"bytes_per_launch={rec[fam][0] + rec[fam][1]:.0f} -->")
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
@@ -676,7 +722,7 @@ def committed_traffic(family):
     except OSError:
         return None
     for m in re.finditer(r"<!-- traffic family=(\w+) source_sha=(\w+) bytes_per_launch=([0-9.]+) -->", text):
-        if m.group(1) == family and m.group(2) == _sha(KERNEL_SRC):
+        if m.group(1) == family and m.group(2) == family_src_sha(family):
             return float(m.group(3))
     return None
 
@@ -716,8 +762,8 @@ def main():
     ap.add_argument("--mfma-summary", nargs=5, metavar=("PMC_CSV", "STATS_CSV", "OUT_MD", "COMMAND", "TRACE_COMMAND"))
     ap.add_argument("--stencil-traffic-summary", nargs=6,
                     metavar=("FETCH_CSV", "WRITE_CSV", "STATS_CSV", "OUT_MD", "COMMAND", "TRACE_COMMAND"))
-    ap.add_argument("--pmc-summary", nargs=5,
-                    metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD", "COMMAND", "TIMER_JSON"))
+    ap.add_argument("--pmc-summary", nargs="+",
+                    metavar="ARG", help="FETCH_CSV WRITE_CSV OUT_MD COMMAND TIMER_JSON [WAIT_CSV]")
     ap.add_argument("--profile-mixed", action="store_true",
                     help="profiling run: only the one-stream timed mixed-precision steps of the "
                          "roofline pass (no FP64, single-rhs, stencil, serving or CPU legs), followed "
