@@ -58,6 +58,7 @@ class SetupParams:
     seed: int = 0
     coarsest_tol: float = 0.0          # 0: exact solve; > 0: GMRES to this relative tolerance
     coarsest_max_iters: int = 32
+    aug_vectors: int = 0               # test vectors augmenting the finest level's coarse space
 
 
 @dataclass
@@ -195,6 +196,60 @@ def normalise(P_tilde: sp.csr_matrix, mode: int, b: int, cls: dict,
     return (sp.diags(c) @ P_tilde).tocsr()
 
 
+# ----------------------------------------------------------- augmented coarse space
+
+def widen_columns(M: sp.csr_matrix, bc: int, bc_aug: int) -> sp.csr_matrix:
+    """Renumber coarse columns node * bc + i as node * bc_aug + i (room for extra dofs per node)."""
+    C = M.tocoo()
+    cols = (C.col // bc) * bc_aug + C.col % bc
+    nnode = M.shape[1] // bc
+    return sp.csr_matrix((C.data, (C.row, cols)), shape=(M.shape[0], nnode * bc_aug))
+
+
+def augment(P: sp.csr_matrix, tv: np.ndarray, tv_coarse: np.ndarray, b: int, bc: int, cls: dict,
+            k: int):
+    """Coarse space augmented with k test vectors (the paper's outlook: test vectors in the
+    SM-AMG method to capture the near-kernel better).  For test vector w_j the wirebasket
+    interpolation leaves the residual e_j = w_j - P (w_j at the vertices), which vanishes on
+    vertex rows.  Each wirebasket W = (I, J) gets k coarse degrees of freedom on its node
+    (I, J), numbered after the node's o^2 b vertex dofs: an orthonormal basis, by Gram-Schmidt
+    in the order j = 0 .. k-1, of e_0 .. e_{k-1} restricted to the non-vertex rows W owns.
+
+    Returns (P_aug, coarse test vectors): the coarse representation of w_j is its vertex values
+    and its coefficients in W's basis, so that P_aug reproduces w_0 .. w_{k-1} exactly."""
+    ndof = P.shape[0]
+    bca = bc + k
+    nW = cls["nI"] * cls["nJ"]
+    owner = np.repeat(cls["owner"], b)
+    frow = np.repeat(cls["kind"] != KIND_V, b)
+    E = tv - (P @ tv_coarse.T).T                         # [Nv][ndof]: residuals of every test vector
+    Pw = widen_columns(P, bc, bca)
+    rows, cols, vals = [], [], []
+    tvc = np.zeros((tv_coarse.shape[0], nW * bca), dtype=complex)
+    for n in range(nW):
+        idx = np.arange(bc)
+        tvc[:, n * bca + idx] = tv_coarse[:, n * bc + idx]
+    for w in range(nW):
+        r = np.nonzero((owner == w) & frow)[0]
+        Q = np.zeros((r.size, k), dtype=complex)
+        for j in range(k):
+            v = E[j, r].copy()
+            for i in range(j):
+                v -= Q[:, i] * np.vdot(Q[:, i], v)
+            nrm = np.linalg.norm(v)
+            if not nrm > 0:
+                raise ValueError("test-vector residual has no component on a wirebasket")
+            Q[:, j] = v / nrm
+        for j in range(k):
+            rows.extend(r.tolist())
+            cols.extend([w * bca + bc + j] * r.size)
+            vals.extend(Q[:, j].tolist())
+        # coefficients of every test vector in W's basis (the next level's test vectors)
+        tvc[:, w * bca + bc:(w + 1) * bca] = E[:, r] @ Q.conj()
+    B = sp.csr_matrix((np.asarray(vals, dtype=complex), (rows, cols)), shape=(ndof, nW * bca))
+    return (Pw + B).tocsr(), tvc
+
+
 # ------------------------------------------------------------------------------- setup
 
 def setup(U: np.ndarray, m0: float, prm: SetupParams) -> list:
@@ -231,8 +286,14 @@ def setup(U: np.ndarray, m0: float, prm: SetupParams) -> list:
             tv_in = tv_coarse.copy()
         lev.P_tilde = local_interpolation(lev.A, Lt, Lx, b, a, o, cls)
         lev.P = normalise(lev.P_tilde, prm.norm, b, cls, tv, tv_coarse)
+        bc = o * o * b
+        if k == 0 and prm.aug_vectors > 0:
+            if tv is None or prm.aug_vectors > tv.shape[0]:
+                raise ValueError("augmentation needs that many test vectors (TESTVEC normalisation)")
+            lev.P, tv_in = augment(lev.P, tv, tv_coarse, b, bc, cls, prm.aug_vectors)
+            bc += prm.aug_vectors
         A = (lev.P.conj().T @ lev.A @ lev.P).tocsr()
-        Lt, Lx, b = Lt // a, Lx // a, o * o * b
+        Lt, Lx, b = Lt // a, Lx // a, bc
     return levels
 
 
