@@ -753,6 +753,8 @@ def main():
                     help="kernel family of the roofline (default: the largest in an instrumented "
                          "one-stream step)")
     ap.add_argument("--workload", default="C3")
+    ap.add_argument("--aug-vectors", type=int, default=None,
+                    help="test vectors augmenting the finest coarse space (default: the workload's)")
     ap.add_argument("--tv-sweeps", type=int, default=None,
                     help="smoother sweeps that relax the test vectors (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -825,12 +827,15 @@ def main():
     stream = torch.cuda.Stream()          # default priority; the library runs on it
     torch.cuda.set_stream(stream)
     w = synth.WORKLOADS[args.workload]
-    if args.tv_sweeps is not None:
+    if args.tv_sweeps is not None or args.aug_vectors is not None:
         import dataclasses
-        w = dataclasses.replace(w, test_vector_sweeps=args.tv_sweeps)
+        if args.tv_sweeps is not None:
+            w = dataclasses.replace(w, test_vector_sweeps=args.tv_sweeps)
+        if args.aug_vectors is not None:
+            w = dataclasses.replace(w, aug_vectors=args.aug_vectors)
     m0 = synth.critical_masses()[w.name] + w.gaps[0] if w.m0 is None else w.m0
     log(f"workload {w.name}: L={w.L} beta={w.beta} m0={m0:.6f} levels={w.levels} a={w.agg} "
-        f"o={w.overlap} nu={w.test_vector_sweeps} nrhs={args.nrhs}")
+        f"o={w.overlap} nu={w.test_vector_sweeps} aug={w.aug_vectors} nrhs={args.nrhs}")
     U = w.links()
     ctx = lib.Context(0, stream.cuda_stream)
     g = lib.Gauge(ctx, synth.links_to_abi(U), m0)

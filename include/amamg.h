@@ -82,6 +82,17 @@ typedef struct {
                                /* from 32 x 32 nodes, vector kernels below (default); 1 matrix */
                                /* cores; 2 vector kernels.  Fixed per hierarchy, so results do */
                                /* not depend on the batch                                      */
+  int32_t aug_vectors;         /* k >= 0 (default 0): the finest level's coarse space is        */
+                               /* augmented with the first k test vectors (Conclusion: test   */
+                               /* vectors in the SM-AMG method to capture the near-kernel):   */
+                               /* every wirebasket gets k coarse dofs on its node, after its  */
+                               /* o^2 b vertex dofs, spanned by an orthonormal basis (Gram-    */
+                               /* Schmidt in test-vector order) of the parts of those vectors */
+                               /* the wirebasket interpolation leaves on the non-vertex rows  */
+                               /* it owns.  Needs AMAMG_NORM_TESTVEC and k <= n_test_vectors; */
+                               /* level 1 then has o^2 * 2 + k dofs per node, a power of two  */
+                               /* <= 64 unless it is the coarsest level                       */
+  int32_t reserved;            /* 0                                                           */
 } amamg_setup_params;
 
 typedef struct {
@@ -250,7 +261,9 @@ amamg_status amamg_tuning_entries(amamg_context *ctx, amamg_tune_entry *out, int
                                   int32_t *count);
 
 /* ---- test hooks (host buffers) ---------------------------------------------------------- */
-/* out = D in for nrhs fields at the given precision (FP64 or FP32 links). */
+/* out = D in for nrhs fields at the given precision (FP64 or FP32 links): the Wilson-Dirac
+ * operator of the Schwinger Model subsection with its boundary conditions (periodic links,
+ * antiperiodic fermions in time).  Layout above; INVALID_ARG for null pointers or nrhs < 1. */
 amamg_status amamg_apply_dirac(amamg_gauge *g, int32_t precision, int32_t nrhs,
                                const double *in, double *out);
 /* out = D in on device buffers (same layout) at the given precision: AMAMG_FP64 uses FP64
@@ -262,9 +275,11 @@ amamg_status amamg_apply_dirac_device(amamg_gauge *g, int32_t precision, int32_t
 /* Grid of level `level` (0 = fine lattice) and degrees of freedom per node. */
 amamg_status amamg_level_info(const amamg_hierarchy *h, int32_t level, int32_t *lt,
                               int32_t *lx, int32_t *b);
-/* Wirebasket classification of level `level` (not the coarsest): per grid point the kind
+/* Wirebasket classification of level `level` (not the coarsest; SM-AMG subsection and its
+ * wirebasket figure: function types by the number of wirebaskets sharing a point, a shared
+ * point interpolated from the wirebasket it was assigned to first): per grid point the kind
  * (0 interior, 1 edge, 2 vertex), the primary wirebasket (-1 for vertices) and the coarse
- * node of a vertex (-1 otherwise).  Arrays of lt*lx entries. */
+ * node of a vertex (-1 otherwise).  Arrays of lt*lx entries, caller-owned host buffers. */
 amamg_status amamg_get_aggregates(const amamg_hierarchy *h, int32_t level, int8_t *kind,
                                   int32_t *owner, int32_t *node);
 /* Interpolation rows of level `level`: double [lt*lx][b][4*bc][2]; row (p, i) holds the

@@ -49,7 +49,7 @@ class SetupParams(C.Structure):
                 ("n_test_vectors", C.c_int32), ("test_vector_sweeps", C.c_int32),
                 ("pre_sweeps", C.c_int32), ("post_sweeps", C.c_int32), ("norm", C.c_int32),
                 ("seed", C.c_uint64), ("coarsest_tol", C.c_double), ("coarsest_max_iters", C.c_int32),
-                ("block_smoother", C.c_int32)]
+                ("block_smoother", C.c_int32), ("aug_vectors", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SolveParams(C.Structure):
@@ -341,10 +341,11 @@ class Hierarchy:
         self.ctx.check(_lib.amamg_get_aggregates(self.h, level, _ptr(kind), _ptr(owner), _ptr(node)))
         return kind, owner, node
 
-    def prolongator_rows(self, level: int, overlap: int) -> np.ndarray:
-        """complex [lt*lx][b][4*bc] interpolation rows (vertex rows zero)."""
+    def prolongator_rows(self, level: int, overlap: int, aug: int = 0) -> np.ndarray:
+        """complex [lt*lx][b][4*bc] interpolation rows (vertex rows zero); bc = o^2 b, plus the
+        augmented dofs on level 0."""
         lt, lx, b = self.level_info(level)
-        bc = overlap * overlap * b
+        bc = overlap * overlap * b + (aug if level == 0 else 0)
         out = np.zeros((lt * lx, b, 4 * bc, 2))
         self.ctx.check(_lib.amamg_get_prolongator(self.h, level, _ptr(out)))
         return out[..., 0] + 1j * out[..., 1]

@@ -37,10 +37,12 @@ struct Geom {
   int Lt, Lx, b;      // grid and degrees of freedom per node
   int a, o;           // aggregate size, overlap
   int nI, nJ;         // wirebaskets per direction (Lt / a, Lx / a)
-  int bc;             // degrees of freedom per coarse node (o * o * b)
+  int bv;             // vertex degrees of freedom per coarse node (o * o * b)
+  int bc;             // degrees of freedom per coarse node: bv, plus the augmented ones
   __host__ __device__ int nnode() const { return Lt * Lx; }
   __host__ __device__ int64_t ndof() const { return int64_t(Lt) * Lx * b; }
   __host__ __device__ int ncol() const { return 4 * bc; }   // interpolation columns per row
+  __host__ __device__ int nvcol() const { return 4 * bv; }  // columns of the local systems' V part
   __host__ __device__ int fp() const { return (a + o) * (a + o); }
 };
 
@@ -135,6 +137,13 @@ void aug_identity(hipStream_t s, const double2* A, int64_t astride, int arow, in
                   int nsys);
 void scatter_P(hipStream_t s, const Geom& g, const double2* X, const int* postab, int nf,
                const int* owner, double2* P);
+// augmented coarse space: per wirebasket, P's k extra columns (corner 0, after the bv vertex
+// dofs) become an orthonormal basis of (tv_j - Ptv_j), j < k, on its owned rows, and every test
+// vector's coefficients in that basis go to tvc (whose vertex dofs hold the injection).  Ptv =
+// P tvc before the call.  info[w] = 1 where a residual vanishes.  maxrows <= kAugMaxRows.
+constexpr int kAugMaxRows = 1024;
+void augment(hipStream_t s, const Geom& g, double2* P, const int* rows, const int* nrows, int maxrows,
+             const double2* tv, const double2* Ptv, double2* tvc, int nv, int k, int* info);
 // P rows scaled by the normalisation (mode 0 TESTVEC, 1 CONST; 2 NONE is a no-op)
 void normalise(hipStream_t s, const Geom& g, double2* P, const int* owner, const double2* tv,
                const double2* tvc, int nv, int mode);

@@ -166,6 +166,9 @@ std::vector<LevelPlan> plan_levels(int nt, int nx, const amamg_setup_params& p) 
   REQUIRE(p.coarsest_tol == 0 || (p.coarsest_max_iters >= 1 && p.coarsest_max_iters <= kCoarsestGmresMaxSteps),
           AMAMG_ERR_INVALID_ARG, "coarsest_max_iters must be in [1, 32]");
   REQUIRE(p.block_smoother >= 0 && p.block_smoother <= 2, AMAMG_ERR_INVALID_ARG, "block_smoother must be 0, 1 or 2");
+  REQUIRE(p.aug_vectors >= 0 && (p.aug_vectors == 0 || (p.norm == AMAMG_NORM_TESTVEC &&
+                                                        p.aug_vectors <= p.n_test_vectors)),
+          AMAMG_ERR_INVALID_ARG, "aug_vectors needs the TESTVEC normalisation and at most n_test_vectors");
   std::vector<LevelPlan> out;
   int Lt = nt, Lx = nx, b = 2;
   const int a = p.agg_size, o = p.overlap;
@@ -184,6 +187,7 @@ std::vector<LevelPlan> plan_levels(int nt, int nx, const amamg_setup_params& p) 
     Lt /= a;
     Lx /= a;
     b *= o * o;
+    if (k == 0) b += p.aug_vectors;     // the finest level's augmented coarse dofs
   }
   const LevelPlan& c = out.back();
   REQUIRE(int64_t(c.Lt) * c.Lx * c.b <= 4096, AMAMG_ERR_UNSUPPORTED_SHAPE,
@@ -193,12 +197,13 @@ std::vector<LevelPlan> plan_levels(int nt, int nx, const amamg_setup_params& p) 
   return out;
 }
 
-Geom make_geom(const LevelPlan& l, int a, int o, bool coarsest) {
+Geom make_geom(const LevelPlan& l, int a, int o, bool coarsest, int aug = 0) {
   Geom g{};
   g.Lt = l.Lt; g.Lx = l.Lx; g.b = l.b; g.a = a; g.o = o;
   g.nI = coarsest ? 0 : l.Lt / a;
   g.nJ = coarsest ? 0 : l.Lx / a;
-  g.bc = o * o * l.b;
+  g.bv = o * o * l.b;
+  g.bc = g.bv + (coarsest ? 0 : aug);
   return g;
 }
 
@@ -221,14 +226,15 @@ size_t setup_bytes(int nt, int nx, const amamg_setup_params& p) {
   const size_t c16 = sizeof(double2), c8 = sizeof(float2);
   size_t b = size_t(nt) * nx * 5 * 4 * c16;
   for (int k = 0; k + 1 < K; ++k) {
-    const Geom g = make_geom(plan[k], a, o, false);
+    const Geom g = make_geom(plan[k], a, o, false, k == 0 ? p.aug_vectors : 0);
     const Geom gc = make_geom(plan[k + 1], a, o, k + 1 == K - 1);
     const size_t nnode = g.nnode(), ndof = g.ndof(), ndc = gc.ndof(), nnc = gc.nnode();
     int nf = 0;
     const std::vector<int> tabs = footprint_tables(a, o, g.b, &nf);
     const size_t nW = size_t(g.nI) * g.nJ, nfd = size_t(nf) * g.b, ncol = g.ncol(), bc = g.bc;
     b += nnode * 9 + size_t(nv) * ndof * c16 + tabs.size() * 4 + nW * nf * g.b * 4 + nW * 8;
-    b += nW * nfd * (nfd + ncol) * c16 + ndof * ncol * (c16 + c8);
+    b += nW * nfd * (nfd + g.nvcol()) * c16 + ndof * ncol * (c16 + c8);
+    if (k == 0 && p.aug_vectors > 0) b += size_t(nv) * ndof * c16 + nW * 4;
     b += size_t(nv) * ndc * c16 * 2;
     b += bc * (2 * ndc + 2 * ndof) * c16 + bc * nW * restrict_chunks(g, nf, F64) * ncol * c16;
     if (k + 1 == K - 1) b += ndc * ndc * c16 * (p.coarsest_tol > 0 ? 5 : 4);
@@ -242,7 +248,7 @@ size_t setup_bytes(int nt, int nx, const amamg_setup_params& p) {
 // Buffers only the setup itself needs; with a scratch pool they live there (and are reused by
 // the next setup) instead of in the hierarchy.
 static bool setup_scratch(const char* name) {
-  static const char* names[] = {"A0", "d_offs5", "d_offs25", "L_tv", "Aug", "info", "Wc",
+  static const char* names[] = {"A0", "d_offs5", "d_offs25", "L_tv", "Aug", "info", "Wc", "Ptv", "ainfo",
                                 "pe", "py", "pz", "pu", "ppart", "Dg", "dinfo", "LUc", "cinfo", "keep"};
   for (const char* n : names)
     if (std::strcmp(n, name) == 0) return true;
@@ -359,7 +365,7 @@ void run_setup(amamg_hierarchy* h, hipStream_t stream, Pool* scratch) {
   const int a = p.agg_size, o = p.overlap;
   h->lv.resize(K);
   for (int k = 0; k < K; ++k) {
-    h->lv[k].g = make_geom(plan[k], a, o, k == K - 1);
+    h->lv[k].g = make_geom(plan[k], a, o, k == K - 1, k == 0 ? p.aug_vectors : 0);
     h->lv[k].coarsest = (k == K - 1);
   }
   const double2* U0 = gg->U;
@@ -417,12 +423,12 @@ void run_setup(amamg_hierarchy* h, hipStream_t stream, Pool* scratch) {
     L.nrows = pool("L_nrows").get<int>("L_nrows", k, size_t(g.nI) * g.nJ);
     HIPCHECK(hipMemcpyAsync(d_tabs, tabs.data(), sizeof(int) * tabs.size(), hipMemcpyHostToDevice, s));
     owned_rows(s, g, d_tabs + g.fp(), nf, L.owner, L.rows, L.nrows);
-    const int nW = g.nI * g.nJ, nfd = nf * g.b, ncol = g.ncol();
-    double2* Aug = pool("Aug").get<double2>("Aug", k, size_t(nW) * nfd * (nfd + ncol));
+    const int nW = g.nI * g.nJ, nfd = nf * g.b, ncol = g.ncol(), nvc = g.nvcol();
+    double2* Aug = pool("Aug").get<double2>("Aug", k, size_t(nW) * nfd * (nfd + nvc));
     int* info = pool("info").get<int>("info", k, nW);
     if (k == 0) gather_local(s, g, A0, 5, d_offs5, d_tabs, nf, Aug);
     else gather_local(s, g, L.A, 25, d_offs25, d_tabs, nf, Aug);
-    dense_solve(s, Aug, nfd, ncol, nW, info);
+    dense_solve(s, Aug, nfd, nvc, nW, info);
     check_launch();
     std::vector<int> hinfo(nW);
     HIPCHECK(hipMemcpyAsync(hinfo.data(), info, sizeof(int) * nW, hipMemcpyDeviceToHost, s));
@@ -441,10 +447,27 @@ void run_setup(amamg_hierarchy* h, hipStream_t stream, Pool* scratch) {
     const int64_t ndof_c = gc.ndof();
     if (nv > 0) {
       Wc = pool("Wc").get<double2>("Wc", k, size_t(nv) * ndof_c);
+      HIPCHECK(hipMemsetAsync(Wc, 0, sizeof(double2) * nv * ndof_c, s));
       inject(s, g, L.node, L.kind, L.tv, Wc, nv);
     }
     normalise(s, g, L.P, L.owner, L.tv, Wc, nv, p.norm);
     check_launch();
+    if (k == 0 && p.aug_vectors > 0) {
+      // augmented coarse space: the test vectors' residuals of the wirebasket interpolation
+      REQUIRE(nf * g.b <= kAugMaxRows, AMAMG_ERR_UNSUPPORTED_SHAPE,
+              "augmented coarse space: wirebaskets own at most 1024 rows");
+      double2* Ptv = pool("Ptv").get<double2>("Ptv", k, size_t(nv) * ndof);
+      int* ainfo = pool("ainfo").get<int>("ainfo", k, nW);
+      prolong(s, F64, L.P, L.rows, L.nrows, L.nf, Wc, Ptv, g, 0, nv, ndof, ndof_c, nullptr);
+      augment(s, g, L.P, L.rows, L.nrows, nf * g.b, L.tv, Ptv, Wc, nv, p.aug_vectors, ainfo);
+      check_launch();
+      std::vector<int> ha(nW);
+      HIPCHECK(hipMemcpyAsync(ha.data(), ainfo, sizeof(int) * nW, hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      for (int w = 0; w < nW; ++w)
+        REQUIRE(ha[w] == 0, AMAMG_ERR_SINGULAR_LOCAL,
+                "a test vector's interpolation residual vanishes on wirebasket " + std::to_string(w));
+    }
 
     // Galerkin operator by probing
     LevelData& C = h->lv[k + 1];
@@ -584,6 +607,7 @@ void amamg_default_setup_params(amamg_setup_params* p) {
   p->test_vector_sweeps = 4; p->pre_sweeps = 0; p->post_sweeps = 2;
   p->norm = AMAMG_NORM_TESTVEC; p->seed = 0;
   p->coarsest_tol = 0; p->coarsest_max_iters = 32; p->block_smoother = 0;
+  p->aug_vectors = 0; p->reserved = 0;
 }
 
 void amamg_default_solve_params(amamg_solve_params* p) {

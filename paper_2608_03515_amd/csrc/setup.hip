@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void k_gather_local(Geom g, const double2* __r
   const int w = blockIdx.x;
   const int I = w / g.nJ, J = w - (w / g.nJ) * g.nJ;
   const int fpw = g.a + g.o;
-  const int nfd = nf * g.b, ncol = g.ncol(), ld = nfd + ncol;
+  const int nfd = nf * g.b, ncol = g.nvcol(), ld = nfd + ncol;
   double2* Aw = Aug + int64_t(w) * nfd * ld;
   for (int64_t e = threadIdx.x; e < int64_t(nfd) * ld; e += blockDim.x) Aw[e] = make_double2(0, 0);
   __syncthreads();
@@ -285,7 +285,7 @@ __global__ void k_scatter_P(Geom g, const double2* __restrict__ X, const int* __
                             int nf, const int* __restrict__ owner, double2* __restrict__ P) {
   const int w = blockIdx.x;
   const int I = w / g.nJ, J = w - (w / g.nJ) * g.nJ;
-  const int fpw = g.a + g.o, ncol = g.ncol(), nfd = nf * g.b;
+  const int fpw = g.a + g.o, ncol = g.nvcol(), nfd = nf * g.b;
   const double2* Xw = X + int64_t(w) * nfd * (nfd + ncol);
   for (int64_t e = threadIdx.x; e < int64_t(nfd) * ncol; e += blockDim.x) {
     const int rrow = int(e / ncol), col = int(e - int64_t(rrow) * ncol);
@@ -294,8 +294,88 @@ __global__ void k_scatter_P(Geom g, const double2* __restrict__ X, const int* __
     const int dt = pos / fpw, dx = pos - (pos / fpw) * fpw;
     const int p = wrap_s(g.a * I + dt, g.Lt) * g.Lx + wrap_s(g.a * J + dx, g.Lx);
     if (owner[p] != w) continue;
-    P[(int64_t(p) * g.b + i) * ncol + col] = Xw[int64_t(rrow) * (nfd + ncol) + nfd + col];
+    // local column (corner, vertex dof) -> the corner's block of bc columns in P's row
+    const int c = col / g.bv, j = col - c * g.bv;
+    P[(int64_t(p) * g.b + i) * g.ncol() + c * g.bc + j] = Xw[int64_t(rrow) * (nfd + ncol) + nfd + col];
   }
+}
+
+// Augmented coarse space, one workgroup per wirebasket w (its owned rows, at most 4 per thread):
+// e_j = tv_j - Ptv_j on the rows; Gram-Schmidt in order j = 0..k-1, each projection subtracted
+// from the updated vector (v -= q_i (q_i^H v)); q_j goes to P's column bv + j of the rows (corner
+// 0, the wirebasket's own node), and q_j^H e_l of every test vector l to the coarse test vector
+// tvc_l at node w, dof bv + j.  Sums over the rows are block reductions in a fixed order.
+constexpr int kAugRowsPerThread = kAugMaxRows / 256;
+
+__device__ inline double2 block_sum_c(double2 v, double2* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (t < h) red[t] = cadd(red[t], red[t + h]);
+    __syncthreads();
+  }
+  const double2 r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_augment(Geom g, double2* __restrict__ P, const int* __restrict__ rows,
+                                                 const int* __restrict__ nrows, int maxrows,
+                                                 const double2* __restrict__ tv, const double2* __restrict__ Ptv,
+                                                 double2* __restrict__ tvc, int nv, int k, int* __restrict__ info) {
+  __shared__ double2 red[256];
+  const int w = blockIdx.x;
+  const int nr = nrows[w];
+  const int64_t nd = g.ndof(), ncd = int64_t(g.nI) * g.nJ * g.bc;
+  const int ncol = g.ncol();
+  int rr[kAugRowsPerThread];
+#pragma unroll
+  for (int u = 0; u < kAugRowsPerThread; ++u) {
+    const int i = threadIdx.x + u * 256;
+    rr[u] = i < nr ? rows[int64_t(w) * maxrows + i] : -1;
+  }
+  if (threadIdx.x == 0) info[w] = 0;
+  for (int j = 0; j < k; ++j) {
+    double2 v[kAugRowsPerThread];
+#pragma unroll
+    for (int u = 0; u < kAugRowsPerThread; ++u)
+      v[u] = rr[u] >= 0 ? csub(tv[int64_t(j) * nd + rr[u]], Ptv[int64_t(j) * nd + rr[u]]) : make_double2(0, 0);
+    for (int i = 0; i < j; ++i) {
+      double2 d = make_double2(0, 0);          // q_i^H v
+#pragma unroll
+      for (int u = 0; u < kAugRowsPerThread; ++u)
+        if (rr[u] >= 0) d = cfmac(P[int64_t(rr[u]) * ncol + g.bv + i], v[u], d);
+      d = block_sum_c(d, red);
+#pragma unroll
+      for (int u = 0; u < kAugRowsPerThread; ++u)
+        if (rr[u] >= 0) v[u] = csub(v[u], cmul(P[int64_t(rr[u]) * ncol + g.bv + i], d));
+    }
+    double2 n2 = make_double2(0, 0);
+#pragma unroll
+    for (int u = 0; u < kAugRowsPerThread; ++u) n2.x += cabs2(v[u]);
+    n2 = block_sum_c(n2, red);
+    const double nrm = sqrt(n2.x);
+    if (!(nrm > 0)) {
+      if (threadIdx.x == 0) info[w] = 1;
+      return;
+    }
+#pragma unroll
+    for (int u = 0; u < kAugRowsPerThread; ++u)
+      if (rr[u] >= 0) P[int64_t(rr[u]) * ncol + g.bv + j] = make_double2(v[u].x / nrm, v[u].y / nrm);
+  }
+  // coefficients of every test vector in the wirebasket's basis
+  for (int l = 0; l < nv; ++l)
+    for (int j = 0; j < k; ++j) {
+      double2 d = make_double2(0, 0);
+#pragma unroll
+      for (int u = 0; u < kAugRowsPerThread; ++u)
+        if (rr[u] >= 0)
+          d = cfmac(P[int64_t(rr[u]) * ncol + g.bv + j],
+                    csub(tv[int64_t(l) * nd + rr[u]], Ptv[int64_t(l) * nd + rr[u]]), d);
+      d = block_sum_c(d, red);
+      if (threadIdx.x == 0) tvc[int64_t(l) * ncd + int64_t(w) * g.bc + g.bv + j] = d;
+    }
 }
 
 __device__ inline int corner_node_s(int w, int c, int nI, int nJ) {
@@ -447,6 +527,12 @@ void scatter_P(hipStream_t s, const Geom& g, const double2* X, const int* postab
                const int* owner, double2* P) {
   hipLaunchKernelGGL(k_scatter_P, dim3(g.nI * g.nJ), dim3(256), 0, s, g, X, postab_fpos + g.fp(),
                      nf, owner, P);
+}
+
+void augment(hipStream_t s, const Geom& g, double2* P, const int* rows, const int* nrows, int maxrows,
+             const double2* tv, const double2* Ptv, double2* tvc, int nv, int k, int* info) {
+  hipLaunchKernelGGL(k_augment, dim3(g.nI * g.nJ), dim3(256), 0, s, g, P, rows, nrows, maxrows, tv, Ptv, tvc,
+                     nv, k, info);
 }
 
 void normalise(hipStream_t s, const Geom& g, double2* P, const int* owner, const double2* tv,

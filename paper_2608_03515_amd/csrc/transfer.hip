@@ -9,7 +9,9 @@
 //   node (I,J) = the o x o vertices (aI + pt, aJ + px), coarse dof (pt*o + px)*b + q;
 //   primary wirebasket of an edge point = the lowest index I * nJ + J containing it.
 // Interpolation storage, row-major over fine dofs: P[p][i][c*bc + j], c = 2*ct + cx the corner
-// node ((I+ct) mod nI, (J+cx) mod nJ) of p's primary wirebasket, bc = o*o*b.  Vertex rows are
+// node ((I+ct) mod nI, (J+cx) mod nJ) of p's primary wirebasket, bc = o*o*b (plus the augmented
+// dofs on the finest level, which follow the vertex dofs of each node and are nonzero only in
+// corner 0, the row's own wirebasket).  Vertex rows are
 // the identity and are not stored (left zero).
 #include "launch.hpp"
 
@@ -473,7 +475,11 @@ __global__ __launch_bounds__(256) void k_restrict_gather(const cplx<R>* __restri
   const int ncol = g.ncol();
   // all loads first (from valid addresses: chunk 0 past the end), then the sums in the order
   // corner, chunk, so that the loads are in flight together
-  const int q = j % g.b, pp = j / g.b;
+  // the node's vertex dofs also take r at the vertex (identity rows); the augmented dofs after
+  // them (j >= bv) only the wirebasket sums
+  const bool vert = j < g.bv;
+  const int jv = vert ? j : 0;
+  const int q = jv % g.b, pp = jv / g.b;
   const int pt = pp / g.o, px = pp - (pp / g.o) * g.o;
   const int p = (g.a * I + pt) * g.Lx + (g.a * J + px);
   const Vin rv = rin[r * stride_f + int64_t(p) * g.b + q];
@@ -504,7 +510,7 @@ __global__ __launch_bounds__(256) void k_restrict_gather(const cplx<R>* __restri
     sum.y += __shfl_xor(sum.y, off);
   }
   if (!live || ln != 0) return;
-  sum = cadd(sum, cconv<C>(rv));
+  if (vert) sum = cadd(sum, cconv<C>(rv));
   rc[r * stride_c + gid] = cconv<Vout>(sum);
 }
 

@@ -119,6 +119,7 @@ class Workload:
     n_test_vectors: int
     test_vector_sweeps: int = 4
     m0: float | None = None          # fixed bare mass, or None when given by critical mass + gap
+    aug_vectors: int = 0             # test vectors augmenting the finest level's coarse space
     gaps: tuple = field(default_factory=tuple)
     restart: int = 20
     tol: float = 1e-10
@@ -129,14 +130,16 @@ class Workload:
     def setup_kw(self, **extra) -> dict:
         """Hierarchy parameters as keyword arguments of the library's setup parameters."""
         kw = dict(levels=self.levels, agg_size=self.agg, overlap=self.overlap,
-                  n_test_vectors=self.n_test_vectors, test_vector_sweeps=self.test_vector_sweeps)
+                  n_test_vectors=self.n_test_vectors, test_vector_sweeps=self.test_vector_sweeps,
+                  aug_vectors=self.aug_vectors)
         kw.update(extra)
         return kw
 
     def oracle_kw(self, **extra) -> dict:
         """The same parameters as keyword arguments of the oracle's setup parameters."""
         kw = dict(levels=self.levels, agg=self.agg, overlap=self.overlap,
-                  n_test_vectors=self.n_test_vectors, test_vector_sweeps=self.test_vector_sweeps)
+                  n_test_vectors=self.n_test_vectors, test_vector_sweeps=self.test_vector_sweeps,
+                  aug_vectors=self.aug_vectors)
         kw.update(extra)
         return kw
 
