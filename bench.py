@@ -328,7 +328,6 @@ def multi_lattice_leg(lib, torch, ctx, groups, instances=8, slots=8, nrhs_per=8,
     links = [synth.serving_links(c) for c in cfgs] if links is None else links[0]
     srv = lib.Server(0, lib.default_server_params(slots=slots, max_instances=instances, precision=lib.MIXED_FP32))
     gids = [srv.add_gauge(synth.links_to_abi(U)) for U in links]
-    del links
     setups = [lib.default_setup_params(**synth.serving_setup(c["L"])) for c in cfgs]
     rhs = [synth.field_to_abi(synth.gaussian_rhs(c["L"], c["L"], c["seed"] + 99, nrhs=nrhs_per)) for c in cfgs]
     for phase in ("cold", "warm"):
@@ -344,11 +343,41 @@ def multi_lattice_leg(lib, torch, ctx, groups, instances=8, slots=8, nrhs_per=8,
             "iterations_max": max(i.iterations for i in done),
             "max_rel_residual": max(i.true_rel_residual for i in done)}
     st = srv.stats()
+    srv.close()
+    # the same 32 lattices as one lock-step solve: each Gram-Schmidt kernel launched once for all
+    # lattices, and (graphs) one captured HIP graph per restart round
+    ctx2 = lib.Context(0, torch.cuda.current_stream().cuda_stream)
+    gs2 = [lib.Gauge(ctx2, synth.links_to_abi(U), mcs[k] + c["gap"]) for k, (U, c) in enumerate(zip(links, cfgs))]
+    t0 = time.perf_counter()
+    hs2 = [lib.Hierarchy(g2, st_) for g2, st_ in zip(gs2, setups)]
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    bs = [torch.from_numpy(r).to("cuda") for r in rhs]
+    for graphs in (0, 1):
+        xs = [torch.zeros_like(b_) for b_ in bs]
+        sp = lib.default_solve_params(precision=lib.MIXED_FP32, graphs=graphs)
+        for rep in range(2):                       # the first call tunes and captures
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            infos, stt = lib.solve_multi_device(hs2, [nrhs_per] * len(cfgs), [b_.data_ptr() for b_ in bs],
+                                                [x_.data_ptr() for x_ in xs], sp,
+                                                torch.cuda.current_stream().cuda_stream)
+            torch.cuda.synchronize()
+            span = time.perf_counter() - t0
+        flat = [i for li in infos for i in li]
+        out[f"lattices_32_lockstep{'_graph' if graphs else ''}"] = {
+            "makespan_s": span, "solves_per_s": len(cfgs) * nrhs_per / span, "setup_s_all": t_setup,
+            "ok": sum(1 for i in flat if i.converged) // nrhs_per, "iterations_max": max(i.iterations for i in flat),
+            "max_rel_residual": max(i.true_rel_residual for i in flat)}
+    for h2 in hs2:
+        h2.close()
+    for g2 in gs2:
+        g2.close()
+    ctx2.close()
     out["lattices_32_setups"] = st.setups
     out["lattices"] = {str(L): sum(1 for c in cfgs if c["L"] == L) for L in synth.MULTI_SIZES}
     out["nrhs_per_lattice"] = nrhs_per
     out["instances"], out["slots"] = instances, slots
-    srv.close()
     return out
 
 

@@ -208,6 +208,23 @@ amamg_status amamg_solve_device(amamg_hierarchy *h, int32_t nrhs, const void *ps
  * ||psi||, flagged 1 in is_true_residual).  Writes min(capacity, length) entries of out and
  * of is_true_residual (either may be NULL); n_written (may be NULL) receives the full length.
  * AMAMG_ERR_INVALID_ARG for an rhs outside the last solve. */
+/* Several lattices solved together (spec: uneven lattices batched in one launch): nlat
+ * hierarchies, distinct and of one context, each with nrhs[l] right-hand sides in its own
+ * device buffers psi_dev[l], x_dev[l] (layout and alignment as amamg_solve_device).  The
+ * lattices advance in lock step: at every Arnoldi step each lattice's V-cycle and matvec run on
+ * one of up to four streams, then each Gram-Schmidt kernel runs once for all lattices (the
+ * Multilevel approach's V-cycle and the FGMRES of Numerical Results, as amamg_solve).  With
+ * params->graphs a whole restart round of all lattices is one captured HIP graph, launched once
+ * per round.  A right-hand side's result is bitwise that of amamg_solve_device on its lattice
+ * alone with nrhs[l] right-hand sides.  info: sum of nrhs entries in lattice order (may be
+ * NULL); residual histories per hierarchy as after amamg_solve.  Runs after the work queued on
+ * hip_stream (NULL: the context stream), which then follows the solve; blocks until done.
+ * Errors as amamg_solve_device; INVALID_ARG for a hierarchy listed twice or of another
+ * context. */
+amamg_status amamg_solve_multi_device(amamg_hierarchy *const *hs, int32_t nlat, const int32_t *nrhs,
+                                      const void *const *psi_dev, void *const *x_dev,
+                                      const amamg_solve_params *params, amamg_solve_info *info,
+                                      void *hip_stream);
 amamg_status amamg_residual_history(const amamg_hierarchy *h, int32_t rhs, double *out,
                                     int32_t capacity, int32_t *n_written,
                                     int32_t *is_true_residual);

@@ -31,7 +31,7 @@ STATUS_CODES = {v: k for k, v in STATUS_NAMES.items()}
 EXPORTED = ["amamg_default_setup_params", "amamg_default_solve_params", "amamg_context_create",
             "amamg_context_destroy", "amamg_last_error", "amamg_gauge_load",
             "amamg_gauge_set_mass", "amamg_gauge_update_links", "amamg_gauge_destroy",
-            "amamg_setup", "amamg_hierarchy_update", "amamg_hierarchy_set_mass", "amamg_hierarchy_derive_mass", "amamg_hierarchy_destroy", "amamg_solve", "amamg_solve_device",
+            "amamg_setup", "amamg_hierarchy_update", "amamg_hierarchy_set_mass", "amamg_hierarchy_derive_mass", "amamg_hierarchy_destroy", "amamg_solve", "amamg_solve_device", "amamg_solve_multi_device",
             "amamg_residual_history", "amamg_apply_dirac", "amamg_apply_dirac_device",
             "amamg_level_info",
             "amamg_get_aggregates", "amamg_get_prolongator", "amamg_get_coarse_operator",
@@ -114,6 +114,8 @@ _sig = {
     "amamg_hierarchy_destroy": (C.c_int, [_vp]),
     "amamg_solve": (C.c_int, [_vp, C.c_int32, _vp, _vp, _P(SolveParams), _P(SolveInfo)]),
     "amamg_solve_device": (C.c_int, [_vp, C.c_int32, _vp, _vp, _P(SolveParams), _P(SolveInfo), _vp]),
+    "amamg_solve_multi_device": (C.c_int, [_P(_vp), C.c_int32, _P(C.c_int32), _P(_vp), _P(_vp), _P(SolveParams),
+                                           _P(SolveInfo), _vp]),
     "amamg_residual_history": (C.c_int, [_vp, C.c_int32, _vp, C.c_int32, _P(C.c_int32), _vp]),
     "amamg_apply_dirac": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _vp]),
     "amamg_apply_dirac_device": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _vp]),
@@ -264,6 +266,27 @@ class Gauge:
         if self.h:
             self.ctx.check(_lib.amamg_gauge_destroy(self.h))
             self.h = None
+
+
+def solve_multi_device(hierarchies, nrhs, psi_ptrs, x_ptrs, params: SolveParams | None = None,
+                       stream: int | None = None):
+    """Several lattices in lock step (amamg_solve_multi_device): hierarchies of one context,
+    per lattice its right-hand-side count and raw device pointers.  Returns (infos per lattice,
+    status)."""
+    L = len(hierarchies)
+    hs = (_vp * L)(*[h.h for h in hierarchies])
+    nr = (C.c_int32 * L)(*nrhs)
+    ps = (_vp * L)(*[_vp(p) for p in psi_ptrs])
+    xs = (_vp * L)(*[_vp(p) for p in x_ptrs])
+    infos = (SolveInfo * sum(nrhs))()
+    st = _lib.amamg_solve_multi_device(hs, L, nr, ps, xs, C.byref(params) if params else None, infos,
+                                       _vp(stream) if stream else None)
+    hierarchies[0].ctx.check(st, ok=(OK, NOT_CONVERGED))
+    out, k = [], 0
+    for n in nrhs:
+        out.append(list(infos[k:k + n]))
+        k += n
+    return out, st
 
 
 class Hierarchy:

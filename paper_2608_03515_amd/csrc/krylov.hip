@@ -29,6 +29,7 @@
 // (c x + s y, -conj(s) x + c y); g_{j+1} = -conj(s) g_j, g_j = c g_j.
 //
 // Vector layouts: basis V [slot][rhs][n], search directions Z [j][rhs][n], w and x [rhs][n].
+#include <algorithm>
 #include <array>
 #include <utility>
 
@@ -116,17 +117,6 @@ __device__ inline void sum_blocks(const double2* __restrict__ part_r, int nblk, 
 
 __device__ inline bool finite_d(double v) { return v == v && v - v == 0.0; }
 
-struct ArnoldiArgs {
-  double2* H;       // [rhs][(m+1) m], H[i][j] at i*m + j
-  double* cs;       // [rhs][m]
-  double2* sn;      // [rhs][m]
-  double2* g;       // [rhs][m+1]
-  int j;
-  double tol, inner_tol;
-  int max_iters;
-  double2* hist;
-  int hist_cap;
-};
 
 // Completes Hessenberg column j = a.j of one rhs: col[0..j] holds its projections and
 // col[j + 1] = hn = h_{j+1,j}; the earlier rotations csl/snl (all in LDS).  Rotates the
@@ -185,13 +175,12 @@ constexpr int update_lanes(int nv) { return nv <= 2 ? 1 : nv <= 24 ? 2 : 4; }
 // Pass A: partials of V^H u into part[.][0, NV) and (HAS_W) of V^H w into part[.][KMAXV,
 // KMAXV + NV), over slots 0..NV-1, where u is slot NV-1 itself.  Each basis value is read
 // from memory once; u and w are read once per element and shared by the element's lanes.
+// One block's share (block blk of right-hand side r, of dm.nblk per rhs) of pass A.
 template <int NV, int S, bool HAS_W>
-__global__ __launch_bounds__(256) void k_gram(KrylovDims dm, const double2* __restrict__ V,
-                                              int64_t vsj, const double2* __restrict__ w,
-                                              double2* __restrict__ part,
-                                              const RhsState* __restrict__ st) {
+__device__ inline void gram_item(const KrylovDims& dm, const double2* __restrict__ V, int64_t vsj,
+                                 const double2* __restrict__ w, double2* __restrict__ part,
+                                 const RhsState* __restrict__ st, int r, int blk) {
   constexpr int K = (NV + S - 1) / S, EPB = 256 / S;
-  const int r = blockIdx.y;
   if (!st[r].active) return;
   __shared__ double2 red[4][KGRAM];
   const int sub = threadIdx.x % S;
@@ -202,7 +191,7 @@ __global__ __launch_bounds__(256) void k_gram(KrylovDims dm, const double2* __re
   const double2* ur = Vr + int64_t(NV - 1) * vsj;
   const double2* wr = HAS_W ? w + r * dm.n : nullptr;
 #pragma unroll 1
-  for (int64_t d = int64_t(blockIdx.x) * EPB + threadIdx.x / S; d < dm.n; d += int64_t(gridDim.x) * EPB) {
+  for (int64_t d = int64_t(blk) * EPB + threadIdx.x / S; d < dm.n; d += int64_t(dm.nblk) * EPB) {
     // every lane loads, slots past the last clamped to it: their sums are never stored (only
     // slots i < NV are), and a masked load would become a branch that waits for every load in
     // flight.  The scheduling barrier keeps all of the element's loads ahead of the products, so
@@ -247,8 +236,17 @@ __global__ __launch_bounds__(256) void k_gram(KrylovDims dm, const double2* __re
   if (t < NV || (HAS_W && t >= KMAXV && t < KMAXV + NV)) {
     double2 a = red[0][t];
     for (int q = 1; q < 4; ++q) a = cadd(a, red[q][t]);
-    part[(int64_t(r) * gridDim.x + blockIdx.x) * KGRAM + t] = a;
+    part[(int64_t(r) * dm.nblk + blk) * KGRAM + t] = a;
   }
+  __syncthreads();                                     // red is reused by the next item
+}
+
+template <int NV, int S, bool HAS_W>
+__global__ __launch_bounds__(256) void k_gram(KrylovDims dm, const double2* __restrict__ V,
+                                              int64_t vsj, const double2* __restrict__ w,
+                                              double2* __restrict__ part,
+                                              const RhsState* __restrict__ st) {
+  gram_item<NV, S, HAS_W>(dm, V, vsj, w, part, st, int(blockIdx.y), int(blockIdx.x));
 }
 
 // Pass B: v = sum_{i<NV} a_i V_i into slot NV-1 (when write_v; slot 0 is already final) and
@@ -256,12 +254,10 @@ __global__ __launch_bounds__(256) void k_gram(KrylovDims dm, const double2* __re
 // KMAXV + NV) and inv = coef[r][KGRAM - 1].x.  Slot NV-1 is overwritten in place: each element
 // is read before it is written, by the same lanes.
 template <int NV, int S>
-__global__ __launch_bounds__(256) void k_lag_update(KrylovDims dm, double2* __restrict__ V, int64_t vsj,
-                                                    const double2* __restrict__ w,
-                                                    const double2* __restrict__ coef,
-                                                    const RhsState* __restrict__ st, int write_v) {
+__device__ inline void lag_update_item(const KrylovDims& dm, double2* __restrict__ V, int64_t vsj,
+                                       const double2* __restrict__ w, const double2* __restrict__ coef,
+                                       const RhsState* __restrict__ st, int write_v, int r, int blk) {
   constexpr int K = (NV + S - 1) / S, EPB = 256 / S;
-  const int r = blockIdx.y;
   if (!st[r].active) return;
   const int sub = threadIdx.x % S;
   const double2* cr = coef + int64_t(r) * KGRAM;
@@ -278,7 +274,7 @@ __global__ __launch_bounds__(256) void k_lag_update(KrylovDims dm, double2* __re
   double2* vo = Vr + int64_t(NV - 1) * vsj;
   double2* uo = Vr + int64_t(NV) * vsj;
 #pragma unroll 1
-  for (int64_t d = int64_t(blockIdx.x) * EPB + threadIdx.x / S; d < dm.n; d += int64_t(gridDim.x) * EPB) {
+  for (int64_t d = int64_t(blk) * EPB + threadIdx.x / S; d < dm.n; d += int64_t(dm.nblk) * EPB) {
     double2 v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -306,15 +302,22 @@ __global__ __launch_bounds__(256) void k_lag_update(KrylovDims dm, double2* __re
   }
 }
 
+template <int NV, int S>
+__global__ __launch_bounds__(256) void k_lag_update(KrylovDims dm, double2* __restrict__ V, int64_t vsj,
+                                                    const double2* __restrict__ w,
+                                                    const double2* __restrict__ coef,
+                                                    const RhsState* __restrict__ st, int write_v) {
+  lag_update_item<NV, S>(dm, V, vsj, w, coef, st, write_v, int(blockIdx.y), int(blockIdx.x));
+}
+
 // Control of step j, one block per rhs, after pass A over slots 0..j (with w when has_w): for
 // j > 0 finalises Hessenberg column j-1 (adds s, h_{j,j-1} = rho_j, rotations, convergence);
 // then, while the rhs goes on and w was given, writes the pass-B coefficients, column j's
 // projections onto slots 0..j and the search-direction scale 1 / rho_j.
-__global__ __launch_bounds__(256) void k_lag_control(KrylovDims dm, const double2* __restrict__ part,
-                                                     RhsState* __restrict__ st, ArnoldiArgs aa,
-                                                     double2* __restrict__ coef,
-                                                     double* __restrict__ zsc, int has_w) {
-  const int r = blockIdx.x;
+__device__ inline void lag_control_item(const KrylovDims& dm, const double2* __restrict__ part,
+                                        RhsState* __restrict__ st, const ArnoldiArgs& aa,
+                                        double2* __restrict__ coef, double* __restrict__ zsc, int has_w,
+                                        int r) {
   if (!st[r].active) return;
   __shared__ double2 du[KMAXV], dw[KMAXV], scratch[8 * KMAXV];
   __shared__ double2 col[KMAXV + 1], snl[KMAXV];
@@ -373,6 +376,57 @@ __global__ __launch_bounds__(256) void k_lag_control(KrylovDims dm, const double
   cr[KGRAM - 1] = make_double2(inv, 0.0);
   Hr[j * m + j] = ce;
   zsc[int64_t(r) * m + j] = inv;
+}
+
+__global__ __launch_bounds__(256) void k_lag_control(KrylovDims dm, const double2* __restrict__ part,
+                                                     RhsState* __restrict__ st, ArnoldiArgs aa,
+                                                     double2* __restrict__ coef,
+                                                     double* __restrict__ zsc, int has_w) {
+  lag_control_item(dm, part, st, aa, coef, zsc, has_w, int(blockIdx.x));
+}
+
+// ---- several batches (lattices) in one launch --------------------------------------------
+// The same work items as the per-batch kernels (block blk of rhs r of batch q), walked by a
+// fixed grid of workgroups: item i goes to workgroup i mod gridDim.x, in increasing order.  An
+// item computes exactly what the per-batch kernel's block computes, so every right-hand side
+// gets bitwise its result in its own batch.  Items never wait on each other.
+__device__ inline int seg_of(const KrylovSeg* __restrict__ seg, int nseg, int item) {
+  int q = 0;
+  while (q + 1 < nseg && seg[q + 1].item0 <= item) ++q;
+  return q;
+}
+
+template <int NV, int S, bool HAS_W>
+__global__ __launch_bounds__(256) void k_gram_multi(const KrylovSeg* __restrict__ seg, int nseg, int total) {
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const KrylovSeg& q = seg[seg_of(seg, nseg, item)];
+    const int i = item - q.item0, r = i / q.dm.nblk, blk = i - r * q.dm.nblk;
+    gram_item<NV, S, HAS_W>(q.dm, q.V, q.vsj, HAS_W ? q.w : nullptr, q.part, q.st, r, blk);
+  }
+}
+
+template <int NV, int S>
+__global__ __launch_bounds__(256) void k_lag_update_multi(const KrylovSeg* __restrict__ seg, int nseg, int total,
+                                                          int write_v) {
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const KrylovSeg& q = seg[seg_of(seg, nseg, item)];
+    const int i = item - q.item0, r = i / q.dm.nblk, blk = i - r * q.dm.nblk;
+    lag_update_item<NV, S>(q.dm, q.V, q.vsj, q.w, q.coef, q.st, write_v, r, blk);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_lag_control_multi(const KrylovSeg* __restrict__ seg, int nseg,
+                                                           int total, int j, int has_w) {
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    // rhs items: item0 counts blocks, so the rhs index comes from the prefix of rhs counts
+    int qi = 0;
+    while (qi + 1 < nseg && seg[qi + 1].rhs0 <= item) ++qi;
+    const KrylovSeg& q = seg[qi];
+    ArnoldiArgs aa = q.aa;
+    aa.j = j;
+    __syncthreads();                                   // the previous item's LDS is free
+    lag_control_item(q.dm, q.part, q.st, aa, q.coef, q.zsc, has_w, item - q.rhs0);
+  }
 }
 
 // ||x||^2 per rhs whose state is active, then: mode 1 fresh states (x = b; the host marks the
@@ -567,6 +621,44 @@ void lag_control(hipStream_t s, const KrylovDims& d, const double2* part, RhsSta
 void lag_update(hipStream_t s, const KrylovDims& d, double2* V, int64_t vsj, int nv, const double2* w,
                 const double2* coef, const RhsState* st, int write_v) {
   kLag[nv - 1](s, d, V, vsj, w, coef, st, write_v);
+}
+
+// several batches: persistent grids of at most kMultiGrid workgroups
+constexpr int kMultiGrid = 2048;
+static dim3 multi_grid(int items) { return dim3(unsigned(std::max(1, std::min(items, kMultiGrid)))); }
+
+template <int NV, bool HAS_W>
+void launch_gram_multi(hipStream_t s, const KrylovSeg* seg, int nseg, int total) {
+  AMAMG_LAUNCH((k_gram_multi<NV, gram_lanes(NV), HAS_W>), multi_grid(total), dim3(256), 0, s, seg, nseg, total);
+}
+template <int NV>
+void launch_lag_update_multi(hipStream_t s, const KrylovSeg* seg, int nseg, int total, int write_v) {
+  AMAMG_LAUNCH((k_lag_update_multi<NV, update_lanes(NV)>), multi_grid(total), dim3(256), 0, s, seg, nseg, total,
+               write_v);
+}
+using GramMultiFn = void (*)(hipStream_t, const KrylovSeg*, int, int);
+using LagMultiFn = void (*)(hipStream_t, const KrylovSeg*, int, int, int);
+template <bool HAS_W, int... I>
+static constexpr std::array<GramMultiFn, sizeof...(I)> table_gram_multi(std::integer_sequence<int, I...>) {
+  return {&launch_gram_multi<I + 1, HAS_W>...};
+}
+template <int... I>
+static constexpr std::array<LagMultiFn, sizeof...(I)> table_lag_multi(std::integer_sequence<int, I...>) {
+  return {&launch_lag_update_multi<I + 1>...};
+}
+static const auto kGramMultiW = table_gram_multi<true>(std::make_integer_sequence<int, KMAXV - 1>{});
+static const auto kLagMulti = table_lag_multi(std::make_integer_sequence<int, KMAXV - 1>{});
+
+void gram_multi(hipStream_t s, const KrylovSeg* seg, int nseg, int total_blocks, int nv) {
+  kGramMultiW[nv - 1](s, seg, nseg, total_blocks);
+}
+
+void lag_control_multi(hipStream_t s, const KrylovSeg* seg, int nseg, int total_rhs, int j, int has_w) {
+  hipLaunchKernelGGL(k_lag_control_multi, multi_grid(total_rhs), dim3(256), 0, s, seg, nseg, total_rhs, j, has_w);
+}
+
+void lag_update_multi(hipStream_t s, const KrylovSeg* seg, int nseg, int total_blocks, int nv, int write_v) {
+  kLagMulti[nv - 1](s, seg, nseg, total_blocks, write_v);
 }
 
 void norm_control(hipStream_t s, const KrylovDims& d, const double2* x, double2* part, RhsState* st,

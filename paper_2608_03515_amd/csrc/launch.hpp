@@ -172,6 +172,38 @@ void lag_control(hipStream_t s, const KrylovDims& d, const double2* part, RhsSta
 // slot nv-1 <- final v (when write_v), slot nv <- next direction u, from coef
 void lag_update(hipStream_t s, const KrylovDims& d, double2* V, int64_t vsj, int nv, const double2* w,
                 const double2* coef, const RhsState* st, int write_v);
+// Hessenberg data and convergence settings of one batch (step j set per launch)
+struct ArnoldiArgs {
+  double2* H;       // [rhs][(m+1) m], H[i][j] at i*m + j
+  double* cs;       // [rhs][m]
+  double2* sn;      // [rhs][m]
+  double2* g;       // [rhs][m+1]
+  int j;
+  double tol, inner_tol;
+  int max_iters;
+  double2* hist;
+  int hist_cap;
+};
+// One batch (a lattice's right-hand sides) of the multi-batch Krylov launches, which run the
+// step's pass A, control and pass B of several batches in lock step, each batch's work items
+// exactly as its own launches would (bitwise the same results).  item0 / rhs0: the batch's
+// first block item (prefix of nrhs * nblk) and first rhs item (prefix of nrhs).
+struct KrylovSeg {
+  KrylovDims dm;
+  double2* V;
+  int64_t vsj;
+  const double2* w;
+  double2* part;
+  RhsState* st;
+  double2* coef;
+  double* zsc;
+  ArnoldiArgs aa;
+  int item0, rhs0;
+};
+// seg: device array of nseg segments; the same nv, j, has_w and write_v for all of them
+void gram_multi(hipStream_t s, const KrylovSeg* seg, int nseg, int total_blocks, int nv);
+void lag_control_multi(hipStream_t s, const KrylovSeg* seg, int nseg, int total_rhs, int j, int has_w);
+void lag_update_multi(hipStream_t s, const KrylovSeg* seg, int nseg, int total_blocks, int nv, int write_v);
 // ||x|| then mode 1: fresh states (x = b); 2: first cycle start (x = r_0); 3: cycle end and
 // restart (x = b - D x)
 void norm_control(hipStream_t s, const KrylovDims& d, const double2* x, double2* part, RhsState* st,

@@ -783,6 +783,40 @@ amamg_status amamg_hierarchy_destroy(amamg_hierarchy* h) {
   return AMAMG_OK;
 }
 
+amamg_status amamg_solve_multi_device(amamg_hierarchy* const* hs, int32_t nlat, const int32_t* nrhs,
+                                      const void* const* psi_dev, void* const* x_dev,
+                                      const amamg_solve_params* params, amamg_solve_info* info,
+                                      void* hip_stream) {
+  if (!hs || nlat < 1 || !hs[0]) return AMAMG_ERR_INVALID_ARG;
+  amamg_context* ctx = hs[0]->gauge->ctx;
+  if (!nrhs || !psi_dev || !x_dev) return fail(ctx, {AMAMG_ERR_INVALID_ARG, "null argument"});
+  std::vector<amamg_hierarchy*> h(nlat);
+  std::vector<int> nr(nlat);
+  std::vector<const double2*> b(nlat);
+  std::vector<double2*> x(nlat);
+  for (int l = 0; l < nlat; ++l) {
+    if (!hs[l] || !psi_dev[l] || !x_dev[l]) return fail(ctx, {AMAMG_ERR_INVALID_ARG, "null hierarchy or field pointer"});
+    if (!aligned16(psi_dev[l]) || !aligned16(x_dev[l]))
+      return fail(ctx, {AMAMG_ERR_INVALID_ARG, "field pointers must be 16-byte aligned"});
+    h[l] = hs[l];
+    nr[l] = nrhs[l];
+    b[l] = static_cast<const double2*>(psi_dev[l]);
+    x[l] = static_cast<double2*>(x_dev[l]);
+  }
+  amamg_solve_params p;
+  if (params) p = *params;
+  else amamg_default_solve_params(&p);
+  try {
+    HIPCHECK(hipSetDevice(ctx->device));
+    const hipStream_t root = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->stream;
+    const amamg_status st = run_solve_multi(h, nr, b, x, p, info, root);
+    if (st == AMAMG_NOT_CONVERGED) ctx->err = "not converged within max_iters";
+    return st;
+  } catch (const Fail& f) {
+    return fail(ctx, f);
+  }
+}
+
 amamg_status amamg_solve_device(amamg_hierarchy* h, int32_t nrhs, const void* psi_dev, void* x_dev,
                                 const amamg_solve_params* params, amamg_solve_info* info, void* hip_stream) {
   if (!h) return AMAMG_ERR_INVALID_ARG;

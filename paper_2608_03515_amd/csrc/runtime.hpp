@@ -321,6 +321,11 @@ struct Batch {
   // p.graphs the cycle is captured into a HIP graph on first use and replayed
   void enqueue_cycle();
   void enqueue_cycle_kernels();
+  // the cycle's pieces: step j's V-cycle and matvec, step j's Gram-Schmidt, the cycle's end
+  void enqueue_step_front(int j);
+  void enqueue_step_krylov(int j);
+  void enqueue_cycle_tail();
+  KrylovSeg krylov_seg() const;
   // enqueue a copy of the state to the pinned mirror and record the event
   void enqueue_state_read();
   bool ready() const;
@@ -337,6 +342,12 @@ struct Batch {
 // batches on separate streams
 amamg_status run_solve(amamg_hierarchy* h, int nrhs, const double2* b, double2* x,
                        const amamg_solve_params& p, amamg_solve_info* info);
+// several lattices (distinct hierarchies of one context) in lock step, the Gram-Schmidt of
+// each step in one launch for all of them; after `root`'s queued work, which then follows the
+// solve; blocks until the solve has finished
+amamg_status run_solve_multi(const std::vector<amamg_hierarchy*>& hs, const std::vector<int>& nrhs,
+                             const std::vector<const double2*>& b, const std::vector<double2*>& x,
+                             const amamg_solve_params& p, amamg_solve_info* info, hipStream_t root);
 
 }  // namespace rt
 }  // namespace amamg

@@ -603,45 +603,73 @@ void Batch::enqueue_cycle() {
 }
 
 void Batch::enqueue_cycle_kernels() {
+  for (int j = 0; j < p.restart; ++j) {
+    enqueue_step_front(j);
+    enqueue_step_krylov(j);
+  }
+  enqueue_cycle_tail();
+}
+
+// Arnoldi step j up to w = D z_j: the V-cycle z_j = M u_j and the matvec.
+void Batch::enqueue_step_front(int j) {
   SolveCtx c = make_ctx(*this);
   const KrylovDims kd = dims(*this);
   const int64_t n = kd.n, vsj = int64_t(ws->cap) * n;
-  const int m = p.restart;
   const Real T = c.T;
   const size_t zs = T == F64 ? sizeof(double2) : sizeof(float2);
   amamg_gauge* gg = h->gauge;
   amamg_context* ctx = gg->ctx;
-  RhsState* st = ws->st;
   const int nt = gg->nt, nx = gg->nx;
-  const double inner_tol = T == F64 ? 0.0 : 1e-5;
-  double2* p1 = ws->part;
   const void* Um0 = link0(gg, c.mat_links);
   const void* Um1 = link1(gg, c.mat_links);
   const double cl = c.mat_links == LINK_F64 ? 16 : 8;
   // Timer steps: served(step) counts the rhs whose cycle reached more than `step` columns.
   // The V-cycle, matvec and Gram pass of step j run for every rhs still active at step j
   // (> j - 1 columns); the update runs for those that go on after column j - 1 (> j).
-  for (int j = 0; j < m; ++j) {
-    double2* uj = ws->V + j * vsj;
-    void* zj = (char*)ws->Z + size_t(j) * vsj * zs;
-    c.step = j - 1;
-    vcycle(c, 0, F64, uj, zj);
-    int rec = timer_start(ctx, s, AMAMG_KT_FINE_MATVEC, j - 1, group, double(nt) * nx * (2 * zs + 32),
-                          double(nt) * nx * 2 * cl);
-    wilson_apply(s, c.mat_links, Um0, Um1, T, zj, F64, ws->w, nullptr, nt, nx, h->m0, ws->cap, n, st);
-    timer_stop(ctx, s, rec);
-    // Gram-Schmidt: family DOTS = the Gram passes (slots 0..j and w), family UPDATE = the
-    // updates (read slots 0..j and w; write slot j + 1 and, for j > 0, slot j)
-    rec = timer_start(ctx, s, AMAMG_KT_DOTS, j - 1, group, double(j + 2) * n * 16);
-    gram(s, kd, ws->V, vsj, j + 1, ws->w, p1, st);
-    timer_stop(ctx, s, rec);
-    lag_control(s, kd, p1, st, ws->H, ws->cs, ws->sn, ws->g, ws->coef, ws->zsc, j, 1, p.rel_tol, inner_tol,
-                p.max_iters, ws->hist, ws->hist_cap);
-    rec = timer_start(ctx, s, AMAMG_KT_UPDATE, j, group, double(j + (j > 0 ? 4 : 3)) * n * 16);
-    lag_update(s, kd, ws->V, vsj, j + 1, ws->w, ws->coef, st, j > 0);
-    timer_stop(ctx, s, rec);
-    check_launch();
-  }
+  double2* uj = ws->V + j * vsj;
+  void* zj = (char*)ws->Z + size_t(j) * vsj * zs;
+  c.step = j - 1;
+  vcycle(c, 0, F64, uj, zj);
+  const int rec = timer_start(ctx, s, AMAMG_KT_FINE_MATVEC, j - 1, group, double(nt) * nx * (2 * zs + 32),
+                              double(nt) * nx * 2 * cl);
+  wilson_apply(s, c.mat_links, Um0, Um1, T, zj, F64, ws->w, nullptr, nt, nx, h->m0, ws->cap, n, ws->st);
+  timer_stop(ctx, s, rec);
+}
+
+// Arnoldi step j's Gram-Schmidt: pass A (slots 0..j and w), control, pass B.
+void Batch::enqueue_step_krylov(int j) {
+  const KrylovDims kd = dims(*this);
+  const int64_t n = kd.n, vsj = int64_t(ws->cap) * n;
+  amamg_context* ctx = h->gauge->ctx;
+  const double inner_tol = p.precision == AMAMG_FP64 ? 0.0 : 1e-5;
+  RhsState* st = ws->st;
+  double2* p1 = ws->part;
+  // family DOTS = the Gram passes (slots 0..j and w), family UPDATE = the updates (read slots
+  // 0..j and w; write slot j + 1 and, for j > 0, slot j)
+  int rec = timer_start(ctx, s, AMAMG_KT_DOTS, j - 1, group, double(j + 2) * n * 16);
+  gram(s, kd, ws->V, vsj, j + 1, ws->w, p1, st);
+  timer_stop(ctx, s, rec);
+  lag_control(s, kd, p1, st, ws->H, ws->cs, ws->sn, ws->g, ws->coef, ws->zsc, j, 1, p.rel_tol, inner_tol,
+              p.max_iters, ws->hist, ws->hist_cap);
+  rec = timer_start(ctx, s, AMAMG_KT_UPDATE, j, group, double(j + (j > 0 ? 4 : 3)) * n * 16);
+  lag_update(s, kd, ws->V, vsj, j + 1, ws->w, ws->coef, st, j > 0);
+  timer_stop(ctx, s, rec);
+  check_launch();
+}
+
+// End of a cycle: the last column, the solution update, the true residual and the next
+// cycle's start.
+void Batch::enqueue_cycle_tail() {
+  const KrylovDims kd = dims(*this);
+  const int64_t n = kd.n, vsj = int64_t(ws->cap) * n;
+  const int m = p.restart;
+  const Real T = p.precision == AMAMG_FP64 ? F64 : F32;
+  amamg_gauge* gg = h->gauge;
+  amamg_context* ctx = gg->ctx;
+  const int nt = gg->nt, nx = gg->nx;
+  const double inner_tol = T == F64 ? 0.0 : 1e-5;
+  RhsState* st = ws->st;
+  double2* p1 = ws->part;
   // the rhs that ran all m steps: last column from the reorthogonalisation of slot m
   int rec = timer_start(ctx, s, AMAMG_KT_DOTS, m - 1, group, double(m + 1) * n * 16);
   gram(s, kd, ws->V, vsj, m + 1, nullptr, p1, st);
@@ -654,6 +682,22 @@ void Batch::enqueue_cycle_kernels() {
   scale_next(s, kd, ws->V, ws->V, st);
   check_launch();
   cycle_enqueued = true;
+}
+
+// This batch as a segment of the multi-batch Krylov launches.
+KrylovSeg Batch::krylov_seg() const {
+  KrylovSeg q{};
+  q.dm = dims(*this);
+  q.V = ws->V;
+  q.vsj = int64_t(ws->cap) * q.dm.n;
+  q.w = ws->w;
+  q.part = ws->part;
+  q.st = ws->st;
+  q.coef = ws->coef;
+  q.zsc = ws->zsc;
+  q.aa = ArnoldiArgs{ws->H, ws->cs, ws->sn, ws->g, 0, p.rel_tol, p.precision == AMAMG_FP64 ? 0.0 : 1e-5,
+                     p.max_iters, ws->hist, ws->hist_cap};
+  return q;
 }
 
 std::vector<double2> Batch::history(int slot) const {
@@ -774,6 +818,200 @@ amamg_status run_solve(amamg_hierarchy* h, int nrhs, const double2* b, double2* 
       }
     }
   }
+  REQUIRE(!nonfinite, AMAMG_ERR_NONFINITE, "non-finite value during the solve");
+  return all_conv ? AMAMG_OK : AMAMG_NOT_CONVERGED;
+}
+
+// ------------------------------------------------------------------------ several lattices
+
+// Several hierarchies (lattices of any sizes) solved together: one batch per lattice on one of
+// up to four streams, advanced in lock step.  Step j runs every lattice's V-cycle and matvec on
+// its own stream, then one launch of each Gram-Schmidt kernel for all lattices (KrylovSeg
+// segments, persistent workgroups over the lattices' work items), then the next step; a cycle
+// ends with each lattice's own tail.  With p.graphs a whole round (all lattices' cycles, with
+// the stream fork and join) is captured into one HIP graph and launched once per round; the
+// graph is captured again when the set of lattices still iterating changes.  Each right-hand
+// side gets bitwise its result in a plain solve of its lattice with the same batch size.
+amamg_status run_solve_multi(const std::vector<amamg_hierarchy*>& hs, const std::vector<int>& nrhs,
+                             const std::vector<const double2*>& b, const std::vector<double2*>& x,
+                             const amamg_solve_params& p, amamg_solve_info* info, hipStream_t root) {
+  check_solve_params(p);
+  const int L = int(hs.size());
+  REQUIRE(L >= 1 && int(nrhs.size()) == L, AMAMG_ERR_INVALID_ARG, "need at least one lattice");
+  amamg_context* ctx = hs[0]->gauge->ctx;
+  for (int l = 0; l < L; ++l) {
+    REQUIRE(nrhs[l] >= 1, AMAMG_ERR_INVALID_ARG, "nrhs must be >= 1 for every lattice");
+    REQUIRE(hs[l]->gauge->ctx == ctx, AMAMG_ERR_INVALID_ARG, "all hierarchies must share one context");
+    for (int k = 0; k < l; ++k) REQUIRE(hs[k] != hs[l], AMAMG_ERR_INVALID_ARG, "a hierarchy is listed twice");
+  }
+  const Real T = p.precision == AMAMG_FP64 ? F64 : F32;
+  const int hist_cap = 2 * p.max_iters + 2;
+  const int NS = std::min(L, 4);
+  std::vector<hipStream_t> ss(NS, nullptr);
+  std::vector<hipEvent_t> evs(L + 1, nullptr);
+  KrylovSeg* dseg = nullptr;
+  hipGraphExec_t graph = nullptr;
+  std::vector<Batch> bt(L);
+  auto cleanup = [&] {
+    for (hipStream_t sx : ss)
+      if (sx) (void)hipStreamSynchronize(sx);
+    if (root) (void)hipStreamSynchronize(root);
+    if (graph) (void)hipGraphExecDestroy(graph);
+    for (hipEvent_t e : evs)
+      if (e) (void)hipEventDestroy(e);
+    for (hipStream_t sx : ss)
+      if (sx) (void)hipStreamDestroy(sx);
+    if (dseg) (void)hipFree(dseg);
+  };
+  try {
+    for (int q = 0; q < NS; ++q) HIPCHECK(hipStreamCreateWithFlags(&ss[q], hipStreamNonBlocking));
+    for (hipEvent_t& e : evs) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->timer.pending.clear();
+    for (int l = 0; l < L; ++l) {
+      amamg_hierarchy* h = hs[l];
+      if (h->ws.empty()) h->ws.push_back(new Workspace());
+      ensure_workspace(*h->ws[0], h, nrhs[l], p.restart, T, hist_cap);
+    }
+    // every lattice's stream starts after the caller's queued work
+    HIPCHECK(hipEventRecord(evs[L], root));
+    for (int q = 0; q < NS; ++q) HIPCHECK(hipStreamWaitEvent(ss[q], evs[L], 0));
+    for (int l = 0; l < L; ++l) bt[l].init(hs[l], hs[l]->ws[0], ss[l % NS], p, b[l], x[l], l);
+    // admission of every right-hand side, as a plain solve's
+    for (int l = 0; l < L; ++l) {
+      std::vector<int> all(nrhs[l]);
+      for (int r = 0; r < nrhs[l]; ++r) all[r] = r;
+      bt[l].admit_begin(all);
+    }
+    for (int l = 0; l < L; ++l) HIPCHECK(hipEventSynchronize(hs[l]->ws[0]->ev));
+    for (int l = 0; l < L; ++l) {
+      const std::vector<int> bad = bt[l].admit_nonfinite();
+      REQUIRE(bad.empty(), AMAMG_ERR_NONFINITE, "non-finite value in a right-hand side of lattice " + std::to_string(l));
+    }
+    for (int l = 0; l < L; ++l) {
+      bt[l].admit_finish({}, p.use_initial_guess != 0);
+      bt[l].enqueue_state_read();
+    }
+    for (int l = 0; l < L; ++l) HIPCHECK(hipEventSynchronize(hs[l]->ws[0]->ev));
+    // segments of the multi-lattice Krylov launches
+    std::vector<KrylovSeg> seg(L);
+    int blocks = 0, rhs = 0;
+    for (int l = 0; l < L; ++l) {
+      seg[l] = bt[l].krylov_seg();
+      seg[l].item0 = blocks;
+      seg[l].rhs0 = rhs;
+      blocks += seg[l].dm.nrhs * seg[l].dm.nblk;
+      rhs += seg[l].dm.nrhs;
+    }
+    HIPCHECK(hipMalloc(&dseg, sizeof(KrylovSeg) * L));
+    HIPCHECK(hipMemcpy(dseg, seg.data(), sizeof(KrylovSeg) * L, hipMemcpyHostToDevice));
+    const hipStream_t s0 = ss[0];
+    // (the kernel timer records events and pre-smoothing a memset, which stay out of graphs)
+    bool use_graph = p.graphs != 0 && ctx->timer.mask == 0;
+    for (int l = 0; l < L; ++l) use_graph = use_graph && hs[l]->prm.pre_sweeps == 0;
+    std::vector<char> live(L, 0), captured;
+    for (;;) {
+      bool any = false;
+      for (int l = 0; l < L; ++l) {
+        live[l] = bt[l].cycle_boundary() ? 1 : 0;
+        any = any || live[l];
+      }
+      if (!any) break;
+      // one round: the lattices' steps in lock step, then their tails
+      auto enqueue_round = [&] {
+        HIPCHECK(hipEventRecord(evs[L], s0));
+        for (int q = 1; q < NS; ++q) HIPCHECK(hipStreamWaitEvent(ss[q], evs[L], 0));
+        for (int j = 0; j < p.restart; ++j) {
+          for (int l = 0; l < L; ++l)
+            if (live[l]) bt[l].enqueue_step_front(j);
+          for (int q = 1; q < NS; ++q) {
+            HIPCHECK(hipEventRecord(evs[q], ss[q]));
+            HIPCHECK(hipStreamWaitEvent(s0, evs[q], 0));
+          }
+          gram_multi(s0, dseg, L, blocks, j + 1);
+          lag_control_multi(s0, dseg, L, rhs, j, 1);
+          lag_update_multi(s0, dseg, L, blocks, j + 1, j > 0 ? 1 : 0);
+          HIPCHECK(hipEventRecord(evs[0], s0));
+          for (int q = 1; q < NS; ++q) HIPCHECK(hipStreamWaitEvent(ss[q], evs[0], 0));
+        }
+        for (int l = 0; l < L; ++l)
+          if (live[l]) bt[l].enqueue_cycle_tail();
+        for (int q = 1; q < NS; ++q) {
+          HIPCHECK(hipEventRecord(evs[q], ss[q]));
+          HIPCHECK(hipStreamWaitEvent(s0, evs[q], 0));
+        }
+        check_launch();
+      };
+      if (use_graph) {
+        if (!graph || live != captured) {
+          if (graph) (void)hipGraphExecDestroy(graph);
+          graph = nullptr;
+          HIPCHECK(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+          hipGraph_t g = nullptr;
+          try {
+            enqueue_round();
+          } catch (...) {
+            (void)hipStreamEndCapture(s0, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+          }
+          HIPCHECK(hipStreamEndCapture(s0, &g));
+          const hipError_t e = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(g);
+          if (e != hipSuccess) {
+            graph = nullptr;
+            throw Fail{AMAMG_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+          }
+          captured = live;
+        }
+        HIPCHECK(hipGraphLaunch(graph, s0));
+      } else {
+        enqueue_round();
+      }
+      // state reads on the lattices' streams after the round
+      HIPCHECK(hipEventRecord(evs[L], s0));
+      for (int q = 1; q < NS; ++q) HIPCHECK(hipStreamWaitEvent(ss[q], evs[L], 0));
+      for (int l = 0; l < L; ++l) {
+        bt[l].cycle_enqueued = live[l] != 0;
+        bt[l].enqueue_state_read();
+      }
+      for (int l = 0; l < L; ++l) HIPCHECK(hipEventSynchronize(hs[l]->ws[0]->ev));
+    }
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+  // the caller's stream follows the solve
+  for (int q = 0; q < NS; ++q) {
+    HIPCHECK(hipEventRecord(evs[q], ss[q]));
+    HIPCHECK(hipStreamWaitEvent(root, evs[q], 0));
+  }
+  bool all_conv = true, nonfinite = false;
+  int off = 0;
+  for (int l = 0; l < L; ++l) {
+    amamg_hierarchy* h = hs[l];
+    Workspace& ws = *h->ws[0];
+    HIPCHECK(hipMemcpyAsync(ws.hhist, ws.hist, sizeof(double2) * size_t(nrhs[l]) * ws.hist_cap, hipMemcpyDeviceToHost,
+                            bt[l].s));
+    HIPCHECK(hipStreamSynchronize(bt[l].s));
+    h->history.assign(nrhs[l], {});
+    for (int r = 0; r < nrhs[l]; ++r) {
+      const RhsState& st = ws.hst[r];
+      const double2* hh = ws.hhist + size_t(r) * ws.hist_cap;
+      h->history[r].assign(hh, hh + std::min(st.hist_len, ws.hist_cap));
+      all_conv = all_conv && st.converged;
+      nonfinite = nonfinite || st.nonfinite;
+      if (info) {
+        amamg_solve_info& o = info[off + r];
+        o.iterations = st.iters;
+        o.restarts = st.restarts;
+        o.converged = st.converged;
+        o.reserved = 0;
+        o.true_rel_residual = st.true_res;
+      }
+    }
+    off += nrhs[l];
+  }
+  cleanup();
   REQUIRE(!nonfinite, AMAMG_ERR_NONFINITE, "non-finite value during the solve");
   return all_conv ? AMAMG_OK : AMAMG_NOT_CONVERGED;
 }

@@ -110,3 +110,42 @@ def test_augmented_parameters_are_checked(lib, ctx):
             lib.Hierarchy(g, lib.default_setup_params(**kw))
         assert e.value.status == code, kw
     g.close()
+
+
+def test_augmented_256_setup_sampled_parity(lib, ctx):
+    """The 256^2 workload's field and mass (a = 8, o = 2, 3 levels, 64 test-vector sweeps) with
+    k = 8: sampled augmented interpolation rows, sampled level-1 blocks (16 dofs per node) and
+    the dense 1024-unknown coarsest operator against the oracle's setup."""
+    w = synth.WORKLOADS["C3"]
+    m0 = synth.critical_masses()["C3"] + w.gaps[0]
+    U = w.links()
+    say("C3 augmented setup parity")
+    olev = amg.setup(U, m0, amg.SetupParams(**w.oracle_kw(aug_vectors=8)))
+    g = lib.Gauge(ctx, synth.links_to_abi(U), m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(**w.setup_kw(aug_vectors=8)))
+    bc = 16
+    rows = h.prolongator_rows(0, 2, aug=8)
+    P = olev[0].P.tocsr()
+    rng = np.random.default_rng(1)
+    for p in rng.choice(256 * 256, 200, replace=False):
+        if olev[0].cls["kind"][p] == KIND_V:
+            continue
+        I, J = divmod(int(olev[0].cls["owner"][p]), 32)
+        for c in range(4):
+            nd = ((I + (c >> 1)) % 32) * 32 + (J + (c & 1)) % 32
+            ref = P[2 * p:2 * p + 2, nd * bc:(nd + 1) * bc].toarray()
+            assert np.abs(rows[p, :, c * bc:(c + 1) * bc] - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+    A1 = h.coarse_operator(1, coarsest=False)
+    ref1 = olev[1].A.tocsr()
+    for n in rng.choice(1024, 40, replace=False):
+        t, x = divmod(int(n), 32)
+        scale = max(1.0, np.abs(ref1[n * bc:(n + 1) * bc].toarray()).max())
+        for off in (0, 1, 7, 12, 13, 17, 24):
+            dt, dx = off // 5 - 2, off % 5 - 2
+            m = ((t + dt) % 32) * 32 + (x + dx) % 32
+            blk = ref1[n * bc:(n + 1) * bc, m * bc:(m + 1) * bc].toarray()
+            assert np.abs(A1[n, off] - blk).max() <= 1e-10 * scale
+    assert rel(h.test_vectors(1, 8), olev[1].test_vectors) < 1e-10
+    assert rel(h.coarse_operator(2, coarsest=True), olev[2].A.toarray()) < 1e-10
+    h.close()
+    g.close()
