@@ -406,8 +406,11 @@ void run_setup(amamg_hierarchy* h, hipStream_t stream, Pool* scratch) {
           for (int c = 0; c < 2; ++c)
             wilson_gs(s, LINK_F64, U0, U1, F64, L.tv, nullptr, g.Lt, g.Lx, h->m0, c, nv, ndof, nullptr);
         } else {
-          for (int c = 0; c < 16; ++c)
-            stencil_gs(s, F64, L.A, L.Dinv, L.tv, nullptr, g.Lt, g.Lx, g.b, coarse_colour(c), nv, ndof, nullptr);
+          // the 16 colours as 4 colour blocks of two paired launches each (bitwise the
+          // colour-by-colour sweep)
+          for (int qb = 0; qb < 4; ++qb)
+            stencil_gs_block(s, F64, L.A, L.Dinv, L.tv, nullptr, g.Lt, g.Lx, g.b, qb, nv, ndof, nullptr, 0,
+                             p.block_smoother);
         }
       }
       check_launch();

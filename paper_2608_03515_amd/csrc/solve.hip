@@ -875,7 +875,19 @@ amamg_status run_solve_multi(const std::vector<amamg_hierarchy*>& hs, const std:
     // every lattice's stream starts after the caller's queued work
     HIPCHECK(hipEventRecord(evs[L], root));
     for (int q = 0; q < NS; ++q) HIPCHECK(hipStreamWaitEvent(ss[q], evs[L], 0));
-    for (int l = 0; l < L; ++l) bt[l].init(hs[l], hs[l]->ws[0], ss[l % NS], p, b[l], x[l], l);
+    // streams by longest-first greedy balance of each lattice's unknowns x right-hand sides, so
+    // that the streams' shares of a lock step are about equal
+    std::vector<int> order(L), sid(L, 0);
+    for (int l = 0; l < L; ++l) order[l] = l;
+    auto work = [&](int l) { return double(hs[l]->lv[0].g.ndof()) * nrhs[l]; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return work(a) > work(c); });
+    std::vector<double> load(NS, 0.0);
+    for (int l : order) {
+      const int q = int(std::min_element(load.begin(), load.end()) - load.begin());
+      sid[l] = q;
+      load[q] += work(l);
+    }
+    for (int l = 0; l < L; ++l) bt[l].init(hs[l], hs[l]->ws[0], ss[sid[l]], p, b[l], x[l], l);
     // admission of every right-hand side, as a plain solve's
     for (int l = 0; l < L; ++l) {
       std::vector<int> all(nrhs[l]);
@@ -942,7 +954,16 @@ amamg_status run_solve_multi(const std::vector<amamg_hierarchy*>& hs, const std:
         check_launch();
       };
       if (use_graph) {
-        if (!graph || live != captured) {
+        // a captured round stays in use while the lattices still iterating hold at least half
+        // of its work: the finished ones' kernels find no active right-hand side and return
+        double live_work = 0, cap_work = 0;
+        for (int l = 0; l < L; ++l) {
+          if (live[l]) live_work += work(l);
+          if (!captured.empty() && captured[l]) cap_work += work(l);
+        }
+        bool covers = !captured.empty();
+        for (int l = 0; l < L && covers; ++l) covers = !live[l] || captured[l];
+        if (!graph || !covers || live_work < 0.5 * cap_work) {
           if (graph) (void)hipGraphExecDestroy(graph);
           graph = nullptr;
           HIPCHECK(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
@@ -964,6 +985,7 @@ amamg_status run_solve_multi(const std::vector<amamg_hierarchy*>& hs, const std:
           captured = live;
         }
         HIPCHECK(hipGraphLaunch(graph, s0));
+        for (int l = 0; l < L; ++l) live[l] = captured[l];   // their state reads follow the graph
       } else {
         enqueue_round();
       }
