@@ -129,7 +129,10 @@ void inject(hipStream_t s, const Geom& g, const int* node, const int8_t* kind, c
 // local systems of every wirebasket: Aug [W][nfd][nfd + ncol] = [A_FF | -A_FV]
 void gather_local(hipStream_t s, const Geom& g, const double2* A, int noff, const int* offs_dev,
                   const int* postab, int nf, double2* Aug);
-// batched dense solves on augmented [A | B] (n x (n + nrhs) row-major per system): B <- A^-1 B
+// batched dense solves on augmented [A | B] (n x (n + nrhs) row-major per system): B <- A^-1 B;
+// info: nsys * kDenseSolveInts ints, info[sys] = 0 or the first zero pivot column + 1 (the
+// rest is the solver's scratch)
+constexpr int kDenseSolveInts = 17;
 void dense_solve(hipStream_t s, double2* Aug, int n, int nrhs, int nsys, int* info);
 void aug_extract(hipStream_t s, const double2* Aug, int n, int nrhs, double2* out, int nsys);
 // Aug = [A | I] from nsys n x n blocks at stride astride with row stride arow

@@ -24,6 +24,10 @@ int period_of(int L) {
   return L;
 }
 
+// Galerkin probing: probe columns per batch (the bc columns of nb node colours, at most 64
+// columns when bc <= 64)
+int probe_batch_colours(int bc, int ncolour) { return std::max(1, std::min(ncolour, 64 / bc)); }
+
 
 }  // namespace
 
@@ -232,13 +236,14 @@ size_t setup_bytes(int nt, int nx, const amamg_setup_params& p) {
     int nf = 0;
     const std::vector<int> tabs = footprint_tables(a, o, g.b, &nf);
     const size_t nW = size_t(g.nI) * g.nJ, nfd = size_t(nf) * g.b, ncol = g.ncol(), bc = g.bc;
-    b += nnode * 9 + size_t(nv) * ndof * c16 + tabs.size() * 4 + nW * nf * g.b * 4 + nW * 8;
+    b += nnode * 9 + size_t(nv) * ndof * c16 + tabs.size() * 4 + nW * nf * g.b * 4 + nW * 4 * (1 + kDenseSolveInts);
     b += nW * nfd * (nfd + g.nvcol()) * c16 + ndof * ncol * (c16 + c8);
     if (k == 0 && p.aug_vectors > 0) b += size_t(nv) * ndof * c16 + nW * 4;
     b += size_t(nv) * ndc * c16 * 2;
-    b += bc * (2 * ndc + 2 * ndof) * c16 + bc * nW * restrict_chunks(g, nf, F64) * ncol * c16;
+    const size_t npc = size_t(probe_batch_colours(int(bc), period_of(gc.Lt) * period_of(gc.Lx))) * bc;
+    b += npc * (2 * ndc + 2 * ndof) * c16 + npc * nW * restrict_chunks(g, nf, F64) * ncol * c16;
     if (k + 1 == K - 1) b += ndc * ndc * c16 * (p.coarsest_tol > 0 ? 5 : 4);
-    else b += nnc * 25 * bc * bc * (c16 + c8) + nnc * bc * bc * (3 * c16 + c8) + nnc * 4;
+    else b += nnc * 25 * bc * bc * (c16 + c8) + nnc * bc * bc * (3 * c16 + c8) + nnc * 4 * kDenseSolveInts;
   }
   return b;
 }
@@ -278,24 +283,29 @@ static void probe_galerkin(amamg_hierarchy* h, int k, bool mass, double2* out, h
   const double2* U1 = gg->U + int64_t(gg->nt) * gg->nx;
   if (dense) HIPCHECK(hipMemsetAsync(out, 0, sizeof(double2) * ndof_c * ndof_c, s));
   else HIPCHECK(hipMemsetAsync(out, 0, sizeof(double2) * gc.nnode() * 25 * bc * bc, s));
-  double2* pe = tmp.get<double2>("pe", k, size_t(bc) * ndof_c);
-  double2* py = tmp.get<double2>("py", k, size_t(bc) * ndof);
-  double2* pz = tmp.get<double2>("pz", k, size_t(bc) * ndof);
-  double2* pu = tmp.get<double2>("pu", k, size_t(bc) * ndof_c);
-  double2* ppart = tmp.get<double2>("ppart", k, size_t(bc) * g.nI * g.nJ * restrict_chunks(g, L.nf, F64) * g.ncol());
-  for (int ct = 0; ct < pt; ++ct)
-    for (int cx = 0; cx < px; ++cx) {
-      probe_make(s, gc, pt, px, ct, cx, pe);
-      prolong(s, F64, L.P, L.rows, L.nrows, L.nf, pe, py, g, 0, bc, ndof, ndof_c, nullptr);
-      const double2* r = pz;
-      if (k == 0 && mass) r = py;
-      else if (k == 0)
-        wilson_apply(s, LINK_F64, U0, U1, F64, py, F64, pz, nullptr, g.Lt, g.Lx, h->m0, bc, ndof, nullptr);
-      else
-        stencil_apply(s, F64, mass ? L.G : L.A, py, pz, nullptr, g.Lt, g.Lx, g.b, bc, ndof, nullptr);
-      restrict_(s, F64, L.P, L.rows, L.nrows, L.nf, F64, r, pu, ppart, g, bc, ndof, ndof_c, nullptr);
-      probe_extract(s, gc, pt, px, ct, cx, pu, out, dense ? 1 : 0);
-    }
+  // the probe vectors of nb colours at once (at most 64 columns per batch): each column's
+  // results are independent of the others in its batch
+  const int ncolour = pt * px, nb = probe_batch_colours(bc, ncolour), nv = nb * bc;
+  double2* pe = tmp.get<double2>("pe", k, size_t(nv) * ndof_c);
+  double2* py = tmp.get<double2>("py", k, size_t(nv) * ndof);
+  double2* pz = tmp.get<double2>("pz", k, size_t(nv) * ndof);
+  double2* pu = tmp.get<double2>("pu", k, size_t(nv) * ndof_c);
+  double2* ppart = tmp.get<double2>("ppart", k, size_t(nv) * g.nI * g.nJ * restrict_chunks(g, L.nf, F64) * g.ncol());
+  for (int c0 = 0; c0 < ncolour; c0 += nb) {
+    const int nc = std::min(nb, ncolour - c0), nvb = nc * bc;
+    for (int q = 0; q < nc; ++q)
+      probe_make(s, gc, pt, px, (c0 + q) / px, (c0 + q) % px, pe + size_t(q) * bc * ndof_c);
+    prolong(s, F64, L.P, L.rows, L.nrows, L.nf, pe, py, g, 0, nvb, ndof, ndof_c, nullptr);
+    const double2* r = pz;
+    if (k == 0 && mass) r = py;
+    else if (k == 0)
+      wilson_apply(s, LINK_F64, U0, U1, F64, py, F64, pz, nullptr, g.Lt, g.Lx, h->m0, nvb, ndof, nullptr);
+    else
+      stencil_apply(s, F64, mass ? L.G : L.A, py, pz, nullptr, g.Lt, g.Lx, g.b, nvb, ndof, nullptr);
+    restrict_(s, F64, L.P, L.rows, L.nrows, L.nf, F64, r, pu, ppart, g, nvb, ndof, ndof_c, nullptr);
+    for (int q = 0; q < nc; ++q)
+      probe_extract(s, gc, pt, px, (c0 + q) / px, (c0 + q) % px, pu + size_t(q) * bc * ndof_c, out, dense ? 1 : 0);
+  }
   check_launch();
 }
 
@@ -309,7 +319,7 @@ static void finish_level(amamg_hierarchy* h, int k, hipStream_t s, Pool& tmp, Po
     const int bc = gc.b, nnc = gc.nnode();
     C.Dinv = keep.get<double2>("C_Dinv", k - 1, size_t(nnc) * bc * bc);
     double2* Dg = tmp.get<double2>("Dg", k - 1, size_t(nnc) * bc * 2 * bc);
-    int* dinfo = tmp.get<int>("dinfo", k - 1, nnc);
+    int* dinfo = tmp.get<int>("dinfo", k - 1, size_t(nnc) * kDenseSolveInts);
     aug_identity(s, C.A + 12 * bc * bc, int64_t(25) * bc * bc, bc, bc, Dg, nnc);
     dense_solve(s, Dg, bc, bc, nnc, dinfo);
     aug_extract(s, Dg, bc, bc, C.Dinv, nnc);
@@ -322,7 +332,7 @@ static void finish_level(amamg_hierarchy* h, int k, hipStream_t s, Pool& tmp, Po
   } else {
     const int n = int(gc.ndof());
     double2* LUc = tmp.get<double2>("LUc", k - 1, size_t(n) * 2 * n);
-    int* cinfo = tmp.get<int>("cinfo", k - 1, 1);
+    int* cinfo = tmp.get<int>("cinfo", k - 1, kDenseSolveInts);
     aug_identity(s, C.Adense, 0, n, n, LUc, 1);
     dense_solve(s, LUc, n, n, 1, cinfo);
     C.Ainv = h->mem.get<double2>("C_Ainv", k - 1, size_t(n) * n);
@@ -428,7 +438,7 @@ void run_setup(amamg_hierarchy* h, hipStream_t stream, Pool* scratch) {
     owned_rows(s, g, d_tabs + g.fp(), nf, L.owner, L.rows, L.nrows);
     const int nW = g.nI * g.nJ, nfd = nf * g.b, ncol = g.ncol(), nvc = g.nvcol();
     double2* Aug = pool("Aug").get<double2>("Aug", k, size_t(nW) * nfd * (nfd + nvc));
-    int* info = pool("info").get<int>("info", k, nW);
+    int* info = pool("info").get<int>("info", k, size_t(nW) * kDenseSolveInts);
     if (k == 0) gather_local(s, g, A0, 5, d_offs5, d_tabs, nf, Aug);
     else gather_local(s, g, L.A, 25, d_offs25, d_tabs, nf, Aug);
     dense_solve(s, Aug, nfd, nvc, nW, info);

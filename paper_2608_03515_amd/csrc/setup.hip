@@ -11,6 +11,9 @@
 // passes postab[pos] = F index (>= 0) or -(1 + vcol) with vcol = c*bc + (pt*o + px)*b the
 // first interpolation column of a vertex (corner c = 2*ct + cx), and fpos[fi] = pos of the
 // fi-th F position.
+#include <type_traits>
+#include <utility>
+
 #include "launch.hpp"
 
 namespace amamg {
@@ -53,14 +56,16 @@ __global__ __launch_bounds__(256) void k_gather_local(Geom g, const double2* __r
   }
 }
 
-// Batched dense solve X = A^{-1} B, one workgroup per system, on the augmented row-major
-// matrix [A | B] (n rows, ld = n + nrhs columns).  Blocked right-looking LU with partial
-// pivoting (largest |a_ik|, lowest row index on ties; the swaps are applied to whole rows, so
-// B is permuted and eliminated along the way), panel width LU_NB; the trailing rank-LU_NB
+// Batched dense solve X = A^{-1} B on the augmented row-major matrix [A | B] (n rows, ld = n +
+// nrhs columns).  Blocked right-looking LU with partial pivoting (largest |a_ik|, lowest row
+// index on ties; the interchanges are applied to the rows of the current and trailing columns,
+// so B is permuted and eliminated along the way), panel width LU_NB; the trailing rank-LU_NB
 // updates run on 64 x 64 tiles staged in LDS.  Then a blocked back substitution U X = B' with
-// the same tiled update.  On exit the B columns hold X.  info[sys] = 0, or k + 1 when the pivot
-// column k is zero or not finite.
+// the same tiled update.  On exit the B columns hold X (and the other columns U and the L
+// factors, the latter without the later interchanges).  info[sys] = 0, or k + 1 when the
+// pivot column k is zero or not finite.
 #define LU_NB 16
+static_assert(kDenseSolveInts == 1 + LU_NB, "dense_solve: info and the panel interchanges");
 
 // M[r][c] -= sum_{q < kb} M[r][lc + q] * M[ur + q][c]  for r in [r0, r1), c in [c0, c1)
 // One 64 x 64 tile of M[r][c] -= sum_{q < kb} M[r][lc + q] * M[ur + q][c], rows [tr, min(tr + 64,
@@ -179,33 +184,277 @@ __device__ bool lu_panel(double2* __restrict__ M, int n, int ld, int k0, int sys
   return true;
 }
 
-// Diagonal block k0 of the back substitution U X = B' on the right-hand-side columns [n, ld):
-// X rows k0 .. k0 + kb for the columns c0 + tid, c0 + tid + stride, ...
-__device__ void back_diag(double2* __restrict__ M, int n, int ld, int k0, int c0, int cstride) {
-  const int kb = min(LU_NB, n - k0);
-  for (int c = n + c0 + threadIdx.x; c < ld; c += cstride) {
-    for (int r = kb - 1; r >= 0; --r) {
-      double2 acc = M[int64_t(k0 + r) * ld + c];
-      for (int q = r + 1; q < kb; ++q) acc = csub(acc, cmul(M[int64_t(k0 + r) * ld + k0 + q], M[int64_t(k0 + q) * ld + c]));
-      const double2 d = M[int64_t(k0 + r) * ld + k0 + r];
-      const double den = cabs2(d);
-      M[int64_t(k0 + r) * ld + c] = cmul(acc, make_double2(d.x / den, -d.y / den));
+// Shared memory of the register panel: per-wave pivot candidates (value, row, row values),
+// the old row k, the row interchanges and the panel's unit lower triangle, double-buffered
+// by step parity so that one barrier per pivot step suffices.
+struct PanelSmem {
+  double sv[2][4];
+  int si[2][4];
+  double2 crow[2][4][LU_NB];
+  double2 krow[2][LU_NB];
+  double2 L11[LU_NB][LU_NB + 1];
+  int perm[LU_NB];
+};
+
+// c ? a : b, component-wise (a select of values, never of their addresses)
+__device__ __forceinline__ double2 sel2(bool c, double2 a, double2 b) {
+  return make_double2(c ? a.x : b.x, c ? a.y : b.y);
+}
+
+// f(integral_constant<int, K>) for K = 0, 1, ... in order, while it returns true (compile-time
+// indices, so that register arrays indexed by K stay in registers)
+template <typename F, int... K>
+__device__ __forceinline__ bool static_while(F&& f, std::integer_sequence<int, K...>) {
+  return (f(std::integral_constant<int, K>{}) && ...);
+}
+
+// Panel k0 as lu_panel factors it (the same pivots and the same operations in the same order),
+// with the panel's rows k0 .. n - 1 in registers: thread t holds rows k0 + t + 256 s, s < S
+// (n - k0 <= 256 S, 256 threads).  A pivot step is one wave reduction and one barrier.  The
+// factored panel columns are written back; the interchanges (sm.perm) and the panel's unit
+// lower triangle (sm.L11) are left for lu_columns, which applies them to the columns right of
+// the panel.  Columns left of the panel (earlier L factors, which the solve never reads again)
+// are not interchanged.
+template <int S>
+__device__ __forceinline__ bool lu_panel_reg(double2* __restrict__ M, int n, int ld, int k0, int sys,
+                                             int* __restrict__ info, PanelSmem& sm) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int kb = min(LU_NB, n - k0), m = n - k0;
+  using Seq = std::make_integer_sequence<int, LU_NB>;
+  double2 P[S][LU_NB];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int lr = tid + 256 * s;
+    const double2* src = M + int64_t(k0 + (lr < m ? lr : 0)) * ld + k0;
+#pragma unroll
+    for (int q = 0; q < LU_NB; ++q) {
+      const double2 v = src[q < kb ? q : 0];
+      const bool in = lr < m && q < kb;
+      P[s][q] = make_double2(in ? v.x : 0.0, in ? v.y : 0.0);
     }
+  }
+  bool fail = false;   // (set by every thread alike: all read the same pivot from LDS)
+  static_while([&](auto kc) __attribute__((always_inline)) -> bool {
+    constexpr int k = decltype(kc)::value;
+    if (k >= kb) return false;   // (uniform) past the panel: done
+    constexpr int par = k & 1;
+    double best = -1.0;
+    int bi = n;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int lr = tid + 256 * s;
+      const double v = cabs2(P[s][k]);
+      if (lr >= k && lr < m && v > best) {
+        best = v;
+        bi = k0 + lr;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double v2 = __shfl_xor(best, off);
+      const int i2 = __shfl_xor(bi, off);
+      if (v2 > best || (v2 == best && i2 < bi)) {
+        best = v2;
+        bi = i2;
+      }
+    }
+    if (lane == 0) {
+      sm.sv[par][wv] = best;
+      sm.si[par][wv] = bi;
+    }
+    if (bi < n && tid == ((bi - k0) & 255)) {
+      const int so = (bi - k0) >> 8;
+#pragma unroll
+      for (int q = 0; q < LU_NB; ++q) {
+        double2 v = P[0][q];
+#pragma unroll
+        for (int s = 1; s < S; ++s) v = sel2(s == so, P[s][q], v);
+        sm.crow[par][wv][q] = v;
+      }
+    }
+    if (tid == k)
+#pragma unroll
+      for (int q = 0; q < LU_NB; ++q) sm.krow[par][q] = P[0][q];
+    __syncthreads();
+    double pmax = sm.sv[par][0];
+    int p = sm.si[par][0], pw = 0;
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+      const double v2 = sm.sv[par][w];
+      const int i2 = sm.si[par][w];
+      if (v2 > pmax || (v2 == pmax && i2 < p)) {
+        pmax = v2;
+        p = i2;
+        pw = w;
+      }
+    }
+    if (!(pmax > 0.0) || !(pmax < 1e300) || p >= n) {
+      if (tid == 0) info[sys] = k0 + k + 1;
+      fail = true;
+      return false;
+    }
+    if (tid == 0) sm.perm[k] = p;
+    double2 prow[LU_NB];
+#pragma unroll
+    for (int q = k; q < LU_NB; ++q) prow[q] = sm.crow[par][pw][q];
+    const int lp = p - k0;
+    if (lp != k) {
+      if (tid == (lp & 255)) {
+        const int so = lp >> 8;
+#pragma unroll
+        for (int q = 0; q < LU_NB; ++q) {
+          const double2 v = sm.krow[par][q];
+#pragma unroll
+          for (int s = 0; s < S; ++s) P[s][q] = sel2(s == so, v, P[s][q]);
+        }
+      }
+      if (tid == k)
+#pragma unroll
+        for (int q = 0; q < LU_NB; ++q) P[0][q] = sm.crow[par][pw][q];
+    }
+    const double2 akk = prow[k];
+    const double den = cabs2(akk);
+    const double2 inv = make_double2(akk.x / den, -akk.y / den);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int lr = tid + 256 * s;
+      if (lr > k && lr < m) {
+        const double2 l = cmul(P[s][k], inv);
+        P[s][k] = l;
+#pragma unroll
+        for (int j = k + 1; j < LU_NB; ++j)
+          if (j < kb) P[s][j] = csub(P[s][j], cmul(l, prow[j]));
+      }
+    }
+    return true;
+  }, Seq{});
+  if (fail) return false;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int lr = tid + 256 * s;
+    if (lr < m)
+#pragma unroll
+      for (int q = 0; q < LU_NB; ++q)
+        if (q < kb) M[int64_t(k0 + lr) * ld + k0 + q] = P[s][q];
+  }
+  if (tid < kb)
+#pragma unroll
+    for (int q = 0; q < LU_NB; ++q) sm.L11[tid][q] = P[0][q];
+  __syncthreads();
+  return true;
+}
+
+// The columns c0, c0 + cstride, ... counted from the end of panel k0 (B included): the panel's
+// row interchanges perm[k] (k < kb, in order) and U12 = L11^{-1} A12 (unit lower triangle),
+// one column per thread with the column's panel rows in registers.  Rows that an interchange
+// sends out of the panel are tracked in registers too, so each value is loaded and stored once.
+__device__ __forceinline__ void lu_columns(double2* __restrict__ M, int ld, int k0, int kb, const int* perm,
+                                           const double2 (*L11)[LU_NB + 1], int c0, int cstride) {
+  int pm[LU_NB];
+#pragma unroll
+  for (int k = 0; k < LU_NB; ++k) pm[k] = k < kb ? perm[k] : k0;   // (unused past kb; a valid row)
+  const int pe = k0 + kb;   // first row (and column) past the panel
+  for (int c = pe + c0; c < ld; c += cstride) {
+    // (a compiler barrier: L11 is re-read from LDS per column rather than held in registers)
+    __asm__ volatile("" ::: "memory");
+    double2 r[LU_NB], e[LU_NB];
+#pragma unroll
+    for (int q = 0; q < LU_NB; ++q) r[q] = M[int64_t(k0 + (q < kb ? q : 0)) * ld + c];
+#pragma unroll
+    for (int k = 0; k < LU_NB; ++k) e[k] = M[int64_t(pm[k] >= pe ? pm[k] : k0) * ld + c];
+    // the interchanges in order; e[k] = what row pm[k] holds after step k
+#pragma unroll
+    for (int k = 0; k < LU_NB; ++k) {
+      const int pk = pm[k];
+      if (k >= kb) {
+      } else if (pk < pe) {
+#pragma unroll
+        for (int q = k + 1; q < LU_NB; ++q)
+          if (pk - k0 == q) {
+            const double2 t = r[q];
+            r[q] = r[k];
+            r[k] = t;
+          }
+      } else {
+        double2 cur = e[k];
+#pragma unroll
+        for (int k2 = 0; k2 < k; ++k2)
+          if (pm[k2] == pk) cur = e[k2];
+        e[k] = r[k];
+        r[k] = cur;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < LU_NB; ++k) {
+      bool last = k < kb && pm[k] >= pe;
+#pragma unroll
+      for (int k2 = k + 1; k2 < LU_NB; ++k2)
+        if (k2 < kb && pm[k2] == pm[k]) last = false;
+      if (last) M[int64_t(pm[k]) * ld + c] = e[k];
+    }
+    // U12 = L11^{-1} A12 (unit lower triangle)
+#pragma unroll
+    for (int rr = 1; rr < LU_NB; ++rr) {
+      double2 acc = r[rr];
+#pragma unroll
+      for (int q = 0; q < rr; ++q) acc = csub(acc, cmul(L11[rr][q], r[q]));
+      if (rr < kb) r[rr] = acc;
+    }
+#pragma unroll
+    for (int q = 0; q < LU_NB; ++q)
+      if (q < kb) M[int64_t(k0 + q) * ld + c] = r[q];
   }
 }
 
+// Diagonal block k0 of the back substitution U X = B' on the right-hand-side columns [n, ld):
+// X rows k0 .. k0 + kb for the columns c0 + tid, c0 + tid + stride, ...
+__device__ __forceinline__ void back_diag(double2* __restrict__ M, int n, int ld, int k0, int c0, int cstride,
+                          double2 (*Ud)[LU_NB + 1]) {
+  const int kb = min(LU_NB, n - k0);
+  {
+    // the diagonal block of U in LDS (LU_NB^2 = 256 entries, one per thread)
+    const int r = threadIdx.x / LU_NB, q = threadIdx.x % LU_NB;
+    const bool in = r < kb && q < kb;
+    const double2 v = M[int64_t(k0 + (in ? r : 0)) * ld + k0 + (in ? q : 0)];
+    Ud[r][q] = sel2(in, v, make_double2(0, 0));
+  }
+  __syncthreads();
+  for (int c = n + c0 + threadIdx.x; c < ld; c += cstride) {
+    __asm__ volatile("" ::: "memory");   // (Ud re-read from LDS per column, not held in registers)
+    double2 x[LU_NB];
+#pragma unroll
+    for (int q = 0; q < LU_NB; ++q) x[q] = M[int64_t(k0 + (q < kb ? q : 0)) * ld + c];
+#pragma unroll
+    for (int r = LU_NB - 1; r >= 0; --r) {
+      double2 acc = x[r];
+#pragma unroll
+      for (int q = r + 1; q < LU_NB; ++q)
+        if (q < kb) acc = csub(acc, cmul(Ud[r][q], x[q]));
+      const double2 d = Ud[r][r];
+      const double den = cabs2(d);
+      if (r < kb) x[r] = cmul(acc, make_double2(d.x / den, -d.y / den));
+    }
+#pragma unroll
+    for (int q = 0; q < LU_NB; ++q)
+      if (q < kb) M[int64_t(k0 + q) * ld + c] = x[q];
+  }
+  __syncthreads();
+}
+
+// n <= 256: the panels in registers.
 __global__ __launch_bounds__(256) void k_dense_solve(double2* __restrict__ A, int n, int ld,
                                                      int* __restrict__ info) {
   const int sys = blockIdx.x;
   double2* M = A + int64_t(sys) * n * ld;
-  __shared__ double sv[256];
-  __shared__ int si[256];
+  __shared__ PanelSmem psm;
   __shared__ double2 Ls[64][LU_NB + 1];
   __shared__ double2 Us[LU_NB][64 + 1];
   if (threadIdx.x == 0) info[sys] = 0;
   for (int k0 = 0; k0 < n; k0 += LU_NB) {
-    if (!lu_panel(M, n, ld, k0, sys, info, sv, si)) return;
+    if (!lu_panel_reg<1>(M, n, ld, k0, sys, info, psm)) return;
     const int kb = min(LU_NB, n - k0);
+    lu_columns(M, ld, k0, kb, psm.perm, psm.L11, threadIdx.x, 256);
+    __syncthreads();
     tile_update(M, ld, k0 + kb, n, k0 + kb, ld, k0, k0, kb, Ls, Us);
     __syncthreads();
   }
@@ -213,23 +462,51 @@ __global__ __launch_bounds__(256) void k_dense_solve(double2* __restrict__ A, in
   const int last = ((n - 1) / LU_NB) * LU_NB;
   for (int k0 = last; k0 >= 0; k0 -= LU_NB) {
     const int kb = min(LU_NB, n - k0);
-    back_diag(M, n, ld, k0, 0, 256);
-    __syncthreads();
+    back_diag(M, n, ld, k0, 0, 256, psm.L11);
     if (k0 > 0) tile_update(M, ld, 0, k0, n, ld, k0, k0, kb, Ls, Us);
     __syncthreads();
   }
 }
 
-// The same factorisation and substitution split over launches for few, large systems: the
-// panels run on one workgroup per system, the trailing updates and the back substitution on
-// one workgroup per 64 x 64 tile (bitwise the same operations as k_dense_solve).
+// The same factorisation and substitution split over launches for few or large systems: the
+// panels run on one workgroup per system (in registers while n - k0 <= 1024, else in global
+// memory), the trailing updates and the back substitution on one workgroup per 64 x 64 tile
+// (bitwise the same operations as k_dense_solve).
+template <int S>
 __global__ __launch_bounds__(256) void k_lu_panel(double2* __restrict__ A, int n, int ld, int k0,
-                                                  int* __restrict__ info) {
+                                                  int* __restrict__ info, int* __restrict__ piv) {
   const int sys = blockIdx.x;
   if (info[sys]) return;
-  __shared__ double sv[256];
-  __shared__ int si[256];
-  (void)lu_panel(A + int64_t(sys) * n * ld, n, ld, k0, sys, info, sv, si);
+  if constexpr (S > 0) {
+    __shared__ PanelSmem psm;
+    if (lu_panel_reg<S>(A + int64_t(sys) * n * ld, n, ld, k0, sys, info, psm) && threadIdx.x < LU_NB)
+      piv[sys * LU_NB + threadIdx.x] = psm.perm[threadIdx.x];
+  } else {
+    __shared__ double sv[256];
+    __shared__ int si[256];
+    (void)lu_panel(A + int64_t(sys) * n * ld, n, ld, k0, sys, info, sv, si);
+  }
+}
+
+// lu_columns of panel k0 for the columns blockIdx.x * 256 + t, one workgroup per 256 columns
+// (after k_lu_panel<S > 0>: L11 from the factored panel, the interchanges from piv)
+__global__ __launch_bounds__(256) void k_lu_cols(double2* __restrict__ A, int n, int ld, int k0,
+                                                 const int* __restrict__ info, const int* __restrict__ piv) {
+  const int sys = blockIdx.y;
+  if (info[sys]) return;
+  double2* M = A + int64_t(sys) * n * ld;
+  const int kb = min(LU_NB, n - k0);
+  __shared__ double2 L11[LU_NB][LU_NB + 1];
+  __shared__ int perm[LU_NB];
+  {
+    const int r = threadIdx.x / LU_NB, q = threadIdx.x % LU_NB;
+    const bool in = r < kb && q < kb;
+    const double2 v = M[int64_t(k0 + (in ? r : 0)) * ld + k0 + (in ? q : 0)];
+    L11[r][q] = sel2(in, v, make_double2(0, 0));
+    if (threadIdx.x < LU_NB) perm[threadIdx.x] = threadIdx.x < kb ? piv[sys * LU_NB + threadIdx.x] : k0;
+  }
+  __syncthreads();
+  lu_columns(M, ld, k0, kb, perm, L11, blockIdx.x * 256 + threadIdx.x, gridDim.x * 256);
 }
 
 __global__ __launch_bounds__(256) void k_lu_tiles(double2* __restrict__ A, int n, int ld, int r0, int r1,
@@ -248,7 +525,8 @@ __global__ __launch_bounds__(256) void k_lu_back_diag(double2* __restrict__ A, i
                                                       const int* __restrict__ info) {
   const int sys = blockIdx.y;
   if (info[sys]) return;
-  back_diag(A + int64_t(sys) * n * ld, n, ld, k0, blockIdx.x * 256, gridDim.x * 256);
+  __shared__ double2 Ud[LU_NB][LU_NB + 1];
+  back_diag(A + int64_t(sys) * n * ld, n, ld, k0, blockIdx.x * 256, gridDim.x * 256, Ud);
 }
 
 __global__ void k_info_zero(int* __restrict__ info, int nsys) {
@@ -484,15 +762,27 @@ void gather_local(hipStream_t s, const Geom& g, const double2* A, int noff, cons
 }
 
 void dense_solve(hipStream_t s, double2* Aug, int n, int nrhs, int nsys, int* info) {
+  int* piv = info + nsys;
   const int ld = n + nrhs;
-  if (nsys >= 32 || n <= 64) {
+  // many small systems: one workgroup per system for the whole solve; otherwise the panels on
+  // one workgroup per system and the trailing updates spread over 64 x 64 tiles
+  if (n <= 256 && (nsys >= 32 || n <= 64)) {
     hipLaunchKernelGGL(k_dense_solve, dim3(nsys), dim3(256), 0, s, Aug, n, ld, info);
     return;
   }
   hipLaunchKernelGGL(k_info_zero, dim3((nsys + 63) / 64), dim3(64), 0, s, info, nsys);
   for (int k0 = 0; k0 < n; k0 += LU_NB) {
     const int kb = min(LU_NB, n - k0);
-    hipLaunchKernelGGL(k_lu_panel, dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info);
+    switch ((n - k0 + 255) / 256) {
+      case 1: hipLaunchKernelGGL(k_lu_panel<1>, dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info, piv); break;
+      case 2: hipLaunchKernelGGL(k_lu_panel<2>, dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info, piv); break;
+      case 3: hipLaunchKernelGGL(k_lu_panel<3>, dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info, piv); break;
+      case 4: hipLaunchKernelGGL(k_lu_panel<4>, dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info, piv); break;
+      default: hipLaunchKernelGGL(k_lu_panel<0>, dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info, piv);
+    }
+    if (n - k0 <= 1024 && k0 + kb < ld)
+      hipLaunchKernelGGL(k_lu_cols, dim3((ld - k0 - kb + 255) / 256, nsys), dim3(256), 0, s, Aug, n, ld, k0,
+                         (const int*)info, (const int*)piv);
     const int r0 = k0 + kb, c0 = k0 + kb;
     if (r0 < n) {
       const int tiles = ((n - r0 + 63) / 64) * ((ld - c0 + 63) / 64);
