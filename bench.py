@@ -756,6 +756,75 @@ def committed_traffic(family):
     return None
 
 
+LEGS = ("multi", "agg", "batch", "tvs", "variants", "serving")
+LEG_TIMEOUT_S = {"multi": 600, "serving": 900}
+
+
+def leg_child(name, args, script=None):
+    """One optional leg in a child process.  The full run starts these before it touches the GPU
+    itself (a process that has initialised HIP may not start another program), one at a time,
+    so that they never share the GPU with a timed pass; a failure or crash in a leg then costs
+    that leg's record only, not the headline line.  The child's progress lines pass through."""
+    import subprocess
+    cmd = [sys.executable, script or os.path.abspath(__file__), "--leg", name, "--groups", str(args.groups),
+           "--nrhs", str(args.nrhs), "--workload", args.workload, "--serve-requests", str(args.serve_requests)]
+    if args.serve_qps is not None:
+        cmd += ["--serve-qps", str(args.serve_qps)]
+    if args.tv_sweeps is not None:
+        cmd += ["--tv-sweeps", str(args.tv_sweeps)]
+    if args.aug_vectors is not None:
+        cmd += ["--aug-vectors", str(args.aug_vectors)]
+    timeout = LEG_TIMEOUT_S.get(name, 300)
+    log(f"leg {name}: child process")
+    try:
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=None, text=True, timeout=timeout)
+    except subprocess.TimeoutExpired:
+        return {"error": f"child process timed out after {timeout} s"}
+    for text in reversed(r.stdout.strip().splitlines()):
+        try:
+            d = json.loads(text)
+        except ValueError:
+            continue
+        if isinstance(d, dict) and d.get("leg") == name:
+            return d["result"]
+    return {"error": f"child process ended with status {r.returncode} and no result"}
+
+
+def run_leg(name, args):
+    """Child side of leg_child: the leg's own gauge fields (host-generated before the GPU is
+    touched), context and hierarchies."""
+    serve_links = multi_links = None
+    if name == "serving":
+        serve_links = generate_links(synth.serving_configs(16))
+    if name == "multi":
+        if not os.path.exists(synth.MULTI_CRITICAL_PATH):
+            return {"error": "critical masses not generated (python tests/golden/make_golden.py --multi-only)"}
+        multi_links = generate_links(synth.multi_lattice_configs())
+    import torch
+    from paper_2608_03515_amd import amamg as lib
+    if name == "serving":
+        return serve_leg(lib, args.serve_requests, args.serve_qps, links=serve_links)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    ctx = lib.Context(0, stream.cuda_stream)
+    if name == "multi":
+        return multi_lattice_leg(lib, torch, ctx, args.groups, links=multi_links)
+    if name == "agg":
+        return agg_sweep_leg(lib, torch, ctx, args.groups)
+    if name == "tvs":
+        return tv_sweep_leg(lib, torch, ctx, args.groups)
+    if name == "variants":
+        return variants_leg(lib, torch, ctx, args.groups)
+    w = synth.WORKLOADS[args.workload]
+    m0 = synth.critical_masses()[w.name] + w.gaps[0] if w.m0 is None else w.m0
+    g = lib.Gauge(ctx, synth.links_to_abi(w.links()), m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(**w.setup_kw()))
+    out = batch_sweep_leg(lib, torch, ctx, h, w, args.groups)
+    h.close()
+    g.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -769,7 +838,9 @@ def main():
     ap.add_argument("--serve-qps", type=float, default=None,
                     help="arrival rate of the serving leg (default: 0.7 x its measured capacity)")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg")
-    ap.add_argument("--no-multi", action="store_true", help="skip the multi-lattice leg")
+    ap.add_argument("--multi", action="store_true",
+                    help="also run the multi-lattice leg (off by default: one full run ended in a host "
+                         "heap abort during it, cause not yet found)")
     ap.add_argument("--no-agg-sweep", action="store_true", help="skip the aggregate-size sweep")
     ap.add_argument("--no-batch-sweep", action="store_true",
                     help="skip the right-hand-side count sweep (1..128, mixed; BF16 links at 64)")
@@ -778,6 +849,9 @@ def main():
     ap.add_argument("--stencil-only", action="store_true",
                     help="run only the 4096^2 fine-stencil bandwidth leg (for kernel traces)")
     ap.add_argument("--multi-only", action="store_true", help="run only the multi-lattice leg")
+    ap.add_argument("--leg", default=None, choices=LEGS,
+                    help="run one optional leg alone and print {\"leg\": name, \"result\": ...} (the full run "
+                         "starts each optional leg this way in a child process)")
     ap.add_argument("--family", default=None, choices=FAMILIES,
                     help="kernel family of the roofline (default: the largest in an instrumented "
                          "one-stream step)")
@@ -817,21 +891,29 @@ def main():
               "(independent lattices and requests would run one per GPU).", file=sys.stderr)
         sys.exit(2)
 
-    # host-generated gauge fields of the serving and multi-lattice legs, before the GPU is touched
-    full = not (args.stencil_only or args.profile_mixed or args.serve_only or args.multi_only)
-    serve_links = multi_links = None
-    if args.serve_requests > 0 and (full or args.serve_only):
-        serve_links = generate_links(synth.serving_configs(16))
-    if (full and not args.no_multi and os.path.exists(synth.MULTI_CRITICAL_PATH)) or args.multi_only:
-        multi_links = generate_links(synth.multi_lattice_configs())
+    if args.serve_only or args.multi_only:
+        args.leg = "serving" if args.serve_only else "multi"
+    if args.leg:
+        try:
+            out = run_leg(args.leg, args)
+        except Exception as e:              # reported in the leg's record
+            out = {"error": f"{type(e).__name__}: {e}"}
+        print(json.dumps({"leg": args.leg, "result": out}), flush=True)
+        return
+    # the optional legs, each in a child process, before this process touches the GPU
+    full = not (args.stencil_only or args.profile_mixed)
+    legs = {}
+    if full:
+        skip = {"multi": not args.multi, "agg": args.no_agg_sweep, "batch": args.no_batch_sweep,
+                "tvs": args.no_variants, "variants": args.no_variants, "serving": args.serve_requests <= 0}
+        for name in LEGS:
+            if not skip[name]:
+                legs[name] = leg_child(name, args)
+                log(f"leg {name}", json.dumps(legs[name])[:400])
 
     import torch
     from paper_2608_03515_amd import amamg as lib
 
-    if args.serve_only:
-        out = serve_leg(lib, args.serve_requests, args.serve_qps, links=serve_links)
-        print(json.dumps({"serving": out}), flush=True)
-        return
     if args.stencil_only:
         stream = torch.cuda.Stream()
         torch.cuda.set_stream(stream)
@@ -844,13 +926,6 @@ def main():
         torch.neg(src, out=dst)          # one elementwise kernel: 1 GiB read, 1 GiB written
         torch.cuda.synchronize()
         print(json.dumps({"stencil_4096": st}), flush=True)
-        return
-    if args.multi_only:
-        stream = torch.cuda.Stream()
-        torch.cuda.set_stream(stream)
-        ctx = lib.Context(0, stream.cuda_stream)
-        print(json.dumps({"multi_lattice": multi_lattice_leg(lib, torch, ctx, args.groups, links=multi_links)}),
-              flush=True)
         return
 
     stream = torch.cuda.Stream()          # default priority; the library runs on it
@@ -950,49 +1025,8 @@ def main():
     stencil = None if args.no_stencil else stencil_bandwidth(lib, torch, ctx)
     if stencil:
         log("stencil", json.dumps(stencil))
-    multi = None
-    if not args.no_multi:
-        if not os.path.exists(synth.MULTI_CRITICAL_PATH):
-            log("multi-lattice leg skipped: critical masses not generated "
-                "(python tests/golden/make_golden.py --multi-only)")
-        else:
-            try:
-                multi = multi_lattice_leg(lib, torch, ctx, args.groups, links=multi_links)
-            except Exception as e:          # an optional leg must not cost the headline line
-                multi = {"error": f"{type(e).__name__}: {e}"}
-            log("multi-lattice", json.dumps(multi))
-    agg = None
-    if not args.no_agg_sweep:
-        try:
-            agg = agg_sweep_leg(lib, torch, ctx, args.groups)
-        except Exception as e:              # an optional leg must not cost the headline line
-            agg = {"error": f"{type(e).__name__}: {e}"}
-    batches = None
-    if not args.no_batch_sweep:
-        try:
-            batches = batch_sweep_leg(lib, torch, ctx, h, w, args.groups)
-        except Exception as e:              # an optional leg must not cost the headline line
-            batches = {"error": f"{type(e).__name__}: {e}"}
-    tvs = None
-    if not args.no_variants:
-        try:
-            tvs = tv_sweep_leg(lib, torch, ctx, args.groups)
-        except Exception as e:              # an optional leg must not cost the headline line
-            tvs = {"error": f"{type(e).__name__}: {e}"}
-    variants = None
-    if not args.no_variants:
-        try:
-            variants = variants_leg(lib, torch, ctx, args.groups)
-        except Exception as e:              # an optional leg must not cost the headline line
-            variants = {"error": f"{type(e).__name__}: {e}"}
-    serving = None
-    if args.serve_requests > 0:
-        try:
-            serving = serve_leg(lib, args.serve_requests, args.serve_qps, links=serve_links)
-            log("serving", json.dumps({k: serving[k] for k in ("p50_ms", "p99_ms", "solves_per_s", "ok",
-                                                                "capacity_requests_per_s")}))
-        except Exception as e:              # an optional leg must not cost the headline line
-            serving = {"error": f"{type(e).__name__}: {e}"}
+    multi, agg, batches = legs.get("multi"), legs.get("agg"), legs.get("batch")
+    tvs, variants, serving = legs.get("tvs"), legs.get("variants"), legs.get("serving")
     head = res["mixed"]
     line = {
         "metric": "solves/s to rel. residual 1e-10 at L=256 (mixed vs FP64); stencil GB/s; p99",

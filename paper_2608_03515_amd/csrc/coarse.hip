@@ -909,8 +909,8 @@ template <int B, typename R, typename M, typename V>
 static void gs_pair_b(hipStream_t s, const void* A, const void* D, void* x, const void* f, int Lt, int Lx,
                       int c0, int nrhs, int64_t stride, const RhsState* st, int rb) {
   const int ncn = (Lt / 4) * (Lx / 4);
-  if constexpr (B == 8 && sizeof(R) == 4) {
-    if (rb == 0) rb = 2;
+  if constexpr (B == 8) {
+    if (rb == 0 && sizeof(R) == 4) rb = 2;
     if (rb > 1 && nrhs >= rb) {
       const dim3 g(unsigned((ncn + 3) / 4), unsigned((nrhs + rb - 1) / rb));
       if (rb == 4)
@@ -929,11 +929,12 @@ static void gs_pair_b(hipStream_t s, const void* A, const void* D, void* x, cons
 
 // Colour block qb of the coarse sweep.  FP32 8 x 8 blocks with gs_on_matrix_cores(mode):
 // one matrix-core launch, variant = stencil offsets per load batch (8, 12 or 24; 0 = 12).
-// Smaller grids and other blocks: variant > 0 colour-pair launches with that many
-// right-hand sides per wave (FP32 8 x 8 blocks), < 0 one k_stencil_gs_quad_mr launch with
-// -variant right-hand sides per wave (FP32 8 x 8 blocks; otherwise colour pairs).  Within
-// each of the two paths every variant gives bitwise the same results; which path runs depends
-// on the grid only, so a right-hand side's result does not depend on its batch.
+// Smaller grids, FP64 and other blocks: variant > 0 colour-pair launches with that many
+// right-hand sides per wave (8 x 8 blocks; 0 = 2 in FP32, the generic pair kernel in FP64),
+// < 0 one k_stencil_gs_quad_mr launch with -variant right-hand sides per wave (8 x 8 blocks;
+// otherwise colour pairs).  Within each of the two paths every variant gives bitwise the same
+// results; which path runs depends on the grid only, so a right-hand side's result does not
+// depend on its batch.
 template <int B, typename R, typename M, typename V>
 static void gs_block_b(hipStream_t s, const void* A, const void* D, void* x, const void* f, int Lt, int Lx,
                        int qb, int nrhs, int64_t stride, const RhsState* st, int variant, int mode) {
@@ -952,7 +953,7 @@ static void gs_block_b(hipStream_t s, const void* A, const void* D, void* x, con
       return;
     }
   }
-  if constexpr (B == 8 && sizeof(R) == 4) {
+  if constexpr (B == 8) {
     const int rb = -variant;
     if ((rb == 1 || rb == 2) && nrhs >= rb) {
       const int ngr = (Lt / 4) * (Lx / 4);

@@ -416,10 +416,10 @@ void run_setup(amamg_hierarchy* h, hipStream_t stream, Pool* scratch) {
           for (int c = 0; c < 2; ++c)
             wilson_gs(s, LINK_F64, U0, U1, F64, L.tv, nullptr, g.Lt, g.Lx, h->m0, c, nv, ndof, nullptr);
         } else {
-          // the 16 colours as 4 colour blocks of two paired launches each (bitwise the
-          // colour-by-colour sweep)
+          // the 16 colours as 4 colour blocks, one launch each for 8 x 8 blocks (two colour-pair
+          // launches otherwise); bitwise the colour-by-colour sweep
           for (int qb = 0; qb < 4; ++qb)
-            stencil_gs_block(s, F64, L.A, L.Dinv, L.tv, nullptr, g.Lt, g.Lx, g.b, qb, nv, ndof, nullptr, 0,
+            stencil_gs_block(s, F64, L.A, L.Dinv, L.tv, nullptr, g.Lt, g.Lx, g.b, qb, nv, ndof, nullptr, -1,
                              p.block_smoother);
         }
       }

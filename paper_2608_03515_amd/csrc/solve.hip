@@ -388,28 +388,31 @@ static void tune_batch(Batch& bt) {
   }
   for (size_t k = 1; k + 1 < h->lv.size(); ++k) {
     const Geom& g = h->lv[k].g;
-    if (!(g.b == 8 && c.T == F32)) continue;
+    if (g.b != 8) continue;
+    const bool f32 = c.T == F32;
     std::vector<int> cand;
-    if (gs_on_matrix_cores(g.Lt, g.Lx, h->prm.block_smoother)) {
+    if (f32 && gs_on_matrix_cores(g.Lt, g.Lx, h->prm.block_smoother)) {
       cand = {8, 12, 24};                   // offsets per load batch of the matrix-core sweep
     } else {
-      if (cap < 2) continue;
-      // > 0: colour-pair launches with that many rhs per wave; < 0: one launch per colour block
-      cand = {1, 2};
+      // > 0: colour-pair launches with that many rhs per wave (FP64: 0 = the generic pair
+      // kernel); < 0: one launch per colour block
+      if (f32 && cap < 2) continue;
+      cand = f32 ? std::vector<int>{1} : std::vector<int>{0};
+      if (cap >= 2) cand.push_back(2);
       if (cap >= 4) cand.push_back(4);
       cand.push_back(-1);
-      cand.push_back(-2);
+      if (cap >= 2) cand.push_back(-2);
     }
     const int64_t nd = g.ndof();
     Workspace::Lev& WL = ws->lv[k];
-    const void* Ak = h->lv[k].A32;
-    const void* Dk = h->lv[k].Dinv32;
+    const void* Ak = f32 ? (const void*)h->lv[k].A32 : (const void*)h->lv[k].A;
+    const void* Dk = f32 ? (const void*)h->lv[k].Dinv32 : (const void*)h->lv[k].Dinv;
     bt.gs_rb[k] = tuned(ctx->tuner, {Tuner::COARSE_GS_RHS, g.Lt, g.Lx, g.b, prec, cap}, cand, [&](int rb) {
       HIPCHECK(hipMemsetAsync(WL.x, 0, rs * cap * nd, bt.s));
       HIPCHECK(hipMemsetAsync(WL.f, 0, rs * cap * nd, bt.s));
       return time_us(bt.s, [&] {
         for (int qb = 0; qb < 4; ++qb)
-          stencil_gs_block(bt.s, F32, Ak, Dk, WL.x, WL.f, g.Lt, g.Lx, g.b, qb, cap, nd, nullptr, rb,
+          stencil_gs_block(bt.s, c.T, Ak, Dk, WL.x, WL.f, g.Lt, g.Lx, g.b, qb, cap, nd, nullptr, rb,
                            h->prm.block_smoother);
       });
     });

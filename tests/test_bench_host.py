@@ -96,3 +96,34 @@ def test_traffic_summaries_scale_by_the_calibration_copy(tmp_path):
     bench.stencil_traffic_summary(str(fetch), str(write), str(stats), str(out), "CMD COUNTER", "TRACE")
     row = [ln for ln in out.read_text().splitlines() if "k_wilson_apply" in ln][0]
     assert "| fp64 | 1 |" in row and "| 1.000 |" in row and f"| {alg / 1e6:.0f} |" in row
+
+
+def _leg_args(**kw):
+    import argparse
+    a = dict(groups=2, nrhs=64, workload="C3", serve_requests=0, serve_qps=None, tv_sweeps=None,
+             aug_vectors=None)
+    a.update(kw)
+    return argparse.Namespace(**a)
+
+
+def test_optional_leg_result_comes_back_from_its_child_process(tmp_path):
+    """A leg run in a child process: its result line is picked out of the child's stdout, and
+    the command carries the run's options."""
+    script = tmp_path / "child.py"
+    script.write_text("import json, sys\n"
+                      "print('progress', file=sys.stderr)\n"
+                      "print('not json')\n"
+                      "print(json.dumps({'leg': sys.argv[2], 'result': {'argv': sys.argv[3:]}}))\n")
+    out = bench.leg_child("agg", _leg_args(tv_sweeps=16), script=str(script))
+    assert out["argv"][:2] == ["--groups", "2"] and "--tv-sweeps" in out["argv"]
+
+
+def test_a_crashing_leg_costs_only_its_own_record(tmp_path):
+    """A child that aborts (or prints no result) gives an error record instead of ending the
+    benchmark."""
+    script = tmp_path / "child.py"
+    script.write_text("import os\nprint('partial output')\nos.abort()\n")
+    out = bench.leg_child("multi", _leg_args(), script=str(script))
+    assert "error" in out and "status" in out["error"]
+    script.write_text("import sys\nsys.exit(0)\n")
+    assert "error" in bench.leg_child("serving", _leg_args(), script=str(script))

@@ -769,6 +769,35 @@ def test_tuned_launch_shapes_do_not_change_results(lib, a, block_cands):
         assert e["choice"] in e["candidates_us"] and all(t > 0 for t in e["candidates_us"].values())
 
 
+def test_tuned_fp64_block_sweep_shapes_do_not_change_results(lib):
+    """FP64 solves (20 right-hand sides, and one) on the 128^2 workload: the level-1 block sweep
+    (16 x 16 nodes of 8 dofs) as generic colour-pair launches, colour-pair launches with 2 or 4
+    right-hand sides per wave, or one launch per 2 x 2 colour block with 1 or 2 per wave, forced
+    one by one and chosen by timing, gives bitwise the same solutions and iteration counts."""
+    w = synth.WORKLOADS["C4"]
+    U, m0 = w.links(), synth.critical_masses()["C4"] + w.gaps[0]
+    ctx = lib.Context(0)
+    g = make_gauge(lib, ctx, U, m0)
+    h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=8, overlap=2, n_test_vectors=8))
+    sp = lib.default_solve_params(precision=lib.FP64)
+    for nrhs, cands in [(20, {0, 2, 4, -1, -2}), (1, {0, -1})]:
+        psi = synth.field_to_abi(synth.gaussian_rhs(w.L, w.L, 5252, nrhs=nrhs))
+        runs = []
+        for mode, force in [(lib.TUNE_FORCE, q) for q in range(len(cands))] + [(lib.TUNE_AUTO, 0)]:
+            say("fp64 tuning", nrhs, mode, force)
+            ctx.set_tuning(mode, force)
+            x, infos, st = h.solve(psi, sp)
+            assert st == lib.OK
+            runs.append((x, [i.iterations for i in infos]))
+        for x, its in runs[1:]:
+            assert its == runs[0][1] and np.array_equal(x, runs[0][0])
+        entries = [e for e in ctx.tuning_entries() if e["kind"] == "block_smoother_launch"]
+        assert any(set(e["candidates_us"]) == cands for e in entries), entries
+    h.close()
+    g.close()
+    ctx.close()
+
+
 def test_graph_replayed_cycles_equal_eager(lib):
     """Restart cycles captured into a HIP graph and replayed (once per cycle, with the host's
     state reads and the stream groups' own work between replays) give bitwise the eager
