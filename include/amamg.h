@@ -289,6 +289,17 @@ amamg_status amamg_apply_dirac(amamg_gauge *g, int32_t precision, int32_t nrhs,
  * Asynchronous on the context stream. */
 amamg_status amamg_apply_dirac_device(amamg_gauge *g, int32_t precision, int32_t nrhs,
                                       const void *in_dev, void *out_dev);
+/* The setup's batched dense solve (SM-AMG subsection: the local block systems of the
+ * wirebasket interpolation; Multilevel approach: the exact coarsest-level solve): for each of
+ * nsys systems the row-major augmented matrix [A | B] of n rows and n + nrhs complex columns
+ * (double [nsys][n][n + nrhs][2], host buffer) is overwritten on return with B replaced by
+ * A^-1 B (LU with partial pivoting; the other columns then hold factors).  info[sys] = 0, or
+ * k + 1 when pivot column k is zero or not finite (that system's B is then not a solution).
+ * The same launches as the setup: one workgroup per system for n <= 256 with 32 or more
+ * systems (or n <= 64), else panel, interchange and tile launches.  Synchronous; allocates
+ * its device buffers.  AMAMG_ERR_INVALID_ARG for n < 1, nrhs < 1, nsys < 1 or null pointers. */
+amamg_status amamg_dense_solve(amamg_context *ctx, int32_t n, int32_t nrhs, int32_t nsys, double *aug,
+                               int32_t *info);
 /* Grid of level `level` (0 = fine lattice) and degrees of freedom per node. */
 amamg_status amamg_level_info(const amamg_hierarchy *h, int32_t level, int32_t *lt,
                               int32_t *lx, int32_t *b);

@@ -32,7 +32,7 @@ EXPORTED = ["amamg_default_setup_params", "amamg_default_solve_params", "amamg_c
             "amamg_context_destroy", "amamg_last_error", "amamg_gauge_load",
             "amamg_gauge_set_mass", "amamg_gauge_update_links", "amamg_gauge_destroy",
             "amamg_setup", "amamg_hierarchy_update", "amamg_hierarchy_set_mass", "amamg_hierarchy_derive_mass", "amamg_hierarchy_destroy", "amamg_solve", "amamg_solve_device", "amamg_solve_multi_device",
-            "amamg_residual_history", "amamg_apply_dirac", "amamg_apply_dirac_device",
+            "amamg_residual_history", "amamg_apply_dirac", "amamg_apply_dirac_device", "amamg_dense_solve",
             "amamg_level_info",
             "amamg_get_aggregates", "amamg_get_prolongator", "amamg_get_coarse_operator",
             "amamg_get_test_vectors", "amamg_apply_transfer", "amamg_apply_transfer_noalloc", "amamg_apply_smoother", "amamg_context_set_tuning",
@@ -112,6 +112,7 @@ _sig = {
     "amamg_hierarchy_set_mass": (C.c_int, [_vp, C.c_double]),
     "amamg_hierarchy_derive_mass": (C.c_int, [_vp, C.c_double, C.POINTER(_vp)]),
     "amamg_hierarchy_destroy": (C.c_int, [_vp]),
+    "amamg_dense_solve": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _vp, _vp]),
     "amamg_solve": (C.c_int, [_vp, C.c_int32, _vp, _vp, _P(SolveParams), _P(SolveInfo)]),
     "amamg_solve_device": (C.c_int, [_vp, C.c_int32, _vp, _vp, _P(SolveParams), _P(SolveInfo), _vp]),
     "amamg_solve_multi_device": (C.c_int, [_P(_vp), C.c_int32, _P(C.c_int32), _P(_vp), _P(_vp), _P(SolveParams),
@@ -206,6 +207,15 @@ class Context:
     def set_tuning(self, mode: int, force: int = 0):
         """TUNE_AUTO (default), TUNE_OFF or TUNE_FORCE with candidate number `force`."""
         self.check(_lib.amamg_context_set_tuning(self.h, mode, force))
+
+    def dense_solve(self, aug: np.ndarray):
+        """The setup's batched dense solve on complex [nsys][n][n + nrhs] augmented matrices
+        (amamg_dense_solve): returns (the overwritten matrices, info per system)."""
+        a = np.ascontiguousarray(aug, dtype=np.complex128).copy()
+        nsys, n, ld = a.shape
+        info = np.zeros(nsys, dtype=np.int32)
+        self.check(_lib.amamg_dense_solve(self.h, n, ld - n, nsys, _ptr(a), _ptr(info)))
+        return a, info
 
     def tuning_entries(self) -> list:
         """The launch shapes tuned so far: dicts with kind, grid, b, precision, nrhs, choice and

@@ -955,6 +955,29 @@ amamg_status amamg_apply_dirac(amamg_gauge* g, int32_t precision, int32_t nrhs, 
   return AMAMG_OK;
 }
 
+amamg_status amamg_dense_solve(amamg_context* ctx, int32_t n, int32_t nrhs, int32_t nsys, double* aug,
+                               int32_t* info) {
+  if (!ctx) return AMAMG_ERR_INVALID_ARG;
+  if (!aug || !info || n < 1 || nrhs < 1 || nsys < 1)
+    return fail(ctx, {AMAMG_ERR_INVALID_ARG, "dense solve: null pointer or a size below 1"});
+  try {
+    HIPCHECK(hipSetDevice(ctx->device));
+    const size_t count = size_t(nsys) * n * (size_t(n) + nrhs);
+    Arena io;
+    double2* d = io.alloc<double2>(count);
+    int* di = io.alloc<int>(size_t(nsys) * kDenseSolveInts);
+    HIPCHECK(hipMemcpyAsync(d, aug, sizeof(double2) * count, hipMemcpyHostToDevice, ctx->stream));
+    dense_solve(ctx->stream, d, n, nrhs, nsys, di);
+    check_launch();
+    HIPCHECK(hipMemcpyAsync(aug, d, sizeof(double2) * count, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHECK(hipMemcpyAsync(info, di, sizeof(int) * nsys, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+  } catch (const Fail& f) {
+    return fail(ctx, f);
+  }
+  return AMAMG_OK;
+}
+
 amamg_status amamg_apply_dirac_device(amamg_gauge* g, int32_t precision, int32_t nrhs,
                                       const void* in_dev, void* out_dev) {
   if (!g || !in_dev || !out_dev || nrhs < 1)
