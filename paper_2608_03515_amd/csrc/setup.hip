@@ -208,26 +208,26 @@ __device__ __forceinline__ bool static_while(F&& f, std::integer_sequence<int, K
   return (f(std::integral_constant<int, K>{}) && ...);
 }
 
-// Panel k0 as lu_panel factors it (the same pivots and the same operations in the same order),
+// Panel k0 (width NB <= LU_NB) as lu_panel factors it (the same pivots and operations in order),
 // with the panel's rows k0 .. n - 1 in registers: thread t holds rows k0 + t + 256 s, s < S
 // (n - k0 <= 256 S, 256 threads).  A pivot step is one wave reduction and one barrier.  The
 // factored panel columns are written back; the interchanges (sm.perm) and the panel's unit
 // lower triangle (sm.L11) are left for lu_columns, which applies them to the columns right of
 // the panel.  Columns left of the panel (earlier L factors, which the solve never reads again)
 // are not interchanged.
-template <int S>
+template <int S, int NB = LU_NB>
 __device__ __forceinline__ bool lu_panel_reg(double2* __restrict__ M, int n, int ld, int k0, int sys,
                                              int* __restrict__ info, PanelSmem& sm) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int kb = min(LU_NB, n - k0), m = n - k0;
-  using Seq = std::make_integer_sequence<int, LU_NB>;
-  double2 P[S][LU_NB];
+  const int kb = min(NB, n - k0), m = n - k0;
+  using Seq = std::make_integer_sequence<int, NB>;
+  double2 P[S][NB];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int lr = tid + 256 * s;
     const double2* src = M + int64_t(k0 + (lr < m ? lr : 0)) * ld + k0;
 #pragma unroll
-    for (int q = 0; q < LU_NB; ++q) {
+    for (int q = 0; q < NB; ++q) {
       const double2 v = src[q < kb ? q : 0];
       const bool in = lr < m && q < kb;
       P[s][q] = make_double2(in ? v.x : 0.0, in ? v.y : 0.0);
@@ -265,7 +265,7 @@ __device__ __forceinline__ bool lu_panel_reg(double2* __restrict__ M, int n, int
     if (bi < n && tid == ((bi - k0) & 255)) {
       const int so = (bi - k0) >> 8;
 #pragma unroll
-      for (int q = 0; q < LU_NB; ++q) {
+      for (int q = 0; q < NB; ++q) {
         double2 v = P[0][q];
 #pragma unroll
         for (int s = 1; s < S; ++s) v = sel2(s == so, P[s][q], v);
@@ -274,7 +274,7 @@ __device__ __forceinline__ bool lu_panel_reg(double2* __restrict__ M, int n, int
     }
     if (tid == k)
 #pragma unroll
-      for (int q = 0; q < LU_NB; ++q) sm.krow[par][q] = P[0][q];
+      for (int q = 0; q < NB; ++q) sm.krow[par][q] = P[0][q];
     __syncthreads();
     double pmax = sm.sv[par][0];
     int p = sm.si[par][0], pw = 0;
@@ -294,15 +294,15 @@ __device__ __forceinline__ bool lu_panel_reg(double2* __restrict__ M, int n, int
       return false;
     }
     if (tid == 0) sm.perm[k] = p;
-    double2 prow[LU_NB];
+    double2 prow[NB];
 #pragma unroll
-    for (int q = k; q < LU_NB; ++q) prow[q] = sm.crow[par][pw][q];
+    for (int q = k; q < NB; ++q) prow[q] = sm.crow[par][pw][q];
     const int lp = p - k0;
     if (lp != k) {
       if (tid == (lp & 255)) {
         const int so = lp >> 8;
 #pragma unroll
-        for (int q = 0; q < LU_NB; ++q) {
+        for (int q = 0; q < NB; ++q) {
           const double2 v = sm.krow[par][q];
 #pragma unroll
           for (int s = 0; s < S; ++s) P[s][q] = sel2(s == so, v, P[s][q]);
@@ -310,7 +310,7 @@ __device__ __forceinline__ bool lu_panel_reg(double2* __restrict__ M, int n, int
       }
       if (tid == k)
 #pragma unroll
-        for (int q = 0; q < LU_NB; ++q) P[0][q] = sm.crow[par][pw][q];
+        for (int q = 0; q < NB; ++q) P[0][q] = sm.crow[par][pw][q];
     }
     const double2 akk = prow[k];
     const double den = cabs2(akk);
@@ -322,7 +322,7 @@ __device__ __forceinline__ bool lu_panel_reg(double2* __restrict__ M, int n, int
         const double2 l = cmul(P[s][k], inv);
         P[s][k] = l;
 #pragma unroll
-        for (int j = k + 1; j < LU_NB; ++j)
+        for (int j = k + 1; j < NB; ++j)
           if (j < kb) P[s][j] = csub(P[s][j], cmul(l, prow[j]));
       }
     }
@@ -334,12 +334,12 @@ __device__ __forceinline__ bool lu_panel_reg(double2* __restrict__ M, int n, int
     const int lr = tid + 256 * s;
     if (lr < m)
 #pragma unroll
-      for (int q = 0; q < LU_NB; ++q)
+      for (int q = 0; q < NB; ++q)
         if (q < kb) M[int64_t(k0 + lr) * ld + k0 + q] = P[s][q];
   }
   if (tid < kb)
 #pragma unroll
-    for (int q = 0; q < LU_NB; ++q) sm.L11[tid][q] = P[0][q];
+    for (int q = 0; q < NB; ++q) sm.L11[tid][q] = P[0][q];
   __syncthreads();
   return true;
 }
@@ -472,14 +472,14 @@ __global__ __launch_bounds__(256) void k_dense_solve(double2* __restrict__ A, in
 // panels run on one workgroup per system (in registers while n - k0 <= 1024, else in global
 // memory), the trailing updates and the back substitution on one workgroup per 64 x 64 tile
 // (bitwise the same operations as k_dense_solve).
-template <int S>
+template <int S, int NB = LU_NB>
 __global__ __launch_bounds__(256) void k_lu_panel(double2* __restrict__ A, int n, int ld, int k0,
                                                   int* __restrict__ info, int* __restrict__ piv) {
   const int sys = blockIdx.x;
   if (info[sys]) return;
   if constexpr (S > 0) {
     __shared__ PanelSmem psm;
-    if (lu_panel_reg<S>(A + int64_t(sys) * n * ld, n, ld, k0, sys, info, psm) && threadIdx.x < LU_NB)
+    if (lu_panel_reg<S, NB>(A + int64_t(sys) * n * ld, n, ld, k0, sys, info, psm) && threadIdx.x < NB)
       piv[sys * LU_NB + threadIdx.x] = psm.perm[threadIdx.x];
   } else {
     __shared__ double sv[256];
@@ -490,12 +490,11 @@ __global__ __launch_bounds__(256) void k_lu_panel(double2* __restrict__ A, int n
 
 // lu_columns of panel k0 for the columns blockIdx.x * 256 + t, one workgroup per 256 columns
 // (after k_lu_panel<S > 0>: L11 from the factored panel, the interchanges from piv)
-__global__ __launch_bounds__(256) void k_lu_cols(double2* __restrict__ A, int n, int ld, int k0,
+__global__ __launch_bounds__(256) void k_lu_cols(double2* __restrict__ A, int n, int ld, int k0, int kb,
                                                  const int* __restrict__ info, const int* __restrict__ piv) {
   const int sys = blockIdx.y;
   if (info[sys]) return;
   double2* M = A + int64_t(sys) * n * ld;
-  const int kb = min(LU_NB, n - k0);
   __shared__ double2 L11[LU_NB][LU_NB + 1];
   __shared__ int perm[LU_NB];
   {
@@ -771,17 +770,25 @@ void dense_solve(hipStream_t s, double2* Aug, int n, int nrhs, int nsys, int* in
     return;
   }
   hipLaunchKernelGGL(k_info_zero, dim3((nsys + 63) / 64), dim3(64), 0, s, info, nsys);
-  for (int k0 = 0; k0 < n; k0 += LU_NB) {
-    const int kb = min(LU_NB, n - k0);
-    switch ((n - k0 + 255) / 256) {
-      case 1: hipLaunchKernelGGL(k_lu_panel<1>, dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info, piv); break;
-      case 2: hipLaunchKernelGGL(k_lu_panel<2>, dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info, piv); break;
-      case 3: hipLaunchKernelGGL(k_lu_panel<3>, dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info, piv); break;
-      case 4: hipLaunchKernelGGL(k_lu_panel<4>, dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info, piv); break;
-      default: hipLaunchKernelGGL(k_lu_panel<0>, dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info, piv);
+  for (int k0 = 0; k0 < n;) {
+    // panel rows in registers: up to 1024 rows at width LU_NB, up to 2048 at width 8; beyond,
+    // in global memory
+    const int rem = n - k0;
+    const int kb = std::min(rem > 1024 && rem <= 2048 ? 8 : LU_NB, rem);
+    if (rem > 2048) {
+      hipLaunchKernelGGL(k_lu_panel<0>, dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info, piv);
+    } else if (rem > 1024) {
+      hipLaunchKernelGGL((k_lu_panel<8, 8>), dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info, piv);
+    } else {
+      switch ((rem + 255) / 256) {
+        case 1: hipLaunchKernelGGL(k_lu_panel<1>, dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info, piv); break;
+        case 2: hipLaunchKernelGGL(k_lu_panel<2>, dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info, piv); break;
+        case 3: hipLaunchKernelGGL(k_lu_panel<3>, dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info, piv); break;
+        default: hipLaunchKernelGGL(k_lu_panel<4>, dim3(nsys), dim3(256), 0, s, Aug, n, ld, k0, info, piv);
+      }
     }
-    if (n - k0 <= 1024 && k0 + kb < ld)
-      hipLaunchKernelGGL(k_lu_cols, dim3((ld - k0 - kb + 255) / 256, nsys), dim3(256), 0, s, Aug, n, ld, k0,
+    if (rem <= 2048 && k0 + kb < ld)
+      hipLaunchKernelGGL(k_lu_cols, dim3((ld - k0 - kb + 255) / 256, nsys), dim3(256), 0, s, Aug, n, ld, k0, kb,
                          (const int*)info, (const int*)piv);
     const int r0 = k0 + kb, c0 = k0 + kb;
     if (r0 < n) {
@@ -789,6 +796,7 @@ void dense_solve(hipStream_t s, double2* Aug, int n, int nrhs, int nsys, int* in
       hipLaunchKernelGGL(k_lu_tiles, dim3(tiles, nsys), dim3(256), 0, s, Aug, n, ld, r0, n, c0, ld, k0, k0, kb,
                          (const int*)info);
     }
+    k0 += kb;
   }
   const int last = ((n - 1) / LU_NB) * LU_NB;
   for (int k0 = last; k0 >= 0; k0 -= LU_NB) {

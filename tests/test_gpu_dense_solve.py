@@ -2,8 +2,9 @@
 the wirebasket interpolation and the exact coarsest-level inverse) against numpy.linalg.solve.
 
 Cases cover every launch path: one workgroup per system (n <= 64, or n <= 256 with 32 or more
-systems), and the panel / interchange / tile launches with the panel rows in registers for 1 to
-4 row groups and in global memory past 1024 rows; ragged last panels; matrices built so that a
+systems), and the panel / interchange / tile launches with the panel rows in registers (1 to 4
+row groups at width 16, 8 row groups at width 8) and in global memory past 2048 rows; ragged last
+panels; matrices built so that a
 row interchanged out of a panel is chosen again as a pivot in the same panel (the interchanges
 are applied to the other columns afterwards, in order); singular systems, which report their
 first zero pivot column without disturbing the other systems.  Bar: relative solution error
@@ -50,7 +51,8 @@ def ctx(lib):
     (200, 5, 3),       # panel launches, rows in one register group
     (600, 40, 2),      # three, two and one register groups
     (300, 7, 33),      # n > 256 with many systems: panel launches
-    (1100, 3, 1),      # panels in global memory while more than 1024 rows remain, then registers
+    (1100, 3, 1),      # panels of width 8 in registers while more than 1024 rows remain
+    (2100, 2, 1),      # panels in global memory past 2048 rows, then width 8, then width 16
 ])
 def test_batched_dense_solve_matches_numpy(lib, ctx, n, nrhs, nsys):
     say("dense solve", n, nrhs, nsys)
