@@ -298,14 +298,17 @@ __global__ __launch_bounds__(256) void k_prolong_tiled(
   }
 }
 
-// Matrix-core transfers (FP32, NCOL = 128 interpolation columns, 64 right-hand sides per
-// workgroup).  Per wirebasket the transfer is a dense complex product between the chunk's
+// Matrix-core transfers (FP32, NCOL = 128 interpolation columns, NR = 64 or 32 right-hand sides
+// per workgroup).  Per wirebasket the transfer is a dense complex product between the chunk's
 // interpolation rows and the right-hand sides; it runs as real 16x16x4 FP32 MFMA tiles
 // (v_mfma_f32_16x16x4f32: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
 // D[4 (l / 16) + i][l % 16], i < 4), four real products per complex one.  D is oriented with the
 // right-hand side as its row index, so a lane's results run along interpolation columns
 // (restriction) or fine rows (prolongation) and the stores are contiguous.  Wave w owns the
-// right-hand sides 16 w .. 16 w + 15 of the workgroup's group of 64.
+// right-hand sides 16 (w % (NR / 16)) .. + 15 of the workgroup's group and, with NR = 32, half of
+// the column (restriction) or row (prolongation) tiles.  Each result is one MFMA chain over the
+// same operands in the same order whatever NR, so batches of up to 32 right-hand sides (NR = 32,
+// no padding of a 64-wide tile) and larger ones give a right-hand side bitwise the same result.
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 __device__ inline mfma_f4 mfma16(float a, float b, mfma_f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -320,30 +323,31 @@ __host__ __device__ inline bool mfma_cols(int ncol) { return ncol == 128; }
 
 // Restriction pass 1 (same partial layout as k_restrict_partial):
 // D[rhs][col] = sum over the chunk's rows of r_rhs[row] conj(P[row][col]).
-template <int NCOL, int RCH, typename Vin>
+template <int NCOL, int RCH, typename Vin, int NR>
 __global__ __launch_bounds__(256) void k_restrict_mfma(
     const float2* __restrict__ P, const int* __restrict__ rows, const int* __restrict__ nrows, int maxrows,
     const Vin* __restrict__ rin, float2* __restrict__ part, int nW, int nchunk, int nrhs, int64_t stride_f,
     const RhsState* __restrict__ st) {
-  static_assert(RCH % 4 == 0 && NCOL % 16 == 0, "tile shape");
-  constexpr int RS = RCH + 1, PS = NCOL + 1, CT = NCOL / 16;
+  constexpr int WR = NR / 16, WS = 4 / WR;              // rhs tiles, column-tile splits
+  static_assert(RCH % 4 == 0 && NCOL % (16 * WS) == 0 && WR * WS == 4, "tile shape");
+  constexpr int RS = RCH + 1, PS = NCOL + 1, CT = NCOL / (16 * WS);
   __shared__ float2 Pl[RCH * PS];
-  __shared__ float2 Rl[kMfmaRhs * RS];
+  __shared__ float2 Rl[NR * RS];
   __shared__ int ri[RCH];
   const int bid = xcd_block(blockIdx.x, gridDim.x);
   const int w = bid / nchunk, chunk = bid - (bid / nchunk) * nchunk;
-  const int g0 = blockIdx.y * kMfmaRhs, ng = min(kMfmaRhs, nrhs - g0);
+  const int g0 = blockIdx.y * NR, ng = min(NR, nrhs - g0);
   const int r0 = chunk * RCH, cnt = max(0, min(nrows[w] - r0, RCH));
-  __shared__ int live[kMfmaRhs];
+  __shared__ int live[NR];
   for (int k = threadIdx.x; k < RCH; k += 256) ri[k] = k < cnt ? rows[int64_t(w) * maxrows + r0 + k] : 0;
-  for (int rr = threadIdx.x; rr < kMfmaRhs; rr += 256) live[rr] = rr < ng && (!st || st[g0 + rr].active);
+  for (int rr = threadIdx.x; rr < NR; rr += 256) live[rr] = rr < ng && (!st || st[g0 + rr].active);
   __syncthreads();
   // the fetches only load, from valid addresses (ri[k] = 0 past the chunk's rows, rhs 0 of the
   // group for dead ones); conversion and masking happen at the store, so that the loads of a
   // batch stay in flight together
   stage<8, 256, float2>(RCH * NCOL, [&](int q) { return P[int64_t(ri[q / NCOL]) * NCOL + q % NCOL]; },
                         [&](int q, float2 v) { Pl[(q / NCOL) * PS + q % NCOL] = q / NCOL < cnt ? v : make_float2(0.f, 0.f); });
-  stage<8, 256, Vin>(kMfmaRhs * RCH, [&](int q) {
+  stage<8, 256, Vin>(NR * RCH, [&](int q) {
     const int rr = q / RCH, k = q - (q / RCH) * RCH;
     return rin[(g0 + (live[rr] ? rr : 0)) * stride_f + ri[k]];
   }, [&](int q, Vin v) {
@@ -352,15 +356,16 @@ __global__ __launch_bounds__(256) void k_restrict_mfma(
   });
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+  const int rt = wv % WR, c0 = (wv / WR) * CT * 16;          // this wave's rhs tile, first column
   mfma_f4 re[CT], im[CT];
 #pragma unroll
   for (int t = 0; t < CT; ++t) re[t] = im[t] = mfma_f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
   for (int kk = 0; kk < RCH; kk += 4) {
-    const float2 a = Rl[(wv * 16 + lr) * RS + kk + lk];            // A[rhs][row] = r
+    const float2 a = Rl[(rt * 16 + lr) * RS + kk + lk];            // A[rhs][row] = r
 #pragma unroll
     for (int t = 0; t < CT; ++t) {
-      const float2 b = Pl[(kk + lk) * PS + t * 16 + lr];            // B[row][col] = P
+      const float2 b = Pl[(kk + lk) * PS + c0 + t * 16 + lr];       // B[row][col] = P
       re[t] = mfma16(a.x, b.x, re[t]);
       re[t] = mfma16(a.y, b.y, re[t]);
       im[t] = mfma16(a.y, b.x, im[t]);
@@ -369,9 +374,9 @@ __global__ __launch_bounds__(256) void k_restrict_mfma(
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int rr = wv * 16 + 4 * lk + i;
+    const int rr = rt * 16 + 4 * lk + i;
     if (live[rr]) {
-      float2* out = part + ((int64_t(g0 + rr) * nW + w) * nchunk + chunk) * NCOL + lr;
+      float2* out = part + ((int64_t(g0 + rr) * nW + w) * nchunk + chunk) * NCOL + c0 + lr;
 #pragma unroll
       for (int t = 0; t < CT; ++t) out[t * 16] = make_float2(re[t][i], im[t][i]);
     }
@@ -380,47 +385,49 @@ __global__ __launch_bounds__(256) void k_restrict_mfma(
 
 // Prolongation y = P e (add: y += P e): D[rhs][row] = sum_col e_rhs[col] P[row][col] over the
 // chunk's rows; chunk 0 also writes the vertex rows of node (I, J) (identity on corner 0).
-template <int NCOL, int RCH>
+template <int NCOL, int RCH, int NR>
 __global__ __launch_bounds__(256) void k_prolong_mfma(
     const float2* __restrict__ P, const int* __restrict__ rows, const int* __restrict__ nrows, int maxrows,
     const float2* __restrict__ e, float2* __restrict__ y, Geom g, int nchunk, int add, int nrhs,
     int64_t stride_f, int64_t stride_c, const RhsState* __restrict__ st) {
-  static_assert(RCH % 16 == 0 && NCOL % 4 == 0, "tile shape");
-  constexpr int PS = NCOL + 1, ES = NCOL + 1, RT = RCH / 16;
+  constexpr int WR = NR / 16, WS = 4 / WR;              // rhs tiles, row-tile splits
+  static_assert(RCH % (16 * WS) == 0 && NCOL % 4 == 0 && WR * WS == 4, "tile shape");
+  constexpr int PS = NCOL + 1, ES = NCOL + 1, RT = RCH / (16 * WS);
   __shared__ float2 Pl[RCH * PS];
-  __shared__ float2 El[kMfmaRhs * ES];
+  __shared__ float2 El[NR * ES];
   __shared__ int ri[RCH];
-  __shared__ int live[kMfmaRhs];
+  __shared__ int live[NR];
   const int bid = xcd_block(blockIdx.x, gridDim.x);
   const int w = bid / nchunk, chunk = bid - (bid / nchunk) * nchunk;
   const int I = w / g.nJ, J = w - (w / g.nJ) * g.nJ;
-  const int g0 = blockIdx.y * kMfmaRhs, ng = min(kMfmaRhs, nrhs - g0);
+  const int g0 = blockIdx.y * NR, ng = min(NR, nrhs - g0);
   const int r0 = chunk * RCH, cnt = max(0, min(nrows[w] - r0, RCH));
   const int nv_rows = chunk == 0 ? g.o * g.o * g.b : 0;
   for (int k = threadIdx.x; k < RCH; k += 256) ri[k] = k < cnt ? rows[int64_t(w) * maxrows + r0 + k] : 0;
-  for (int rr = threadIdx.x; rr < kMfmaRhs; rr += 256) live[rr] = rr < ng && (!st || st[g0 + rr].active);
+  for (int rr = threadIdx.x; rr < NR; rr += 256) live[rr] = rr < ng && (!st || st[g0 + rr].active);
   __syncthreads();
   stage<8, 256, float2>(RCH * NCOL, [&](int q) { return P[int64_t(ri[q / NCOL]) * NCOL + q % NCOL]; },
                         [&](int q, float2 v) { Pl[(q / NCOL) * PS + q % NCOL] = q / NCOL < cnt ? v : make_float2(0.f, 0.f); });
   int cn[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) cn[c] = ((I + (c >> 1)) % g.nI) * g.nJ + (J + (c & 1)) % g.nJ;
-  stage<8, 256, float2>(kMfmaRhs * NCOL, [&](int q) {
+  stage<8, 256, float2>(NR * NCOL, [&](int q) {
     const int rr = q / NCOL, col = q - (q / NCOL) * NCOL;
     const int c = col / g.bc, j = col - (col / g.bc) * g.bc;
     return e[(g0 + (rr < ng ? rr : 0)) * stride_c + int64_t(cn[c]) * g.bc + j];
   }, [&](int q, float2 v) { El[(q / NCOL) * ES + q % NCOL] = q / NCOL < ng ? v : make_float2(0.f, 0.f); });
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+  const int rt = wv % WR, k0 = (wv / WR) * RT * 16;           // this wave's rhs tile, first row
   mfma_f4 re[RT], im[RT];
 #pragma unroll
   for (int t = 0; t < RT; ++t) re[t] = im[t] = mfma_f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
   for (int kc = 0; kc < NCOL; kc += 4) {
-    const float2 a = El[(wv * 16 + lr) * ES + kc + lk];            // A[rhs][col] = e
+    const float2 a = El[(rt * 16 + lr) * ES + kc + lk];            // A[rhs][col] = e
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
-      const float2 b = Pl[(t * 16 + lr) * PS + kc + lk];            // B[col][row] = P[row][col]
+      const float2 b = Pl[(k0 + t * 16 + lr) * PS + kc + lk];       // B[col][row] = P[row][col]
       re[t] = mfma16(a.x, b.x, re[t]);
       re[t] = mfma16(-a.y, b.y, re[t]);
       im[t] = mfma16(a.x, b.y, im[t]);
@@ -429,12 +436,12 @@ __global__ __launch_bounds__(256) void k_prolong_mfma(
   }
 #pragma unroll
   for (int t = 0; t < RT; ++t) {
-    const int k = t * 16 + lr;
+    const int k = k0 + t * 16 + lr;
     if (k >= cnt) continue;
     const int row = ri[k];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int rr = wv * 16 + 4 * lk + i;
+      const int rr = rt * 16 + 4 * lk + i;
       if (!live[rr]) continue;
       float2* yr = y + (g0 + rr) * stride_f;
       float2 v = make_float2(re[t][i], im[t][i]);
@@ -632,8 +639,14 @@ static void prolong_mfma(hipStream_t s, const void* P, const int* rows, const in
                          int64_t stride_c, const RhsState* st) {
   constexpr int RCH = MfmaRows<NCOL>::PROLONG;
   const int nchunk = (maxrows + RCH - 1) / RCH;
+  if (nrhs <= 32) {
+    const dim3 grid(unsigned(g.nI * g.nJ * nchunk), 1);
+    AMAMG_LAUNCH((k_prolong_mfma<NCOL, RCH, 32>), grid, dim3(256), 0, s, (const float2*)P, rows, nrows, maxrows,
+                 (const float2*)e, (float2*)y, g, nchunk, add, nrhs, stride_f, stride_c, st);
+    return;
+  }
   const dim3 grid(unsigned(g.nI * g.nJ * nchunk), unsigned((nrhs + kMfmaRhs - 1) / kMfmaRhs));
-  AMAMG_LAUNCH((k_prolong_mfma<NCOL, RCH>), grid, dim3(256), 0, s, (const float2*)P, rows, nrows, maxrows,
+  AMAMG_LAUNCH((k_prolong_mfma<NCOL, RCH, kMfmaRhs>), grid, dim3(256), 0, s, (const float2*)P, rows, nrows, maxrows,
                (const float2*)e, (float2*)y, g, nchunk, add, nrhs, stride_f, stride_c, st);
 }
 
@@ -641,8 +654,14 @@ template <int NCOL, typename Vin>
 static void restrict_mfma(hipStream_t s, const void* P, const int* rows, const int* nrows, int maxrows,
                           const void* r, void* part, int nW, int nchunk, int nrhs, int64_t stride_f,
                           const RhsState* st) {
+  if (nrhs <= 32) {
+    hipLaunchKernelGGL((k_restrict_mfma<NCOL, MfmaRows<NCOL>::RESTRICT, Vin, 32>), dim3(unsigned(nW * nchunk), 1),
+                       dim3(256), 0, s, (const float2*)P, rows, nrows, maxrows, (const Vin*)r, (float2*)part, nW,
+                       nchunk, nrhs, stride_f, st);
+    return;
+  }
   const dim3 grid(unsigned(nW * nchunk), unsigned((nrhs + kMfmaRhs - 1) / kMfmaRhs));
-  hipLaunchKernelGGL((k_restrict_mfma<NCOL, MfmaRows<NCOL>::RESTRICT, Vin>), grid, dim3(256), 0, s,
+  hipLaunchKernelGGL((k_restrict_mfma<NCOL, MfmaRows<NCOL>::RESTRICT, Vin, kMfmaRhs>), grid, dim3(256), 0, s,
                      (const float2*)P, rows, nrows, maxrows, (const Vin*)r, (float2*)part, nW, nchunk, nrhs,
                      stride_f, st);
 }

@@ -673,9 +673,9 @@ def test_smoothers_match_oracle(lib, ctx, c4_oracle, a4o2_oracle, hier, nrhs):
 def test_transfers_match_oracle(lib, ctx, c4_oracle):
     """Restriction P^H and prolongation P of the 128^2 a = 8, o = 2 hierarchy (32 interpolation
     columns on the fine level: register tiles; 128 on level 1: the mixed V-cycle's matrix-core
-    tiles, 64 right-hand sides a workgroup) and of the 64^2 a = 4, o = 1 one (8 columns), FP64
+    tiles, 32 or 64 right-hand sides a workgroup) and of the 64^2 a = 4, o = 1 one (8 columns), FP64
     and FP32, for 1, 17, 64 and 70 right-hand sides (a partial tile, a full group, a second
-    group)."""
+    group); the two level-1 tile widths give a right-hand side bitwise the same result."""
     rng = np.random.default_rng(8080)
     U, m0, olev = c4_oracle
     g = make_gauge(lib, ctx, U, m0)
@@ -685,6 +685,16 @@ def test_transfers_match_oracle(lib, ctx, c4_oracle):
             for precision in (lib.FP64, lib.MIXED_FP32):
                 say("transfer C4", level, nrhs, precision)
                 _transfer_case(lib, h, olev, level, rng, nrhs, precision)
+    # level 1 in FP32: up to 32 right-hand sides run 32-wide matrix-core tiles, more run 64-wide
+    # ones; each result is the same MFMA chain in the same order, so bitwise the same
+    say("transfer C4 level 1, 32- against 64-wide tiles")
+    n, nc = olev[1].P.shape
+    d = rng.standard_normal((64, n)) + 1j * rng.standard_normal((64, n))
+    e = rng.standard_normal((64, nc)) + 1j * rng.standard_normal((64, nc))
+    for direction, v in ((0, d), (1, e)):
+        wide = h.transfer(1, v, direction, lib.MIXED_FP32)
+        for lo, hi in ((0, 17), (17, 49), (40, 64)):
+            assert np.array_equal(h.transfer(1, v[lo:hi], direction, lib.MIXED_FP32), wide[lo:hi]), (direction, lo)
     h.close()
     g.close()
     w = synth.WORKLOADS["C2"]
