@@ -567,22 +567,25 @@ __global__ __launch_bounds__(256) void k_stencil_gs_quad_mfma(const float2* __re
 // y = Ainv v for the coarsest level on FP64 matrix cores: a dense complex product of the
 // inverse with the right-hand sides, D[rhs][row] = sum_k v_rhs[k] Ainv[row][k], as real
 // v_mfma_f64_16x16x4f64 tiles (lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
-// D[4 i + l / 16][l % 16], i < 4).  A workgroup owns 16 right-hand sides x 16 rows; its four
-// waves take a quarter of k each (a multiple of 4; padding contributes zeros) and the quarters
-// are added in order through LDS.  The inverse is read once per 16 right-hand sides.  A single
-// right-hand side pads its tile (about 3 % slower there than a vector kernel), which keeps each
+// D[4 i + l / 16][l % 16], i < 4).  A workgroup owns 16 right-hand sides x 16 rows; its
+// kDenseWaves waves take a slice of k each (a multiple of 4; padding contributes zeros) and the
+// slices are added in order through LDS.  The product is latency-bound at these sizes (the
+// 512 x 512 inverse is 4 MB): 16 slices keep every wave's loads in one batch in flight and put
+// 16 times more waves on the chip than a workgroup per tile with one wave.  The inverse is read
+// once per 16 right-hand sides.  A single right-hand side pads its tile, which keeps each
 // right-hand side's arithmetic the same in every batch.
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 __device__ inline mfma_d4 mfma_f64(double a, double b, mfma_d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+constexpr int kDenseWaves = 16;
 
 template <typename Vin, typename Vout>
-__global__ __launch_bounds__(256) void k_dense_apply_mfma(const double2* __restrict__ Ainv,
-                                                          const Vin* __restrict__ v, Vout* __restrict__ y,
-                                                          int n, int nrhs, int64_t stride,
-                                                          const RhsState* __restrict__ st) {
-  __shared__ double2 red[4][256];
+__global__ __launch_bounds__(64 * kDenseWaves) void k_dense_apply_mfma(const double2* __restrict__ Ainv,
+                                                                      const Vin* __restrict__ v, Vout* __restrict__ y,
+                                                                      int n, int nrhs, int64_t stride,
+                                                                      const RhsState* __restrict__ st) {
+  __shared__ double2 red[kDenseWaves][256];
   __shared__ int live[16];                                 // the 16 rhs' flags, for the stores
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
   const int row0 = blockIdx.x * 16, r0 = blockIdx.y * 16;
@@ -591,18 +594,18 @@ __global__ __launch_bounds__(256) void k_dense_apply_mfma(const double2* __restr
   if (threadIdx.x < 16) live[threadIdx.x] = alive;
   const int rb = row0 + lr;                                // row of this lane's B values
   const bool blive = rb < n;
-  const int kq = (((n + 3) / 4 + 3) / 4) * 4;              // k per wave
-  const int k0 = wv * kq, k1 = min(n, k0 + kq);
+  const int kq = (((n + 3) / 4 + kDenseWaves - 1) / kDenseWaves) * 4;   // k per wave
+  const int k0 = min(n, wv * kq), k1 = min(n, k0 + kq);
   const Vin* va = v + int64_t(alive ? ra : 0) * stride;
   const double2* Ab = Ainv + int64_t(blive ? rb : 0) * n;
   mfma_d4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
-#pragma unroll 4
+#pragma unroll 8
   for (int kk = k0; kk < k1; kk += 4) {
     const int k = kk + lk;
     const bool kin = k < k1;
     // unconditional loads from valid addresses, then selects: no branch separates the loads
-    const Vin av = va[kin ? k : k0];
-    const double2 bv = Ab[kin ? k : k0];
+    const Vin av = va[kin ? k : 0];
+    const double2 bv = Ab[kin ? k : 0];
     const double2 a = alive && kin ? cconv<double2>(av) : make_double2(0, 0);
     const double2 b = blive && kin ? bv : make_double2(0, 0);
     re = mfma_f64(a.x, b.x, re);
@@ -613,14 +616,13 @@ __global__ __launch_bounds__(256) void k_dense_apply_mfma(const double2* __restr
 #pragma unroll
   for (int i = 0; i < 4; ++i) red[wv][i * 64 + lane] = make_double2(re[i], im[i]);
   __syncthreads();
-  if (wv != 0) return;
+  if (wv >= 4) return;
+  const int i = wv;                                        // wave i adds the slices of D's rows 4 i + l / 16
+  double2 acc = red[0][i * 64 + lane];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    double2 acc = red[0][i * 64 + lane];
-    for (int q = 1; q < 4; ++q) acc = cadd(acc, red[q][i * 64 + lane]);
-    const int r = r0 + 4 * i + lk, row = row0 + lr;
-    if (live[4 * i + lk] && row < n) y[r * stride + row] = cconv<Vout>(acc);
-  }
+  for (int q = 1; q < kDenseWaves; ++q) acc = cadd(acc, red[q][i * 64 + lane]);
+  const int r = r0 + 4 * i + lk, row = row0 + lr;
+  if (live[4 * i + lk] && row < n) y[r * stride + row] = cconv<Vout>(acc);
 }
 
 // Unpreconditioned GMRES from x = 0 on the coarsest level (the paper's coarsest-level solver,
@@ -1019,10 +1021,10 @@ void dense_apply(hipStream_t s, Real prec, const double2* Ainv, const void* v, v
   // one kernel for every batch size: a right-hand side's result must not depend on the batch
   const dim3 g(unsigned((n + 15) / 16), unsigned((nrhs + 15) / 16));
   if (prec == F64)
-    hipLaunchKernelGGL((k_dense_apply_mfma<double2, double2>), g, dim3(256), 0, s, Ainv,
+    hipLaunchKernelGGL((k_dense_apply_mfma<double2, double2>), g, dim3(64 * kDenseWaves), 0, s, Ainv,
                        (const double2*)v, (double2*)y, n, nrhs, stride, st);
   else
-    hipLaunchKernelGGL((k_dense_apply_mfma<float2, float2>), g, dim3(256), 0, s, Ainv,
+    hipLaunchKernelGGL((k_dense_apply_mfma<float2, float2>), g, dim3(64 * kDenseWaves), 0, s, Ainv,
                        (const float2*)v, (float2*)y, n, nrhs, stride, st);
 }
 

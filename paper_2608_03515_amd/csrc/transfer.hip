@@ -298,6 +298,154 @@ __global__ __launch_bounds__(256) void k_prolong_tiled(
   }
 }
 
+// Transfers of a few right-hand sides (up to kRowsRhs) on the levels served by the tiled
+// kernels.  The tiled kernels stage interpolation rows in LDS for passes of 16 or 32 right-hand
+// sides; with one right-hand side most of their lanes idle while each chunk pays the staging's
+// round trips.  These read the interpolation straight into registers, one thread per output
+// value, and repeat the tiled kernels' arithmetic exactly: the same conversions and the same
+// multiply-add chains in the same order (prolongation: over a row's columns; restriction: over
+// the rows of a chunk of the same length), so a right-hand side gets bitwise the same result in
+// every batch.
+constexpr int kRowsRhs = 4;
+
+// one interpolation row into registers, converted to the compute type; FP32 rows are read as
+// 16-byte pairs (rows are NCOL * 8 bytes long, NCOL even, and start 16-byte aligned)
+template <int NCOL, typename C>
+__device__ inline void load_row(const double2* __restrict__ p, C (&out)[NCOL]) {
+  double2 v[NCOL];
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) v[c] = p[c];
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) out[c] = cconv<C>(v[c]);
+}
+template <int NCOL, typename C>
+__device__ inline void load_row(const float2* __restrict__ p, C (&out)[NCOL]) {
+  static_assert(NCOL % 2 == 0, "rows of float pairs");
+  float4 v[NCOL / 2];
+  const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+  for (int c = 0; c < NCOL / 2; ++c) v[c] = q[c];
+#pragma unroll
+  for (int c = 0; c < NCOL / 2; ++c) {
+    out[2 * c] = cconv<C>(make_float2(v[c].x, v[c].y));
+    out[2 * c + 1] = cconv<C>(make_float2(v[c].z, v[c].w));
+  }
+}
+
+// Prolongation, one wave per (wirebasket W, chunk of 64 owned rows): lane k holds row k's
+// interpolation and serves the right-hand sides in turn; the coarse values of W's corners are
+// staged once in LDS.  Chunk 0 also writes the vertex rows of node (I, J) (identity on corner 0).
+template <int NCOL, typename R, typename M, typename Vin, typename Vout>
+__global__ __launch_bounds__(64) void k_prolong_rows(
+    const M* __restrict__ P, const int* __restrict__ rows, const int* __restrict__ nrows, int maxrows,
+    const Vin* __restrict__ e, Vout* __restrict__ y, Geom g, int nchunk, int add, int nrhs,
+    int64_t stride_f, int64_t stride_c, const RhsState* __restrict__ st) {
+  using C = cplx<R>;
+  __shared__ C El[kRowsRhs * NCOL];
+  __shared__ int live[kRowsRhs];
+  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  const int w = bid / nchunk, chunk = bid - (bid / nchunk) * nchunk;
+  const int I = w / g.nJ, J = w - (w / g.nJ) * g.nJ;
+  const int k = chunk * 64 + int(threadIdx.x);
+  const bool own = k < nrows[w];
+  const int row = own ? rows[int64_t(w) * maxrows + k] : 0;
+  C pr[NCOL];
+  load_row<NCOL>(P + int64_t(row) * NCOL, pr);
+  int cn[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) cn[c] = ((I + (c >> 1)) % g.nI) * g.nJ + (J + (c & 1)) % g.nJ;
+  for (int q = threadIdx.x; q < kRowsRhs * NCOL; q += 64) {
+    const int rr = q / NCOL, col = q % NCOL;
+    const int c = col / g.bc, j = col - (col / g.bc) * g.bc;
+    const Vin v = e[(rr < nrhs ? rr : 0) * stride_c + int64_t(cn[c]) * g.bc + j];
+    El[q] = rr < nrhs ? cconv<C>(v) : czero<R>();
+  }
+  if (threadIdx.x < kRowsRhs) live[threadIdx.x] = int(threadIdx.x) < nrhs && (!st || st[threadIdx.x].active);
+  __syncthreads();
+  if (own)
+    for (int rr = 0; rr < nrhs; ++rr) {
+      if (!live[rr]) continue;
+      C acc = czero<R>();
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) acc = cfma(pr[c], El[rr * NCOL + c], acc);
+      Vout* yr = y + rr * stride_f;
+      if (add) acc = cadd(acc, cconv<C>(yr[row]));
+      yr[row] = cconv<Vout>(acc);
+    }
+  const int nv_rows = chunk == 0 ? g.o * g.o * g.b : 0;
+  for (int q = threadIdx.x; q < nrhs * nv_rows; q += 64) {
+    const int rr = q / nv_rows, v = q - rr * nv_rows;      // (pt*o + px)*b + qq of node (I, J)
+    if (!live[rr]) continue;
+    const int qq = v % g.b, pp = v / g.b;
+    const int pt = pp / g.o, px = pp - (pp / g.o) * g.o;
+    const int64_t vrow = int64_t((g.a * I + pt) * g.Lx + (g.a * J + px)) * g.b + qq;
+    C acc = El[rr * NCOL + v];
+    Vout* yr = y + rr * stride_f;
+    if (add) acc = cadd(acc, cconv<C>(yr[vrow]));
+    yr[vrow] = cconv<Vout>(acc);
+  }
+}
+
+// Restriction pass 1 (same partial layout and chunks as k_restrict_partial_tiled): thread
+// (chunk, col) accumulates conj(P[k][col]) r[k] over the chunk's RCH rows for NS right-hand
+// sides; a workgroup serves 8 chunks.  The chunks' row indices and r values are staged in LDS
+// while the interpolation values load into registers.
+constexpr int kRowsChunks = 8;
+template <int NCOL, int RCH, int NS, typename R, typename M, typename Vin>
+__global__ __launch_bounds__(kRowsChunks * NCOL) void k_restrict_rows(
+    const M* __restrict__ P, const int* __restrict__ rows, const int* __restrict__ nrows, int maxrows,
+    const Vin* __restrict__ rin, cplx<R>* __restrict__ part, int nW, int nchunk, int nrhs,
+    int64_t stride_f, const RhsState* __restrict__ st) {
+  using C = cplx<R>;
+  constexpr int CPB = kRowsChunks, NT = CPB * NCOL;        // chunks per workgroup, threads
+  __shared__ int ri[CPB * RCH];
+  __shared__ C Rl[NS * CPB * RCH];
+  __shared__ int cnts[CPB];
+  const int npair = nW * nchunk, gc0 = blockIdx.x * CPB;
+  if (threadIdx.x < CPB) {
+    const int gc = gc0 + int(threadIdx.x);
+    const int w = gc / nchunk, r0 = (gc - w * nchunk) * RCH;
+    cnts[threadIdx.x] = gc < npair ? max(0, min(nrows[w] - r0, RCH)) : 0;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < CPB * RCH; q += NT) {
+    const int cb = q / RCH, k = q - cb * RCH, gc = gc0 + cb;
+    const int w = gc / nchunk, r0 = (gc - w * nchunk) * RCH;
+    ri[q] = k < cnts[cb] ? rows[int64_t(w) * maxrows + r0 + k] : 0;
+  }
+  __syncthreads();
+  const int cb = threadIdx.x / NCOL, col = threadIdx.x % NCOL;
+  const int gc = gc0 + cb, cnt = cnts[cb];
+  M pv[RCH];
+#pragma unroll
+  for (int k = 0; k < RCH; ++k) pv[k] = P[int64_t(ri[cb * RCH + k]) * NCOL + col];
+  // r values of the workgroup's rows (the fetch only loads; masking happens at the store)
+  for (int q = threadIdx.x; q < NS * CPB * RCH; q += NT) {
+    const int rr = q / (CPB * RCH), kq = q - rr * (CPB * RCH);
+    const bool lv = rr < nrhs && (!st || st[rr].active);
+    const Vin v = rin[(lv ? rr : 0) * stride_f + ri[kq]];
+    Rl[q] = lv ? cconv<C>(v) : czero<R>();
+  }
+  __syncthreads();
+  if (gc >= npair) return;
+  const int w = gc / nchunk, chunk = gc - w * nchunk;
+  C acc[NS];
+#pragma unroll
+  for (int rr = 0; rr < NS; ++rr) acc[rr] = czero<R>();
+#pragma unroll
+  for (int k = 0; k < RCH; ++k) {
+    if (k < cnt) {
+      const C pk = cconv<C>(pv[k]);
+#pragma unroll
+      for (int rr = 0; rr < NS; ++rr) acc[rr] = cfmac(pk, Rl[rr * CPB * RCH + cb * RCH + k], acc[rr]);
+    }
+  }
+#pragma unroll
+  for (int rr = 0; rr < NS; ++rr)
+    if (rr < nrhs && (!st || st[rr].active))
+      part[((int64_t(rr) * nW + w) * nchunk + chunk) * NCOL + col] = acc[rr];
+}
+
 // Matrix-core transfers (FP32, NCOL = 128 interpolation columns, NR = 64 or 32 right-hand sides
 // per workgroup).  Per wirebasket the transfer is a dense complex product between the chunk's
 // interpolation rows and the right-hand sides; it runs as real 16x16x4 FP32 MFMA tiles
@@ -624,9 +772,23 @@ int restrict_chunks(const Geom& g, int nf, Real prec) {
 }
 
 template <int NCOL, typename R, typename M, typename V>
+static void prolong_rows(hipStream_t s, const void* P, const int* rows, const int* nrows, int maxrows,
+                         const void* e, void* y, const Geom& g, int add, int nrhs, int64_t stride_f,
+                         int64_t stride_c, const RhsState* st) {
+  const int nchunk = (maxrows + 63) / 64;
+  AMAMG_LAUNCH((k_prolong_rows<NCOL, R, M, V, V>), dim3(unsigned(g.nI * g.nJ * nchunk)), dim3(64), 0, s,
+               (const M*)P, rows, nrows, maxrows, (const V*)e, (V*)y, g, nchunk, add, nrhs, stride_f,
+               stride_c, st);
+}
+
+template <int NCOL, typename R, typename M, typename V>
 static void prolong_tiled(hipStream_t s, const void* P, const int* rows, const int* nrows, int maxrows,
                           const void* e, void* y, const Geom& g, int add, int nrhs, int64_t stride_f,
                           int64_t stride_c, const RhsState* st) {
+  if (nrhs <= kRowsRhs) {
+    prolong_rows<NCOL, R, M, V>(s, P, rows, nrows, maxrows, e, y, g, add, nrhs, stride_f, stride_c, st);
+    return;
+  }
   const int nchunk = (maxrows + TiledRows<R, NCOL>::PROLONG - 1) / TiledRows<R, NCOL>::PROLONG;
   AMAMG_LAUNCH((k_prolong_tiled<NCOL, TiledRows<R, NCOL>::PROLONG, TiledRows<R, NCOL>::RHS_P, R, M, V, V>), dim3(unsigned(g.nI * g.nJ * nchunk)), dim3(256), 0, s,
                (const M*)P, rows, nrows, maxrows, (const V*)e, (V*)y, g, nchunk, add, nrhs, stride_f,
@@ -667,9 +829,27 @@ static void restrict_mfma(hipStream_t s, const void* P, const int* rows, const i
 }
 
 template <int NCOL, typename R, typename M, typename Vin>
+static void restrict_rows(hipStream_t s, const void* P, const int* rows, const int* nrows, int maxrows,
+                          const void* r, void* part, int nW, int nchunk, int nrhs, int64_t stride_f,
+                          const RhsState* st) {
+  constexpr int RCH = TiledRows<R, NCOL>::RESTRICT;
+  const dim3 grid(unsigned((nW * nchunk + kRowsChunks - 1) / kRowsChunks)), block(kRowsChunks * NCOL);
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_restrict_rows<NCOL, RCH, 1, R, M, Vin>), grid, block, 0, s, (const M*)P, rows, nrows,
+                       maxrows, (const Vin*)r, (cplx<R>*)part, nW, nchunk, nrhs, stride_f, st);
+  else
+    hipLaunchKernelGGL((k_restrict_rows<NCOL, RCH, kRowsRhs, R, M, Vin>), grid, block, 0, s, (const M*)P, rows,
+                       nrows, maxrows, (const Vin*)r, (cplx<R>*)part, nW, nchunk, nrhs, stride_f, st);
+}
+
+template <int NCOL, typename R, typename M, typename Vin>
 static void restrict_tiled(hipStream_t s, const void* P, const int* rows, const int* nrows, int maxrows,
                            const void* r, void* part, int nW, int nchunk, int nrhs, int64_t stride_f,
                            const RhsState* st) {
+  if (nrhs <= kRowsRhs) {
+    restrict_rows<NCOL, R, M, Vin>(s, P, rows, nrows, maxrows, r, part, nW, nchunk, nrhs, stride_f, st);
+    return;
+  }
   hipLaunchKernelGGL((k_restrict_partial_tiled<NCOL, TiledRows<R, NCOL>::RESTRICT, TiledRows<R, NCOL>::RHS_R, R, M, Vin>), dim3(unsigned(nW * nchunk)), dim3(256), 0,
                      s, (const M*)P, rows, nrows, maxrows, (const Vin*)r, (cplx<R>*)part, nW, nchunk, nrhs,
                      stride_f, st);
