@@ -98,7 +98,8 @@ __global__ __launch_bounds__(256) void k_restrict_partial(const M* __restrict__ 
 
 // Prolongation y = P e (add: y += P e) for every right-hand side.  Workgroup (W, chunk) writes
 // the chunk's owned rows of W; chunk 0 also writes the vertex rows of node (I, J) of W, which
-// are the identity on corner 0 of W.
+// are the identity on corner 0 of W.  A row's sum runs as one chain per corner node, the four
+// added in corner order (the order k_prolong_corner4 keeps).
 template <typename R, typename M, typename Vin, typename Vout>
 __global__ __launch_bounds__(256) void k_prolong(const M* __restrict__ P,
                                                  const int* __restrict__ rows,
@@ -142,9 +143,13 @@ __global__ __launch_bounds__(256) void k_prolong(const M* __restrict__ P,
       C acc;
       int64_t row;
       if (k < cnt) {
-        acc = czero<R>();
+        // one chain per corner (columns c bc .. c bc + bc - 1), the four added in corner order
         const C* El_r = El + rr * ncol;
-        for (int col = 0; col < ncol; ++col) acc = cfma(Pl[k * pld + col], El_r[col], acc);
+        for (int c = 0; c < 4; ++c) {
+          C pc = czero<R>();
+          for (int j = c * g.bc; j < (c + 1) * g.bc; ++j) pc = cfma(Pl[k * pld + j], El_r[j], pc);
+          acc = c == 0 ? pc : cadd(acc, pc);
+        }
         row = ri[k];
       } else {
         const int v = k - cnt;                       // (pt*o + px)*b + q of node (I, J)
@@ -374,6 +379,78 @@ __global__ __launch_bounds__(64) void k_prolong_rows(
     }
   const int nv_rows = chunk == 0 ? g.o * g.o * g.b : 0;
   for (int q = threadIdx.x; q < nrhs * nv_rows; q += 64) {
+    const int rr = q / nv_rows, v = q - rr * nv_rows;      // (pt*o + px)*b + qq of node (I, J)
+    if (!live[rr]) continue;
+    const int qq = v % g.b, pp = v / g.b;
+    const int pt = pp / g.o, px = pp - (pp / g.o) * g.o;
+    const int64_t vrow = int64_t((g.a * I + pt) * g.Lx + (g.a * J + px)) * g.b + qq;
+    C acc = El[rr * NCOL + v];
+    Vout* yr = y + rr * stride_f;
+    if (add) acc = cadd(acc, cconv<C>(yr[vrow]));
+    yr[vrow] = cconv<Vout>(acc);
+  }
+}
+
+// Prolongation of up to kRowsRhs right-hand sides for the generic kernel's levels with BC
+// degrees of freedom per corner node (128 interpolation columns: level 1 of a = 8, o = 2 in
+// FP64).  Four lanes per row, one per corner node: lane c keeps the row's BC values of corner c
+// in registers and runs k_prolong's chain for that corner; lane 0 of the four adds the four
+// chains in corner order.  Workgroup (W, chunk of 64 owned rows); chunk 0 also writes the vertex
+// rows of node (I, J).
+template <int BC, typename R, typename M, typename Vin, typename Vout>
+__global__ __launch_bounds__(256) void k_prolong_corner4(
+    const M* __restrict__ P, const int* __restrict__ rows, const int* __restrict__ nrows, int maxrows,
+    const Vin* __restrict__ e, Vout* __restrict__ y, Geom g, int nchunk, int add, int nrhs,
+    int64_t stride_f, int64_t stride_c, const RhsState* __restrict__ st) {
+  using C = cplx<R>;
+  constexpr int NCOL = 4 * BC;
+  __shared__ C El[kRowsRhs * NCOL];
+  __shared__ int live[kRowsRhs];
+  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  const int w = bid / nchunk, chunk = bid - (bid / nchunk) * nchunk;
+  const int I = w / g.nJ, J = w - (w / g.nJ) * g.nJ;
+  const int c = threadIdx.x & 3, k = chunk * 64 + int(threadIdx.x >> 2);
+  const bool own = k < nrows[w];
+  const int row = own ? rows[int64_t(w) * maxrows + k] : 0;
+  C pr[BC];
+  {
+    M v[BC];
+    const M* pc = P + int64_t(row) * NCOL + c * BC;
+#pragma unroll
+    for (int j = 0; j < BC; ++j) v[j] = pc[j];
+#pragma unroll
+    for (int j = 0; j < BC; ++j) pr[j] = cconv<C>(v[j]);
+  }
+  int cn[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) cn[q] = ((I + (q >> 1)) % g.nI) * g.nJ + (J + (q & 1)) % g.nJ;
+  for (int q = threadIdx.x; q < kRowsRhs * NCOL; q += 256) {
+    const int rr = q / NCOL, col = q % NCOL;
+    const int cc = col / BC, j = col - cc * BC;
+    const Vin v = e[(rr < nrhs ? rr : 0) * stride_c + int64_t(cn[cc]) * BC + j];
+    El[q] = rr < nrhs ? cconv<C>(v) : czero<R>();
+  }
+  if (threadIdx.x < kRowsRhs) live[threadIdx.x] = int(threadIdx.x) < nrhs && (!st || st[threadIdx.x].active);
+  __syncthreads();
+  for (int rr = 0; rr < nrhs; ++rr) {
+    if (!live[rr]) continue;                                 // uniform over the workgroup
+    C pc = czero<R>();
+#pragma unroll
+    for (int j = 0; j < BC; ++j) pc = cfma(pr[j], El[rr * NCOL + c * BC + j], pc);
+    const int l0 = threadIdx.x & 63 & ~3;
+    C q1, q2, q3;
+    q1.x = __shfl(pc.x, l0 + 1); q1.y = __shfl(pc.y, l0 + 1);
+    q2.x = __shfl(pc.x, l0 + 2); q2.y = __shfl(pc.y, l0 + 2);
+    q3.x = __shfl(pc.x, l0 + 3); q3.y = __shfl(pc.y, l0 + 3);
+    if (c == 0 && own) {
+      C acc = cadd(cadd(cadd(pc, q1), q2), q3);
+      Vout* yr = y + rr * stride_f;
+      if (add) acc = cadd(acc, cconv<C>(yr[row]));
+      yr[row] = cconv<Vout>(acc);
+    }
+  }
+  const int nv_rows = chunk == 0 ? g.o * g.o * g.b : 0;
+  for (int q = threadIdx.x; q < nrhs * nv_rows; q += 256) {
     const int rr = q / nv_rows, v = q - rr * nv_rows;      // (pt*o + px)*b + qq of node (I, J)
     if (!live[rr]) continue;
     const int qq = v % g.b, pp = v / g.b;
@@ -828,11 +905,10 @@ static void restrict_mfma(hipStream_t s, const void* P, const int* rows, const i
                      stride_f, st);
 }
 
-template <int NCOL, typename R, typename M, typename Vin>
+template <int NCOL, int RCH, typename R, typename M, typename Vin>
 static void restrict_rows(hipStream_t s, const void* P, const int* rows, const int* nrows, int maxrows,
                           const void* r, void* part, int nW, int nchunk, int nrhs, int64_t stride_f,
                           const RhsState* st) {
-  constexpr int RCH = TiledRows<R, NCOL>::RESTRICT;
   const dim3 grid(unsigned((nW * nchunk + kRowsChunks - 1) / kRowsChunks)), block(kRowsChunks * NCOL);
   if (nrhs == 1)
     hipLaunchKernelGGL((k_restrict_rows<NCOL, RCH, 1, R, M, Vin>), grid, block, 0, s, (const M*)P, rows, nrows,
@@ -847,7 +923,8 @@ static void restrict_tiled(hipStream_t s, const void* P, const int* rows, const 
                            const void* r, void* part, int nW, int nchunk, int nrhs, int64_t stride_f,
                            const RhsState* st) {
   if (nrhs <= kRowsRhs) {
-    restrict_rows<NCOL, R, M, Vin>(s, P, rows, nrows, maxrows, r, part, nW, nchunk, nrhs, stride_f, st);
+    restrict_rows<NCOL, TiledRows<R, NCOL>::RESTRICT, R, M, Vin>(s, P, rows, nrows, maxrows, r, part, nW, nchunk,
+                                                                nrhs, stride_f, st);
     return;
   }
   hipLaunchKernelGGL((k_restrict_partial_tiled<NCOL, TiledRows<R, NCOL>::RESTRICT, TiledRows<R, NCOL>::RHS_R, R, M, Vin>), dim3(unsigned(nW * nchunk)), dim3(256), 0,
@@ -878,6 +955,13 @@ void prolong(hipStream_t s, Real prec, const void* P, const int* rows, const int
   if (g.ncol() == 8) {
     if (prec == F64) prolong_tiled<8, double, double2, double2>(s, P, rows, nrows, maxrows, e, y, g, add, nrhs, stride_f, stride_c, st);
     else prolong_tiled<8, float, float2, float2>(s, P, rows, nrows, maxrows, e, y, g, add, nrhs, stride_f, stride_c, st);
+    return;
+  }
+  if (prec == F64 && g.bc == 32 && nrhs <= kRowsRhs) {
+    const int nchunk = (maxrows + 63) / 64;
+    AMAMG_LAUNCH((k_prolong_corner4<32, double, double2, double2, double2>), dim3(unsigned(g.nI * g.nJ * nchunk)),
+                 dim3(256), 0, s, (const double2*)P, rows, nrows, maxrows, (const double2*)e, (double2*)y, g, nchunk,
+                 add, nrhs, stride_f, stride_c, st);
     return;
   }
   const TileShape ts = tile_shape(g.ncol(), cs, nf * g.b);
@@ -944,9 +1028,14 @@ void restrict_(hipStream_t s, Real prec, const void* P, const int* rows, const i
     return;
   }
   if (prec == F64) {
-    hipLaunchKernelGGL((k_restrict_partial<double, double2, double2>), g1, dim3(256), sm, s,
-                       (const double2*)P, rows, nrows, maxrows, (const double2*)r, (double2*)part, g,
-                       ts, nrhs, stride_f, st);
+    // level 1 of a = 8, o = 2: 128 columns in chunks of 8 rows
+    if (g.ncol() == 128 && ts.rch == 8 && nrhs <= kRowsRhs)
+      restrict_rows<128, 8, double, double2, double2>(s, P, rows, nrows, maxrows, r, part, nW, ts.nchunk, nrhs,
+                                                      stride_f, st);
+    else
+      hipLaunchKernelGGL((k_restrict_partial<double, double2, double2>), g1, dim3(256), sm, s,
+                         (const double2*)P, rows, nrows, maxrows, (const double2*)r, (double2*)part, g,
+                         ts, nrhs, stride_f, st);
     hipLaunchKernelGGL((k_restrict_gather<double, double2, double2>), g2, dim3(256), 0, s,
                        (const double2*)part, (const double2*)r, (double2*)rc, g, ts.nchunk, lanes,
                        stride_f, stride_c, st);
