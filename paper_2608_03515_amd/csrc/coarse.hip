@@ -423,6 +423,83 @@ __global__ __launch_bounds__(256) void k_stencil_gs_quad_mr(const M* __restrict_
   }
 }
 
+// One colour block qb of the coarse sweep for B = 8, one wave per node: a workgroup takes one
+// 2 x 2 group and one right-hand side, wave v node v of the group in sweep order (I0, J0),
+// (I0, J0 + 1), (I0 + 1, J0), (I0 + 1, J0 + 1).  Every wave loads its node's 24 stencil blocks,
+// the inverse diagonal block and the neighbour values that this launch does not change before
+// the first barrier; then the nodes update in order, one per phase, each taking the earlier
+// nodes' new values (in the storage type) from LDS.  Per node the arithmetic is exactly
+// k_stencil_gs_quad_mr's, so the results are bitwise the same.  With few right-hand sides this
+// spreads a colour block over four times as many waves, each with a quarter of the loads.
+template <typename R, typename M, typename Vx>
+__global__ __launch_bounds__(256) void k_stencil_gs_node4(const M* __restrict__ A, const M* __restrict__ Dinv,
+                                                          Vx* x, const Vx* __restrict__ f, int Lt, int Lx,
+                                                          int qb, int nrhs, int64_t stride,
+                                                          const RhsState* __restrict__ st) {
+  constexpr int B = 8, NB = 24;
+  constexpr int UPL = 6, UP = 7, UPR = 8, LEFT = 11;   // slots of (-1,-1), (-1,0), (-1,+1), (0,-1)
+  using C = cplx<R>;
+  __shared__ C fresh[3][B];                            // new values of nodes 0..2
+  const int r = blockIdx.y;
+  if (st && !st[r].active) return;                     // uniform over the workgroup
+  const int lane = threadIdx.x & 63, v = threadIdx.x >> 6;
+  const int i = lane >> 3, jl = lane & 7;
+  const int qx = Lx >> 2, k = blockIdx.x;
+  const int t = 4 * (k / qx) + 2 * (qb >> 1) + (v >> 1), xc = 4 * (k % qx) + 2 * (qb & 1) + (v & 1);
+  const int n = t * Lx + xc;
+  Vx* xr = x + r * stride;
+  C a[NB], xv[NB];
+  {
+    int q = 0;
+#pragma unroll
+    for (int dt = -2; dt <= 2; ++dt) {
+      const int tt = wrap1(t + dt, Lt) * Lx;
+#pragma unroll
+      for (int dx = -2; dx <= 2; ++dx) {
+        if (dt == 0 && dx == 0) continue;
+        const int d = (dt + 2) * 5 + (dx + 2);
+        a[q] = cconv<C>(A[(int64_t(n) * 25 + d) * B * B + i * B + jl]);
+        // the group's earlier nodes are loaded too (old values) and replaced before use
+        xv[q] = cconv<C>(xr[int64_t(tt + wrap1(xc + dx, Lx)) * B + jl]);
+        ++q;
+      }
+    }
+  }
+  const C d = cconv<C>(Dinv[int64_t(n) * B * B + i * B + jl]);
+  const C fv = f ? cconv<C>(f[r * stride + int64_t(n) * B + i]) : czero<R>();
+  __syncthreads();                                     // every load of the launch precedes every store
+  for (int ph = 0; ph < 4; ++ph) {
+    if (v == ph) {
+      // stencil slots of the group's earlier nodes
+      if (v == 1) {
+        xv[LEFT] = fresh[0][jl];
+      } else if (v == 2) {
+        xv[UP] = fresh[0][jl];
+        xv[UPR] = fresh[1][jl];
+      } else if (v == 3) {
+        xv[UPL] = fresh[0][jl];
+        xv[UP] = fresh[1][jl];
+        xv[LEFT] = fresh[2][jl];
+      }
+      C acc = czero<R>();
+#pragma unroll
+      for (int q = 0; q < NB; ++q) acc = cfma(a[q], xv[q], acc);
+      acc.x = group_sum<8>(acc.x);
+      acc.y = group_sum<8>(acc.y);
+      C res = mk<R>(-acc.x, -acc.y);
+      if (f) res = cadd(res, fv);
+      C out = cfma(d, mk<R>(__shfl(res.x, jl * 8), __shfl(res.y, jl * 8)), czero<R>());
+      out.x = group_sum<8>(out.x);
+      out.y = group_sum<8>(out.y);
+      if (jl == 0) {
+        xr[int64_t(n) * B + i] = cconv<Vx>(out);
+        if (v < 3) fresh[v][i] = cconv<C>(cconv<Vx>(out));
+      }
+    }
+    if (ph < 3) __syncthreads();
+  }
+}
+
 // One colour block qb of the coarse sweep for FP32 8 x 8 blocks on matrix cores.  A workgroup
 // takes one 2 x 2 group of the block and a tile of 16 right-hand sides; wave v owns node v of
 // the group in sweep order (I0, J0), (I0, J0 + 1), (I0 + 1, J0),
@@ -933,8 +1010,8 @@ static void gs_pair_b(hipStream_t s, const void* A, const void* D, void* x, cons
 // one matrix-core launch, variant = stencil offsets per load batch (8, 12 or 24; 0 = 12).
 // Smaller grids, FP64 and other blocks: variant > 0 colour-pair launches with that many
 // right-hand sides per wave (8 x 8 blocks; 0 = 2 in FP32, the generic pair kernel in FP64),
-// < 0 one k_stencil_gs_quad_mr launch with -variant right-hand sides per wave (8 x 8 blocks;
-// otherwise colour pairs).  Within each of the two paths every variant gives bitwise the same
+// -1 and -2 one k_stencil_gs_quad_mr launch with -variant right-hand sides per wave, and
+// kGsNodeWaves one k_stencil_gs_node4 launch (8 x 8 blocks; otherwise colour pairs).  Within each of the two paths every variant gives bitwise the same
 // results; which path runs depends on the grid only, so a right-hand side's result does not
 // depend on its batch.
 template <int B, typename R, typename M, typename V>
@@ -956,6 +1033,12 @@ static void gs_block_b(hipStream_t s, const void* A, const void* D, void* x, con
     }
   }
   if constexpr (B == 8) {
+    if (variant == kGsNodeWaves) {
+      const dim3 g(unsigned((Lt / 4) * (Lx / 4)), unsigned(nrhs));
+      AMAMG_LAUNCH((k_stencil_gs_node4<R, M, V>), g, dim3(256), 0, s, (const M*)A, (const M*)D, (V*)x,
+                   (const V*)f, Lt, Lx, qb, nrhs, stride, st);
+      return;
+    }
     const int rb = -variant;
     if ((rb == 1 || rb == 2) && nrhs >= rb) {
       const int ngr = (Lt / 4) * (Lx / 4);

@@ -87,12 +87,14 @@ void stencil_gs(hipStream_t s, Real prec, const void* A, const void* Dinv, void*
 inline bool gs_on_matrix_cores(int Lt, int Lx, int mode) {
   return mode == 1 || (mode == 0 && Lt * Lx >= 1024);
 }
+constexpr int kGsNodeWaves = -4;
 // colour block qb (0..3) of the coarse sweep order (coarse_colour(4 qb) .. coarse_colour(4 qb +
 // 3)).  FP32 8 x 8 blocks with gs_on_matrix_cores(mode): one matrix-core launch, variant = offsets
 // per load batch (8, 12 or 24; 0 = 12).  Otherwise bitwise equal to four stencil_gs launches
 // in that order; variant (FP32 8 x 8 blocks): > 0 colour-pair launches with that many
-// right-hand sides per wave, < 0 one launch per block with -variant right-hand sides per wave.
-// The variant is a launch parameter only
+// right-hand sides per wave, -1 and -2 one launch per block with -variant right-hand sides per
+// wave, kGsNodeWaves one launch per block with one wave per node and one right-hand side per
+// workgroup.  The variant is a launch parameter only
 void stencil_gs_block(hipStream_t s, Real prec, const void* A, const void* Dinv, void* x, const void* f,
                       int Lt, int Lx, int b, int qb, int nrhs, int64_t stride, const RhsState* st, int variant = 0,
                       int mode = 0);

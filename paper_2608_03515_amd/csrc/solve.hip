@@ -395,13 +395,14 @@ static void tune_batch(Batch& bt) {
       cand = {8, 12, 24};                   // offsets per load batch of the matrix-core sweep
     } else {
       // > 0: colour-pair launches with that many rhs per wave (FP64: 0 = the generic pair
-      // kernel); < 0: one launch per colour block
+      // kernel); < 0: one launch per colour block (kGsNodeWaves: one wave per node)
       if (f32 && cap < 2) continue;
       cand = f32 ? std::vector<int>{1} : std::vector<int>{0};
       if (cap >= 2) cand.push_back(2);
       if (cap >= 4) cand.push_back(4);
       cand.push_back(-1);
       if (cap >= 2) cand.push_back(-2);
+      cand.push_back(kGsNodeWaves);
     }
     const int64_t nd = g.ndof();
     Workspace::Lev& WL = ws->lv[k];

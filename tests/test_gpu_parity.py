@@ -740,13 +740,13 @@ def test_c4_mixed_batch_within_bound(lib, ctx, block_smoother):
         assert abs(i32[r].iterations - i64[r].iterations) <= max(5, i64[r].iterations // 10)
 
 
-@pytest.mark.parametrize("a,block_cands", [(8, {1, 2, 4, -1, -2}), (4, {8, 12, 24})])
+@pytest.mark.parametrize("a,block_cands", [(8, {1, 2, 4, -1, -2, -4}), (4, {8, 12, 24})])
 def test_tuned_launch_shapes_do_not_change_results(lib, a, block_cands):
     """The autotuner's launch shapes give bitwise the same mixed solve of 20 right-hand sides,
     forced one by one and chosen by timing; the timed entries are recorded.  Fine smoother tile
     width 16/32/64; level 1 with 16 x 16 nodes (128^2 workload, a = 8, o = 2): the vector block
     sweep as colour-pair launches with 1/2/4 right-hand sides per wave or one launch per 2 x 2
-    colour block with 1/2; with 32 x 32 nodes (a = 4, o = 2): the matrix-core sweep with 8, 12
+    colour block with 1/2 or with one wave per node; with 32 x 32 nodes (a = 4, o = 2): the matrix-core sweep with 8, 12
     or 24 stencil offsets per load batch."""
     w = synth.WORKLOADS["C4"]
     psi = synth.field_to_abi(synth.gaussian_rhs(w.L, w.L, 5151, nrhs=20))
@@ -782,15 +782,16 @@ def test_tuned_launch_shapes_do_not_change_results(lib, a, block_cands):
 def test_tuned_fp64_block_sweep_shapes_do_not_change_results(lib):
     """FP64 solves (20 right-hand sides, and one) on the 128^2 workload: the level-1 block sweep
     (16 x 16 nodes of 8 dofs) as generic colour-pair launches, colour-pair launches with 2 or 4
-    right-hand sides per wave, or one launch per 2 x 2 colour block with 1 or 2 per wave, forced
-    one by one and chosen by timing, gives bitwise the same solutions and iteration counts."""
+    right-hand sides per wave, or one launch per 2 x 2 colour block with 1 or 2 per wave or with
+    one wave per node, forced one by one and chosen by timing, gives bitwise the same solutions
+    and iteration counts."""
     w = synth.WORKLOADS["C4"]
     U, m0 = w.links(), synth.critical_masses()["C4"] + w.gaps[0]
     ctx = lib.Context(0)
     g = make_gauge(lib, ctx, U, m0)
     h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=8, overlap=2, n_test_vectors=8))
     sp = lib.default_solve_params(precision=lib.FP64)
-    for nrhs, cands in [(20, {0, 2, 4, -1, -2}), (1, {0, -1})]:
+    for nrhs, cands in [(20, {0, 2, 4, -1, -2, -4}), (1, {0, -1, -4})]:
         psi = synth.field_to_abi(synth.gaussian_rhs(w.L, w.L, 5252, nrhs=nrhs))
         runs = []
         for mode, force in [(lib.TUNE_FORCE, q) for q in range(len(cands))] + [(lib.TUNE_AUTO, 0)]:
