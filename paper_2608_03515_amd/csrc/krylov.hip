@@ -77,31 +77,33 @@ __device__ inline void block_partial(const double2 (&acc)[NV], int nv, double2* 
 
 // fin[i] = sum over blocks of part_r[blk * STRIDE + i] for i < nv, added in a fixed order (8
 // strided groups of blocks with eight independent partial sums each, then the groups in order).
-// Must be called by all 256 threads; fin and scratch are shared arrays.
+// A thread's blocks (at most kSumGroups * 8 of them) are all loaded before the first add, so
+// the reduction costs one memory round trip.  Must be called by all 256 threads; fin and
+// scratch are shared arrays.
+constexpr int kSumGroups = 4;                 // groups of 64 blocks
+static_assert(64 * kSumGroups >= kMaxKrylovBlocks, "every block's partial is loaded");
 template <int STRIDE>
 __device__ inline void sum_blocks(const double2* __restrict__ part_r, int nblk, int nv,
                                   double2* fin, double2* scratch) {
   const int i = threadIdx.x & (KMAXV - 1), c = threadIdx.x / KMAXV;
   double2 s = make_double2(0, 0);
   if (i < nv) {
+    double2 pv[kSumGroups][8];
+#pragma unroll
+    for (int g = 0; g < kSumGroups; ++g)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int b = c + 64 * g + 8 * u;
+        pv[g][u] = part_r[int64_t(b < nblk ? b : 0) * STRIDE + i];
+      }
     double2 q[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) q[u] = make_double2(0, 0);
-    // groups of 64 blocks that are all present take their eight loads at once; the last,
-    // partial group masks them (each q[u] still adds its blocks in increasing order)
-    int b = c;
-    for (; b + 56 < nblk; b += 64) {
-      double2 pv[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) pv[u] = part_r[int64_t(b + 8 * u) * STRIDE + i];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) q[u] = cadd(q[u], pv[u]);
-    }
-    if (b < nblk) {
+    for (int g = 0; g < kSumGroups; ++g)
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (b + 8 * u < nblk) q[u] = cadd(q[u], part_r[int64_t(b + 8 * u) * STRIDE + i]);
-    }
+        if (c + 64 * g + 8 * u < nblk) q[u] = cadd(q[u], pv[g][u]);
 #pragma unroll
     for (int u = 0; u < 8; ++u) s = cadd(s, q[u]);
   }
@@ -123,7 +125,7 @@ __device__ inline bool finite_d(double v) { return v == v && v - v == 0.0; }
 // column, forms rotation j, updates g and tests the end of the cycle; the caller writes the
 // column back to H.
 __device__ inline void arnoldi_step(const KrylovDims& dm, RhsState& s, int r, double hn, double2* col,
-                                    const double* csl, const double2* snl, const ArnoldiArgs& a) {
+                                    const double* csl, const double2* snl, const ArnoldiArgs& a, double2 gj) {
   const int m = dm.m, j = a.j;
   double* csr = a.cs + int64_t(r) * m;
   double2* snr = a.sn + int64_t(r) * m;
@@ -151,7 +153,6 @@ __device__ inline void arnoldi_step(const KrylovDims& dm, RhsState& s, int r, do
   col[j + 1] = make_double2(0, 0);
   csr[j] = c;
   snr[j] = sv;
-  const double2 gj = gr[j];
   gr[j + 1] = cscale(cmulc(sv, gj), -1.0);
   gr[j] = cscale(gj, c);
   s.iters += 1;
@@ -318,22 +319,36 @@ __device__ inline void lag_control_item(const KrylovDims& dm, const double2* __r
                                         RhsState* __restrict__ st, const ArnoldiArgs& aa,
                                         double2* __restrict__ coef, double* __restrict__ zsc, int has_w,
                                         int r) {
-  if (!st[r].active) return;
   __shared__ double2 du[KMAXV], dw[KMAXV], scratch[8 * KMAXV];
   __shared__ double2 col[KMAXV + 1], snl[KMAXV];
   __shared__ double csl[KMAXV];
   __shared__ double rho_sh;
   __shared__ int go;
-  const int m = dm.m, j = aa.j, nv = j + 1;
+  const int m = dm.m, j = aa.j, nv = j + 1, t = threadIdx.x;   // j < KMAXV < blockDim.x
+  double2* Hr = aa.H + int64_t(r) * (m + 1) * m;
+  // the serial section's reads (column j - 1 of H, the rotations, the state and g_{j-1}) are
+  // issued before the partial sums' loads, so that they share one memory round trip
+  double2 h_old = make_double2(0, 0), sn_old = make_double2(0, 0), g_old = make_double2(0, 0);
+  double cs_old = 0.0;
+  RhsState s0 = {};
+  if (j > 0 && t < j) h_old = Hr[t * m + j - 1];
+  if (t + 1 < j) {
+    cs_old = aa.cs[int64_t(r) * m + t];
+    sn_old = aa.sn[int64_t(r) * m + t];
+  }
+  if (t == 0) {
+    s0 = st[r];
+    if (j > 0) g_old = aa.g[int64_t(r) * (m + 1) + j - 1];
+  }
+  if (!st[r].active) return;                           // uniform over the workgroup
   const double2* pr = part + int64_t(r) * dm.nblk * KGRAM;
   sum_blocks<KGRAM>(pr, dm.nblk, nv, du, scratch);
   if (has_w) sum_blocks<KGRAM>(pr + KMAXV, dm.nblk, nv, dw, scratch);
-  double2* Hr = aa.H + int64_t(r) * (m + 1) * m;
   if (j > 0) {
-    for (int i = threadIdx.x; i < j; i += blockDim.x) col[i] = cadd(Hr[i * m + j - 1], du[i]);
-    for (int i = threadIdx.x; i < j - 1; i += blockDim.x) {
-      csl[i] = aa.cs[int64_t(r) * m + i];
-      snl[i] = aa.sn[int64_t(r) * m + i];
+    if (t < j) col[t] = cadd(h_old, du[t]);
+    if (t + 1 < j) {
+      csl[t] = cs_old;
+      snl[t] = sn_old;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -341,10 +356,10 @@ __device__ inline void lag_control_item(const KrylovDims& dm, const double2* __r
       for (int i = 0; i < j; ++i) ssq += cabs2(du[i]);
       const double rho = sqrt(fmax(du[j].x - ssq, 0.0));
       col[j] = make_double2(rho, 0.0);
-      RhsState s = st[r];
+      RhsState s = s0;
       ArnoldiArgs a1 = aa;
       a1.j = j - 1;
-      arnoldi_step(dm, s, r, rho, col, csl, snl, a1);
+      arnoldi_step(dm, s, r, rho, col, csl, snl, a1, g_old);
       st[r] = s;
       rho_sh = rho;
       go = s.active && has_w;

@@ -166,6 +166,7 @@ void axpy_real(hipStream_t s, double2* y, double a, const double2* x, int64_t n)
 // reorthogonalisation: gram (slots 0..j with w), lag_control (step j), lag_update; a cycle of m
 // steps ends with gram over slots 0..m without w and lag_control for step m.
 struct KrylovDims { int64_t n; int nrhs; int nblk; int m; };
+constexpr int kMaxKrylovBlocks = 256;          // nblk <= this
 // partials of V^H u (u = slot nv-1) and, when w is given, of V^H w, over slots 0..nv-1
 void gram(hipStream_t s, const KrylovDims& d, const double2* V, int64_t vsj, int nv, const double2* w,
           double2* part, const RhsState* st);

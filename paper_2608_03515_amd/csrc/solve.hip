@@ -20,7 +20,6 @@ namespace rt {
 // (16 per compute unit), at least 8 elements per thread once that many blocks exist (the
 // per-block reduction of the previous pass's partials is then amortised), at most one block
 // per 256 elements and at most kMaxKrylovBlocks.
-constexpr int kMaxKrylovBlocks = 256;
 static int krylov_blocks(int64_t n, int nrhs) {
   const int64_t want = std::max<int64_t>(n / 2048, (4096 + nrhs - 1) / nrhs);
   return int(std::max<int64_t>(1, std::min<int64_t>({int64_t(kMaxKrylovBlocks), n / 256, want})));

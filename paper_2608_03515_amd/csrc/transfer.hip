@@ -687,7 +687,7 @@ __global__ __launch_bounds__(256) void k_prolong_mfma(
   }
 }
 
-template <typename R, typename Vin, typename Vout>
+template <typename R, typename Vin, typename Vout, int CHL>
 __global__ __launch_bounds__(256) void k_restrict_gather(const cplx<R>* __restrict__ part,
                                                          const Vin* __restrict__ rin,
                                                          Vout* __restrict__ rc, Geom g, int nchunk,
@@ -715,7 +715,6 @@ __global__ __launch_bounds__(256) void k_restrict_gather(const cplx<R>* __restri
   const int pt = pp / g.o, px = pp - (pp / g.o) * g.o;
   const int p = (g.a * I + pt) * g.Lx + (g.a * J + px);
   const Vin rv = rin[r * stride_f + int64_t(p) * g.b + q];
-  constexpr int CHL = 2;                       // chunks per lane held in registers
   const C* pw[4];
   C pv[4][CHL];
 #pragma unroll
@@ -835,6 +834,20 @@ __global__ void k_inject(Geom g, const int* __restrict__ node, const int8_t* __r
 static size_t tile_smem(const TileShape& t, int ncol, int cs) {
   return size_t(t.rch) * (ncol + 1) * cs + size_t(t.rg) * (t.rch > ncol ? t.rch : ncol) * cs +
          size_t(t.rch) * sizeof(int);
+}
+
+// Pass 2 of the restriction.  CHL chunks per lane are loaded at once (the rest, if any, one
+// after another); the sums run in the same order whatever CHL, so CHL only sets how many loads
+// are in flight: 2 when every lane has at most two chunks, else 8.
+template <typename R, typename Vin, typename Vout>
+static void launch_gather(hipStream_t s, dim3 g2, const void* part, const void* r, void* rc, const Geom& g,
+                          int nchunk, int lanes, int64_t stride_f, int64_t stride_c, const RhsState* st) {
+  if (nchunk > 2 * lanes)
+    hipLaunchKernelGGL((k_restrict_gather<R, Vin, Vout, 8>), g2, dim3(256), 0, s, (const cplx<R>*)part,
+                       (const Vin*)r, (Vout*)rc, g, nchunk, lanes, stride_f, stride_c, st);
+  else
+    hipLaunchKernelGGL((k_restrict_gather<R, Vin, Vout, 2>), g2, dim3(256), 0, s, (const cplx<R>*)part,
+                       (const Vin*)r, (Vout*)rc, g, nchunk, lanes, stride_f, stride_c, st);
 }
 
 int restrict_chunks(const Geom& g, int nf, Real prec) {
@@ -994,13 +1007,9 @@ void restrict_(hipStream_t s, Real prec, const void* P, const int* rows, const i
     if (rin == F64) restrict_mfma<128, double2>(s, P, rows, nrows, maxrows, r, part, nW, nchunk, nrhs, stride_f, st);
     else restrict_mfma<128, float2>(s, P, rows, nrows, maxrows, r, part, nW, nchunk, nrhs, stride_f, st);
     if (rin == F64)
-      hipLaunchKernelGGL((k_restrict_gather<float, double2, float2>), g2, dim3(256), 0, s,
-                         (const float2*)part, (const double2*)r, (float2*)rc, g, nchunk, lanes,
-                         stride_f, stride_c, st);
+      launch_gather<float, double2, float2>(s, g2, part, r, rc, g, nchunk, lanes, stride_f, stride_c, st);
     else
-      hipLaunchKernelGGL((k_restrict_gather<float, float2, float2>), g2, dim3(256), 0, s,
-                         (const float2*)part, (const float2*)r, (float2*)rc, g, nchunk, lanes,
-                         stride_f, stride_c, st);
+      launch_gather<float, float2, float2>(s, g2, part, r, rc, g, nchunk, lanes, stride_f, stride_c, st);
     return;
   }
   if (tiled_cols(g.ncol())) {
@@ -1014,17 +1023,11 @@ void restrict_(hipStream_t s, Real prec, const void* P, const int* rows, const i
       else restrict_tiled<8, float, float2, float2>(s, P, rows, nrows, maxrows, r, part, nW, nchunk, nrhs, stride_f, st);
     }
     if (prec == F64)
-      hipLaunchKernelGGL((k_restrict_gather<double, double2, double2>), g2, dim3(256), 0, s,
-                         (const double2*)part, (const double2*)r, (double2*)rc, g, nchunk, lanes,
-                         stride_f, stride_c, st);
+      launch_gather<double, double2, double2>(s, g2, part, r, rc, g, nchunk, lanes, stride_f, stride_c, st);
     else if (rin == F64)
-      hipLaunchKernelGGL((k_restrict_gather<float, double2, float2>), g2, dim3(256), 0, s,
-                         (const float2*)part, (const double2*)r, (float2*)rc, g, nchunk, lanes,
-                         stride_f, stride_c, st);
+      launch_gather<float, double2, float2>(s, g2, part, r, rc, g, nchunk, lanes, stride_f, stride_c, st);
     else
-      hipLaunchKernelGGL((k_restrict_gather<float, float2, float2>), g2, dim3(256), 0, s,
-                         (const float2*)part, (const float2*)r, (float2*)rc, g, nchunk, lanes,
-                         stride_f, stride_c, st);
+      launch_gather<float, float2, float2>(s, g2, part, r, rc, g, nchunk, lanes, stride_f, stride_c, st);
     return;
   }
   if (prec == F64) {
@@ -1036,23 +1039,17 @@ void restrict_(hipStream_t s, Real prec, const void* P, const int* rows, const i
       hipLaunchKernelGGL((k_restrict_partial<double, double2, double2>), g1, dim3(256), sm, s,
                          (const double2*)P, rows, nrows, maxrows, (const double2*)r, (double2*)part, g,
                          ts, nrhs, stride_f, st);
-    hipLaunchKernelGGL((k_restrict_gather<double, double2, double2>), g2, dim3(256), 0, s,
-                       (const double2*)part, (const double2*)r, (double2*)rc, g, ts.nchunk, lanes,
-                       stride_f, stride_c, st);
+    launch_gather<double, double2, double2>(s, g2, part, r, rc, g, ts.nchunk, lanes, stride_f, stride_c, st);
   } else if (rin == F64) {
     hipLaunchKernelGGL((k_restrict_partial<float, float2, double2>), g1, dim3(256), sm, s,
                        (const float2*)P, rows, nrows, maxrows, (const double2*)r, (float2*)part, g,
                        ts, nrhs, stride_f, st);
-    hipLaunchKernelGGL((k_restrict_gather<float, double2, float2>), g2, dim3(256), 0, s,
-                       (const float2*)part, (const double2*)r, (float2*)rc, g, ts.nchunk, lanes,
-                       stride_f, stride_c, st);
+    launch_gather<float, double2, float2>(s, g2, part, r, rc, g, ts.nchunk, lanes, stride_f, stride_c, st);
   } else {
     hipLaunchKernelGGL((k_restrict_partial<float, float2, float2>), g1, dim3(256), sm, s,
                        (const float2*)P, rows, nrows, maxrows, (const float2*)r, (float2*)part, g,
                        ts, nrhs, stride_f, st);
-    hipLaunchKernelGGL((k_restrict_gather<float, float2, float2>), g2, dim3(256), 0, s,
-                       (const float2*)part, (const float2*)r, (float2*)rc, g, ts.nchunk, lanes,
-                       stride_f, stride_c, st);
+    launch_gather<float, float2, float2>(s, g2, part, r, rc, g, ts.nchunk, lanes, stride_f, stride_c, st);
   }
 }
 
