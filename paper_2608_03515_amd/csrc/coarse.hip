@@ -676,19 +676,29 @@ __global__ __launch_bounds__(64 * kDenseWaves) void k_dense_apply_mfma(const dou
   const Vin* va = v + int64_t(alive ? ra : 0) * stride;
   const double2* Ab = Ainv + int64_t(blive ? rb : 0) * n;
   mfma_d4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
-#pragma unroll 8
-  for (int kk = k0; kk < k1; kk += 4) {
-    const int k = kk + lk;
-    const bool kin = k < k1;
-    // unconditional loads from valid addresses, then selects: no branch separates the loads
-    const Vin av = va[kin ? k : 0];
-    const double2 bv = Ab[kin ? k : 0];
-    const double2 a = alive && kin ? cconv<double2>(av) : make_double2(0, 0);
-    const double2 b = blive && kin ? bv : make_double2(0, 0);
-    re = mfma_f64(a.x, b.x, re);
-    re = mfma_f64(-a.y, b.y, re);
-    im = mfma_f64(a.x, b.y, im);
-    im = mfma_f64(a.y, b.x, im);
+  // KB k-steps of operands are loaded (unconditionally, from valid addresses) before their
+  // products, so that a wave waits for memory once per KB steps.  Steps past k1 multiply zeros:
+  // the accumulators start at +0 and never hold -0, so adding them leaves every bit unchanged.
+  constexpr int KB = 8;
+  for (int kb = k0; kb < k1; kb += 4 * KB) {
+    Vin av[KB];
+    double2 bv[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const int k = kb + 4 * u + lk;
+      av[u] = va[k < k1 ? k : 0];
+      bv[u] = Ab[k < k1 ? k : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const bool kin = kb + 4 * u + lk < k1;
+      const double2 a = alive && kin ? cconv<double2>(av[u]) : make_double2(0, 0);
+      const double2 b = blive && kin ? bv[u] : make_double2(0, 0);
+      re = mfma_f64(a.x, b.x, re);
+      re = mfma_f64(-a.y, b.y, re);
+      im = mfma_f64(a.x, b.y, im);
+      im = mfma_f64(a.y, b.x, im);
+    }
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) red[wv][i * 64 + lane] = make_double2(re[i], im[i]);

@@ -320,21 +320,24 @@ static KrylovDims dims(const Batch& bt) {
 
 // ------------------------------------------------------------------------------ autotuning
 
-// Mean time in microseconds of `run` on stream s (one untimed run, then three timed).
+// Mean time in microseconds of `run` on stream s (one untimed run, then the timed ones).
 template <typename F> static double time_us(hipStream_t s, F run) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
+  // ten timed runs: candidates a microsecond or two apart per launch (the level-1 sweeps of a
+  // single right-hand side) are told apart reliably
+  constexpr int kReps = 10;
   run();
   HIPCHECK(hipEventRecord(e0, s));
-  for (int q = 0; q < 3; ++q) run();
+  for (int q = 0; q < kReps; ++q) run();
   HIPCHECK(hipEventRecord(e1, s));
   HIPCHECK(hipEventSynchronize(e1));
   float ms = 0.f;
   HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  return double(ms) * 1000.0 / 3.0;
+  return double(ms) * 1000.0 / kReps;
 }
 
 // The tuned value for `key`: cached, or (mode AUTO) the fastest candidate by `measure`, or
