@@ -674,14 +674,15 @@ def test_transfers_match_oracle(lib, ctx, c4_oracle):
     """Restriction P^H and prolongation P of the 128^2 a = 8, o = 2 hierarchy (32 interpolation
     columns on the fine level: register tiles; 128 on level 1: the mixed V-cycle's matrix-core
     tiles, 32 or 64 right-hand sides a workgroup) and of the 64^2 a = 4, o = 1 one (8 columns), FP64
-    and FP32, for 1, 17, 64 and 70 right-hand sides (a partial tile, a full group, a second
-    group); the two level-1 tile widths give a right-hand side bitwise the same result."""
+    and FP32, for 1, 3, 17, 64 and 70 right-hand sides (the small-batch kernels, a partial tile, a
+    full group, a second group); the two level-1 tile widths give a right-hand side bitwise the
+    same result."""
     rng = np.random.default_rng(8080)
     U, m0, olev = c4_oracle
     g = make_gauge(lib, ctx, U, m0)
     h = lib.Hierarchy(g, lib.default_setup_params(levels=3, agg_size=8, overlap=2, n_test_vectors=8))
     for level in (0, 1):
-        for nrhs in (1, 17, 64, 70):
+        for nrhs in (1, 3, 17, 64, 70):
             for precision in (lib.FP64, lib.MIXED_FP32):
                 say("transfer C4", level, nrhs, precision)
                 _transfer_case(lib, h, olev, level, rng, nrhs, precision)
@@ -846,6 +847,42 @@ def graph_runs(lib, h, psi, coarsest_tol):
                 for (v, f), (v0, f0) in zip(hist, runs[0][2]):
                     assert np.array_equal(v, v0) and np.array_equal(f, f0)
             assert max(r for _, r in runs[0][1]) >= 1          # several cycles: several replays
+
+
+def test_c3_single_rhs_fp64_matches_stored_oracle_solve(lib):
+    """The 256^2 workload's right-hand side 0 solved alone in FP64, the benchmark's single-rhs
+    path (small-batch transfer kernels, the coarsest apply with a padded tile, the tuned level-1
+    sweep shape), against the oracle's stored FP64 solve (tests/golden/c3_solve.json, written
+    by make_golden.py from the oracle alone): iteration and restart counts exact, sampled
+    solution entries and the solution norm within 1e-9, the residual history's flags exact and
+    its values within 1e-6."""
+    import json
+    import os
+    import torch
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c3_solve.json")) as fh:
+        gold = json.load(fh)
+    w = synth.WORKLOADS["C3"]
+    psi = synth.gaussian_rhs(w.L, w.L, w.rhs_seed, nrhs=1)
+    stream = torch.cuda.Stream()
+    ctx = lib.Context(0, stream.cuda_stream)
+    g = make_gauge(lib, ctx, w.links(), gold["m0"])
+    h = lib.Hierarchy(g, lib.default_setup_params(**w.setup_kw()))
+    say("C3 single rhs FP64")
+    x, infos, st = h.solve(synth.field_to_abi(psi), lib.default_solve_params(precision=lib.FP64))
+    hist, flags = h.residual_history(0)
+    h.close()
+    g.close()
+    ctx.close()
+    assert st == lib.OK and infos[0].converged
+    assert infos[0].iterations == gold["iterations"] and infos[0].restarts == gold["restarts"]
+    xf = synth.field_from_abi(x)[0].reshape(-1, 2)
+    ref = np.array([complex(re, im) for _, _, re, im in gold["samples"]])
+    got = np.array([xf[s, q] for s, q, _, _ in gold["samples"]])
+    assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max()
+    assert abs(np.linalg.norm(xf) - gold["x_norm"]) <= 1e-9 * gold["x_norm"]
+    gh = np.array([v for v, _ in gold["history"]])
+    assert np.array_equal(flags[:len(gh)], np.array([t for _, t in gold["history"]]))
+    assert np.allclose(hist[:len(gh)], gh, rtol=1e-6, atol=1e-14)
 
 
 def test_c3_full_size_solve_in_bench_configuration(lib):
