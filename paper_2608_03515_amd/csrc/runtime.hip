@@ -239,6 +239,7 @@ size_t setup_bytes(int nt, int nx, const amamg_setup_params& p) {
     b += nnode * 9 + size_t(nv) * ndof * c16 + tabs.size() * 4 + nW * nf * g.b * 4 + nW * 4 * (1 + kDenseSolveInts);
     b += nW * nfd * (nfd + g.nvcol()) * c16 + ndof * ncol * (c16 + c8);
     if (k == 0 && p.aug_vectors > 0) b += size_t(nv) * ndof * c16 + nW * 4;
+    if (k == 0) b += size_t(nv) * ndof * c16;                     // tv_alt
     b += size_t(nv) * ndc * c16 * 2;
     const size_t npc = size_t(probe_batch_colours(int(bc), period_of(gc.Lt) * period_of(gc.Lx))) * bc;
     b += npc * (2 * ndc + 2 * ndof) * c16 + npc * nW * restrict_chunks(g, nf, F64) * ncol * c16;
@@ -253,7 +254,7 @@ size_t setup_bytes(int nt, int nx, const amamg_setup_params& p) {
 // Buffers only the setup itself needs; with a scratch pool they live there (and are reused by
 // the next setup) instead of in the hierarchy.
 static bool setup_scratch(const char* name) {
-  static const char* names[] = {"A0", "d_offs5", "d_offs25", "L_tv", "Aug", "info", "Wc", "Ptv", "ainfo",
+  static const char* names[] = {"A0", "d_offs5", "d_offs25", "L_tv", "tv_alt", "Aug", "info", "Wc", "Ptv", "ainfo",
                                 "pe", "py", "pz", "pu", "ppart", "Dg", "dinfo", "LUc", "cinfo", "keep"};
   for (const char* n : names)
     if (std::strcmp(n, name) == 0) return true;
@@ -411,16 +412,26 @@ void run_setup(amamg_hierarchy* h, hipStream_t stream, Pool* scratch) {
       L.tv = pool("L_tv").get<double2>("L_tv", k, size_t(nv) * ndof);
       if (k == 0) testvec_hash(s, p.seed, 0, nv, ndof, L.tv);
       else HIPCHECK(hipMemcpyAsync(L.tv, W, sizeof(double2) * nv * ndof, hipMemcpyDeviceToDevice, s));
-      for (int sw = 0; sw < p.test_vector_sweeps; ++sw) {
-        if (k == 0) {
-          for (int c = 0; c < 2; ++c)
-            wilson_gs(s, LINK_F64, U0, U1, F64, L.tv, nullptr, g.Lt, g.Lx, h->m0, c, nv, ndof, nullptr);
-        } else {
-          // the 16 colours as 4 colour blocks, one launch each for 8 x 8 blocks (two colour-pair
-          // launches otherwise); bitwise the colour-by-colour sweep
+      if (k == 0 && p.test_vector_sweeps > 0) {
+        // two red-black sweeps per launch, between L_tv and a second buffer (bitwise the
+        // colour-by-colour launches); the result ends in L_tv
+        double2* alt = pool("tv_alt").get<double2>("tv_alt", k, size_t(nv) * ndof);
+        double2* cur = L.tv;
+        double2* nxt = alt;
+        for (int sw = 0; sw < p.test_vector_sweeps; sw += 2) {
+          const int ns = std::min(2, p.test_vector_sweeps - sw);
+          wilson_gs_sweeps(s, LINK_F64, U0, U1, F64, cur, nxt, nullptr, g.Lt, g.Lx, h->m0, ns, nv, ndof, nullptr);
+          std::swap(cur, nxt);
+        }
+        if (cur != L.tv)
+          HIPCHECK(hipMemcpyAsync(L.tv, cur, sizeof(double2) * nv * ndof, hipMemcpyDeviceToDevice, s));
+      } else {
+        for (int sw = 0; sw < p.test_vector_sweeps; ++sw) {
+          // the 16 colours as 4 colour blocks, one launch each for 8 x 8 blocks (one wave per node;
+          // two colour-pair launches for other blocks); bitwise the colour-by-colour sweep
           for (int qb = 0; qb < 4; ++qb)
-            stencil_gs_block(s, F64, L.A, L.Dinv, L.tv, nullptr, g.Lt, g.Lx, g.b, qb, nv, ndof, nullptr, -1,
-                             p.block_smoother);
+            stencil_gs_block(s, F64, L.A, L.Dinv, L.tv, nullptr, g.Lt, g.Lx, g.b, qb, nv, ndof, nullptr,
+                             kGsNodeWaves, p.block_smoother);
         }
       }
       check_launch();
