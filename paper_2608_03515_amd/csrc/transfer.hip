@@ -539,7 +539,7 @@ __device__ inline mfma_f4 mfma16(float a, float b, mfma_f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 template <int NCOL> struct MfmaRows;                   // fine rows per chunk
-template <> struct MfmaRows<128> { static constexpr int RESTRICT = 16, PROLONG = 32; };
+template <> struct MfmaRows<128> { static constexpr int RESTRICT = 32, PROLONG = 32; };
 constexpr int kMfmaRhs = 64;
 // The matrix-core path serves 128 columns (coarse levels of a = 8, o = 2); with 32 columns (the
 // fine level) the register-tiled kernels above are faster: their smaller LDS footprint keeps
