@@ -539,7 +539,9 @@ __device__ inline mfma_f4 mfma16(float a, float b, mfma_f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 template <int NCOL> struct MfmaRows;                   // fine rows per chunk
-template <> struct MfmaRows<128> { static constexpr int RESTRICT = 32, PROLONG = 32; };
+// prolongation rows per chunk: 64 with 64-rhs tiles, 32 with 32-rhs tiles (which then keep
+// two workgroups per compute unit); a row's result does not depend on its chunk
+template <> struct MfmaRows<128> { static constexpr int RESTRICT = 32, PROLONG = 64, PROLONG32 = 32; };
 constexpr int kMfmaRhs = 64;
 // The matrix-core path serves 128 columns (coarse levels of a = 8, o = 2); with 32 columns (the
 // fine level) the register-tiled kernels above are faster: their smaller LDS footprint keeps
@@ -889,14 +891,16 @@ template <int NCOL>
 static void prolong_mfma(hipStream_t s, const void* P, const int* rows, const int* nrows, int maxrows,
                          const void* e, void* y, const Geom& g, int add, int nrhs, int64_t stride_f,
                          int64_t stride_c, const RhsState* st) {
-  constexpr int RCH = MfmaRows<NCOL>::PROLONG;
-  const int nchunk = (maxrows + RCH - 1) / RCH;
   if (nrhs <= 32) {
+    constexpr int RCH32 = MfmaRows<NCOL>::PROLONG32;
+    const int nchunk = (maxrows + RCH32 - 1) / RCH32;
     const dim3 grid(unsigned(g.nI * g.nJ * nchunk), 1);
-    AMAMG_LAUNCH((k_prolong_mfma<NCOL, RCH, 32>), grid, dim3(256), 0, s, (const float2*)P, rows, nrows, maxrows,
+    AMAMG_LAUNCH((k_prolong_mfma<NCOL, RCH32, 32>), grid, dim3(256), 0, s, (const float2*)P, rows, nrows, maxrows,
                  (const float2*)e, (float2*)y, g, nchunk, add, nrhs, stride_f, stride_c, st);
     return;
   }
+  constexpr int RCH = MfmaRows<NCOL>::PROLONG;
+  const int nchunk = (maxrows + RCH - 1) / RCH;
   const dim3 grid(unsigned(g.nI * g.nJ * nchunk), unsigned((nrhs + kMfmaRhs - 1) / kMfmaRhs));
   AMAMG_LAUNCH((k_prolong_mfma<NCOL, RCH, kMfmaRhs>), grid, dim3(256), 0, s, (const float2*)P, rows, nrows, maxrows,
                (const float2*)e, (float2*)y, g, nchunk, add, nrhs, stride_f, stride_c, st);
