@@ -840,12 +840,15 @@ static size_t tile_smem(const TileShape& t, int ncol, int cs) {
 
 // Pass 2 of the restriction.  CHL chunks per lane are loaded at once (the rest, if any, one
 // after another); the sums run in the same order whatever CHL, so CHL only sets how many loads
-// are in flight: 2 when every lane has at most two chunks, else 8.
+// are in flight: as many as a lane has chunks, 1 or 2, else 8.
 template <typename R, typename Vin, typename Vout>
 static void launch_gather(hipStream_t s, dim3 g2, const void* part, const void* r, void* rc, const Geom& g,
                           int nchunk, int lanes, int64_t stride_f, int64_t stride_c, const RhsState* st) {
   if (nchunk > 2 * lanes)
     hipLaunchKernelGGL((k_restrict_gather<R, Vin, Vout, 8>), g2, dim3(256), 0, s, (const cplx<R>*)part,
+                       (const Vin*)r, (Vout*)rc, g, nchunk, lanes, stride_f, stride_c, st);
+  else if (nchunk <= lanes)
+    hipLaunchKernelGGL((k_restrict_gather<R, Vin, Vout, 1>), g2, dim3(256), 0, s, (const cplx<R>*)part,
                        (const Vin*)r, (Vout*)rc, g, nchunk, lanes, stride_f, stride_c, st);
   else
     hipLaunchKernelGGL((k_restrict_gather<R, Vin, Vout, 2>), g2, dim3(256), 0, s, (const cplx<R>*)part,
