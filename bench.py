@@ -518,15 +518,23 @@ def flop_summary(w, iterations, s_per_step):
 # Kernel-name patterns of each timed family in the mixed step (the first pattern is the family's
 # main kernel, one dispatch per timed launch; further patterns are kernels the same launch
 # record covers), and the source file each is built from.
+# kernel-name patterns of each family; "a&b" matches names holding both parts (the solve's FP32
+# fused sweeps at any tuned tile width, not the setup's FP64 test-vector sweeps)
 FAMILY_PATTERNS = {
     "fine_matvec": ("k_wilson_apply<64, float",),
-    "fine_gs": ("k_wilson_gs_fused<",),
+    "fine_gs": ("k_wilson_gs_fused<2, 16, &, float, ",),
     "restrict0": ("k_restrict_partial_tiled<32, 60, 32, float", "k_restrict_gather<float, HIP_vector_type<double"),
     "prolong0": ("k_prolong_tiled<32, 64, 32, float",),
     "coarse_gs": ("k_stencil_gs_quad_mfma<",),
     "dots": ("k_gram<",),
     "update": ("k_lag_update<",),
 }
+
+
+def pat_in(pat, name):
+    return all(part in name for part in pat.split("&"))
+
+
 _CSRC = os.path.join(ROOT, "paper_2608_03515_amd", "csrc")
 FAMILY_SRC = {"fine_matvec": "fine.hip", "fine_gs": "fine.hip", "restrict0": "transfer.hip",
               "prolong0": "transfer.hip", "coarse_gs": "coarse.hip", "dots": "krylov.hip", "update": "krylov.hip"}
@@ -558,11 +566,11 @@ def trace_summary(stats_csv, out_md, command, top=25):
     lines += ["", "Families (all instantiations):", "", "| family | calls | avg us | total ms |", "|---|---:|---:|---:|"]
     for fam, pats in FAMILY_PATTERNS.items():
         for pat in pats:
-            sel = [r for r in rows if pat in r["Name"]]
+            sel = [r for r in rows if pat_in(pat, r["Name"])]
             n = sum(int(r["Calls"]) for r in sel)
             t = sum(float(r["TotalDurationNs"]) for r in sel)
             if n:
-                lines.append(f"| {fam} (`{pat}*`) | {n} | {t / n / 1e3:.2f} | {t / 1e6:.2f} |")
+                lines.append(f"| {fam} (`{pat.replace('&', '…')}*`) | {n} | {t / n / 1e3:.2f} | {t / 1e6:.2f} |")
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
@@ -612,12 +620,12 @@ def pmc_summary(fetch_csv, write_csv, out_md, command, timer_json, wait_csv=None
               "algorithmic GB/s | % of 8 TB/s |", "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
     rec = {}
     for fam, pats in FAMILY_PATTERNS.items():
-        fv0 = [v for k, vs in fe.items() if pats[0] in k for v in vs]
+        fv0 = [v for k, vs in fe.items() if pat_in(pats[0], k) for v in vs]
         nwork = sum(1 for v in fv0 if v * 1024 / f_fac > 1e6)
         if not nwork:
             continue
-        fv = [v for k, vs in fe.items() if any(p in k for p in pats) for v in vs]
-        wv = [v for k, vs in wr.items() if any(p in k for p in pats) for v in vs]
+        fv = [v for k, vs in fe.items() if any(pat_in(p, k) for p in pats) for v in vs]
+        wv = [v for k, vs in wr.items() if any(pat_in(p, k) for p in pats) for v in vs]
         rd = sum(fv) * 1024 / f_fac / nwork
         wt = sum(wv) * 1024 / w_fac / nwork
         ft = fams.get(fam, {})
@@ -634,9 +642,9 @@ def pmc_summary(fetch_csv, write_csv, out_md, command, timer_json, wait_csv=None
                   "family's main kernel:", "", "| family | SQ_WAIT_ANY / SQ_ACTIVE_INST_VALU | waves / dispatch |",
                   "|---|---:|---:|"]
         for fam, pats in FAMILY_PATTERNS.items():
-            w = sum(v for k, vs in wa.items() if pats[0] in k for v in vs)
-            a = sum(v for k, vs in va.items() if pats[0] in k for v in vs)
-            nw = [v for k, vs in wv_.items() if pats[0] in k for v in vs]
+            w = sum(v for k, vs in wa.items() if pat_in(pats[0], k) for v in vs)
+            a = sum(v for k, vs in va.items() if pat_in(pats[0], k) for v in vs)
+            nw = [v for k, vs in wv_.items() if pat_in(pats[0], k) for v in vs]
             if a > 0:
                 lines.append(f"| {fam} | {w / a:.2f} | {sum(nw) / max(1, len(nw)):.0f} |")
     lines.append("")
