@@ -521,7 +521,7 @@ def flop_summary(w, iterations, s_per_step):
 # kernel-name patterns of each family; "a&b" matches names holding both parts (the solve's FP32
 # fused sweeps at any tuned tile width, not the setup's FP64 test-vector sweeps)
 FAMILY_PATTERNS = {
-    "fine_matvec": ("k_wilson_apply<64, float",),
+    "fine_matvec": ("k_wilson_apply<64, 2, float",),
     "fine_gs": ("k_wilson_gs_fused<2, 16, &, float, ",),
     "restrict0": ("k_restrict_partial_tiled<32, 60, 32, float", "k_restrict_gather<float, HIP_vector_type<double"),
     "prolong0": ("k_prolong_tiled<32, 64, 32, float",),
@@ -680,11 +680,11 @@ def stencil_traffic_summary(fetch_csv, write_csv, stats_csv, out_md, command, tr
     dur = {r["Name"].split("(")[0]: float(r["AverageNs"]) for r in csv.DictReader(open(stats_csv))}
 
     def mode(name):
-        # template arguments: tile, compute type, link storage, ...
+        # template arguments: tile width, sites per thread, compute type, link storage, ...
         args = [a.strip() for a in name.split("k_wilson_apply<", 1)[1].split(",")]
-        if "bf16" in args[2]:
+        if "bf16" in args[3]:
             return "fp32_bf16links"
-        return "fp64" if args[1] == "double" else "fp32"
+        return "fp64" if args[2] == "double" else "fp32"
     lines = [f"# HBM traffic, {os.path.basename(out_md)[:-3]}", "",
              "Two counter passes (one counter each) and a kernel trace, from the repository root:", ""]
     for c in ("FETCH_SIZE", "WRITE_SIZE"):

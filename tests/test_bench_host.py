@@ -87,7 +87,7 @@ def test_traffic_summaries_scale_by_the_calibration_copy(tmp_path):
     finally:
         bench.TRAFFIC_MD = saved
     # the stencil's summary on the same calibration, with a kernel trace for the duration
-    st = "void amamg::k_wilson_apply<64, double, HIP_vector_type<double, 2u>, HIP_vector_type<double, 2u> >(...)"
+    st = "void amamg::k_wilson_apply<64, 1, double, HIP_vector_type<double, 2u>, HIP_vector_type<double, 2u> >(...)"
     alg = bench.STENCIL_BYTES_PER_SITE["fp64"] * bench.STENCIL_L ** 2
     _write_csv(fetch, hdr, [[cal, "FETCH_SIZE", 2 ** 19], [st, "FETCH_SIZE", alg * 0.5 / 1024]])
     _write_csv(write, hdr, [[cal, "WRITE_SIZE", 2 ** 20], [st, "WRITE_SIZE", 0.0]])
