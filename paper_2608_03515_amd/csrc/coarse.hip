@@ -536,8 +536,10 @@ __global__ __launch_bounds__(256) void k_stencil_gs_quad_mfma(const float2* __re
                                                                   int qb, int nrhs, int64_t stride,
                                                                   const RhsState* __restrict__ st) {
   static_assert(24 % NB == 0, "batches must cover the 24 offsets");
+  constexpr int XS = 9;                   // float2 per (node, rhs) in LDS: 8 dofs + 1 against bank conflicts
   __shared__ float res[4][16][17];        // [node][row][rhs]: f - sum
   __shared__ float nx[4][16][17];         // new values: rows 0..7 Re, 8..15 Im
+  __shared__ float2 xs[36 * 16 * XS];     // old values of the group's 6 x 6 neighbourhood
   const int lane = threadIdx.x & 63, v = threadIdx.x >> 6;
   const int rl = lane & 15, kq = lane >> 4, row8 = lane & 7;
   const bool im_row = (lane >> 3) & 1;
@@ -547,9 +549,26 @@ __global__ __launch_bounds__(256) void k_stencil_gs_quad_mfma(const float2* __re
   const int tn = t0 + (v >> 1), xn = x0 + (v & 1), n = tn * Lx + xn;
   const int rhs = blockIdx.y * 16 + rl;
   const bool live = rhs < nrhs && (!st || st[rhs].active);
-  const float2* xr = x + int64_t(live ? rhs : 0) * stride;
   const float2* Ab = A + int64_t(n) * 25 * 64 + row8 * 8 + kq;
   const float2 z2 = make_float2(0.f, 0.f);
+  // the neighbourhood rows t0 - 2 .. t0 + 3, columns x0 - 2 .. x0 + 3 of the workgroup's 16 rhs,
+  // staged once (each node's 8 dofs as four 16-byte loads) instead of each wave loading its
+  // node's 24 neighbours; dead rhs read rhs 0's values and are masked where they are used
+  {
+    const int r0 = blockIdx.y * 16;
+    stage<9, 256, float4>(36 * 16 * 4, [&](int q) {
+      const int slot = q / 64, rr = (q / 4) % 16, p = q % 4;
+      const int m = wrap1(t0 - 2 + slot / 6, Lt) * Lx + wrap1(x0 - 2 + slot % 6, Lx);
+      const int rh = r0 + rr < nrhs ? r0 + rr : 0;
+      return reinterpret_cast<const float4*>(x + int64_t(rh) * stride + int64_t(m) * 8)[p];
+    }, [&](int q, float4 val) {
+      const int slot = q / 64, rr = (q / 4) % 16, p = q % 4;
+      float2* d = xs + (slot * 16 + rr) * XS + 2 * p;
+      d[0] = make_float2(val.x, val.y);
+      d[1] = make_float2(val.z, val.w);
+    });
+    __syncthreads();
+  }
   // phase 1, batches of NB offsets (stencil order without the centre): all loads of a batch are
   // issued before its products.  An earlier node's block gets zero right-hand-side values,
   // which leaves the sums unchanged bit for bit; the batch size does not change them either.
@@ -564,11 +583,11 @@ __global__ __launch_bounds__(256) void k_stencil_gs_quad_mfma(const float2* __re
       const int dt = d / 5 - 2, dx = d % 5 - 2;
       const int ga = (v >> 1) + dt, gb = (v & 1) + dx;
       zero[j] = (ga >= 0 && ga <= 1 && gb >= 0 && gb <= 1 && 2 * ga + gb < v) || !live;
-      const int m = wrap1(tn + dt, Lt) * Lx + wrap1(xn + dx, Lx);
+      const float2* xv = xs + (((ga + 2) * 6 + (gb + 2)) * 16 + rl) * XS;
       aL[j] = Ab[d * 64];
       aH[j] = Ab[d * 64 + 4];
-      bL[j] = xr[int64_t(m) * 8 + kq];
-      bH[j] = xr[int64_t(m) * 8 + 4 + kq];
+      bL[j] = xv[kq];
+      bH[j] = xv[4 + kq];
     }
     // the mask is applied where the values are used: overwriting a load's destination register
     // in a branch would make every load of the batch wait for the one before it
