@@ -120,6 +120,7 @@ __global__ __launch_bounds__(256) void k_prolong(const M* __restrict__ P,
   const int nr = nrows[w];
   const int r0 = chunk * ts.rch, cnt = max(0, min(nr - r0, ts.rch));
   const int nv_rows = chunk == 0 ? g.o * g.o * g.b : 0;     // vertex rows of node (I, J)
+  if (cnt == 0 && nv_rows == 0) return;              // no row of W in this chunk
   for (int k = threadIdx.x; k < cnt; k += 256) ri[k] = rows[int64_t(w) * maxrows + r0 + k];
   __syncthreads();
   stage<8, 256, M>(cnt * ncol, [&](int q) { return P[int64_t(ri[q / ncol]) * ncol + q % ncol]; },
@@ -256,6 +257,7 @@ __global__ __launch_bounds__(256) void k_prolong_tiled(
   const int I = w / g.nJ, J = w - (w / g.nJ) * g.nJ;
   const int r0 = chunk * RCH, cnt = max(0, min(nrows[w] - r0, RCH));
   const int nv_rows = chunk == 0 ? g.o * g.o * g.b : 0;
+  if (cnt == 0 && nv_rows == 0) return;              // no row of W in this chunk
   for (int k = threadIdx.x; k < cnt; k += 256) ri[k] = rows[int64_t(w) * maxrows + r0 + k];
   __syncthreads();
   stage<8, 256, M>(cnt * NCOL, [&](int q) { return P[int64_t(ri[q / NCOL]) * NCOL + q % NCOL]; },
@@ -630,6 +632,7 @@ __global__ __launch_bounds__(256) void k_prolong_mfma(
   const int g0 = blockIdx.y * NR, ng = min(NR, nrhs - g0);
   const int r0 = chunk * RCH, cnt = max(0, min(nrows[w] - r0, RCH));
   const int nv_rows = chunk == 0 ? g.o * g.o * g.b : 0;
+  if (cnt == 0 && nv_rows == 0) return;              // no row of W in this chunk
   for (int k = threadIdx.x; k < RCH; k += 256) ri[k] = k < cnt ? rows[int64_t(w) * maxrows + r0 + k] : 0;
   for (int rr = threadIdx.x; rr < NR; rr += 256) live[rr] = rr < ng && (!st || st[g0 + rr].active);
   __syncthreads();
