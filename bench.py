@@ -895,7 +895,7 @@ def main():
         stencil_traffic_summary(*args.stencil_traffic_summary)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(independent lattices and requests would run one per GPU).", file=sys.stderr)
         sys.exit(2)
 
